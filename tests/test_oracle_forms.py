@@ -1,0 +1,372 @@
+"""Pins of the oracle's spatial forms, residual and Jacobian.
+
+* The discrete residual tested with a discrete test function equals the weak
+  form of A^tp_gamma (eq. def-a-gam-tp with eq. def-b-gam, convective form
+  eq. Defc) evaluated on the exact polynomial fields, integrated here with a
+  12-point Gauss rule and written directly from the variational form, with
+  no finite element basis.  This fixes every volume and boundary term, its
+  sign and its indices.
+* The Jacobian equals the central difference of the residual: the residual
+  is quadratic in U wherever no boundary point changes the sign of v.n, so
+  the central difference is exact up to rounding (eq. JacobianLocal).
+* Structure of eq. JacobianLocal: J21 = J12^T, J22 = 0, the skew part at zero
+  state is (K - K^T) (x) M_h, constant pressures span the kernel for
+  Gamma_D = boundary of the domain.
+* Cartesian Kronecker identities of M_h and A_h against 1D matrices built
+  here from their definitions.
+"""
+from math import comb
+
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+from numpy.polynomial import polynomial as P
+
+from oracle import Problem, Slab
+from oracle import tables as T
+from paper_2602_13841_amd import inputs as I
+
+
+# --------------------------------------------------------------------------
+# polynomial helpers (global polynomials on [0,1]^d)
+# --------------------------------------------------------------------------
+def pval(c, x):
+    d = x.shape[1]
+    if d == 2:
+        return P.polyval2d(x[:, 0], x[:, 1], c)
+    return P.polyval3d(x[:, 0], x[:, 1], x[:, 2], c)
+
+
+def pgrad(c, x):
+    return np.stack([pval(P.polyder(c, axis=a), x) for a in range(x.shape[1])], axis=1)
+
+
+def gauss_box(d, nq=12):
+    gx, gw = T.gauss_legendre01(nq)
+    grids = np.meshgrid(*([gx] * d), indexing="ij")
+    wg = np.meshgrid(*([gw] * d), indexing="ij")
+    pts = np.stack([g.ravel() for g in grids], axis=1)
+    w = np.prod(np.stack([g.ravel() for g in wg], axis=1), axis=1)
+    return pts, w
+
+
+def face_points(d, ax, side, nq=12):
+    pts, w = gauss_box(d - 1, nq) if d > 1 else (np.zeros((1, 0)), np.ones(1))
+    full = np.zeros((len(w), d))
+    j = 0
+    for a in range(d):
+        if a == ax:
+            full[:, a] = float(side)
+        else:
+            full[:, a] = pts[:, j]
+            j += 1
+    n = np.zeros(d)
+    n[ax] = 1.0 if side else -1.0
+    return full, w, n
+
+
+def legendre_on01(i, s):
+    c = np.zeros(i + 1)
+    c[i] = 1.0
+    return np.sqrt(2 * i + 1) * npleg.legval(2 * s - 1, c)
+
+
+def modal_coefficients(prob, qcoef, modes):
+    """Per-cell coefficients of a global polynomial in the orthonormal basis
+    (L2 projection on the reference cell of each Cartesian cell)."""
+    d = prob.dim
+    pts, w = gauss_box(d, 10)
+    n = prob.n
+    ncell = int(np.prod(n))
+    out = np.zeros((ncell, len(modes)))
+    psi = np.stack([np.prod([legendre_on01(m[a], pts[:, a]) for a in range(d)], axis=0) for m in modes], axis=1)
+    for cell in range(ncell):
+        cc = []
+        rest = cell
+        for a in range(d):
+            cc.append(rest % n[a])
+            rest //= n[a]
+        x = (np.array(cc)[None, :] + pts) / np.array(n)[None, :]
+        qv = pval(qcoef, x)
+        out[cell] = (w * qv) @ psi
+    return out.ravel()
+
+
+def random_q(d, deg, rng, scale=1.0):
+    c = rng.uniform(-1, 1, (deg + 2,) * d) * scale
+    return c
+
+
+def random_p(d, r, rng):
+    c = rng.uniform(-1, 1, (r + 1,) * d)
+    idx = np.indices(c.shape).sum(axis=0)
+    c[idx > r] = 0.0
+    return c
+
+
+def exact_weak_form(prob, vc, pc, zc, qc):
+    """s(v,p)(z,q) from the variational form, exact Gauss integration."""
+    d, nu = prob.dim, prob.nu
+    g1, g2 = prob.gamma1, prob.gamma2
+    pts, w = gauss_box(d)
+    v = np.stack([pval(c, pts) for c in vc], axis=1)
+    gv = np.stack([pgrad(c, pts) for c in vc], axis=1)       # [p, c, a] = d_a v_c
+    z = np.stack([pval(c, pts) for c in zc], axis=1)
+    gz = np.stack([pgrad(c, pts) for c in zc], axis=1)
+    p = pval(pc, pts)
+    q = pval(qc, pts)
+    vol = nu * np.einsum("pca,pca->p", gv, gz)
+    vol -= p * np.einsum("pcc->p", gz)
+    vol -= np.einsum("pc,pa,pca->p", v, v, gz)
+    vol -= np.einsum("pcc->p", gv) * q
+    total = np.sum(w * vol)
+    for ax in range(d):
+        for side in (0, 1):
+            f = 2 * ax + side
+            fp, fw, n = face_points(d, ax, side)
+            v = np.stack([pval(c, fp) for c in vc], axis=1)
+            gv = np.stack([pgrad(c, fp) for c in vc], axis=1)
+            z = np.stack([pval(c, fp) for c in zc], axis=1)
+            gz = np.stack([pgrad(c, fp) for c in zc], axis=1)
+            p = pval(pc, fp)
+            q = pval(qc, fp)
+            vn = v @ n
+            zn = z @ n
+            vz = np.sum(v * z, axis=1)
+            integrand = vn * vz
+            if (prob.dirichlet_mask >> f) & 1:
+                h = 1.0 / prob.n[ax]
+                ominus = 0.5 * (np.abs(vn) - vn)
+                gvn = np.einsum("pca,a->pc", gv, n)
+                gzn = np.einsum("pca,a->pc", gz, n)
+                integrand = integrand - nu * np.sum(gvn * z, axis=1) + p * zn - ominus * vz
+                integrand = integrand - nu * np.sum(v * gzn, axis=1)
+                integrand = integrand + nu * g1 / h * vz + g2 / h * vn * zn + vn * q
+            total += np.sum(fw * integrand)
+    return total
+
+
+@pytest.mark.parametrize("d,n,r,mask", [(2, (2, 3), 1, None), (2, (3, 2), 2, 0b0110),
+                                        (3, (2, 1, 2), 1, None), (3, (1, 2, 1), 2, 0b101001)])
+def test_spatial_residual_equals_weak_form(d, n, r, mask):
+    rng = np.random.default_rng(7 + d + r)
+    prob = Problem(dim=d, n=n, r=r, k=0, nu=0.37, tau=1.0, dirichlet_mask=mask, gamma1=3.0, gamma2=5.0)
+    s = Slab(prob)
+    sp_ = s.space
+    xn = sp_.node_coordinates()
+    # velocity with a fixed sign per component so (v.n)^- is polynomial on every face
+    base = np.array([2.0, -1.5, 1.7])[:d]
+    vc = []
+    for c in range(d):
+        cc = random_q(d, r, rng, 0.2 / (r + 2) ** d)
+        cc[(0,) * d] += base[c]
+        vc.append(cc)
+    zc = [random_q(d, r, rng) for _ in range(d)]
+    pc = random_p(d, r, rng)
+    qc = random_p(d, r, rng)
+    V = np.concatenate([pval(c, xn) for c in vc])
+    Z = np.concatenate([pval(c, xn) for c in zc])
+    Pm = modal_coefficients(prob, pc, sp_.modes)
+    Qm = modal_coefficients(prob, qc, sp_.modes)
+    res = sp_.spatial_residual(V, Pm)
+    got = Z @ res[: sp_.Nv] + Qm @ res[sp_.Nv:]
+    want = exact_weak_form(prob, vc, pc, zc, qc)
+    assert abs(got - want) <= 1e-11 * max(1.0, abs(want)), (got, want)
+    # mass matrices: Z^T M_h V = int v.z, Q^T M_p P = int p q
+    Mh, Mp = sp_.masses()
+    pts, w = gauss_box(d)
+    vz = sum(pval(vc[c], pts) * pval(zc[c], pts) for c in range(d))
+    assert abs(Z @ (Mh @ V) - np.sum(w * vz)) < 1e-12 * max(1, abs(np.sum(w * vz)))
+    pq = np.sum(w * pval(pc, pts) * pval(qc, pts))
+    assert abs(Qm @ (Mp @ Pm) - pq) < 1e-12 * max(1, abs(pq))
+
+
+def _signed_state(s, rng, amp=0.1):
+    """Slab state whose velocity keeps one sign per component (no kink crossings)."""
+    d = s.prob.dim
+    V = []
+    for a in range(s.nt):
+        comps = []
+        for c in range(d):
+            base = [1.5, -1.2, 1.1][c]
+            comps.append(base + amp * rng.uniform(-1, 1, s.space.nnodes))
+        V.append(np.concatenate(comps))
+    Pp = rng.uniform(-1, 1, (s.nt, s.Np))
+    return s.join(np.array(V), Pp)
+
+
+@pytest.mark.parametrize("d,n,r,k,pert", [(2, (3, 2), 1, 1, False), (2, (2, 2), 3, 2, True),
+                                          (3, (2, 1, 2), 1, 2, True), (3, (1, 1, 2), 2, 1, False)])
+def test_jacobian_is_exact_central_difference(d, n, r, k, pert):
+    rng = np.random.default_rng(11)
+    vert = I.perturbed_vertices(d, n, 0.2, 5) if pert else None
+    prob = Problem(dim=d, n=n, r=r, k=k, nu=0.05, tau=0.1, vertices=vert)
+    s = Slab(prob)
+    U = _signed_state(s, rng)
+    X = rng.uniform(-1, 1, s.N)
+    rhs = rng.uniform(-1, 1, s.N)
+    vprev = rng.uniform(-1, 1, s.Nv)
+    J = s.jacobian(U)
+    y = J @ X
+    for eps in (1e-2, 1e-4):
+        fd = (s.residual(U + eps * X, rhs, vprev) - s.residual(U - eps * X, rhs, vprev)) / (2 * eps)
+        assert np.max(np.abs(fd - y)) <= 1e-11 / eps * np.max(np.abs(y)) + 1e-12
+    # element-wise action equals the assembled matrix
+    assert np.max(np.abs(s.vmult(U, X) - y)) <= 1e-13 * np.max(np.abs(y))
+    rows = rng.choice(s.N, 25, replace=False)
+    assert np.max(np.abs(s.vmult_rows(U, X, rows) - y[rows])) <= 1e-13 * np.max(np.abs(y))
+
+
+def test_dense_brute_force_tiny():
+    """Dense Jacobian column by column from residual differences on a 1x1 mesh."""
+    prob = Problem(dim=2, n=(1, 1), r=1, k=1, nu=0.3, tau=0.2)
+    s = Slab(prob)
+    rng = np.random.default_rng(3)
+    U = _signed_state(s, rng)
+    J = s.jacobian(U).toarray()
+    eps = 1e-3
+    Jfd = np.zeros_like(J)
+    for j in range(s.N):
+        e = np.zeros(s.N)
+        e[j] = eps
+        Jfd[:, j] = (s.residual(U + e) - s.residual(U - e)) / (2 * eps)
+    assert np.max(np.abs(J - Jfd)) < 1e-10 * np.max(np.abs(J))
+
+
+@pytest.mark.parametrize("pert", [False, True])
+def test_jacobian_structure(pert):
+    d, n, r, k = 2, (3, 3), 2, 2
+    vert = I.perturbed_vertices(d, n, 0.2, 9) if pert else None
+    prob = Problem(dim=d, n=n, r=r, k=k, nu=0.2, tau=0.1, vertices=vert)
+    s = Slab(prob)
+    rng = np.random.default_rng(5)
+    U = rng.uniform(-1, 1, s.N)
+    J = s.jacobian(U).toarray()
+    nv = s.nt * s.Nv
+    J11, J12, J21, J22 = J[:nv, :nv], J[:nv, nv:], J[nv:, :nv], J[nv:, nv:]
+    assert np.max(np.abs(J21 - J12.T)) < 1e-13 * np.max(np.abs(J12))
+    assert np.all(J22 == 0)
+    # constant pressure of any single time node is in the kernel (Gamma_D = boundary)
+    for a in range(s.nt):
+        x = np.zeros(s.N)
+        Pm = np.zeros((s.nt, s.Np))
+        Pm[a].reshape(-1, s.space.npm)[:, 0] = 1.0
+        x[nv:] = Pm.ravel()
+        assert np.max(np.abs(J @ x)) < 1e-12 * np.max(np.abs(J))
+    # zero state: only the temporal part is nonsymmetric
+    J0 = s.jacobian(np.zeros(s.N)).toarray()
+    Mh, _ = s.mass
+    skew = np.kron(s.tt.K - s.tt.K.T, Mh.toarray())
+    assert np.max(np.abs((J0 - J0.T)[:nv, :nv] - skew)) < 1e-12 * np.max(np.abs(J0))
+
+
+def _fe1d(n, r, nq=12):
+    """1D global mass and stiffness of continuous degree-(r+1) Lagrange
+    elements on GLL nodes, from exact integrals of the 1D polynomials."""
+    nodes = T.gauss_lobatto01(r + 2)
+    gx, gw = T.gauss_legendre01(nq)
+    L = T.lagrange_values(nodes, gx)
+    D = T.lagrange_derivatives(nodes, gx)
+    h = 1.0 / n
+    N = (r + 1) * n + 1
+    M = np.zeros((N, N))
+    A = np.zeros((N, N))
+    for c in range(n):
+        idx = np.arange(r + 2) + (r + 1) * c
+        M[np.ix_(idx, idx)] += h * (L.T * gw) @ L
+        A[np.ix_(idx, idx)] += (D.T * gw) @ D / h
+    return M, A
+
+
+@pytest.mark.parametrize("d,n,r", [(2, (3, 2), 1), (2, (2, 2), 2), (3, (2, 1, 2), 1)])
+def test_cartesian_kronecker_identities(d, n, r):
+    # no Dirichlet faces and zero state: L_vv = nu A_h per component
+    prob = Problem(dim=d, n=n, r=r, k=0, nu=1.0, tau=1.0, dirichlet_mask=0)
+    s = Slab(prob)
+    sp_ = s.space
+    L = sp_.spatial_jacobian(np.zeros(sp_.Nv)).toarray()
+    Mh, Mp = sp_.masses()
+    nn = sp_.nnodes
+    M1 = [_fe1d(n[a], r)[0] for a in range(d)]
+    A1 = [_fe1d(n[a], r)[1] for a in range(d)]
+    if d == 2:
+        Mk = np.kron(M1[1], M1[0])
+        Ak = np.kron(M1[1], A1[0]) + np.kron(A1[1], M1[0])
+    else:
+        Mk = np.kron(M1[2], np.kron(M1[1], M1[0]))
+        Ak = (np.kron(M1[2], np.kron(M1[1], A1[0])) + np.kron(M1[2], np.kron(A1[1], M1[0]))
+              + np.kron(A1[2], np.kron(M1[1], M1[0])))
+    for c in range(d):
+        blk = slice(c * nn, (c + 1) * nn)
+        assert np.max(np.abs(Mh.toarray()[blk, blk] - Mk)) < 1e-14
+        assert np.max(np.abs(L[blk, blk] - Ak)) < 1e-12
+    h = np.prod([1.0 / x for x in n])
+    assert np.allclose(Mp.toarray(), h * np.eye(sp_.Np), atol=1e-15)
+
+
+def test_manufactured_field_reading_is_divergence_free():
+    """The printed 2D field of Sec. Convergence test has nonzero divergence;
+    with the sign of the second component flipped it is divergence free,
+    vanishes on the boundary and at t = 0 (reading used by the tests)."""
+    x = np.random.default_rng(0).uniform(0, 1, (200, 2))
+    h = 1e-6
+
+    def v_printed(x):
+        s, c = np.sin(np.pi * x), np.cos(np.pi * x)
+        return np.stack([s[:, 0] ** 2 * s[:, 1] * c[:, 1], s[:, 0] * c[:, 0] * s[:, 1] ** 2], axis=1)
+
+    def v_read(x):
+        v = v_printed(x)
+        v[:, 1] *= -1
+        return v
+
+    def div(f, x):
+        e0 = np.array([h, 0])
+        e1 = np.array([0, h])
+        return ((f(x + e0) - f(x - e0))[:, 0] + (f(x + e1) - f(x - e1))[:, 1]) / (2 * h)
+
+    assert np.max(np.abs(div(v_printed, x))) > 0.1
+    assert np.max(np.abs(div(v_read, x))) < 1e-8
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_reduced_time_quadrature_error_rate(k):
+    """Radau integration of the convective term (eq. QuadNL, eq. AlgFconv)
+    against exact time integration for a smooth-in-time field, tested with a
+    smooth temporal test function: the per-slab error shrinks like
+    tau^(2k+2) (Peano kernel of a rule exact to degree 2k; Lemma GR-div)."""
+    prob = Problem(dim=2, n=(2, 2), r=1, k=k, nu=0.0, tau=1.0, dirichlet_mask=0)
+    s = Slab(prob)
+    sp_ = s.space
+    rng = np.random.default_rng(2)
+    W0, W1, W2 = (rng.uniform(-1, 1, sp_.Nv) for _ in range(3))
+    Z = rng.uniform(-1, 1, sp_.Nv)
+    zero_p = np.zeros(sp_.Np)
+
+    def field(t):
+        return W0 + np.sin(t) * W1 + np.cos(2 * t) * W2
+
+    def conv(v):
+        return sp_.spatial_residual(v, zero_p)[: sp_.Nv] @ Z
+
+    errs = []
+    taus = [0.08, 0.04, 0.02, 0.01]
+    for tau in taus:
+        tt = T.time_tables(k, tau)
+        V = [field(t) for t in tt.t]                # DG(k) interpolant at the Radau nodes
+        psi = np.cos(tt.t)                          # smooth temporal test weights
+        radau = sum(tt.w[a] * psi[a] * conv(V[a]) for a in range(k + 1))
+        gx, gw = T.gauss_legendre01(3 * k + 2)
+        exact = 0.0
+        for x, wq in zip(gx, gw):
+            t = tau * x
+            ph = tt.values([t])[0]
+            vt = sum(ph[b] * V[b] for b in range(k + 1))
+            exact += tau * wq * (ph @ psi) * conv(vt)
+        errs.append(abs(radau - exact))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] > 2 * k + 2 - 0.3 and np.mean(rates) > 2 * k + 2 - 0.5, rates
+    # k = 0: exact (constant-in-time state)
+    tt = T.time_tables(0, 0.1)
+    v0 = field(tt.t[0])
+    assert abs(tt.w[0] * conv(v0) - 0.1 * conv(v0)) < 1e-14
