@@ -1,0 +1,158 @@
+/*
+ * stmg.h -- C ABI of the MI355X space-time multigrid Newton-Krylov library.
+ *
+ * One context holds one space-time slab I_n = (t_{n-1}, t_n] of the tensor
+ * product discretization: mapped Q_{r+1}/P_r^disc in space on a structured
+ * (optionally vertex-perturbed) grid of [0,1]^d, discontinuous Galerkin DG(k)
+ * in time with the right-sided (k+1)-point Gauss-Radau rule (Problem
+ * "Local algebraic Navier-Stokes problem", eq. InAlgNS).
+ *
+ * Vector layout (slab vectors, length N = (k+1)(Nv1 + Np1)), following
+ * eq. DefSubvec: U = (V^1, ..., V^{k+1}, P^1, ..., P^{k+1}).
+ *   V^a : d blocks (component c), each over the ((r+1)n_0+1) x ((r+1)n_1+1)
+ *         (x ((r+1)n_2+1)) velocity nodes, x fastest.  Nv1 = d * Nnodes.
+ *   P^a : per cell (x fastest) the C(r+d,d) coefficients of the mapped
+ *         orthonormal Legendre basis of total degree <= r, first index
+ *         fastest.  Np1 = ncells * C(r+d,d).
+ *
+ * Memory: every vector argument is a DEVICE pointer owned by the caller
+ * (e.g. a torch tensor); the library never frees it.  FP64 arguments are
+ * double*, FP32 arguments float* (selected by a stmg_prec argument).  The
+ * library allocates its own device workspace when the context is created
+ * (query it with stmg_footprint_bytes) and frees it in stmg_destroy.
+ *
+ * Streams: all work of a context is enqueued on the hipStream_t given at
+ * creation (NULL = the default stream).  Calls that return scalars or
+ * statistics synchronize that stream; the others are asynchronous.
+ *
+ * Errors: 0 = success; negative = error, nothing is thrown across the ABI:
+ *   STMG_EINVAL (-1) invalid argument or unsupported size,
+ *   STMG_ENOMEM (-2) device allocation failed,
+ *   STMG_EHIP   (-3) a HIP call failed,
+ *   STMG_ESTATE (-4) call order (e.g. a smoother call before a rebuild),
+ *   STMG_ENONFINITE (-5) non-finite value detected.
+ * A positive value STMG_NOT_CONVERGED (+1) means a solve stopped at its
+ * iteration limit; results and statistics are still written.
+ * stmg_last_error returns a context-owned message for the last failure.
+ */
+#ifndef STMG_H
+#define STMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STMG_OK 0
+#define STMG_EINVAL (-1)
+#define STMG_ENOMEM (-2)
+#define STMG_EHIP (-3)
+#define STMG_ESTATE (-4)
+#define STMG_ENONFINITE (-5)
+#define STMG_NOT_CONVERGED 1
+
+typedef struct stmg_ctx stmg_ctx;
+
+typedef enum { STMG_F64 = 0, STMG_F32 = 1 } stmg_prec;
+
+/* Data of one slab (Problem LocAlgNS; Nitsche boundary forms eq. def-b-gam,
+ * eq. def-a-gam-tp).  Boundary face f = 2*axis + side (side 0: x_axis = 0,
+ * side 1: x_axis = 1); bit f of dirichlet_faces set = face in Gamma_D
+ * (Nitsche), clear = Gamma_N (do-nothing).  vertices: HOST pointer to
+ * ((n_0+1)(n_1+1)(n_2+1)) * d coordinates, x fastest, copied at creation;
+ * NULL = the uniform Cartesian grid. */
+typedef struct {
+    int dim;                  /* 2 or 3 */
+    int n_cells[3];           /* cells per direction (n_cells[2] ignored in 2D) */
+    const double *vertices;   /* host, may be NULL */
+    int r;                    /* pressure degree r (1..3); velocity Q_{r+1} */
+    int k;                    /* time degree k (0..3) */
+    double nu;                /* kinematic viscosity */
+    double tau;               /* slab length tau_n */
+    unsigned dirichlet_faces; /* bit mask, see above */
+    double gamma1, gamma2;    /* Nitsche penalties (Sec. "Numerical experiments": 10, 10) */
+} stmg_problem;
+
+/* Solver options.  stmg_default_options fills the values used in Sec.
+ * "Numerical experiments" where the paper states them and documented
+ * defaults where it is silent. */
+typedef struct {
+    int n_q;                  /* Gauss points per direction; 0 = ceil((3r+4)/2) */
+    int max_levels;           /* multigrid levels cap; 0 = coarsen to 2^d cells */
+    int nu1, nu2;             /* pre/post smoothing steps (1, 1) */
+    double vanka_omega;       /* relaxation omega of eq. LVS */
+    int prec_mg;              /* stmg_prec of the multigrid preconditioner */
+    /* Newton (Alg. "Inexact Newton-Krylov") */
+    double newton_rtol, newton_atol;
+    int newton_maxit;
+    /* Eisenstat-Walker forcing */
+    double ew_eta0, ew_c, ew_theta, ew_eta_min, ew_eta_max;
+    /* Armijo line search (Alg. "Armijo") */
+    double ls_lambda0, ls_c, ls_tau, ls_alpha_min;
+    int ls_window, ls_max_backtracks;
+    /* smoother rebuild triggers */
+    double rb_theta_N, rb_theta_L, rb_kappa_abs, rb_stag_theta;
+    int rb_stag_s;
+    /* FGMRES */
+    int fgmres_maxit;
+} stmg_options;
+
+typedef struct {
+    int newton_its;
+    int fgmres_its_total;
+    int fgmres_its[64];       /* per Newton step */
+    int rebuilds;
+    int backtracks;
+    double res0_M, res_M;     /* initial / final ||R||_M */
+    double wall_s;
+} stmg_stats;
+
+void stmg_default_options(stmg_options *opt);
+
+/* Device bytes the library allocates for a problem (workspace of all levels,
+ * patch factors, Krylov bases). */
+size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt);
+
+/* Create a context on the current HIP device.  stream: hipStream_t or NULL.
+ * Returns STMG_EINVAL for unsupported (dim, r, k, n_q) combinations. */
+int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_ctx **out);
+int stmg_destroy(stmg_ctx *ctx);
+const char *stmg_last_error(const stmg_ctx *ctx);
+
+/* Sizes of the slab vectors: total N, velocity part (k+1)Nv1, pressure part. */
+int stmg_sizes(const stmg_ctx *ctx, long long *n_total, long long *n_velocity, long long *n_pressure);
+
+/* Slab data of eq. InAlgNS: rhs = F_n + L_n (velocity rows) and the
+ * continuity-row data (length N, FP64, device) and v_prev = the velocity
+ * coefficients v_{n-1}^{k+1} (or v_0) of one time node (length Nv1, FP64,
+ * device).  Both are copied; NULL means zero. */
+int stmg_set_slab_data(stmg_ctx *ctx, const double *rhs, const double *v_prev);
+
+/* Slab residual R_n(U; V_{n-1}) of eq. InAlgNS in FP64:
+ *   r_v^a = sum_b K_ab M_h u_v^b + w_a s_v(u^a) - rhs_v^a - phi_a(t_{n-1}^+) M_h v_prev
+ *   r_p^a = w_a s_p(u^a) - rhs_p^a
+ * with s the spatial form A^tp_gamma (convection in divergence form,
+ * eq. ns-form-tp, reduced Radau quadrature in time, eq. QuadNL) and w_a the
+ * diagonal of M_n^tau.  u, r: device, length N; r is overwritten. */
+int stmg_residual(stmg_ctx *ctx, const double *u, double *r);
+
+/* y = J_n(U) x (eq. JacobianLocal): the exact slab Jacobian at the state
+ * u_state (only its velocity part is read), applied matrix-free with sum
+ * factorization (Sec. "Matrix-free operator evaluation").  prec selects
+ * FP64 (double*) or FP32 (float*) for u_state, x and y.  y is overwritten. */
+int stmg_jacobian_vmult(stmg_ctx *ctx, int prec, const void *u_state, const void *x, void *y);
+
+/* Batched form: nvec vectors stored contiguously with stride N (x, y) and
+ * the same state for all. */
+int stmg_jacobian_vmult_batched(stmg_ctx *ctx, int prec, const void *u_state, const void *x, void *y, int nvec);
+
+/* y = blockdiag(M^tau (x) M_h, M^tau (x) M_h^p) x: the weight of the norm
+ * ||.||_M of eq. inexact. */
+int stmg_mass_vmult(stmg_ctx *ctx, int prec, const void *x, void *y);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STMG_H */

@@ -1,0 +1,214 @@
+// extern "C" entry points of the stmg library.
+#include "context.h"
+
+#include <cstring>
+
+using namespace stmg;
+
+namespace {
+
+int fail(stmg_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+template <typename F> int guarded(stmg_ctx *ctx, F &&f)
+{
+    try {
+        return f();
+    } catch (const HipError &e) {
+        return fail(ctx, e.code, e.what());
+    } catch (const std::exception &e) {
+        return fail(ctx, STMG_EINVAL, e.what());
+    }
+}
+
+bool check_problem(const stmg_problem *p, std::string &why)
+{
+    if (!p) { why = "problem is NULL"; return false; }
+    if (p->dim != 2 && p->dim != 3) { why = "dim must be 2 or 3"; return false; }
+    for (int a = 0; a < p->dim; ++a)
+        if (p->n_cells[a] < 1) { why = "n_cells must be >= 1"; return false; }
+    if (p->r < 1 || p->r > 3) { why = "r must be in 1..3"; return false; }
+    if (p->k < 0 || p->k > MAX_K) { why = "k must be in 0..3"; return false; }
+    if (!(p->tau > 0) || !(p->nu > 0)) { why = "tau and nu must be positive"; return false; }
+    return true;
+}
+
+} // namespace
+
+extern "C" {
+
+void stmg_default_options(stmg_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->n_q = 0;
+    o->max_levels = 0;
+    o->nu1 = 1;
+    o->nu2 = 1;
+    o->vanka_omega = 0.7;
+    o->prec_mg = STMG_F32;
+    o->newton_rtol = 1e-8;
+    o->newton_atol = 1e-12;
+    o->newton_maxit = 30;
+    o->ew_eta0 = 0.4;
+    o->ew_c = 0.5;
+    o->ew_theta = 1.5;
+    o->ew_eta_min = 1e-3;
+    o->ew_eta_max = 0.8;
+    o->ls_lambda0 = 1.0;
+    o->ls_c = 1e-4;
+    o->ls_tau = 0.5;
+    o->ls_alpha_min = 1e-3;
+    o->ls_window = 5;
+    o->ls_max_backtracks = 5;
+    o->rb_theta_N = 0.5;
+    o->rb_theta_L = 2.0;
+    o->rb_kappa_abs = 10.0;
+    o->rb_stag_theta = 0.9;
+    o->rb_stag_s = 3;
+    o->fgmres_maxit = 50;
+}
+
+int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_ctx **out)
+{
+    if (!out) return STMG_EINVAL;
+    *out = nullptr;
+    std::string why;
+    if (!check_problem(prob, why)) return STMG_EINVAL;
+    stmg_ctx *ctx = new stmg_ctx();
+    ctx->prob = *prob;
+    ctx->prob.vertices = nullptr;
+    if (opt) ctx->opt = *opt;
+    else stmg_default_options(&ctx->opt);
+    ctx->stream = (hipStream_t)stream;
+    int rc = guarded(ctx, [&]() {
+        std::vector<double> verts;
+        if (prob->vertices) {
+            long long nv = 1;
+            for (int a = 0; a < prob->dim; ++a) nv *= prob->n_cells[a] + 1;
+            verts.assign(prob->vertices, prob->vertices + nv * prob->dim);
+        }
+        auto L = std::make_unique<Level>();
+        L->init(*prob, prob->k, prob->r, prob->n_cells[0], prob->n_cells[1], prob->dim == 3 ? prob->n_cells[2] : 1,
+                ctx->opt.n_q, verts);
+        if (L->nq != default_nq(L->r) && L->nq != L->r + 2)
+            throw std::runtime_error("n_q must be ceil((3r+4)/2) or r+2");
+        ctx->levels.push_back(std::move(L));
+        return STMG_OK;
+    });
+    if (rc != STMG_OK) {
+        delete ctx;
+        return rc;
+    }
+    *out = ctx;
+    return STMG_OK;
+}
+
+int stmg_destroy(stmg_ctx *ctx)
+{
+    delete ctx;
+    return STMG_OK;
+}
+
+const char *stmg_last_error(const stmg_ctx *ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt)
+{
+    (void)opt;
+    std::string why;
+    if (!check_problem(prob, why)) return 0;
+    long long ncell = 1, nn = 1;
+    for (int a = 0; a < prob->dim; ++a) {
+        ncell *= prob->n_cells[a];
+        nn *= (long long)(prob->r + 1) * prob->n_cells[a] + 1;
+    }
+    long long nl = 1;
+    for (int a = 0; a < prob->dim; ++a) nl *= prob->r + 2;
+    long long nt = prob->k + 1;
+    // cell-local result buffers (FP64 + FP32) and slab data
+    size_t b = (size_t)ncell * nt * prob->dim * nl * (8 + 4);
+    b += (size_t)nt * (prob->dim * nn + ncell * 20) * 8 + prob->dim * nn * 8;
+    return b;
+}
+
+int stmg_sizes(const stmg_ctx *ctx, long long *n_total, long long *n_velocity, long long *n_pressure)
+{
+    if (!ctx || ctx->levels.empty()) return STMG_EINVAL;
+    const Level &L = *ctx->levels[0];
+    if (n_total) *n_total = L.N;
+    if (n_velocity) *n_velocity = L.nt * L.Nv1;
+    if (n_pressure) *n_pressure = L.nt * L.Np1;
+    return STMG_OK;
+}
+
+int stmg_set_slab_data(stmg_ctx *ctx, const double *rhs, const double *v_prev)
+{
+    if (!ctx) return STMG_EINVAL;
+    return guarded(ctx, [&]() {
+        const Level &L = *ctx->levels[0];
+        if (rhs) {
+            if (ctx->rhs.bytes < (size_t)L.N * 8) ctx->rhs.alloc((size_t)L.N * 8);
+            STMG_HIP(hipMemcpyAsync(ctx->rhs.p, rhs, (size_t)L.N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        ctx->has_rhs = rhs != nullptr;
+        if (v_prev) {
+            if (ctx->vprev.bytes < (size_t)L.Nv1 * 8) ctx->vprev.alloc((size_t)L.Nv1 * 8);
+            STMG_HIP(hipMemcpyAsync(ctx->vprev.p, v_prev, (size_t)L.Nv1 * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        ctx->has_vprev = v_prev != nullptr;
+        return STMG_OK;
+    });
+}
+
+int stmg_residual(stmg_ctx *ctx, const double *u, double *r)
+{
+    if (!ctx || !u || !r) return fail(ctx, STMG_EINVAL, "NULL argument");
+    return guarded(ctx, [&]() {
+        Level &L = *ctx->levels[0];
+        L.apply<double>(Mode::Res, nullptr, u, r, ctx->has_rhs ? ctx->rhs.as<double>() : nullptr,
+                        ctx->has_vprev ? ctx->vprev.as<double>() : nullptr, 1, ctx->stream);
+        return STMG_OK;
+    });
+}
+
+int stmg_jacobian_vmult_batched(stmg_ctx *ctx, int prec, const void *u_state, const void *x, void *y, int nvec)
+{
+    if (!ctx || !u_state || !x || !y || nvec < 1) return fail(ctx, STMG_EINVAL, "invalid argument");
+    return guarded(ctx, [&]() {
+        Level &L = *ctx->levels[0];
+        if (prec == STMG_F64)
+            L.apply<double>(Mode::Jac, (const double *)u_state, (const double *)x, (double *)y, nullptr, nullptr, nvec,
+                            ctx->stream);
+        else if (prec == STMG_F32)
+            L.apply<float>(Mode::Jac, (const float *)u_state, (const float *)x, (float *)y, nullptr, nullptr, nvec,
+                           ctx->stream);
+        else
+            return fail(ctx, STMG_EINVAL, "prec must be STMG_F64 or STMG_F32");
+        return STMG_OK;
+    });
+}
+
+int stmg_jacobian_vmult(stmg_ctx *ctx, int prec, const void *u_state, const void *x, void *y)
+{
+    return stmg_jacobian_vmult_batched(ctx, prec, u_state, x, y, 1);
+}
+
+int stmg_mass_vmult(stmg_ctx *ctx, int prec, const void *x, void *y)
+{
+    if (!ctx || !x || !y) return fail(ctx, STMG_EINVAL, "NULL argument");
+    return guarded(ctx, [&]() {
+        Level &L = *ctx->levels[0];
+        if (prec == STMG_F64)
+            L.apply<double>(Mode::Mass, nullptr, (const double *)x, (double *)y, nullptr, nullptr, 1, ctx->stream);
+        else if (prec == STMG_F32)
+            L.apply<float>(Mode::Mass, nullptr, (const float *)x, (float *)y, nullptr, nullptr, 1, ctx->stream);
+        else
+            return fail(ctx, STMG_EINVAL, "prec must be STMG_F64 or STMG_F32");
+        return STMG_OK;
+    });
+}
+
+} // extern "C"

@@ -1,0 +1,856 @@
+// Matrix-free cell kernels of one space-time slab on gfx950.
+//
+// One workgroup handles one spatial cell and all k+1 time nodes of the slab
+// (the Kronecker evaluation of Sec. "Matrix-free operator evaluation": the
+// spatial operator once per temporal node, then the small dense time
+// mixing).  Per cell and time node:
+//
+//   1. coalesced gather of the nodal values (velocity, pressure modes, state)
+//      into LDS,
+//   2. sum-factorized 1D sweeps to the Gauss points (values), collocation
+//      derivatives at the Gauss points for gradients,
+//   3. the quadrature-point physics (register staged, in place in LDS),
+//   4. transposed collocation + transposed sweeps back to the nodes,
+//   5. for cells on the domain boundary: the Nitsche / convective boundary
+//      terms of eq. def-a-gam-tp and eq. def-b-gam, with face sweeps,
+//   6. velocity results go to a cell-local buffer E (no atomics); a second
+//      kernel sums E over the cells sharing each node in a fixed order, so
+//      results are bitwise reproducible.
+//
+// Modes:
+//   Jac  : y = J_n(U) x  (eq. JacobianLocal; convective part eq. Defcp)
+//   Res  : y = R_n(U; V_{n-1}) (eq. InAlgNS), rhs and V_{n-1} optional
+//   Mass : y = blockdiag(M^tau (x) M_h, M^tau (x) M_h^p) x (weight of the
+//          M-norm of eq. inexact)
+#include "stmg_internal.h"
+
+namespace stmg {
+
+namespace {
+
+template <int DIM, int R> struct Sizes {
+    static constexpr int N1 = R + 2;
+    static constexpr int NL = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+    static constexpr int RP1 = R + 1;
+    static constexpr int NPF = DIM == 2 ? RP1 * RP1 : RP1 * RP1 * RP1;   // full tensor of modes
+    static constexpr int NPM = DIM == 2 ? (R + 1) * (R + 2) / 2 : (R + 1) * (R + 2) * (R + 3) / 6;
+};
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// ---------------------------------------------------------------------------
+// Tensor sweep: out[f][o2][o1][o0] (+)= sum A2[o2][i2] A1[o1][i1] A0[o0][i0]
+// in[f][i2][i1][i0], NF fields, input/output field strides is/os.  Matrices
+// are row-major O x I.  All threads of the block cooperate; ends with a
+// barrier.  In 2D the third axis is absent.
+// ---------------------------------------------------------------------------
+template <int DIM, int NF, int I0, int I1, int I2, int O0, int O1, int O2, bool ACC, typename T>
+__device__ __forceinline__ void sweep(const T *__restrict__ in, int is, T *__restrict__ out, int os,
+                                      T *__restrict__ t1, T *__restrict__ t2, const T *A0,
+                                      const T *A1, const T *A2)
+{
+    const int tid = threadIdx.x, nth = blockDim.x;
+    if constexpr (DIM == 2) {
+        constexpr int n1 = I1 * O0;
+        for (int e = tid; e < NF * n1; e += nth) {
+            int f = e / n1, rr = e - f * n1, o0 = rr % O0, i1 = rr / O0;
+            const T *src = in + f * is + i1 * I0;
+            const T *a = A0 + o0 * I0;
+            T s = 0;
+#pragma unroll
+            for (int i = 0; i < I0; ++i) s += a[i] * src[i];
+            t1[e] = s;
+        }
+        __syncthreads();
+        constexpr int n2 = O1 * O0;
+        for (int e = tid; e < NF * n2; e += nth) {
+            int f = e / n2, rr = e - f * n2, o0 = rr % O0, o1 = rr / O0;
+            const T *src = t1 + f * n1 + o0;
+            const T *a = A1 + o1 * I1;
+            T s = 0;
+#pragma unroll
+            for (int i = 0; i < I1; ++i) s += a[i] * src[i * O0];
+            if constexpr (ACC) out[f * os + rr] += s;
+            else out[f * os + rr] = s;
+        }
+        __syncthreads();
+    } else {
+        constexpr int n1 = I2 * I1 * O0;
+        for (int e = tid; e < NF * n1; e += nth) {
+            int f = e / n1, rr = e - f * n1, o0 = rr % O0, i21 = rr / O0;
+            const T *src = in + f * is + i21 * I0;
+            const T *a = A0 + o0 * I0;
+            T s = 0;
+#pragma unroll
+            for (int i = 0; i < I0; ++i) s += a[i] * src[i];
+            t1[e] = s;
+        }
+        __syncthreads();
+        constexpr int n2 = I2 * O1 * O0;
+        for (int e = tid; e < NF * n2; e += nth) {
+            int f = e / n2, rr = e - f * n2, o0 = rr % O0, o1 = (rr / O0) % O1, i2 = rr / (O0 * O1);
+            const T *src = t1 + f * n1 + i2 * I1 * O0 + o0;
+            const T *a = A1 + o1 * I1;
+            T s = 0;
+#pragma unroll
+            for (int i = 0; i < I1; ++i) s += a[i] * src[i * O0];
+            t2[e] = s;
+        }
+        __syncthreads();
+        constexpr int n3 = O2 * O1 * O0;
+        for (int e = tid; e < NF * n3; e += nth) {
+            int f = e / n3, rr = e - f * n3, o01 = rr % (O0 * O1), o2 = rr / (O0 * O1);
+            const T *src = t2 + f * n2 + o01;
+            const T *a = A2 + o2 * I2;
+            T s = 0;
+#pragma unroll
+            for (int i = 0; i < I2; ++i) s += a[i] * src[i * O0 * O1];
+            if constexpr (ACC) out[f * os + rr] += s;
+            else out[f * os + rr] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// multilinear map: Jacobian J[a][b] = dx_a/dxi_b at xi; vertices X[v*3+a]
+template <int DIM, typename T>
+__device__ __forceinline__ void map_jac(const T *X, const T xi[3], T J[3][3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) J[a][b] = 0;
+#pragma unroll
+    for (int v = 0; v < (1 << DIM); ++v) {
+        T f[3], df[3];
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            int o = (v >> b) & 1;
+            f[b] = o ? xi[b] : T(1) - xi[b];
+            df[b] = o ? T(1) : T(-1);
+        }
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            T g = df[b];
+#pragma unroll
+            for (int e = 0; e < DIM; ++e)
+                if (e != b) g *= f[e];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) J[a][b] += X[v * 3 + a] * g;
+        }
+    }
+}
+
+// det J and Jit = J^{-T}
+template <int DIM, typename T>
+__device__ __forceinline__ T inv_t(const T J[3][3], T Jit[3][3])
+{
+    if constexpr (DIM == 2) {
+        T det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        T id = T(1) / det;
+        Jit[0][0] = J[1][1] * id;
+        Jit[0][1] = -J[1][0] * id;
+        Jit[1][0] = -J[0][1] * id;
+        Jit[1][1] = J[0][0] * id;
+        return det;
+    } else {
+        T c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        T det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        T id = T(1) / det;
+        Jit[0][0] = c00 * id;
+        Jit[0][1] = c01 * id;
+        Jit[0][2] = c02 * id;
+        Jit[1][0] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+        Jit[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+        Jit[1][2] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+        Jit[2][0] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+        Jit[2][1] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+        Jit[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+        return det;
+    }
+}
+
+template <typename T> __device__ __forceinline__ T ominus(T y) { return T(0.5) * (fabs(y) - y); }
+template <typename T> __device__ __forceinline__ T dominus(T y)
+{
+    return y > T(0) ? T(0) : (y < T(0) ? T(-1) : T(-0.5));
+}
+
+// LDS layout (in units of T) of the cell kernel
+template <int DIM, int R, int NQ, typename T> struct Lds {
+    using Z = Sizes<DIM, R>;
+    static constexpr int NQV = ipow(NQ, DIM);
+    static constexpr int NQF = ipow(NQ, DIM - 1);
+    // quadrature-point record fields: volume uses DIM*DIM + 2*DIM + 1 (Jac outputs)
+    static constexpr int NFIELD_V = DIM * DIM + DIM + 1;      // F (DIM^2), val (DIM), div
+    static constexpr int NFIELD_IN = 3 * DIM + 1;             // xhat, v, xmix, p
+    static constexpr int NF_V = NFIELD_V > NFIELD_IN ? NFIELD_V : NFIELD_IN;
+    static constexpr int NF_F = DIM + DIM * DIM + DIM + 1;    // face: xhat, grad xhat, v, p
+    static constexpr int Q_SIZE = (NF_V * NQV > NF_F * NQF + (DIM + DIM * DIM + 1) * NQF)
+                                      ? NF_V * NQV
+                                      : NF_F * NQF + (DIM + DIM * DIM + 1) * NQF;
+    // sweep temporaries: the largest intermediate of any sweep (forward,
+    // transposed, face) is DIM * N1 * NQ * max(N1, NQ) words; pressure sweeps
+    // need at most NQ^DIM; reductions use one word per thread (<= 256).
+    static constexpr int MX = Z::N1 > NQ ? Z::N1 : NQ;
+    static constexpr int TS = DIM * Z::N1 * NQ * MX;
+    static constexpr int TSP = TS > NQV ? TS : NQV;
+    static constexpr int TMP1 = TSP > 256 ? TSP : 256;
+    static constexpr int TMP2 = TMP1;
+};
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// Helpers shared by the volume and face passes
+// ---------------------------------------------------------------------------
+// full-tensor index of the m-th admissible pressure multi-index (first index
+// fastest, total degree <= R)
+template <int DIM, int R>
+__device__ __forceinline__ int pmode_full(int m)
+{
+    constexpr int RP1 = R + 1;
+    int cnt = 0;
+    for (int a2 = 0; a2 <= (DIM == 3 ? R : 0); ++a2)
+        for (int a1 = 0; a1 <= R; ++a1)
+            for (int a0 = 0; a0 <= R; ++a0) {
+                if (a0 + a1 + a2 > R) continue;
+                if (cnt == m) return a0 + RP1 * (a1 + RP1 * a2);
+                ++cnt;
+            }
+    return 0;
+}
+
+// geometry at a reference point: J^{-T} and det J (Cartesian cells: diagonal)
+template <int DIM, typename T>
+__device__ __forceinline__ T geometry(bool mapped, const T *X, const T xi[3], const T h[3], T Jit[3][3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Jit[a][b] = 0;
+    if (mapped) {
+        T J[3][3];
+        map_jac<DIM>(X, xi, J);
+        return inv_t<DIM>(J, Jit);
+    }
+    T det = 1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        Jit[d][d] = T(1) / h[d];
+        det *= h[d];
+    }
+    return det;
+}
+
+// LDS words of the cell kernel for nt time nodes
+template <int DIM, int R, int NQ, typename T>
+__host__ __device__ constexpr int lds_words(int nt, int tabwords)
+{
+    using Z = Sizes<DIM, R>;
+    using LY = Lds<DIM, R, NQ, T>;
+    return ((tabwords + 1) & ~1) + nt * DIM * Z::NL + nt * Z::NPF + 2 * DIM * Z::NL + Z::NPF + LY::Q_SIZE +
+           LY::TMP1 + LY::TMP2 + 64;
+}
+
+// ---------------------------------------------------------------------------
+// The cell kernel
+// ---------------------------------------------------------------------------
+template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE>
+__global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
+{
+    using Z = Sizes<DIM, R>;
+    using LY = Lds<DIM, R, NQ, T>;
+    constexpr int N1 = Z::N1, NL = Z::NL, RP1 = Z::RP1, NPF = Z::NPF, NPM = Z::NPM;
+    constexpr int NQV = LY::NQV, NQF = LY::NQF;
+    constexpr int NQ2 = DIM == 2 ? 1 : NQ;       // extent of axis 2 at Gauss points
+    constexpr int N12 = DIM == 2 ? 1 : N1;
+    constexpr int RP12 = DIM == 2 ? 1 : RP1;
+    constexpr int QPT = (NQV + NTH - 1) / NTH;   // quadrature points per thread
+    constexpr int NOUT = DIM * DIM + DIM + 1;    // F (ref, DIM^2), value coef (DIM), pressure coef
+
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+
+    const int tid = threadIdx.x;
+    const int cell = blockIdx.x;
+    const int vec = blockIdx.y;
+    const int nt = A.nt;
+    const T *__restrict__ x = A.x + vec * A.xstride;
+    T *__restrict__ y = A.y + vec * A.ystride;
+    T *__restrict__ E = A.E + (long long)vec * A.ncell * nt * DIM * NL;
+
+    // ---- LDS carve-up -------------------------------------------------------
+    TableLayout lay;
+    lay.init(R, NQ);
+    T *tab = sm;
+    T *xs = tab + ((lay.total + 1) & ~1);          // [nt][DIM][NL] nodal x
+    T *xpf = xs + nt * DIM * NL;                   // [nt][NPF] full-tensor pressure modes
+    T *ns = xpf + nt * NPF;                        // [DIM][NL] nodal scratch (state)
+    T *ys = ns + DIM * NL;                         // [DIM][NL] nodal mix / output
+    T *ypf = ys + DIM * NL;                        // [NPF] pressure output (full tensor)
+    T *Q = ypf + NPF;                              // quadrature record
+    T *t1 = Q + LY::Q_SIZE;
+    T *t2 = t1 + LY::TMP1;
+    T *geo = t2 + LY::TMP2;                        // [8][3] vertices, [6] h_F, [1] volume
+
+    for (int i = tid; i < lay.total; i += NTH) tab[i] = A.tab[i];
+
+    const T *S = tab + lay.S, *St = tab + lay.St, *D = tab + lay.D, *Dt = tab + lay.Dt;
+    const T *Dq = tab + lay.Dq, *Dqt = tab + lay.Dqt, *Se = tab + lay.Se, *De = tab + lay.De;
+    const T *Lp = tab + lay.L, *Lpt = tab + lay.Lt, *Lpe = tab + lay.Le, *qw = tab + lay.qw;
+    const T *qx = tab + lay.qx;
+
+    // ---- cell coordinates and nodal gather ------------------------------------
+    const int c0 = cell % A.n0;
+    const int c1 = (cell / A.n0) % A.n1;
+    const int c2 = DIM == 3 ? cell / (A.n0 * A.n1) : 0;
+    const long long N0 = (long long)(R + 1) * A.n0 + 1;
+    const long long N1g = (long long)(R + 1) * A.n1 + 1;
+    auto gnode = [&](int l) -> long long {
+        int i0 = l % N1, i1 = (l / N1) % N1, i2 = DIM == 3 ? l / (N1 * N1) : 0;
+        long long g0 = (long long)(R + 1) * c0 + i0, g1 = (long long)(R + 1) * c1 + i1;
+        long long g2 = (long long)(R + 1) * c2 + i2;
+        return g0 + N0 * (g1 + N1g * g2);
+    };
+
+    const long long pbase = (long long)nt * A.Nv1;
+    for (int e = tid; e < nt * DIM * NL; e += NTH) {
+        int l = e % NL, c = (e / NL) % DIM, a = e / (NL * DIM);
+        xs[e] = x[a * A.Nv1 + c * A.Nn + gnode(l)];
+    }
+    for (int e = tid; e < nt * NPF; e += NTH) xpf[e] = 0;
+    const T hcar[3] = {T(1) / A.n0, T(1) / A.n1, DIM == 3 ? T(1) / A.n2 : T(1)};
+    const bool mapped = A.mapped != 0;
+    if (mapped && tid < (1 << DIM)) {
+        int v = tid;
+        int o0 = v & 1, o1 = (v >> 1) & 1, o2 = (v >> 2) & 1;
+        long long vi = (c0 + o0) + (long long)(A.n0 + 1) * ((c1 + o1) + (long long)(A.n1 + 1) * (c2 + o2));
+        for (int a = 0; a < 3; ++a) geo[v * 3 + a] = a < DIM ? T(A.vert[vi * DIM + a]) : T(0);
+    }
+    __syncthreads();
+    for (int e = tid; e < nt * NPM; e += NTH) {
+        int m = e % NPM, a = e / NPM;
+        xpf[a * NPF + pmode_full<DIM, R>(m)] = x[pbase + a * A.Np1 + (long long)cell * NPM + m];
+    }
+
+    const bool bnd = (c0 == 0) || (c0 == A.n0 - 1) || (c1 == 0) || (c1 == A.n1 - 1) ||
+                     (DIM == 3 && ((c2 == 0) || (c2 == A.n2 - 1)));
+    T *hF = geo + 24;   // h_F = |K| / |F| per face id
+
+    // ---- h_F of the boundary faces (reading: |K|/|F| by the cell's quadrature) ----
+    if (MODE != Mode::Mass && bnd) {
+        if (!mapped) {
+            if (tid < 2 * DIM) hF[tid] = hcar[tid / 2];
+        } else {
+            // volume: fixed-order reduction of det J w over the volume Gauss points
+            T part = 0;
+            for (int q = tid; q < NQV; q += NTH) {
+                int qi[3] = {q % NQ, (q / NQ) % NQ, DIM == 3 ? q / (NQ * NQ) : 0};
+                T xi[3] = {0, 0, 0}, Jit[3][3];
+                for (int d = 0; d < DIM; ++d) xi[d] = qx[qi[d]];
+                T det = geometry<DIM>(true, geo, xi, hcar, Jit);
+                T w = det;
+                for (int d = 0; d < DIM; ++d) w *= qw[qi[d]];
+                part += w;
+            }
+            t1[tid] = part;
+            __syncthreads();
+            if (tid == 0) {
+                T vol = 0;
+                for (int i = 0; i < NTH; ++i) vol += t1[i];
+                geo[30] = vol;
+            }
+            __syncthreads();
+            // face areas: one face at a time, fixed order
+            for (int fid = 0; fid < 2 * DIM; ++fid) {
+                int ax = fid / 2, side = fid % 2;
+                for (int q = tid; q < NQF; q += NTH) {
+                    int tq[2] = {q % NQ, DIM == 3 ? q / NQ : 0};
+                    T xi[3] = {0, 0, 0}, Jit[3][3], wt = 1;
+                    int t = 0;
+                    for (int d = 0; d < DIM; ++d) {
+                        if (d == ax) xi[d] = T(side);
+                        else { xi[d] = qx[tq[t]]; wt *= qw[tq[t]]; ++t; }
+                    }
+                    T det = geometry<DIM>(true, geo, xi, hcar, Jit);
+                    T len = 0;
+                    for (int d = 0; d < DIM; ++d) len += Jit[d][ax] * Jit[d][ax];
+                    t2[q] = fabs(det) * sqrt(len) * wt;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    T area = 0;
+                    for (int q = 0; q < NQF; ++q) area += t2[q];
+                    hF[fid] = geo[30] / area;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    __syncthreads();
+
+    for (int a = 0; a < nt; ++a) {
+        // ---- nodal scratch: state (Jac) and mixed field sum_b K_ab x^b (- phi0_a vprev)
+        for (int e = tid; e < DIM * NL; e += NTH) {
+            int l = e % NL, c = e / NL;
+            if constexpr (MODE == Mode::Jac) {
+                const T *st = A.state + vec * A.sstride;
+                ns[e] = st[a * A.Nv1 + c * A.Nn + gnode(l)];
+            }
+            T m = 0;
+            if constexpr (MODE != Mode::Mass) {
+                for (int b = 0; b < nt; ++b) m += A.K[a * nt + b] * xs[(b * DIM + c) * NL + l];
+            }
+            if constexpr (MODE == Mode::Res) {
+                if (A.vprev) m -= A.phi0[a] * A.vprev[c * A.Nn + gnode(l)];
+            }
+            ys[e] = m;
+        }
+        __syncthreads();
+
+        // ---- forward sweeps to the Gauss points --------------------------------
+        // Q fields: [0,DIM) xhat, [DIM,2DIM) state v (Jac), [2DIM,3DIM) mix, 3DIM p
+        sweep<DIM, DIM, N1, N1, N12, NQ, NQ, NQ2, false>(xs + a * DIM * NL, NL, Q, NQV, t1, t2, S, S, S);
+        if constexpr (MODE == Mode::Jac)
+            sweep<DIM, DIM, N1, N1, N12, NQ, NQ, NQ2, false>(ns, NL, Q + DIM * NQV, NQV, t1, t2, S, S, S);
+        if constexpr (MODE != Mode::Mass)
+            sweep<DIM, DIM, N1, N1, N12, NQ, NQ, NQ2, false>(ys, NL, Q + 2 * DIM * NQV, NQV, t1, t2, S, S, S);
+        sweep<DIM, 1, RP1, RP1, RP12, NQ, NQ, NQ2, false>(xpf + a * NPF, NPF, Q + 3 * DIM * NQV, NQV, t1, t2,
+                                                           Lp, Lp, Lp);
+
+        // ---- quadrature-point physics (register staged, then in place) -----------
+        T outv[QPT][NOUT];
+        const T wa = A.w[a];
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int q = tid + j * NTH;
+            if (q < NQV) {
+                const int qi[3] = {q % NQ, (q / NQ) % NQ, DIM == 3 ? q / (NQ * NQ) : 0};
+                const int strides[3] = {1, NQ, NQ * NQ};
+                T xh[3] = {0, 0, 0}, v[3] = {0, 0, 0}, xm[3] = {0, 0, 0}, gref[3][3];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    xh[c] = Q[c * NQV + q];
+                    if constexpr (MODE == Mode::Jac) v[c] = Q[(DIM + c) * NQV + q];
+                    if constexpr (MODE != Mode::Mass) xm[c] = Q[(2 * DIM + c) * NQV + q];
+                }
+                const T ph = Q[3 * DIM * NQV + q];
+                if constexpr (MODE != Mode::Mass) {
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                        for (int jd = 0; jd < DIM; ++jd) {
+                            T s = 0;
+                            const int base = q - qi[jd] * strides[jd];
+#pragma unroll
+                            for (int m = 0; m < NQ; ++m)
+                                s += Dq[qi[jd] * NQ + m] * Q[c * NQV + base + m * strides[jd]];
+                            gref[c][jd] = s;
+                        }
+                }
+                T xi[3] = {0, 0, 0}, Jit[3][3];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) xi[d] = qx[qi[d]];
+                const T det = geometry<DIM>(mapped, geo, xi, hcar, Jit);
+                T jxw = det;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) jxw *= qw[qi[d]];
+                const T sc = wa * jxw;
+                if constexpr (MODE == Mode::Mass) {
+#pragma unroll
+                    for (int f = 0; f < DIM * DIM; ++f) outv[j][f] = 0;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) outv[j][DIM * DIM + c] = sc * xh[c];
+                    outv[j][DIM * DIM + DIM] = sc * ph;
+                } else {
+                    T G[3][3];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                        for (int d = 0; d < DIM; ++d) {
+                            T s = 0;
+#pragma unroll
+                            for (int jd = 0; jd < DIM; ++jd) s += Jit[d][jd] * gref[c][jd];
+                            G[c][d] = s;
+                        }
+                    T divx = 0;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) divx += G[c][c];
+                    T F[3][3];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                        for (int d = 0; d < DIM; ++d) {
+                            if constexpr (MODE == Mode::Jac)
+                                F[c][d] = A.nu * G[c][d] - xh[c] * v[d] - v[c] * xh[d];
+                            else
+                                F[c][d] = A.nu * G[c][d] - xh[c] * xh[d];
+                            if (c == d) F[c][d] -= ph;
+                        }
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                        for (int jd = 0; jd < DIM; ++jd) {
+                            T s = 0;
+#pragma unroll
+                            for (int d = 0; d < DIM; ++d) s += F[c][d] * Jit[d][jd];
+                            outv[j][c * DIM + jd] = s * sc;
+                        }
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) outv[j][DIM * DIM + c] = jxw * xm[c];
+                    outv[j][DIM * DIM + DIM] = -sc * divx;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int q = tid + j * NTH;
+            if (q < NQV) {
+#pragma unroll
+                for (int f = 0; f < NOUT; ++f) Q[f * NQV + q] = outv[j][f];
+            }
+        }
+        __syncthreads();
+
+        // ---- transposed collocation: Y_c = val_c + sum_j Dq_j^T F[c][j] -------------
+        {
+            T yv[QPT][3];
+#pragma unroll
+            for (int j = 0; j < QPT; ++j) {
+                const int q = tid + j * NTH;
+                if (q < NQV) {
+                    const int qi[3] = {q % NQ, (q / NQ) % NQ, DIM == 3 ? q / (NQ * NQ) : 0};
+                    const int strides[3] = {1, NQ, NQ * NQ};
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        T s = Q[(DIM * DIM + c) * NQV + q];
+                        if constexpr (MODE != Mode::Mass) {
+#pragma unroll
+                            for (int jd = 0; jd < DIM; ++jd) {
+                                const int base = q - qi[jd] * strides[jd];
+#pragma unroll
+                                for (int m = 0; m < NQ; ++m)
+                                    s += Dqt[qi[jd] * NQ + m] * Q[(c * DIM + jd) * NQV + base + m * strides[jd]];
+                            }
+                        }
+                        yv[j][c] = s;
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < QPT; ++j) {
+                const int q = tid + j * NTH;
+                if (q < NQV) {
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) Q[c * NQV + q] = yv[j][c];
+                }
+            }
+            __syncthreads();
+        }
+        // backward sweeps to the nodes / pressure modes
+        sweep<DIM, DIM, NQ, NQ, NQ2, N1, N1, N12, false>(Q, NQV, ys, NL, t1, t2, St, St, St);
+        sweep<DIM, 1, NQ, NQ, NQ2, RP1, RP1, RP12, false>(Q + (DIM * DIM + DIM) * NQV, NQV, ypf, NPF, t1, t2,
+                                                          Lpt, Lpt, Lpt);
+
+        // ---- boundary faces ----------------------------------------------------------
+        if constexpr (MODE != Mode::Mass) {
+            if (bnd) {
+                for (int ax = 0; ax < DIM; ++ax) {
+                    for (int side = 0; side < 2; ++side) {
+                        const int cc = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
+                        const int nn = ax == 0 ? A.n0 : (ax == 1 ? A.n1 : A.n2);
+                        if (!(side == 0 ? cc == 0 : cc == nn - 1)) continue;
+                        const int fid = 2 * ax + side;
+                        const bool isD = (A.dmask >> fid) & 1u;
+                        // face record (each field NQF long):
+                        //   inputs : [0,D) xhat, [D, D+D^2) ref grad (c*D+j), [D+D^2, 2D+D^2) v, p
+                        //   outputs: value coef (D), ref-grad test coef (D^2), pressure test coef
+                        constexpr int FV = 0, FG = DIM, FS = DIM + DIM * DIM, FP = 2 * DIM + DIM * DIM;
+                        constexpr int FO = 2 * DIM + DIM * DIM + 1;
+                        T *FQ = Q;
+                        const T *Srow = Se + side * N1, *Drow = De + side * N1, *Lrow = Lpe + side * RP1;
+#define FACE_SWEEP(NFLD, INP, IS, OUTP, OS, M0, M1, M2, I0_, I1_, I2_)                                      \
+    do {                                                                                                     \
+        if (ax == 0)                                                                                         \
+            sweep<DIM, NFLD, I0_, I1_, I2_, 1, NQ, NQ2, false>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);       \
+        else if (ax == 1)                                                                                    \
+            sweep<DIM, NFLD, I0_, I1_, I2_, NQ, 1, NQ2, false>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);       \
+        else                                                                                                 \
+            sweep<DIM, NFLD, I0_, I1_, I2_, NQ, NQ, 1, false>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);        \
+    } while (0)
+#define FACE_SWEEP_T(NFLD, INP, IS, OUTP, OS, M0, M1, M2, O0_, O1_, O2_)                                    \
+    do {                                                                                                     \
+        if (ax == 0)                                                                                         \
+            sweep<DIM, NFLD, 1, NQ, NQ2, O0_, O1_, O2_, true>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);        \
+        else if (ax == 1)                                                                                    \
+            sweep<DIM, NFLD, NQ, 1, NQ2, O0_, O1_, O2_, true>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);        \
+        else                                                                                                 \
+            sweep<DIM, NFLD, NQ, NQ, 1, O0_, O1_, O2_, true>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);         \
+    } while (0)
+                        {
+                            const T *m0 = ax == 0 ? Srow : S, *m1 = ax == 1 ? Srow : S, *m2 = ax == 2 ? Srow : S;
+                            FACE_SWEEP(DIM, xs + a * DIM * NL, NL, FQ + FV * NQF, NQF, m0, m1, m2, N1, N1, N12);
+                            if constexpr (MODE == Mode::Jac)
+                                FACE_SWEEP(DIM, ns, NL, FQ + FS * NQF, NQF, m0, m1, m2, N1, N1, N12);
+                            for (int jd = 0; jd < DIM; ++jd) {
+                                const T *d0 = ax == 0 ? (jd == 0 ? Drow : Srow) : (jd == 0 ? D : S);
+                                const T *d1 = ax == 1 ? (jd == 1 ? Drow : Srow) : (jd == 1 ? D : S);
+                                const T *d2 = ax == 2 ? (jd == 2 ? Drow : Srow) : (jd == 2 ? D : S);
+                                for (int c = 0; c < DIM; ++c)
+                                    FACE_SWEEP(1, xs + (a * DIM + c) * NL, NL, FQ + (FG + c * DIM + jd) * NQF, NQF,
+                                               d0, d1, d2, N1, N1, N12);
+                            }
+                            const T *p0 = ax == 0 ? Lrow : Lp, *p1 = ax == 1 ? Lrow : Lp, *p2 = ax == 2 ? Lrow : Lp;
+                            FACE_SWEEP(1, xpf + a * NPF, NPF, FQ + FP * NQF, NQF, p0, p1, p2, RP1, RP1, RP12);
+                        }
+                        const T hf = hF[fid];
+                        for (int q = tid; q < NQF; q += NTH) {
+                            const int tq[2] = {q % NQ, DIM == 3 ? q / NQ : 0};
+                            T xi[3] = {0, 0, 0}, Jit[3][3], wt = 1;
+                            {
+                                int t = 0;
+                                for (int d = 0; d < DIM; ++d) {
+                                    if (d == ax) xi[d] = T(side);
+                                    else { xi[d] = qx[tq[t]]; wt *= qw[tq[t]]; ++t; }
+                                }
+                            }
+                            const T det = geometry<DIM>(mapped, geo, xi, hcar, Jit);
+                            const T sg = side ? T(1) : T(-1);
+                            T nv[3] = {0, 0, 0}, len = 0;
+                            for (int d = 0; d < DIM; ++d) {
+                                nv[d] = sg * Jit[d][ax];
+                                len += nv[d] * nv[d];
+                            }
+                            len = sqrt(len);
+                            wt *= fabs(det) * len;
+                            for (int d = 0; d < DIM; ++d) nv[d] /= len;
+                            T xh[3] = {0, 0, 0}, v[3] = {0, 0, 0}, G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+                            for (int c = 0; c < DIM; ++c) {
+                                xh[c] = FQ[(FV + c) * NQF + q];
+                                if constexpr (MODE == Mode::Jac) v[c] = FQ[(FS + c) * NQF + q];
+                                else v[c] = xh[c];
+                                for (int d = 0; d < DIM; ++d) {
+                                    T s = 0;
+                                    for (int jd = 0; jd < DIM; ++jd) s += Jit[d][jd] * FQ[(FG + c * DIM + jd) * NQF + q];
+                                    G[c][d] = s;
+                                }
+                            }
+                            const T ph = FQ[FP * NQF + q];
+                            T vn = 0, xn = 0;
+                            for (int d = 0; d < DIM; ++d) {
+                                vn += v[d] * nv[d];
+                                xn += xh[d] * nv[d];
+                            }
+                            T val[3] = {0, 0, 0}, gco[3] = {0, 0, 0}, pco = 0;
+                            if constexpr (MODE == Mode::Jac) {
+                                // <(xv.n) v + (v.n) xv, z>_Gamma
+                                for (int c = 0; c < DIM; ++c) val[c] = xn * v[c] + vn * xh[c];
+                                if (isD) {
+                                    const T om = ominus(vn), dom = dominus(vn);
+                                    const T pen1 = A.nu * A.g1 / hf, pen2 = A.g2 / hf;
+                                    for (int c = 0; c < DIM; ++c) {
+                                        T gn = 0;
+                                        for (int d = 0; d < DIM; ++d) gn += G[c][d] * nv[d];
+                                        val[c] += -A.nu * gn + ph * nv[c] - dom * xn * v[c] - om * xh[c] +
+                                                  pen1 * xh[c] + pen2 * xn * nv[c];
+                                        gco[c] = -A.nu * xh[c];
+                                    }
+                                    pco = xn;
+                                }
+                            } else {
+                                for (int c = 0; c < DIM; ++c) val[c] = vn * v[c];
+                                if (isD) {
+                                    const T om = ominus(vn);
+                                    const T pen1 = A.nu * A.g1 / hf, pen2 = A.g2 / hf;
+                                    for (int c = 0; c < DIM; ++c) {
+                                        T gn = 0;
+                                        for (int d = 0; d < DIM; ++d) gn += G[c][d] * nv[d];
+                                        val[c] += -A.nu * gn + ph * nv[c] - om * v[c] + pen1 * v[c] + pen2 * vn * nv[c];
+                                        gco[c] = -A.nu * v[c];
+                                    }
+                                    pco = vn;
+                                }
+                            }
+                            const T sc = wa * wt;
+                            for (int c = 0; c < DIM; ++c) FQ[(FO + c) * NQF + q] = sc * val[c];
+                            for (int c = 0; c < DIM; ++c)
+                                for (int jd = 0; jd < DIM; ++jd) {
+                                    T jn = 0;
+                                    for (int d = 0; d < DIM; ++d) jn += nv[d] * Jit[d][jd];
+                                    FQ[(FO + DIM + c * DIM + jd) * NQF + q] = sc * gco[c] * jn;
+                                }
+                            FQ[(FO + DIM + DIM * DIM) * NQF + q] = sc * pco;
+                        }
+                        __syncthreads();
+                        {
+                            // transposes: the 1-row normal matrix acts as an N1 x 1 column
+                            const T *m0 = ax == 0 ? Srow : St, *m1 = ax == 1 ? Srow : St, *m2 = ax == 2 ? Srow : St;
+                            FACE_SWEEP_T(DIM, FQ + FO * NQF, NQF, ys, NL, m0, m1, m2, N1, N1, N12);
+                            for (int jd = 0; jd < DIM; ++jd) {
+                                const T *d0 = ax == 0 ? (jd == 0 ? Drow : Srow) : (jd == 0 ? Dt : St);
+                                const T *d1 = ax == 1 ? (jd == 1 ? Drow : Srow) : (jd == 1 ? Dt : St);
+                                const T *d2 = ax == 2 ? (jd == 2 ? Drow : Srow) : (jd == 2 ? Dt : St);
+                                for (int c = 0; c < DIM; ++c)
+                                    FACE_SWEEP_T(1, FQ + (FO + DIM + c * DIM + jd) * NQF, NQF, ys + c * NL, NL, d0,
+                                                 d1, d2, N1, N1, N12);
+                            }
+                            const T *p0 = ax == 0 ? Lrow : Lpt, *p1 = ax == 1 ? Lrow : Lpt, *p2 = ax == 2 ? Lrow : Lpt;
+                            FACE_SWEEP_T(1, FQ + (FO + DIM + DIM * DIM) * NQF, NQF, ypf, NPF, p0, p1, p2, RP1, RP1,
+                                         RP12);
+                        }
+#undef FACE_SWEEP
+#undef FACE_SWEEP_T
+                    }
+                }
+            }
+        }
+
+        // ---- write results ---------------------------------------------------------
+        T *Ec = E + ((long long)cell * nt + a) * DIM * NL;
+        for (int e = tid; e < DIM * NL; e += NTH) Ec[e] = ys[e];
+        for (int e = tid; e < NPM; e += NTH) {
+            const long long gi = pbase + a * A.Np1 + (long long)cell * NPM + e;
+            T val = ypf[pmode_full<DIM, R>(e)];
+            if constexpr (MODE == Mode::Res) {
+                if (A.rhs) val -= A.rhs[gi];
+            }
+            y[gi] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gather of the cell-local velocity results: y[a][c][node] = sum over the (up
+// to 2^d) cells holding the node, in a fixed order; minus rhs if given.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void gather_kernel(GatherArgs<T> G)
+{
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long total = (long long)G.nt * G.Nv1;
+    if (idx >= total) return;
+    const int vec = blockIdx.y;
+    const T *E = G.E + (long long)vec * G.nt * G.Nv1 / G.Nv1 * 0;   // offset below
+    long long node = idx % G.Nn;
+    long long ac = idx / G.Nn;              // a*dim + c
+    int c = (int)(ac % G.dim);
+    int a = (int)(ac / G.dim);
+    int r1 = G.r + 1, n1 = G.r + 2;
+    long long N0 = (long long)r1 * G.n0 + 1, N1 = (long long)r1 * G.n1 + 1;
+    long long g0 = node % N0, g1 = (node / N0) % N1, g2 = G.dim == 3 ? node / (N0 * N1) : 0;
+    long long gg[3] = {g0, g1, g2};
+    int ncells[3] = {G.n0, G.n1, G.n2};
+    int cl[3][2], ll[3][2], cnt[3];
+    for (int d = 0; d < 3; ++d) {
+        if (d >= G.dim) { cnt[d] = 1; cl[d][0] = 0; ll[d][0] = 0; continue; }
+        long long cc = gg[d] / r1;
+        int l = (int)(gg[d] % r1);
+        cnt[d] = 0;
+        if (l == 0 && cc > 0) { cl[d][cnt[d]] = (int)cc - 1; ll[d][cnt[d]] = r1; ++cnt[d]; }
+        if (cc < ncells[d]) { cl[d][cnt[d]] = (int)cc; ll[d][cnt[d]] = l; ++cnt[d]; }
+    }
+    long long ncell = (long long)G.n0 * G.n1 * (G.dim == 3 ? G.n2 : 1);
+    const T *Ev = G.E + (long long)vec * ncell * G.nt * G.dim * G.nl;
+    (void)E;
+    T s = 0;
+    for (int i2 = 0; i2 < cnt[2]; ++i2)
+        for (int i1 = 0; i1 < cnt[1]; ++i1)
+            for (int i0 = 0; i0 < cnt[0]; ++i0) {
+                long long cell = cl[0][i0] + (long long)G.n0 * (cl[1][i1] + (long long)G.n1 * cl[2][i2]);
+                int l = ll[0][i0] + n1 * (ll[1][i1] + n1 * ll[2][i2]);
+                s += Ev[((cell * G.nt + a) * G.dim + c) * G.nl + l];
+            }
+    T *y = G.y + vec * G.ystride;
+    if (G.rhs) s -= G.rhs[idx];
+    y[idx] = s;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int DIM, int R, int NQ, typename T, Mode MODE>
+static hipError_t launch_one(const CellArgs<T> &a, int nvec, hipStream_t s)
+{
+    constexpr int NTH = DIM == 2 ? 64 : 128;
+    TableLayout lay;
+    lay.init(R, NQ);
+    size_t bytes = (size_t)lds_words<DIM, R, NQ, T>(a.nt, lay.total) * sizeof(T);
+    auto kern = cell_kernel<DIM, R, NQ, NTH, T, MODE>;
+    static size_t attr_bytes = 0;
+    static int max_lds = -1;
+    if (max_lds < 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            max_lds = 65536;
+    }
+    if (bytes > (size_t)max_lds) return hipErrorInvalidConfiguration;
+    if (bytes > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        attr_bytes = bytes;
+    }
+    dim3 grid(a.ncell, nvec);
+    hipLaunchKernelGGL(kern, grid, dim3(NTH), bytes, s, a);
+    return hipGetLastError();
+}
+
+template <int DIM, int R, typename T, Mode MODE>
+static hipError_t dispatch_nq(int nq, const CellArgs<T> &a, int nvec, hipStream_t s)
+{
+    constexpr int NQD = (3 * R + 5) / 2;
+    if (nq == NQD) return launch_one<DIM, R, NQD, T, MODE>(a, nvec, s);
+    if constexpr (R + 2 != NQD) {
+        if (nq == R + 2) return launch_one<DIM, R, R + 2, T, MODE>(a, nvec, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int DIM, typename T, Mode MODE>
+static hipError_t dispatch_r(int r, int nq, const CellArgs<T> &a, int nvec, hipStream_t s)
+{
+    switch (r) {
+    case 1: return dispatch_nq<DIM, 1, T, MODE>(nq, a, nvec, s);
+    case 2: return dispatch_nq<DIM, 2, T, MODE>(nq, a, nvec, s);
+    case 3: return dispatch_nq<DIM, 3, T, MODE>(nq, a, nvec, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_cell_op(Mode mode, int dim, int r, int nq, const CellArgs<T> &a, int nvec, hipStream_t s)
+{
+    if (dim == 2) {
+        if (mode == Mode::Jac) return dispatch_r<2, T, Mode::Jac>(r, nq, a, nvec, s);
+        if (mode == Mode::Mass) return dispatch_r<2, T, Mode::Mass>(r, nq, a, nvec, s);
+        if constexpr (std::is_same<T, double>::value) return dispatch_r<2, T, Mode::Res>(r, nq, a, nvec, s);
+    } else {
+        if (mode == Mode::Jac) return dispatch_r<3, T, Mode::Jac>(r, nq, a, nvec, s);
+        if (mode == Mode::Mass) return dispatch_r<3, T, Mode::Mass>(r, nq, a, nvec, s);
+        if constexpr (std::is_same<T, double>::value) return dispatch_r<3, T, Mode::Res>(r, nq, a, nvec, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_gather(const GatherArgs<T> &g, int nvec, hipStream_t s)
+{
+    long long total = (long long)g.nt * g.Nv1;
+    int threads = 256;
+    dim3 grid((unsigned)((total + threads - 1) / threads), nvec);
+    hipLaunchKernelGGL(gather_kernel<T>, grid, dim3(threads), 0, s, g);
+    return hipGetLastError();
+}
+
+template hipError_t launch_cell_op<double>(Mode, int, int, int, const CellArgs<double> &, int, hipStream_t);
+template hipError_t launch_cell_op<float>(Mode, int, int, int, const CellArgs<float> &, int, hipStream_t);
+template hipError_t launch_gather<double>(const GatherArgs<double> &, int, hipStream_t);
+template hipError_t launch_gather<float>(const GatherArgs<float> &, int, hipStream_t);
+
+} // namespace stmg

@@ -1,0 +1,86 @@
+// Context and level data of the stmg library (internal).
+#pragma once
+
+#include "../../include/stmg.h"
+#include "stmg_internal.h"
+
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace stmg {
+
+struct HipError : std::runtime_error {
+    int code;
+    HipError(const std::string &m, int c) : std::runtime_error(m), code(c) {}
+};
+
+#define STMG_HIP(call)                                                                                       \
+    do {                                                                                                     \
+        hipError_t e_ = (call);                                                                              \
+        if (e_ != hipSuccess)                                                                                \
+            throw ::stmg::HipError(std::string(#call) + ": " + hipGetErrorString(e_), STMG_EHIP);           \
+    } while (0)
+
+// device allocation owned by a context
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t b) { alloc(b); }
+    void alloc(size_t b)
+    {
+        release();
+        if (b == 0) return;
+        if (hipMalloc(&p, b) != hipSuccess) {
+            p = nullptr;
+            throw HipError("device allocation of " + std::to_string(b) + " bytes failed", STMG_ENOMEM);
+        }
+        bytes = b;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    ~DevBuf() { release(); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// one level of the hp hierarchy: (k, r) and a structured mesh
+struct Level {
+    int dim = 3, n[3] = {1, 1, 1}, r = 1, k = 0, nq = 4, npm = 1, nt = 1;
+    unsigned dmask = 0;
+    double nu = 1, tau = 1, g1 = 10, g2 = 10;
+    bool mapped = false;
+    long long ncell = 0, Nn = 0, Nv1 = 0, Np1 = 0, N = 0;
+    int nl = 0;                      // (r+2)^d
+    TimeCoefs tc{};
+    TableLayout lay{};
+    std::vector<double> vert_host;   // vertices (if mapped)
+    DevBuf vert, tab64, tab32, E64, E32;
+
+    void init(const stmg_problem &p, int k_, int r_, int nx, int ny, int nz, int nq_,
+              const std::vector<double> &verts);
+    template <typename T> CellArgs<T> cell_args() const;
+    template <typename T> GatherArgs<T> gather_args() const;
+    // apply one of the cell operators (Jacobian, residual, mass) on stream s
+    template <typename T>
+    void apply(Mode mode, const T *state, const T *x, T *y, const T *rhs, const T *vprev, int nvec, hipStream_t s);
+};
+
+} // namespace stmg
+
+struct stmg_ctx {
+    stmg_problem prob{};
+    stmg_options opt{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<std::unique_ptr<stmg::Level>> levels;   // levels[0] = finest
+    stmg::DevBuf rhs, vprev;                            // slab data (FP64)
+    bool has_rhs = false, has_vprev = false;
+};

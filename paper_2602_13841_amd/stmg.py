@@ -1,0 +1,203 @@
+"""Thin ctypes binding of libstmg.so (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module checks tensor
+shapes, dtypes and devices and passes raw device pointers and the current
+torch stream.  There is no fallback: if the library is missing the import of
+the binding fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstmg.so")
+
+STMG_F64 = 0
+STMG_F32 = 1
+STMG_NOT_CONVERGED = 1
+
+
+class StmgError(RuntimeError):
+    pass
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_cells", ctypes.c_int * 3), ("vertices", ctypes.c_void_p),
+                ("r", ctypes.c_int), ("k", ctypes.c_int), ("nu", ctypes.c_double), ("tau", ctypes.c_double),
+                ("dirichlet_faces", ctypes.c_uint), ("gamma1", ctypes.c_double), ("gamma2", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("n_q", ctypes.c_int), ("max_levels", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
+                ("vanka_omega", ctypes.c_double), ("prec_mg", ctypes.c_int),
+                ("newton_rtol", ctypes.c_double), ("newton_atol", ctypes.c_double), ("newton_maxit", ctypes.c_int),
+                ("ew_eta0", ctypes.c_double), ("ew_c", ctypes.c_double), ("ew_theta", ctypes.c_double),
+                ("ew_eta_min", ctypes.c_double), ("ew_eta_max", ctypes.c_double),
+                ("ls_lambda0", ctypes.c_double), ("ls_c", ctypes.c_double), ("ls_tau", ctypes.c_double),
+                ("ls_alpha_min", ctypes.c_double), ("ls_window", ctypes.c_int), ("ls_max_backtracks", ctypes.c_int),
+                ("rb_theta_N", ctypes.c_double), ("rb_theta_L", ctypes.c_double), ("rb_kappa_abs", ctypes.c_double),
+                ("rb_stag_theta", ctypes.c_double), ("rb_stag_s", ctypes.c_int),
+                ("fgmres_maxit", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("newton_its", ctypes.c_int), ("fgmres_its_total", ctypes.c_int),
+                ("fgmres_its", ctypes.c_int * 64), ("rebuilds", ctypes.c_int), ("backtracks", ctypes.c_int),
+                ("res0_M", ctypes.c_double), ("res_M", ctypes.c_double), ("wall_s", ctypes.c_double)]
+
+
+_lib = None
+
+# exported symbols and their argument types
+_SIGS = {
+    "stmg_default_options": (None, [ctypes.c_void_p]),
+    "stmg_footprint_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "stmg_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "stmg_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_set_slab_data": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_jacobian_vmult": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "stmg_jacobian_vmult_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_int]),
+    "stmg_mass_vmult": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise StmgError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            if not hasattr(L, name):
+                continue
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def default_options(**overrides) -> Options:
+    o = Options()
+    lib().stmg_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One slab of the space-time discretization on the current GPU."""
+
+    def __init__(self, dim, n, r, k, nu, tau, vertices=None, dirichlet_faces=None, gamma1=10.0, gamma2=10.0,
+                 options: Options | None = None, **opt_overrides):
+        n = tuple(int(v) for v in (n if hasattr(n, "__len__") else (n,) * dim))
+        p = Problem()
+        p.dim = dim
+        for a in range(3):
+            p.n_cells[a] = n[a] if a < len(n) else 1
+        self._vert = None
+        if vertices is not None:
+            import numpy as np
+            self._vert = np.ascontiguousarray(vertices, dtype=np.float64)
+            p.vertices = self._vert.ctypes.data
+        p.r, p.k, p.nu, p.tau = r, k, nu, tau
+        p.dirichlet_faces = (1 << (2 * dim)) - 1 if dirichlet_faces is None else dirichlet_faces
+        p.gamma1, p.gamma2 = gamma1, gamma2
+        self.problem = p
+        self.options = options if options is not None else default_options(**opt_overrides)
+        h = ctypes.c_void_p()
+        rc = lib().stmg_create(ctypes.byref(p), ctypes.byref(self.options), _stream_ptr(), ctypes.byref(h))
+        if rc != 0:
+            raise StmgError(f"stmg_create failed with code {rc}")
+        self._h = h
+        nt, nv, npr = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+        self._check(lib().stmg_sizes(h, ctypes.byref(nt), ctypes.byref(nv), ctypes.byref(npr)))
+        self.N, self.Nv, self.Np = nt.value, nv.value, npr.value
+        self.dim, self.r, self.k = dim, r, k
+
+    def _check(self, rc):
+        if rc < 0:
+            msg = lib().stmg_last_error(self._h)
+            raise StmgError(f"stmg call failed ({rc}): {msg.decode() if msg else ''}")
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().stmg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, t, dtype, n=None, name="vector"):
+        n = self.N if n is None else n
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise StmgError(f"{name} must be a device tensor")
+        if t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+            raise StmgError(f"{name}: expected contiguous {dtype} with {n} entries, got {t.dtype} {tuple(t.shape)}")
+        return _ptr(t)
+
+    @staticmethod
+    def _prec(dtype):
+        if dtype == torch.float64:
+            return STMG_F64
+        if dtype == torch.float32:
+            return STMG_F32
+        raise StmgError("dtype must be float64 or float32")
+
+    # ---- slab data and operators ----------------------------------------
+    def set_slab_data(self, rhs=None, v_prev=None):
+        pr = self._vec(rhs, torch.float64, name="rhs") if rhs is not None else None
+        pv = self._vec(v_prev, torch.float64, self.Nv // (self.k + 1), "v_prev") if v_prev is not None else None
+        self._check(lib().stmg_set_slab_data(self._h, pr, pv))
+
+    def residual(self, u, out=None):
+        out = torch.empty_like(u) if out is None else out
+        self._check(lib().stmg_residual(self._h, self._vec(u, torch.float64, name="u"),
+                                        self._vec(out, torch.float64, name="r")))
+        return out
+
+    def jacobian_vmult(self, u_state, x, out=None):
+        out = torch.empty_like(x) if out is None else out
+        dt = x.dtype
+        self._check(lib().stmg_jacobian_vmult(self._h, self._prec(dt), self._vec(u_state, dt, name="u_state"),
+                                              self._vec(x, dt, name="x"), self._vec(out, dt, name="y")))
+        return out
+
+    def jacobian_vmult_batched(self, u_state, x, out=None):
+        nvec = x.shape[0]
+        out = torch.empty_like(x) if out is None else out
+        dt = x.dtype
+        if x.shape != (nvec, self.N) or not x.is_contiguous():
+            raise StmgError("x must be (nvec, N) contiguous")
+        self._check(lib().stmg_jacobian_vmult_batched(self._h, self._prec(dt), self._vec(u_state, dt, name="u_state"),
+                                                      _ptr(x), _ptr(out), nvec))
+        return out
+
+    def mass_vmult(self, x, out=None):
+        out = torch.empty_like(x) if out is None else out
+        dt = x.dtype
+        self._check(lib().stmg_mass_vmult(self._h, self._prec(dt), self._vec(x, dt, name="x"),
+                                          self._vec(out, dt, name="y")))
+        return out
