@@ -151,6 +151,15 @@ int stmg_jacobian_vmult_batched(stmg_ctx *ctx, int prec, const void *u_state, co
  * ||.||_M of eq. inexact. */
 int stmg_mass_vmult(stmg_ctx *ctx, int prec, const void *x, void *y);
 
+/* Named kernel timers (hipEvent pairs on the context stream around each
+ * kernel launch, e.g. "cell_jac_f64", "gather_f64", "cell_res_f64",
+ * "cell_mass_f32"); off by default.  stmg_timing_get synchronizes the
+ * recorded events and returns the accumulated milliseconds and the number
+ * of launches of that name since the last reset. */
+int stmg_timing_enable(stmg_ctx *ctx, int on);
+int stmg_timing_reset(stmg_ctx *ctx);
+int stmg_timing_get(stmg_ctx *ctx, const char *name, double *total_ms, long long *count);
+
 #ifdef __cplusplus
 }
 #endif

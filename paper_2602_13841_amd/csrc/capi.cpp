@@ -96,6 +96,7 @@ int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream,
                 ctx->opt.n_q, verts);
         if (L->nq != default_nq(L->r) && L->nq != L->r + 2)
             throw std::runtime_error("n_q must be ceil((3r+4)/2) or r+2");
+        L->timers = &ctx->timers;
         ctx->levels.push_back(std::move(L));
         return STMG_OK;
     });
@@ -207,6 +208,41 @@ int stmg_mass_vmult(stmg_ctx *ctx, int prec, const void *x, void *y)
             L.apply<float>(Mode::Mass, nullptr, (const float *)x, (float *)y, nullptr, nullptr, 1, ctx->stream);
         else
             return fail(ctx, STMG_EINVAL, "prec must be STMG_F64 or STMG_F32");
+        return STMG_OK;
+    });
+}
+
+int stmg_timing_enable(stmg_ctx *ctx, int on)
+{
+    if (!ctx) return STMG_EINVAL;
+    ctx->timers.on = on != 0;
+    return STMG_OK;
+}
+
+int stmg_timing_reset(stmg_ctx *ctx)
+{
+    if (!ctx) return STMG_EINVAL;
+    return guarded(ctx, [&]() {
+        ctx->timers.flush();
+        ctx->timers.acc.clear();
+        return STMG_OK;
+    });
+}
+
+int stmg_timing_get(stmg_ctx *ctx, const char *name, double *total_ms, long long *count)
+{
+    if (!ctx || !name) return STMG_EINVAL;
+    return guarded(ctx, [&]() {
+        ctx->timers.flush();
+        double t = 0;
+        long long c = 0;
+        for (auto &kv : ctx->timers.acc)
+            if (kv.first == name) {
+                t = kv.second.first;
+                c = kv.second.second;
+            }
+        if (total_ms) *total_ms = t;
+        if (count) *count = c;
         return STMG_OK;
     });
 }

@@ -51,6 +51,80 @@ struct DevBuf {
     template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
 };
 
+// Named device timers: hipEvent pairs recorded on the launching stream around
+// kernels, accumulated per name when read back.  Off unless enabled.
+struct Timers {
+    bool on = false;
+    struct Rec {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<std::string, std::pair<double, long long>>> acc;
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        STMG_HIP(hipEventCreate(&e));
+        return e;
+    }
+    int begin(const char *name, hipStream_t s)
+    {
+        if (!on) return -1;
+        Rec r{name, get(), get()};
+        STMG_HIP(hipEventRecord(r.a, s));
+        pending.push_back(r);
+        return (int)pending.size() - 1;
+    }
+    void end(int idx, hipStream_t s)
+    {
+        if (idx >= 0) STMG_HIP(hipEventRecord(pending[idx].b, s));
+    }
+    void flush()
+    {
+        for (auto &r : pending) {
+            STMG_HIP(hipEventSynchronize(r.b));
+            float ms = 0;
+            STMG_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+            bool found = false;
+            for (auto &kv : acc)
+                if (kv.first == r.name) {
+                    kv.second.first += ms;
+                    kv.second.second += 1;
+                    found = true;
+                }
+            if (!found) acc.push_back({r.name, {double(ms), 1LL}});
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+    ~Timers()
+    {
+        for (auto &r : pending) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+struct TimerScope {
+    Timers *t;
+    int idx;
+    hipStream_t s;
+    TimerScope(Timers *t_, const char *name, hipStream_t s_) : t(t_), idx(t_ ? t_->begin(name, s_) : -1), s(s_) {}
+    ~TimerScope()
+    {
+        if (t && idx >= 0) t->end(idx, s);
+    }
+};
+
 // one level of the hp hierarchy: (k, r) and a structured mesh
 struct Level {
     int dim = 3, n[3] = {1, 1, 1}, r = 1, k = 0, nq = 4, npm = 1, nt = 1;
@@ -63,6 +137,7 @@ struct Level {
     TableLayout lay{};
     std::vector<double> vert_host;   // vertices (if mapped)
     DevBuf vert, tab64, tab32, E64, E32;
+    Timers *timers = nullptr;
 
     void init(const stmg_problem &p, int k_, int r_, int nx, int ny, int nz, int nq_,
               const std::vector<double> &verts);
@@ -83,4 +158,5 @@ struct stmg_ctx {
     std::vector<std::unique_ptr<stmg::Level>> levels;   // levels[0] = finest
     stmg::DevBuf rhs, vprev;                            // slab data (FP64)
     bool has_rhs = false, has_vprev = false;
+    stmg::Timers timers;
 };

@@ -114,13 +114,22 @@ void Level::apply(Mode mode, const T *state, const T *x, T *y, const T *rhs, con
     a.xstride = N;
     a.ystride = N;
     a.sstride = 0;
-    STMG_HIP(launch_cell_op<T>(mode, dim, r, nq, a, nvec, s));
+    static const char *names64[3] = {"cell_jac_f64", "cell_res_f64", "cell_mass_f64"};
+    static const char *names32[3] = {"cell_jac_f32", "cell_res_f32", "cell_mass_f32"};
+    const char *nm = std::is_same<T, double>::value ? names64[(int)mode] : names32[(int)mode];
+    {
+        TimerScope ts(timers, nm, s);
+        STMG_HIP(launch_cell_op<T>(mode, dim, r, nq, a, nvec, s));
+    }
     GatherArgs<T> g = gather_args<T>();
     g.E = Eb.as<T>();
     g.rhs = rhs;
     g.y = y;
     g.ystride = N;
-    STMG_HIP(launch_gather<T>(g, nvec, s));
+    {
+        TimerScope ts(timers, std::is_same<T, double>::value ? "gather_f64" : "gather_f32", s);
+        STMG_HIP(launch_gather<T>(g, nvec, s));
+    }
 }
 
 template CellArgs<double> Level::cell_args<double>() const;

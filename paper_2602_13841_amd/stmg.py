@@ -66,6 +66,9 @@ _SIGS = {
     "stmg_jacobian_vmult_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.c_void_p, ctypes.c_int]),
     "stmg_mass_vmult": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "stmg_timing_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "stmg_timing_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -194,6 +197,18 @@ class Context:
         self._check(lib().stmg_jacobian_vmult_batched(self._h, self._prec(dt), self._vec(u_state, dt, name="u_state"),
                                                       _ptr(x), _ptr(out), nvec))
         return out
+
+    # ---- kernel timers -----------------------------------------------------
+    def timing(self, on: bool = True):
+        self._check(lib().stmg_timing_enable(self._h, 1 if on else 0))
+
+    def timing_reset(self):
+        self._check(lib().stmg_timing_reset(self._h))
+
+    def timing_get(self, name: str):
+        ms, cnt = ctypes.c_double(), ctypes.c_longlong()
+        self._check(lib().stmg_timing_get(self._h, name.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
 
     def mass_vmult(self, x, out=None):
         out = torch.empty_like(x) if out is None else out
