@@ -81,7 +81,7 @@ typedef struct {
     int n_q;                  /* Gauss points per direction; 0 = ceil((3r+4)/2) */
     int max_levels;           /* multigrid levels cap; 0 = coarsen to 2^d cells */
     int nu1, nu2;             /* pre/post smoothing steps (1, 1) */
-    double vanka_omega;       /* relaxation omega of eq. LVS */
+    double vanka_omega;       /* relaxation omega of eq. LVS; 0 = 1.4 / 2^d */
     int prec_mg;              /* stmg_prec of the multigrid preconditioner */
     /* Newton (Alg. "Inexact Newton-Krylov") */
     double newton_rtol, newton_atol;
@@ -150,6 +150,72 @@ int stmg_jacobian_vmult_batched(stmg_ctx *ctx, int prec, const void *u_state, co
 /* y = blockdiag(M^tau (x) M_h, M^tau (x) M_h^p) x: the weight of the norm
  * ||.||_M of eq. inexact. */
 int stmg_mass_vmult(stmg_ctx *ctx, int prec, const void *x, void *y);
+
+/* ---- hp space-time multigrid (Sec. "Preconditioning of GMRES by hp
+ * space-time multigrid") ----------------------------------------------------
+ * Levels: 0 = the slab itself; p-coarsening first, (k, r) -> (k//2 if k >= 2
+ * else k, max(1, r//2)), then h-coarsening of the mesh while every n_cells
+ * is even and >= 4 (capped by opt.max_levels).  Level vectors use the slab
+ * layout of their own (k, r, n_cells). */
+int stmg_num_levels(const stmg_ctx *ctx);
+int stmg_level_info(const stmg_ctx *ctx, int level, int *k, int *r, int *n_cells, long long *n_total);
+
+/* Set the Newton state U (FP64, device, length N): the level states (finer
+ * state evaluated at the coarser nodes and Radau nodes) and the FP64 LU of
+ * the coarsest level Jacobian (bordered by the constant pressures of each
+ * time node when every face is Dirichlet). */
+int stmg_set_state(stmg_ctx *ctx, const double *u_state);
+/* Copy of the state of a level (FP64 slab vector of that level). */
+int stmg_level_state(stmg_ctx *ctx, int level, double *out);
+
+/* Set the state and rebuild the inexact space-time Vanka smoother on every
+ * level but the coarsest (eq. DefTildeHn, eq. DefVnAst: the spatial core at
+ * the midpoint value V* = sum_a phi_a(t*) V^a, shared by all time nodes;
+ * patch = all unknowns of one cell at all time nodes; local matrix = the
+ * principal submatrix of the surrogate; LU with partial pivoting in the
+ * multigrid precision). */
+int stmg_smoother_rebuild(stmg_ctx *ctx, const double *u_state);
+
+/* y = J_level x at the level state (FP64, or FP32 if the multigrid runs in
+ * FP32). */
+int stmg_level_jacobian_vmult(stmg_ctx *ctx, int level, int prec, const void *x, void *y);
+
+/* `sweeps` additive Vanka sweeps on a level (eq. vanka0):
+ *   d <- d + omega sum_K R_K^T S_K^{-1} R_K (r - J_level d).
+ * r, d: device slab vectors of that level in the multigrid precision
+ * (prec must equal opt.prec_mg); d is updated in place.  STMG_ESTATE if the
+ * smoother has not been built. */
+int stmg_vanka_smooth(stmg_ctx *ctx, int level, int prec, const void *r, void *d, int sweeps);
+
+/* d = B r: one V-cycle from a zero initial guess (nu1 pre- and nu2
+ * post-smoothing sweeps, restriction = transpose of the canonical-embedding
+ * prolongation, coarsest level solved directly), in the multigrid
+ * precision on the finest-level slab vectors. */
+int stmg_vcycle(stmg_ctx *ctx, int prec, const void *r, void *d);
+
+/* Grid transfers between level and level+1 (slab vectors of the two
+ * levels): y_fine = P x_coarse (eq. MatGeomProl and the polynomial
+ * prolongation), y_coarse = P^T x_fine. */
+int stmg_prolongate(stmg_ctx *ctx, int level, int prec, const void *xc, void *yf);
+int stmg_restrict(stmg_ctx *ctx, int level, int prec, const void *xf, void *yc);
+
+/* Right-preconditioned flexible GMRES on J(u_state) x = b (FP64, zero
+ * initial guess, Arnoldi in the M inner product, preconditioner = one
+ * V-cycle), stopped when the M-norm residual estimate is <= rtol ||b||_M or
+ * after maxit iterations.  its: iterations; hist: its+1 residual estimates
+ * (host array, may be NULL).  Needs a built smoother.  Returns
+ * STMG_NOT_CONVERGED at the iteration limit. */
+int stmg_fgmres(stmg_ctx *ctx, const double *u_state, const double *b, double *x, double rtol, int maxit, int *its,
+                double *hist);
+
+/* Solve the slab problem R_n(U; V_{n-1}) = 0 (eq. InAlgNS) by the inexact
+ * Newton method of Alg. "Inexact Newton-Krylov" with Alg. "Armijo":
+ * Eisenstat-Walker forcing, nonmonotone Armijo backtracking, smoother
+ * rebuilds on Newton/linear deterioration and FGMRES stagnation, FGMRES
+ * preconditioned by one hp-STMG V-cycle.  u_inout: initial guess in,
+ * solution out (device, FP64).  Stops when ||R||_M <= max(atol, rtol
+ * ||R_0||_M).  stats may be NULL. */
+int stmg_newton_gmres_solve(stmg_ctx *ctx, double *u_inout, stmg_stats *stats);
 
 /* Named kernel timers (hipEvent pairs on the context stream around each
  * kernel launch, e.g. "cell_jac_f64", "gather_f64", "cell_res_f64",

@@ -79,7 +79,8 @@ def _lattice_index(node, N):
 
 def _locate(g, r, ncell):
     """Cell and Gauss-Lobatto local index of lattice coordinate g along one axis
-    (nodes on a cell interface are assigned to the lower cell)."""
+    (a node on a cell interface is assigned to the cell above it, the last
+    node to the last cell)."""
     c = g // (r + 1)
     loc = g - (r + 1) * c
     if c >= ncell:

@@ -1,5 +1,5 @@
 // extern "C" entry points of the stmg library.
-#include "context.h"
+#include "mg.h"
 
 #include <cstring>
 
@@ -48,7 +48,7 @@ void stmg_default_options(stmg_options *o)
     o->max_levels = 0;
     o->nu1 = 1;
     o->nu2 = 1;
-    o->vanka_omega = 0.7;
+    o->vanka_omega = 0.0;
     o->prec_mg = STMG_F32;
     o->newton_rtol = 1e-8;
     o->newton_atol = 1e-12;
@@ -98,6 +98,7 @@ int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream,
             throw std::runtime_error("n_q must be ceil((3r+4)/2) or r+2");
         L->timers = &ctx->timers;
         ctx->levels.push_back(std::move(L));
+        mg_build(ctx);
         return STMG_OK;
     });
     if (rc != STMG_OK) {
@@ -210,6 +211,147 @@ int stmg_mass_vmult(stmg_ctx *ctx, int prec, const void *x, void *y)
             return fail(ctx, STMG_EINVAL, "prec must be STMG_F64 or STMG_F32");
         return STMG_OK;
     });
+}
+
+int stmg_num_levels(const stmg_ctx *ctx)
+{
+    return ctx ? (int)ctx->levels.size() : STMG_EINVAL;
+}
+
+int stmg_level_info(const stmg_ctx *ctx, int level, int *k, int *r, int *n_cells, long long *n_total)
+{
+    if (!ctx || level < 0 || level >= (int)ctx->levels.size()) return STMG_EINVAL;
+    const Level &L = *ctx->levels[level];
+    if (k) *k = L.k;
+    if (r) *r = L.r;
+    if (n_cells)
+        for (int a = 0; a < 3; ++a) n_cells[a] = L.n[a];
+    if (n_total) *n_total = L.N;
+    return STMG_OK;
+}
+
+static bool check_prec(stmg_ctx *ctx, int prec)
+{
+    return prec == ctx->mg->prec;
+}
+
+int stmg_set_state(stmg_ctx *ctx, const double *u_state)
+{
+    if (!ctx || !u_state) return fail(ctx, STMG_EINVAL, "NULL argument");
+    return guarded(ctx, [&]() {
+        mg_set_state(ctx, u_state);
+        return STMG_OK;
+    });
+}
+
+int stmg_level_state(stmg_ctx *ctx, int level, double *out)
+{
+    if (!ctx || !out || level < 0 || level >= (int)ctx->levels.size()) return fail(ctx, STMG_EINVAL, "invalid argument");
+    return guarded(ctx, [&]() {
+        if (!ctx->mg->state_set) return fail(ctx, STMG_ESTATE, "no state set");
+        const Level &L = *ctx->levels[level];
+        STMG_HIP(hipMemcpyAsync(out, ctx->mg->lv[level].st64.p, L.N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        return STMG_OK;
+    });
+}
+
+int stmg_smoother_rebuild(stmg_ctx *ctx, const double *u_state)
+{
+    if (!ctx || !u_state) return fail(ctx, STMG_EINVAL, "NULL argument");
+    return guarded(ctx, [&]() {
+        mg_set_state(ctx, u_state);
+        mg_rebuild(ctx);
+        return STMG_OK;
+    });
+}
+
+int stmg_level_jacobian_vmult(stmg_ctx *ctx, int level, int prec, const void *x, void *y)
+{
+    if (!ctx || !x || !y || level < 0 || level >= (int)ctx->levels.size()) return fail(ctx, STMG_EINVAL, "invalid argument");
+    return guarded(ctx, [&]() {
+        if (!ctx->mg->state_set) return fail(ctx, STMG_ESTATE, "no state set");
+        Level &L = *ctx->levels[level];
+        MgLevel &M = ctx->mg->lv[level];
+        if (prec == STMG_F64)
+            L.apply<double>(Mode::Jac, M.st64.as<double>(), (const double *)x, (double *)y, nullptr, nullptr, 1, ctx->stream);
+        else if (prec == STMG_F32 && ctx->mg->prec == STMG_F32)
+            L.apply<float>(Mode::Jac, M.st32.as<float>(), (const float *)x, (float *)y, nullptr, nullptr, 1, ctx->stream);
+        else
+            return fail(ctx, STMG_EINVAL, "precision not available on this context");
+        return STMG_OK;
+    });
+}
+
+int stmg_vanka_smooth(stmg_ctx *ctx, int level, int prec, const void *r, void *d, int sweeps)
+{
+    if (!ctx || !r || !d || level < 0 || level + 1 >= (int)ctx->levels.size() || sweeps < 0)
+        return fail(ctx, STMG_EINVAL, "invalid argument (smoothing runs on every level but the coarsest)");
+    return guarded(ctx, [&]() {
+        if (!check_prec(ctx, prec)) return fail(ctx, STMG_EINVAL, "prec must equal the multigrid precision");
+        if (!ctx->mg->lv[level].have_patches) return fail(ctx, STMG_ESTATE, "smoother not built (call stmg_smoother_rebuild)");
+        for (int i = 0; i < sweeps; ++i) {
+            if (prec == STMG_F64) mg_smooth<double>(ctx, level, (const double *)r, (double *)d);
+            else mg_smooth<float>(ctx, level, (const float *)r, (float *)d);
+        }
+        return STMG_OK;
+    });
+}
+
+int stmg_vcycle(stmg_ctx *ctx, int prec, const void *r, void *d)
+{
+    if (!ctx || !r || !d) return fail(ctx, STMG_EINVAL, "NULL argument");
+    return guarded(ctx, [&]() {
+        if (!check_prec(ctx, prec)) return fail(ctx, STMG_EINVAL, "prec must equal the multigrid precision");
+        if (ctx->levels.size() > 1 && !ctx->mg->lv[0].have_patches)
+            return fail(ctx, STMG_ESTATE, "smoother not built (call stmg_smoother_rebuild)");
+        if (!ctx->mg->state_set) return fail(ctx, STMG_ESTATE, "no state set");
+        if (prec == STMG_F64) mg_vcycle<double>(ctx, 0, (const double *)r, (double *)d);
+        else mg_vcycle<float>(ctx, 0, (const float *)r, (float *)d);
+        return STMG_OK;
+    });
+}
+
+int stmg_prolongate(stmg_ctx *ctx, int level, int prec, const void *xc, void *yf)
+{
+    if (!ctx || !xc || !yf || level < 0 || level + 1 >= (int)ctx->levels.size()) return fail(ctx, STMG_EINVAL, "invalid argument");
+    return guarded(ctx, [&]() {
+        const Level &F = *ctx->levels[level], &C = *ctx->levels[level + 1];
+        if (prec == STMG_F64) ctx->mg->tr[level]->prolongate<double>(F, C, (const double *)xc, (double *)yf, 0.0, ctx->stream);
+        else ctx->mg->tr[level]->prolongate<float>(F, C, (const float *)xc, (float *)yf, 0.0f, ctx->stream);
+        return STMG_OK;
+    });
+}
+
+int stmg_restrict(stmg_ctx *ctx, int level, int prec, const void *xf, void *yc)
+{
+    if (!ctx || !xf || !yc || level < 0 || level + 1 >= (int)ctx->levels.size()) return fail(ctx, STMG_EINVAL, "invalid argument");
+    return guarded(ctx, [&]() {
+        const Level &F = *ctx->levels[level], &C = *ctx->levels[level + 1];
+        if (prec == STMG_F64) ctx->mg->tr[level]->restrict_<double>(F, C, (const double *)xf, (double *)yc, ctx->stream);
+        else ctx->mg->tr[level]->restrict_<float>(F, C, (const float *)xf, (float *)yc, ctx->stream);
+        return STMG_OK;
+    });
+}
+
+int stmg_fgmres(stmg_ctx *ctx, const double *u_state, const double *b, double *x, double rtol, int maxit, int *its,
+                double *hist)
+{
+    if (!ctx || !u_state || !b || !x || maxit < 1) return fail(ctx, STMG_EINVAL, "invalid argument");
+    return guarded(ctx, [&]() {
+        if (ctx->levels.size() > 1 && !ctx->mg->lv[0].have_patches)
+            return fail(ctx, STMG_ESTATE, "smoother not built (call stmg_smoother_rebuild)");
+        FgmresOut o = fgmres(ctx, u_state, b, x, rtol, maxit);
+        if (its) *its = o.its;
+        if (hist)
+            for (size_t i = 0; i < o.hist.size(); ++i) hist[i] = o.hist[i];
+        return o.converged ? STMG_OK : STMG_NOT_CONVERGED;
+    });
+}
+
+int stmg_newton_gmres_solve(stmg_ctx *ctx, double *u_inout, stmg_stats *stats)
+{
+    if (!ctx || !u_inout) return fail(ctx, STMG_EINVAL, "NULL argument");
+    return guarded(ctx, [&]() { return newton_solve(ctx, u_inout, stats); });
 }
 
 int stmg_timing_enable(stmg_ctx *ctx, int on)

@@ -767,7 +767,9 @@ __global__ void gather_kernel(GatherArgs<T> G)
                 s += Ev[((cell * G.nt + a) * G.dim + c) * G.nl + l];
             }
     T *y = G.y + vec * G.ystride;
+    s *= G.alpha;
     if (G.rhs) s -= G.rhs[idx];
+    if (G.accumulate) s += y[idx];
     y[idx] = s;
 }
 

@@ -48,6 +48,22 @@ struct DevBuf {
     ~DevBuf() { release(); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes)
+    {
+        o.p = nullptr;
+        o.bytes = 0;
+    }
+    DevBuf &operator=(DevBuf &&o) noexcept
+    {
+        if (this != &o) {
+            release();
+            p = o.p;
+            bytes = o.bytes;
+            o.p = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
     template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
 };
 
@@ -149,14 +165,3 @@ struct Level {
 };
 
 } // namespace stmg
-
-struct stmg_ctx {
-    stmg_problem prob{};
-    stmg_options opt{};
-    hipStream_t stream = nullptr;
-    std::string err;
-    std::vector<std::unique_ptr<stmg::Level>> levels;   // levels[0] = finest
-    stmg::DevBuf rhs, vprev;                            // slab data (FP64)
-    bool has_rhs = false, has_vprev = false;
-    stmg::Timers timers;
-};

@@ -94,6 +94,8 @@ template <typename T> GatherArgs<T> Level::gather_args() const
     g.Nv1 = Nv1;
     g.Nslab = N;
     g.nl = nl;
+    g.alpha = T(1);
+    g.accumulate = 0;
     return g;
 }
 
@@ -133,6 +135,8 @@ void Level::apply(Mode mode, const T *state, const T *x, T *y, const T *rhs, con
 }
 
 template CellArgs<double> Level::cell_args<double>() const;
+template GatherArgs<double> Level::gather_args<double>() const;
+template GatherArgs<float> Level::gather_args<float>() const;
 template CellArgs<float> Level::cell_args<float>() const;
 template void Level::apply<double>(Mode, const double *, const double *, double *, const double *, const double *,
                                    int, hipStream_t);

@@ -1,0 +1,561 @@
+// hp space-time multigrid (Sec. "Preconditioning of GMRES by hp space-time
+// multigrid"), FGMRES (eq. inexact) and the inexact Newton method with
+// Eisenstat-Walker forcing and nonmonotone Armijo backtracking (Alg.
+// "Inexact Newton-Krylov", Alg. "Armijo").  Host code driving device
+// kernels; control decisions (Givens rotations, stopping tests, line search)
+// use scalars read back once per iteration.
+//
+// Readings where the paper leaves details open:
+// * hierarchy: p-coarsening first, (k, r) -> (k//2 if k >= 2 else k,
+//   max(1, r//2)), then h-coarsening while every n is even and >= 4;
+// * level operators: rediscretized at the finer state evaluated at the
+//   coarser nodes and Radau nodes; the coarsest level is solved directly in
+//   FP64, bordered by the constant pressure of each time node when Gamma_D
+//   is the whole boundary;
+// * smoother relaxation omega = 1.4 / 2^d unless set;
+// * FGMRES: Arnoldi in the M_n inner product, classical Gram-Schmidt with
+//   one reorthogonalization, zero initial guess, no restart;
+// * Newton: Eisenstat-Walker update of Alg. "Inexact Newton-Krylov";
+//   g0 = (M r).(J dU); the nonmonotone window keeps the last accepted merit
+//   values across Newton steps of a slab; interpolated backtracking uses the
+//   quadratic model after the first failure and the cubic model through the
+//   last two failures, clamped to [0.1 alpha, 0.5 alpha]; the rebuild
+//   thresholds theta_N, theta_L, kappa_abs, (s, theta) are options.
+#include "mg.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+namespace stmg {
+
+namespace {
+
+template <typename T> T *state_of(MgLevel &M) { return std::is_same<T, double>::value ? M.st64.as<T>() : M.st32.as<T>(); }
+
+std::vector<double> coarse_vertices(const std::vector<double> &v, int dim, const int n[3])
+{
+    if (v.empty()) return {};
+    std::vector<double> out;
+    int nz = dim == 3 ? n[2] : 0;
+    for (int i2 = 0; i2 <= nz; i2 += 2)
+        for (int i1 = 0; i1 <= n[1]; i1 += 2)
+            for (int i0 = 0; i0 <= n[0]; i0 += 2) {
+                long long idx = i0 + (long long)(n[0] + 1) * (i1 + (long long)(n[1] + 1) * i2);
+                for (int a = 0; a < dim; ++a) out.push_back(v[idx * dim + a]);
+            }
+    return out;
+}
+
+} // namespace
+
+void Krylov::ensure(long long N_, int maxit_)
+{
+    if (N_ == N && maxit_ <= maxit) return;
+    N = N_;
+    maxit = maxit_;
+    V.alloc(sizeof(double) * N * (maxit + 1));
+    MV.alloc(sizeof(double) * N * (maxit + 1));
+    Z.alloc(sizeof(double) * N * maxit);
+    w.alloc(sizeof(double) * N);
+    u.alloc(sizeof(double) * N);
+    h.alloc(sizeof(double) * 3 * (maxit + 2));
+    partial.alloc(sizeof(double) * multidot_partial_words(maxit + 1));
+    y.alloc(sizeof(double) * (maxit + 1));
+    for (DevBuf *b : {&r, &Mr, &dU, &Ut, &rt, &tmp}) b->alloc(sizeof(double) * N);
+    dot.alloc(8 * 8);
+}
+
+void mg_build(stmg_ctx *ctx)
+{
+    auto mg = std::make_unique<Mg>();
+    const stmg_options &o = ctx->opt;
+    Level &L0 = *ctx->levels[0];
+    mg->prec = o.prec_mg == STMG_F64 ? STMG_F64 : STMG_F32;
+    mg->omega = o.vanka_omega > 0 ? o.vanka_omega : 1.4 / double(1 << L0.dim);
+    mg->nu1 = std::max(0, o.nu1);
+    mg->nu2 = std::max(0, o.nu2);
+    int dev = 0, lds = 65536;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+        mg->max_lds = (size_t)lds;
+    mg->max_lds = mg->max_lds > 8192 ? mg->max_lds - 8192 : mg->max_lds;   // static LDS of the LU kernel
+    int k = L0.k, r = L0.r, n[3] = {L0.n[0], L0.n[1], L0.n[2]};
+    const int maxl = o.max_levels;
+    std::vector<char> kinds;
+    std::vector<double> verts = L0.vert_host;
+    auto count = [&]() { return (int)ctx->levels.size(); };
+    while ((r > 1 || k > 1) && (maxl == 0 || count() < maxl)) {
+        r = std::max(1, r / 2);
+        k = k >= 2 ? k / 2 : k;
+        auto L = std::make_unique<Level>();
+        L->init(ctx->prob, k, r, n[0], n[1], n[2], r == L0.r ? L0.nq : default_nq(r), verts);
+        L->timers = &ctx->timers;
+        ctx->levels.push_back(std::move(L));
+        kinds.push_back('p');
+    }
+    auto hok = [&]() {
+        for (int a = 0; a < L0.dim; ++a)
+            if (n[a] % 2 != 0 || n[a] < 4) return false;
+        return true;
+    };
+    while (hok() && (maxl == 0 || count() < maxl)) {
+        verts = coarse_vertices(verts, L0.dim, n);
+        for (int a = 0; a < L0.dim; ++a) n[a] /= 2;
+        auto L = std::make_unique<Level>();
+        L->init(ctx->prob, k, r, n[0], n[1], n[2], r == L0.r ? L0.nq : default_nq(r), verts);
+        L->timers = &ctx->timers;
+        ctx->levels.push_back(std::move(L));
+        kinds.push_back('h');
+    }
+    const int nl = (int)ctx->levels.size();
+    mg->lv.resize(nl);
+    for (int l = 0; l < nl; ++l) {
+        MgLevel &M = mg->lv[l];
+        M.L = ctx->levels[l].get();
+        size_t N = (size_t)M.L->N;
+        M.st64.alloc(N * 8);
+        STMG_HIP(hipMemset(M.st64.p, 0, N * 8));
+        if (mg->prec == STMG_F32) {
+            M.st32.alloc(N * 4);
+            STMG_HIP(hipMemset(M.st32.p, 0, N * 4));
+        }
+        size_t w = mg->prec == STMG_F64 ? 8 : 4;
+        M.r.alloc(N * w);
+        M.d.alloc(N * w);
+        M.t.alloc(N * w);
+        M.E.alloc((size_t)M.L->ncell * M.L->nt * M.L->dim * M.L->nl * w);
+    }
+    for (int l = 0; l + 1 < nl; ++l) {
+        auto T = std::make_unique<Transfer>();
+        T->build(*ctx->levels[l], *ctx->levels[l + 1], kinds[l]);
+        mg->tr.push_back(std::move(T));
+    }
+    mg->border = L0.dmask == (unsigned)((1 << (2 * L0.dim)) - 1);
+    ctx->mg = std::move(mg);
+}
+
+void mg_set_state(stmg_ctx *ctx, const double *u)
+{
+    Mg &mg = *ctx->mg;
+    hipStream_t s = ctx->stream;
+    const int nl = (int)mg.lv.size();
+    STMG_HIP(hipMemcpyAsync(mg.lv[0].st64.p, u, mg.lv[0].L->N * 8, hipMemcpyDeviceToDevice, s));
+    for (int l = 1; l < nl; ++l)
+        mg.tr[l - 1]->interpolate_state<double>(*mg.lv[l - 1].L, *mg.lv[l].L, mg.lv[l - 1].st64.as<double>(),
+                                                mg.lv[l].st64.as<double>(), s);
+    if (mg.prec == STMG_F32)
+        for (int l = 0; l < nl; ++l)
+            STMG_HIP((vec_cast<double, float>(mg.lv[l].L->N, mg.lv[l].st64.as<double>(), mg.lv[l].st32.as<float>(), s)));
+    // coarsest level: dense Jacobian from J e_i, bordered, LU in FP64
+    MgLevel &C = mg.lv[nl - 1];
+    Level &Lc = *C.L;
+    const int n = (int)Lc.N, nb = mg.border ? Lc.nt : 0, m = n + nb;
+    if (mg.cn != n) {
+        mg.cX.alloc((size_t)n * n * 8);
+        mg.cY.alloc((size_t)n * n * 8);
+        mg.cA.alloc((size_t)m * m * 8);
+        mg.cpiv.alloc((size_t)m * 4);
+        mg.cinfo.alloc(4);
+        mg.cr64.alloc((size_t)m * 8);
+        mg.cx64.alloc((size_t)m * 8);
+        mg.cn = n;
+        mg.cm = m;
+    }
+    {
+        TimerScope ts(&ctx->timers, "coarse_factor", s);
+        STMG_HIP(launch_identity(mg.cX.as<double>(), n, s));
+        Lc.apply<double>(Mode::Jac, C.st64.as<double>(), mg.cX.as<double>(), mg.cY.as<double>(), nullptr, nullptr, n, s);
+        STMG_HIP(launch_coarse_matrix(mg.cY.as<double>(), n, nb, Lc.nt, (long long)Lc.nt * Lc.Nv1, Lc.Np1, Lc.npm,
+                                      Lc.ncell, mg.cA.as<double>(), s));
+        STMG_HIP(hipMemsetAsync(mg.cinfo.p, 0, 4, s));
+        STMG_HIP(launch_lu<double>(mg.cA.as<double>(), mg.cpiv.as<int>(), m, 1, mg.cinfo.as<int>(), mg.max_lds, s));
+    }
+    mg.state_set = true;
+}
+
+template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_t max_lds)
+{
+    Level &L = *M.L;
+    hipStream_t s = ctx->stream;
+    M.vstar.alloc((size_t)L.Nv1 * sizeof(T));
+    STMG_HIP(launch_midpoint<T>(state_of<T>(M), L.Nv1, L.nt, L.tc.phimid, M.vstar.as<T>(), s));
+    const long long rw = elem_record_words(L.dim, L.r);
+    size_t eb = (size_t)L.ncell * rw * sizeof(T);
+    if (M.elem.bytes < eb) M.elem.alloc(eb);
+    ElemArgs<T> ea{};
+    ea.n0 = L.n[0];
+    ea.n1 = L.n[1];
+    ea.n2 = L.n[2];
+    ea.Nn = L.Nn;
+    ea.vstar = M.vstar.as<T>();
+    ea.tab = std::is_same<T, double>::value ? (const T *)L.tab64.p : (const T *)L.tab32.p;
+    ea.vert = L.mapped ? L.vert.as<double>() : nullptr;
+    ea.mapped = L.mapped ? 1 : 0;
+    ea.dmask = L.dmask;
+    ea.nu = (T)L.nu;
+    ea.g1 = (T)L.g1;
+    ea.g2 = (T)L.g2;
+    ea.out = M.elem.as<T>();
+    ea.rec_words = rw;
+    STMG_HIP(launch_elem<T>(L.dim, L.r, L.nq, ea, (int)L.ncell, s));
+    M.m = L.nt * (L.dim * L.nl + L.npm);
+    size_t pb = (size_t)L.ncell * M.m * M.m * sizeof(T);
+    if (M.patches.bytes < pb) M.patches.alloc(pb);
+    if (M.piv.bytes < (size_t)L.ncell * M.m * 4) M.piv.alloc((size_t)L.ncell * M.m * 4);
+    if (!M.info.p) M.info.alloc(4);
+    PatchArgs<T, T> pa{};
+    pa.n0 = L.n[0];
+    pa.n1 = L.n[1];
+    pa.n2 = L.n[2];
+    pa.nt = L.nt;
+    pa.elem = M.elem.as<T>();
+    pa.rec_words = rw;
+    for (int i = 0; i < L.nt * L.nt; ++i) pa.K[i] = L.tc.K[i];
+    for (int i = 0; i < L.nt; ++i) pa.w[i] = L.tc.w[i];
+    pa.patches = M.patches.as<T>();
+    STMG_HIP((launch_patch<T, T>(L.dim, L.r, pa, (int)L.ncell, s)));
+    STMG_HIP(hipMemsetAsync(M.info.p, 0, 4, s));
+    STMG_HIP(launch_lu<T>(M.patches.as<T>(), M.piv.as<int>(), M.m, (int)L.ncell, M.info.as<int>(), max_lds, s));
+    M.have_patches = true;
+}
+
+void mg_rebuild(stmg_ctx *ctx)
+{
+    Mg &mg = *ctx->mg;
+    TimerScope ts(&ctx->timers, "vanka_rebuild", ctx->stream);
+    for (size_t l = 0; l + 1 < mg.lv.size(); ++l) {
+        if (mg.prec == STMG_F64) rebuild_level<double>(ctx, mg.lv[l], mg.max_lds);
+        else rebuild_level<float>(ctx, mg.lv[l], mg.max_lds);
+    }
+}
+
+template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
+{
+    Mg &mg = *ctx->mg;
+    MgLevel &M = mg.lv[l];
+    Level &L = *M.L;
+    hipStream_t s = ctx->stream;
+    T *t = M.t.as<T>();
+    L.apply<T>(Mode::Jac, state_of<T>(M), d, t, nullptr, nullptr, 1, s);
+    STMG_HIP(vec_axpby<T>(L.N, T(1), r, T(-1), t, s));
+    TimerScope ts(&ctx->timers, "vanka_apply", s);
+    SolveArgs<T, T> sa{};
+    sa.n0 = L.n[0];
+    sa.n1 = L.n[1];
+    sa.n2 = L.n[2];
+    sa.nt = L.nt;
+    sa.Nn = L.Nn;
+    sa.Nv1 = L.Nv1;
+    sa.Np1 = L.Np1;
+    sa.defect = t;
+    sa.patches = M.patches.as<T>();
+    sa.piv = M.piv.as<int>();
+    sa.E = M.E.as<T>();
+    sa.d = d;
+    sa.omega = (T)mg.omega;
+    STMG_HIP((launch_solve<T, T>(L.dim, L.r, sa, (int)L.ncell, M.m, s)));
+    GatherArgs<T> g = L.gather_args<T>();
+    g.E = M.E.as<T>();
+    g.rhs = nullptr;
+    g.y = d;
+    g.ystride = L.N;
+    g.alpha = (T)mg.omega;
+    g.accumulate = 1;
+    STMG_HIP(launch_gather<T>(g, 1, s));
+}
+
+template <typename T> void mg_vcycle(stmg_ctx *ctx, int l, const T *r, T *d)
+{
+    Mg &mg = *ctx->mg;
+    const int nl = (int)mg.lv.size();
+    hipStream_t s = ctx->stream;
+    MgLevel &M = mg.lv[l];
+    Level &L = *M.L;
+    if (l == nl - 1) {
+        TimerScope ts(&ctx->timers, "coarse_solve", s);
+        STMG_HIP((vec_cast<T, double>(L.N, r, mg.cr64.as<double>(), s)));
+        STMG_HIP(launch_dense_solve(mg.cA.as<double>(), mg.cpiv.as<int>(), mg.cm, mg.cr64.as<double>(),
+                                    mg.cx64.as<double>(), mg.cn, s));
+        STMG_HIP((vec_cast<double, T>(L.N, mg.cx64.as<double>(), d, s)));
+        return;
+    }
+    STMG_HIP(vec_fill<T>(L.N, T(0), d, s));
+    for (int i = 0; i < mg.nu1; ++i) mg_smooth<T>(ctx, l, r, d);
+    T *t = M.t.as<T>();
+    L.apply<T>(Mode::Jac, state_of<T>(M), d, t, nullptr, nullptr, 1, s);
+    STMG_HIP(vec_axpby<T>(L.N, T(1), r, T(-1), t, s));
+    MgLevel &C = mg.lv[l + 1];
+    mg.tr[l]->restrict_<T>(L, *C.L, t, C.r.as<T>(), s);
+    mg_vcycle<T>(ctx, l + 1, C.r.as<T>(), C.d.as<T>());
+    mg.tr[l]->prolongate<T>(L, *C.L, C.d.as<T>(), d, T(1), s);
+    for (int i = 0; i < mg.nu2; ++i) mg_smooth<T>(ctx, l, r, d);
+}
+
+template void mg_smooth<double>(stmg_ctx *, int, const double *, double *);
+template void mg_smooth<float>(stmg_ctx *, int, const float *, float *);
+template void mg_vcycle<double>(stmg_ctx *, int, const double *, double *);
+template void mg_vcycle<float>(stmg_ctx *, int, const float *, float *);
+
+void mg_precondition(stmg_ctx *ctx, const double *v, double *z)
+{
+    Mg &mg = *ctx->mg;
+    MgLevel &M = mg.lv[0];
+    hipStream_t s = ctx->stream;
+    if (mg.prec == STMG_F64) {
+        mg_vcycle<double>(ctx, 0, v, z);
+        return;
+    }
+    STMG_HIP((vec_cast<double, float>(M.L->N, v, M.r.as<float>(), s)));
+    mg_vcycle<float>(ctx, 0, M.r.as<float>(), M.d.as<float>());
+    STMG_HIP((vec_cast<float, double>(M.L->N, M.d.as<float>(), z, s)));
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES
+// ---------------------------------------------------------------------------
+FgmresOut fgmres(stmg_ctx *ctx, const double *state, const double *b, double *x, double rtol, int maxit)
+{
+    Level &L = *ctx->levels[0];
+    const long long N = L.N;
+    hipStream_t s = ctx->stream;
+    Krylov &K = ctx->kry;
+    K.ensure(N, maxit);
+    double *V = K.V.as<double>(), *MV = K.MV.as<double>(), *Z = K.Z.as<double>();
+    double *w = K.w.as<double>(), *u = K.u.as<double>(), *h = K.h.as<double>(), *part = K.partial.as<double>();
+    FgmresOut out;
+    STMG_HIP(hipMemcpyAsync(V, b, N * 8, hipMemcpyDeviceToDevice, s));
+    L.apply<double>(Mode::Mass, nullptr, V, MV, nullptr, nullptr, 1, s);
+    STMG_HIP(vec_multidot(N, 1, MV, V, N, h, part, 0, s));
+    double beta2 = 0;
+    STMG_HIP(hipMemcpyAsync(&beta2, h, 8, hipMemcpyDeviceToHost, s));
+    STMG_HIP(hipStreamSynchronize(s));
+    const double beta = std::sqrt(std::max(beta2, 0.0));
+    out.hist.push_back(beta);
+    if (beta == 0.0) {
+        STMG_HIP(vec_fill<double>(N, 0.0, x, s));
+        out.converged = true;
+        return out;
+    }
+    STMG_HIP(vec_axpby<double>(N, 1.0 / beta, V, 0.0, V, s));
+    STMG_HIP(vec_axpby<double>(N, 1.0 / beta, MV, 0.0, MV, s));
+    std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0);
+    std::vector<double> hh(2 * (maxit + 1) + 1);
+    g[0] = beta;
+    int its = 0;
+    for (int j = 0; j < maxit; ++j) {
+        double *vj = V + (long long)j * N, *zj = Z + (long long)j * N;
+        mg_precondition(ctx, vj, zj);
+        L.apply<double>(Mode::Jac, state, zj, w, nullptr, nullptr, 1, s);
+        L.apply<double>(Mode::Mass, nullptr, w, u, nullptr, nullptr, 1, s);
+        double *h1 = h, *h2 = h + (maxit + 1), *hn = h + 2 * (maxit + 1);
+        STMG_HIP(vec_multidot(N, j + 1, u, V, N, h1, part, 0, s));
+        STMG_HIP(vec_subtract_combination(N, j + 1, h1, V, N, w, s));
+        STMG_HIP(vec_subtract_combination(N, j + 1, h1, MV, N, u, s));
+        STMG_HIP(vec_multidot(N, j + 1, u, V, N, h2, part, 0, s));
+        STMG_HIP(vec_subtract_combination(N, j + 1, h2, V, N, w, s));
+        STMG_HIP(vec_subtract_combination(N, j + 1, h2, MV, N, u, s));
+        STMG_HIP(vec_multidot(N, 1, u, w, N, hn, part, 0, s));
+        STMG_HIP(hipMemcpyAsync(hh.data(), h, sizeof(double) * (2 * (maxit + 1) + 1), hipMemcpyDeviceToHost, s));
+        STMG_HIP(hipStreamSynchronize(s));
+        std::vector<double> col(j + 2);
+        for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[(maxit + 1) + i];
+        const double hnv = std::sqrt(std::max(hh[2 * (maxit + 1)], 0.0));
+        col[j + 1] = hnv;
+        for (int i = 0; i < j; ++i) {
+            double t = cs[i] * col[i] + sn[i] * col[i + 1];
+            col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+            col[i] = t;
+        }
+        double den = std::hypot(col[j], col[j + 1]);
+        if (den > 0) {
+            cs[j] = col[j] / den;
+            sn[j] = col[j + 1] / den;
+        } else {
+            cs[j] = 1.0;
+            sn[j] = 0.0;
+        }
+        col[j] = cs[j] * col[j] + sn[j] * col[j + 1];
+        col[j + 1] = 0.0;
+        for (int i = 0; i <= j + 1; ++i) H[(size_t)i * maxit + j] = col[i];
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        its = j + 1;
+        const double res = std::fabs(g[j + 1]);
+        out.hist.push_back(res);
+        if (res <= rtol * beta || hnv == 0.0) {
+            out.converged = res <= rtol * beta;
+            break;
+        }
+        STMG_HIP(vec_axpby<double>(N, 1.0 / hnv, w, 0.0, V + (long long)(j + 1) * N, s));
+        STMG_HIP(vec_axpby<double>(N, 1.0 / hnv, u, 0.0, MV + (long long)(j + 1) * N, s));
+    }
+    // back substitution H y = g
+    std::vector<double> y(its, 0.0);
+    for (int i = its - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int k = i + 1; k < its; ++k) t -= H[(size_t)i * maxit + k] * y[k];
+        y[i] = t / H[(size_t)i * maxit + i];
+    }
+    STMG_HIP(hipMemcpyAsync(K.y.p, y.data(), sizeof(double) * its, hipMemcpyHostToDevice, s));
+    STMG_HIP(vec_combination(N, its, K.y.as<double>(), Z, N, x, s));
+    STMG_HIP(hipStreamSynchronize(s));
+    out.its = its;
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// Newton
+// ---------------------------------------------------------------------------
+namespace {
+
+bool interp_step(double phi0, double g0, const std::vector<std::pair<double, double>> &fails, double &out)
+{
+    const double a1 = fails.back().first, p1 = fails.back().second;
+    if (fails.size() == 1) {
+        double den = 2.0 * (p1 - phi0 - g0 * a1);
+        if (den <= 0.0) return false;
+        out = -g0 * a1 * a1 / den;
+        return true;
+    }
+    const double a2 = fails[fails.size() - 2].first, p2 = fails[fails.size() - 2].second;
+    double r1 = p1 - phi0 - g0 * a1, r2 = p2 - phi0 - g0 * a2;
+    double det = a1 * a1 * a2 * a2 * (a1 - a2);
+    if (det == 0.0) return false;
+    double cc = (a2 * a2 * r1 - a1 * a1 * r2) / det;
+    double bb = (-a2 * a2 * a2 * r1 + a1 * a1 * a1 * r2) / det;
+    if (cc == 0.0) {
+        if (bb <= 0.0) return false;
+        out = -g0 / (2.0 * bb);
+        return true;
+    }
+    double disc = bb * bb - 3.0 * cc * g0;
+    if (disc < 0.0) return false;
+    out = (-bb + std::sqrt(disc)) / (3.0 * cc);
+    return true;
+}
+
+} // namespace
+
+int newton_solve(stmg_ctx *ctx, double *U, stmg_stats *stats)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    Level &L = *ctx->levels[0];
+    Mg &mg = *ctx->mg;
+    const stmg_options &p = ctx->opt;
+    const long long N = L.N;
+    hipStream_t s = ctx->stream;
+    Krylov &W = ctx->kry;
+    const double *rhs = ctx->has_rhs ? ctx->rhs.as<double>() : nullptr;
+    const double *vprev = ctx->has_vprev ? ctx->vprev.as<double>() : nullptr;
+    W.ensure(N, std::max(1, p.fgmres_maxit));
+    double *part = W.partial.as<double>();
+    auto dotM = [&](const double *a, const double *Mb) {
+        STMG_HIP(vec_multidot(N, 1, a, Mb, N, W.dot.as<double>(), part, 0, s));
+        double v = 0;
+        STMG_HIP(hipMemcpyAsync(&v, W.dot.p, 8, hipMemcpyDeviceToHost, s));
+        STMG_HIP(hipStreamSynchronize(s));
+        return v;
+    };
+    auto residual = [&](const double *X, double *R) { L.apply<double>(Mode::Res, nullptr, X, R, rhs, vprev, 1, s); };
+    auto mnorm = [&](const double *v) {
+        L.apply<double>(Mode::Mass, nullptr, v, W.tmp.as<double>(), nullptr, nullptr, 1, s);
+        return std::sqrt(std::max(dotM(v, W.tmp.as<double>()), 0.0));
+    };
+    const double eps = 1e-30;
+    stmg_stats st{};
+    residual(U, W.r.as<double>());
+    const double n0 = mnorm(W.r.as<double>());
+    if (!std::isfinite(n0)) {
+        ctx->err = "non-finite initial residual";
+        return STMG_ENONFINITE;
+    }
+    st.res0_M = n0;
+    double nrm = n0, n_prev = n0, eta = p.ew_eta0, rho_prev = 1.0;
+    int kappa_prev = 1, kappa_ref = 1, k = 0;
+    std::vector<double> window{0.5 * n0 * n0};
+    for (size_t l = 0; l < mg.lv.size(); ++l) mg.lv[l].have_patches = false;
+    while (nrm > std::max(p.newton_atol, p.newton_rtol * n0) && k < p.newton_maxit) {
+        mg_set_state(ctx, U);
+        if (!mg.lv[0].have_patches || rho_prev >= p.rb_theta_N ||
+            kappa_prev >= std::max(p.rb_theta_L * kappa_ref, p.rb_kappa_abs)) {
+            mg_rebuild(ctx);
+            st.rebuilds++;
+            kappa_ref = std::max(1, kappa_prev);
+        }
+        if (k > 0)
+            eta = std::min(std::max(p.ew_c * eta * std::pow(nrm / std::max(n_prev, eps), p.ew_theta), p.ew_eta_min),
+                           p.ew_eta_max);
+        // solve J dU = -r
+        STMG_HIP(vec_axpby<double>(N, -1.0, W.r.as<double>(), 0.0, W.rt.as<double>(), s));
+        FgmresOut fo = fgmres(ctx, U, W.rt.as<double>(), W.dU.as<double>(), eta, p.fgmres_maxit);
+        if (k < 64) st.fgmres_its[k] = fo.its;
+        st.fgmres_its_total += fo.its;
+        // g0 = (M r) . (J dU)
+        L.apply<double>(Mode::Mass, nullptr, W.r.as<double>(), W.Mr.as<double>(), nullptr, nullptr, 1, s);
+        L.apply<double>(Mode::Jac, U, W.dU.as<double>(), W.tmp.as<double>(), nullptr, nullptr, 1, s);
+        const double g0 = dotM(W.tmp.as<double>(), W.Mr.as<double>());
+        const double phi0 = 0.5 * nrm * nrm;
+        // Armijo with nonmonotone window
+        double alpha = p.ls_lambda0, accepted = -1.0;
+        std::vector<std::pair<double, double>> fails;
+        int nback = 0;
+        while (alpha > p.ls_alpha_min) {
+            STMG_HIP(hipMemcpyAsync(W.Ut.p, U, N * 8, hipMemcpyDeviceToDevice, s));
+            STMG_HIP(vec_axpby<double>(N, alpha, W.dU.as<double>(), 1.0, W.Ut.as<double>(), s));
+            residual(W.Ut.as<double>(), W.rt.as<double>());
+            const double mt = mnorm(W.rt.as<double>());
+            const double phit = 0.5 * mt * mt;
+            double phimax = phi0;
+            if (p.ls_window > 0) phimax = *std::max_element(window.begin(), window.end());
+            if (std::isfinite(phit) && phit <= phimax + p.ls_c * alpha * g0) {
+                if (p.ls_window > 0) {
+                    window.push_back(phit);
+                    if ((int)window.size() > p.ls_window) window.erase(window.begin(), window.end() - p.ls_window);
+                }
+                accepted = alpha;
+                break;
+            }
+            fails.push_back({alpha, phit});
+            nback++;
+            st.backtracks++;
+            if (nback > p.ls_max_backtracks) break;
+            double ai = 0;
+            if (!interp_step(phi0, g0, fails, ai) || !std::isfinite(ai)) alpha = p.ls_tau * alpha;
+            else alpha = std::min(std::max(ai, 0.1 * alpha), 0.5 * alpha);
+        }
+        if (accepted < 0) alpha = p.ls_alpha_min;
+        STMG_HIP(vec_axpby<double>(N, alpha, W.dU.as<double>(), 1.0, U, s));
+        n_prev = nrm;
+        residual(U, W.r.as<double>());
+        nrm = mnorm(W.r.as<double>());
+        if (!std::isfinite(nrm)) {
+            ctx->err = "non-finite residual";
+            return STMG_ENONFINITE;
+        }
+        rho_prev = nrm / std::max(n_prev, eps);
+        kappa_prev = std::max(1, fo.its);
+        int run = 0;
+        bool stag = false;
+        for (size_t i = 0; i + 1 < fo.hist.size(); ++i) {
+            if (fo.hist[i] <= 0) continue;
+            double q = fo.hist[i + 1] / fo.hist[i];
+            run = q >= p.rb_stag_theta ? run + 1 : 0;
+            if (run >= p.rb_stag_s) stag = true;
+        }
+        if (stag) {
+            mg_set_state(ctx, U);
+            mg_rebuild(ctx);
+            st.rebuilds++;
+        }
+        ++k;
+    }
+    STMG_HIP(hipStreamSynchronize(s));
+    st.newton_its = k;
+    st.res_M = nrm;
+    st.wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return nrm <= std::max(p.newton_atol, p.newton_rtol * n0) ? STMG_OK : STMG_NOT_CONVERGED;
+}
+
+} // namespace stmg

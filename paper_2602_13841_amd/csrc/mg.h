@@ -1,0 +1,74 @@
+// hp space-time multigrid hierarchy, Krylov and Newton drivers (internal).
+#pragma once
+
+#include "context.h"
+#include "transfers.h"
+#include "vanka.h"
+#include "vec_ops.h"
+
+namespace stmg {
+
+struct MgLevel {
+    Level *L = nullptr;
+    DevBuf st64, st32;            // level state (slab vector; velocity part used)
+    DevBuf vstar;                 // midpoint velocity in the multigrid precision
+    DevBuf elem;                  // element records
+    DevBuf patches, piv, info;    // patch LU factors
+    int m = 0;                    // patch size
+    bool have_patches = false;
+    DevBuf r, d, t, E;            // work vectors in the multigrid precision
+};
+
+struct Mg {
+    int prec = STMG_F32;
+    double omega = 0.35;
+    int nu1 = 1, nu2 = 1;
+    std::vector<MgLevel> lv;
+    std::vector<std::unique_ptr<Transfer>> tr;   // tr[l]: level l -> l+1
+    // coarsest level direct solve (FP64)
+    DevBuf cX, cY, cA, cpiv, cinfo, cr64, cx64;
+    int cn = 0, cm = 0;
+    bool border = false;
+    bool state_set = false;
+    size_t max_lds = 65536;
+};
+
+// FGMRES and Newton workspace (FP64)
+struct Krylov {
+    int maxit = 0;
+    long long N = 0;
+    DevBuf V, MV, Z, w, u, h, partial, y;
+    DevBuf r, Mr, dU, Ut, rt, tmp, dot;     // Newton vectors
+    void ensure(long long N_, int maxit_);
+};
+
+void mg_build(stmg_ctx *ctx);
+void mg_set_state(stmg_ctx *ctx, const double *u);
+void mg_rebuild(stmg_ctx *ctx);
+template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d);
+template <typename T> void mg_vcycle(stmg_ctx *ctx, int l, const T *r, T *d);
+// z = B v for FP64 vectors on the finest level (casts around the cycle)
+void mg_precondition(stmg_ctx *ctx, const double *v, double *z);
+
+struct FgmresOut {
+    int its = 0;
+    bool converged = false;
+    std::vector<double> hist;
+};
+FgmresOut fgmres(stmg_ctx *ctx, const double *state, const double *b, double *x, double rtol, int maxit);
+int newton_solve(stmg_ctx *ctx, double *u, stmg_stats *stats);
+
+} // namespace stmg
+
+struct stmg_ctx {
+    stmg_problem prob{};
+    stmg_options opt{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<std::unique_ptr<stmg::Level>> levels;   // levels[0] = finest
+    stmg::DevBuf rhs, vprev;                            // slab data (FP64)
+    bool has_rhs = false, has_vprev = false;
+    stmg::Timers timers;
+    std::unique_ptr<stmg::Mg> mg;
+    stmg::Krylov kry;
+};

@@ -106,6 +106,8 @@ struct GatherArgs {
     T *y;
     long long ystride;
     int nl;     // (r+2)^dim
+    T alpha;        // y = alpha * sum (+ y if accumulate) (- rhs)
+    int accumulate;
 };
 
 // launchers (cell_ops.hip)

@@ -1,0 +1,41 @@
+// Grid transfers between two levels of the hp hierarchy (internal).
+#pragma once
+
+#include "context.h"
+#include "vec_ops.h"
+
+namespace stmg {
+
+struct HostCsr {
+    int nrows = 0, ncols = 0;
+    std::vector<int> rowptr, col;
+    std::vector<double> val;
+};
+
+struct DevCsr {
+    int nrows = 0, ncols = 0;
+    long long nnz = 0;
+    DevBuf rowptr, col, val64, val32;
+    void upload(const HostCsr &A);
+};
+
+HostCsr transpose(const HostCsr &A);
+HostCsr velocity_prolongation(const Level &f, const Level &c, char kind);
+HostCsr state_interpolation(const Level &f, const Level &c, char kind);
+HostCsr pressure_prolongation(const Level &f, const Level &c, char kind);
+
+struct Transfer {
+    char kind = 'h';
+    DevCsr vel, velT, pres, presT, state;
+    DevBuf Pt64, Pt32, PtT64, PtT32, It64, It32;
+    void build(const Level &f, const Level &c, char kind);
+    // yf = P xc + beta yf  (slab vectors)
+    template <typename T> void prolongate(const Level &f, const Level &c, const T *xc, T *yf, T beta, hipStream_t s) const;
+    // yc = P^T xf
+    template <typename T> void restrict_(const Level &f, const Level &c, const T *xf, T *yc, hipStream_t s) const;
+    // coarse velocity state (all time nodes) from the fine one
+    template <typename T>
+    void interpolate_state(const Level &f, const Level &c, const T *vf, T *vc, hipStream_t s) const;
+};
+
+} // namespace stmg

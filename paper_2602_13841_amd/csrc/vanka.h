@@ -1,0 +1,58 @@
+// Vanka smoother kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace stmg {
+
+template <typename T> struct ElemArgs {
+    int n0, n1, n2;
+    long long Nn;
+    const T *vstar;        // midpoint velocity, one time node [c][node]
+    const T *tab;          // table block of the level
+    const double *vert;    // vertices or null
+    int mapped;
+    unsigned dmask;
+    T nu, g1, g2;
+    T *out;                // element records
+    long long rec_words;
+};
+
+template <typename TE, typename TP> struct PatchArgs {
+    int n0, n1, n2;
+    int nt;
+    const TE *elem;
+    long long rec_words;
+    double K[16];
+    double w[4];
+    TP *patches;           // [cell][m*m] column-major
+};
+
+template <typename T, typename TP> struct SolveArgs {
+    int n0, n1, n2;
+    int nt;
+    long long Nn, Nv1, Np1;
+    const T *defect;       // slab vector
+    const TP *patches;
+    const int *piv;
+    T *E;                  // [cell][a][c][l] velocity part of the patch solution
+    T *d;                  // slab vector: pressure part updated in place
+    T omega;
+};
+
+int elem_record_words(int dim, int r);
+template <typename T> hipError_t launch_elem(int dim, int r, int nq, const ElemArgs<T> &a, int ncell, hipStream_t s);
+template <typename TE, typename TP>
+hipError_t launch_patch(int dim, int r, const PatchArgs<TE, TP> &a, int ncell, hipStream_t s);
+template <typename T> hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds, hipStream_t s);
+template <typename T, typename TP>
+hipError_t launch_solve(int dim, int r, const SolveArgs<T, TP> &a, int ncell, int m, hipStream_t s);
+hipError_t launch_dense_solve(const double *LU, const int *piv, int m, const double *rhs, double *x, int nout,
+                              hipStream_t s);
+hipError_t launch_identity(double *X, int n, hipStream_t s);
+hipError_t launch_coarse_matrix(const double *Y, int n, int nb, int nt, long long pbase, long long Np1, int npm,
+                                long long ncell, double *A, hipStream_t s);
+template <typename T>
+hipError_t launch_midpoint(const T *state, long long Nv1, int nt, const double *pm, T *vstar, hipStream_t s);
+
+} // namespace stmg

@@ -1,0 +1,989 @@
+// Inexact space-time Vanka smoother on gfx950 (Sec. "Inexact space-time
+// Vanka smoother", eq. LVS, eq. DefTildeHn, eq. DefVnAst, eq. vanka0).
+//
+// Rebuild, once per smoother update:
+//   1. elem_kernel      one workgroup per cell: the spatial element matrices
+//                       at the midpoint state V* (velocity block of the
+//                       linearized A^tp_gamma incl. boundary faces, velocity
+//                       mass, velocity-pressure coupling).  The pair (i, j)
+//                       x point-chunk loop is a small dense contraction held
+//                       in registers (2x2 pairs per thread).
+//   2. patch_kernel     one workgroup per cell K: the principal submatrix of
+//                       the surrogate on all unknowns of K at all time nodes,
+//                       summing the element matrices of every cell that
+//                       holds both nodes of an entry, expanded with the time
+//                       matrices: K_ab M_S + delta_ab w_a L_S (velocity),
+//                       delta_ab w_a B_S^(T) (pressure).  Column-major.
+//   3. lu_kernel        one workgroup per patch: blocked right-looking LU
+//                       with partial pivoting; the panel lives in LDS, the
+//                       trailing update streams the patch once per panel.
+// Apply, per smoothing step:
+//   4. solve_kernel     one workgroup per patch: gather the defect, apply the
+//                       pivots, blocked forward/backward substitution (64-wide
+//                       diagonal blocks inside one wavefront), velocity result
+//                       to a cell-local buffer, pressure result added in place
+//                       (pressure unknowns belong to a single patch).
+//   5. the deterministic node gather of cell_ops adds omega * sum over the
+//      patches sharing each velocity node.
+#include "stmg_internal.h"
+#include "vanka.h"
+
+namespace stmg {
+
+namespace {
+
+constexpr int ipow_(int b, int e) { return e == 0 ? 1 : b * ipow_(b, e - 1); }
+
+template <int DIM, int R> struct VS {
+    static constexpr int N1 = R + 2;
+    static constexpr int NL = ipow_(N1, DIM);
+    static constexpr int RP1 = R + 1;
+    static constexpr int NPM = DIM == 2 ? (R + 1) * (R + 2) / 2 : (R + 1) * (R + 2) * (R + 3) / 6;
+};
+
+template <int DIM, int R> __device__ __forceinline__ void pmode(int m, int al[3])
+{
+    int cnt = 0;
+    for (int a2 = 0; a2 <= (DIM == 3 ? R : 0); ++a2)
+        for (int a1 = 0; a1 <= R; ++a1)
+            for (int a0 = 0; a0 <= R; ++a0) {
+                if (a0 + a1 + a2 > R) continue;
+                if (cnt == m) {
+                    al[0] = a0;
+                    al[1] = a1;
+                    al[2] = a2;
+                    return;
+                }
+                ++cnt;
+            }
+}
+
+template <int DIM, typename T> __device__ __forceinline__ void map_jac_v(const T *X, const T xi[3], T J[3][3])
+{
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) J[a][b] = 0;
+    for (int v = 0; v < (1 << DIM); ++v) {
+        T f[3], df[3];
+        for (int b = 0; b < DIM; ++b) {
+            int o = (v >> b) & 1;
+            f[b] = o ? xi[b] : T(1) - xi[b];
+            df[b] = o ? T(1) : T(-1);
+        }
+        for (int b = 0; b < DIM; ++b) {
+            T g = df[b];
+            for (int e = 0; e < DIM; ++e)
+                if (e != b) g *= f[e];
+            for (int a = 0; a < DIM; ++a) J[a][b] += X[v * 3 + a] * g;
+        }
+    }
+}
+
+template <int DIM, typename T> __device__ __forceinline__ T inv_t_v(const T J[3][3], T Jit[3][3])
+{
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Jit[a][b] = 0;
+    if constexpr (DIM == 2) {
+        T det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        T id = T(1) / det;
+        Jit[0][0] = J[1][1] * id;
+        Jit[0][1] = -J[1][0] * id;
+        Jit[1][0] = -J[0][1] * id;
+        Jit[1][1] = J[0][0] * id;
+        return det;
+    } else {
+        T c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        T det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        T id = T(1) / det;
+        Jit[0][0] = c00 * id;
+        Jit[0][1] = c01 * id;
+        Jit[0][2] = c02 * id;
+        Jit[1][0] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+        Jit[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+        Jit[1][2] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+        Jit[2][0] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+        Jit[2][1] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+        Jit[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+        return det;
+    }
+}
+
+template <typename T> __device__ __forceinline__ T om_(T y) { return T(0.5) * (fabs(y) - y); }
+template <typename T> __device__ __forceinline__ T dom_(T y) { return y > T(0) ? T(0) : (y < T(0) ? T(-1) : T(-0.5)); }
+
+// ---------------------------------------------------------------------------
+// element matrices at the midpoint state
+// ---------------------------------------------------------------------------
+constexpr int EL_THREADS = 256;
+constexpr int PCH = 8;        // points per chunk
+constexpr int TILE = 32;      // pair tile (TILE x TILE), 2x2 pairs per thread
+constexpr int PREC = 24;      // words of a point record
+
+// point record fields
+enum : int {
+    P_W = 0, P_V = 1, P_N = 4, P_JIT = 7, P_FACE = 16, P_ISD = 17, P_VN = 18, P_OM = 19, P_DOM = 20, P_PEN1 = 21,
+    P_PEN2 = 22
+};
+
+template <int DIM, int R, int NQ, typename T>
+__global__ void __launch_bounds__(EL_THREADS) elem_kernel(ElemArgs<T> A)
+{
+    using Z = VS<DIM, R>;
+    constexpr int N1 = Z::N1, NL = Z::NL, RP1 = Z::RP1, NPM = Z::NPM;
+    constexpr int NQV = ipow_(NQ, DIM), NQF = ipow_(NQ, DIM - 1);
+    constexpr int NT = EL_THREADS;
+    __shared__ T tabS[NQ * N1], tabD[NQ * N1], tabSe[2 * N1], tabDe[2 * N1], tabL[NQ * RP1], tabLe[2 * RP1];
+    __shared__ T qw[NQ], qx[NQ];
+    __shared__ T vloc[DIM * NL];
+    __shared__ T geo[32];
+    __shared__ T prec[PCH * PREC];
+    __shared__ int pidx[PCH * 3];                 // per-axis 1D index (>=0 Gauss, -1 s=0, -2 s=1)
+    __shared__ T Bi[PCH * TILE * 4], Bj[PCH * TILE * 4];
+    __shared__ T red[NT];
+    __shared__ int faces[6];
+    __shared__ int nfaces;
+
+    const int tid = threadIdx.x;
+    const int cell = blockIdx.x;
+    TableLayout lay;
+    lay.init(R, NQ);
+    for (int i = tid; i < NQ * N1; i += NT) {
+        tabS[i] = A.tab[lay.S + i];
+        tabD[i] = A.tab[lay.D + i];
+    }
+    for (int i = tid; i < 2 * N1; i += NT) {
+        tabSe[i] = A.tab[lay.Se + i];
+        tabDe[i] = A.tab[lay.De + i];
+    }
+    for (int i = tid; i < NQ * RP1; i += NT) tabL[i] = A.tab[lay.L + i];
+    for (int i = tid; i < 2 * RP1; i += NT) tabLe[i] = A.tab[lay.Le + i];
+    for (int i = tid; i < NQ; i += NT) {
+        qw[i] = A.tab[lay.qw + i];
+        qx[i] = A.tab[lay.qx + i];
+    }
+    const int c0 = cell % A.n0, c1 = (cell / A.n0) % A.n1, c2 = DIM == 3 ? cell / (A.n0 * A.n1) : 0;
+    const long long N0 = (long long)(R + 1) * A.n0 + 1, N1g = (long long)(R + 1) * A.n1 + 1;
+    for (int e = tid; e < DIM * NL; e += NT) {
+        int l = e % NL, c = e / NL;
+        int i0 = l % N1, i1 = (l / N1) % N1, i2 = DIM == 3 ? l / (N1 * N1) : 0;
+        long long g = ((long long)(R + 1) * c0 + i0) + N0 * (((long long)(R + 1) * c1 + i1) + N1g * ((long long)(R + 1) * c2 + i2));
+        vloc[e] = A.vstar[c * A.Nn + g];
+    }
+    const bool mapped = A.mapped != 0;
+    if (mapped && tid < (1 << DIM)) {
+        int v = tid, o0 = v & 1, o1 = (v >> 1) & 1, o2 = (v >> 2) & 1;
+        long long vi = (c0 + o0) + (long long)(A.n0 + 1) * ((c1 + o1) + (long long)(A.n1 + 1) * (c2 + o2));
+        for (int a = 0; a < 3; ++a) geo[v * 3 + a] = a < DIM ? T(A.vert[vi * DIM + a]) : T(0);
+    }
+    if (tid == 0) {
+        int nf = 0;
+        int cc[3] = {c0, c1, c2}, nn[3] = {A.n0, A.n1, A.n2};
+        for (int ax = 0; ax < DIM; ++ax) {
+            if (cc[ax] == 0) faces[nf++] = 2 * ax;
+            if (cc[ax] == nn[ax] - 1) faces[nf++] = 2 * ax + 1;
+        }
+        nfaces = nf;
+    }
+    __syncthreads();
+    const T hcar[3] = {T(1) / A.n0, T(1) / A.n1, DIM == 3 ? T(1) / A.n2 : T(1)};
+    T *hF = geo + 24;
+    // h_F = |K| / |F| (mapped cells by quadrature, fixed-order sums)
+    if (nfaces > 0) {
+        if (!mapped) {
+            if (tid < 2 * DIM) hF[tid] = hcar[tid / 2];
+        } else {
+            T part = 0;
+            for (int q = tid; q < NQV; q += NT) {
+                int qi[3] = {q % NQ, (q / NQ) % NQ, DIM == 3 ? q / (NQ * NQ) : 0};
+                T xi[3] = {0, 0, 0}, J[3][3], Jit[3][3];
+                for (int d = 0; d < DIM; ++d) xi[d] = qx[qi[d]];
+                map_jac_v<DIM>(geo, xi, J);
+                T w = inv_t_v<DIM>(J, Jit);
+                for (int d = 0; d < DIM; ++d) w *= qw[qi[d]];
+                part += w;
+            }
+            red[tid] = part;
+            __syncthreads();
+            if (tid == 0) {
+                T vol = 0;
+                for (int i = 0; i < NT; ++i) vol += red[i];
+                geo[31] = vol;
+            }
+            __syncthreads();
+            for (int fid = 0; fid < 2 * DIM; ++fid) {
+                int ax = fid / 2, side = fid % 2;
+                T part2 = 0;
+                if (tid < NQF) {
+                    int q = tid, tq[2] = {q % NQ, DIM == 3 ? q / NQ : 0}, t = 0;
+                    T xi[3] = {0, 0, 0}, J[3][3], Jit[3][3], wt = 1;
+                    for (int d = 0; d < DIM; ++d) {
+                        if (d == ax) xi[d] = T(side);
+                        else { xi[d] = qx[tq[t]]; wt *= qw[tq[t]]; ++t; }
+                    }
+                    map_jac_v<DIM>(geo, xi, J);
+                    T det = inv_t_v<DIM>(J, Jit), len = 0;
+                    for (int d = 0; d < DIM; ++d) len += Jit[d][ax] * Jit[d][ax];
+                    part2 = fabs(det) * sqrt(len) * wt;
+                }
+                red[tid] = part2;
+                __syncthreads();
+                if (tid == 0) {
+                    T area = 0;
+                    for (int q = 0; q < NQF; ++q) area += red[q];
+                    hF[fid] = geo[31] / area;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    __syncthreads();
+    const int npts = NQV + nfaces * NQF;
+    const int nchunks = (npts + PCH - 1) / PCH;
+
+    // 1D value / derivative of basis index i on axis value index idx
+    auto sv = [&](int idx, int i) -> T { return idx >= 0 ? tabS[idx * N1 + i] : tabSe[(idx == -1 ? 0 : 1) * N1 + i]; };
+    auto dv = [&](int idx, int i) -> T { return idx >= 0 ? tabD[idx * N1 + i] : tabDe[(idx == -1 ? 0 : 1) * N1 + i]; };
+    auto lv = [&](int idx, int i) -> T { return idx >= 0 ? tabL[idx * RP1 + i] : tabLe[(idx == -1 ? 0 : 1) * RP1 + i]; };
+
+    // point records of chunk ch -> prec / pidx (threads < PCH)
+    auto build_chunk = [&](int ch) {
+        if (tid < PCH) {
+            int p = ch * PCH + tid;
+            T *P = prec + tid * PREC;
+            int *ix = pidx + tid * 3;
+            if (p >= npts) {
+                P[P_W] = 0;
+                P[P_FACE] = T(-2);
+                ix[0] = ix[1] = ix[2] = 0;
+            } else {
+                int fid = -1, ax = -1, side = 0;
+                if (p < NQV) {
+                    ix[0] = p % NQ;
+                    ix[1] = DIM > 1 ? (p / NQ) % NQ : 0;
+                    ix[2] = DIM == 3 ? p / (NQ * NQ) : 0;
+                } else {
+                    int f = (p - NQV) / NQF, q = (p - NQV) % NQF;
+                    fid = faces[f];
+                    ax = fid / 2;
+                    side = fid % 2;
+                    int tq[2] = {q % NQ, DIM == 3 ? q / NQ : 0}, t = 0;
+                    for (int d = 0; d < 3; ++d) ix[d] = 0;
+                    for (int d = 0; d < DIM; ++d) ix[d] = (d == ax) ? (side ? -2 : -1) : tq[t++];
+                }
+                T xi[3] = {0, 0, 0};
+                for (int d = 0; d < DIM; ++d) xi[d] = ix[d] >= 0 ? qx[ix[d]] : (ix[d] == -1 ? T(0) : T(1));
+                T Jit[3][3], det;
+                if (mapped) {
+                    T J[3][3];
+                    map_jac_v<DIM>(geo, xi, J);
+                    det = inv_t_v<DIM>(J, Jit);
+                } else {
+                    det = 1;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) Jit[a][b] = 0;
+                    for (int d = 0; d < DIM; ++d) {
+                        Jit[d][d] = T(1) / hcar[d];
+                        det *= hcar[d];
+                    }
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) P[P_JIT + 3 * a + b] = Jit[a][b];
+                // state value
+                T v[3] = {0, 0, 0};
+                for (int l = 0; l < NL; ++l) {
+                    int li[3] = {l % N1, (l / N1) % N1, DIM == 3 ? l / (N1 * N1) : 0};
+                    T nv = 1;
+                    for (int d = 0; d < DIM; ++d) nv *= sv(ix[d], li[d]);
+                    for (int c = 0; c < DIM; ++c) v[c] += vloc[c * NL + l] * nv;
+                }
+                for (int c = 0; c < 3; ++c) P[P_V + c] = v[c];
+                if (fid < 0) {
+                    T w = det;
+                    for (int d = 0; d < DIM; ++d) w *= qw[ix[d]];
+                    P[P_W] = w;
+                    P[P_FACE] = T(-1);
+                } else {
+                    T sg = side ? T(1) : T(-1), nv[3] = {0, 0, 0}, len = 0;
+                    for (int d = 0; d < DIM; ++d) {
+                        nv[d] = sg * Jit[d][ax];
+                        len += nv[d] * nv[d];
+                    }
+                    len = sqrt(len);
+                    T w = fabs(det) * len;
+                    for (int d = 0; d < DIM; ++d)
+                        if (d != ax) w *= qw[ix[d]];
+                    T vn = 0;
+                    for (int d = 0; d < DIM; ++d) {
+                        nv[d] /= len;
+                        vn += v[d] * nv[d];
+                    }
+                    for (int d = 0; d < 3; ++d) P[P_N + d] = nv[d];
+                    P[P_W] = w;
+                    P[P_FACE] = T(fid);
+                    P[P_ISD] = ((A.dmask >> fid) & 1u) ? T(1) : T(0);
+                    P[P_VN] = vn;
+                    P[P_OM] = om_(vn);
+                    P[P_DOM] = dom_(vn);
+                    T h = hF[fid];
+                    P[P_PEN1] = A.nu * A.g1 / h;
+                    P[P_PEN2] = A.g2 / h;
+                }
+            }
+        }
+    };
+    // basis values/gradients of node l at chunk point p -> B[(p*TILE + slot)*4 ..]
+    auto basis = [&](int p, int l, T *out) {
+        const int *ix = pidx + p * 3;
+        const T *P = prec + p * PREC;
+        int li[3] = {l % N1, (l / N1) % N1, DIM == 3 ? l / (N1 * N1) : 0};
+        T s[3] = {1, 1, 1}, d[3] = {0, 0, 0};
+        for (int a = 0; a < DIM; ++a) {
+            s[a] = sv(ix[a], li[a]);
+            d[a] = dv(ix[a], li[a]);
+        }
+        T val = 1, gref[3];
+        for (int a = 0; a < DIM; ++a) val *= s[a];
+        for (int a = 0; a < DIM; ++a) {
+            T g = d[a];
+            for (int b = 0; b < DIM; ++b)
+                if (b != a) g *= s[b];
+            gref[a] = g;
+        }
+        out[0] = val;
+        for (int a = 0; a < DIM; ++a) {
+            T g = 0;
+            for (int b = 0; b < DIM; ++b) g += P[P_JIT + 3 * a + b] * gref[b];
+            out[1 + a] = g;
+        }
+        if (DIM == 2) out[3] = 0;
+    };
+
+    T *rec = A.out + (long long)cell * A.rec_words;
+    T *Avv = rec;
+    T *Mv = rec + DIM * DIM * NL * NL;
+    T *Avp = Mv + NL * NL;
+    const T nu = A.nu;
+    constexpr int NTILE = (NL + TILE - 1) / TILE;
+    const int tx = tid % 16, ty = tid / 16;
+
+    for (int ti = 0; ti < NTILE; ++ti)
+        for (int tj = 0; tj < NTILE; ++tj) {
+            const int ib = ti * TILE, jb = tj * TILE;
+            T acc[2][2][11];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int k = 0; k < 11; ++k) acc[a][b][k] = 0;
+            for (int ch = 0; ch < nchunks; ++ch) {
+                build_chunk(ch);
+                __syncthreads();
+                for (int e = tid; e < PCH * TILE; e += NT) {
+                    int p = e / TILE, s = e % TILE;
+                    T tmp[4];
+                    int li = ib + s, lj = jb + s;
+                    if (li < NL) basis(p, li, tmp);
+                    else tmp[0] = tmp[1] = tmp[2] = tmp[3] = 0;
+                    for (int k = 0; k < 4; ++k) Bi[(p * TILE + s) * 4 + k] = tmp[k];
+                    if (lj < NL) basis(p, lj, tmp);
+                    else tmp[0] = tmp[1] = tmp[2] = tmp[3] = 0;
+                    for (int k = 0; k < 4; ++k) Bj[(p * TILE + s) * 4 + k] = tmp[k];
+                }
+                __syncthreads();
+                for (int p = 0; p < PCH; ++p) {
+                    const T *P = prec + p * PREC;
+                    const T w = P[P_W];
+                    if (w == T(0)) continue;
+                    const T face = P[P_FACE];
+                    const T v0 = P[P_V], v1 = P[P_V + 1], v2 = P[P_V + 2];
+                    const T vv[3] = {v0, v1, v2};
+                    for (int a = 0; a < 2; ++a) {
+                        const T *bi = Bi + (p * TILE + ty + 16 * a) * 4;
+                        const T Ni = bi[0], Gi[3] = {bi[1], bi[2], bi[3]};
+                        for (int b = 0; b < 2; ++b) {
+                            const T *bj = Bj + (p * TILE + tx + 16 * b) * 4;
+                            const T Nj = bj[0], Gj[3] = {bj[1], bj[2], bj[3]};
+                            T *ac = acc[a][b];
+                            if (face < T(-0.5)) {
+                                // volume: nu grad.grad - Nj (v.grad Ni)  |  -v_c Nj d_e Ni  |  mass
+                                T gg = Gi[0] * Gj[0] + Gi[1] * Gj[1] + Gi[2] * Gj[2];
+                                T vgi = v0 * Gi[0] + v1 * Gi[1] + v2 * Gi[2];
+                                ac[0] += w * (nu * gg - Nj * vgi);
+                                T wn = w * Nj;
+                                for (int c = 0; c < DIM; ++c)
+                                    for (int e2 = 0; e2 < DIM; ++e2) ac[1 + c * 3 + e2] -= wn * vv[c] * Gi[e2];
+                                ac[10] += w * Ni * Nj;
+                            } else {
+                                const T n[3] = {P[P_N], P[P_N + 1], P[P_N + 2]};
+                                const T isD = P[P_ISD], vn = P[P_VN];
+                                T NN = Ni * Nj;
+                                T Gnj = Gj[0] * n[0] + Gj[1] * n[1] + Gj[2] * n[2];
+                                T Gni = Gi[0] * n[0] + Gi[1] * n[1] + Gi[2] * n[2];
+                                T sc = vn * NN;
+                                if (isD != T(0))
+                                    sc += -nu * Gnj * Ni - P[P_OM] * NN - nu * Nj * Gni + P[P_PEN1] * NN;
+                                ac[0] += w * sc;
+                                T f1 = isD != T(0) ? (T(1) - P[P_DOM]) : T(1);
+                                T f2 = isD != T(0) ? P[P_PEN2] : T(0);
+                                for (int c = 0; c < DIM; ++c)
+                                    for (int e2 = 0; e2 < DIM; ++e2)
+                                        ac[1 + c * 3 + e2] += w * NN * (n[e2] * vv[c] * f1 + f2 * n[e2] * n[c]);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            for (int a = 0; a < 2; ++a) {
+                int i = ib + ty + 16 * a;
+                if (i >= NL) continue;
+                for (int b = 0; b < 2; ++b) {
+                    int j = jb + tx + 16 * b;
+                    if (j >= NL) continue;
+                    const T *ac = acc[a][b];
+                    for (int c = 0; c < DIM; ++c)
+                        for (int e2 = 0; e2 < DIM; ++e2) {
+                            T val = ac[1 + c * 3 + e2] + (c == e2 ? ac[0] : T(0));
+                            Avv[((long long)(c * DIM + e2) * NL + i) * NL + j] = val;
+                        }
+                    Mv[(long long)i * NL + j] = ac[10];
+                }
+            }
+        }
+
+    // velocity-pressure coupling: (c,i) x m
+    {
+        constexpr int NPAIR = NL * NPM;
+        constexpr int PPT = (NPAIR + NT - 1) / NT;
+        T acc[PPT][3];
+        for (int s = 0; s < PPT; ++s) acc[s][0] = acc[s][1] = acc[s][2] = 0;
+        for (int ch = 0; ch < nchunks; ++ch) {
+            build_chunk(ch);
+            __syncthreads();
+            for (int s = 0; s < PPT; ++s) {
+                int pr = tid + s * NT;
+                if (pr >= NPAIR) break;
+                int i = pr / NPM, m = pr % NPM;
+                int al[3] = {0, 0, 0};
+                pmode<DIM, R>(m, al);
+                for (int p = 0; p < PCH; ++p) {
+                    const T *P = prec + p * PREC;
+                    T w = P[P_W];
+                    if (w == T(0)) continue;
+                    const int *ix = pidx + p * 3;
+                    T psi = 1;
+                    for (int a = 0; a < DIM; ++a) psi *= lv(ix[a], al[a]);
+                    T b[4];
+                    basis(p, i, b);
+                    if (P[P_FACE] < T(-0.5)) {
+                        for (int c = 0; c < DIM; ++c) acc[s][c] -= w * psi * b[1 + c];
+                    } else if (P[P_ISD] != T(0)) {
+                        for (int c = 0; c < DIM; ++c) acc[s][c] += w * psi * P[P_N + c] * b[0];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        for (int s = 0; s < PPT; ++s) {
+            int pr = tid + s * NT;
+            if (pr >= NPAIR) break;
+            int i = pr / NPM, m = pr % NPM;
+            for (int c = 0; c < DIM; ++c) Avp[((long long)c * NL + i) * NPM + m] = acc[s][c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// patch assembly (principal submatrix of the surrogate, space-time expansion)
+// ---------------------------------------------------------------------------
+template <int DIM, int R, typename TE, typename TP>
+__global__ void __launch_bounds__(256) patch_kernel(PatchArgs<TE, TP> A)
+{
+    using Z = VS<DIM, R>;
+    constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
+    const int cell = blockIdx.x;
+    const int nt = A.nt;
+    const int nv = nt * DIM * NL;
+    const int m = nv + nt * NPM;
+    const int cc[3] = {cell % A.n0, (cell / A.n0) % A.n1, DIM == 3 ? cell / (A.n0 * A.n1) : 0};
+    const int nn[3] = {A.n0, A.n1, A.n2};
+    TP *out = A.patches + (long long)cell * m * m;
+    const long long rw = A.rec_words;
+    for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
+        int row = (int)(e % m), col = (int)(e / m);
+        double val = 0;
+        if (row < nv && col < nv) {
+            int i = row % NL, c = (row / NL) % DIM, a = row / (NL * DIM);
+            int j = col % NL, e2 = (col / NL) % DIM, b = col / (NL * DIM);
+            double kab = A.K[a * nt + b];
+            bool need_m = (c == e2) && kab != 0.0;
+            bool need_l = (a == b);
+            if (need_m || need_l) {
+                int li[3] = {i % N1, (i / N1) % N1, DIM == 3 ? i / (N1 * N1) : 0};
+                int lj[3] = {j % N1, (j / N1) % N1, DIM == 3 ? j / (N1 * N1) : 0};
+                // allowed neighbour offsets per axis: both nodes must lie in the neighbour
+                int opts[3][3], nopt[3];
+                for (int ax = 0; ax < 3; ++ax) {
+                    nopt[ax] = 0;
+                    opts[ax][nopt[ax]++] = 0;
+                    if (ax >= DIM) continue;
+                    if (li[ax] == 0 && lj[ax] == 0 && cc[ax] > 0) opts[ax][nopt[ax]++] = -1;
+                    if (li[ax] == R + 1 && lj[ax] == R + 1 && cc[ax] < nn[ax] - 1) opts[ax][nopt[ax]++] = 1;
+                }
+                double ms = 0, ls = 0;
+                for (int o2 = 0; o2 < nopt[2]; ++o2)
+                    for (int o1 = 0; o1 < nopt[1]; ++o1)
+                        for (int o0 = 0; o0 < nopt[0]; ++o0) {
+                            int dd[3] = {opts[0][o0], opts[1][o1], opts[2][o2]};
+                            long long nb = (cc[0] + dd[0]) + (long long)A.n0 * ((cc[1] + dd[1]) + (long long)A.n1 * (cc[2] + dd[2]));
+                            int ip = 0, jp = 0, st = 1;
+                            for (int ax = 0; ax < DIM; ++ax) {
+                                ip += st * (li[ax] - dd[ax] * (R + 1));
+                                jp += st * (lj[ax] - dd[ax] * (R + 1));
+                                st *= N1;
+                            }
+                            const TE *rec = A.elem + nb * rw;
+                            if (need_m) ms += (double)rec[DIM * DIM * NL * NL + (long long)ip * NL + jp];
+                            if (need_l) ls += (double)rec[((long long)(c * DIM + e2) * NL + ip) * NL + jp];
+                        }
+                if (need_m) val += kab * ms;
+                if (need_l) val += A.w[a] * ls;
+            }
+        } else if (row < nv && col >= nv) {
+            int i = row % NL, c = (row / NL) % DIM, a = row / (NL * DIM);
+            int q = col - nv, b = q / NPM, mm = q % NPM;
+            if (a == b) {
+                const TE *rec = A.elem + (long long)cell * rw + DIM * DIM * NL * NL + NL * NL;
+                val = A.w[a] * (double)rec[((long long)c * NL + i) * NPM + mm];
+            }
+        } else if (row >= nv && col < nv) {
+            int j = col % NL, e2 = (col / NL) % DIM, b = col / (NL * DIM);
+            int q = row - nv, a = q / NPM, mm = q % NPM;
+            if (a == b) {
+                const TE *rec = A.elem + (long long)cell * rw + DIM * DIM * NL * NL + NL * NL;
+                val = A.w[a] * (double)rec[((long long)e2 * NL + j) * NPM + mm];
+            }
+        }
+        out[(long long)col * m + row] = (TP)val;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// batched blocked LU with partial pivoting, column-major, one block / matrix
+// ---------------------------------------------------------------------------
+constexpr int LU_THREADS = 256;
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, int *__restrict__ pivall, int m, int *info)
+{
+    extern __shared__ unsigned char lds_raw[];
+    T *pan = reinterpret_cast<T *>(lds_raw);           // [NB][m] panel (column c at c*m)
+    T *ut = pan + (size_t)NB * m;                      // [NB][64] U12 tile
+    __shared__ T rv[LU_THREADS];
+    __shared__ int ri[LU_THREADS];
+    __shared__ int ppiv[NB];
+    const int tid = threadIdx.x;
+    T *Am = Aall + (long long)blockIdx.x * m * m;
+    int *piv = pivall + (long long)blockIdx.x * m;
+    for (int j0 = 0; j0 < m; j0 += NB) {
+        const int nb = min(NB, m - j0);
+        const int mr = m - j0;                           // rows of the panel
+        for (int e = tid; e < nb * mr; e += LU_THREADS) {
+            int c = e / mr, r = e % mr;
+            pan[c * m + r] = Am[(long long)(j0 + c) * m + j0 + r];
+        }
+        __syncthreads();
+        for (int c = 0; c < nb; ++c) {
+            // pivot search in column c, rows c..mr-1 (first maximum wins)
+            T best = T(-1);
+            int bi = c;
+            for (int r = c + tid; r < mr; r += LU_THREADS) {
+                T v = fabs(pan[c * m + r]);
+                if (v > best) { best = v; bi = r; }
+            }
+            rv[tid] = best;
+            ri[tid] = bi;
+            __syncthreads();
+            for (int s = LU_THREADS / 2; s > 0; s >>= 1) {
+                if (tid < s) {
+                    T o = rv[tid + s];
+                    int oi = ri[tid + s];
+                    if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) { rv[tid] = o; ri[tid] = oi; }
+                }
+                __syncthreads();
+            }
+            const int p = ri[0];
+            if (tid == 0) {
+                piv[j0 + c] = j0 + p;
+                ppiv[c] = j0 + p;
+                if (rv[0] == T(0) && info) atomicAdd(info, 1);
+            }
+            // swap rows c and p inside the panel
+            if (p != c)
+                for (int cc = tid; cc < nb; cc += LU_THREADS) {
+                    T t = pan[cc * m + c];
+                    pan[cc * m + c] = pan[cc * m + p];
+                    pan[cc * m + p] = t;
+                }
+            __syncthreads();
+            const T d = pan[c * m + c];
+            const T inv = d != T(0) ? T(1) / d : T(0);
+            for (int r = c + 1 + tid; r < mr; r += LU_THREADS) pan[c * m + r] *= inv;
+            __syncthreads();
+            // update the remaining panel columns
+            for (int e = tid; e < (nb - c - 1) * (mr - c - 1); e += LU_THREADS) {
+                int cc = c + 1 + e / (mr - c - 1), r = c + 1 + e % (mr - c - 1);
+                pan[cc * m + r] -= pan[c * m + r] * pan[cc * m + c];
+            }
+            __syncthreads();
+        }
+        // write the panel back
+        for (int e = tid; e < nb * mr; e += LU_THREADS) {
+            int c = e / mr, r = e % mr;
+            Am[(long long)(j0 + c) * m + j0 + r] = pan[c * m + r];
+        }
+        // row interchanges of this panel applied to the other columns
+        for (int col = tid; col < m; col += LU_THREADS) {
+            if (col >= j0 && col < j0 + nb) continue;
+            T *cp = Am + (long long)col * m;
+            for (int c = 0; c < nb; ++c) {
+                int p = ppiv[c];
+                if (p != j0 + c) {
+                    T t = cp[j0 + c];
+                    cp[j0 + c] = cp[p];
+                    cp[p] = t;
+                }
+            }
+        }
+        __syncthreads();
+        // U12 = L11^{-1} A12 and A22 -= L21 U12, 64 columns at a time
+        const int r0 = j0 + nb;
+        for (int cb = r0; cb < m; cb += 64) {
+            const int ncb = min(64, m - cb);
+            if (tid < ncb) {
+                T *cp = Am + (long long)(cb + tid) * m;
+                T u[NB];
+                for (int c = 0; c < nb; ++c) u[c] = cp[j0 + c];
+                for (int c = 0; c < nb; ++c)
+                    for (int k = 0; k < c; ++k) u[c] -= pan[k * m + c] * u[k];
+                for (int c = 0; c < nb; ++c) {
+                    cp[j0 + c] = u[c];
+                    ut[c * 64 + tid] = u[c];
+                }
+            }
+            __syncthreads();
+            for (int r = r0 + tid; r < m; r += LU_THREADS) {
+                T l[NB];
+                for (int c = 0; c < nb; ++c) l[c] = pan[c * m + (r - j0)];
+                for (int k = 0; k < ncb; ++k) {
+                    T *ap = Am + (long long)(cb + k) * m + r;
+                    T s = *ap;
+                    for (int c = 0; c < nb; ++c) s -= l[c] * ut[c * 64 + k];
+                    *ap = s;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// patch solves
+// ---------------------------------------------------------------------------
+constexpr int SV_THREADS = 256;
+
+// forward / backward substitution on rhs b (LDS, length m) with LU (col-major)
+template <typename T>
+__device__ void lu_substitute(const T *__restrict__ LU, int m, T *b)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // forward: unit lower
+    for (int kb = 0; kb < m; kb += 64) {
+        const int nbk = min(64, m - kb);
+        if (wv == 0) {
+            T y = lane < nbk ? b[kb + lane] : T(0);
+            for (int c = 0; c < nbk; ++c) {
+                T yc = __shfl(y, c, 64);
+                if (lane > c && lane < nbk) y -= LU[(long long)(kb + c) * m + kb + lane] * yc;
+            }
+            if (lane < nbk) b[kb + lane] = y;
+        }
+        __syncthreads();
+        for (int r = kb + nbk + tid; r < m; r += SV_THREADS) {
+            T s = b[r];
+            for (int c = 0; c < nbk; ++c) s -= LU[(long long)(kb + c) * m + r] * b[kb + c];
+            b[r] = s;
+        }
+        __syncthreads();
+    }
+    // backward: upper with diagonal
+    const int nblk = (m + 63) / 64;
+    for (int bk = nblk - 1; bk >= 0; --bk) {
+        const int kb = bk * 64, nbk = min(64, m - kb);
+        if (wv == 0) {
+            T x = lane < nbk ? b[kb + lane] : T(0);
+            for (int c = nbk - 1; c >= 0; --c) {
+                T xc = __shfl(x, c, 64);
+                T dcc = LU[(long long)(kb + c) * m + kb + c];
+                xc = xc / dcc;
+                if (lane == c) x = xc;
+                if (lane < c) x -= LU[(long long)(kb + c) * m + kb + lane] * xc;
+            }
+            if (lane < nbk) b[kb + lane] = x;
+        }
+        __syncthreads();
+        for (int r = tid; r < kb; r += SV_THREADS) {
+            T s = b[r];
+            for (int c = 0; c < nbk; ++c) s -= LU[(long long)(kb + c) * m + r] * b[kb + c];
+            b[r] = s;
+        }
+        __syncthreads();
+    }
+}
+
+template <int DIM, int R, typename T, typename TP>
+__global__ void __launch_bounds__(SV_THREADS) solve_kernel(SolveArgs<T, TP> A)
+{
+    using Z = VS<DIM, R>;
+    constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
+    extern __shared__ unsigned char lds_raw[];
+    TP *b = reinterpret_cast<TP *>(lds_raw);
+    const int cell = blockIdx.x, tid = threadIdx.x;
+    const int nt = A.nt, nv = nt * DIM * NL, m = nv + nt * NPM;
+    const int c0 = cell % A.n0, c1 = (cell / A.n0) % A.n1, c2 = DIM == 3 ? cell / (A.n0 * A.n1) : 0;
+    const long long N0 = (long long)(R + 1) * A.n0 + 1, N1g = (long long)(R + 1) * A.n1 + 1;
+    auto gnode = [&](int l) -> long long {
+        int i0 = l % N1, i1 = (l / N1) % N1, i2 = DIM == 3 ? l / (N1 * N1) : 0;
+        return ((long long)(R + 1) * c0 + i0) + N0 * (((long long)(R + 1) * c1 + i1) + N1g * ((long long)(R + 1) * c2 + i2));
+    };
+    const long long pbase = (long long)nt * A.Nv1;
+    for (int row = tid; row < m; row += SV_THREADS) {
+        long long g;
+        if (row < nv) {
+            int l = row % NL, c = (row / NL) % DIM, a = row / (NL * DIM);
+            g = a * A.Nv1 + c * A.Nn + gnode(l);
+        } else {
+            int q = row - nv, a = q / NPM, mm = q % NPM;
+            g = pbase + a * A.Np1 + (long long)cell * NPM + mm;
+        }
+        b[row] = (TP)A.defect[g];
+    }
+    __syncthreads();
+    const int *piv = A.piv + (long long)cell * m;
+    if (tid == 0)
+        for (int j = 0; j < m; ++j) {
+            int p = piv[j];
+            if (p != j) {
+                TP t = b[j];
+                b[j] = b[p];
+                b[p] = t;
+            }
+        }
+    __syncthreads();
+    lu_substitute<TP>(A.patches + (long long)cell * m * m, m, b);
+    // velocity -> cell-local buffer [cell][a][c][l]; pressure += omega * x
+    T *Ec = A.E + (long long)cell * nv;
+    for (int row = tid; row < m; row += SV_THREADS) {
+        if (row < nv) Ec[row] = (T)b[row];
+        else {
+            int q = row - nv, a = q / NPM, mm = q % NPM;
+            long long g = pbase + a * A.Np1 + (long long)cell * NPM + mm;
+            A.d[g] += A.omega * (T)b[row];
+        }
+    }
+}
+
+// dense solve of one LU-factored system (coarse level): x = A^{-1} rhs
+template <typename T>
+__global__ void __launch_bounds__(SV_THREADS) dense_solve_kernel(const T *LU, const int *piv, int m, const T *rhs,
+                                                                  T *x, int nout)
+{
+    extern __shared__ unsigned char lds_raw[];
+    T *b = reinterpret_cast<T *>(lds_raw);
+    const int tid = threadIdx.x;
+    for (int r = tid; r < m; r += SV_THREADS) b[r] = r < nout ? rhs[r] : T(0);
+    __syncthreads();
+    if (tid == 0)
+        for (int j = 0; j < m; ++j) {
+            int p = piv[j];
+            if (p != j) {
+                T t = b[j];
+                b[j] = b[p];
+                b[p] = t;
+            }
+        }
+    __syncthreads();
+    lu_substitute<T>(LU, m, b);
+    for (int r = tid; r < nout; r += SV_THREADS) x[r] = b[r];
+}
+
+// coarse matrix from the columns J e_i (batched vmult output, row-major
+// columns) and the border of constant pressures
+__global__ void coarse_matrix_kernel(const double *Y, int n, int nb, int nt, long long pbase, long long Np1, int npm,
+                                     long long ncell, double *A)
+{
+    const int m = n + nb;
+    long long total = (long long)m * m;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+        int row = (int)(e % m), col = (int)(e / m);
+        double v = 0;
+        if (row < n && col < n) v = Y[(long long)col * n + row];
+        else if (row < n && col >= n) {
+            int a = col - n;
+            long long q = row - pbase;
+            if (q >= a * Np1 && q < (a + 1) * Np1 && ((q - a * Np1) % npm) == 0) v = 1.0;
+        } else if (row >= n && col < n) {
+            int a = row - n;
+            long long q = col - pbase;
+            if (q >= a * Np1 && q < (a + 1) * Np1 && ((q - a * Np1) % npm) == 0) v = 1.0;
+        }
+        A[e] = v;
+    }
+    (void)nt;
+    (void)ncell;
+}
+
+__global__ void identity_kernel(double *X, int n)
+{
+    long long total = (long long)n * n;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x)
+        X[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
+// V* = sum_a phimid_a V^a (velocity of one time node)
+template <typename T>
+__global__ void midpoint_kernel(const T *state, long long Nv1, int nt, const double *phim_unused, T pm0, T pm1, T pm2,
+                                T pm3, T *vstar)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nv1) return;
+    T pm[4] = {pm0, pm1, pm2, pm3};
+    T s = 0;
+    for (int a = 0; a < nt; ++a) s += pm[a] * state[a * Nv1 + i];
+    vstar[i] = s;
+    (void)phim_unused;
+}
+
+template <int NB, typename T> size_t lu_lds_bytes(int m) { return ((size_t)NB * m + NB * 64) * sizeof(T); }
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int elem_record_words(int dim, int r)
+{
+    int nl = 1;
+    for (int a = 0; a < dim; ++a) nl *= r + 2;
+    int npm = dim == 2 ? (r + 1) * (r + 2) / 2 : (r + 1) * (r + 2) * (r + 3) / 6;
+    return dim * dim * nl * nl + nl * nl + dim * nl * npm;
+}
+
+template <typename T>
+hipError_t launch_elem(int dim, int r, int nq, const ElemArgs<T> &a, int ncell, hipStream_t s)
+{
+#define ELC(D, RR, Q)                                                                                                  \
+    if (dim == D && r == RR && nq == Q) {                                                                              \
+        hipLaunchKernelGGL((elem_kernel<D, RR, Q, T>), dim3(ncell), dim3(EL_THREADS), 0, s, a);                       \
+        return hipGetLastError();                                                                                      \
+    }
+    ELC(2, 1, 4) ELC(2, 1, 3) ELC(2, 2, 5) ELC(2, 2, 4) ELC(2, 3, 7) ELC(2, 3, 5)
+    ELC(3, 1, 4) ELC(3, 1, 3) ELC(3, 2, 5) ELC(3, 2, 4) ELC(3, 3, 7) ELC(3, 3, 5)
+#undef ELC
+    return hipErrorInvalidValue;
+}
+
+template <typename TE, typename TP>
+hipError_t launch_patch(int dim, int r, const PatchArgs<TE, TP> &a, int ncell, hipStream_t s)
+{
+#define PC(D, RR)                                                                                                      \
+    if (dim == D && r == RR) {                                                                                         \
+        hipLaunchKernelGGL((patch_kernel<D, RR, TE, TP>), dim3(ncell), dim3(256), 0, s, a);                           \
+        return hipGetLastError();                                                                                      \
+    }
+    PC(2, 1) PC(2, 2) PC(2, 3) PC(3, 1) PC(3, 2) PC(3, 3)
+#undef PC
+    return hipErrorInvalidValue;
+}
+
+template <typename T> hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds, hipStream_t s)
+{
+#define LUC(NBV)                                                                                                       \
+    if (lu_lds_bytes<NBV, T>(m) <= max_lds) {                                                                          \
+        size_t bytes = lu_lds_bytes<NBV, T>(m);                                                                        \
+        hipError_t e = hipFuncSetAttribute((const void *)lu_kernel<T, NBV>,                                            \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                    \
+        if (e != hipSuccess) return e;                                                                                 \
+        hipLaunchKernelGGL((lu_kernel<T, NBV>), dim3(batch), dim3(LU_THREADS), bytes, s, A, piv, m, info);            \
+        return hipGetLastError();                                                                                      \
+    }
+    LUC(32) LUC(16) LUC(8) LUC(4) LUC(2) LUC(1)
+#undef LUC
+    return hipErrorInvalidConfiguration;
+}
+
+template <typename T, typename TP>
+hipError_t launch_solve(int dim, int r, const SolveArgs<T, TP> &a, int ncell, int m, hipStream_t s)
+{
+    size_t bytes = (size_t)m * sizeof(TP);
+#define SC(D, RR)                                                                                                      \
+    if (dim == D && r == RR) {                                                                                         \
+        hipError_t e = hipFuncSetAttribute((const void *)solve_kernel<D, RR, T, TP>,                                   \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                    \
+        if (e != hipSuccess) return e;                                                                                 \
+        hipLaunchKernelGGL((solve_kernel<D, RR, T, TP>), dim3(ncell), dim3(SV_THREADS), bytes, s, a);                 \
+        return hipGetLastError();                                                                                      \
+    }
+    SC(2, 1) SC(2, 2) SC(2, 3) SC(3, 1) SC(3, 2) SC(3, 3)
+#undef SC
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_dense_solve(const double *LU, const int *piv, int m, const double *rhs, double *x, int nout,
+                              hipStream_t s)
+{
+    size_t bytes = (size_t)m * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void *)dense_solve_kernel<double>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(dense_solve_kernel<double>, dim3(1), dim3(SV_THREADS), bytes, s, LU, piv, m, rhs, x, nout);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity(double *X, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(identity_kernel, dim3(256), dim3(256), 0, s, X, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_matrix(const double *Y, int n, int nb, int nt, long long pbase, long long Np1, int npm,
+                                long long ncell, double *A, hipStream_t s)
+{
+    hipLaunchKernelGGL(coarse_matrix_kernel, dim3(256), dim3(256), 0, s, Y, n, nb, nt, pbase, Np1, npm, ncell, A);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_midpoint(const T *state, long long Nv1, int nt, const double *pm, T *vstar, hipStream_t s)
+{
+    T p[4] = {0, 0, 0, 0};
+    for (int a = 0; a < nt && a < 4; ++a) p[a] = (T)pm[a];
+    int th = 256;
+    hipLaunchKernelGGL(midpoint_kernel<T>, dim3((unsigned)((Nv1 + th - 1) / th)), dim3(th), 0, s, state, Nv1, nt,
+                       (const double *)nullptr, p[0], p[1], p[2], p[3], vstar);
+    return hipGetLastError();
+}
+
+template hipError_t launch_elem<double>(int, int, int, const ElemArgs<double> &, int, hipStream_t);
+template hipError_t launch_elem<float>(int, int, int, const ElemArgs<float> &, int, hipStream_t);
+template hipError_t launch_patch<double, double>(int, int, const PatchArgs<double, double> &, int, hipStream_t);
+template hipError_t launch_patch<float, float>(int, int, const PatchArgs<float, float> &, int, hipStream_t);
+template hipError_t launch_patch<double, float>(int, int, const PatchArgs<double, float> &, int, hipStream_t);
+template hipError_t launch_lu<double>(double *, int *, int, int, int *, size_t, hipStream_t);
+template hipError_t launch_lu<float>(float *, int *, int, int, int *, size_t, hipStream_t);
+template hipError_t launch_solve<double, double>(int, int, const SolveArgs<double, double> &, int, int, hipStream_t);
+template hipError_t launch_solve<float, float>(int, int, const SolveArgs<float, float> &, int, int, hipStream_t);
+template hipError_t launch_solve<double, float>(int, int, const SolveArgs<double, float> &, int, int, hipStream_t);
+template hipError_t launch_midpoint<double>(const double *, long long, int, const double *, double *, hipStream_t);
+template hipError_t launch_midpoint<float>(const float *, long long, int, const double *, float *, hipStream_t);
+
+} // namespace stmg

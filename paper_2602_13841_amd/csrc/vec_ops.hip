@@ -1,0 +1,195 @@
+// Streaming vector kernels of the Krylov and multigrid layers (HBM bound).
+//
+// Reductions are deterministic: a fixed grid of blocks writes partial sums,
+// one block sums them in a fixed order; results stay on the device.
+#include "vec_ops.h"
+
+namespace stmg {
+
+namespace {
+
+constexpr int RED_THREADS = 256;
+constexpr int RED_BLOCKS = 512;
+
+template <typename T> __global__ void axpby_kernel(long long n, T a, const T *__restrict__ x, T b, T *__restrict__ y)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) y[i] = a * x[i] + (b == T(0) ? T(0) : b * y[i]);
+}
+
+template <typename S, typename D> __global__ void cast_kernel(long long n, const S *__restrict__ x, D *__restrict__ y)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) y[i] = (D)x[i];
+}
+
+template <typename T> __global__ void fill_kernel(long long n, T v, T *__restrict__ y)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) y[i] = v;
+}
+
+// partial[k * RED_BLOCKS + block] = sum over this block's slice of u * V_k
+__global__ void __launch_bounds__(RED_THREADS)
+    multidot_partial(long long n, int nk, const double *__restrict__ u, const double *__restrict__ V,
+                     long long ldv, double *__restrict__ partial)
+{
+    __shared__ double red[RED_THREADS];
+    const int k = blockIdx.y;
+    const double *v = V + (long long)k * ldv;
+    double s = 0;
+    for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (long long)RED_BLOCKS * RED_THREADS)
+        s += u[i] * v[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[k * RED_BLOCKS + blockIdx.x] = red[0];
+    (void)nk;
+}
+
+// out[k] = (accumulate ? out[k] : 0) + sum_b partial[k][b]
+__global__ void __launch_bounds__(RED_THREADS)
+    multidot_final(int nk, const double *__restrict__ partial, double *__restrict__ out, int accumulate)
+{
+    __shared__ double red[RED_THREADS];
+    for (int k = 0; k < nk; ++k) {
+        double s = 0;
+        for (int b = threadIdx.x; b < RED_BLOCKS; b += RED_THREADS) s += partial[k * RED_BLOCKS + b];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = (accumulate ? out[k] : 0.0) + red[0];
+        __syncthreads();
+    }
+}
+
+// w -= sum_k h[k] V_k  and (if MV) u -= sum_k h[k] MV_k ; h on the device
+__global__ void subtract_combination(long long n, int nk, const double *__restrict__ h, const double *__restrict__ V,
+                                     long long ldv, double *__restrict__ w)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) {
+        double s = w[i];
+        for (int k = 0; k < nk; ++k) s -= h[k] * V[(long long)k * ldv + i];
+        w[i] = s;
+    }
+}
+
+// x = sum_k y[k] Z_k (y on the device)
+__global__ void combination(long long n, int nk, const double *__restrict__ y, const double *__restrict__ Z, long long ldz,
+                            double *__restrict__ x)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) {
+        double s = 0;
+        for (int k = 0; k < nk; ++k) s += y[k] * Z[(long long)k * ldz + i];
+        x[i] = s;
+    }
+}
+
+// y[ot][c][row] (+)= sum_it Tm[ot][it] sum_{k in row} val[k] x[it][c][col[k]]
+template <typename T>
+__global__ void kron_csr_kernel(KronCsrArgs<T> A)
+{
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long total = (long long)A.nt_out * A.ncomp * A.nrows;
+    if (idx >= total) return;
+    int row = (int)(idx % A.nrows);
+    long long rest = idx / A.nrows;
+    int c = (int)(rest % A.ncomp);
+    int ot = (int)(rest / A.ncomp);
+    int k0 = A.rowptr[row], k1 = A.rowptr[row + 1];
+    T acc = 0;
+    for (int it = 0; it < A.nt_in; ++it) {
+        T tm = A.Tm[ot * A.nt_in + it];
+        if (tm == T(0)) continue;
+        const T *xs = A.x + it * A.in_t_stride + c * A.in_c_stride;
+        T s = 0;
+        for (int k = k0; k < k1; ++k) s += A.val[k] * xs[A.col[k]];
+        acc += tm * s;
+    }
+    T *yp = A.y + ot * A.out_t_stride + c * A.out_c_stride + row;
+    *yp = A.beta == T(0) ? acc : acc + A.beta * *yp;
+}
+
+inline int grid_for(long long n, int th = 256)
+{
+    long long b = (n + th - 1) / th;
+    if (b > 65535LL * 16) b = 65535LL * 16;
+    return (int)(b < 1 ? 1 : b);
+}
+
+} // namespace
+
+template <typename T> hipError_t vec_axpby(long long n, T a, const T *x, T b, T *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(axpby_kernel<T>, dim3(grid_for(n)), dim3(256), 0, s, n, a, x, b, y);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t vec_fill(long long n, T v, T *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_kernel<T>, dim3(grid_for(n)), dim3(256), 0, s, n, v, y);
+    return hipGetLastError();
+}
+
+template <typename S, typename D> hipError_t vec_cast(long long n, const S *x, D *y, hipStream_t s)
+{
+    hipLaunchKernelGGL((cast_kernel<S, D>), dim3(grid_for(n)), dim3(256), 0, s, n, x, y);
+    return hipGetLastError();
+}
+
+hipError_t vec_multidot(long long n, int nk, const double *u, const double *V, long long ldv, double *out,
+                        double *partial, int accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(multidot_partial, dim3(RED_BLOCKS, nk), dim3(RED_THREADS), 0, s, n, nk, u, V, ldv, partial);
+    hipLaunchKernelGGL(multidot_final, dim3(1), dim3(RED_THREADS), 0, s, nk, partial, out, accumulate);
+    return hipGetLastError();
+}
+
+size_t multidot_partial_words(int nk) { return (size_t)nk * RED_BLOCKS; }
+
+hipError_t vec_subtract_combination(long long n, int nk, const double *h, const double *V, long long ldv, double *w,
+                                    hipStream_t s)
+{
+    hipLaunchKernelGGL(subtract_combination, dim3(grid_for(n)), dim3(256), 0, s, n, nk, h, V, ldv, w);
+    return hipGetLastError();
+}
+
+hipError_t vec_combination(long long n, int nk, const double *y, const double *Z, long long ldz, double *x,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(combination, dim3(grid_for(n)), dim3(256), 0, s, n, nk, y, Z, ldz, x);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t kron_csr_apply(const KronCsrArgs<T> &a, hipStream_t s)
+{
+    long long total = (long long)a.nt_out * a.ncomp * a.nrows;
+    int th = 256;
+    hipLaunchKernelGGL(kron_csr_kernel<T>, dim3((unsigned)((total + th - 1) / th)), dim3(th), 0, s, a);
+    return hipGetLastError();
+}
+
+template hipError_t vec_axpby<double>(long long, double, const double *, double, double *, hipStream_t);
+template hipError_t vec_axpby<float>(long long, float, const float *, float, float *, hipStream_t);
+template hipError_t vec_fill<double>(long long, double, double *, hipStream_t);
+template hipError_t vec_fill<float>(long long, float, float *, hipStream_t);
+template hipError_t vec_cast<double, float>(long long, const double *, float *, hipStream_t);
+template hipError_t vec_cast<float, double>(long long, const float *, double *, hipStream_t);
+template hipError_t vec_cast<double, double>(long long, const double *, double *, hipStream_t);
+template hipError_t kron_csr_apply<double>(const KronCsrArgs<double> &, hipStream_t);
+template hipError_t kron_csr_apply<float>(const KronCsrArgs<float> &, hipStream_t);
+
+} // namespace stmg

@@ -66,6 +66,24 @@ _SIGS = {
     "stmg_jacobian_vmult_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.c_void_p, ctypes.c_int]),
     "stmg_mass_vmult": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_num_levels": (ctypes.c_int, [ctypes.c_void_p]),
+    "stmg_level_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_level_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "stmg_smoother_rebuild": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_level_jacobian_vmult": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                                 ctypes.c_void_p]),
+    "stmg_vanka_smooth": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int]),
+    "stmg_vcycle": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_prolongate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "stmg_restrict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "stmg_fgmres": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_newton_gmres_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "stmg_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "stmg_timing_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "stmg_timing_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -197,6 +215,79 @@ class Context:
         self._check(lib().stmg_jacobian_vmult_batched(self._h, self._prec(dt), self._vec(u_state, dt, name="u_state"),
                                                       _ptr(x), _ptr(out), nvec))
         return out
+
+    # ---- multigrid hierarchy, smoother, Krylov, Newton ----------------------
+    @property
+    def mg_dtype(self):
+        return torch.float64 if self.options.prec_mg == STMG_F64 else torch.float32
+
+    def num_levels(self):
+        return lib().stmg_num_levels(self._h)
+
+    def level_info(self, level):
+        k, r, n, N = ctypes.c_int(), ctypes.c_int(), (ctypes.c_int * 3)(), ctypes.c_longlong()
+        self._check(lib().stmg_level_info(self._h, level, ctypes.byref(k), ctypes.byref(r), n, ctypes.byref(N)))
+        return k.value, r.value, tuple(n[: self.dim]), N.value
+
+    def set_state(self, u):
+        self._check(lib().stmg_set_state(self._h, self._vec(u, torch.float64, name="u_state")))
+
+    def level_state(self, level):
+        N = self.level_info(level)[3]
+        out = torch.empty(N, dtype=torch.float64, device=torch.device("cuda"))
+        self._check(lib().stmg_level_state(self._h, level, _ptr(out)))
+        return out
+
+    def smoother_rebuild(self, u):
+        self._check(lib().stmg_smoother_rebuild(self._h, self._vec(u, torch.float64, name="u_state")))
+
+    def level_jacobian_vmult(self, level, x, out=None):
+        N = self.level_info(level)[3]
+        out = torch.empty_like(x) if out is None else out
+        self._check(lib().stmg_level_jacobian_vmult(self._h, level, self._prec(x.dtype), self._vec(x, x.dtype, N, "x"),
+                                                    self._vec(out, x.dtype, N, "y")))
+        return out
+
+    def vanka_smooth(self, level, r, d, sweeps=1):
+        N = self.level_info(level)[3]
+        self._check(lib().stmg_vanka_smooth(self._h, level, self._prec(r.dtype), self._vec(r, r.dtype, N, "r"),
+                                            self._vec(d, r.dtype, N, "d"), sweeps))
+        return d
+
+    def vcycle(self, r, out=None):
+        out = torch.empty_like(r) if out is None else out
+        self._check(lib().stmg_vcycle(self._h, self._prec(r.dtype), self._vec(r, r.dtype, name="r"),
+                                      self._vec(out, r.dtype, name="d")))
+        return out
+
+    def prolongate(self, level, xc, out=None):
+        Nf, Nc = self.level_info(level)[3], self.level_info(level + 1)[3]
+        out = torch.empty(Nf, dtype=xc.dtype, device=xc.device) if out is None else out
+        self._check(lib().stmg_prolongate(self._h, level, self._prec(xc.dtype), self._vec(xc, xc.dtype, Nc, "xc"),
+                                          self._vec(out, xc.dtype, Nf, "yf")))
+        return out
+
+    def restrict(self, level, xf, out=None):
+        Nf, Nc = self.level_info(level)[3], self.level_info(level + 1)[3]
+        out = torch.empty(Nc, dtype=xf.dtype, device=xf.device) if out is None else out
+        self._check(lib().stmg_restrict(self._h, level, self._prec(xf.dtype), self._vec(xf, xf.dtype, Nf, "xf"),
+                                        self._vec(out, xf.dtype, Nc, "yc")))
+        return out
+
+    def fgmres(self, u_state, b, rtol, maxit=50):
+        x = torch.empty_like(b)
+        its = ctypes.c_int()
+        hist = (ctypes.c_double * (maxit + 2))()
+        rc = self._check(lib().stmg_fgmres(self._h, self._vec(u_state, torch.float64, name="u_state"),
+                                           self._vec(b, torch.float64, name="b"), self._vec(x, torch.float64, name="x"),
+                                           rtol, maxit, ctypes.byref(its), hist))
+        return x, its.value, list(hist[: its.value + 1]), rc == 0
+
+    def newton_solve(self, u):
+        st = Stats()
+        rc = self._check(lib().stmg_newton_gmres_solve(self._h, self._vec(u, torch.float64, name="u"),
+                                                       ctypes.byref(st)))
+        return u, st, rc
 
     # ---- kernel timers -----------------------------------------------------
     def timing(self, on: bool = True):

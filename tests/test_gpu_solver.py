@@ -1,0 +1,186 @@
+"""Parity of the HIP multigrid, Vanka, FGMRES and Newton path with the
+oracle (GPU).
+
+Bar: with the multigrid in FP64 the level states, level Jacobians, transfers,
+Vanka sweeps and V-cycles match the oracle to 1e-9 relative (LU solves of
+saddle-point patches lose a few digits against 1e-12), FGMRES and Newton
+iteration counts are identical and the solutions agree to 1e-8; with the
+multigrid in FP32 (the default) sweeps and cycles match to 2e-4 relative
+and solves converge to the same tolerance with iteration counts within one.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from oracle import manufactured as MS  # noqa: E402
+from oracle import solver as S  # noqa: E402
+from paper_2602_13841_amd import inputs as I  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stmg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_13841_amd import stmg as Sm
+    return Sm
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda")
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+CASES = [
+    # name, dim, n, r, k, nu, tau, perturbed, mask, max_levels
+    ("c1_4x4", 2, (4, 4), 1, 1, 1.0, 0.1, False, None, 0),
+    ("2d_r2k2_pert", 2, (4, 4), 2, 2, 0.05, 0.05, True, None, 0),
+    ("2d_r3k1_neumann", 2, (4, 2), 3, 1, 0.1, 0.1, True, 0b0111, 0),
+    ("3d_r1k1_4cube", 3, (4, 4, 4), 1, 1, 0.01, 0.125, False, None, 0),
+    ("3d_r2k2_2cube_pert", 3, (2, 2, 2), 2, 2, 0.02, 0.05, True, None, 0),
+]
+IDS = [c[0] for c in CASES]
+
+
+def make(case, stmg, prec):
+    name, d, n, r, k, nu, tau, pert, mask, maxl = case
+    vert = I.perturbed_vertices(d, n, 0.2, 60 + r) if pert else None
+    prob = oracle.Problem(dim=d, n=n, r=r, k=k, nu=nu, tau=tau, vertices=vert, dirichlet_mask=mask)
+    H = S.Hierarchy(prob, max_levels=maxl)
+    ctx = stmg.Context(d, n, r, k, nu, tau, vertices=vert, dirichlet_faces=prob.dirichlet_mask,
+                       prec_mg=prec, max_levels=maxl)
+    return prob, H, ctx
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_levels_states_jacobians_transfers(case, stmg):
+    prob, H, ctx = make(case, stmg, stmg.STMG_F64)
+    assert ctx.num_levels() == len(H.levels)
+    for l, L in enumerate(H.levels):
+        k, r, n, N = ctx.level_info(l)
+        assert (k, r, n, N) == (L.slab.prob.k, L.slab.prob.r, tuple(L.slab.prob.n), L.slab.N)
+    U = I.uniform(H.levels[0].slab.N, 21)
+    H.set_state(U)
+    ctx.set_state(dev(U))
+    for l, L in enumerate(H.levels):
+        s = L.slab
+        nvel = s.nt * s.Nv
+        got = ctx.level_state(l).cpu().numpy()
+        assert rel(got[:nvel], L.state[:nvel]) < 1e-12
+        x = I.uniform(s.N, 22 + l)
+        y = ctx.level_jacobian_vmult(l, dev(x)).cpu().numpy()
+        assert rel(y, L.J @ x) < 1e-12
+    for l in range(len(H.levels) - 1):
+        Nf, Nc = H.levels[l].slab.N, H.levels[l + 1].slab.N
+        xc, xf = I.uniform(Nc, 30 + l), I.uniform(Nf, 40 + l)
+        assert rel(ctx.prolongate(l, dev(xc)).cpu().numpy(), H.P[l] @ xc) < 1e-13
+        assert rel(ctx.restrict(l, dev(xf)).cpu().numpy(), H.P[l].T @ xf) < 1e-13
+        assert rel(ctx.prolongate(l, dev(xc, torch.float32)).cpu().numpy(), H.P[l] @ xc) < 1e-6
+        assert rel(ctx.restrict(l, dev(xf, torch.float32)).cpu().numpy(), H.P[l].T @ xf) < 1e-6
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_vanka_sweep_and_vcycle(case, prec, stmg):
+    p = stmg.STMG_F64 if prec == "f64" else stmg.STMG_F32
+    dt = torch.float64 if prec == "f64" else torch.float32
+    tol = 1e-9 if prec == "f64" else 2e-4
+    prob, H, ctx = make(case, stmg, p)
+    s0 = H.levels[0].slab
+    U = I.uniform(s0.N, 23)
+    H.set_state(U)
+    ctx.smoother_rebuild(dev(U))
+    if len(H.levels) > 1:
+        H.rebuild_smoother()
+        r = I.uniform(s0.N, 24)
+        d0 = I.uniform(s0.N, 25) * 0.1
+        want = H.smooth(0, r, d0)
+        d = dev(d0, dt)
+        ctx.vanka_smooth(0, dev(r, dt), d)
+        assert rel(d.cpu().numpy(), want) < tol
+    r = I.uniform(s0.N, 26)
+    want = H.vcycle(r)
+    got = ctx.vcycle(dev(r, dt)).cpu().numpy()
+    assert rel(got, want) < tol
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=IDS[:4])
+def test_fgmres_matches_oracle(case, stmg):
+    prob, H, ctx = make(case, stmg, stmg.STMG_F64)
+    s0 = H.levels[0].slab
+    # smooth Newton-like state: the smooth field at every time node, damped in time
+    name, d, n, r, k = case[:5]
+    v = I.smooth_velocity(d, n, r, 29)
+    V = np.array([v * (1.0 - 0.3 * t) for t in s0.tt.t / s0.prob.tau])
+    U = s0.join(V, np.zeros((s0.nt, s0.Np)))
+    H.set_state(U)
+    H.rebuild_smoother()
+    ctx.smoother_rebuild(dev(U))
+    b = I.uniform(s0.N, 28)
+    if H.pure_dirichlet:
+        # consistent right-hand side: orthogonal to the constant pressures of
+        # each time node (the kernel of J^T when Gamma_D is the whole boundary)
+        E = S.constant_pressure_vectors(s0)
+        b = b - E @ ((E.T @ b) / np.sum(E * E, axis=0))
+    M = s0.slab_mass()
+    J = H.levels[0].J
+    ref = S.fgmres(lambda z: J @ z, H.vcycle, lambda v: M @ v, b, 1e-6, 50)
+    x, its, hist, conv = ctx.fgmres(dev(U), dev(b), 1e-6, 50)
+    assert ref.converged and conv
+    assert its == ref.its
+    assert rel(hist, ref.history) < 1e-6
+    assert rel(x.cpu().numpy(), ref.x) < 1e-6
+
+
+def _newton_case(which):
+    if which == "c1_manufactured":
+        prob = oracle.Problem(dim=2, n=(4, 4), r=1, k=1, nu=1.0, tau=0.1)
+        slab = oracle.Slab(prob)
+        return prob, slab, MS.slab_rhs(slab, 0.0), np.zeros(slab.Nv), 2
+    if which == "c1_8x8_manufactured":
+        prob = oracle.Problem(dim=2, n=(8, 8), r=1, k=1, nu=1.0, tau=0.1)
+        slab = oracle.Slab(prob)
+        return prob, slab, MS.slab_rhs(slab, 0.0), np.zeros(slab.Nv), 2
+    if which == "3d_4cube_r1k1":
+        prob = oracle.Problem(dim=3, n=(4, 4, 4), r=1, k=1, nu=1e-2, tau=1 / 8)
+        slab = oracle.Slab(prob)
+        return prob, slab, None, I.smooth_velocity(3, (4, 4, 4), 1, 5), 0
+    prob = oracle.Problem(dim=2, n=(4, 4), r=2, k=2, nu=1e-2, tau=1 / 8,
+                          vertices=I.perturbed_vertices(2, (4, 4), 0.2, 7))
+    slab = oracle.Slab(prob)
+    return prob, slab, None, I.smooth_velocity(2, (4, 4), 2, 8), 0
+
+
+@pytest.mark.parametrize("which", ["c1_manufactured", "c1_8x8_manufactured", "3d_4cube_r1k1", "2d_r2k2_pert_decay"])
+def test_newton_matches_oracle(which, stmg):
+    prob, slab, rhs, vprev, maxl = _newton_case(which)
+    H = S.Hierarchy(prob, max_levels=maxl)
+    U_ref, st_ref = S.newton_solve(slab, H, np.zeros(slab.N), rhs, vprev)
+    assert st_ref.converged
+    results = {}
+    for prec in (stmg.STMG_F64, stmg.STMG_F32):
+        ctx = stmg.Context(prob.dim, prob.n, prob.r, prob.k, prob.nu, prob.tau, vertices=prob.vertices,
+                           prec_mg=prec, max_levels=maxl)
+        ctx.set_slab_data(dev(rhs) if rhs is not None else None, dev(vprev))
+        u = torch.zeros(slab.N, dtype=torch.float64, device="cuda")
+        u, st, rc = ctx.newton_solve(u)
+        results[prec] = (u.cpu().numpy(), st, rc)
+    u64, st64, rc64 = results[stmg.STMG_F64]
+    assert rc64 == 0
+    assert st64.newton_its == st_ref.newton_its
+    assert list(st64.fgmres_its[: st64.newton_its]) == st_ref.fgmres_its
+    assert st64.rebuilds == st_ref.rebuilds
+    assert abs(st64.res0_M - st_ref.res0) <= 1e-12 * st_ref.res0
+    assert rel(u64, U_ref) < 1e-7
+    u32, st32, rc32 = results[stmg.STMG_F32]
+    assert rc32 == 0
+    assert st32.res_M <= max(1e-12, 1e-8 * st32.res0_M)
+    assert abs(st32.newton_its - st_ref.newton_its) <= 1
+    assert rel(u32, U_ref) < 1e-6
