@@ -81,7 +81,7 @@ typedef struct {
     int n_q;                  /* Gauss points per direction; 0 = ceil((3r+4)/2) */
     int max_levels;           /* multigrid levels cap; 0 = coarsen to 2^d cells */
     int nu1, nu2;             /* pre/post smoothing steps (1, 1) */
-    double vanka_omega;       /* relaxation omega of eq. LVS; 0 = 1.4 / 2^d */
+    double vanka_omega;       /* relaxation omega of eq. LVS; 0 = default (1.0 weighted, 1.4/2^d plain) */
     int prec_mg;              /* stmg_prec of the multigrid preconditioner */
     /* Newton (Alg. "Inexact Newton-Krylov") */
     double newton_rtol, newton_atol;
@@ -96,6 +96,11 @@ typedef struct {
     int rb_stag_s;
     /* FGMRES */
     int fgmres_maxit;
+    /* Vanka sweep weighting (eq. vanka0 leaves omega open): 1 = each
+     * unknown's correction divided by the number of patches holding it
+     * (partition of unity, omega default 1.0; the default); 0 = the plain
+     * sum of the patch corrections with a scalar omega (default 1.4/2^d). */
+    int vanka_weighting;
 } stmg_options;
 
 typedef struct {
@@ -216,6 +221,39 @@ int stmg_fgmres(stmg_ctx *ctx, const double *u_state, const double *b, double *x
  * solution out (device, FP64).  Stops when ||R||_M <= max(atol, rtol
  * ||R_0||_M).  stats may be NULL. */
 int stmg_newton_gmres_solve(stmg_ctx *ctx, double *u_inout, stmg_stats *stats);
+
+/* ---- serving (continuous batching of slab solves) ------------------------
+ * A request is one slab problem with HOST data: v_prev (Nv1 doubles, may be
+ * NULL = 0), rhs (N doubles or NULL), u_init (N doubles or NULL = 0) and the
+ * output buffer u_out (N doubles, may be NULL).  arrival_s: arrival time in
+ * seconds after the start of stmg_serve.  prob.vertices must stay valid
+ * until stmg_serve returns. */
+typedef struct {
+    stmg_problem prob;
+    double arrival_s;
+    const double *v_prev;
+    const double *rhs;
+    const double *u_init;
+    double *u_out;
+} stmg_request;
+
+typedef struct {
+    double start_s, end_s;    /* admission and completion time */
+    double latency_s;         /* completion - arrival */
+    int rc;                   /* return code of the solve */
+    size_t footprint;         /* device bytes reserved for the request */
+    stmg_stats stats;
+} stmg_request_result;
+
+/* Serve n requests with `slots` concurrent solves on the current device:
+ * FIFO in arrival order, a request is admitted when it has arrived, a slot
+ * is free and its footprint (stmg_footprint_bytes) fits in hbm_budget bytes
+ * (0 = no budget).  Every admitted request runs on its own stream and
+ * context, so the work of overlapping requests overlaps on the device.
+ * wall_s: total time (may be NULL).  Returns 0, or the last negative
+ * request code; STMG_ENOMEM if a single request exceeds the budget. */
+int stmg_serve(const stmg_request *reqs, int n, const stmg_options *opt, int slots, size_t hbm_budget,
+               stmg_request_result *res, double *wall_s);
 
 /* Named kernel timers (hipEvent pairs on the context stream around each
  * kernel launch, e.g. "cell_jac_f64", "gather_f64", "cell_res_f64",

@@ -17,7 +17,9 @@ equations" and the algorithms of the appendix:
 * inexact space-time Vanka smoother (eq. LVS, eq. DefTildeHn, eq. vanka0):
   patch = all unknowns of one cell at all time nodes, local matrix = the
   principal submatrix of the midpoint-frozen surrogate Jacobian, LU with
-  partial pivoting, additive sweep d += omega sum_K R^T S^{-1} R (r - J d);
+  partial pivoting, additive sweep d += omega W sum_K R^T S^{-1} R (r - J d)
+  with W = diag(1 / number of patches holding the unknown) (default) or
+  W = I (literal plain sum, option);
 * V-cycle with nu1 = nu2 = 1, coarsest level solved directly (bordered by
   the constant pressures of each time node when Gamma_D is the whole
   boundary);
@@ -255,9 +257,12 @@ class Level:
 class Hierarchy:
     """hp-STMG hierarchy of one slab problem."""
 
-    def __init__(self, prob: Problem, max_levels: int = 0, omega: float | None = None):
+    def __init__(self, prob: Problem, max_levels: int = 0, omega: float | None = None, weighting: int = 1):
         self.prob = prob
-        self.omega = default_omega(prob.dim) if omega is None else omega
+        self.weighting = weighting
+        if omega is None:
+            omega = 1.0 if weighting else default_omega(prob.dim)
+        self.omega = omega
         specs = level_specs(prob, max_levels)
         self.levels = []
         self.kinds = []
@@ -309,6 +314,10 @@ class Hierarchy:
         vstar = s.tt.phimid @ V                   # eq. DefVnAst
         Jt = s.jacobian(L.state, surrogate_state=vstar)
         L.patches = [(idx, sla.lu_factor(Jt[idx][:, idx].toarray())) for idx in patch_indices(s)]
+        mult = np.zeros(s.N)
+        for idx, _ in L.patches:
+            mult[idx] += 1.0
+        L.mult = mult
 
     def _coarse_factor(self):
         L = self.levels[-1]
@@ -332,12 +341,16 @@ class Hierarchy:
 
     # ---- smoother and cycle ----------------------------------------------
     def smooth(self, li, r, d):
-        """One additive Vanka sweep (eq. vanka0) on level li."""
+        """One additive Vanka sweep (eq. vanka0) on level li.  weighting = 1:
+        each unknown's update is divided by the number of patches holding it
+        (partition of unity) before the relaxation omega."""
         L = self.levels[li]
         defect = r - L.J @ d
         upd = np.zeros_like(d)
         for idx, lu in L.patches:
             upd[idx] += sla.lu_solve(lu, defect[idx])
+        if self.weighting:
+            upd = upd / L.mult
         return d + self.omega * upd
 
     def vcycle(self, r, li=0, nu1=1, nu2=1):
@@ -356,9 +369,11 @@ class Hierarchy:
 
 
 def default_omega(dim: int) -> float:
-    """Relaxation of the additive sweep (eq. vanka0; the paper leaves omega
-    open): 1.4 / 2^d, i.e. about 1.4 over the number of patches that share a
-    vertex (reading fixed by a sweep on the 2D and 3D test problems)."""
+    """Scalar relaxation of the plain additive sweep (eq. vanka0 with
+    weighting = 0; the paper leaves omega open): 1.4 / 2^d, about 1.4 over
+    the number of patches that share a vertex (fixed by a sweep on 2D and 3D
+    test problems).  The default sweep (weighting = 1) instead divides each
+    unknown's correction by the number of patches holding it, with omega = 1."""
     return 1.4 / (1 << dim)
 
 

@@ -1,6 +1,7 @@
 // extern "C" entry points of the stmg library.
 #include "mg.h"
 
+#include <cmath>
 #include <cstring>
 
 using namespace stmg;
@@ -70,6 +71,7 @@ void stmg_default_options(stmg_options *o)
     o->rb_stag_theta = 0.9;
     o->rb_stag_s = 3;
     o->fgmres_maxit = 50;
+    o->vanka_weighting = 1;
 }
 
 int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_ctx **out)
@@ -119,21 +121,61 @@ const char *stmg_last_error(const stmg_ctx *ctx) { return ctx ? ctx->err.c_str()
 
 size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt)
 {
-    (void)opt;
     std::string why;
     if (!check_problem(prob, why)) return 0;
-    long long ncell = 1, nn = 1;
-    for (int a = 0; a < prob->dim; ++a) {
-        ncell *= prob->n_cells[a];
-        nn *= (long long)(prob->r + 1) * prob->n_cells[a] + 1;
+    stmg_options o;
+    if (opt) o = *opt;
+    else stmg_default_options(&o);
+    const int d = prob->dim;
+    const size_t w = o.prec_mg == STMG_F64 ? 8 : 4;
+    const int maxit = o.fgmres_maxit > 0 ? o.fgmres_maxit : 50;
+    // level specs (same rule as the hierarchy)
+    struct Spec { int k, r, n[3]; };
+    std::vector<Spec> specs;
+    Spec sp{prob->k, prob->r, {prob->n_cells[0], prob->n_cells[1], d == 3 ? prob->n_cells[2] : 1}};
+    specs.push_back(sp);
+    auto cnt = [&]() { return (int)specs.size(); };
+    while ((sp.r > 1 || sp.k > 1) && (o.max_levels == 0 || cnt() < o.max_levels)) {
+        sp.r = std::max(1, sp.r / 2);
+        sp.k = sp.k >= 2 ? sp.k / 2 : sp.k;
+        specs.push_back(sp);
     }
-    long long nl = 1;
-    for (int a = 0; a < prob->dim; ++a) nl *= prob->r + 2;
-    long long nt = prob->k + 1;
-    // cell-local result buffers (FP64 + FP32) and slab data
-    size_t b = (size_t)ncell * nt * prob->dim * nl * (8 + 4);
-    b += (size_t)nt * (prob->dim * nn + ncell * 20) * 8 + prob->dim * nn * 8;
-    return b;
+    auto hok = [&]() {
+        for (int a = 0; a < d; ++a)
+            if (sp.n[a] % 2 != 0 || sp.n[a] < 4) return false;
+        return true;
+    };
+    while (hok() && (o.max_levels == 0 || cnt() < o.max_levels)) {
+        for (int a = 0; a < d; ++a) sp.n[a] /= 2;
+        specs.push_back(sp);
+    }
+    size_t total = 0;
+    long long N0 = 0;
+    for (size_t l = 0; l < specs.size(); ++l) {
+        const Spec &q = specs[l];
+        long long ncell = 1, nn = 1, nl = 1;
+        for (int a = 0; a < d; ++a) {
+            ncell *= q.n[a];
+            nn *= (long long)(q.r + 1) * q.n[a] + 1;
+            nl *= q.r + 2;
+        }
+        const long long npm = d == 2 ? (q.r + 1) * (q.r + 2) / 2 : (q.r + 1) * (q.r + 2) * (q.r + 3) / 6;
+        const long long nt = q.k + 1, Nv1 = d * nn, N = nt * (Nv1 + ncell * npm);
+        const long long m = nt * (d * nl + npm);
+        if (l == 0) N0 = N;
+        total += (size_t)N * (8 + 4) + 3 * (size_t)N * w;                  // states, work vectors
+        total += (size_t)ncell * nt * d * nl * (8 + 4 + w);                // cell-local result buffers
+        total += (size_t)nn * (size_t)std::pow(q.r + 3, d) * 16 * 3;       // transfer CSRs (upper bound)
+        if (l + 1 < specs.size()) {
+            total += (size_t)Nv1 * w + (size_t)ncell * (d * d * nl * nl + nl * nl + d * nl * npm) * w;
+            total += (size_t)ncell * m * m * w + (size_t)ncell * m * 4;       // patch factors
+        } else {
+            total += (size_t)N * N * 8 * 2 + (size_t)(N + nt) * (N + nt) * 8 + (size_t)N * ncell * nt * d * nl * 8;
+        }
+    }
+    total += (size_t)N0 * 8 * (3 * (size_t)maxit + 12);                       // Krylov bases, Newton vectors
+    total += 64u << 20;                                                       // tables, scratch
+    return total;
 }
 
 int stmg_sizes(const stmg_ctx *ctx, long long *n_total, long long *n_velocity, long long *n_pressure)

@@ -24,6 +24,8 @@
 //          M-norm of eq. inexact)
 #include "stmg_internal.h"
 
+#include <mutex>
+
 namespace stmg {
 
 namespace {
@@ -767,6 +769,7 @@ __global__ void gather_kernel(GatherArgs<T> G)
                 s += Ev[((cell * G.nt + a) * G.dim + c) * G.nl + l];
             }
     T *y = G.y + vec * G.ystride;
+    if (G.inv_mult) s /= T(cnt[0] * cnt[1] * cnt[2]);
     s *= G.alpha;
     if (G.rhs) s -= G.rhs[idx];
     if (G.accumulate) s += y[idx];
@@ -784,6 +787,8 @@ static hipError_t launch_one(const CellArgs<T> &a, int nvec, hipStream_t s)
     lay.init(R, NQ);
     size_t bytes = (size_t)lds_words<DIM, R, NQ, T>(a.nt, lay.total) * sizeof(T);
     auto kern = cell_kernel<DIM, R, NQ, NTH, T, MODE>;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
     static size_t attr_bytes = 0;
     static int max_lds = -1;
     if (max_lds < 0) {

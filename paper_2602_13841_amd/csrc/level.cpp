@@ -96,6 +96,7 @@ template <typename T> GatherArgs<T> Level::gather_args() const
     g.nl = nl;
     g.alpha = T(1);
     g.accumulate = 0;
+    g.inv_mult = 0;
     return g;
 }
 

@@ -12,7 +12,9 @@
 //   coarser nodes and Radau nodes; the coarsest level is solved directly in
 //   FP64, bordered by the constant pressure of each time node when Gamma_D
 //   is the whole boundary;
-// * smoother relaxation omega = 1.4 / 2^d unless set;
+// * smoother relaxation: each unknown's correction divided by the number of
+//   patches holding it, omega = 1 (default), or the plain sum with a scalar
+//   omega = 1.4 / 2^d;
 // * FGMRES: Arnoldi in the M_n inner product, classical Gram-Schmidt with
 //   one reorthogonalization, zero initial guess, no restart;
 // * Newton: Eisenstat-Walker update of Alg. "Inexact Newton-Krylov";
@@ -26,8 +28,26 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 namespace stmg {
+
+// progress log on stderr when the environment variable STMG_VERBOSE is set
+static bool verbose()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = std::getenv("STMG_VERBOSE");
+        v = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+
+static double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 namespace {
 
@@ -72,7 +92,8 @@ void mg_build(stmg_ctx *ctx)
     const stmg_options &o = ctx->opt;
     Level &L0 = *ctx->levels[0];
     mg->prec = o.prec_mg == STMG_F64 ? STMG_F64 : STMG_F32;
-    mg->omega = o.vanka_omega > 0 ? o.vanka_omega : 1.4 / double(1 << L0.dim);
+    mg->weighting = o.vanka_weighting ? 1 : 0;
+    mg->omega = o.vanka_omega > 0 ? o.vanka_omega : (mg->weighting ? 1.0 : 1.4 / double(1 << L0.dim));
     mg->nu1 = std::max(0, o.nu1);
     mg->nu2 = std::max(0, o.nu2);
     int dev = 0, lds = 65536;
@@ -198,7 +219,10 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
     ea.g2 = (T)L.g2;
     ea.out = M.elem.as<T>();
     ea.rec_words = rw;
-    STMG_HIP(launch_elem<T>(L.dim, L.r, L.nq, ea, (int)L.ncell, s));
+    {
+        TimerScope ts(&ctx->timers, "vanka_elem", s);
+        STMG_HIP(launch_elem<T>(L.dim, L.r, L.nq, ea, (int)L.ncell, s));
+    }
     M.m = L.nt * (L.dim * L.nl + L.npm);
     size_t pb = (size_t)L.ncell * M.m * M.m * sizeof(T);
     if (M.patches.bytes < pb) M.patches.alloc(pb);
@@ -214,9 +238,15 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
     for (int i = 0; i < L.nt * L.nt; ++i) pa.K[i] = L.tc.K[i];
     for (int i = 0; i < L.nt; ++i) pa.w[i] = L.tc.w[i];
     pa.patches = M.patches.as<T>();
-    STMG_HIP((launch_patch<T, T>(L.dim, L.r, pa, (int)L.ncell, s)));
+    {
+        TimerScope ts(&ctx->timers, "vanka_patch", s);
+        STMG_HIP((launch_patch<T, T>(L.dim, L.r, pa, (int)L.ncell, s)));
+    }
     STMG_HIP(hipMemsetAsync(M.info.p, 0, 4, s));
-    STMG_HIP(launch_lu<T>(M.patches.as<T>(), M.piv.as<int>(), M.m, (int)L.ncell, M.info.as<int>(), max_lds, s));
+    {
+        TimerScope ts(&ctx->timers, "vanka_lu", s);
+        STMG_HIP(launch_lu<T>(M.patches.as<T>(), M.piv.as<int>(), M.m, (int)L.ncell, M.info.as<int>(), max_lds, s));
+    }
     M.have_patches = true;
 }
 
@@ -225,8 +255,15 @@ void mg_rebuild(stmg_ctx *ctx)
     Mg &mg = *ctx->mg;
     TimerScope ts(&ctx->timers, "vanka_rebuild", ctx->stream);
     for (size_t l = 0; l + 1 < mg.lv.size(); ++l) {
+        double t0 = verbose() ? now_s() : 0.0;
         if (mg.prec == STMG_F64) rebuild_level<double>(ctx, mg.lv[l], mg.max_lds);
         else rebuild_level<float>(ctx, mg.lv[l], mg.max_lds);
+        if (verbose()) {
+            STMG_HIP(hipStreamSynchronize(ctx->stream));
+            std::fprintf(stderr, "[stmg] rebuild level %zu: %lld patches of %d, %.3f s\n", l, mg.lv[l].L->ncell,
+                         mg.lv[l].m, now_s() - t0);
+            std::fflush(stderr);
+        }
     }
 }
 
@@ -262,6 +299,7 @@ template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
     g.ystride = L.N;
     g.alpha = (T)mg.omega;
     g.accumulate = 1;
+    g.inv_mult = mg.weighting;
     STMG_HIP(launch_gather<T>(g, 1, s));
 }
 
@@ -549,6 +587,12 @@ int newton_solve(stmg_ctx *ctx, double *U, stmg_stats *stats)
             st.rebuilds++;
         }
         ++k;
+        if (verbose()) {
+            std::fprintf(stderr, "[stmg] newton %d: |R|_M %.3e (rho %.3f) fgmres %d alpha %.3g rebuilds %d  %.2f s\n", k,
+                         nrm, rho_prev, fo.its, alpha, st.rebuilds,
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+            std::fflush(stderr);
+        }
     }
     STMG_HIP(hipStreamSynchronize(s));
     st.newton_its = k;

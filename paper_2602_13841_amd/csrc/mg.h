@@ -22,6 +22,7 @@ struct MgLevel {
 struct Mg {
     int prec = STMG_F32;
     double omega = 0.35;
+    int weighting = 0;
     int nu1 = 1, nu2 = 1;
     std::vector<MgLevel> lv;
     std::vector<std::unique_ptr<Transfer>> tr;   // tr[l]: level l -> l+1

@@ -108,6 +108,7 @@ struct GatherArgs {
     int nl;     // (r+2)^dim
     T alpha;        // y = alpha * sum (+ y if accumulate) (- rhs)
     int accumulate;
+    int inv_mult;   // divide the sum by the number of cells holding the node
 };
 
 // launchers (cell_ops.hip)

@@ -25,7 +25,7 @@ template <typename TE, typename TP> struct PatchArgs {
     long long rec_words;
     double K[16];
     double w[4];
-    TP *patches;           // [cell][m*m] column-major
+    TP *patches;           // [cell][m*m] row-major
 };
 
 template <typename T, typename TP> struct SolveArgs {
@@ -33,18 +33,30 @@ template <typename T, typename TP> struct SolveArgs {
     int nt;
     long long Nn, Nv1, Np1;
     const T *defect;       // slab vector
-    const TP *patches;
+    const TP *patches;     // row-major LU factors
     const int *piv;
     T *E;                  // [cell][a][c][l] velocity part of the patch solution
     T *d;                  // slab vector: pressure part updated in place
     T omega;
 };
 
+// a batch of LU factorizations: uniform size m, or per-matrix sizes and
+// offsets (elements of A, entries of the pivot array)
+struct LuBatch {
+    int uniform_m;
+    const int *m_of;
+    const long long *a_off;
+    const long long *p_off;
+};
+
 int elem_record_words(int dim, int r);
 template <typename T> hipError_t launch_elem(int dim, int r, int nq, const ElemArgs<T> &a, int ncell, hipStream_t s);
 template <typename TE, typename TP>
 hipError_t launch_patch(int dim, int r, const PatchArgs<TE, TP> &a, int ncell, hipStream_t s);
-template <typename T> hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds, hipStream_t s);
+// m: the (largest) matrix size; vb: variable sizes (nullptr = all m x m, contiguous)
+template <typename T>
+hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds, hipStream_t s,
+                     const LuBatch *vb = nullptr);
 template <typename T, typename TP>
 hipError_t launch_solve(int dim, int r, const SolveArgs<T, TP> &a, int ncell, int m, hipStream_t s);
 hipError_t launch_dense_solve(const double *LU, const int *piv, int m, const double *rhs, double *x, int nout,

@@ -13,10 +13,13 @@
 //                       summing the element matrices of every cell that
 //                       holds both nodes of an entry, expanded with the time
 //                       matrices: K_ab M_S + delta_ab w_a L_S (velocity),
-//                       delta_ab w_a B_S^(T) (pressure).  Column-major.
+//                       delta_ab w_a B_S^(T) (pressure).  Row-major.
 //   3. lu_kernel        one workgroup per patch: blocked right-looking LU
-//                       with partial pivoting; the panel lives in LDS, the
-//                       trailing update streams the patch once per panel.
+//                       with partial pivoting (row-major, so row interchanges
+//                       move contiguous rows); the panel lives in LDS and is
+//                       factored with three barriers per column; the trailing
+//                       update streams the patch once per panel, on MFMA
+//                       (FP32) or register tiles (FP64).
 // Apply, per smoothing step:
 //   4. solve_kernel     one workgroup per patch: gather the defect, apply the
 //                       pivots, blocked forward/backward substitution (64-wide
@@ -509,7 +512,7 @@ __global__ void __launch_bounds__(256) patch_kernel(PatchArgs<TE, TP> A)
     TP *out = A.patches + (long long)cell * m * m;
     const long long rw = A.rec_words;
     for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
-        int row = (int)(e % m), col = (int)(e / m);
+        int row = (int)(e / m), col = (int)(e % m);
         double val = 0;
         if (row < nv && col < nv) {
             int i = row % NL, c = (row / NL) % DIM, a = row / (NL * DIM);
@@ -563,155 +566,264 @@ __global__ void __launch_bounds__(256) patch_kernel(PatchArgs<TE, TP> A)
                 val = A.w[a] * (double)rec[((long long)e2 * NL + j) * NPM + mm];
             }
         }
-        out[(long long)col * m + row] = (TP)val;
+        out[(long long)row * m + col] = (TP)val;
     }
 }
 
 // ---------------------------------------------------------------------------
-// batched blocked LU with partial pivoting, column-major, one block / matrix
+// batched blocked LU with partial pivoting, row-major, one workgroup per
+// matrix; the matrices of one launch may have different sizes
 // ---------------------------------------------------------------------------
 constexpr int LU_THREADS = 256;
+constexpr int LU_CB = 64;        // column block of the trailing update
+constexpr int LU_SWC = 64;       // column chunk of the row interchanges
+
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// trailing update A22 -= L21 U12 of one column block, FP32 on MFMA
+// (v_mfma_f32_16x16x4f32: A lane l -> (row l%16, k l/16), B lane l ->
+// (k l/16, col l%16), D lane l reg i -> (row 4(l/16)+i, col l%16))
+template <int NBP>
+__device__ __forceinline__ void trailing_update(float *A, int m, int j0, int nb, int cb, int ncb, const float *pan,
+                                                const float *ut)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r0 = j0 + nb;
+    const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32;
+    for (int t = wv; t < nrt * nct; t += LU_THREADS / 64) {
+        const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
+        floatx4_t acc[2][2];
+        for (int si = 0; si < 2; ++si)
+            for (int sj = 0; sj < 2; ++sj)
+                for (int i = 0; i < 4; ++i) {
+                    int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
+                    acc[si][sj][i] = (row < m && col < cb + ncb) ? A[(long long)row * m + col] : 0.0f;
+                }
+        for (int k0 = 0; k0 < nb; k0 += 4) {
+            const int k = k0 + (lane >> 4);
+            float a[2], b[2];
+            for (int si = 0; si < 2; ++si) {
+                int row = R + 16 * si + (lane & 15);
+                a[si] = (row < m && k < nb) ? -pan[(row - j0) * NBP + k] : 0.0f;
+            }
+            for (int sj = 0; sj < 2; ++sj) b[sj] = ut[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)];
+            for (int si = 0; si < 2; ++si)
+                for (int sj = 0; sj < 2; ++sj)
+                    acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[si], b[sj], acc[si][sj], 0, 0, 0);
+        }
+        for (int si = 0; si < 2; ++si)
+            for (int sj = 0; sj < 2; ++sj)
+                for (int i = 0; i < 4; ++i) {
+                    int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
+                    if (row < m && col < cb + ncb) A[(long long)row * m + col] = acc[si][sj][i];
+                }
+    }
+}
+
+// FP64: register tiles of 4 x 4 per thread on the vector ALUs
+template <int NBP>
+__device__ __forceinline__ void trailing_update(double *A, int m, int j0, int nb, int cb, int ncb, const double *pan,
+                                                const double *ut)
+{
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int r0 = j0 + nb;
+    for (int R = r0; R < m; R += 64) {
+        for (int C = cb; C < cb + ncb; C += 64) {
+            double acc[4][4];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    int row = R + ty + 16 * i, col = C + tx + 16 * j;
+                    acc[i][j] = (row < m && col < cb + ncb) ? A[(long long)row * m + col] : 0.0;
+                }
+            for (int k = 0; k < nb; ++k) {
+                double a[4], b[4];
+                for (int i = 0; i < 4; ++i) {
+                    int row = R + ty + 16 * i;
+                    a[i] = row < m ? pan[(row - j0) * NBP + k] : 0.0;
+                }
+                for (int j = 0; j < 4; ++j) b[j] = ut[k * LU_CB + (C - cb) + tx + 16 * j];
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) acc[i][j] -= a[i] * b[j];
+            }
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    int row = R + ty + 16 * i, col = C + tx + 16 * j;
+                    if (row < m && col < cb + ncb) A[(long long)row * m + col] = acc[i][j];
+                }
+        }
+    }
+}
 
 template <typename T, int NB>
-__global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, int *__restrict__ pivall, int m, int *info)
+__global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, int *__restrict__ pivall, LuBatch B,
+                                                        int *info)
 {
+    constexpr int NBP = NB + 1;
     extern __shared__ unsigned char lds_raw[];
-    T *pan = reinterpret_cast<T *>(lds_raw);           // [NB][m] panel (column c at c*m)
-    T *ut = pan + (size_t)NB * m;                      // [NB][64] U12 tile
-    __shared__ T rv[LU_THREADS];
-    __shared__ int ri[LU_THREADS];
-    __shared__ int ppiv[NB];
-    const int tid = threadIdx.x;
-    T *Am = Aall + (long long)blockIdx.x * m * m;
-    int *piv = pivall + (long long)blockIdx.x * m;
+    const int bid = blockIdx.x;
+    const int m = B.m_of ? B.m_of[bid] : B.uniform_m;
+    T *A = Aall + (B.a_off ? B.a_off[bid] : (long long)bid * m * m);
+    int *piv = pivall + (B.p_off ? B.p_off[bid] : (long long)bid * m);
+    T *pan = reinterpret_cast<T *>(lds_raw);          // [m][NBP] panel rows
+    T *ut = pan + (size_t)m * NBP;                     // [NB][LU_CB] U12 block
+    T *stg = ut + (size_t)NB * LU_CB;                  // [2 NB][LU_SWC] row interchange staging
+    __shared__ T rv[LU_THREADS / 64];
+    __shared__ int ri[LU_THREADS / 64];
+    __shared__ int sw[NB];
+    __shared__ int aff_src[2 * NB], aff_dst[2 * NB];
+    __shared__ int n_aff;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int j0 = 0; j0 < m; j0 += NB) {
-        const int nb = min(NB, m - j0);
-        const int mr = m - j0;                           // rows of the panel
-        for (int e = tid; e < nb * mr; e += LU_THREADS) {
-            int c = e / mr, r = e % mr;
-            pan[c * m + r] = Am[(long long)(j0 + c) * m + j0 + r];
+        const int nb = min(NB, m - j0), mr = m - j0;
+        for (int e = tid; e < mr * nb; e += LU_THREADS) {
+            int r = e / nb, c = e % nb;
+            pan[r * NBP + c] = A[(long long)(j0 + r) * m + j0 + c];
         }
         __syncthreads();
         for (int c = 0; c < nb; ++c) {
-            // pivot search in column c, rows c..mr-1 (first maximum wins)
             T best = T(-1);
             int bi = c;
             for (int r = c + tid; r < mr; r += LU_THREADS) {
-                T v = fabs(pan[c * m + r]);
+                T v = fabs(pan[r * NBP + c]);
                 if (v > best) { best = v; bi = r; }
             }
-            rv[tid] = best;
-            ri[tid] = bi;
+            for (int off = 32; off > 0; off >>= 1) {
+                T ov = __shfl_xor(best, off, 64);
+                int oi = __shfl_xor(bi, off, 64);
+                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+            }
+            if (lane == 0) { rv[wv] = best; ri[wv] = bi; }
             __syncthreads();
-            for (int s = LU_THREADS / 2; s > 0; s >>= 1) {
-                if (tid < s) {
-                    T o = rv[tid + s];
-                    int oi = ri[tid + s];
-                    if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) { rv[tid] = o; ri[tid] = oi; }
+            T bv = rv[0];
+            int p = ri[0];
+            for (int w = 1; w < LU_THREADS / 64; ++w)
+                if (rv[w] > bv || (rv[w] == bv && ri[w] < p)) { bv = rv[w]; p = ri[w]; }
+            if (tid == 0) {
+                piv[j0 + c] = j0 + p;
+                sw[c] = p;
+                if (bv == T(0) && info) atomicAdd(info, 1);
+            }
+            if (p != c && tid < nb) {
+                T t = pan[c * NBP + tid];
+                pan[c * NBP + tid] = pan[p * NBP + tid];
+                pan[p * NBP + tid] = t;
+            }
+            __syncthreads();
+            const T d = pan[c * NBP + c];
+            const T inv = d != T(0) ? T(1) / d : T(0);
+            for (int r = c + 1 + tid; r < mr; r += LU_THREADS) {
+                T l = pan[r * NBP + c] * inv;
+                pan[r * NBP + c] = l;
+                for (int cc = c + 1; cc < nb; ++cc) pan[r * NBP + cc] -= l * pan[c * NBP + cc];
+            }
+            __syncthreads();
+        }
+        // composed row permutation of this panel: affected local rows dst <- src
+        if (tid == 0) {
+            int pos[2 * NB], cont[2 * NB], n = 0;
+            for (int c = 0; c < nb; ++c) {
+                int p = sw[c];
+                if (p == c) continue;
+                int ic = -1, ip = -1;
+                for (int i = 0; i < n; ++i) {
+                    if (pos[i] == c) ic = i;
+                    if (pos[i] == p) ip = i;
+                }
+                if (ic < 0) { pos[n] = c; cont[n] = c; ic = n++; }
+                if (ip < 0) { pos[n] = p; cont[n] = p; ip = n++; }
+                int t = cont[ic];
+                cont[ic] = cont[ip];
+                cont[ip] = t;
+            }
+            int k = 0;
+            for (int i = 0; i < n; ++i)
+                if (pos[i] != cont[i]) { aff_dst[k] = pos[i]; aff_src[k] = cont[i]; ++k; }
+            n_aff = k;
+        }
+        __syncthreads();
+        // apply the permutation to whole rows (panel columns are rewritten below)
+        const int na = n_aff;
+        if (na > 0) {
+            for (int c0 = 0; c0 < m; c0 += LU_SWC) {
+                const int nc = min(LU_SWC, m - c0);
+                for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
+                    int i = e / LU_SWC, j = e % LU_SWC;
+                    if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * m + c0 + j];
+                }
+                __syncthreads();
+                for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
+                    int i = e / LU_SWC, j = e % LU_SWC;
+                    if (j < nc) A[(long long)(j0 + aff_dst[i]) * m + c0 + j] = stg[i * LU_SWC + j];
                 }
                 __syncthreads();
             }
-            const int p = ri[0];
-            if (tid == 0) {
-                piv[j0 + c] = j0 + p;
-                ppiv[c] = j0 + p;
-                if (rv[0] == T(0) && info) atomicAdd(info, 1);
-            }
-            // swap rows c and p inside the panel
-            if (p != c)
-                for (int cc = tid; cc < nb; cc += LU_THREADS) {
-                    T t = pan[cc * m + c];
-                    pan[cc * m + c] = pan[cc * m + p];
-                    pan[cc * m + p] = t;
-                }
-            __syncthreads();
-            const T d = pan[c * m + c];
-            const T inv = d != T(0) ? T(1) / d : T(0);
-            for (int r = c + 1 + tid; r < mr; r += LU_THREADS) pan[c * m + r] *= inv;
-            __syncthreads();
-            // update the remaining panel columns
-            for (int e = tid; e < (nb - c - 1) * (mr - c - 1); e += LU_THREADS) {
-                int cc = c + 1 + e / (mr - c - 1), r = c + 1 + e % (mr - c - 1);
-                pan[cc * m + r] -= pan[c * m + r] * pan[cc * m + c];
-            }
-            __syncthreads();
         }
-        // write the panel back
-        for (int e = tid; e < nb * mr; e += LU_THREADS) {
-            int c = e / mr, r = e % mr;
-            Am[(long long)(j0 + c) * m + j0 + r] = pan[c * m + r];
-        }
-        // row interchanges of this panel applied to the other columns
-        for (int col = tid; col < m; col += LU_THREADS) {
-            if (col >= j0 && col < j0 + nb) continue;
-            T *cp = Am + (long long)col * m;
-            for (int c = 0; c < nb; ++c) {
-                int p = ppiv[c];
-                if (p != j0 + c) {
-                    T t = cp[j0 + c];
-                    cp[j0 + c] = cp[p];
-                    cp[p] = t;
-                }
-            }
+        // write the factored panel back
+        for (int e = tid; e < mr * nb; e += LU_THREADS) {
+            int r = e / nb, c = e % nb;
+            A[(long long)(j0 + r) * m + j0 + c] = pan[r * NBP + c];
         }
         __syncthreads();
-        // U12 = L11^{-1} A12 and A22 -= L21 U12, 64 columns at a time
-        const int r0 = j0 + nb;
-        for (int cb = r0; cb < m; cb += 64) {
-            const int ncb = min(64, m - cb);
+        // U12 = L11^{-1} A12 and the trailing update, one column block at a time
+        for (int cb = j0 + nb; cb < m; cb += LU_CB) {
+            const int ncb = min(LU_CB, m - cb);
+            for (int e = tid; e < NB * LU_CB; e += LU_THREADS) ut[e] = T(0);
+            __syncthreads();
             if (tid < ncb) {
-                T *cp = Am + (long long)(cb + tid) * m;
+                const int col = cb + tid;
                 T u[NB];
-                for (int c = 0; c < nb; ++c) u[c] = cp[j0 + c];
-                for (int c = 0; c < nb; ++c)
-                    for (int k = 0; k < c; ++k) u[c] -= pan[k * m + c] * u[k];
-                for (int c = 0; c < nb; ++c) {
-                    cp[j0 + c] = u[c];
-                    ut[c * 64 + tid] = u[c];
+                for (int c = 0; c < NB; ++c) u[c] = c < nb ? A[(long long)(j0 + c) * m + col] : T(0);
+                for (int c = 1; c < NB; ++c) {
+                    if (c >= nb) break;
+                    T s = u[c];
+                    for (int k = 0; k < c; ++k) s -= pan[c * NBP + k] * u[k];
+                    u[c] = s;
                 }
+                for (int c = 0; c < NB; ++c)
+                    if (c < nb) {
+                        A[(long long)(j0 + c) * m + col] = u[c];
+                        ut[c * LU_CB + tid] = u[c];
+                    }
             }
             __syncthreads();
-            for (int r = r0 + tid; r < m; r += LU_THREADS) {
-                T l[NB];
-                for (int c = 0; c < nb; ++c) l[c] = pan[c * m + (r - j0)];
-                for (int k = 0; k < ncb; ++k) {
-                    T *ap = Am + (long long)(cb + k) * m + r;
-                    T s = *ap;
-                    for (int c = 0; c < nb; ++c) s -= l[c] * ut[c * 64 + k];
-                    *ap = s;
-                }
-            }
+            trailing_update<NBP>(A, m, j0, nb, cb, ncb, pan, ut);
             __syncthreads();
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// patch solves
+// triangular solves with a row-major LU (unit lower L, upper U), rhs b in LDS
 // ---------------------------------------------------------------------------
 constexpr int SV_THREADS = 256;
 
-// forward / backward substitution on rhs b (LDS, length m) with LU (col-major)
 template <typename T>
-__device__ void lu_substitute(const T *__restrict__ LU, int m, T *b)
+__device__ void lu_substitute(const T *__restrict__ LU, int m, T *b, T *dblk)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int g = tid >> 4, l16 = tid & 15;
     // forward: unit lower
     for (int kb = 0; kb < m; kb += 64) {
         const int nbk = min(64, m - kb);
+        for (int e = tid; e < nbk * 64; e += SV_THREADS) {
+            int i = e / 64, j = e % 64;
+            if (j < nbk) dblk[i * 65 + j] = LU[(long long)(kb + i) * m + kb + j];
+        }
+        __syncthreads();
         if (wv == 0) {
             T y = lane < nbk ? b[kb + lane] : T(0);
             for (int c = 0; c < nbk; ++c) {
                 T yc = __shfl(y, c, 64);
-                if (lane > c && lane < nbk) y -= LU[(long long)(kb + c) * m + kb + lane] * yc;
+                if (lane > c && lane < nbk) y -= dblk[lane * 65 + c] * yc;
             }
             if (lane < nbk) b[kb + lane] = y;
         }
         __syncthreads();
-        for (int r = kb + nbk + tid; r < m; r += SV_THREADS) {
-            T s = b[r];
-            for (int c = 0; c < nbk; ++c) s -= LU[(long long)(kb + c) * m + r] * b[kb + c];
-            b[r] = s;
+        for (int r = kb + nbk + g; r < m; r += SV_THREADS / 16) {
+            T s = 0;
+            for (int c = l16; c < nbk; c += 16) s += LU[(long long)r * m + kb + c] * b[kb + c];
+            for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+            if (l16 == 0) b[r] -= s;
         }
         __syncthreads();
     }
@@ -719,22 +831,26 @@ __device__ void lu_substitute(const T *__restrict__ LU, int m, T *b)
     const int nblk = (m + 63) / 64;
     for (int bk = nblk - 1; bk >= 0; --bk) {
         const int kb = bk * 64, nbk = min(64, m - kb);
+        for (int e = tid; e < nbk * 64; e += SV_THREADS) {
+            int i = e / 64, j = e % 64;
+            if (j < nbk) dblk[i * 65 + j] = LU[(long long)(kb + i) * m + kb + j];
+        }
+        __syncthreads();
         if (wv == 0) {
             T x = lane < nbk ? b[kb + lane] : T(0);
             for (int c = nbk - 1; c >= 0; --c) {
-                T xc = __shfl(x, c, 64);
-                T dcc = LU[(long long)(kb + c) * m + kb + c];
-                xc = xc / dcc;
+                T xc = __shfl(x, c, 64) / dblk[c * 65 + c];
                 if (lane == c) x = xc;
-                if (lane < c) x -= LU[(long long)(kb + c) * m + kb + lane] * xc;
+                if (lane < c) x -= dblk[lane * 65 + c] * xc;
             }
             if (lane < nbk) b[kb + lane] = x;
         }
         __syncthreads();
-        for (int r = tid; r < kb; r += SV_THREADS) {
-            T s = b[r];
-            for (int c = 0; c < nbk; ++c) s -= LU[(long long)(kb + c) * m + r] * b[kb + c];
-            b[r] = s;
+        for (int r = g; r < kb; r += SV_THREADS / 16) {
+            T s = 0;
+            for (int c = l16; c < nbk; c += 16) s += LU[(long long)r * m + kb + c] * b[kb + c];
+            for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+            if (l16 == 0) b[r] -= s;
         }
         __syncthreads();
     }
@@ -749,6 +865,7 @@ __global__ void __launch_bounds__(SV_THREADS) solve_kernel(SolveArgs<T, TP> A)
     TP *b = reinterpret_cast<TP *>(lds_raw);
     const int cell = blockIdx.x, tid = threadIdx.x;
     const int nt = A.nt, nv = nt * DIM * NL, m = nv + nt * NPM;
+    TP *dblk = b + ((m + 1) & ~1);
     const int c0 = cell % A.n0, c1 = (cell / A.n0) % A.n1, c2 = DIM == 3 ? cell / (A.n0 * A.n1) : 0;
     const long long N0 = (long long)(R + 1) * A.n0 + 1, N1g = (long long)(R + 1) * A.n1 + 1;
     auto gnode = [&](int l) -> long long {
@@ -779,7 +896,7 @@ __global__ void __launch_bounds__(SV_THREADS) solve_kernel(SolveArgs<T, TP> A)
             }
         }
     __syncthreads();
-    lu_substitute<TP>(A.patches + (long long)cell * m * m, m, b);
+    lu_substitute<TP>(A.patches + (long long)cell * m * m, m, b, dblk);
     // velocity -> cell-local buffer [cell][a][c][l]; pressure += omega * x
     T *Ec = A.E + (long long)cell * nv;
     for (int row = tid; row < m; row += SV_THREADS) {
@@ -799,6 +916,7 @@ __global__ void __launch_bounds__(SV_THREADS) dense_solve_kernel(const T *LU, co
 {
     extern __shared__ unsigned char lds_raw[];
     T *b = reinterpret_cast<T *>(lds_raw);
+    T *dblk = b + ((m + 1) & ~1);
     const int tid = threadIdx.x;
     for (int r = tid; r < m; r += SV_THREADS) b[r] = r < nout ? rhs[r] : T(0);
     __syncthreads();
@@ -812,7 +930,7 @@ __global__ void __launch_bounds__(SV_THREADS) dense_solve_kernel(const T *LU, co
             }
         }
     __syncthreads();
-    lu_substitute<T>(LU, m, b);
+    lu_substitute<T>(LU, m, b, dblk);
     for (int r = tid; r < nout; r += SV_THREADS) x[r] = b[r];
 }
 
@@ -836,7 +954,7 @@ __global__ void coarse_matrix_kernel(const double *Y, int n, int nb, int nt, lon
             long long q = col - pbase;
             if (q >= a * Np1 && q < (a + 1) * Np1 && ((q - a * Np1) % npm) == 0) v = 1.0;
         }
-        A[e] = v;
+        A[(long long)row * m + col] = v;
     }
     (void)nt;
     (void)ncell;
@@ -863,7 +981,10 @@ __global__ void midpoint_kernel(const T *state, long long Nv1, int nt, const dou
     (void)phim_unused;
 }
 
-template <int NB, typename T> size_t lu_lds_bytes(int m) { return ((size_t)NB * m + NB * 64) * sizeof(T); }
+template <int NB, typename T> size_t lu_lds_bytes(int m)
+{
+    return ((size_t)m * (NB + 1) + (size_t)NB * LU_CB + (size_t)2 * NB * LU_SWC) * sizeof(T);
+}
 
 } // namespace
 
@@ -905,18 +1026,22 @@ hipError_t launch_patch(int dim, int r, const PatchArgs<TE, TP> &a, int ncell, h
     return hipErrorInvalidValue;
 }
 
-template <typename T> hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds, hipStream_t s)
+template <typename T>
+hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds, hipStream_t s, const LuBatch *vb)
 {
+    LuBatch B{};
+    if (vb) B = *vb;
+    else B.uniform_m = m;
 #define LUC(NBV)                                                                                                       \
     if (lu_lds_bytes<NBV, T>(m) <= max_lds) {                                                                          \
         size_t bytes = lu_lds_bytes<NBV, T>(m);                                                                        \
         hipError_t e = hipFuncSetAttribute((const void *)lu_kernel<T, NBV>,                                            \
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                    \
         if (e != hipSuccess) return e;                                                                                 \
-        hipLaunchKernelGGL((lu_kernel<T, NBV>), dim3(batch), dim3(LU_THREADS), bytes, s, A, piv, m, info);            \
+        hipLaunchKernelGGL((lu_kernel<T, NBV>), dim3(batch), dim3(LU_THREADS), bytes, s, A, piv, B, info);            \
         return hipGetLastError();                                                                                      \
     }
-    LUC(32) LUC(16) LUC(8) LUC(4) LUC(2) LUC(1)
+    LUC(32) LUC(16) LUC(8) LUC(4)
 #undef LUC
     return hipErrorInvalidConfiguration;
 }
@@ -924,7 +1049,7 @@ template <typename T> hipError_t launch_lu(T *A, int *piv, int m, int batch, int
 template <typename T, typename TP>
 hipError_t launch_solve(int dim, int r, const SolveArgs<T, TP> &a, int ncell, int m, hipStream_t s)
 {
-    size_t bytes = (size_t)m * sizeof(TP);
+    size_t bytes = ((size_t)((m + 1) & ~1) + 64 * 65) * sizeof(TP);
 #define SC(D, RR)                                                                                                      \
     if (dim == D && r == RR) {                                                                                         \
         hipError_t e = hipFuncSetAttribute((const void *)solve_kernel<D, RR, T, TP>,                                   \
@@ -941,7 +1066,7 @@ hipError_t launch_solve(int dim, int r, const SolveArgs<T, TP> &a, int ncell, in
 hipError_t launch_dense_solve(const double *LU, const int *piv, int m, const double *rhs, double *x, int nout,
                               hipStream_t s)
 {
-    size_t bytes = (size_t)m * sizeof(double);
+    size_t bytes = ((size_t)((m + 1) & ~1) + 64 * 65) * sizeof(double);
     hipError_t e = hipFuncSetAttribute((const void *)dense_solve_kernel<double>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
@@ -978,8 +1103,8 @@ template hipError_t launch_elem<float>(int, int, int, const ElemArgs<float> &, i
 template hipError_t launch_patch<double, double>(int, int, const PatchArgs<double, double> &, int, hipStream_t);
 template hipError_t launch_patch<float, float>(int, int, const PatchArgs<float, float> &, int, hipStream_t);
 template hipError_t launch_patch<double, float>(int, int, const PatchArgs<double, float> &, int, hipStream_t);
-template hipError_t launch_lu<double>(double *, int *, int, int, int *, size_t, hipStream_t);
-template hipError_t launch_lu<float>(float *, int *, int, int, int *, size_t, hipStream_t);
+template hipError_t launch_lu<double>(double *, int *, int, int, int *, size_t, hipStream_t, const LuBatch *);
+template hipError_t launch_lu<float>(float *, int *, int, int, int *, size_t, hipStream_t, const LuBatch *);
 template hipError_t launch_solve<double, double>(int, int, const SolveArgs<double, double> &, int, int, hipStream_t);
 template hipError_t launch_solve<float, float>(int, int, const SolveArgs<float, float> &, int, int, hipStream_t);
 template hipError_t launch_solve<double, float>(int, int, const SolveArgs<double, float> &, int, int, hipStream_t);

@@ -40,13 +40,23 @@ class Options(ctypes.Structure):
                 ("ls_alpha_min", ctypes.c_double), ("ls_window", ctypes.c_int), ("ls_max_backtracks", ctypes.c_int),
                 ("rb_theta_N", ctypes.c_double), ("rb_theta_L", ctypes.c_double), ("rb_kappa_abs", ctypes.c_double),
                 ("rb_stag_theta", ctypes.c_double), ("rb_stag_s", ctypes.c_int),
-                ("fgmres_maxit", ctypes.c_int)]
+                ("fgmres_maxit", ctypes.c_int), ("vanka_weighting", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("newton_its", ctypes.c_int), ("fgmres_its_total", ctypes.c_int),
                 ("fgmres_its", ctypes.c_int * 64), ("rebuilds", ctypes.c_int), ("backtracks", ctypes.c_int),
                 ("res0_M", ctypes.c_double), ("res_M", ctypes.c_double), ("wall_s", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("prob", Problem), ("arrival_s", ctypes.c_double), ("v_prev", ctypes.c_void_p),
+                ("rhs", ctypes.c_void_p), ("u_init", ctypes.c_void_p), ("u_out", ctypes.c_void_p)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("start_s", ctypes.c_double), ("end_s", ctypes.c_double), ("latency_s", ctypes.c_double),
+                ("rc", ctypes.c_int), ("footprint", ctypes.c_size_t), ("stats", Stats)]
 
 
 _lib = None
@@ -84,6 +94,8 @@ _SIGS = {
     "stmg_fgmres": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "stmg_newton_gmres_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_serve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
     "stmg_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "stmg_timing_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "stmg_timing_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -116,6 +128,65 @@ def default_options(**overrides) -> Options:
     return o
 
 
+def make_problem(dim, n, r, k, nu, tau, vertices=None, dirichlet_faces=None, gamma1=10.0, gamma2=10.0):
+    """Problem structure; returns (struct, keep-alive vertex array)."""
+    import numpy as np
+    n = tuple(int(v) for v in (n if hasattr(n, "__len__") else (n,) * dim))
+    p = Problem()
+    p.dim = dim
+    for a in range(3):
+        p.n_cells[a] = n[a] if a < len(n) else 1
+    vert = None
+    if vertices is not None:
+        vert = np.ascontiguousarray(vertices, dtype=np.float64)
+        p.vertices = vert.ctypes.data
+    p.r, p.k, p.nu, p.tau = r, k, nu, tau
+    p.dirichlet_faces = (1 << (2 * dim)) - 1 if dirichlet_faces is None else dirichlet_faces
+    p.gamma1, p.gamma2 = gamma1, gamma2
+    return p, vert
+
+
+def footprint_bytes(problem: Problem, options: Options | None = None) -> int:
+    o = options if options is not None else default_options()
+    return int(lib().stmg_footprint_bytes(ctypes.byref(problem), ctypes.byref(o)))
+
+
+def serve(requests, options: Options | None = None, slots: int = 4, hbm_budget: int = 0):
+    """Run a request stream through the library's serving loop.
+
+    requests: list of dicts with keys dim, n, r, k, nu, tau, arrival_s and
+    optional vertices, dirichlet_faces, v_prev (numpy, one time node),
+    rhs (numpy, slab).  Returns (solutions, results, wall_s)."""
+    import numpy as np
+    o = options if options is not None else default_options()
+    nreq = len(requests)
+    arr = (Request * nreq)()
+    keep, outs = [], []
+    for i, q in enumerate(requests):
+        p, vert = make_problem(q["dim"], q["n"], q["r"], q["k"], q["nu"], q["tau"], q.get("vertices"),
+                               q.get("dirichlet_faces"))
+        keep.append(vert)
+        arr[i].prob = p
+        arr[i].arrival_s = float(q.get("arrival_s", 0.0))
+        for key in ("v_prev", "rhs", "u_init"):
+            v = q.get(key)
+            if v is not None:
+                v = np.ascontiguousarray(v, dtype=np.float64)
+                keep.append(v)
+                setattr(arr[i], key, v.ctypes.data)
+        from . import inputs as _I
+        N = _I.sizes(q["dim"], q["n"], q["r"], q["k"])[2]
+        out = np.zeros(N)
+        outs.append(out)
+        arr[i].u_out = out.ctypes.data
+    res = (RequestResult * nreq)()
+    wall = ctypes.c_double()
+    rc = lib().stmg_serve(arr, nreq, ctypes.byref(o), slots, hbm_budget, res, ctypes.byref(wall))
+    if rc < 0:
+        raise StmgError(f"stmg_serve failed ({rc})")
+    return outs, list(res), wall.value
+
+
 def _stream_ptr():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -129,19 +200,7 @@ class Context:
 
     def __init__(self, dim, n, r, k, nu, tau, vertices=None, dirichlet_faces=None, gamma1=10.0, gamma2=10.0,
                  options: Options | None = None, **opt_overrides):
-        n = tuple(int(v) for v in (n if hasattr(n, "__len__") else (n,) * dim))
-        p = Problem()
-        p.dim = dim
-        for a in range(3):
-            p.n_cells[a] = n[a] if a < len(n) else 1
-        self._vert = None
-        if vertices is not None:
-            import numpy as np
-            self._vert = np.ascontiguousarray(vertices, dtype=np.float64)
-            p.vertices = self._vert.ctypes.data
-        p.r, p.k, p.nu, p.tau = r, k, nu, tau
-        p.dirichlet_faces = (1 << (2 * dim)) - 1 if dirichlet_faces is None else dirichlet_faces
-        p.gamma1, p.gamma2 = gamma1, gamma2
+        p, self._vert = make_problem(dim, n, r, k, nu, tau, vertices, dirichlet_faces, gamma1, gamma2)
         self.problem = p
         self.options = options if options is not None else default_options(**opt_overrides)
         h = ctypes.c_void_p()

@@ -184,3 +184,86 @@ def test_newton_matches_oracle(which, stmg):
     assert st32.res_M <= max(1e-12, 1e-8 * st32.res0_M)
     assert abs(st32.newton_its - st_ref.newton_its) <= 1
     assert rel(u32, U_ref) < 1e-6
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[3]], ids=[IDS[1], IDS[3]])
+def test_plain_sum_vanka_sweep_and_vcycle(case, stmg):
+    """Literal plain sum of the patch corrections with a scalar omega (option)."""
+    name, d, n, r, k, nu, tau, pert, mask, maxl = case
+    vert = I.perturbed_vertices(d, n, 0.2, 60 + r) if pert else None
+    prob = oracle.Problem(dim=d, n=n, r=r, k=k, nu=nu, tau=tau, vertices=vert, dirichlet_mask=mask)
+    H = S.Hierarchy(prob, max_levels=maxl, weighting=0)
+    ctx = stmg.Context(d, n, r, k, nu, tau, vertices=vert, dirichlet_faces=prob.dirichlet_mask,
+                       prec_mg=stmg.STMG_F64, max_levels=maxl, vanka_weighting=0)
+    s0 = H.levels[0].slab
+    U = I.uniform(s0.N, 33)
+    H.set_state(U)
+    H.rebuild_smoother()
+    ctx.smoother_rebuild(dev(U))
+    r_ = I.uniform(s0.N, 34)
+    d0 = I.uniform(s0.N, 35) * 0.1
+    d_ = dev(d0)
+    ctx.vanka_smooth(0, dev(r_), d_)
+    assert rel(d_.cpu().numpy(), H.smooth(0, r_, d0)) < 1e-9
+    assert rel(ctx.vcycle(dev(r_)).cpu().numpy(), H.vcycle(r_)) < 1e-9
+
+
+def test_plain_sum_newton_matches_oracle(stmg):
+    prob, slab, rhs, vprev, maxl = _newton_case("3d_4cube_r1k1")
+    H = S.Hierarchy(prob, max_levels=maxl, weighting=0)
+    U_ref, st_ref = S.newton_solve(slab, H, np.zeros(slab.N), rhs, vprev)
+    ctx = stmg.Context(prob.dim, prob.n, prob.r, prob.k, prob.nu, prob.tau, prec_mg=stmg.STMG_F64,
+                       max_levels=maxl, vanka_weighting=0)
+    ctx.set_slab_data(None, dev(vprev))
+    u, st, rc = ctx.newton_solve(torch.zeros(slab.N, dtype=torch.float64, device="cuda"))
+    assert rc == 0 and st.newton_its == st_ref.newton_its
+    assert list(st.fgmres_its[: st.newton_its]) == st_ref.fgmres_its
+    assert rel(u.cpu().numpy(), U_ref) < 1e-7
+
+
+def _serving_mix(seed=0):
+    rng = np.random.default_rng(seed)
+    specs = [(2, (4, 4), 1, 1, 1.0), (2, (8, 8), 2, 1, 1e-2), (3, (2, 2, 2), 1, 0, 1.0), (3, (4, 4, 4), 1, 1, 1e-2),
+             (2, (4, 4), 3, 2, 1e-3), (3, (2, 2, 2), 2, 2, 1e-2), (2, (8, 8), 1, 2, 1e-2), (3, (4, 4, 4), 2, 0, 1.0)]
+    reqs = []
+    t = 0.0
+    for i, (d, n, r, k, nu) in enumerate(specs):
+        t += rng.exponential(0.01)
+        reqs.append(dict(dim=d, n=n, r=r, k=k, nu=nu, tau=0.1, arrival_s=t,
+                         v_prev=I.smooth_velocity(d, n, r, 100 + i)))
+    return reqs
+
+
+def test_serving_results_identical_alone_and_in_mix(stmg):
+    """Continuous batching: requests admitted while others run; every result is
+    bitwise identical to the same request served alone, and to a direct solve."""
+    reqs = _serving_mix()
+    opt = stmg.default_options()
+    mixed, res, wall = stmg.serve(reqs, opt, slots=4, hbm_budget=0)
+    assert all(r.rc == 0 for r in res)
+    # overlap: some request started before another finished
+    spans = sorted((r.start_s, r.end_s) for r in res)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    for i, q in enumerate(reqs):
+        q1 = dict(q, arrival_s=0.0)
+        alone, res1, _ = stmg.serve([q1], opt, slots=1)
+        assert res1[0].rc == 0
+        assert np.array_equal(alone[0], mixed[i])
+        assert res1[0].stats.newton_its == res[i].stats.newton_its
+    # a budget smaller than two requests serializes admission but keeps results
+    big = max(r.footprint for r in res)
+    ser, res2, _ = stmg.serve(reqs, opt, slots=4, hbm_budget=big + 1)
+    for i in range(len(reqs)):
+        assert np.array_equal(ser[i], mixed[i])
+    # direct solve through a context equals the served result
+    q = reqs[3]
+    ctx = stmg.Context(q["dim"], q["n"], q["r"], q["k"], q["nu"], q["tau"])
+    ctx.set_slab_data(None, dev(q["v_prev"]))
+    u, st, rc = ctx.newton_solve(torch.zeros(ctx.N, dtype=torch.float64, device="cuda"))
+    assert rc == 0 and np.array_equal(u.cpu().numpy(), mixed[3])
+
+
+def test_serving_rejects_oversized_request(stmg):
+    reqs = _serving_mix()[:2]
+    with pytest.raises(stmg.StmgError):
+        stmg.serve(reqs, stmg.default_options(), slots=2, hbm_budget=1 << 20)
