@@ -361,13 +361,19 @@ static int max_points(const ospace *s)
     return nv + 2 * d * nf;
 }
 
-/* area of face f of the cell from its points */
+/* Penalty length h_{Gamma_D} of face f (Nitsche penalty B^r_gamma, eq. def-b-gam):
+ * the paper leaves it undefined.  Reading: the cell's normal extent |K|/|F|
+ * divided by the square of the velocity degree r+1, the usual interior-penalty
+ * scaling.  Without the degree factor the viscous Nitsche form with
+ * gamma_1 = 10 is not coercive for Q4 velocities (its threshold is about
+ * (r+1)^2 on Cartesian cells). */
 static void face_h(const ospace *s, const qpoint *pts, int np, double vol, double hf[6])
 {
     double area[6] = {0, 0, 0, 0, 0, 0};
+    const double p2 = (double)(s->r + 1) * (double)(s->r + 1);
     for (int p = 0; p < np; ++p)
         if (pts[p].face >= 0) area[pts[p].face] += pts[p].wt;
-    for (int f = 0; f < 2 * s->dim; ++f) hf[f] = area[f] > 0 ? vol / area[f] : 0.0;
+    for (int f = 0; f < 2 * s->dim; ++f) hf[f] = area[f] > 0 ? vol / area[f] / p2 : 0.0;
 }
 
 static double ominus(double y) { return 0.5 * (fabs(y) - y); }

@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
 
     const bool bnd = (c0 == 0) || (c0 == A.n0 - 1) || (c1 == 0) || (c1 == A.n1 - 1) ||
                      (DIM == 3 && ((c2 == 0) || (c2 == A.n2 - 1)));
-    T *hF = geo + 24;   // h_F = |K| / |F| per face id
+    T *hF = geo + 24;   // |K| / |F| per face id
 
     // ---- h_F of the boundary faces (reading: |K|/|F| by the cell's quadrature) ----
     if (MODE != Mode::Mass && bnd) {
@@ -610,7 +610,8 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
                             const T *p0 = ax == 0 ? Lrow : Lp, *p1 = ax == 1 ? Lrow : Lp, *p2 = ax == 2 ? Lrow : Lp;
                             FACE_SWEEP(1, xpf + a * NPF, NPF, FQ + FP * NQF, NQF, p0, p1, p2, RP1, RP1, RP12);
                         }
-                        const T hf = hF[fid];
+                        // penalty length: |K|/|F| over the squared velocity degree
+                        const T hf = hF[fid] / T((R + 1) * (R + 1));
                         for (int q = tid; q < NQF; q += NTH) {
                             const int tq[2] = {q % NQ, DIM == 3 ? q / NQ : 0};
                             T xi[3] = {0, 0, 0}, Jit[3][3], wt = 1;

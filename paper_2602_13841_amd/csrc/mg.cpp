@@ -588,8 +588,10 @@ int newton_solve(stmg_ctx *ctx, double *U, stmg_stats *stats)
         }
         ++k;
         if (verbose()) {
-            std::fprintf(stderr, "[stmg] newton %d: |R|_M %.3e (rho %.3f) fgmres %d alpha %.3g rebuilds %d  %.2f s\n", k,
-                         nrm, rho_prev, fo.its, alpha, st.rebuilds,
+            std::fprintf(stderr,
+                         "[stmg] newton %d: |R|_M %.3e (rho %.3f) fgmres %d (eta %.2e reached %.2e) alpha %.3g "
+                         "rebuilds %d  %.2f s\n",
+                         k, nrm, rho_prev, fo.its, eta, fo.hist.back() / fo.hist.front(), alpha, st.rebuilds,
                          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
             std::fflush(stderr);
         }

@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(EL_THREADS) elem_kernel(ElemArgs<T> A)
     __syncthreads();
     const T hcar[3] = {T(1) / A.n0, T(1) / A.n1, DIM == 3 ? T(1) / A.n2 : T(1)};
     T *hF = geo + 24;
-    // h_F = |K| / |F| (mapped cells by quadrature, fixed-order sums)
+    // |K| / |F| (mapped cells by quadrature, fixed-order sums)
     if (nfaces > 0) {
         if (!mapped) {
             if (tid < 2 * DIM) hF[tid] = hcar[tid / 2];
@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(EL_THREADS) elem_kernel(ElemArgs<T> A)
                     P[P_VN] = vn;
                     P[P_OM] = om_(vn);
                     P[P_DOM] = dom_(vn);
-                    T h = hF[fid];
+                    T h = hF[fid] / T((R + 1) * (R + 1)); // penalty length: over the squared velocity degree
                     P[P_PEN1] = A.nu * A.g1 / h;
                     P[P_PEN2] = A.g2 / h;
                 }

@@ -45,6 +45,8 @@ CASES = [
     ("2d_r3k1_neumann", 2, (4, 2), 3, 1, 0.1, 0.1, True, 0b0111, 0),
     ("3d_r1k1_4cube", 3, (4, 4, 4), 1, 1, 0.01, 0.125, False, None, 0),
     ("3d_r2k2_2cube_pert", 3, (2, 2, 2), 2, 2, 0.02, 0.05, True, None, 0),
+    ("3d_r3k1_2cube_pert", 3, (2, 2, 2), 3, 1, 0.01, 0.05, True, None, 0),
+    ("3d_r3k1_4cube", 3, (4, 4, 4), 3, 1, 0.01, 0.05, False, None, 0),
 ]
 IDS = [c[0] for c in CASES]
 

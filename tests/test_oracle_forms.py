@@ -135,7 +135,8 @@ def exact_weak_form(prob, vc, pc, zc, qc):
             vz = np.sum(v * z, axis=1)
             integrand = vn * vz
             if (prob.dirichlet_mask >> f) & 1:
-                h = 1.0 / prob.n[ax]
+                # penalty length: normal cell extent over the squared velocity degree
+                h = 1.0 / prob.n[ax] / (prob.r + 1) ** 2
                 ominus = 0.5 * (np.abs(vn) - vn)
                 gvn = np.einsum("pca,a->pc", gv, n)
                 gzn = np.einsum("pca,a->pc", gz, n)
@@ -370,3 +371,25 @@ def test_reduced_time_quadrature_error_rate(k):
     tt = T.time_tables(0, 0.1)
     v0 = field(tt.t[0])
     assert abs(tt.w[0] * conv(v0) - 0.1 * conv(v0)) < 1e-14
+
+
+@pytest.mark.parametrize("d,n,pert", [(2, (3, 3), False), (2, (3, 3), True), (3, (2, 2, 2), False), (3, (2, 2, 2), True)])
+def test_nitsche_viscous_form_coercive(d, n, pert):
+    """With gamma_1 = gamma_2 = 10 the velocity block of the Stokes part
+    (viscous form plus Nitsche terms, zero state) is positive definite for
+    r = 1, 2, 3 on Cartesian and perturbed cells: the penalty length carries
+    the squared velocity degree.  Without it (equivalently gamma_1 below
+    about (r+1)^2 on an unscaled length) the r = 3 form has negative
+    eigenvalues, which this pins by scaling gamma_1 down by (r+1)^2."""
+    from paper_2602_13841_amd import inputs as I
+    for r in (1, 2, 3):
+        vert = I.perturbed_vertices(d, n, 0.2, 7) if pert else None
+        mins = []
+        for g in (10.0, 10.0 / (r + 1) ** 2):
+            prob = Problem(dim=d, n=n, r=r, k=0, nu=1.0, tau=1.0, gamma1=g, gamma2=g, vertices=vert)
+            sp_ = Slab(prob).space
+            A = sp_.spatial_jacobian(np.zeros(sp_.Nv)).toarray()[: sp_.Nv, : sp_.Nv]
+            mins.append(np.linalg.eigvalsh(0.5 * (A + A.T))[0])
+        assert mins[0] > 0, (r, mins)
+        if r == 3:
+            assert mins[1] < 0, (r, mins)
