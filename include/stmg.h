@@ -101,6 +101,13 @@ typedef struct {
      * (partition of unity, omega default 1.0; the default); 0 = the plain
      * sum of the patch corrections with a scalar omega (default 1.4/2^d). */
     int vanka_weighting;
+    /* Patch solves of the midpoint surrogate (eq. DefTildeHn): 1 = split the
+     * time coupling by the eigen-decomposition of W^{-1} K, one spatial
+     * (complex for a conjugate eigenvalue pair) factorization per distinct
+     * eigen-system, the same result as the full space-time patch up to
+     * rounding at (k+1)x less factor memory (the default); 0 = factor the
+     * full (k+1)-node patch. */
+    int vanka_time_decoupled;
 } stmg_options;
 
 typedef struct {

@@ -72,6 +72,7 @@ void stmg_default_options(stmg_options *o)
     o->rb_stag_s = 3;
     o->fgmres_maxit = 50;
     o->vanka_weighting = 1;
+    o->vanka_time_decoupled = 1;
 }
 
 int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_ctx **out)
@@ -168,7 +169,12 @@ size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt)
         total += (size_t)nn * (size_t)std::pow(q.r + 3, d) * 16 * 3;       // transfer CSRs (upper bound)
         if (l + 1 < specs.size()) {
             total += (size_t)Nv1 * w + (size_t)ncell * (d * d * nl * nl + nl * nl + d * nl * npm) * w;
-            total += (size_t)ncell * m * m * w + (size_t)ncell * m * 4;       // patch factors
+            if (o.vanka_time_decoupled) {
+                const long long ms = d * nl + npm;                          // nt real-plane equivalents
+                total += (size_t)ncell * nt * ms * ms * w + (size_t)ncell * nt * ms * 8;
+            } else {
+                total += (size_t)ncell * m * m * w + (size_t)ncell * m * 4;   // patch factors
+            }
         } else {
             total += (size_t)N * N * 8 * 2 + (size_t)(N + nt) * (N + nt) * 8 + (size_t)N * ncell * nt * d * nl * 8;
         }

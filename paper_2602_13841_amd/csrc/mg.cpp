@@ -93,6 +93,7 @@ void mg_build(stmg_ctx *ctx)
     Level &L0 = *ctx->levels[0];
     mg->prec = o.prec_mg == STMG_F64 ? STMG_F64 : STMG_F32;
     mg->weighting = o.vanka_weighting ? 1 : 0;
+    mg->td = o.vanka_time_decoupled != 0;
     mg->omega = o.vanka_omega > 0 ? o.vanka_omega : (mg->weighting ? 1.0 : 1.4 / double(1 << L0.dim));
     mg->nu1 = std::max(0, o.nu1);
     mg->nu2 = std::max(0, o.nu2);
@@ -224,6 +225,55 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
         STMG_HIP(launch_elem<T>(L.dim, L.r, L.nq, ea, (int)L.ncell, s));
     }
     M.m = L.nt * (L.dim * L.nl + L.npm);
+    M.ms = L.dim * L.nl + L.npm;
+    if (ctx->mg->td) {
+        // one spatial matrix per eigen-system of the time coupling
+        M.tdg = time_diagonalization(L.tc);
+        const long long ms = M.ms, mat = ms * ms;
+        long long off = 0;
+        for (int sy = 0; sy < M.tdg.nsys; ++sy) {
+            M.sys_off[sy] = off;
+            M.piv_off[sy] = (long long)sy * L.ncell * ms;
+            off += (long long)L.ncell * (M.tdg.cplx[sy] ? 2 : 1) * mat;
+        }
+        const size_t pb = (size_t)off * sizeof(T), ib = (size_t)M.tdg.nsys * L.ncell * ms * 4;
+        if (M.patches.bytes < pb) M.patches.alloc(pb);
+        if (M.piv.bytes < ib) M.piv.alloc(ib);
+        if (M.perm.bytes < ib) M.perm.alloc(ib);
+        if (!M.info.p) M.info.alloc(4);
+        PatchTdArgs<T, T> pa{};
+        pa.n0 = L.n[0];
+        pa.n1 = L.n[1];
+        pa.n2 = L.n[2];
+        pa.elem = M.elem.as<T>();
+        pa.rec_words = rw;
+        pa.nsys = M.tdg.nsys;
+        for (int sy = 0; sy < M.tdg.nsys; ++sy) {
+            pa.cplx[sy] = M.tdg.cplx[sy];
+            pa.lre[sy] = M.tdg.lre[sy];
+            pa.lim[sy] = M.tdg.lim[sy];
+            pa.sys[sy] = M.patches.as<T>() + M.sys_off[sy];
+        }
+        {
+            TimerScope ts(&ctx->timers, "vanka_patch", s);
+            STMG_HIP((launch_patch_td<T, T>(L.dim, L.r, pa, (int)L.ncell, s)));
+        }
+        STMG_HIP(hipMemsetAsync(M.info.p, 0, 4, s));
+        {
+            TimerScope ts(&ctx->timers, "vanka_lu", s);
+            for (int sy = 0; sy < M.tdg.nsys; ++sy) {
+                T *A = M.patches.as<T>() + M.sys_off[sy];
+                int *pv = M.piv.as<int>() + M.piv_off[sy];
+                if (M.tdg.cplx[sy])
+                    STMG_HIP(launch_lu_c<T>(A, pv, M.ms, 2 * mat, (int)L.ncell, M.info.as<int>(), max_lds, s));
+                else
+                    STMG_HIP(launch_lu<T>(A, pv, M.ms, (int)L.ncell, M.info.as<int>(), max_lds, s));
+            }
+            STMG_HIP(launch_piv_to_perm(M.piv.as<int>(), M.perm.as<int>(), M.ms, (long long)M.tdg.nsys * L.ncell, s));
+        }
+        M.have_patches = true;
+        return;
+    }
     size_t pb = (size_t)L.ncell * M.m * M.m * sizeof(T);
     if (M.patches.bytes < pb) M.patches.alloc(pb);
     if (M.piv.bytes < (size_t)L.ncell * M.m * 4) M.piv.alloc((size_t)L.ncell * M.m * 4);
@@ -277,21 +327,49 @@ template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
     L.apply<T>(Mode::Jac, state_of<T>(M), d, t, nullptr, nullptr, 1, s);
     STMG_HIP(vec_axpby<T>(L.N, T(1), r, T(-1), t, s));
     TimerScope ts(&ctx->timers, "vanka_apply", s);
-    SolveArgs<T, T> sa{};
-    sa.n0 = L.n[0];
-    sa.n1 = L.n[1];
-    sa.n2 = L.n[2];
-    sa.nt = L.nt;
-    sa.Nn = L.Nn;
-    sa.Nv1 = L.Nv1;
-    sa.Np1 = L.Np1;
-    sa.defect = t;
-    sa.patches = M.patches.as<T>();
-    sa.piv = M.piv.as<int>();
-    sa.E = M.E.as<T>();
-    sa.d = d;
-    sa.omega = (T)mg.omega;
-    STMG_HIP((launch_solve<T, T>(L.dim, L.r, sa, (int)L.ncell, M.m, s)));
+    if (mg.td) {
+        SolveTdArgs<T, T> sa{};
+        sa.n0 = L.n[0];
+        sa.n1 = L.n[1];
+        sa.n2 = L.n[2];
+        sa.nt = L.nt;
+        sa.Nn = L.Nn;
+        sa.Nv1 = L.Nv1;
+        sa.Np1 = L.Np1;
+        sa.defect = t;
+        sa.nsys = M.tdg.nsys;
+        for (int sy = 0; sy < M.tdg.nsys; ++sy) {
+            sa.cplx[sy] = M.tdg.cplx[sy];
+            sa.sys[sy] = M.patches.as<T>() + M.sys_off[sy];
+            sa.perm[sy] = M.perm.as<int>() + M.piv_off[sy];
+            for (int a = 0; a < L.nt; ++a) {
+                sa.Tre[sy * 4 + a] = (T)M.tdg.Tre[sy * MAX_NT + a];
+                sa.Tim[sy * 4 + a] = (T)M.tdg.Tim[sy * MAX_NT + a];
+                sa.Fre[a * 4 + sy] = (T)M.tdg.Fre[a * MAX_NT + sy];
+                sa.Fim[a * 4 + sy] = (T)M.tdg.Fim[a * MAX_NT + sy];
+            }
+        }
+        sa.E = M.E.as<T>();
+        sa.d = d;
+        sa.omega = (T)mg.omega;
+        STMG_HIP((launch_solve_td<T, T>(L.dim, L.r, sa, (int)L.ncell, M.ms, s)));
+    } else {
+        SolveArgs<T, T> sa{};
+        sa.n0 = L.n[0];
+        sa.n1 = L.n[1];
+        sa.n2 = L.n[2];
+        sa.nt = L.nt;
+        sa.Nn = L.Nn;
+        sa.Nv1 = L.Nv1;
+        sa.Np1 = L.Np1;
+        sa.defect = t;
+        sa.patches = M.patches.as<T>();
+        sa.piv = M.piv.as<int>();
+        sa.E = M.E.as<T>();
+        sa.d = d;
+        sa.omega = (T)mg.omega;
+        STMG_HIP((launch_solve<T, T>(L.dim, L.r, sa, (int)L.ncell, M.m, s)));
+    }
     GatherArgs<T> g = L.gather_args<T>();
     g.E = M.E.as<T>();
     g.rhs = nullptr;

@@ -14,8 +14,13 @@ struct MgLevel {
     DevBuf vstar;                 // midpoint velocity in the multigrid precision
     DevBuf elem;                  // element records
     DevBuf patches, piv, info;    // patch LU factors
-    int m = 0;                    // patch size
+    int m = 0;                    // patch size (full space-time patch)
     bool have_patches = false;
+    // time-decoupled patches: one spatial factorization per eigen-system
+    TimeDiag tdg{};
+    int ms = 0;                   // spatial patch size
+    long long sys_off[MAX_NT] = {0, 0, 0, 0}, piv_off[MAX_NT] = {0, 0, 0, 0};
+    DevBuf perm;
     DevBuf r, d, t, E;            // work vectors in the multigrid precision
 };
 
@@ -23,6 +28,7 @@ struct Mg {
     int prec = STMG_F32;
     double omega = 0.35;
     int weighting = 0;
+    bool td = true;               // time-decoupled patch solves
     int nu1 = 1, nu2 = 1;
     std::vector<MgLevel> lv;
     std::vector<std::unique_ptr<Transfer>> tr;   // tr[l]: level l -> l+1

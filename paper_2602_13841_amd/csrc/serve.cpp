@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <thread>
@@ -50,7 +52,10 @@ extern "C" int stmg_serve(const stmg_request *reqs, int n, const stmg_options *o
     std::mutex mu;
     std::condition_variable cv;
     size_t in_use = 0;
-    int next = 0;
+    int next = 0, done = 0;
+    // progress log on stderr when the environment variable STMG_VERBOSE is set
+    const char *ev = std::getenv("STMG_VERBOSE");
+    const bool verbose = ev && *ev && *ev != '0';
     const double t0 = clock_s();
     auto worker = [&]() {
         (void)hipSetDevice(dev);
@@ -117,6 +122,12 @@ extern "C" int stmg_serve(const stmg_request *reqs, int n, const stmg_options *o
             {
                 std::lock_guard<std::mutex> lk(mu);
                 in_use -= foot[idx];
+                if (verbose) {
+                    ++done;
+                    std::fprintf(stderr, "[stmg] serve %d/%d: request %d (%dD n=%d r=%d k=%d) rc %d, %.2f s in slot\n",
+                                 done, n, idx, q.prob.dim, q.prob.n_cells[0], q.prob.r, q.prob.k, rc, R.end_s - R.start_s);
+                    std::fflush(stderr);
+                }
             }
             cv.notify_all();
         }

@@ -22,6 +22,18 @@ struct TimeCoefs {
     double s[MAX_NT];            // Radau nodes on [0,1]
 };
 
+// Spectral splitting of the time coupling W^{-1} K of a midpoint-surrogate
+// patch: nsys distinct eigen-systems (real eigenvalues first, then one
+// member of each conjugate pair).  Patch solve: y_s = sum_a T[s][a] r_a,
+// (lambda_s Mhat + Ahat) z_s = y_s, d_a = sum_s Re(F[a][s] z_s).
+struct TimeDiag {
+    int nsys;
+    int cplx[MAX_NT];
+    double lre[MAX_NT], lim[MAX_NT];
+    double Tre[MAX_NT * MAX_NT], Tim[MAX_NT * MAX_NT];   // [s * MAX_NT + a]
+    double Fre[MAX_NT * MAX_NT], Fim[MAX_NT * MAX_NT];   // [a * MAX_NT + s]
+};
+
 // host tables (tables.cpp)
 void gauss_rule(int nq, std::vector<double> &x01, std::vector<double> &w01);
 void lobatto_points(int npts, std::vector<double> &x01);
@@ -31,6 +43,7 @@ void lagrange_tables(const std::vector<double> &nodes, const std::vector<double>
 void legendre01_table(int r, const std::vector<double> &pts, std::vector<double> &out);
 std::vector<int> pressure_multi_indices(int r, int dim);
 TimeCoefs time_coefficients(int k, double tau);
+TimeDiag time_diagonalization(const TimeCoefs &tc);
 std::vector<double> time_embedding(int kf, int kc);
 int default_nq(int r);
 

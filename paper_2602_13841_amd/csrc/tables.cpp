@@ -275,3 +275,215 @@ std::vector<double> build_table_block(int r, int nq, const TableLayout &lay)
 }
 
 } // namespace stmg
+
+// ---------------------------------------------------------------------------
+// Diagonalization of the time coupling of the midpoint-surrogate patch
+// ---------------------------------------------------------------------------
+#include <complex>
+
+namespace stmg {
+
+namespace {
+
+using cplx = std::complex<double>;
+
+// Gaussian elimination with complete pivoting on an n x n complex matrix of
+// rank n-1: returns a null vector normalized to largest component 1.
+std::vector<cplx> null_vector(std::vector<cplx> B, int n)
+{
+    std::vector<int> colp(n);
+    for (int j = 0; j < n; ++j) colp[j] = j;
+    for (int c = 0; c < n - 1; ++c) {
+        int pr = c, pc = c;
+        double best = -1.0;
+        for (int i = c; i < n; ++i)
+            for (int j = c; j < n; ++j)
+                if (std::abs(B[i * n + j]) > best) {
+                    best = std::abs(B[i * n + j]);
+                    pr = i;
+                    pc = j;
+                }
+        for (int j = 0; j < n; ++j) std::swap(B[c * n + j], B[pr * n + j]);
+        for (int i = 0; i < n; ++i) std::swap(B[i * n + c], B[i * n + pc]);
+        std::swap(colp[c], colp[pc]);
+        for (int i = c + 1; i < n; ++i) {
+            cplx l = B[i * n + c] / B[c * n + c];
+            for (int j = c; j < n; ++j) B[i * n + j] -= l * B[c * n + j];
+        }
+    }
+    // the last permuted unknown is free (= 1); back substitution for the rest
+    std::vector<cplx> y(n);
+    y[n - 1] = 1.0;
+    for (int i = n - 2; i >= 0; --i) {
+        cplx s = 0.0;
+        for (int j = i + 1; j < n; ++j) s += B[i * n + j] * y[j];
+        y[i] = -s / B[i * n + i];
+    }
+    std::vector<cplx> v(n);
+    for (int j = 0; j < n; ++j) v[colp[j]] = y[j];
+    cplx big = 0.0;
+    for (int j = 0; j < n; ++j)
+        if (std::abs(v[j]) > std::abs(big)) big = v[j];
+    for (int j = 0; j < n; ++j) v[j] /= big;
+    return v;
+}
+
+// inverse of an n x n complex matrix (partial pivoting)
+std::vector<cplx> inverse(std::vector<cplx> A, int n)
+{
+    std::vector<cplx> X(n * n, 0.0);
+    for (int i = 0; i < n; ++i) X[i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int i = c + 1; i < n; ++i)
+            if (std::abs(A[i * n + c]) > std::abs(A[p * n + c])) p = i;
+        for (int j = 0; j < n; ++j) {
+            std::swap(A[c * n + j], A[p * n + j]);
+            std::swap(X[c * n + j], X[p * n + j]);
+        }
+        const cplx d = A[c * n + c];
+        if (d == cplx(0.0)) throw std::runtime_error("singular eigenvector matrix of the time coupling");
+        for (int j = 0; j < n; ++j) {
+            A[c * n + j] /= d;
+            X[c * n + j] /= d;
+        }
+        for (int i = 0; i < n; ++i) {
+            if (i == c) continue;
+            const cplx l = A[i * n + c];
+            for (int j = 0; j < n; ++j) {
+                A[i * n + j] -= l * A[c * n + j];
+                X[i * n + j] -= l * X[c * n + j];
+            }
+        }
+    }
+    return X;
+}
+
+} // namespace
+
+// The surrogate patch of eq. DefTildeHn has the Kronecker form
+//   K (x) Mhat + W (x) Ahat = (W (x) I) (E (x) Mhat + I (x) Ahat),  E = W^{-1} K,
+// with Mhat the velocity mass and Ahat the shared spatial core.  With
+// E = S diag(lambda) S^{-1} the patch solve splits into one spatial solve per
+// eigenvalue, (lambda Mhat + Ahat) z = (S^{-1} W^{-1} r)_lambda; a conjugate
+// pair needs one complex solve.  Eigenvalues are the roots of the
+// characteristic polynomial (Faddeev-LeVerrier coefficients, Durand-Kerner
+// iteration, Newton polish), eigenvectors the null vectors of E - lambda I.
+TimeDiag time_diagonalization(const TimeCoefs &tc)
+{
+    const int n = tc.nt;
+    TimeDiag td{};
+    std::vector<double> E(n * n);
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) E[a * n + b] = tc.K[a * n + b] / tc.w[a];
+    // characteristic polynomial p(x) = x^n + c[n-1] x^{n-1} + ... + c[0]
+    std::vector<double> c(n + 1, 0.0), Mk(n * n, 0.0), AM(n * n);
+    c[n] = 1.0;
+    for (int k = 1; k <= n; ++k) {
+        // M_k = E M_{k-1} + c_{n-k+1} I, c_{n-k} = -tr(E M_k) / k
+        std::vector<double> Mn(n * n, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int l = 0; l < n; ++l) s += E[i * n + l] * Mk[l * n + j];
+                Mn[i * n + j] = s + (i == j ? c[n - k + 1] : 0.0);
+            }
+        Mk = Mn;
+        double tr = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int l = 0; l < n; ++l) tr += E[i * n + l] * Mk[l * n + i];
+        c[n - k] = -tr / k;
+    }
+    auto poly = [&](cplx x) {
+        cplx v = 1.0;
+        for (int k = n - 1; k >= 0; --k) v = v * x + c[k];
+        return v;
+    };
+    auto dpoly = [&](cplx x) {
+        cplx v = double(n);
+        for (int k = n - 1; k >= 1; --k) v = v * x + double(k) * c[k];
+        return v;
+    };
+    double scale = 0.0;
+    for (int i = 0; i < n * n; ++i) scale = std::max(scale, std::abs(E[i]));
+    std::vector<cplx> z(n);
+    for (int i = 0; i < n; ++i) z[i] = scale * std::pow(cplx(0.4, 0.9), i);
+    for (int it = 0; it < 500; ++it) {
+        double move = 0.0;
+        for (int i = 0; i < n; ++i) {
+            cplx den = 1.0;
+            for (int j = 0; j < n; ++j)
+                if (j != i) den *= (z[i] - z[j]);
+            cplx dz = poly(z[i]) / den;
+            z[i] -= dz;
+            move = std::max(move, std::abs(dz));
+        }
+        if (move <= 1e-15 * scale) break;
+    }
+    for (int i = 0; i < n; ++i)
+        for (int it = 0; it < 3; ++it) {
+            cplx d = dpoly(z[i]);
+            if (d != cplx(0.0)) z[i] -= poly(z[i]) / d;
+        }
+    // order: real eigenvalues, then one member (Im > 0) of each conjugate pair
+    std::vector<cplx> lam;
+    for (int i = 0; i < n; ++i)
+        if (std::fabs(z[i].imag()) <= 1e-10 * std::abs(z[i])) lam.push_back(cplx(z[i].real(), 0.0));
+    const int nreal = (int)lam.size();
+    for (int i = 0; i < n; ++i)
+        if (z[i].imag() > 1e-10 * std::abs(z[i])) lam.push_back(z[i]);
+    if (nreal + 2 * ((int)lam.size() - nreal) != n) throw std::runtime_error("time coupling eigenvalues not paired");
+    // eigenvector matrix S: columns per system (pairs: v, conj v)
+    std::vector<cplx> S(n * n);
+    std::vector<int> col_of(lam.size());
+    int col = 0;
+    for (size_t s = 0; s < lam.size(); ++s) {
+        std::vector<cplx> B(n * n);
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) B[a * n + b] = E[a * n + b] - (a == b ? lam[s] : 0.0);
+        std::vector<cplx> v = null_vector(B, n);
+        if ((int)s < nreal)
+            for (int a = 0; a < n; ++a) v[a] = cplx(v[a].real(), 0.0);
+        col_of[s] = col;
+        for (int a = 0; a < n; ++a) S[a * n + col] = v[a];
+        ++col;
+        if ((int)s >= nreal) {
+            for (int a = 0; a < n; ++a) S[a * n + col] = std::conj(v[a]);
+            ++col;
+        }
+    }
+    std::vector<cplx> Si = inverse(S, n);
+    // check E S = S Lambda
+    double err = 0.0, ref = 0.0;
+    for (int a = 0; a < n; ++a)
+        for (int j = 0; j < n; ++j) {
+            cplx es = 0.0;
+            for (int b = 0; b < n; ++b) es += E[a * n + b] * S[b * n + j];
+            cplx lj = 0.0;
+            for (size_t s = 0; s < lam.size(); ++s) {
+                if (col_of[s] == j) lj = lam[s];
+                if ((int)s >= nreal && col_of[s] + 1 == j) lj = std::conj(lam[s]);
+            }
+            err = std::max(err, std::abs(es - S[a * n + j] * lj));
+            ref = std::max(ref, std::abs(es));
+        }
+    if (!(err <= 1e-10 * std::max(ref, 1e-300))) throw std::runtime_error("time coupling diagonalization inaccurate");
+    td.nsys = (int)lam.size();
+    for (int s = 0; s < td.nsys; ++s) {
+        td.cplx[s] = s >= nreal ? 1 : 0;
+        td.lre[s] = lam[s].real();
+        td.lim[s] = lam[s].imag();
+        const int j = col_of[s];
+        const double f = td.cplx[s] ? 2.0 : 1.0;
+        for (int a = 0; a < n; ++a) {
+            cplx t = Si[j * n + a] / tc.w[a];
+            td.Tre[s * MAX_NT + a] = t.real();
+            td.Tim[s * MAX_NT + a] = t.imag();
+            td.Fre[a * MAX_NT + s] = f * S[a * n + j].real();
+            td.Fim[a * MAX_NT + s] = f * S[a * n + j].imag();
+        }
+    }
+    return td;
+}
+
+} // namespace stmg

@@ -40,6 +40,34 @@ template <typename T, typename TP> struct SolveArgs {
     T omega;
 };
 
+// time-decoupled patches (one spatial matrix per eigen-system of the time
+// coupling; complex systems planar: real plane then imaginary plane)
+template <typename TE, typename TP> struct PatchTdArgs {
+    int n0, n1, n2;
+    const TE *elem;
+    long long rec_words;
+    int nsys;
+    int cplx[4];
+    double lre[4], lim[4];
+    TP *sys[4];            // per system: [cell][plane][ms][ms] row-major
+};
+
+template <typename T, typename TP> struct SolveTdArgs {
+    int n0, n1, n2;
+    int nt;
+    long long Nn, Nv1, Np1;
+    const T *defect;
+    int nsys;
+    int cplx[4];
+    const TP *sys[4];      // LU factors per system
+    const int *perm[4];    // row permutation per system: [cell][ms]
+    TP Tre[16], Tim[16];   // [s * 4 + a]
+    TP Fre[16], Fim[16];   // [a * 4 + s]
+    T *E;
+    T *d;
+    T omega;
+};
+
 // a batch of LU factorizations: uniform size m, or per-matrix sizes and
 // offsets (elements of A, entries of the pivot array)
 struct LuBatch {
@@ -59,6 +87,15 @@ hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds
                      const LuBatch *vb = nullptr);
 template <typename T, typename TP>
 hipError_t launch_solve(int dim, int r, const SolveArgs<T, TP> &a, int ncell, int m, hipStream_t s);
+template <typename TE, typename TP>
+hipError_t launch_patch_td(int dim, int r, const PatchTdArgs<TE, TP> &a, int ncell, hipStream_t s);
+// batched complex LU: matrix b at A + b * a_stride (real plane, imaginary plane)
+template <typename T>
+hipError_t launch_lu_c(T *A, int *piv, int m, long long a_stride, int batch, int *info, size_t max_lds, hipStream_t s);
+hipError_t launch_piv_to_perm(const int *piv, int *perm, int m, long long nmat, hipStream_t s);
+size_t solve_td_lds_bytes(int ms, int nt, size_t word);
+template <typename T, typename TP>
+hipError_t launch_solve_td(int dim, int r, const SolveTdArgs<T, TP> &a, int ncell, int ms, hipStream_t s);
 hipError_t launch_dense_solve(const double *LU, const int *piv, int m, const double *rhs, double *x, int nout,
                               hipStream_t s);
 hipError_t launch_identity(double *X, int n, hipStream_t s);

@@ -909,6 +909,541 @@ __global__ void __launch_bounds__(SV_THREADS) solve_kernel(SolveArgs<T, TP> A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Time-decoupled patches.  With the midpoint surrogate the patch matrix is
+// K (x) Mhat + W (x) Ahat (one spatial core for all time nodes); after the
+// spectral splitting of W^{-1} K every eigenvalue lambda of the splitting
+// needs the spatial matrix lambda Mhat + Ahat only: real for a real
+// eigenvalue, complex (planar: real plane, then imaginary plane) for a
+// conjugate pair.  Spatial patch order: velocity [c][l], then pressure modes.
+// ---------------------------------------------------------------------------
+template <int DIM, int R, typename TE, typename TP>
+__global__ void __launch_bounds__(256) patch_td_kernel(PatchTdArgs<TE, TP> A)
+{
+    using Z = VS<DIM, R>;
+    constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
+    constexpr int NV = DIM * NL, MS = NV + NPM;
+    constexpr long long MAT = (long long)MS * MS;
+    const int cell = blockIdx.x;
+    const int cc[3] = {cell % A.n0, (cell / A.n0) % A.n1, DIM == 3 ? cell / (A.n0 * A.n1) : 0};
+    const int nn[3] = {A.n0, A.n1, A.n2};
+    const long long rw = A.rec_words;
+    const TE *own = A.elem + (long long)cell * rw + DIM * DIM * NL * NL + NL * NL;
+    for (int e = threadIdx.x; e < MS * MS; e += blockDim.x) {
+        const int row = e / MS, col = e - (e / MS) * MS;
+        double mv = 0, lv = 0;
+        if (row < NV && col < NV) {
+            const int i = row % NL, c = row / NL, j = col % NL, e2 = col / NL;
+            const bool need_m = c == e2;
+            int li[3] = {i % N1, (i / N1) % N1, DIM == 3 ? i / (N1 * N1) : 0};
+            int lj[3] = {j % N1, (j / N1) % N1, DIM == 3 ? j / (N1 * N1) : 0};
+            // neighbour offsets per axis that hold both nodes
+            int opts[3][3], nopt[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                nopt[ax] = 0;
+                opts[ax][nopt[ax]++] = 0;
+                if (ax >= DIM) continue;
+                if (li[ax] == 0 && lj[ax] == 0 && cc[ax] > 0) opts[ax][nopt[ax]++] = -1;
+                if (li[ax] == R + 1 && lj[ax] == R + 1 && cc[ax] < nn[ax] - 1) opts[ax][nopt[ax]++] = 1;
+            }
+            for (int o2 = 0; o2 < nopt[2]; ++o2)
+                for (int o1 = 0; o1 < nopt[1]; ++o1)
+                    for (int o0 = 0; o0 < nopt[0]; ++o0) {
+                        const int dd[3] = {opts[0][o0], opts[1][o1], opts[2][o2]};
+                        const long long nb = (cc[0] + dd[0]) +
+                                             (long long)A.n0 * ((cc[1] + dd[1]) + (long long)A.n1 * (cc[2] + dd[2]));
+                        int ip = 0, jp = 0, st = 1;
+                        for (int ax = 0; ax < DIM; ++ax) {
+                            ip += st * (li[ax] - dd[ax] * (R + 1));
+                            jp += st * (lj[ax] - dd[ax] * (R + 1));
+                            st *= N1;
+                        }
+                        const TE *rec = A.elem + nb * rw;
+                        if (need_m) mv += (double)rec[DIM * DIM * NL * NL + (long long)ip * NL + jp];
+                        lv += (double)rec[((long long)(c * DIM + e2) * NL + ip) * NL + jp];
+                    }
+        } else if (row < NV) {
+            lv = (double)own[(long long)row * NPM + (col - NV)];     // row = c * NL + i
+        } else if (col < NV) {
+            lv = (double)own[(long long)col * NPM + (row - NV)];
+        }
+        for (int s = 0; s < A.nsys; ++s) {
+            TP *o = A.sys[s] + (long long)cell * (A.cplx[s] ? 2 : 1) * MAT;
+            o[e] = (TP)(A.lre[s] * mv + lv);
+            if (A.cplx[s]) o[MAT + e] = (TP)(A.lim[s] * mv);
+        }
+    }
+}
+
+// complex trailing update C -= L21 U12 of one column block (planar), FP32 on
+// MFMA: four real products per k step
+template <int NBP>
+__device__ __forceinline__ void trailing_update_c(float *Ar, float *Ai, int m, int j0, int nb, int cb, int ncb,
+                                                  const float *pr, const float *pi, const float *ur, const float *ui)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r0 = j0 + nb;
+    const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32;
+    for (int t = wv; t < nrt * nct; t += LU_THREADS / 64) {
+        const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
+        floatx4_t cr[2][2], ci[2][2];
+        for (int si = 0; si < 2; ++si)
+            for (int sj = 0; sj < 2; ++sj)
+                for (int i = 0; i < 4; ++i) {
+                    const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
+                    const bool ok = row < m && col < cb + ncb;
+                    cr[si][sj][i] = ok ? Ar[(long long)row * m + col] : 0.0f;
+                    ci[si][sj][i] = ok ? Ai[(long long)row * m + col] : 0.0f;
+                }
+        for (int k0 = 0; k0 < nb; k0 += 4) {
+            const int k = k0 + (lane >> 4);
+            float ar[2], ai[2], nai[2], br[2], bi[2];
+            for (int si = 0; si < 2; ++si) {
+                const int row = R + 16 * si + (lane & 15);
+                const bool ok = row < m && k < nb;
+                ar[si] = ok ? -pr[(row - j0) * NBP + k] : 0.0f;
+                ai[si] = ok ? -pi[(row - j0) * NBP + k] : 0.0f;
+                nai[si] = -ai[si];
+            }
+            for (int sj = 0; sj < 2; ++sj) {
+                br[sj] = ur[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)];
+                bi[sj] = ui[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)];
+            }
+            for (int si = 0; si < 2; ++si)
+                for (int sj = 0; sj < 2; ++sj) {
+                    cr[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[si], br[sj], cr[si][sj], 0, 0, 0);
+                    cr[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[si], bi[sj], cr[si][sj], 0, 0, 0);
+                    ci[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[si], bi[sj], ci[si][sj], 0, 0, 0);
+                    ci[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[si], br[sj], ci[si][sj], 0, 0, 0);
+                }
+        }
+        for (int si = 0; si < 2; ++si)
+            for (int sj = 0; sj < 2; ++sj)
+                for (int i = 0; i < 4; ++i) {
+                    const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
+                    if (row < m && col < cb + ncb) {
+                        Ar[(long long)row * m + col] = cr[si][sj][i];
+                        Ai[(long long)row * m + col] = ci[si][sj][i];
+                    }
+                }
+    }
+}
+
+// FP64: complex register tiles of 4 x 4 per thread on the vector ALUs
+template <int NBP>
+__device__ __forceinline__ void trailing_update_c(double *Ar, double *Ai, int m, int j0, int nb, int cb, int ncb,
+                                                  const double *pr, const double *pi, const double *ur,
+                                                  const double *ui)
+{
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int r0 = j0 + nb;
+    for (int R = r0; R < m; R += 64) {
+        for (int C = cb; C < cb + ncb; C += 64) {
+            double cr[4][4], ci[4][4];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    const int row = R + ty + 16 * i, col = C + tx + 16 * j;
+                    const bool ok = row < m && col < cb + ncb;
+                    cr[i][j] = ok ? Ar[(long long)row * m + col] : 0.0;
+                    ci[i][j] = ok ? Ai[(long long)row * m + col] : 0.0;
+                }
+            for (int k = 0; k < nb; ++k) {
+                double ar[4], ai[4], br[4], bi[4];
+                for (int i = 0; i < 4; ++i) {
+                    const int row = R + ty + 16 * i;
+                    ar[i] = row < m ? pr[(row - j0) * NBP + k] : 0.0;
+                    ai[i] = row < m ? pi[(row - j0) * NBP + k] : 0.0;
+                }
+                for (int j = 0; j < 4; ++j) {
+                    br[j] = ur[k * LU_CB + (C - cb) + tx + 16 * j];
+                    bi[j] = ui[k * LU_CB + (C - cb) + tx + 16 * j];
+                }
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) {
+                        cr[i][j] -= ar[i] * br[j] - ai[i] * bi[j];
+                        ci[i][j] -= ar[i] * bi[j] + ai[i] * br[j];
+                    }
+            }
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    const int row = R + ty + 16 * i, col = C + tx + 16 * j;
+                    if (row < m && col < cb + ncb) {
+                        Ar[(long long)row * m + col] = cr[i][j];
+                        Ai[(long long)row * m + col] = ci[i][j];
+                    }
+                }
+        }
+    }
+}
+
+// batched blocked complex LU with partial pivoting (largest modulus), planar
+// row-major storage: matrix b at Aall + b * a_stride, real plane then
+// imaginary plane; same panel / interchange / update structure as the real
+// kernel
+template <typename T, int NB>
+__global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, int *__restrict__ pivall, int m,
+                                                          long long a_stride, int *info)
+{
+    constexpr int NBP = NB + 1;
+    extern __shared__ unsigned char lds_raw[];
+    const int bid = blockIdx.x;
+    T *Ar = Aall + (long long)bid * a_stride;
+    T *Ai = Ar + (long long)m * m;
+    int *piv = pivall + (long long)bid * m;
+    T *pr = reinterpret_cast<T *>(lds_raw);           // [m][NBP] panel, real
+    T *pi = pr + (size_t)m * NBP;                      // [m][NBP] panel, imaginary
+    T *ur = pi + (size_t)m * NBP;                      // [NB][LU_CB] U12 block
+    T *ui = ur + (size_t)NB * LU_CB;
+    T *stg = ui + (size_t)NB * LU_CB;                  // [2 NB][LU_SWC] interchange staging
+    __shared__ T rv[LU_THREADS / 64];
+    __shared__ int ri[LU_THREADS / 64];
+    __shared__ int sw[NB];
+    __shared__ int aff_src[2 * NB], aff_dst[2 * NB];
+    __shared__ int n_aff;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int j0 = 0; j0 < m; j0 += NB) {
+        const int nb = min(NB, m - j0), mr = m - j0;
+        for (int e = tid; e < mr * nb; e += LU_THREADS) {
+            const int r = e / nb, c = e % nb;
+            const long long g = (long long)(j0 + r) * m + j0 + c;
+            pr[r * NBP + c] = Ar[g];
+            pi[r * NBP + c] = Ai[g];
+        }
+        __syncthreads();
+        for (int c = 0; c < nb; ++c) {
+            T best = T(-1);
+            int bi = c;
+            for (int r = c + tid; r < mr; r += LU_THREADS) {
+                const T x = pr[r * NBP + c], y = pi[r * NBP + c];
+                const T v = x * x + y * y;
+                if (v > best) { best = v; bi = r; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                T ov = __shfl_xor(best, off, 64);
+                int oi = __shfl_xor(bi, off, 64);
+                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+            }
+            if (lane == 0) { rv[wv] = best; ri[wv] = bi; }
+            __syncthreads();
+            T bv = rv[0];
+            int p = ri[0];
+            for (int w = 1; w < LU_THREADS / 64; ++w)
+                if (rv[w] > bv || (rv[w] == bv && ri[w] < p)) { bv = rv[w]; p = ri[w]; }
+            if (tid == 0) {
+                piv[j0 + c] = j0 + p;
+                sw[c] = p;
+                if (bv == T(0) && info) atomicAdd(info, 1);
+            }
+            if (p != c && tid < nb) {
+                T t = pr[c * NBP + tid];
+                pr[c * NBP + tid] = pr[p * NBP + tid];
+                pr[p * NBP + tid] = t;
+                t = pi[c * NBP + tid];
+                pi[c * NBP + tid] = pi[p * NBP + tid];
+                pi[p * NBP + tid] = t;
+            }
+            __syncthreads();
+            const T dr = pr[c * NBP + c], di = pi[c * NBP + c];
+            const T den = dr * dr + di * di;
+            const T ir = den != T(0) ? dr / den : T(0), ii = den != T(0) ? -di / den : T(0);
+            for (int r = c + 1 + tid; r < mr; r += LU_THREADS) {
+                const T xr = pr[r * NBP + c], xi = pi[r * NBP + c];
+                const T lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
+                pr[r * NBP + c] = lr;
+                pi[r * NBP + c] = li;
+                for (int cc = c + 1; cc < nb; ++cc) {
+                    const T vr = pr[c * NBP + cc], vi = pi[c * NBP + cc];
+                    pr[r * NBP + cc] -= lr * vr - li * vi;
+                    pi[r * NBP + cc] -= lr * vi + li * vr;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            int pos[2 * NB], cont[2 * NB], n = 0;
+            for (int c = 0; c < nb; ++c) {
+                const int p = sw[c];
+                if (p == c) continue;
+                int ic = -1, ip = -1;
+                for (int i = 0; i < n; ++i) {
+                    if (pos[i] == c) ic = i;
+                    if (pos[i] == p) ip = i;
+                }
+                if (ic < 0) { pos[n] = c; cont[n] = c; ic = n++; }
+                if (ip < 0) { pos[n] = p; cont[n] = p; ip = n++; }
+                const int t = cont[ic];
+                cont[ic] = cont[ip];
+                cont[ip] = t;
+            }
+            int k = 0;
+            for (int i = 0; i < n; ++i)
+                if (pos[i] != cont[i]) { aff_dst[k] = pos[i]; aff_src[k] = cont[i]; ++k; }
+            n_aff = k;
+        }
+        __syncthreads();
+        const int na = n_aff;
+        if (na > 0) {
+            for (int plane = 0; plane < 2; ++plane) {
+                T *A = plane ? Ai : Ar;
+                for (int c0 = 0; c0 < m; c0 += LU_SWC) {
+                    const int nc = min(LU_SWC, m - c0);
+                    for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
+                        const int i = e / LU_SWC, j = e % LU_SWC;
+                        if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * m + c0 + j];
+                    }
+                    __syncthreads();
+                    for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
+                        const int i = e / LU_SWC, j = e % LU_SWC;
+                        if (j < nc) A[(long long)(j0 + aff_dst[i]) * m + c0 + j] = stg[i * LU_SWC + j];
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        for (int e = tid; e < mr * nb; e += LU_THREADS) {
+            const int r = e / nb, c = e % nb;
+            const long long g = (long long)(j0 + r) * m + j0 + c;
+            Ar[g] = pr[r * NBP + c];
+            Ai[g] = pi[r * NBP + c];
+        }
+        __syncthreads();
+        for (int cb = j0 + nb; cb < m; cb += LU_CB) {
+            const int ncb = min(LU_CB, m - cb);
+            for (int e = tid; e < NB * LU_CB; e += LU_THREADS) {
+                ur[e] = T(0);
+                ui[e] = T(0);
+            }
+            __syncthreads();
+            if (tid < ncb) {
+                const int col = cb + tid;
+                T vr[NB], vi[NB];
+                for (int c = 0; c < NB; ++c) {
+                    const bool ok = c < nb;
+                    vr[c] = ok ? Ar[(long long)(j0 + c) * m + col] : T(0);
+                    vi[c] = ok ? Ai[(long long)(j0 + c) * m + col] : T(0);
+                }
+                for (int c = 1; c < NB; ++c) {
+                    if (c >= nb) break;
+                    T sr = vr[c], si = vi[c];
+                    for (int k = 0; k < c; ++k) {
+                        const T lr = pr[c * NBP + k], li = pi[c * NBP + k];
+                        sr -= lr * vr[k] - li * vi[k];
+                        si -= lr * vi[k] + li * vr[k];
+                    }
+                    vr[c] = sr;
+                    vi[c] = si;
+                }
+                for (int c = 0; c < NB; ++c)
+                    if (c < nb) {
+                        Ar[(long long)(j0 + c) * m + col] = vr[c];
+                        Ai[(long long)(j0 + c) * m + col] = vi[c];
+                        ur[c * LU_CB + tid] = vr[c];
+                        ui[c * LU_CB + tid] = vi[c];
+                    }
+            }
+            __syncthreads();
+            trailing_update_c<NBP>(Ar, Ai, m, j0, nb, cb, ncb, pr, pi, ur, ui);
+            __syncthreads();
+        }
+    }
+}
+
+// sequential LAPACK-style row interchanges -> one gather permutation per
+// matrix: (P b)[i] = b[perm[i]]
+__global__ void piv_to_perm_kernel(const int *__restrict__ piv, int *__restrict__ perm, int m, long long nmat)
+{
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nmat) return;
+    const int *p = piv + b * m;
+    int *q = perm + b * m;
+    for (int i = 0; i < m; ++i) q[i] = i;
+    for (int j = 0; j < m; ++j) {
+        const int k = p[j];
+        const int t = q[j];
+        q[j] = q[k];
+        q[k] = t;
+    }
+}
+
+// triangular solves with a planar complex row-major LU (unit lower L, upper
+// U), rhs (br, bi) in LDS
+template <typename T>
+__device__ void lu_substitute_c(const T *__restrict__ Lr, const T *__restrict__ Li, int m, T *br, T *bi, T *dr,
+                                T *di)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int g = tid >> 4, l16 = tid & 15;
+    for (int kb = 0; kb < m; kb += 64) {
+        const int nbk = min(64, m - kb);
+        for (int e = tid; e < nbk * 64; e += SV_THREADS) {
+            const int i = e / 64, j = e % 64;
+            if (j < nbk) {
+                dr[i * 65 + j] = Lr[(long long)(kb + i) * m + kb + j];
+                di[i * 65 + j] = Li[(long long)(kb + i) * m + kb + j];
+            }
+        }
+        __syncthreads();
+        if (wv == 0) {
+            T yr = lane < nbk ? br[kb + lane] : T(0), yi = lane < nbk ? bi[kb + lane] : T(0);
+            for (int c = 0; c < nbk; ++c) {
+                const T cr = __shfl(yr, c, 64), ci = __shfl(yi, c, 64);
+                if (lane > c && lane < nbk) {
+                    const T lr = dr[lane * 65 + c], li = di[lane * 65 + c];
+                    yr -= lr * cr - li * ci;
+                    yi -= lr * ci + li * cr;
+                }
+            }
+            if (lane < nbk) {
+                br[kb + lane] = yr;
+                bi[kb + lane] = yi;
+            }
+        }
+        __syncthreads();
+        for (int r = kb + nbk + g; r < m; r += SV_THREADS / 16) {
+            T sr = 0, si = 0;
+            for (int c = l16; c < nbk; c += 16) {
+                const T lr = Lr[(long long)r * m + kb + c], li = Li[(long long)r * m + kb + c];
+                const T xr = br[kb + c], xi = bi[kb + c];
+                sr += lr * xr - li * xi;
+                si += lr * xi + li * xr;
+            }
+            for (int off = 8; off > 0; off >>= 1) {
+                sr += __shfl_xor(sr, off, 16);
+                si += __shfl_xor(si, off, 16);
+            }
+            if (l16 == 0) {
+                br[r] -= sr;
+                bi[r] -= si;
+            }
+        }
+        __syncthreads();
+    }
+    const int nblk = (m + 63) / 64;
+    for (int bk = nblk - 1; bk >= 0; --bk) {
+        const int kb = bk * 64, nbk = min(64, m - kb);
+        for (int e = tid; e < nbk * 64; e += SV_THREADS) {
+            const int i = e / 64, j = e % 64;
+            if (j < nbk) {
+                dr[i * 65 + j] = Lr[(long long)(kb + i) * m + kb + j];
+                di[i * 65 + j] = Li[(long long)(kb + i) * m + kb + j];
+            }
+        }
+        __syncthreads();
+        if (wv == 0) {
+            T xr = lane < nbk ? br[kb + lane] : T(0), xi = lane < nbk ? bi[kb + lane] : T(0);
+            for (int c = nbk - 1; c >= 0; --c) {
+                const T vr = __shfl(xr, c, 64), vi = __shfl(xi, c, 64);
+                const T ur = dr[c * 65 + c], ui = di[c * 65 + c];
+                const T den = ur * ur + ui * ui;
+                const T qr = (vr * ur + vi * ui) / den, qi = (vi * ur - vr * ui) / den;
+                if (lane == c) {
+                    xr = qr;
+                    xi = qi;
+                }
+                if (lane < c) {
+                    const T lr = dr[lane * 65 + c], li = di[lane * 65 + c];
+                    xr -= lr * qr - li * qi;
+                    xi -= lr * qi + li * qr;
+                }
+            }
+            if (lane < nbk) {
+                br[kb + lane] = xr;
+                bi[kb + lane] = xi;
+            }
+        }
+        __syncthreads();
+        for (int r = g; r < kb; r += SV_THREADS / 16) {
+            T sr = 0, si = 0;
+            for (int c = l16; c < nbk; c += 16) {
+                const T lr = Lr[(long long)r * m + kb + c], li = Li[(long long)r * m + kb + c];
+                const T xr = br[kb + c], xi = bi[kb + c];
+                sr += lr * xr - li * xi;
+                si += lr * xi + li * xr;
+            }
+            for (int off = 8; off > 0; off >>= 1) {
+                sr += __shfl_xor(sr, off, 16);
+                si += __shfl_xor(si, off, 16);
+            }
+            if (l16 == 0) {
+                br[r] -= sr;
+                bi[r] -= si;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// one time-decoupled patch solve per cell: gather the patch defect of all
+// time nodes, per eigen-system transform (with the LU row permutation),
+// substitute, transform back; velocity to the cell buffer E, pressure
+// updated in place (pressure unknowns belong to one cell)
+template <int DIM, int R, typename T, typename TP>
+__global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP> A)
+{
+    using Z = VS<DIM, R>;
+    constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
+    constexpr int NV = DIM * NL, MS = NV + NPM, MSP = (MS + 1) & ~1;
+    constexpr long long MAT = (long long)MS * MS;
+    extern __shared__ unsigned char lds_raw[];
+    const int nt = A.nt;
+    TP *rl = reinterpret_cast<TP *>(lds_raw);   // [nt][MS] patch defect
+    TP *out = rl + nt * MSP;                    // [nt][MS] patch correction
+    TP *br = out + nt * MSP;
+    TP *bi = br + MSP;
+    TP *dr = bi + MSP;
+    TP *di = dr + 64 * 65;
+    const int cell = blockIdx.x, tid = threadIdx.x;
+    const int c0 = cell % A.n0, c1 = (cell / A.n0) % A.n1, c2 = DIM == 3 ? cell / (A.n0 * A.n1) : 0;
+    const long long N0 = (long long)(R + 1) * A.n0 + 1, N1g = (long long)(R + 1) * A.n1 + 1;
+    const long long pbase = (long long)nt * A.Nv1;
+    for (int e = tid; e < nt * MS; e += SV_THREADS) {
+        const int a = e / MS, j = e - (e / MS) * MS;
+        long long g;
+        if (j < NV) {
+            const int l = j % NL, c = j / NL;
+            const int i0 = l % N1, i1 = (l / N1) % N1, i2 = DIM == 3 ? l / (N1 * N1) : 0;
+            g = a * A.Nv1 + c * A.Nn +
+                (((long long)(R + 1) * c0 + i0) + N0 * (((long long)(R + 1) * c1 + i1) + N1g * ((long long)(R + 1) * c2 + i2)));
+        } else {
+            g = pbase + a * A.Np1 + (long long)cell * NPM + (j - NV);
+        }
+        rl[a * MSP + j] = (TP)A.defect[g];
+        out[a * MSP + j] = TP(0);
+    }
+    __syncthreads();
+    for (int s = 0; s < A.nsys; ++s) {
+        const bool cx = A.cplx[s] != 0;
+        const int *perm = A.perm[s] + (long long)cell * MS;
+        for (int i = tid; i < MS; i += SV_THREADS) {
+            const int src = perm[i];
+            TP sr = 0, si = 0;
+            for (int a = 0; a < nt; ++a) {
+                sr += A.Tre[s * 4 + a] * rl[a * MSP + src];
+                si += A.Tim[s * 4 + a] * rl[a * MSP + src];
+            }
+            br[i] = sr;
+            bi[i] = si;
+        }
+        __syncthreads();
+        const TP *LU = A.sys[s] + (long long)cell * (cx ? 2 : 1) * MAT;
+        if (cx) lu_substitute_c<TP>(LU, LU + MAT, MS, br, bi, dr, di);
+        else lu_substitute<TP>(LU, MS, br, dr);
+        for (int e = tid; e < nt * MS; e += SV_THREADS) {
+            const int a = e / MS, j = e - (e / MS) * MS;
+            TP v = A.Fre[a * 4 + s] * br[j];
+            if (cx) v -= A.Fim[a * 4 + s] * bi[j];
+            out[a * MSP + j] += v;
+        }
+        __syncthreads();
+    }
+    T *Ec = A.E + (long long)cell * nt * NV;
+    for (int e = tid; e < nt * MS; e += SV_THREADS) {
+        const int a = e / MS, j = e - (e / MS) * MS;
+        if (j < NV) Ec[a * NV + j] = (T)out[a * MSP + j];
+        else A.d[pbase + a * A.Np1 + (long long)cell * NPM + (j - NV)] += A.omega * (T)out[a * MSP + j];
+    }
+}
+
 // dense solve of one LU-factored system (coarse level): x = A^{-1} rhs
 template <typename T>
 __global__ void __launch_bounds__(SV_THREADS) dense_solve_kernel(const T *LU, const int *piv, int m, const T *rhs,
@@ -984,6 +1519,11 @@ __global__ void midpoint_kernel(const T *state, long long Nv1, int nt, const dou
 template <int NB, typename T> size_t lu_lds_bytes(int m)
 {
     return ((size_t)m * (NB + 1) + (size_t)NB * LU_CB + (size_t)2 * NB * LU_SWC) * sizeof(T);
+}
+
+template <int NB, typename T> size_t lu_c_lds_bytes(int m)
+{
+    return ((size_t)2 * m * (NB + 1) + (size_t)2 * NB * LU_CB + (size_t)2 * NB * LU_SWC) * sizeof(T);
 }
 
 } // namespace
@@ -1063,6 +1603,67 @@ hipError_t launch_solve(int dim, int r, const SolveArgs<T, TP> &a, int ncell, in
     return hipErrorInvalidValue;
 }
 
+template <typename TE, typename TP>
+hipError_t launch_patch_td(int dim, int r, const PatchTdArgs<TE, TP> &a, int ncell, hipStream_t s)
+{
+#define PC(D, RR)                                                                                                      \
+    if (dim == D && r == RR) {                                                                                         \
+        hipLaunchKernelGGL((patch_td_kernel<D, RR, TE, TP>), dim3(ncell), dim3(256), 0, s, a);                        \
+        return hipGetLastError();                                                                                      \
+    }
+    PC(2, 1) PC(2, 2) PC(2, 3) PC(3, 1) PC(3, 2) PC(3, 3)
+#undef PC
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_lu_c(T *A, int *piv, int m, long long a_stride, int batch, int *info, size_t max_lds, hipStream_t s)
+{
+#define LUC(NBV)                                                                                                       \
+    if (lu_c_lds_bytes<NBV, T>(m) <= max_lds) {                                                                        \
+        size_t bytes = lu_c_lds_bytes<NBV, T>(m);                                                                      \
+        hipError_t e = hipFuncSetAttribute((const void *)lu_kernel_c<T, NBV>,                                          \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                    \
+        if (e != hipSuccess) return e;                                                                                 \
+        hipLaunchKernelGGL((lu_kernel_c<T, NBV>), dim3(batch), dim3(LU_THREADS), bytes, s, A, piv, m, a_stride, info); \
+        return hipGetLastError();                                                                                      \
+    }
+    LUC(32) LUC(16) LUC(8) LUC(4)
+#undef LUC
+    return hipErrorInvalidConfiguration;
+}
+
+hipError_t launch_piv_to_perm(const int *piv, int *perm, int m, long long nmat, hipStream_t s)
+{
+    if (nmat <= 0) return hipSuccess;
+    const int th = 256;
+    hipLaunchKernelGGL(piv_to_perm_kernel, dim3((unsigned)((nmat + th - 1) / th)), dim3(th), 0, s, piv, perm, m, nmat);
+    return hipGetLastError();
+}
+
+size_t solve_td_lds_bytes(int ms, int nt, size_t word)
+{
+    const size_t msp = (size_t)((ms + 1) & ~1);
+    return (2 * nt * msp + 2 * msp + 2 * 64 * 65) * word;
+}
+
+template <typename T, typename TP>
+hipError_t launch_solve_td(int dim, int r, const SolveTdArgs<T, TP> &a, int ncell, int ms, hipStream_t s)
+{
+    size_t bytes = solve_td_lds_bytes(ms, a.nt, sizeof(TP));
+#define SC(D, RR)                                                                                                      \
+    if (dim == D && r == RR) {                                                                                         \
+        hipError_t e = hipFuncSetAttribute((const void *)solve_td_kernel<D, RR, T, TP>,                                \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                    \
+        if (e != hipSuccess) return e;                                                                                 \
+        hipLaunchKernelGGL((solve_td_kernel<D, RR, T, TP>), dim3(ncell), dim3(SV_THREADS), bytes, s, a);              \
+        return hipGetLastError();                                                                                      \
+    }
+    SC(2, 1) SC(2, 2) SC(2, 3) SC(3, 1) SC(3, 2) SC(3, 3)
+#undef SC
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_dense_solve(const double *LU, const int *piv, int m, const double *rhs, double *x, int nout,
                               hipStream_t s)
 {
@@ -1108,6 +1709,13 @@ template hipError_t launch_lu<float>(float *, int *, int, int, int *, size_t, hi
 template hipError_t launch_solve<double, double>(int, int, const SolveArgs<double, double> &, int, int, hipStream_t);
 template hipError_t launch_solve<float, float>(int, int, const SolveArgs<float, float> &, int, int, hipStream_t);
 template hipError_t launch_solve<double, float>(int, int, const SolveArgs<double, float> &, int, int, hipStream_t);
+template hipError_t launch_patch_td<double, double>(int, int, const PatchTdArgs<double, double> &, int, hipStream_t);
+template hipError_t launch_patch_td<float, float>(int, int, const PatchTdArgs<float, float> &, int, hipStream_t);
+template hipError_t launch_lu_c<double>(double *, int *, int, long long, int, int *, size_t, hipStream_t);
+template hipError_t launch_lu_c<float>(float *, int *, int, long long, int, int *, size_t, hipStream_t);
+template hipError_t launch_solve_td<double, double>(int, int, const SolveTdArgs<double, double> &, int, int,
+                                                    hipStream_t);
+template hipError_t launch_solve_td<float, float>(int, int, const SolveTdArgs<float, float> &, int, int, hipStream_t);
 template hipError_t launch_midpoint<double>(const double *, long long, int, const double *, double *, hipStream_t);
 template hipError_t launch_midpoint<float>(const float *, long long, int, const double *, float *, hipStream_t);
 

@@ -142,3 +142,32 @@ def slab_state(dim: int, n, r: int, k: int, seed: int, kind: str = "uniform") ->
         return uniform(N, seed)
     v = smooth_velocity(dim, n, r, seed)
     return np.concatenate([np.tile(v, k + 1), np.zeros(Np)])
+
+
+def serving_stream(nreq: int, seed: int, dims=(2, 3), ns=(8, 12, 16, 24), rs=(1, 2, 3), ks=(0, 1, 2),
+                   res=(1.0, 100.0, 1000.0), tau: float = 1.0 / 64):
+    """A mixed stream of slab-solve requests: dimension, cells per axis,
+    degrees and Reynolds number drawn uniformly (PCG64, `seed`).  Each request
+    is the no-slip problem with zero force whose previous-slab
+    velocity is the smooth field (one field per distinct (dim, n, r), seed
+    5).  Returns a list of dicts with keys dim, n, r, k, nu, tau, v_prev."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fields = {}
+    out = []
+    for _ in range(nreq):
+        d = int(rng.choice(dims))
+        n = int(rng.choice(ns))
+        r = int(rng.choice(rs))
+        k = int(rng.choice(ks))
+        re = float(rng.choice(res))
+        key = (d, n, r)
+        if key not in fields:
+            fields[key] = smooth_velocity(d, (n,) * d, r, 5)
+        out.append(dict(dim=d, n=(n,) * d, r=r, k=k, nu=1.0 / re, tau=tau, v_prev=fields[key]))
+    return out
+
+
+def poisson_arrivals(nreq: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / rate, nreq))
