@@ -1,7 +1,9 @@
 #!/usr/bin/env python
 """Benchmark of the slab hot path on one MI355X.
 
-Metric: space-time DoF/s of the Jacobian vmult, FP64 (the value) vs FP32.
+Metric: space-time DoF/s of the Jacobian vmult, FP64 (the value) vs FP32;
+slab solves/s (Newton-FGMRES with the hp-STMG preconditioner in FP32 and in
+FP64); p50/p99 latency of a served request stream.
 Workload: 3D unit cube, 16^3 affine hexahedra, Q3/P2disc (r=2) x DG(2),
 nu = 1e-2 (Re = 100), tau = 1/32, Newton state = seeded smooth divergence-free
 Fourier field (8 modes per axis, max |v| = 1) at every time node, direction
@@ -85,6 +87,86 @@ def cpu_baseline(U, X, seconds=12.0):
                       f"({100 * frac:.1f}% of one vmult), element-matrix action, {dt:.1f} s"}
 
 
+SOLVE_WORKLOAD = dict(dim=3, n=(32, 32, 32), r=3, k=1, nu=1e-3, tau=1.0 / 64, perturb=0.2, vert_seed=4, v0_seed=5)
+TIMER_NAMES = ["vanka_elem", "vanka_patch", "vanka_lu", "vanka_apply", "cell_jac_f64", "cell_jac_f32", "gather_f64",
+               "gather_f32", "cell_res_f64", "cell_mass_f64", "coarse_factor", "coarse_solve", "transfer"]
+
+
+def bench_solve(prec, warm=True):
+    """One Newton-FGMRES slab solve of the 32^3 perturbed-mesh workload
+    (r=3, k=1, Re=1000, tau=1/64), previous-slab velocity = smooth field,
+    zero initial guess, stopping at |R|_M <= 1e-8 |R_0|_M.  Returns solves/s,
+    DoF/s (N / wall), iteration counts and the kernel-time split."""
+    import torch
+    from paper_2602_13841_amd import inputs as I
+    from paper_2602_13841_amd import stmg
+    w = SOLVE_WORKLOAD
+    d, n = w["dim"], w["n"]
+    if warm:
+        # load the code objects of this configuration on a small mesh
+        c = stmg.Context(d, (4, 4, 4), w["r"], w["k"], w["nu"], w["tau"], prec_mg=prec)
+        c.set_slab_data(None, torch.tensor(I.smooth_velocity(d, (4, 4, 4), w["r"], 1), device="cuda"))
+        c.newton_solve(torch.zeros(c.N, dtype=torch.float64, device="cuda"))
+        del c
+    vert = I.perturbed_vertices(d, n, w["perturb"], w["vert_seed"])
+    ctx = stmg.Context(d, n, w["r"], w["k"], w["nu"], w["tau"], vertices=vert, prec_mg=prec,
+                       newton_rtol=1e-8, newton_atol=0.0)
+    ctx.set_slab_data(None, torch.tensor(I.smooth_velocity(d, n, w["r"], w["v0_seed"]), device="cuda"))
+    u = torch.zeros(ctx.N, dtype=torch.float64, device="cuda")
+    ctx.timing_reset()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, st, rc = ctx.newton_solve(u)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.timing(False)
+    tm = {k: round(ctx.timing_get(k)[0] / 1e3, 4) for k in TIMER_NAMES if ctx.timing_get(k)[1]}
+    out = {"prec_mg": "f64" if prec == stmg.STMG_F64 else "f32", "N": ctx.N, "levels": ctx.num_levels(),
+           "converged": rc == 0, "newton": st.newton_its, "fgmres": list(st.fgmres_its[: st.newton_its]),
+           "rebuilds": st.rebuilds, "res_rel": st.res_M / st.res0_M, "wall_s": wall,
+           "solves_per_s": 1.0 / wall, "dof_per_s": ctx.N / wall, "kernel_s": tm}
+    del ctx, u
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_serve(nreq, slots):
+    """Serving: the first `nreq` requests of the seeded mixed stream (2D/3D,
+    8..24 cells per axis, r in 1..3, k in 0..2, Re in {1, 100, 1000}).  A
+    closed-loop run (all requests at t = 0) gives the throughput X; a second
+    run with Poisson arrivals at 0.8 X gives the latencies (completion -
+    arrival)."""
+    import torch
+    from paper_2602_13841_amd import inputs as I
+    from paper_2602_13841_amd import stmg
+    reqs = I.serving_stream(nreq, 7)
+    o = stmg.default_options(newton_rtol=1e-8, newton_atol=0.0)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * 0.85)
+    # per-request progress lines of the serving loop on stderr
+    os.environ["STMG_VERBOSE"] = "1"
+    for q in reqs:
+        q["arrival_s"] = 0.0
+    _, res, wall = stmg.serve(reqs, o, slots=slots, hbm_budget=budget)
+    X = nreq / wall
+    lam = 0.8 * X
+    arr = I.poisson_arrivals(nreq, lam, 8)
+    for q, a in zip(reqs, arr):
+        q["arrival_s"] = float(a)
+    _, res2, wall2 = stmg.serve(reqs, o, slots=slots, hbm_budget=budget)
+    lat = np.array([x.latency_s for x in res2])
+    ok = sum(1 for x in res + res2 if x.rc == 0)
+    classes = {}
+    for q, x in zip(reqs, res2):
+        classes.setdefault(f"{q['dim']}D", []).append(x.latency_s)
+    return {"requests": nreq, "slots": slots, "hbm_budget_GB": budget / 1e9, "closed_loop_wall_s": wall,
+            "solves_per_s": X, "arrival_rate": lam, "poisson_wall_s": wall2,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "p50_by_dim": {k: float(np.percentile(v, 50)) for k, v in classes.items()},
+            "converged": ok, "runs": 2 * nreq}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +174,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rotate-bytes", type=float, default=1.1 * 2 ** 30)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -139,6 +225,8 @@ def main():
     t64, cell64, gat64, nsets64 = run(torch.float64, args.steps, args.warmup)
     t32, cell32, gat32, nsets32 = run(torch.float32, args.steps, args.warmup)
 
+    del ctx
+    torch.cuda.empty_cache()
     flops = vmult_flops(w["dim"], w["n"], w["r"], w["k"], nq)
     bytes64 = (2 * N + Nv) * 8
     achieved = flops / (cell64 * 1e-3)
@@ -168,6 +256,18 @@ def main():
         "fp32": {"value": N / t32, "unit": "DoF/s", "ms_per_step": t32 * 1e3, "cell_ms": cell32,
                  "gather_ms": gat32, "speedup_vs_fp64": t64 / t32},
     }
+    if not args.no_solve:
+        print("[bench] slab solve, FP32 multigrid", file=sys.stderr, flush=True)
+        s32 = bench_solve(stmg.STMG_F32)
+        print("[bench] slab solve, FP64 multigrid", file=sys.stderr, flush=True)
+        s64 = bench_solve(stmg.STMG_F64)
+        out["solve"] = {"workload": "3D 32^3 hexes perturbed by 0.2h, Q4/P3disc (r=3) x DG(1), Re=1000, "
+                                    "tau=1/64, smooth previous-slab velocity, |R|_M <= 1e-8 |R_0|_M",
+                        "fp32_mg": s32, "fp64_mg": s64,
+                        "speedup_fp32_vs_fp64": s64["wall_s"] / s32["wall_s"]}
+    if not args.no_serve:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serving"] = bench_serve(args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:
         U_, X_ = U, X
         out["cpu_baseline"] = cpu_baseline(U_, X_)
