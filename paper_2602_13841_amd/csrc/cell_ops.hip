@@ -180,27 +180,336 @@ template <typename T> __device__ __forceinline__ T dominus(T y)
     return y > T(0) ? T(0) : (y < T(0) ? T(-1) : T(-0.5));
 }
 
+// ---------------------------------------------------------------------------
+// Register-pencil tensor contractions for the volume pass.  A stage treats
+// all fields of two groups (group A: NFA fields with nodal extent IA and 1D
+// matrix MA; group B: NFB fields, IB, MB; matrices NQ x I row-major) at once;
+// a work item is (field, pencil), with the loop over the slowest axis kept
+// in registers.  Reads along the contracted axis are shared by the lanes of
+// a pencil row (LDS broadcast).  Layouts are x fastest; every stage ends
+// with a barrier.
+// ---------------------------------------------------------------------------
+template <int DIM, int NQ, int NFA, int IA, int NFB, int IB> struct PencilSizes {
+    static constexpr int B1A = DIM == 3 ? NQ * IA * IA : NQ * IA;    // stage-1 output per field
+    static constexpr int B1B = DIM == 3 ? NQ * IB * IB : NQ * IB;
+    static constexpr int B2A = DIM == 3 ? NQ * NQ * IA : 0;          // stage-2 output per field
+    static constexpr int B2B = DIM == 3 ? NQ * NQ * IB : 0;
+    static constexpr int BUF1 = NFA * B1A + NFB * B1B;
+    static constexpr int BUF2 = NFA * B2A + NFB * B2B;
+};
+
+// nodal -> quadrature points: inA [NFA][IA^DIM], inB [NFB][IB^DIM];
+// outA field f at QA + f * NQ^DIM, outB field f at QB + f * NQ^DIM
+template <int DIM, int NQ, int NFA, int IA, int NFB, int IB, int NTH, typename T>
+__device__ __forceinline__ void pencil_fwd(const T *__restrict__ inA, const T *__restrict__ inB, T *__restrict__ QA,
+                                           T *__restrict__ QB, T *__restrict__ buf1, T *__restrict__ buf2,
+                                           const T *__restrict__ MA, const T *__restrict__ MB)
+{
+    using PS = PencilSizes<DIM, NQ, NFA, IA, NFB, IB>;
+    constexpr int NQV = DIM == 3 ? NQ * NQ * NQ : NQ * NQ;
+    const int tid = threadIdx.x;
+    if constexpr (DIM == 3) {
+        // stage 1: contract z; item (f, j, i), column over k in registers
+        constexpr int NA = NFA * IA * IA, NB = NFB * IB * IB;
+        for (int w = tid; w < NA + NB; w += NTH) {
+            const bool ga = w < NA;
+            const int ww = ga ? w : w - NA;
+            const int I = ga ? IA : IB;
+            const int f = ww / (I * I), ji = ww - f * I * I;
+            const T *src = (ga ? inA + f * IA * IA * IA : inB + f * IB * IB * IB) + ji;
+            T *dst = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + ji;
+            const T *M = ga ? MA : MB;
+            T u[IA > IB ? IA : IB];
+#pragma unroll
+            for (int k = 0; k < (IA > IB ? IA : IB); ++k) u[k] = k < I ? src[k * I * I] : T(0);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                T s = 0;
+#pragma unroll
+                for (int k = 0; k < (IA > IB ? IA : IB); ++k)
+                    if (k < I) s += M[q * I + k] * u[k];
+                dst[q * I * I] = s;
+            }
+        }
+        __syncthreads();
+        // stage 2: contract y; item (f, qy, i), loop over qz
+        constexpr int NA2 = NFA * NQ * IA, NB2 = NFB * NQ * IB;
+        for (int w = tid; w < NA2 + NB2; w += NTH) {
+            const bool ga = w < NA2;
+            const int ww = ga ? w : w - NA2;
+            const int I = ga ? IA : IB;
+            const int f = ww / (NQ * I), rr = ww - f * NQ * I, qy = rr / I, i = rr - qy * I;
+            const T *src = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + i;
+            T *dst = (ga ? buf2 + f * PS::B2A : buf2 + NFA * PS::B2A + f * PS::B2B) + qy * I + i;
+            const T *m = (ga ? MA : MB) + qy * I;
+            T mr[IA > IB ? IA : IB];
+#pragma unroll
+            for (int j = 0; j < (IA > IB ? IA : IB); ++j) mr[j] = j < I ? m[j] : T(0);
+#pragma unroll 1
+            for (int qz = 0; qz < NQ; ++qz) {
+                T s = 0;
+#pragma unroll
+                for (int j = 0; j < (IA > IB ? IA : IB); ++j)
+                    if (j < I) s += mr[j] * src[(qz * I + j) * I];
+                dst[qz * NQ * I] = s;
+            }
+        }
+        __syncthreads();
+        // stage 3: contract x; item (f, qy, qx), loop over qz
+        constexpr int NA3 = NFA * NQ * NQ, NB3 = NFB * NQ * NQ;
+        for (int w = tid; w < NA3 + NB3; w += NTH) {
+            const bool ga = w < NA3;
+            const int ww = ga ? w : w - NA3;
+            const int I = ga ? IA : IB;
+            const int f = ww / (NQ * NQ), rr = ww - f * NQ * NQ, qy = rr / NQ, qx = rr - qy * NQ;
+            const T *src = (ga ? buf2 + f * PS::B2A : buf2 + NFA * PS::B2A + f * PS::B2B) + qy * I;
+            T *dst = (ga ? QA : QB) + f * NQV + qy * NQ + qx;
+            const T *m = (ga ? MA : MB) + qx * I;
+            T mr[IA > IB ? IA : IB];
+#pragma unroll
+            for (int i = 0; i < (IA > IB ? IA : IB); ++i) mr[i] = i < I ? m[i] : T(0);
+#pragma unroll 1
+            for (int qz = 0; qz < NQ; ++qz) {
+                T s = 0;
+#pragma unroll
+                for (int i = 0; i < (IA > IB ? IA : IB); ++i)
+                    if (i < I) s += mr[i] * src[qz * NQ * I + i];
+                dst[qz * NQ * NQ] = s;
+            }
+        }
+        __syncthreads();
+    } else {
+        // stage 1: contract y; item (f, i), column over j in registers
+        constexpr int NA = NFA * IA, NB = NFB * IB;
+        for (int w = tid; w < NA + NB; w += NTH) {
+            const bool ga = w < NA;
+            const int ww = ga ? w : w - NA;
+            const int I = ga ? IA : IB;
+            const int f = ww / I, i = ww - f * I;
+            const T *src = (ga ? inA + f * IA * IA : inB + f * IB * IB) + i;
+            T *dst = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + i;
+            const T *M = ga ? MA : MB;
+            T u[IA > IB ? IA : IB];
+#pragma unroll
+            for (int j = 0; j < (IA > IB ? IA : IB); ++j) u[j] = j < I ? src[j * I] : T(0);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                T s = 0;
+#pragma unroll
+                for (int j = 0; j < (IA > IB ? IA : IB); ++j)
+                    if (j < I) s += M[q * I + j] * u[j];
+                dst[q * I] = s;
+            }
+        }
+        __syncthreads();
+        // stage 2: contract x; item (f, qx), loop over qy
+        constexpr int NA2 = NFA * NQ, NB2 = NFB * NQ;
+        for (int w = tid; w < NA2 + NB2; w += NTH) {
+            const bool ga = w < NA2;
+            const int ww = ga ? w : w - NA2;
+            const int I = ga ? IA : IB;
+            const int f = ww / NQ, qx = ww - f * NQ;
+            const T *src = ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B;
+            T *dst = (ga ? QA : QB) + f * NQV + qx;
+            const T *m = (ga ? MA : MB) + qx * I;
+            T mr[IA > IB ? IA : IB];
+#pragma unroll
+            for (int i = 0; i < (IA > IB ? IA : IB); ++i) mr[i] = i < I ? m[i] : T(0);
+#pragma unroll 1
+            for (int qy = 0; qy < NQ; ++qy) {
+                T s = 0;
+#pragma unroll
+                for (int i = 0; i < (IA > IB ? IA : IB); ++i)
+                    if (i < I) s += mr[i] * src[qy * I + i];
+                dst[qy * NQ] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// quadrature points -> nodes (transposed interpolation): field f of group A at
+// QA + f * NQ^DIM into outA [NFA][IA^DIM], group B likewise
+template <int DIM, int NQ, int NFA, int IA, int NFB, int IB, int NTH, typename T>
+__device__ __forceinline__ void pencil_bwd(const T *__restrict__ QA, const T *__restrict__ QB, T *__restrict__ outA,
+                                           T *__restrict__ outB, T *__restrict__ buf1, T *__restrict__ buf2,
+                                           const T *__restrict__ MA, const T *__restrict__ MB)
+{
+    using PS = PencilSizes<DIM, NQ, NFA, IA, NFB, IB>;
+    constexpr int NQV = DIM == 3 ? NQ * NQ * NQ : NQ * NQ;
+    constexpr int IM = IA > IB ? IA : IB;
+    const int tid = threadIdx.x;
+    if constexpr (DIM == 3) {
+        // stage 3^T: contract qx -> i; item (f, qy, i), loop over qz
+        constexpr int NA = NFA * NQ * IA, NB = NFB * NQ * IB;
+        for (int w = tid; w < NA + NB; w += NTH) {
+            const bool ga = w < NA;
+            const int ww = ga ? w : w - NA;
+            const int I = ga ? IA : IB;
+            const int f = ww / (NQ * I), rr = ww - f * NQ * I, qy = rr / I, i = rr - qy * I;
+            const T *src = (ga ? QA : QB) + f * NQV + qy * NQ;
+            T *dst = (ga ? buf2 + f * PS::B2A : buf2 + NFA * PS::B2A + f * PS::B2B) + qy * I + i;
+            const T *M = ga ? MA : MB;
+            T mc[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) mc[q] = M[q * I + i];
+#pragma unroll 1
+            for (int qz = 0; qz < NQ; ++qz) {
+                T s = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) s += mc[q] * src[qz * NQ * NQ + q];
+                dst[qz * NQ * I] = s;
+            }
+        }
+        __syncthreads();
+        // stage 2^T: contract qy -> j; item (f, j, i), loop over qz
+        constexpr int NA2 = NFA * IA * IA, NB2 = NFB * IB * IB;
+        for (int w = tid; w < NA2 + NB2; w += NTH) {
+            const bool ga = w < NA2;
+            const int ww = ga ? w : w - NA2;
+            const int I = ga ? IA : IB;
+            const int f = ww / (I * I), rr = ww - f * I * I, j = rr / I, i = rr - j * I;
+            const T *src = (ga ? buf2 + f * PS::B2A : buf2 + NFA * PS::B2A + f * PS::B2B) + i;
+            T *dst = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + j * I + i;
+            const T *M = ga ? MA : MB;
+            T mc[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) mc[q] = M[q * I + j];
+#pragma unroll 1
+            for (int qz = 0; qz < NQ; ++qz) {
+                T s = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) s += mc[q] * src[(qz * NQ + q) * I];
+                dst[qz * I * I] = s;
+            }
+        }
+        __syncthreads();
+        // stage 1^T: contract qz -> k; item (f, j, i), column over qz in registers
+        for (int w = tid; w < NA2 + NB2; w += NTH) {
+            const bool ga = w < NA2;
+            const int ww = ga ? w : w - NA2;
+            const int I = ga ? IA : IB;
+            const int f = ww / (I * I), ji = ww - f * I * I;
+            const T *src = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + ji;
+            T *dst = (ga ? outA + f * IA * IA * IA : outB + f * IB * IB * IB) + ji;
+            const T *M = ga ? MA : MB;
+            T col[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) col[q] = src[q * I * I];
+#pragma unroll
+            for (int k = 0; k < IM; ++k) {
+                if (k >= I) break;
+                T s = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) s += M[q * I + k] * col[q];
+                dst[k * I * I] = s;
+            }
+        }
+        __syncthreads();
+    } else {
+        // stage 2^T: contract qx -> i; item (f, i), loop over qy
+        constexpr int NA = NFA * IA, NB = NFB * IB;
+        for (int w = tid; w < NA + NB; w += NTH) {
+            const bool ga = w < NA;
+            const int ww = ga ? w : w - NA;
+            const int I = ga ? IA : IB;
+            const int f = ww / I, i = ww - f * I;
+            const T *src = (ga ? QA : QB) + f * NQV;
+            T *dst = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + i;
+            const T *M = ga ? MA : MB;
+            T mc[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) mc[q] = M[q * I + i];
+#pragma unroll 1
+            for (int qy = 0; qy < NQ; ++qy) {
+                T s = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) s += mc[q] * src[qy * NQ + q];
+                dst[qy * I] = s;
+            }
+        }
+        __syncthreads();
+        // stage 1^T: contract qy -> j; item (f, i), column over qy in registers
+        for (int w = tid; w < NA + NB; w += NTH) {
+            const bool ga = w < NA;
+            const int ww = ga ? w : w - NA;
+            const int I = ga ? IA : IB;
+            const int f = ww / I, i = ww - f * I;
+            const T *src = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + i;
+            T *dst = (ga ? outA + f * IA * IA : outB + f * IB * IB) + i;
+            const T *M = ga ? MA : MB;
+            T col[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) col[q] = src[q * I];
+#pragma unroll
+            for (int j = 0; j < IM; ++j) {
+                if (j >= I) break;
+                T s = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) s += M[q * I + j] * col[q];
+                dst[j * I] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// transposed collocation in place: Y_c = val_c + sum_j Dq_j^T F[c][j] for the
+// DIM velocity components; F[c][j] at Q + (c * DIM + j) * NQV, val_c at
+// Q + (DIM * DIM + c) * NQV (overwritten by Y_c).  Item (c, pencil) with the
+// slowest-axis column in registers; Dq is NQ x NQ row-major.
+template <int DIM, int NQ, int NTH, typename T>
+__device__ __forceinline__ void colloc_bwd(T *__restrict__ Q, const T *__restrict__ Dq)
+{
+    constexpr int NQV = DIM == 3 ? NQ * NQ * NQ : NQ * NQ;
+    constexpr int NP = DIM == 3 ? NQ * NQ : NQ;       // pencils per field
+    constexpr int SL = DIM == 3 ? NQ * NQ : NQ;       // stride of the slowest axis
+    const int tid = threadIdx.x;
+    for (int w = tid; w < DIM * NP; w += NTH) {
+        const int c = w / NP, p = w - c * NP;
+        const T *Fs = Q + (c * DIM + (DIM - 1)) * NQV + p;    // slowest-axis flux column
+        T col[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) col[q] = Fs[q * SL];
+        T *Y = Q + (DIM * DIM + c) * NQV + p;
+        const int px = DIM == 3 ? p % NQ : p, py = DIM == 3 ? p / NQ : 0;
+#pragma unroll 1
+        for (int qs = 0; qs < NQ; ++qs) {
+            T s = Y[qs * SL];
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) s += Dq[m * NQ + qs] * col[m];
+            // x direction: F[c][0] along the row through (qs, py)
+            const T *Fx = Q + (c * DIM + 0) * NQV + qs * SL + (DIM == 3 ? py * NQ : 0);
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) s += Dq[m * NQ + px] * Fx[m];
+            if constexpr (DIM == 3) {
+                const T *Fy = Q + (c * DIM + 1) * NQV + qs * SL + px;
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) s += Dq[m * NQ + py] * Fy[m * NQ];
+            }
+            Y[qs * SL] = s;
+        }
+    }
+    __syncthreads();
+}
+
 // LDS layout (in units of T) of the cell kernel
-template <int DIM, int R, int NQ, typename T> struct Lds {
+template <int DIM, int R, int NQ, typename T, Mode MODE> struct Lds {
     using Z = Sizes<DIM, R>;
     static constexpr int NQV = ipow(NQ, DIM);
-    static constexpr int NQF = ipow(NQ, DIM - 1);
-    // quadrature-point record fields: volume uses DIM*DIM + 2*DIM + 1 (Jac outputs)
-    static constexpr int NFIELD_V = DIM * DIM + DIM + 1;      // F (DIM^2), val (DIM), div
-    static constexpr int NFIELD_IN = 3 * DIM + 1;             // xhat, v, xmix, p
-    static constexpr int NF_V = NFIELD_V > NFIELD_IN ? NFIELD_V : NFIELD_IN;
-    static constexpr int NF_F = DIM + DIM * DIM + DIM + 1;    // face: xhat, grad xhat, v, p
-    static constexpr int Q_SIZE = (NF_V * NQV > NF_F * NQF + (DIM + DIM * DIM + 1) * NQF)
-                                      ? NF_V * NQV
-                                      : NF_F * NQF + (DIM + DIM * DIM + 1) * NQF;
-    // sweep temporaries: the largest intermediate of any sweep (forward,
-    // transposed, face) is DIM * N1 * NQ * max(N1, NQ) words; pressure sweeps
-    // need at most NQ^DIM; reductions use one word per thread (<= 256).
-    static constexpr int MX = Z::N1 > NQ ? Z::N1 : NQ;
-    static constexpr int TS = DIM * Z::N1 * NQ * MX;
-    static constexpr int TSP = TS > NQV ? TS : NQV;
-    static constexpr int TMP1 = TSP > 256 ? TSP : 256;
-    static constexpr int TMP2 = TMP1;
+    // nodal input fields of the volume pass: xhat, state (Jac), mixed field (not Mass)
+    static constexpr int NFA = MODE == Mode::Jac ? 3 * DIM : (MODE == Mode::Res ? 2 * DIM : DIM);
+    // quadrature-point record: inputs NFA + 1 (pressure) fields, then the
+    // outputs F (DIM^2), value coefficients (DIM), pressure coefficient in
+    // fields of their own (written while neighbours still read the inputs)
+    static constexpr int NFIELD_V = DIM * DIM + DIM + 1;
+    static constexpr int NFIELD_IN = NFA + 1;
+    static constexpr int OUT0 = NFIELD_IN;                    // first output field
+    static constexpr int Q_SIZE = (NFIELD_IN + NFIELD_V) * NQV;
+    // temporaries of the pencil stages
+    using PS = PencilSizes<DIM, NQ, NFA, Z::N1, 1, Z::RP1>;
+    static constexpr int TMP1 = PS::BUF1;
+    static constexpr int TMP2 = PS::BUF2 > 1 ? PS::BUF2 : 1;
 };
 
 } // namespace
@@ -248,13 +557,13 @@ __device__ __forceinline__ T geometry(bool mapped, const T *X, const T xi[3], co
 }
 
 // LDS words of the cell kernel for nt time nodes
-template <int DIM, int R, int NQ, typename T>
+template <int DIM, int R, int NQ, typename T, Mode MODE>
 __host__ __device__ constexpr int lds_words(int nt, int tabwords)
 {
     using Z = Sizes<DIM, R>;
-    using LY = Lds<DIM, R, NQ, T>;
-    return ((tabwords + 1) & ~1) + nt * DIM * Z::NL + nt * Z::NPF + 2 * DIM * Z::NL + Z::NPF + LY::Q_SIZE +
-           LY::TMP1 + LY::TMP2 + 64;
+    using LY = Lds<DIM, R, NQ, T, MODE>;
+    return ((tabwords + 1) & ~1) + nt * DIM * Z::NL + nt * Z::NPF + LY::NFA * Z::NL + DIM * Z::NL + Z::NPF +
+           LY::Q_SIZE + LY::TMP1 + LY::TMP2 + 64;
 }
 
 // ---------------------------------------------------------------------------
@@ -264,14 +573,10 @@ template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE>
 __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
 {
     using Z = Sizes<DIM, R>;
-    using LY = Lds<DIM, R, NQ, T>;
+    using LY = Lds<DIM, R, NQ, T, MODE>;
     constexpr int N1 = Z::N1, NL = Z::NL, RP1 = Z::RP1, NPF = Z::NPF, NPM = Z::NPM;
-    constexpr int NQV = LY::NQV, NQF = LY::NQF;
-    constexpr int NQ2 = DIM == 2 ? 1 : NQ;       // extent of axis 2 at Gauss points
-    constexpr int N12 = DIM == 2 ? 1 : N1;
-    constexpr int RP12 = DIM == 2 ? 1 : RP1;
+    constexpr int NQV = LY::NQV;
     constexpr int QPT = (NQV + NTH - 1) / NTH;   // quadrature points per thread
-    constexpr int NOUT = DIM * DIM + DIM + 1;    // F (ref, DIM^2), value coef (DIM), pressure coef
 
     extern __shared__ unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
@@ -290,8 +595,10 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
     T *tab = sm;
     T *xs = tab + ((lay.total + 1) & ~1);          // [nt][DIM][NL] nodal x
     T *xpf = xs + nt * DIM * NL;                   // [nt][NPF] full-tensor pressure modes
-    T *ns = xpf + nt * NPF;                        // [DIM][NL] nodal scratch (state)
-    T *ys = ns + DIM * NL;                         // [DIM][NL] nodal mix / output
+    constexpr int NFA = LY::NFA;
+    T *cur = xpf + nt * NPF;                       // [NFA][NL] nodal xhat^a, state^a (Jac), mixed field
+    T *ns = cur + DIM * NL;                        // state (Jac)
+    T *ys = cur + NFA * NL;                        // [DIM][NL] nodal output
     T *ypf = ys + DIM * NL;                        // [NPF] pressure output (full tensor)
     T *Q = ypf + NPF;                              // quadrature record
     T *t1 = Q + LY::Q_SIZE;
@@ -338,12 +645,213 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
         xpf[a * NPF + pmode_full<DIM, R>(m)] = x[pbase + a * A.Np1 + (long long)cell * NPM + m];
     }
 
-    const bool bnd = (c0 == 0) || (c0 == A.n0 - 1) || (c1 == 0) || (c1 == A.n1 - 1) ||
-                     (DIM == 3 && ((c2 == 0) || (c2 == A.n2 - 1)));
+    __syncthreads();
+
+    for (int a = 0; a < nt; ++a) {
+        // ---- nodal inputs: xhat^a, state^a (Jac), mixed field sum_b K_ab x^b (- phi0_a vprev)
+        constexpr int MIXF = MODE == Mode::Jac ? 2 * DIM : DIM;
+        for (int e = tid; e < DIM * NL; e += NTH) {
+            const int l = e % NL, c = e / NL;
+            cur[e] = xs[(a * DIM + c) * NL + l];
+            if constexpr (MODE == Mode::Jac) {
+                const T *st = A.state + vec * A.sstride;
+                ns[e] = st[a * A.Nv1 + c * A.Nn + gnode(l)];
+            }
+            if constexpr (MODE != Mode::Mass) {
+                T m = 0;
+                for (int b = 0; b < nt; ++b) m += A.K[a * nt + b] * xs[(b * DIM + c) * NL + l];
+                if constexpr (MODE == Mode::Res) {
+                    if (A.vprev) m -= A.phi0[a] * A.vprev[c * A.Nn + gnode(l)];
+                }
+                cur[MIXF * NL + e] = m;
+            }
+        }
+        __syncthreads();
+
+        // ---- nodes -> Gauss points: Q fields [0, NFA) velocity-type, NFA pressure
+        pencil_fwd<DIM, NQ, NFA, N1, 1, RP1, NTH, T>(cur, xpf + a * NPF, Q, Q + NFA * NQV, t1, t2, S, Lp);
+
+        // ---- quadrature-point physics: outputs straight into their own fields -----
+        T *Qo = Q + LY::OUT0 * NQV;
+        const T wa = A.w[a];
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int q = tid + j * NTH;
+            if (q < NQV) {
+                const int qi[3] = {q % NQ, (q / NQ) % NQ, DIM == 3 ? q / (NQ * NQ) : 0};
+                const int strides[3] = {1, NQ, NQ * NQ};
+                T xi[3] = {0, 0, 0}, Jit[3][3];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) xi[d] = qx[qi[d]];
+                const T det = geometry<DIM>(mapped, geo, xi, hcar, Jit);
+                T jxw = det;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) jxw *= qw[qi[d]];
+                const T sc = wa * jxw;
+                T xh[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    xh[c] = Q[c * NQV + q];
+                    if constexpr (MODE == Mode::Jac) v[c] = Q[(DIM + c) * NQV + q];
+                    else v[c] = xh[c];
+                }
+                const T ph = Q[NFA * NQV + q];
+                if constexpr (MODE == Mode::Mass) {
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) Qo[(DIM * DIM + c) * NQV + q] = sc * xh[c];
+                    Qo[(DIM * DIM + DIM) * NQV + q] = sc * ph;
+                } else {
+                    T divx = 0;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        T gref[3];
+#pragma unroll
+                        for (int jd = 0; jd < DIM; ++jd) {
+                            T s = 0;
+                            const T *src = Q + c * NQV + q - qi[jd] * strides[jd];
+#pragma unroll
+                            for (int m = 0; m < NQ; ++m) s += Dq[qi[jd] * NQ + m] * src[m * strides[jd]];
+                            gref[jd] = s;
+                        }
+                        T Fc[3];
+#pragma unroll
+                        for (int d = 0; d < DIM; ++d) {
+                            T g = 0;
+#pragma unroll
+                            for (int jd = 0; jd < DIM; ++jd) g += Jit[d][jd] * gref[jd];
+                            if (d == c) divx += g;
+                            // (nu grad x - x (x) v - v (x) x - p I) for the Jacobian; Res: v = x
+                            Fc[d] = A.nu * g - xh[c] * v[d] - (MODE == Mode::Jac ? v[c] * xh[d] : T(0));
+                            if (d == c) Fc[d] -= ph;
+                        }
+#pragma unroll
+                        for (int jd = 0; jd < DIM; ++jd) {
+                            T s = 0;
+#pragma unroll
+                            for (int d = 0; d < DIM; ++d) s += Fc[d] * Jit[d][jd];
+                            Qo[(c * DIM + jd) * NQV + q] = s * sc;
+                        }
+                        Qo[(DIM * DIM + c) * NQV + q] = jxw * Q[(MIXF + c) * NQV + q];
+                    }
+                    Qo[(DIM * DIM + DIM) * NQV + q] = -sc * divx;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- transposed collocation (value slots become Y_c), then Gauss points -> nodes
+        if constexpr (MODE != Mode::Mass) colloc_bwd<DIM, NQ, NTH, T>(Qo, Dq);
+        pencil_bwd<DIM, NQ, DIM, N1, 1, RP1, NTH, T>(Qo + DIM * DIM * NQV, Qo + (DIM * DIM + DIM) * NQV, ys, ypf, t1,
+                                                     t2, S, Lp);
+
+        // ---- write results ---------------------------------------------------------
+        T *Ec = E + ((long long)cell * nt + a) * DIM * NL;
+        for (int e = tid; e < DIM * NL; e += NTH) Ec[e] = ys[e];
+        for (int e = tid; e < NPM; e += NTH) {
+            const long long gi = pbase + a * A.Np1 + (long long)cell * NPM + e;
+            T val = ypf[pmode_full<DIM, R>(e)];
+            if constexpr (MODE == Mode::Res) {
+                if (A.rhs) val -= A.rhs[gi];
+            }
+            y[gi] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Boundary-face kernel: the Nitsche and convective boundary terms (eq.
+// def-a-gam-tp, eq. def-b-gam) of the cells on the domain boundary, one
+// workgroup per boundary cell and all time nodes.  Runs after the volume
+// kernel on the same stream and adds to its results (cell buffer E, pressure
+// rows), so the summation order is fixed.
+// ---------------------------------------------------------------------------
+template <int DIM, int R, int NQ, typename T> struct FaceLds {
+    using Z = Sizes<DIM, R>;
+    static constexpr int NQV = ipow(NQ, DIM);
+    static constexpr int NQF = ipow(NQ, DIM - 1);
+    static constexpr int NF_F = DIM + DIM * DIM + DIM + 1;    // xhat, grad xhat, v, p
+    static constexpr int Q_SIZE = NF_F * NQF + (DIM + DIM * DIM + 1) * NQF;
+    static constexpr int MX = Z::N1 > NQ ? Z::N1 : NQ;
+    static constexpr int TS = DIM * Z::N1 * NQ * MX;
+    static constexpr int TSP = TS > NQV ? TS : NQV;
+    static constexpr int TMP = TSP > 256 ? TSP : 256;
+};
+
+template <int DIM, int R, int NQ, typename T>
+__host__ __device__ constexpr int face_lds_words(int tabwords)
+{
+    using Z = Sizes<DIM, R>;
+    using LY = FaceLds<DIM, R, NQ, T>;
+    return ((tabwords + 1) & ~1) + 4 * DIM * Z::NL + 2 * Z::NPF + LY::Q_SIZE + 2 * LY::TMP + 64;
+}
+
+template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE>
+__global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
+{
+    using Z = Sizes<DIM, R>;
+    using LY = FaceLds<DIM, R, NQ, T>;
+    constexpr int N1 = Z::N1, NL = Z::NL, RP1 = Z::RP1, NPF = Z::NPF, NPM = Z::NPM;
+    constexpr int NQV = LY::NQV, NQF = LY::NQF;
+    constexpr int NQ2 = DIM == 2 ? 1 : NQ;
+    constexpr int N12 = DIM == 2 ? 1 : N1;
+    constexpr int RP12 = DIM == 2 ? 1 : RP1;
+
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+
+    const int tid = threadIdx.x;
+    const int cell = A.bcells[blockIdx.x];
+    const int vec = blockIdx.y;
+    const int nt = A.nt;
+    const T *__restrict__ x = A.x + vec * A.xstride;
+    T *__restrict__ y = A.y + vec * A.ystride;
+    T *__restrict__ E = A.E + (long long)vec * A.ncell * nt * DIM * NL;
+
+    TableLayout lay;
+    lay.init(R, NQ);
+    T *tab = sm;
+    T *xs = tab + ((lay.total + 1) & ~1);          // [DIM][NL] nodal x of the time node
+    T *ns = xs + DIM * NL;                         // [DIM][NL] nodal state
+    T *ys = ns + DIM * NL;                         // [DIM][NL] nodal output
+    T *xpf = ys + DIM * NL;                        // [NPF] pressure modes (full tensor)
+    T *ypf = xpf + NPF;                            // [NPF] pressure output
+    T *Q = ypf + NPF;                              // face record
+    T *t1 = Q + LY::Q_SIZE;
+    T *t2 = t1 + LY::TMP;
+    T *geo = t2 + LY::TMP;                         // [8][3] vertices, [6] h_F, [1] volume
+
+    for (int i = tid; i < lay.total; i += NTH) tab[i] = A.tab[i];
+    const T *S = tab + lay.S, *St = tab + lay.St, *D = tab + lay.D, *Dt = tab + lay.Dt;
+    const T *Se = tab + lay.Se, *De = tab + lay.De;
+    const T *Lp = tab + lay.L, *Lpt = tab + lay.Lt, *Lpe = tab + lay.Le, *qw = tab + lay.qw;
+    const T *qx = tab + lay.qx;
+
+    const int c0 = cell % A.n0;
+    const int c1 = (cell / A.n0) % A.n1;
+    const int c2 = DIM == 3 ? cell / (A.n0 * A.n1) : 0;
+    const long long N0 = (long long)(R + 1) * A.n0 + 1;
+    const long long N1g = (long long)(R + 1) * A.n1 + 1;
+    auto gnode = [&](int l) -> long long {
+        int i0 = l % N1, i1 = (l / N1) % N1, i2 = DIM == 3 ? l / (N1 * N1) : 0;
+        long long g0 = (long long)(R + 1) * c0 + i0, g1 = (long long)(R + 1) * c1 + i1;
+        long long g2 = (long long)(R + 1) * c2 + i2;
+        return g0 + N0 * (g1 + N1g * g2);
+    };
+    const long long pbase = (long long)nt * A.Nv1;
+    const T hcar[3] = {T(1) / A.n0, T(1) / A.n1, DIM == 3 ? T(1) / A.n2 : T(1)};
+    const bool mapped = A.mapped != 0;
+    if (mapped && tid < (1 << DIM)) {
+        int v = tid;
+        int o0 = v & 1, o1 = (v >> 1) & 1, o2 = (v >> 2) & 1;
+        long long vi = (c0 + o0) + (long long)(A.n0 + 1) * ((c1 + o1) + (long long)(A.n1 + 1) * (c2 + o2));
+        for (int a = 0; a < 3; ++a) geo[v * 3 + a] = a < DIM ? T(A.vert[vi * DIM + a]) : T(0);
+    }
+    __syncthreads();
     T *hF = geo + 24;   // |K| / |F| per face id
 
     // ---- h_F of the boundary faces (reading: |K|/|F| by the cell's quadrature) ----
-    if (MODE != Mode::Mass && bnd) {
+    {
         if (!mapped) {
             if (tid < 2 * DIM) hF[tid] = hcar[tid / 2];
         } else {
@@ -394,174 +902,29 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
     }
     __syncthreads();
 
+
     for (int a = 0; a < nt; ++a) {
-        // ---- nodal scratch: state (Jac) and mixed field sum_b K_ab x^b (- phi0_a vprev)
+        const T wa = A.w[a];
         for (int e = tid; e < DIM * NL; e += NTH) {
-            int l = e % NL, c = e / NL;
+            const int l = e % NL, c = e / NL;
+            const long long g = a * A.Nv1 + c * A.Nn + gnode(l);
+            xs[e] = x[g];
             if constexpr (MODE == Mode::Jac) {
                 const T *st = A.state + vec * A.sstride;
-                ns[e] = st[a * A.Nv1 + c * A.Nn + gnode(l)];
+                ns[e] = st[g];
             }
-            T m = 0;
-            if constexpr (MODE != Mode::Mass) {
-                for (int b = 0; b < nt; ++b) m += A.K[a * nt + b] * xs[(b * DIM + c) * NL + l];
-            }
-            if constexpr (MODE == Mode::Res) {
-                if (A.vprev) m -= A.phi0[a] * A.vprev[c * A.Nn + gnode(l)];
-            }
-            ys[e] = m;
+            ys[e] = 0;
+        }
+        for (int e = tid; e < NPF; e += NTH) {
+            xpf[e] = 0;
+            ypf[e] = 0;
         }
         __syncthreads();
-
-        // ---- forward sweeps to the Gauss points --------------------------------
-        // Q fields: [0,DIM) xhat, [DIM,2DIM) state v (Jac), [2DIM,3DIM) mix, 3DIM p
-        sweep<DIM, DIM, N1, N1, N12, NQ, NQ, NQ2, false>(xs + a * DIM * NL, NL, Q, NQV, t1, t2, S, S, S);
-        if constexpr (MODE == Mode::Jac)
-            sweep<DIM, DIM, N1, N1, N12, NQ, NQ, NQ2, false>(ns, NL, Q + DIM * NQV, NQV, t1, t2, S, S, S);
-        if constexpr (MODE != Mode::Mass)
-            sweep<DIM, DIM, N1, N1, N12, NQ, NQ, NQ2, false>(ys, NL, Q + 2 * DIM * NQV, NQV, t1, t2, S, S, S);
-        sweep<DIM, 1, RP1, RP1, RP12, NQ, NQ, NQ2, false>(xpf + a * NPF, NPF, Q + 3 * DIM * NQV, NQV, t1, t2,
-                                                           Lp, Lp, Lp);
-
-        // ---- quadrature-point physics (register staged, then in place) -----------
-        T outv[QPT][NOUT];
-        const T wa = A.w[a];
-#pragma unroll
-        for (int j = 0; j < QPT; ++j) {
-            const int q = tid + j * NTH;
-            if (q < NQV) {
-                const int qi[3] = {q % NQ, (q / NQ) % NQ, DIM == 3 ? q / (NQ * NQ) : 0};
-                const int strides[3] = {1, NQ, NQ * NQ};
-                T xh[3] = {0, 0, 0}, v[3] = {0, 0, 0}, xm[3] = {0, 0, 0}, gref[3][3];
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    xh[c] = Q[c * NQV + q];
-                    if constexpr (MODE == Mode::Jac) v[c] = Q[(DIM + c) * NQV + q];
-                    if constexpr (MODE != Mode::Mass) xm[c] = Q[(2 * DIM + c) * NQV + q];
-                }
-                const T ph = Q[3 * DIM * NQV + q];
-                if constexpr (MODE != Mode::Mass) {
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-                        for (int jd = 0; jd < DIM; ++jd) {
-                            T s = 0;
-                            const int base = q - qi[jd] * strides[jd];
-#pragma unroll
-                            for (int m = 0; m < NQ; ++m)
-                                s += Dq[qi[jd] * NQ + m] * Q[c * NQV + base + m * strides[jd]];
-                            gref[c][jd] = s;
-                        }
-                }
-                T xi[3] = {0, 0, 0}, Jit[3][3];
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) xi[d] = qx[qi[d]];
-                const T det = geometry<DIM>(mapped, geo, xi, hcar, Jit);
-                T jxw = det;
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) jxw *= qw[qi[d]];
-                const T sc = wa * jxw;
-                if constexpr (MODE == Mode::Mass) {
-#pragma unroll
-                    for (int f = 0; f < DIM * DIM; ++f) outv[j][f] = 0;
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) outv[j][DIM * DIM + c] = sc * xh[c];
-                    outv[j][DIM * DIM + DIM] = sc * ph;
-                } else {
-                    T G[3][3];
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-                        for (int d = 0; d < DIM; ++d) {
-                            T s = 0;
-#pragma unroll
-                            for (int jd = 0; jd < DIM; ++jd) s += Jit[d][jd] * gref[c][jd];
-                            G[c][d] = s;
-                        }
-                    T divx = 0;
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) divx += G[c][c];
-                    T F[3][3];
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-                        for (int d = 0; d < DIM; ++d) {
-                            if constexpr (MODE == Mode::Jac)
-                                F[c][d] = A.nu * G[c][d] - xh[c] * v[d] - v[c] * xh[d];
-                            else
-                                F[c][d] = A.nu * G[c][d] - xh[c] * xh[d];
-                            if (c == d) F[c][d] -= ph;
-                        }
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-                        for (int jd = 0; jd < DIM; ++jd) {
-                            T s = 0;
-#pragma unroll
-                            for (int d = 0; d < DIM; ++d) s += F[c][d] * Jit[d][jd];
-                            outv[j][c * DIM + jd] = s * sc;
-                        }
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) outv[j][DIM * DIM + c] = jxw * xm[c];
-                    outv[j][DIM * DIM + DIM] = -sc * divx;
-                }
-            }
-        }
+        for (int e = tid; e < NPM; e += NTH) xpf[pmode_full<DIM, R>(e)] = x[pbase + a * A.Np1 + (long long)cell * NPM + e];
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < QPT; ++j) {
-            const int q = tid + j * NTH;
-            if (q < NQV) {
-#pragma unroll
-                for (int f = 0; f < NOUT; ++f) Q[f * NQV + q] = outv[j][f];
-            }
-        }
-        __syncthreads();
-
-        // ---- transposed collocation: Y_c = val_c + sum_j Dq_j^T F[c][j] -------------
-        {
-            T yv[QPT][3];
-#pragma unroll
-            for (int j = 0; j < QPT; ++j) {
-                const int q = tid + j * NTH;
-                if (q < NQV) {
-                    const int qi[3] = {q % NQ, (q / NQ) % NQ, DIM == 3 ? q / (NQ * NQ) : 0};
-                    const int strides[3] = {1, NQ, NQ * NQ};
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) {
-                        T s = Q[(DIM * DIM + c) * NQV + q];
-                        if constexpr (MODE != Mode::Mass) {
-#pragma unroll
-                            for (int jd = 0; jd < DIM; ++jd) {
-                                const int base = q - qi[jd] * strides[jd];
-#pragma unroll
-                                for (int m = 0; m < NQ; ++m)
-                                    s += Dqt[qi[jd] * NQ + m] * Q[(c * DIM + jd) * NQV + base + m * strides[jd]];
-                            }
-                        }
-                        yv[j][c] = s;
-                    }
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < QPT; ++j) {
-                const int q = tid + j * NTH;
-                if (q < NQV) {
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) Q[c * NQV + q] = yv[j][c];
-                }
-            }
-            __syncthreads();
-        }
-        // backward sweeps to the nodes / pressure modes
-        sweep<DIM, DIM, NQ, NQ, NQ2, N1, N1, N12, false>(Q, NQV, ys, NL, t1, t2, St, St, St);
-        sweep<DIM, 1, NQ, NQ, NQ2, RP1, RP1, RP12, false>(Q + (DIM * DIM + DIM) * NQV, NQV, ypf, NPF, t1, t2,
-                                                          Lpt, Lpt, Lpt);
-
         // ---- boundary faces ----------------------------------------------------------
-        if constexpr (MODE != Mode::Mass) {
-            if (bnd) {
+        {
+            {
                 for (int ax = 0; ax < DIM; ++ax) {
                     for (int side = 0; side < 2; ++side) {
                         const int cc = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
@@ -596,7 +959,7 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
     } while (0)
                         {
                             const T *m0 = ax == 0 ? Srow : S, *m1 = ax == 1 ? Srow : S, *m2 = ax == 2 ? Srow : S;
-                            FACE_SWEEP(DIM, xs + a * DIM * NL, NL, FQ + FV * NQF, NQF, m0, m1, m2, N1, N1, N12);
+                            FACE_SWEEP(DIM, xs, NL, FQ + FV * NQF, NQF, m0, m1, m2, N1, N1, N12);
                             if constexpr (MODE == Mode::Jac)
                                 FACE_SWEEP(DIM, ns, NL, FQ + FS * NQF, NQF, m0, m1, m2, N1, N1, N12);
                             for (int jd = 0; jd < DIM; ++jd) {
@@ -604,11 +967,11 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
                                 const T *d1 = ax == 1 ? (jd == 1 ? Drow : Srow) : (jd == 1 ? D : S);
                                 const T *d2 = ax == 2 ? (jd == 2 ? Drow : Srow) : (jd == 2 ? D : S);
                                 for (int c = 0; c < DIM; ++c)
-                                    FACE_SWEEP(1, xs + (a * DIM + c) * NL, NL, FQ + (FG + c * DIM + jd) * NQF, NQF,
+                                    FACE_SWEEP(1, xs + c * NL, NL, FQ + (FG + c * DIM + jd) * NQF, NQF,
                                                d0, d1, d2, N1, N1, N12);
                             }
                             const T *p0 = ax == 0 ? Lrow : Lp, *p1 = ax == 1 ? Lrow : Lp, *p2 = ax == 2 ? Lrow : Lp;
-                            FACE_SWEEP(1, xpf + a * NPF, NPF, FQ + FP * NQF, NQF, p0, p1, p2, RP1, RP1, RP12);
+                            FACE_SWEEP(1, xpf, NPF, FQ + FP * NQF, NQF, p0, p1, p2, RP1, RP1, RP12);
                         }
                         // penalty length: |K|/|F| over the squared velocity degree
                         const T hf = hF[fid] / T((R + 1) * (R + 1));
@@ -713,16 +1076,12 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
             }
         }
 
-        // ---- write results ---------------------------------------------------------
+        // ---- add to the volume results -----------------------------------------------
         T *Ec = E + ((long long)cell * nt + a) * DIM * NL;
-        for (int e = tid; e < DIM * NL; e += NTH) Ec[e] = ys[e];
+        for (int e = tid; e < DIM * NL; e += NTH) Ec[e] += ys[e];
         for (int e = tid; e < NPM; e += NTH) {
             const long long gi = pbase + a * A.Np1 + (long long)cell * NPM + e;
-            T val = ypf[pmode_full<DIM, R>(e)];
-            if constexpr (MODE == Mode::Res) {
-                if (A.rhs) val -= A.rhs[gi];
-            }
-            y[gi] = val;
+            y[gi] += ypf[pmode_full<DIM, R>(e)];
         }
         __syncthreads();
     }
@@ -781,12 +1140,34 @@ __global__ void gather_kernel(GatherArgs<T> G)
 // launchers
 // ---------------------------------------------------------------------------
 template <int DIM, int R, int NQ, typename T, Mode MODE>
-static hipError_t launch_one(const CellArgs<T> &a, int nvec, hipStream_t s)
+static hipError_t launch_face(const CellArgs<T> &a, int nvec, hipStream_t s)
 {
     constexpr int NTH = DIM == 2 ? 64 : 128;
+    if (a.nbcell <= 0) return hipSuccess;
     TableLayout lay;
     lay.init(R, NQ);
-    size_t bytes = (size_t)lds_words<DIM, R, NQ, T>(a.nt, lay.total) * sizeof(T);
+    size_t bytes = (size_t)face_lds_words<DIM, R, NQ, T>(lay.total) * sizeof(T);
+    auto kern = face_kernel<DIM, R, NQ, NTH, T, MODE>;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    static size_t attr_bytes = 0;
+    if (bytes > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        attr_bytes = bytes;
+    }
+    dim3 grid(a.nbcell, nvec);
+    hipLaunchKernelGGL(kern, grid, dim3(NTH), bytes, s, a);
+    return hipGetLastError();
+}
+
+template <int DIM, int R, int NQ, typename T, Mode MODE>
+static hipError_t launch_one(const CellArgs<T> &a, int nvec, hipStream_t s)
+{
+    constexpr int NTH = DIM == 2 ? 64 : 256;
+    TableLayout lay;
+    lay.init(R, NQ);
+    size_t bytes = (size_t)lds_words<DIM, R, NQ, T, MODE>(a.nt, lay.total) * sizeof(T);
     auto kern = cell_kernel<DIM, R, NQ, NTH, T, MODE>;
     static std::mutex mu;
     std::lock_guard<std::mutex> lk(mu);
@@ -806,7 +1187,10 @@ static hipError_t launch_one(const CellArgs<T> &a, int nvec, hipStream_t s)
     }
     dim3 grid(a.ncell, nvec);
     hipLaunchKernelGGL(kern, grid, dim3(NTH), bytes, s, a);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if constexpr (MODE != Mode::Mass) return launch_face<DIM, R, NQ, T, MODE>(a, nvec, s);
+    return hipSuccess;
 }
 
 template <int DIM, int R, typename T, Mode MODE>

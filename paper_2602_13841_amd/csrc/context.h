@@ -153,6 +153,8 @@ struct Level {
     TableLayout lay{};
     std::vector<double> vert_host;   // vertices (if mapped)
     DevBuf vert, tab64, tab32, E64, E32;
+    DevBuf bcells;                   // cells with a face on the domain boundary
+    int nbcell = 0;
     Timers *timers = nullptr;
 
     void init(const stmg_problem &p, int k_, int r_, int nx, int ny, int nz, int nq_,

@@ -2,6 +2,7 @@
 #include "context.h"
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 
 namespace stmg {
@@ -46,6 +47,19 @@ void Level::init(const stmg_problem &p, int k_, int r_, int nx, int ny, int nz, 
     tab32.alloc(tbf.size() * sizeof(float));
     STMG_HIP(hipMemcpy(tab64.p, tb.data(), tb.size() * sizeof(double), hipMemcpyHostToDevice));
     STMG_HIP(hipMemcpy(tab32.p, tbf.data(), tbf.size() * sizeof(float), hipMemcpyHostToDevice));
+    {
+        std::vector<int> bc;
+        for (long long c = 0; c < ncell; ++c) {
+            const int cc[3] = {(int)(c % n[0]), (int)((c / n[0]) % n[1]), (int)(c / ((long long)n[0] * n[1]))};
+            bool b = false;
+            for (int a = 0; a < dim; ++a) b = b || cc[a] == 0 || cc[a] == n[a] - 1;
+            if (b) bc.push_back((int)c);
+        }
+        nbcell = (int)bc.size();
+        bcells.alloc(std::max<size_t>(bc.size(), 1) * sizeof(int));
+        if (!bc.empty())
+            STMG_HIP(hipMemcpy(bcells.p, bc.data(), bc.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     mapped = !verts.empty();
     vert_host = verts;
     if (mapped) {
@@ -70,6 +84,8 @@ template <typename T> CellArgs<T> Level::cell_args() const
     a.vert = mapped ? vert.as<double>() : nullptr;
     a.mapped = mapped ? 1 : 0;
     a.dmask = dmask;
+    a.bcells = bcells.as<int>();
+    a.nbcell = nbcell;
     a.nu = (T)nu;
     a.g1 = (T)g1;
     a.g2 = (T)g2;

@@ -105,6 +105,8 @@ struct CellArgs {
     T w[MAX_NT];
     T phi0[MAX_NT];
     long long xstride, ystride, sstride;   // batch strides (vectors along grid.y)
+    const int *bcells;       // cells with a face on the domain boundary
+    int nbcell;
 };
 
 template <typename T>
