@@ -181,316 +181,296 @@ template <typename T> __device__ __forceinline__ T dominus(T y)
 }
 
 // ---------------------------------------------------------------------------
-// Register-pencil tensor contractions for the volume pass.  A stage treats
-// all fields of two groups (group A: NFA fields with nodal extent IA and 1D
-// matrix MA; group B: NFB fields, IB, MB; matrices NQ x I row-major) at once;
-// a work item is (field, pencil), with the loop over the slowest axis kept
-// in registers.  Reads along the contracted axis are shared by the lanes of
-// a pencil row (LDS broadcast).  Layouts are x fastest; every stage ends
-// with a barrier.
+// Register-pencil tensor contractions of the volume pass.  A stage treats all
+// fields of two groups at once (group A: NFA fields, nodal extent IA, 1D
+// matrices of group A; group B: NFB fields, IB); a work item is one pencil
+// along the contracted axis: its I inputs go to registers and its NQ outputs
+// are written back (I + NQ LDS accesses per item).  Layouts are x fastest;
+// every stage ends with a barrier.  Matrices are NQ x I row-major.
 // ---------------------------------------------------------------------------
 template <int DIM, int NQ, int NFA, int IA, int NFB, int IB> struct PencilSizes {
-    static constexpr int B1A = DIM == 3 ? NQ * IA * IA : NQ * IA;    // stage-1 output per field
-    static constexpr int B1B = DIM == 3 ? NQ * IB * IB : NQ * IB;
-    static constexpr int B2A = DIM == 3 ? NQ * NQ * IA : 0;          // stage-2 output per field
-    static constexpr int B2B = DIM == 3 ? NQ * NQ * IB : 0;
+    // rows along x of the buffer feeding the x contraction are padded to an
+    // odd length (conflict-free strided row reads)
+    static constexpr int RA = IA | 1, RB = IB | 1;
+    static constexpr int B1A = DIM == 3 ? NQ * IA * IA : NQ * RA;    // after the first contraction
+    static constexpr int B1B = DIM == 3 ? NQ * IB * IB : NQ * RB;
+    static constexpr int B2A = DIM == 3 ? NQ * NQ * RA : 0;          // after the second (3D)
+    static constexpr int B2B = DIM == 3 ? NQ * NQ * RB : 0;
     static constexpr int BUF1 = NFA * B1A + NFB * B1B;
-    static constexpr int BUF2 = NFA * B2A + NFB * B2B;
+    static constexpr int BUF2 = (NFA * B2A + NFB * B2B) > 1 ? NFA * B2A + NFB * B2B : 1;
 };
 
-// nodal -> quadrature points: inA [NFA][IA^DIM], inB [NFB][IB^DIM];
-// outA field f at QA + f * NQ^DIM, outB field f at QB + f * NQ^DIM
-template <int DIM, int NQ, int NFA, int IA, int NFB, int IB, int NTH, typename T>
+// contract one pencil: out[o * os] = sum_i M[o * I + i] in[i * is], o < NQ
+template <int I, int NQ, typename T, typename MP>
+__device__ __forceinline__ void pencil_apply(const T *__restrict__ in, int is, T *__restrict__ out, int os, MP M)
+{
+    T u[I];
+#pragma unroll
+    for (int i = 0; i < I; ++i) u[i] = in[i * is];
+#pragma unroll
+    for (int o = 0; o < NQ; ++o) {
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < I; ++i) s += M[o * I + i] * u[i];
+        out[o * os] = s;
+    }
+}
+
+// transposed: out[i * os] = sum_o M[o * I + i] in[o * is], i < I
+template <int I, int NQ, typename T, typename MP>
+__device__ __forceinline__ void pencil_apply_t(const T *__restrict__ in, int is, T *__restrict__ out, int os, MP M)
+{
+    T u[NQ];
+#pragma unroll
+    for (int o = 0; o < NQ; ++o) u[o] = in[o * is];
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+        T s = 0;
+#pragma unroll
+        for (int o = 0; o < NQ; ++o) s += M[o * I + i] * u[o];
+        out[i * os] = s;
+    }
+}
+
+// nodes -> Gauss points.  inA [NFA][IA^DIM], inB [NFB][IB^DIM]; field f of
+// group A to QA + f * NQ^DIM, of group B to QB + f * NQ^DIM.  For the first
+// NGRAD fields of group A also the reference derivative along x (nodal
+// derivative table DA, NQ x IA) to GX + f * DIM * NQ^DIM.
+template <int DIM, int NQ, int NFA, int IA, int NFB, int IB, int NGRAD, int NTH, typename T, typename MP>
 __device__ __forceinline__ void pencil_fwd(const T *__restrict__ inA, const T *__restrict__ inB, T *__restrict__ QA,
-                                           T *__restrict__ QB, T *__restrict__ buf1, T *__restrict__ buf2,
-                                           const T *__restrict__ MA, const T *__restrict__ MB)
+                                           T *__restrict__ QB, T *__restrict__ GX, T *__restrict__ buf1,
+                                           T *__restrict__ buf2, MP MA, MP DA, MP MB)
 {
     using PS = PencilSizes<DIM, NQ, NFA, IA, NFB, IB>;
     constexpr int NQV = DIM == 3 ? NQ * NQ * NQ : NQ * NQ;
     const int tid = threadIdx.x;
     if constexpr (DIM == 3) {
-        // stage 1: contract z; item (f, j, i), column over k in registers
+        // z: item (f, j, i)
         constexpr int NA = NFA * IA * IA, NB = NFB * IB * IB;
         for (int w = tid; w < NA + NB; w += NTH) {
-            const bool ga = w < NA;
-            const int ww = ga ? w : w - NA;
-            const int I = ga ? IA : IB;
-            const int f = ww / (I * I), ji = ww - f * I * I;
-            const T *src = (ga ? inA + f * IA * IA * IA : inB + f * IB * IB * IB) + ji;
-            T *dst = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + ji;
-            const T *M = ga ? MA : MB;
-            T u[IA > IB ? IA : IB];
-#pragma unroll
-            for (int k = 0; k < (IA > IB ? IA : IB); ++k) u[k] = k < I ? src[k * I * I] : T(0);
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                T s = 0;
-#pragma unroll
-                for (int k = 0; k < (IA > IB ? IA : IB); ++k)
-                    if (k < I) s += M[q * I + k] * u[k];
-                dst[q * I * I] = s;
+            if (w < NA) {
+                const int f = w / (IA * IA), ji = w - f * IA * IA;
+                pencil_apply<IA, NQ>(inA + f * IA * IA * IA + ji, IA * IA, buf1 + f * PS::B1A + ji, IA * IA, MA);
+            } else {
+                const int ww = w - NA, f = ww / (IB * IB), ji = ww - f * IB * IB;
+                pencil_apply<IB, NQ>(inB + f * IB * IB * IB + ji, IB * IB, buf1 + NFA * PS::B1A + f * PS::B1B + ji,
+                                     IB * IB, MB);
             }
         }
         __syncthreads();
-        // stage 2: contract y; item (f, qy, i), loop over qz
+        // y: item (f, qz, i)
         constexpr int NA2 = NFA * NQ * IA, NB2 = NFB * NQ * IB;
         for (int w = tid; w < NA2 + NB2; w += NTH) {
-            const bool ga = w < NA2;
-            const int ww = ga ? w : w - NA2;
-            const int I = ga ? IA : IB;
-            const int f = ww / (NQ * I), rr = ww - f * NQ * I, qy = rr / I, i = rr - qy * I;
-            const T *src = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + i;
-            T *dst = (ga ? buf2 + f * PS::B2A : buf2 + NFA * PS::B2A + f * PS::B2B) + qy * I + i;
-            const T *m = (ga ? MA : MB) + qy * I;
-            T mr[IA > IB ? IA : IB];
-#pragma unroll
-            for (int j = 0; j < (IA > IB ? IA : IB); ++j) mr[j] = j < I ? m[j] : T(0);
-#pragma unroll 1
-            for (int qz = 0; qz < NQ; ++qz) {
-                T s = 0;
-#pragma unroll
-                for (int j = 0; j < (IA > IB ? IA : IB); ++j)
-                    if (j < I) s += mr[j] * src[(qz * I + j) * I];
-                dst[qz * NQ * I] = s;
+            if (w < NA2) {
+                const int f = w / (NQ * IA), rr = w - f * NQ * IA, qz = rr / IA, i = rr - qz * IA;
+                pencil_apply<IA, NQ>(buf1 + f * PS::B1A + qz * IA * IA + i, IA,
+                                     buf2 + f * PS::B2A + qz * NQ * PS::RA + i, PS::RA, MA);
+            } else {
+                const int ww = w - NA2, f = ww / (NQ * IB), rr = ww - f * NQ * IB, qz = rr / IB, i = rr - qz * IB;
+                pencil_apply<IB, NQ>(buf1 + NFA * PS::B1A + f * PS::B1B + qz * IB * IB + i, IB,
+                                     buf2 + NFA * PS::B2A + f * PS::B2B + qz * NQ * PS::RB + i, PS::RB, MB);
             }
         }
         __syncthreads();
-        // stage 3: contract x; item (f, qy, qx), loop over qz
+        // x: item (f, qz, qy)
         constexpr int NA3 = NFA * NQ * NQ, NB3 = NFB * NQ * NQ;
         for (int w = tid; w < NA3 + NB3; w += NTH) {
-            const bool ga = w < NA3;
-            const int ww = ga ? w : w - NA3;
-            const int I = ga ? IA : IB;
-            const int f = ww / (NQ * NQ), rr = ww - f * NQ * NQ, qy = rr / NQ, qx = rr - qy * NQ;
-            const T *src = (ga ? buf2 + f * PS::B2A : buf2 + NFA * PS::B2A + f * PS::B2B) + qy * I;
-            T *dst = (ga ? QA : QB) + f * NQV + qy * NQ + qx;
-            const T *m = (ga ? MA : MB) + qx * I;
-            T mr[IA > IB ? IA : IB];
-#pragma unroll
-            for (int i = 0; i < (IA > IB ? IA : IB); ++i) mr[i] = i < I ? m[i] : T(0);
-#pragma unroll 1
-            for (int qz = 0; qz < NQ; ++qz) {
-                T s = 0;
-#pragma unroll
-                for (int i = 0; i < (IA > IB ? IA : IB); ++i)
-                    if (i < I) s += mr[i] * src[qz * NQ * I + i];
-                dst[qz * NQ * NQ] = s;
+            if (w < NA3) {
+                const int f = w / (NQ * NQ), rr = w - f * NQ * NQ;
+                const T *src = buf2 + f * PS::B2A + rr * PS::RA;
+                pencil_apply<IA, NQ>(src, 1, QA + f * NQV + rr * NQ, 1, MA);
+                if (f < NGRAD) pencil_apply<IA, NQ>(src, 1, GX + f * DIM * NQV + rr * NQ, 1, DA);
+            } else {
+                const int ww = w - NA3, f = ww / (NQ * NQ), rr = ww - f * NQ * NQ;
+                pencil_apply<IB, NQ>(buf2 + NFA * PS::B2A + f * PS::B2B + rr * PS::RB, 1, QB + f * NQV + rr * NQ, 1,
+                                     MB);
             }
         }
         __syncthreads();
     } else {
-        // stage 1: contract y; item (f, i), column over j in registers
+        // y: item (f, i)
         constexpr int NA = NFA * IA, NB = NFB * IB;
         for (int w = tid; w < NA + NB; w += NTH) {
-            const bool ga = w < NA;
-            const int ww = ga ? w : w - NA;
-            const int I = ga ? IA : IB;
-            const int f = ww / I, i = ww - f * I;
-            const T *src = (ga ? inA + f * IA * IA : inB + f * IB * IB) + i;
-            T *dst = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + i;
-            const T *M = ga ? MA : MB;
-            T u[IA > IB ? IA : IB];
-#pragma unroll
-            for (int j = 0; j < (IA > IB ? IA : IB); ++j) u[j] = j < I ? src[j * I] : T(0);
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                T s = 0;
-#pragma unroll
-                for (int j = 0; j < (IA > IB ? IA : IB); ++j)
-                    if (j < I) s += M[q * I + j] * u[j];
-                dst[q * I] = s;
+            if (w < NA) {
+                const int f = w / IA, i = w - f * IA;
+                pencil_apply<IA, NQ>(inA + f * IA * IA + i, IA, buf1 + f * PS::B1A + i, PS::RA, MA);
+            } else {
+                const int ww = w - NA, f = ww / IB, i = ww - f * IB;
+                pencil_apply<IB, NQ>(inB + f * IB * IB + i, IB, buf1 + NFA * PS::B1A + f * PS::B1B + i, PS::RB, MB);
             }
         }
         __syncthreads();
-        // stage 2: contract x; item (f, qx), loop over qy
+        // x: item (f, qy)
         constexpr int NA2 = NFA * NQ, NB2 = NFB * NQ;
         for (int w = tid; w < NA2 + NB2; w += NTH) {
-            const bool ga = w < NA2;
-            const int ww = ga ? w : w - NA2;
-            const int I = ga ? IA : IB;
-            const int f = ww / NQ, qx = ww - f * NQ;
-            const T *src = ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B;
-            T *dst = (ga ? QA : QB) + f * NQV + qx;
-            const T *m = (ga ? MA : MB) + qx * I;
-            T mr[IA > IB ? IA : IB];
-#pragma unroll
-            for (int i = 0; i < (IA > IB ? IA : IB); ++i) mr[i] = i < I ? m[i] : T(0);
-#pragma unroll 1
-            for (int qy = 0; qy < NQ; ++qy) {
-                T s = 0;
-#pragma unroll
-                for (int i = 0; i < (IA > IB ? IA : IB); ++i)
-                    if (i < I) s += mr[i] * src[qy * I + i];
-                dst[qy * NQ] = s;
+            if (w < NA2) {
+                const int f = w / NQ, qy = w - f * NQ;
+                const T *src = buf1 + f * PS::B1A + qy * PS::RA;
+                pencil_apply<IA, NQ>(src, 1, QA + f * NQV + qy * NQ, 1, MA);
+                if (f < NGRAD) pencil_apply<IA, NQ>(src, 1, GX + f * DIM * NQV + qy * NQ, 1, DA);
+            } else {
+                const int ww = w - NA2, f = ww / NQ, qy = ww - f * NQ;
+                pencil_apply<IB, NQ>(buf1 + NFA * PS::B1A + f * PS::B1B + qy * PS::RB, 1, QB + f * NQV + qy * NQ, 1,
+                                     MB);
             }
         }
         __syncthreads();
     }
 }
 
-// quadrature points -> nodes (transposed interpolation): field f of group A at
-// QA + f * NQ^DIM into outA [NFA][IA^DIM], group B likewise
-template <int DIM, int NQ, int NFA, int IA, int NFB, int IB, int NTH, typename T>
-__device__ __forceinline__ void pencil_bwd(const T *__restrict__ QA, const T *__restrict__ QB, T *__restrict__ outA,
-                                           T *__restrict__ outB, T *__restrict__ buf1, T *__restrict__ buf2,
-                                           const T *__restrict__ MA, const T *__restrict__ MB)
+// reference derivatives along y (and z) of NF fields at the Gauss points by
+// collocation (Dq, NQ x NQ): field f at U + f * NQ^DIM, derivative along axis
+// d (1 <= d < DIM) to G + (f * DIM + d) * NQ^DIM
+template <int DIM, int NQ, int NF, int NTH, typename T, typename MP>
+__device__ __forceinline__ void colloc_fwd(const T *__restrict__ U, T *__restrict__ G, MP Dq)
+{
+    constexpr int NQV = DIM == 3 ? NQ * NQ * NQ : NQ * NQ;
+    constexpr int NP = DIM == 3 ? NQ * NQ : NQ;      // pencils per field and axis
+    const int tid = threadIdx.x;
+    for (int w = tid; w < NF * (DIM - 1) * NP; w += NTH) {
+        const int f = w / ((DIM - 1) * NP), rr = w - f * (DIM - 1) * NP, d = 1 + rr / NP, p = rr - (d - 1) * NP;
+        int base, st;
+        if (d == 1) {                 // pencil along y through (qz, qx), p = qz * NQ + qx
+            const int qz = DIM == 3 ? p / NQ : 0, qxx = DIM == 3 ? p - qz * NQ : p;
+            base = qz * NQ * NQ + qxx;
+            st = NQ;
+        } else {                      // pencil along z through (qy, qx), p = qy * NQ + qx
+            base = p;
+            st = NQ * NQ;
+        }
+        pencil_apply<NQ, NQ>(U + f * NQV + base, st, G + (f * DIM + d) * NQV + base, st, Dq);
+    }
+    __syncthreads();
+}
+
+// transposed collocation of the test-function gradients along z and y, in
+// place: Y_c += Dq_d^T F[c][d] for d = DIM-1 .. 1 (F at F0 + (c * DIM + d) *
+// NQ^DIM, Y_c at Y0 + c * NQ^DIM); the x part is applied by pencil_bwd with
+// the nodal derivative table
+template <int DIM, int NQ, int NTH, typename T, typename MP>
+__device__ __forceinline__ void colloc_bwd(const T *__restrict__ F0, T *__restrict__ Y0, MP Dq)
+{
+    constexpr int NQV = DIM == 3 ? NQ * NQ * NQ : NQ * NQ;
+    constexpr int NP = DIM == 3 ? NQ * NQ : NQ;
+    const int tid = threadIdx.x;
+#pragma unroll 1
+    for (int d = DIM - 1; d >= 1; --d) {
+        for (int w = tid; w < DIM * NP; w += NTH) {
+            const int c = w / NP, p = w - c * NP;
+            int base, st;
+            if (d == 1) {
+                const int qz = DIM == 3 ? p / NQ : 0, qxx = DIM == 3 ? p - qz * NQ : p;
+                base = qz * NQ * NQ + qxx;
+                st = NQ;
+            } else {
+                base = p;
+                st = NQ * NQ;
+            }
+            const T *f = F0 + (c * DIM + d) * NQV + base;
+            T *y = Y0 + c * NQV + base;
+            T u[NQ];
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) u[m] = f[m * st];
+#pragma unroll
+            for (int o = 0; o < NQ; ++o) {
+                T s = y[o * st];
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) s += Dq[m * NQ + o] * u[m];
+                y[o * st] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Gauss points -> nodes (transposed interpolation) of group A (NFA fields at
+// QA + f * NQ^DIM, with the x part of the test gradient: FX + f * NQ^DIM
+// contracted with the transposed nodal derivative table DA when NXG > 0) and
+// group B; results to outA [NFA][IA^DIM], outB [NFB][IB^DIM]
+template <int DIM, int NQ, int NFA, int IA, int NFB, int IB, bool XGRAD, int NTH, typename T, typename MP>
+__device__ __forceinline__ void pencil_bwd(const T *__restrict__ QA, const T *__restrict__ FX, int fx_stride,
+                                           const T *__restrict__ QB, T *__restrict__ outA, T *__restrict__ outB,
+                                           T *__restrict__ buf1, T *__restrict__ buf2, MP MA, MP DA, MP MB)
 {
     using PS = PencilSizes<DIM, NQ, NFA, IA, NFB, IB>;
     constexpr int NQV = DIM == 3 ? NQ * NQ * NQ : NQ * NQ;
-    constexpr int IM = IA > IB ? IA : IB;
     const int tid = threadIdx.x;
-    if constexpr (DIM == 3) {
-        // stage 3^T: contract qx -> i; item (f, qy, i), loop over qz
-        constexpr int NA = NFA * NQ * IA, NB = NFB * NQ * IB;
-        for (int w = tid; w < NA + NB; w += NTH) {
-            const bool ga = w < NA;
-            const int ww = ga ? w : w - NA;
-            const int I = ga ? IA : IB;
-            const int f = ww / (NQ * I), rr = ww - f * NQ * I, qy = rr / I, i = rr - qy * I;
-            const T *src = (ga ? QA : QB) + f * NQV + qy * NQ;
-            T *dst = (ga ? buf2 + f * PS::B2A : buf2 + NFA * PS::B2A + f * PS::B2B) + qy * I + i;
-            const T *M = ga ? MA : MB;
-            T mc[NQ];
+    // x: item (f, row) with the row over qx; rows = NQ^(DIM-1)
+    constexpr int NR = DIM == 3 ? NQ * NQ : NQ;
+    constexpr int NA = NFA * NR, NB = NFB * NR;
+    T *dstA = DIM == 3 ? buf2 : buf1;
+    constexpr int SA = DIM == 3 ? PS::B2A : PS::B1A, SB = DIM == 3 ? PS::B2B : PS::B1B;
+    for (int w = tid; w < NA + NB; w += NTH) {
+        if (w < NA) {
+            const int f = w / NR, rr = w - f * NR;
+            const T *y = QA + f * NQV + rr * NQ;
+            T u[NQ], g[NQ];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) mc[q] = M[q * I + i];
-#pragma unroll 1
-            for (int qz = 0; qz < NQ; ++qz) {
+            for (int o = 0; o < NQ; ++o) u[o] = y[o];
+            if constexpr (XGRAD) {
+                const T *fx = FX + f * fx_stride + rr * NQ;
+#pragma unroll
+                for (int o = 0; o < NQ; ++o) g[o] = fx[o];
+            }
+            T *out = dstA + f * SA + rr * PS::RA;
+#pragma unroll
+            for (int i = 0; i < IA; ++i) {
                 T s = 0;
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) s += mc[q] * src[qz * NQ * NQ + q];
-                dst[qz * NQ * I] = s;
+                for (int o = 0; o < NQ; ++o) {
+                    s += MA[o * IA + i] * u[o];
+                    if constexpr (XGRAD) s += DA[o * IA + i] * g[o];
+                }
+                out[i] = s;
             }
-        }
-        __syncthreads();
-        // stage 2^T: contract qy -> j; item (f, j, i), loop over qz
-        constexpr int NA2 = NFA * IA * IA, NB2 = NFB * IB * IB;
-        for (int w = tid; w < NA2 + NB2; w += NTH) {
-            const bool ga = w < NA2;
-            const int ww = ga ? w : w - NA2;
-            const int I = ga ? IA : IB;
-            const int f = ww / (I * I), rr = ww - f * I * I, j = rr / I, i = rr - j * I;
-            const T *src = (ga ? buf2 + f * PS::B2A : buf2 + NFA * PS::B2A + f * PS::B2B) + i;
-            T *dst = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + j * I + i;
-            const T *M = ga ? MA : MB;
-            T mc[NQ];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) mc[q] = M[q * I + j];
-#pragma unroll 1
-            for (int qz = 0; qz < NQ; ++qz) {
-                T s = 0;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) s += mc[q] * src[(qz * NQ + q) * I];
-                dst[qz * I * I] = s;
-            }
-        }
-        __syncthreads();
-        // stage 1^T: contract qz -> k; item (f, j, i), column over qz in registers
-        for (int w = tid; w < NA2 + NB2; w += NTH) {
-            const bool ga = w < NA2;
-            const int ww = ga ? w : w - NA2;
-            const int I = ga ? IA : IB;
-            const int f = ww / (I * I), ji = ww - f * I * I;
-            const T *src = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + ji;
-            T *dst = (ga ? outA + f * IA * IA * IA : outB + f * IB * IB * IB) + ji;
-            const T *M = ga ? MA : MB;
-            T col[NQ];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) col[q] = src[q * I * I];
-#pragma unroll
-            for (int k = 0; k < IM; ++k) {
-                if (k >= I) break;
-                T s = 0;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) s += M[q * I + k] * col[q];
-                dst[k * I * I] = s;
-            }
-        }
-        __syncthreads();
-    } else {
-        // stage 2^T: contract qx -> i; item (f, i), loop over qy
-        constexpr int NA = NFA * IA, NB = NFB * IB;
-        for (int w = tid; w < NA + NB; w += NTH) {
-            const bool ga = w < NA;
-            const int ww = ga ? w : w - NA;
-            const int I = ga ? IA : IB;
-            const int f = ww / I, i = ww - f * I;
-            const T *src = (ga ? QA : QB) + f * NQV;
-            T *dst = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + i;
-            const T *M = ga ? MA : MB;
-            T mc[NQ];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) mc[q] = M[q * I + i];
-#pragma unroll 1
-            for (int qy = 0; qy < NQ; ++qy) {
-                T s = 0;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) s += mc[q] * src[qy * NQ + q];
-                dst[qy * I] = s;
-            }
-        }
-        __syncthreads();
-        // stage 1^T: contract qy -> j; item (f, i), column over qy in registers
-        for (int w = tid; w < NA + NB; w += NTH) {
-            const bool ga = w < NA;
-            const int ww = ga ? w : w - NA;
-            const int I = ga ? IA : IB;
-            const int f = ww / I, i = ww - f * I;
-            const T *src = (ga ? buf1 + f * PS::B1A : buf1 + NFA * PS::B1A + f * PS::B1B) + i;
-            T *dst = (ga ? outA + f * IA * IA : outB + f * IB * IB) + i;
-            const T *M = ga ? MA : MB;
-            T col[NQ];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) col[q] = src[q * I];
-#pragma unroll
-            for (int j = 0; j < IM; ++j) {
-                if (j >= I) break;
-                T s = 0;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) s += M[q * I + j] * col[q];
-                dst[j * I] = s;
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// transposed collocation in place: Y_c = val_c + sum_j Dq_j^T F[c][j] for the
-// DIM velocity components; F[c][j] at Q + (c * DIM + j) * NQV, val_c at
-// Q + (DIM * DIM + c) * NQV (overwritten by Y_c).  Item (c, pencil) with the
-// slowest-axis column in registers; Dq is NQ x NQ row-major.
-template <int DIM, int NQ, int NTH, typename T>
-__device__ __forceinline__ void colloc_bwd(T *__restrict__ Q, const T *__restrict__ Dq)
-{
-    constexpr int NQV = DIM == 3 ? NQ * NQ * NQ : NQ * NQ;
-    constexpr int NP = DIM == 3 ? NQ * NQ : NQ;       // pencils per field
-    constexpr int SL = DIM == 3 ? NQ * NQ : NQ;       // stride of the slowest axis
-    const int tid = threadIdx.x;
-    for (int w = tid; w < DIM * NP; w += NTH) {
-        const int c = w / NP, p = w - c * NP;
-        const T *Fs = Q + (c * DIM + (DIM - 1)) * NQV + p;    // slowest-axis flux column
-        T col[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) col[q] = Fs[q * SL];
-        T *Y = Q + (DIM * DIM + c) * NQV + p;
-        const int px = DIM == 3 ? p % NQ : p, py = DIM == 3 ? p / NQ : 0;
-#pragma unroll 1
-        for (int qs = 0; qs < NQ; ++qs) {
-            T s = Y[qs * SL];
-#pragma unroll
-            for (int m = 0; m < NQ; ++m) s += Dq[m * NQ + qs] * col[m];
-            // x direction: F[c][0] along the row through (qs, py)
-            const T *Fx = Q + (c * DIM + 0) * NQV + qs * SL + (DIM == 3 ? py * NQ : 0);
-#pragma unroll
-            for (int m = 0; m < NQ; ++m) s += Dq[m * NQ + px] * Fx[m];
-            if constexpr (DIM == 3) {
-                const T *Fy = Q + (c * DIM + 1) * NQV + qs * SL + px;
-#pragma unroll
-                for (int m = 0; m < NQ; ++m) s += Dq[m * NQ + py] * Fy[m * NQ];
-            }
-            Y[qs * SL] = s;
+        } else {
+            const int ww = w - NA, f = ww / NR, rr = ww - f * NR;
+            pencil_apply_t<IB, NQ>(QB + f * NQV + rr * NQ, 1, dstA + NFA * SA + f * SB + rr * PS::RB, 1, MB);
         }
     }
     __syncthreads();
+    if constexpr (DIM == 3) {
+        // y: item (f, qz, i), buf2 [f][qz][qy][i] -> buf1 [f][qz][j][i]
+        constexpr int NA2 = NFA * NQ * IA, NB2 = NFB * NQ * IB;
+        for (int w = tid; w < NA2 + NB2; w += NTH) {
+            if (w < NA2) {
+                const int f = w / (NQ * IA), rr = w - f * NQ * IA, qz = rr / IA, i = rr - qz * IA;
+                pencil_apply_t<IA, NQ>(buf2 + f * PS::B2A + qz * NQ * PS::RA + i, PS::RA,
+                                       buf1 + f * PS::B1A + qz * IA * IA + i, IA, MA);
+            } else {
+                const int ww = w - NA2, f = ww / (NQ * IB), rr = ww - f * NQ * IB, qz = rr / IB, i = rr - qz * IB;
+                pencil_apply_t<IB, NQ>(buf2 + NFA * PS::B2A + f * PS::B2B + qz * NQ * PS::RB + i, PS::RB,
+                                       buf1 + NFA * PS::B1A + f * PS::B1B + qz * IB * IB + i, IB, MB);
+            }
+        }
+        __syncthreads();
+        // z: item (f, j, i), buf1 [f][qz][j][i] -> out [f][k][j][i]
+        constexpr int NA3 = NFA * IA * IA, NB3 = NFB * IB * IB;
+        for (int w = tid; w < NA3 + NB3; w += NTH) {
+            if (w < NA3) {
+                const int f = w / (IA * IA), ji = w - f * IA * IA;
+                pencil_apply_t<IA, NQ>(buf1 + f * PS::B1A + ji, IA * IA, outA + f * IA * IA * IA + ji, IA * IA, MA);
+            } else {
+                const int ww = w - NA3, f = ww / (IB * IB), ji = ww - f * IB * IB;
+                pencil_apply_t<IB, NQ>(buf1 + NFA * PS::B1A + f * PS::B1B + ji, IB * IB, outB + f * IB * IB * IB + ji,
+                                       IB * IB, MB);
+            }
+        }
+        __syncthreads();
+    } else {
+        // y: item (f, i), buf1 [f][qy][i] -> out [f][j][i]
+        constexpr int NA2 = NFA * IA, NB2 = NFB * IB;
+        for (int w = tid; w < NA2 + NB2; w += NTH) {
+            if (w < NA2) {
+                const int f = w / IA, i = w - f * IA;
+                pencil_apply_t<IA, NQ>(buf1 + f * PS::B1A + i, PS::RA, outA + f * IA * IA + i, IA, MA);
+            } else {
+                const int ww = w - NA2, f = ww / IB, i = ww - f * IB;
+                pencil_apply_t<IB, NQ>(buf1 + NFA * PS::B1A + f * PS::B1B + i, PS::RB, outB + f * IB * IB + i, IB, MB);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // LDS layout (in units of T) of the cell kernel
@@ -499,13 +479,12 @@ template <int DIM, int R, int NQ, typename T, Mode MODE> struct Lds {
     static constexpr int NQV = ipow(NQ, DIM);
     // nodal input fields of the volume pass: xhat, state (Jac), mixed field (not Mass)
     static constexpr int NFA = MODE == Mode::Jac ? 3 * DIM : (MODE == Mode::Res ? 2 * DIM : DIM);
-    // quadrature-point record: inputs NFA + 1 (pressure) fields, then the
-    // outputs F (DIM^2), value coefficients (DIM), pressure coefficient in
-    // fields of their own (written while neighbours still read the inputs)
-    static constexpr int NFIELD_V = DIM * DIM + DIM + 1;
-    static constexpr int NFIELD_IN = NFA + 1;
-    static constexpr int OUT0 = NFIELD_IN;                    // first output field
-    static constexpr int Q_SIZE = (NFIELD_IN + NFIELD_V) * NQV;
+    // quadrature-point record: NFA velocity-type fields, pressure, reference
+    // gradients of xhat [c][d]; the physics overwrites them at its own point
+    // (F into the gradients, value coefficients into xhat, the pressure
+    // coefficient into the pressure)
+    static constexpr int DQ0 = NFA + 1;                       // reference gradients of xhat
+    static constexpr int Q_SIZE = (NFA + 1 + (MODE == Mode::Mass ? 0 : DIM * DIM)) * NQV;
     // temporaries of the pencil stages
     using PS = PencilSizes<DIM, NQ, NFA, Z::N1, 1, Z::RP1>;
     static constexpr int TMP1 = PS::BUF1;
@@ -607,10 +586,11 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
 
     for (int i = tid; i < lay.total; i += NTH) tab[i] = A.tab[i];
 
-    const T *S = tab + lay.S, *St = tab + lay.St, *D = tab + lay.D, *Dt = tab + lay.Dt;
-    const T *Dq = tab + lay.Dq, *Dqt = tab + lay.Dqt, *Se = tab + lay.Se, *De = tab + lay.De;
-    const T *Lp = tab + lay.L, *Lpt = tab + lay.Lt, *Lpe = tab + lay.Le, *qw = tab + lay.qw;
-    const T *qx = tab + lay.qx;
+    // 1D matrices of the sweeps: uniform across the workgroup, read through the
+    // scalar (read-only) path from global memory; point tables from LDS
+    using CP = const __attribute__((address_space(4))) T *;   // constant for the whole kernel
+    const CP S = (CP)(A.tab + lay.S), D = (CP)(A.tab + lay.D), Dq = (CP)(A.tab + lay.Dq), Lp = (CP)(A.tab + lay.L);
+    const T *qw = tab + lay.qw, *qx = tab + lay.qx;
 
     // ---- cell coordinates and nodal gather ------------------------------------
     const int c0 = cell % A.n0;
@@ -669,17 +649,18 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
         __syncthreads();
 
         // ---- nodes -> Gauss points: Q fields [0, NFA) velocity-type, NFA pressure
-        pencil_fwd<DIM, NQ, NFA, N1, 1, RP1, NTH, T>(cur, xpf + a * NPF, Q, Q + NFA * NQV, t1, t2, S, Lp);
+        constexpr int NG = MODE == Mode::Mass ? 0 : DIM;
+        T *G = Q + LY::DQ0 * NQV;
+        pencil_fwd<DIM, NQ, NFA, N1, 1, RP1, NG, NTH, T>(cur, xpf + a * NPF, Q, Q + NFA * NQV, G, t1, t2, S, D, Lp);
+        if constexpr (MODE != Mode::Mass) colloc_fwd<DIM, NQ, DIM, NTH, T>(Q, G, Dq);
 
-        // ---- quadrature-point physics: outputs straight into their own fields -----
-        T *Qo = Q + LY::OUT0 * NQV;
+        // ---- quadrature-point physics, in place at each point ----------------------
         const T wa = A.w[a];
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
             const int q = tid + j * NTH;
             if (q < NQV) {
                 const int qi[3] = {q % NQ, (q / NQ) % NQ, DIM == 3 ? q / (NQ * NQ) : 0};
-                const int strides[3] = {1, NQ, NQ * NQ};
                 T xi[3] = {0, 0, 0}, Jit[3][3];
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) xi[d] = qx[qi[d]];
@@ -698,21 +679,15 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
                 const T ph = Q[NFA * NQV + q];
                 if constexpr (MODE == Mode::Mass) {
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) Qo[(DIM * DIM + c) * NQV + q] = sc * xh[c];
-                    Qo[(DIM * DIM + DIM) * NQV + q] = sc * ph;
+                    for (int c = 0; c < DIM; ++c) Q[c * NQV + q] = sc * xh[c];
+                    Q[NFA * NQV + q] = sc * ph;
                 } else {
                     T divx = 0;
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) {
                         T gref[3];
 #pragma unroll
-                        for (int jd = 0; jd < DIM; ++jd) {
-                            T s = 0;
-                            const T *src = Q + c * NQV + q - qi[jd] * strides[jd];
-#pragma unroll
-                            for (int m = 0; m < NQ; ++m) s += Dq[qi[jd] * NQ + m] * src[m * strides[jd]];
-                            gref[jd] = s;
-                        }
+                        for (int jd = 0; jd < DIM; ++jd) gref[jd] = G[(c * DIM + jd) * NQV + q];
                         T Fc[3];
 #pragma unroll
                         for (int d = 0; d < DIM; ++d) {
@@ -720,7 +695,7 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
 #pragma unroll
                             for (int jd = 0; jd < DIM; ++jd) g += Jit[d][jd] * gref[jd];
                             if (d == c) divx += g;
-                            // (nu grad x - x (x) v - v (x) x - p I) for the Jacobian; Res: v = x
+                            // nu grad x - x (x) v - v (x) x - p I (Jacobian); Res: v = x, one convective term
                             Fc[d] = A.nu * g - xh[c] * v[d] - (MODE == Mode::Jac ? v[c] * xh[d] : T(0));
                             if (d == c) Fc[d] -= ph;
                         }
@@ -729,20 +704,25 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
                             T s = 0;
 #pragma unroll
                             for (int d = 0; d < DIM; ++d) s += Fc[d] * Jit[d][jd];
-                            Qo[(c * DIM + jd) * NQV + q] = s * sc;
+                            G[(c * DIM + jd) * NQV + q] = s * sc;
                         }
-                        Qo[(DIM * DIM + c) * NQV + q] = jxw * Q[(MIXF + c) * NQV + q];
                     }
-                    Qo[(DIM * DIM + DIM) * NQV + q] = -sc * divx;
+                    T xm[3];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) xm[c] = Q[(MIXF + c) * NQV + q];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) Q[c * NQV + q] = jxw * xm[c];
+                    Q[NFA * NQV + q] = -sc * divx;
                 }
             }
         }
         __syncthreads();
 
-        // ---- transposed collocation (value slots become Y_c), then Gauss points -> nodes
-        if constexpr (MODE != Mode::Mass) colloc_bwd<DIM, NQ, NTH, T>(Qo, Dq);
-        pencil_bwd<DIM, NQ, DIM, N1, 1, RP1, NTH, T>(Qo + DIM * DIM * NQV, Qo + (DIM * DIM + DIM) * NQV, ys, ypf, t1,
-                                                     t2, S, Lp);
+        // ---- transposed collocation along y, z (into the value fields), then Gauss
+        //      points -> nodes with the x part of the test gradient
+        if constexpr (MODE != Mode::Mass) colloc_bwd<DIM, NQ, NTH, T>(G, Q, Dq);
+        pencil_bwd<DIM, NQ, DIM, N1, 1, RP1, MODE != Mode::Mass, NTH, T>(Q, G, DIM * NQV, Q + NFA * NQV, ys, ypf, t1,
+                                                                        t2, S, D, Lp);
 
         // ---- write results ---------------------------------------------------------
         T *Ec = E + ((long long)cell * nt + a) * DIM * NL;
@@ -762,7 +742,7 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
 // ---------------------------------------------------------------------------
 // Boundary-face kernel: the Nitsche and convective boundary terms (eq.
 // def-a-gam-tp, eq. def-b-gam) of the cells on the domain boundary, one
-// workgroup per boundary cell and all time nodes.  Runs after the volume
+// workgroup per boundary cell and time node.  Runs after the volume
 // kernel on the same stream and adds to its results (cell buffer E, pressure
 // rows), so the summation order is fixed.
 // ---------------------------------------------------------------------------
@@ -801,7 +781,8 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
     T *sm = reinterpret_cast<T *>(smem_raw);
 
     const int tid = threadIdx.x;
-    const int cell = A.bcells[blockIdx.x];
+    const int cell = A.bcells[blockIdx.x / A.nt];
+    const int a = blockIdx.x % A.nt;              // one time node per workgroup
     const int vec = blockIdx.y;
     const int nt = A.nt;
     const T *__restrict__ x = A.x + vec * A.xstride;
@@ -903,7 +884,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
     __syncthreads();
 
 
-    for (int a = 0; a < nt; ++a) {
+    {
         const T wa = A.w[a];
         for (int e = tid; e < DIM * NL; e += NTH) {
             const int l = e % NL, c = e / NL;
@@ -1156,7 +1137,7 @@ static hipError_t launch_face(const CellArgs<T> &a, int nvec, hipStream_t s)
         if (e != hipSuccess) return e;
         attr_bytes = bytes;
     }
-    dim3 grid(a.nbcell, nvec);
+    dim3 grid(a.nbcell * a.nt, nvec);
     hipLaunchKernelGGL(kern, grid, dim3(NTH), bytes, s, a);
     return hipGetLastError();
 }
