@@ -220,6 +220,8 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
     ea.g2 = (T)L.g2;
     ea.out = M.elem.as<T>();
     ea.rec_words = rw;
+    ea.bcells = L.bcells.as<int>();
+    ea.nbcell = L.nbcell;
     {
         TimerScope ts(&ctx->timers, "vanka_elem", s);
         STMG_HIP(launch_elem<T>(L.dim, L.r, L.nq, ea, (int)L.ncell, s));

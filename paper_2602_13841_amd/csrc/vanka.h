@@ -16,6 +16,8 @@ template <typename T> struct ElemArgs {
     T nu, g1, g2;
     T *out;                // element records
     long long rec_words;
+    const int *bcells;     // cells with a face on the domain boundary
+    int nbcell;
 };
 
 template <typename TE, typename TP> struct PatchArgs {
