@@ -561,7 +561,7 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
     T *sm = reinterpret_cast<T *>(smem_raw);
 
     const int tid = threadIdx.x;
-    const int cell = blockIdx.x;
+    const int cell = xcd_cell(blockIdx.x, gridDim.x);
     const int vec = blockIdx.y;
     const int nt = A.nt;
     const T *__restrict__ x = A.x + vec * A.xstride;
@@ -781,8 +781,9 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
     T *sm = reinterpret_cast<T *>(smem_raw);
 
     const int tid = threadIdx.x;
-    const int cell = A.bcells[blockIdx.x / A.nt];
-    const int a = blockIdx.x % A.nt;              // one time node per workgroup
+    const int bsl = xcd_cell(blockIdx.x, gridDim.x);
+    const int cell = A.bcells[bsl / A.nt];
+    const int a = bsl % A.nt;                     // one time node per workgroup
     const int vec = blockIdx.y;
     const int nt = A.nt;
     const T *__restrict__ x = A.x + vec * A.xstride;

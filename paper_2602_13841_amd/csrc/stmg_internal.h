@@ -126,6 +126,15 @@ struct GatherArgs {
     int inv_mult;   // divide the sum by the number of cells holding the node
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2; give every XCD a contiguous range of cells so neighbouring cells (which
+// share nodes) read through the same L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_cell(int b, int n)
+{
+    const int q = n >> 3, rem = n & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < rem ? x : rem) + k;
+}
+
 // launchers (cell_ops.hip)
 template <typename T>
 hipError_t launch_cell_op(Mode mode, int dim, int r, int nq, const CellArgs<T> &a, int nvec, hipStream_t s);

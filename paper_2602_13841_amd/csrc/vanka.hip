@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(EL_THREADS) elem_kernel(ElemArgs<T> A)
     __shared__ int nfaces;
 
     const int tid = threadIdx.x;
-    const int cell = FACE_ONLY ? A.bcells[blockIdx.x] : blockIdx.x;
+    const int cell = FACE_ONLY ? A.bcells[xcd_cell(blockIdx.x, gridDim.x)] : xcd_cell(blockIdx.x, gridDim.x);
     TableLayout lay;
     lay.init(R, NQ);
     for (int i = tid; i < NQ * N1; i += NT) {
@@ -542,7 +542,7 @@ __global__ void __launch_bounds__(EM_THREADS) elem_mfma_kernel(ElemArgs<float> A
     __shared__ int pal[32 * 3];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int cell = blockIdx.x;
+    const int cell = xcd_cell(blockIdx.x, gridDim.x);
     TableLayout lay;
     lay.init(R, NQ);
     for (int i = tid; i < NQ * N1; i += EM_THREADS) {
@@ -765,7 +765,7 @@ __global__ void __launch_bounds__(256) patch_kernel(PatchArgs<TE, TP> A)
 {
     using Z = VS<DIM, R>;
     constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
-    const int cell = blockIdx.x;
+    const int cell = xcd_cell(blockIdx.x, gridDim.x);
     const int nt = A.nt;
     const int nv = nt * DIM * NL;
     const int m = nv + nt * NPM;
@@ -1124,7 +1124,7 @@ __global__ void __launch_bounds__(SV_THREADS) solve_kernel(SolveArgs<T, TP> A)
     constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
     extern __shared__ unsigned char lds_raw[];
     TP *b = reinterpret_cast<TP *>(lds_raw);
-    const int cell = blockIdx.x, tid = threadIdx.x;
+    const int cell = xcd_cell(blockIdx.x, gridDim.x), tid = threadIdx.x;
     const int nt = A.nt, nv = nt * DIM * NL, m = nv + nt * NPM;
     TP *dblk = b + ((m + 1) & ~1);
     const int c0 = cell % A.n0, c1 = (cell / A.n0) % A.n1, c2 = DIM == 3 ? cell / (A.n0 * A.n1) : 0;
@@ -1185,7 +1185,7 @@ __global__ void __launch_bounds__(256) patch_td_kernel(PatchTdArgs<TE, TP> A)
     constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
     constexpr int NV = DIM * NL, MS = NV + NPM;
     constexpr long long MAT = (long long)MS * MS;
-    const int cell = blockIdx.x;
+    const int cell = xcd_cell(blockIdx.x, gridDim.x);
     const int cc[3] = {cell % A.n0, (cell / A.n0) % A.n1, DIM == 3 ? cell / (A.n0 * A.n1) : 0};
     const int nn[3] = {A.n0, A.n1, A.n2};
     const long long rw = A.rec_words;
@@ -1653,7 +1653,7 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP>
     TP *bi = br + MSP;
     TP *dr = bi + MSP;
     TP *di = dr + 64 * 65;
-    const int cell = blockIdx.x, tid = threadIdx.x;
+    const int cell = xcd_cell(blockIdx.x, gridDim.x), tid = threadIdx.x;
     const int c0 = cell % A.n0, c1 = (cell / A.n0) % A.n1, c2 = DIM == 3 ? cell / (A.n0 * A.n1) : 0;
     const long long N0 = (long long)(R + 1) * A.n0 + 1, N1g = (long long)(R + 1) * A.n1 + 1;
     const long long pbase = (long long)nt * A.Nv1;
