@@ -28,8 +28,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_VALU = 78.6e12      # 256 CU * 64 FP64 FMA lanes/clk * 2 flop * 2.4 GHz
+PEAK_FP64_VALU = 78.6e12      # 256 CU * 4 SIMD * 16 FP64 lanes/clk * 2 flop * 2.4 GHz
 PEAK_HBM = 8.0e12
+# HBM bytes per launch of the FP64 Jacobian volume kernel on this workload:
+# rocprofv3 --pmc FETCH_SIZE (x2, the factor a 1 GiB device copy shows) plus
+# WRITE_SIZE (x1); profiles/cell_kernel_jac_16cube_r2k2.md
+CELL_KERNEL_TRAFFIC_BYTES = (2 * 10056 + 19393) * 1024
 
 WORKLOAD = dict(dim=3, n=(16, 16, 16), r=2, k=2, nu=1e-2, tau=1.0 / 32)
 
@@ -88,7 +92,8 @@ def cpu_baseline(U, X, seconds=12.0):
 
 
 SOLVE_WORKLOAD = dict(dim=3, n=(32, 32, 32), r=3, k=1, nu=1e-3, tau=1.0 / 64, perturb=0.2, vert_seed=4, v0_seed=5)
-TIMER_NAMES = ["vanka_elem", "vanka_patch", "vanka_lu", "vanka_apply", "cell_jac_f64", "cell_jac_f32", "gather_f64",
+TIMER_NAMES = ["vanka_elem", "vanka_patch", "vanka_lu", "vanka_apply", "cell_jac_f64", "cell_jac_f32", "face_jac_f64",
+               "face_jac_f32", "gather_f64",
                "gather_f32", "cell_res_f64", "cell_mass_f64", "coarse_factor", "coarse_solve", "transfer"]
 
 
@@ -178,6 +183,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="one 1 GiB device-to-device copy first (reference for the rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -188,6 +195,14 @@ def main():
     from paper_2602_13841_amd import stmg
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     w = WORKLOAD
     ctx = stmg.Context(w["dim"], w["n"], w["r"], w["k"], w["nu"], w["tau"])
     N, Nv = ctx.N, ctx.Nv
@@ -216,14 +231,16 @@ def main():
         ctx.timing(False)
         suffix = "f64" if dtype == torch.float64 else "f32"
         cell_ms, cell_n = ctx.timing_get("cell_jac_" + suffix)
+        face_ms, face_n = ctx.timing_get("face_jac_" + suffix)
         gat_ms, gat_n = ctx.timing_get("gather_" + suffix)
         ctx.timing_reset()
         del Us, Xs, Ys
         torch.cuda.empty_cache()
-        return (t1 - t0) / steps, cell_ms / max(cell_n, 1), gat_ms / max(gat_n, 1), nsets
+        return ((t1 - t0) / steps, cell_ms / max(cell_n, 1), face_ms / max(face_n, 1), gat_ms / max(gat_n, 1),
+                nsets)
 
-    t64, cell64, gat64, nsets64 = run(torch.float64, args.steps, args.warmup)
-    t32, cell32, gat32, nsets32 = run(torch.float32, args.steps, args.warmup)
+    t64, cell64, face64, gat64, nsets64 = run(torch.float64, args.steps, args.warmup)
+    t32, cell32, face32, gat32, nsets32 = run(torch.float32, args.steps, args.warmup)
 
     del ctx
     torch.cuda.empty_cache()
@@ -247,14 +264,14 @@ def main():
                                "tau=1/32, smooth divergence-free Fourier state",
                    "N": N, "n_q": nq, "rotating_sets": nsets64},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-                     "kernel": "cell_kernel<3,2,5,Jac,f64>", "flops_per_launch": flops,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": CELL_KERNEL_TRAFFIC_BYTES,
+                     "kernel": "cell_kernel<3,2,5,Jac,f64> (volume terms)", "flops_per_launch": flops,
                      "kernel_ms": cell64},
-        "roofline_hbm": {"achieved": bytes64 / ((cell64 + gat64) * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
-                         "unit": "GB/s", "frac": bytes64 / ((cell64 + gat64) * 1e-3) / PEAK_HBM,
-                         "algorithmic_bytes": bytes64, "cell_ms": cell64, "gather_ms": gat64},
+        "roofline_hbm": {"achieved": bytes64 / ((cell64 + face64 + gat64) * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                         "unit": "GB/s", "frac": bytes64 / ((cell64 + face64 + gat64) * 1e-3) / PEAK_HBM,
+                         "algorithmic_bytes": bytes64, "cell_ms": cell64, "face_ms": face64, "gather_ms": gat64},
         "fp32": {"value": N / t32, "unit": "DoF/s", "ms_per_step": t32 * 1e3, "cell_ms": cell32,
-                 "gather_ms": gat32, "speedup_vs_fp64": t64 / t32},
+                 "face_ms": face32, "gather_ms": gat32, "speedup_vs_fp64": t64 / t32},
     }
     if not args.no_solve:
         print("[bench] slab solve, FP32 multigrid", file=sys.stderr, flush=True)

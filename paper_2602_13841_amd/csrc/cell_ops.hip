@@ -1169,10 +1169,7 @@ static hipError_t launch_one(const CellArgs<T> &a, int nvec, hipStream_t s)
     }
     dim3 grid(a.ncell, nvec);
     hipLaunchKernelGGL(kern, grid, dim3(NTH), bytes, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if constexpr (MODE != Mode::Mass) return launch_face<DIM, R, NQ, T, MODE>(a, nvec, s);
-    return hipSuccess;
+    return hipGetLastError();
 }
 
 template <int DIM, int R, typename T, Mode MODE>
@@ -1195,6 +1192,41 @@ static hipError_t dispatch_r(int r, int nq, const CellArgs<T> &a, int nvec, hipS
     case 3: return dispatch_nq<DIM, 3, T, MODE>(nq, a, nvec, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int DIM, typename T, Mode MODE>
+static hipError_t dispatch_face(int r, int nq, const CellArgs<T> &a, int nvec, hipStream_t s)
+{
+    switch (r) {
+    case 1:
+        if (nq == 4) return launch_face<DIM, 1, 4, T, MODE>(a, nvec, s);
+        if (nq == 3) return launch_face<DIM, 1, 3, T, MODE>(a, nvec, s);
+        break;
+    case 2:
+        if (nq == 5) return launch_face<DIM, 2, 5, T, MODE>(a, nvec, s);
+        if (nq == 4) return launch_face<DIM, 2, 4, T, MODE>(a, nvec, s);
+        break;
+    case 3:
+        if (nq == 7) return launch_face<DIM, 3, 7, T, MODE>(a, nvec, s);
+        if (nq == 5) return launch_face<DIM, 3, 5, T, MODE>(a, nvec, s);
+        break;
+    default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_face_op(Mode mode, int dim, int r, int nq, const CellArgs<T> &a, int nvec, hipStream_t s)
+{
+    if (mode == Mode::Mass) return hipSuccess;
+    if (dim == 2) {
+        if (mode == Mode::Jac) return dispatch_face<2, T, Mode::Jac>(r, nq, a, nvec, s);
+        if constexpr (std::is_same<T, double>::value) return dispatch_face<2, T, Mode::Res>(r, nq, a, nvec, s);
+    } else {
+        if (mode == Mode::Jac) return dispatch_face<3, T, Mode::Jac>(r, nq, a, nvec, s);
+        if constexpr (std::is_same<T, double>::value) return dispatch_face<3, T, Mode::Res>(r, nq, a, nvec, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -1222,6 +1254,8 @@ hipError_t launch_gather(const GatherArgs<T> &g, int nvec, hipStream_t s)
     return hipGetLastError();
 }
 
+template hipError_t launch_face_op<double>(Mode, int, int, int, const CellArgs<double> &, int, hipStream_t);
+template hipError_t launch_face_op<float>(Mode, int, int, int, const CellArgs<float> &, int, hipStream_t);
 template hipError_t launch_cell_op<double>(Mode, int, int, int, const CellArgs<double> &, int, hipStream_t);
 template hipError_t launch_cell_op<float>(Mode, int, int, int, const CellArgs<float> &, int, hipStream_t);
 template hipError_t launch_gather<double>(const GatherArgs<double> &, int, hipStream_t);

@@ -140,6 +140,12 @@ void Level::apply(Mode mode, const T *state, const T *x, T *y, const T *rhs, con
         TimerScope ts(timers, nm, s);
         STMG_HIP(launch_cell_op<T>(mode, dim, r, nq, a, nvec, s));
     }
+    if (mode != Mode::Mass) {
+        static const char *fn64[2] = {"face_jac_f64", "face_res_f64"};
+        static const char *fn32[2] = {"face_jac_f32", "face_res_f32"};
+        TimerScope ts(timers, std::is_same<T, double>::value ? fn64[(int)mode] : fn32[(int)mode], s);
+        STMG_HIP(launch_face_op<T>(mode, dim, r, nq, a, nvec, s));
+    }
     GatherArgs<T> g = gather_args<T>();
     g.E = Eb.as<T>();
     g.rhs = rhs;

@@ -138,6 +138,9 @@ __device__ __forceinline__ int xcd_cell(int b, int n)
 // launchers (cell_ops.hip)
 template <typename T>
 hipError_t launch_cell_op(Mode mode, int dim, int r, int nq, const CellArgs<T> &a, int nvec, hipStream_t s);
+// boundary-face terms of the Jacobian / residual, added after launch_cell_op
+template <typename T>
+hipError_t launch_face_op(Mode mode, int dim, int r, int nq, const CellArgs<T> &a, int nvec, hipStream_t s);
 template <typename T>
 hipError_t launch_gather(const GatherArgs<T> &g, int nvec, hipStream_t s);
 
