@@ -752,10 +752,14 @@ template <int DIM, int R, int NQ, typename T> struct FaceLds {
     static constexpr int NQF = ipow(NQ, DIM - 1);
     static constexpr int NF_F = DIM + DIM * DIM + DIM + 1;    // xhat, grad xhat, v, p
     static constexpr int Q_SIZE = NF_F * NQF + (DIM + DIM * DIM + 1) * NQF;
-    static constexpr int MX = Z::N1 > NQ ? Z::N1 : NQ;
-    static constexpr int TS = DIM * Z::N1 * NQ * MX;
-    static constexpr int TSP = TS > NQV ? TS : NQV;
-    static constexpr int TMP = TSP > 256 ? TSP : 256;
+    // normal-reduced layers and the tangential pencil buffer (also used by the
+    // h_F reductions: one word per thread, NQF face points)
+    static constexpr int LN = DIM == 3 ? Z::N1 * Z::N1 : Z::N1;
+    static constexpr int LP = DIM == 3 ? Z::RP1 * Z::RP1 : Z::RP1;
+    static constexpr int L1 = 3 * DIM * LN + LP;
+    static constexpr int L2 = DIM == 3 ? 4 * DIM * Z::N1 * NQ + Z::RP1 * NQ : 1;
+    static constexpr int TMP1 = L1 > 256 ? L1 : 256;
+    static constexpr int TMP2 = (L2 > NQF ? L2 : NQF) > 256 ? (L2 > NQF ? L2 : NQF) : 256;
 };
 
 template <int DIM, int R, int NQ, typename T>
@@ -763,7 +767,7 @@ __host__ __device__ constexpr int face_lds_words(int tabwords)
 {
     using Z = Sizes<DIM, R>;
     using LY = FaceLds<DIM, R, NQ, T>;
-    return ((tabwords + 1) & ~1) + 4 * DIM * Z::NL + 2 * Z::NPF + LY::Q_SIZE + 2 * LY::TMP + 64;
+    return ((tabwords + 1) & ~1) + 4 * DIM * Z::NL + 2 * Z::NPF + LY::Q_SIZE + LY::TMP1 + LY::TMP2 + 64;
 }
 
 template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE>
@@ -800,13 +804,13 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
     T *ypf = xpf + NPF;                            // [NPF] pressure output
     T *Q = ypf + NPF;                              // face record
     T *t1 = Q + LY::Q_SIZE;
-    T *t2 = t1 + LY::TMP;
-    T *geo = t2 + LY::TMP;                         // [8][3] vertices, [6] h_F, [1] volume
+    T *t2 = t1 + LY::TMP1;
+    T *geo = t2 + LY::TMP2;                        // [8][3] vertices, [6] h_F, [1] volume
 
     for (int i = tid; i < lay.total; i += NTH) tab[i] = A.tab[i];
-    const T *S = tab + lay.S, *St = tab + lay.St, *D = tab + lay.D, *Dt = tab + lay.Dt;
-    const T *Se = tab + lay.Se, *De = tab + lay.De;
-    const T *Lp = tab + lay.L, *Lpt = tab + lay.Lt, *Lpe = tab + lay.Le, *qw = tab + lay.qw;
+    using CP = const __attribute__((address_space(4))) T *;   // constant for the whole kernel
+    const CP S = (CP)(A.tab + lay.S), D = (CP)(A.tab + lay.D), Lp = (CP)(A.tab + lay.L);
+    const T *Se = tab + lay.Se, *De = tab + lay.De, *Lpe = tab + lay.Le, *qw = tab + lay.qw;
     const T *qx = tab + lay.qx;
 
     const int c0 = cell % A.n0;
@@ -917,46 +921,101 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                         // face record (each field NQF long):
                         //   inputs : [0,D) xhat, [D, D+D^2) ref grad (c*D+j), [D+D^2, 2D+D^2) v, p
                         //   outputs: value coef (D), ref-grad test coef (D^2), pressure test coef
-                        constexpr int FV = 0, FG = DIM, FS = DIM + DIM * DIM, FP = 2 * DIM + DIM * DIM;
-                        constexpr int FO = 2 * DIM + DIM * DIM + 1;
-                        T *FQ = Q;
-                        const T *Srow = Se + side * N1, *Drow = De + side * N1, *Lrow = Lpe + side * RP1;
-#define FACE_SWEEP(NFLD, INP, IS, OUTP, OS, M0, M1, M2, I0_, I1_, I2_)                                      \
-    do {                                                                                                     \
-        if (ax == 0)                                                                                         \
-            sweep<DIM, NFLD, I0_, I1_, I2_, 1, NQ, NQ2, false>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);       \
-        else if (ax == 1)                                                                                    \
-            sweep<DIM, NFLD, I0_, I1_, I2_, NQ, 1, NQ2, false>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);       \
-        else                                                                                                 \
-            sweep<DIM, NFLD, I0_, I1_, I2_, NQ, NQ, 1, false>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);        \
-    } while (0)
-#define FACE_SWEEP_T(NFLD, INP, IS, OUTP, OS, M0, M1, M2, O0_, O1_, O2_)                                    \
-    do {                                                                                                     \
-        if (ax == 0)                                                                                         \
-            sweep<DIM, NFLD, 1, NQ, NQ2, O0_, O1_, O2_, true>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);        \
-        else if (ax == 1)                                                                                    \
-            sweep<DIM, NFLD, NQ, 1, NQ2, O0_, O1_, O2_, true>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);        \
-        else                                                                                                 \
-            sweep<DIM, NFLD, NQ, NQ, 1, O0_, O1_, O2_, true>(INP, IS, OUTP, OS, t1, t2, M0, M1, M2);         \
-    } while (0)
-                        {
-                            const T *m0 = ax == 0 ? Srow : S, *m1 = ax == 1 ? Srow : S, *m2 = ax == 2 ? Srow : S;
-                            FACE_SWEEP(DIM, xs, NL, FQ + FV * NQF, NQF, m0, m1, m2, N1, N1, N12);
-                            if constexpr (MODE == Mode::Jac)
-                                FACE_SWEEP(DIM, ns, NL, FQ + FS * NQF, NQF, m0, m1, m2, N1, N1, N12);
-                            for (int jd = 0; jd < DIM; ++jd) {
-                                const T *d0 = ax == 0 ? (jd == 0 ? Drow : Srow) : (jd == 0 ? D : S);
-                                const T *d1 = ax == 1 ? (jd == 1 ? Drow : Srow) : (jd == 1 ? D : S);
-                                const T *d2 = ax == 2 ? (jd == 2 ? Drow : Srow) : (jd == 2 ? D : S);
-                                for (int c = 0; c < DIM; ++c)
-                                    FACE_SWEEP(1, xs + c * NL, NL, FQ + (FG + c * DIM + jd) * NQF, NQF,
-                                               d0, d1, d2, N1, N1, N12);
-                            }
-                            const T *p0 = ax == 0 ? Lrow : Lp, *p1 = ax == 1 ? Lrow : Lp, *p2 = ax == 2 ? Lrow : Lp;
-                            FACE_SWEEP(1, xpf, NPF, FQ + FP * NQF, NQF, p0, p1, p2, RP1, RP1, RP12);
-                        }
                         // penalty length: |K|/|F| over the squared velocity degree
                         const T hf = hF[fid] / T((R + 1) * (R + 1));
+                        // tangential axes (ta0 < ta1) and strides of the nodal / modal tensors
+                        const int ta0 = DIM == 2 ? 1 - ax : (ax == 0 ? 1 : 0);
+                        const int ta1 = DIM == 2 ? 0 : (ax == 2 ? 1 : 2);
+                        const int sN[3] = {1, N1, N1 * N1}, sP[3] = {1, RP1, RP1 * RP1};
+                        const T *Srow = Se + side * N1, *Drow = De + side * N1, *Lrow = Lpe + side * RP1;
+                        constexpr int LN = DIM == 3 ? N1 * N1 : N1;      // nodes of a layer
+                        constexpr int LP = DIM == 3 ? RP1 * RP1 : RP1;   // modes of a layer
+                        T *lay = t1;                                     // [3D fields][LN] + [LP]
+                        T *play = lay + 3 * DIM * LN;
+                        T *abuf = t2;                                    // 3D: [pipe][j1][q0]
+                        T *FQ = Q;
+                        constexpr int FV = 0, FG = DIM, FS = DIM + DIM * DIM, FP = 2 * DIM + DIM * DIM;
+                        constexpr int FO = 2 * DIM + DIM * DIM + 1;
+                        // 1. reduce along the normal: value layers of xhat and v, normal-derivative
+                        //    layers of xhat, value layer of the pressure modes
+                        for (int w = tid; w < 3 * DIM * LN + LP; w += NTH) {
+                            if (w < 3 * DIM * LN) {
+                                const int f = w / LN, it = w - f * LN;
+                                const int j0 = DIM == 3 ? it % N1 : it, j1 = DIM == 3 ? it / N1 : 0;
+                                const int base = j0 * sN[ta0] + (DIM == 3 ? j1 * sN[ta1] : 0);
+                                const int grp = f / DIM, c = f - grp * DIM;
+                                const T *src = (grp == 2 && MODE == Mode::Jac ? ns : xs) + c * NL + base;
+                                const T *wr = grp == 1 ? Drow : Srow;
+                                T s = 0;
+#pragma unroll
+                                for (int i = 0; i < N1; ++i) s += wr[i] * src[i * sN[ax]];
+                                lay[w] = s;
+                            } else {
+                                const int it = w - 3 * DIM * LN;
+                                const int j0 = DIM == 3 ? it % RP1 : it, j1 = DIM == 3 ? it / RP1 : 0;
+                                const T *src = xpf + j0 * sP[ta0] + (DIM == 3 ? j1 * sP[ta1] : 0);
+                                T s = 0;
+#pragma unroll
+                                for (int i = 0; i < RP1; ++i) s += Lrow[i] * src[i * sP[ax]];
+                                play[it] = s;
+                            }
+                        }
+                        __syncthreads();
+                        // 2. tangential interpolation to the face points q = q0 + NQ q1
+                        if constexpr (DIM == 3) {
+                            // contract t0: pipes xS (DIM), xD (DIM), nS (DIM), vS (DIM), p; item (pipe, j1)
+                            constexpr int NPV = 4 * DIM;
+                            for (int w = tid; w < NPV * N1 + RP1; w += NTH) {
+                                if (w < NPV * N1) {
+                                    const int pipe = w / N1, j1 = w - pipe * N1;
+                                    const int grp = pipe / DIM, c = pipe - grp * DIM;
+                                    const int lf = grp == 0 || grp == 1 ? c : (grp == 2 ? DIM + c : 2 * DIM + c);
+                                    pencil_apply<N1, NQ>(lay + lf * LN + j1 * N1, 1, abuf + pipe * N1 * NQ + j1 * NQ,
+                                                         1, grp == 1 ? D : S);
+                                } else {
+                                    const int j1 = w - NPV * N1;
+                                    pencil_apply<RP1, NQ>(play + j1 * RP1, 1, abuf + NPV * N1 * NQ + j1 * NQ, 1, Lp);
+                                }
+                            }
+                            __syncthreads();
+                            // contract t1: item (output field, q0); outputs x (S), g_t1 (D), g_t0, g_ax, v, p
+                            constexpr int NOF = 5 * DIM + 1;
+                            for (int w = tid; w < NOF * NQ; w += NTH) {
+                                const int of = w / NQ, q0 = w - of * NQ;
+                                const int grp = of / DIM, c = of - grp * DIM;
+                                if (of < 5 * DIM) {
+                                    int pipe, dst;
+                                    CP M = S;
+                                    if (grp == 0) { pipe = c; dst = FV + c; }
+                                    else if (grp == 1) { pipe = c; dst = FG + c * DIM + ta1; M = D; }
+                                    else if (grp == 2) { pipe = DIM + c; dst = FG + c * DIM + ta0; }
+                                    else if (grp == 3) { pipe = 2 * DIM + c; dst = FG + c * DIM + ax; }
+                                    else { pipe = 3 * DIM + c; dst = FS + c; }
+                                    pencil_apply<N1, NQ>(abuf + pipe * N1 * NQ + q0, NQ, FQ + dst * NQF + q0, NQ, M);
+                                } else {
+                                    pencil_apply<RP1, NQ>(abuf + NPV * N1 * NQ + q0, NQ, FQ + FP * NQF + q0, NQ, Lp);
+                                }
+                            }
+                            __syncthreads();
+                        } else {
+                            // one tangential axis: item = output field
+                            for (int w = tid; w < 4 * DIM + 1; w += NTH) {
+                                const int grp = w / DIM, c = w - grp * DIM;
+                                if (w < 4 * DIM) {
+                                    int lf, dst;
+                                    CP M = S;
+                                    if (grp == 0) { lf = c; dst = FV + c; }
+                                    else if (grp == 1) { lf = c; dst = FG + c * DIM + ta0; M = D; }
+                                    else if (grp == 2) { lf = DIM + c; dst = FG + c * DIM + ax; }
+                                    else { lf = 2 * DIM + c; dst = FS + c; }
+                                    pencil_apply<N1, NQ>(lay + lf * LN, 1, FQ + dst * NQF, 1, M);
+                                } else {
+                                    pencil_apply<RP1, NQ>(play, 1, FQ + FP * NQF, 1, Lp);
+                                }
+                            }
+                            __syncthreads();
+                        }
+                        // 3. point terms
                         for (int q = tid; q < NQF; q += NTH) {
                             const int tq[2] = {q % NQ, DIM == 3 ? q / NQ : 0};
                             T xi[3] = {0, 0, 0}, Jit[3][3], wt = 1;
@@ -1035,24 +1094,108 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                             FQ[(FO + DIM + DIM * DIM) * NQF + q] = sc * pco;
                         }
                         __syncthreads();
-                        {
-                            // transposes: the 1-row normal matrix acts as an N1 x 1 column
-                            const T *m0 = ax == 0 ? Srow : St, *m1 = ax == 1 ? Srow : St, *m2 = ax == 2 ? Srow : St;
-                            FACE_SWEEP_T(DIM, FQ + FO * NQF, NQF, ys, NL, m0, m1, m2, N1, N1, N12);
-                            for (int jd = 0; jd < DIM; ++jd) {
-                                const T *d0 = ax == 0 ? (jd == 0 ? Drow : Srow) : (jd == 0 ? Dt : St);
-                                const T *d1 = ax == 1 ? (jd == 1 ? Drow : Srow) : (jd == 1 ? Dt : St);
-                                const T *d2 = ax == 2 ? (jd == 2 ? Drow : Srow) : (jd == 2 ? Dt : St);
-                                for (int c = 0; c < DIM; ++c)
-                                    FACE_SWEEP_T(1, FQ + (FO + DIM + c * DIM + jd) * NQF, NQF, ys + c * NL, NL, d0,
-                                                 d1, d2, N1, N1, N12);
+                        // 4. transposed tangential passes into value / normal-derivative layers
+                        //    A_c (value layer: val, tangential gradient coefficients), B_c (normal
+                        //    derivative layer: normal gradient coefficient), P (pressure)
+                        T *Alay = lay, *Blay = lay + DIM * LN, *Play = lay + 2 * DIM * LN;
+                        if constexpr (DIM == 3) {
+                            // contract q1: pipes (val S + g_t1 D) (DIM), g_t0 S (DIM), g_ax S (DIM), p Lp;
+                            // item (pipe, q0), rows j1
+                            constexpr int NPB = 3 * DIM;
+                            for (int w = tid; w < (NPB + 1) * NQ; w += NTH) {
+                                const int pipe = w / NQ, q0 = w - pipe * NQ;
+                                const int grp = pipe / DIM, c = pipe - grp * DIM;
+                                T *out = abuf + pipe * N1 * NQ + q0;
+                                if (pipe < NPB) {
+                                    T u[NQ], g[NQ];
+                                    const int fa = grp == 0 ? FO + c : (grp == 1 ? FO + DIM + c * DIM + ta0 : FO + DIM + c * DIM + ax);
+#pragma unroll
+                                    for (int q1 = 0; q1 < NQ; ++q1) u[q1] = FQ[fa * NQF + q0 + NQ * q1];
+                                    if (grp == 0)
+#pragma unroll
+                                        for (int q1 = 0; q1 < NQ; ++q1) g[q1] = FQ[(FO + DIM + c * DIM + ta1) * NQF + q0 + NQ * q1];
+#pragma unroll
+                                    for (int j1 = 0; j1 < N1; ++j1) {
+                                        T s = 0;
+#pragma unroll
+                                        for (int q1 = 0; q1 < NQ; ++q1) {
+                                            s += S[q1 * N1 + j1] * u[q1];
+                                            if (grp == 0) s += D[q1 * N1 + j1] * g[q1];
+                                        }
+                                        out[j1 * NQ] = s;
+                                    }
+                                } else {
+                                    pencil_apply_t<RP1, NQ>(FQ + (FO + DIM + DIM * DIM) * NQF + q0, NQ, out, NQ, Lp);
+                                }
                             }
-                            const T *p0 = ax == 0 ? Lrow : Lpt, *p1 = ax == 1 ? Lrow : Lpt, *p2 = ax == 2 ? Lrow : Lpt;
-                            FACE_SWEEP_T(1, FQ + (FO + DIM + DIM * DIM) * NQF, NQF, ypf, NPF, p0, p1, p2, RP1, RP1,
-                                         RP12);
+                            __syncthreads();
+                            // contract q0: item (layer, j1); A_c = S^T(pipe c) + D^T(pipe DIM+c), B_c = S^T(pipe 2DIM+c)
+                            for (int w = tid; w < 2 * DIM * N1 + RP1; w += NTH) {
+                                if (w < 2 * DIM * N1) {
+                                    const int lf = w / N1, j1 = w - lf * N1;
+                                    const int grp = lf / DIM, c = lf - grp * DIM;
+                                    T *out = (grp == 0 ? Alay : Blay) + c * LN + j1 * N1;
+                                    const T *u0 = abuf + (grp == 0 ? c : 2 * DIM + c) * N1 * NQ + j1 * NQ;
+                                    const T *u1 = abuf + (DIM + c) * N1 * NQ + j1 * NQ;
+                                    T u[NQ], g[NQ];
+#pragma unroll
+                                    for (int q0 = 0; q0 < NQ; ++q0) {
+                                        u[q0] = u0[q0];
+                                        g[q0] = grp == 0 ? u1[q0] : T(0);
+                                    }
+#pragma unroll
+                                    for (int j0 = 0; j0 < N1; ++j0) {
+                                        T s = 0;
+#pragma unroll
+                                        for (int q0 = 0; q0 < NQ; ++q0) s += S[q0 * N1 + j0] * u[q0] + D[q0 * N1 + j0] * g[q0];
+                                        out[j0] = s;
+                                    }
+                                } else {
+                                    const int j1 = w - 2 * DIM * N1;
+                                    pencil_apply_t<RP1, NQ>(abuf + 3 * DIM * N1 * NQ + j1 * NQ, 1, Play + j1 * RP1, 1, Lp);
+                                }
+                            }
+                            __syncthreads();
+                        } else {
+                            for (int w = tid; w < 2 * DIM + 1; w += NTH) {
+                                const int grp = w / DIM, c = w - grp * DIM;
+                                if (w < 2 * DIM) {
+                                    T *out = (grp == 0 ? Alay : Blay) + c * LN;
+                                    T u[NQ], g[NQ];
+                                    const int fa = grp == 0 ? FO + c : FO + DIM + c * DIM + ax;
+#pragma unroll
+                                    for (int q0 = 0; q0 < NQ; ++q0) {
+                                        u[q0] = FQ[fa * NQF + q0];
+                                        g[q0] = grp == 0 ? FQ[(FO + DIM + c * DIM + ta0) * NQF + q0] : T(0);
+                                    }
+#pragma unroll
+                                    for (int j0 = 0; j0 < N1; ++j0) {
+                                        T s = 0;
+#pragma unroll
+                                        for (int q0 = 0; q0 < NQ; ++q0) s += S[q0 * N1 + j0] * u[q0] + D[q0 * N1 + j0] * g[q0];
+                                        out[j0] = s;
+                                    }
+                                } else {
+                                    pencil_apply_t<RP1, NQ>(FQ + (FO + DIM + DIM * DIM) * NQF, 1, Play, 1, Lp);
+                                }
+                            }
+                            __syncthreads();
                         }
-#undef FACE_SWEEP
-#undef FACE_SWEEP_T
+                        // 5. expansion along the normal into the nodal / modal outputs
+                        for (int w = tid; w < DIM * NL + NPF; w += NTH) {
+                            if (w < DIM * NL) {
+                                const int c = w / NL, l = w - c * NL;
+                                const int li[3] = {l % N1, (l / N1) % N1, DIM == 3 ? l / (N1 * N1) : 0};
+                                const int it = li[ta0] + (DIM == 3 ? N1 * li[ta1] : 0);
+                                ys[w] += Srow[li[ax]] * Alay[c * LN + it] + Drow[li[ax]] * Blay[c * LN + it];
+                            } else {
+                                const int m = w - DIM * NL;
+                                const int mi[3] = {m % RP1, (m / RP1) % RP1, DIM == 3 ? m / (RP1 * RP1) : 0};
+                                const int it = mi[ta0] + (DIM == 3 ? RP1 * mi[ta1] : 0);
+                                ypf[m] += Lrow[mi[ax]] * Play[it];
+                            }
+                        }
+                        __syncthreads();
                     }
                 }
             }
@@ -1124,7 +1267,7 @@ __global__ void gather_kernel(GatherArgs<T> G)
 template <int DIM, int R, int NQ, typename T, Mode MODE>
 static hipError_t launch_face(const CellArgs<T> &a, int nvec, hipStream_t s)
 {
-    constexpr int NTH = DIM == 2 ? 64 : 128;
+    constexpr int NTH = 64;   // one wavefront per (boundary cell, time node)
     if (a.nbcell <= 0) return hipSuccess;
     TableLayout lay;
     lay.init(R, NQ);
