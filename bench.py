@@ -136,6 +136,77 @@ def bench_solve(prec, warm=True):
     return out
 
 
+def bench_batched_lu(npatch=4096, seed=6):
+    """Batched Vanka patch factorizations of mixed sizes: `npatch` full
+    space-time surrogate patches (eq. LVS, eq. DefTildeHn) of interior cells of
+    8^3-cell meshes (h = 1/8, tau = h/2), (r, k, nu) uniform on {1, 2, 3} x
+    {0, 1, 2} x {1, 1e-2, 1e-3} (PCG64 seed), nodal states U(-1, 1); the
+    patches are assembled by the library.  One stmg_batched_lu launch per
+    precision (FP64, FP32 on MFMA), then the triangular solves."""
+    import torch
+    from paper_2602_13841_amd import inputs as I
+    from paper_2602_13841_amd import stmg
+    rng = np.random.Generator(np.random.PCG64(seed))
+    draws = [(int(rng.choice([1, 2, 3])), int(rng.choice([0, 1, 2])), float(rng.choice([1.0, 1e-2, 1e-3])))
+             for _ in range(npatch)]
+    combos = sorted(set(draws))
+    n = 8
+    interior = [c0 + n * (c1 + n * c2) for c2 in range(1, n - 1) for c1 in range(1, n - 1) for c0 in range(1, n - 1)]
+    mats = {}
+    for ci, (r, k, nu) in enumerate(combos):
+        ctx = stmg.Context(3, (n, n, n), r, k, nu, 1.0 / 16, prec_mg=stmg.STMG_F64)
+        ctx.smoother_rebuild(torch.tensor(I.uniform(ctx.N, 200 + ci), device="cuda"))
+        need = sum(1 for d in draws if d == (r, k, nu))
+        mats[(r, k, nu)] = [ctx.level_patch(0, interior[j % len(interior)]).clone().reshape(-1) for j in range(need)]
+        del ctx
+    used = {key: 0 for key in mats}
+    blocks = []
+    for dd in draws:
+        blocks.append(mats[dd][used[dd]])
+        used[dd] += 1
+    del mats
+    sizes = np.array([int(round(np.sqrt(b.numel()))) for b in blocks], dtype=np.int32)
+    a_off = np.concatenate([[0], np.cumsum(sizes.astype(np.int64) ** 2)[:-1]])
+    p_off = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))[:-1]])
+    A64 = torch.cat(blocks)
+    del blocks
+    torch.cuda.empty_cache()
+    flops = float(np.sum(2.0 / 3.0 * sizes.astype(np.float64) ** 3))
+    out = {"patches": npatch, "sizes": [int(sizes.min()), int(sizes.max()), float(sizes.mean())],
+           "lu_flops": flops}
+    rng2 = np.random.Generator(np.random.PCG64(seed + 1))
+    rhs = torch.tensor(rng2.uniform(-1, 1, int(sizes.sum())), device="cuda")
+    for name, dt, peak in (("fp64", torch.float64, 78.6e12), ("fp32_mfma", torch.float32, 157.3e12)):
+        A = A64.to(dt)
+        piv = torch.zeros(int(sizes.sum()), dtype=torch.int32, device="cuda")
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        stmg.batched_lu(A, a_off, sizes, piv, p_off, info)
+        e1.record()
+        b = rhs.to(dt)
+        stmg.batched_lu_solve(A, a_off, sizes, piv, p_off, b, p_off)
+        e2.record()
+        torch.cuda.synchronize()
+        t_lu, t_sv = e0.elapsed_time(e1) * 1e-3, e1.elapsed_time(e2) * 1e-3
+        # normwise backward error on a sample of patches (host check)
+        x = b.double().cpu().numpy()
+        worst = 0.0
+        for i in list(range(0, npatch, max(1, npatch // 16))):
+            M = A64[a_off[i]: a_off[i] + int(sizes[i]) ** 2].view(int(sizes[i]), -1).cpu().numpy()
+            xi = x[p_off[i]: p_off[i] + sizes[i]]
+            ri = rhs[p_off[i]: p_off[i] + sizes[i]].cpu().numpy()
+            be = np.max(np.abs(M @ xi - ri)) / (np.max(np.abs(M).sum(1)) * np.max(np.abs(xi)) + np.max(np.abs(ri)))
+            worst = max(worst, float(be))
+        out[name] = {"lu_s": t_lu, "patches_per_s": npatch / t_lu, "tflops": flops / t_lu / 1e12,
+                     "frac_of_peak": flops / t_lu / peak, "solve_s": t_sv, "zero_pivots": int(info.item()),
+                     "backward_error_sample_max": worst}
+        del A, piv, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_serve(nreq, slots):
     """Serving: the first `nreq` requests of the seeded mixed stream (2D/3D,
     8..24 cells per axis, r in 1..3, k in 0..2, Re in {1, 100, 1000}).  A
@@ -181,6 +252,7 @@ def main():
     ap.add_argument("--rotate-bytes", type=float, default=1.1 * 2 ** 30)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-batched-lu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true",
@@ -282,6 +354,9 @@ def main():
                                     "tau=1/64, smooth previous-slab velocity, |R|_M <= 1e-8 |R_0|_M",
                         "fp32_mg": s32, "fp64_mg": s64,
                         "speedup_fp32_vs_fp64": s64["wall_s"] / s32["wall_s"]}
+    if not args.no_batched_lu:
+        print("[bench] batched patch factorizations", file=sys.stderr, flush=True)
+        out["batched_lu"] = bench_batched_lu()
     if not args.no_serve:
         print("[bench] serving", file=sys.stderr, flush=True)
         out["serving"] = bench_serve(args.serve_requests, args.serve_slots)

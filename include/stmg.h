@@ -192,6 +192,16 @@ int stmg_smoother_rebuild(stmg_ctx *ctx, const double *u_state);
  * FP32). */
 int stmg_level_jacobian_vmult(stmg_ctx *ctx, int level, int prec, const void *x, void *y);
 
+/* The full space-time surrogate patch of one cell (eq. LVS with the core of
+ * eq. DefTildeHn, before factorization): the principal submatrix of the
+ * surrogate Jacobian on all unknowns of `cell` at all time nodes, m x m
+ * row-major with m = (k+1)(d (r+2)^d + C(r+d,d)) of that level, unknowns
+ * ordered velocity [a][c][local node], then pressure [a][mode].  Uses the
+ * element matrices of the last stmg_smoother_rebuild (STMG_ESTATE before
+ * it).  out: device array of m*m values in the multigrid precision (prec
+ * must equal opt.prec_mg). */
+int stmg_level_patch(stmg_ctx *ctx, int level, int cell, int prec, void *out);
+
 /* `sweeps` additive Vanka sweeps on a level (eq. vanka0):
  *   d <- d + omega sum_K R_K^T S_K^{-1} R_K (r - J_level d).
  * r, d: device slab vectors of that level in the multigrid precision
@@ -228,6 +238,29 @@ int stmg_fgmres(stmg_ctx *ctx, const double *u_state, const double *b, double *x
  * solution out (device, FP64).  Stops when ||R||_M <= max(atol, rtol
  * ||R_0||_M).  stats may be NULL. */
 int stmg_newton_gmres_solve(stmg_ctx *ctx, double *u_inout, stmg_stats *stats);
+
+/* ---- batched patch factorizations (no context) ---------------------------
+ * A batch of dense matrices of mixed sizes, factored in one launch by LU
+ * with partial pivoting (the Vanka patch factorization of Sec. "Inexact
+ * space-time Vanka smoother" as a standalone batch; the trailing updates run
+ * on MFMA in FP32).  prec: STMG_F64 or STMG_F32.  Matrix b is m_of[b] x
+ * m_of[b], row-major, at element offset a_off[b] of the device array A and
+ * is overwritten by its factors (unit lower L below the diagonal, U on and
+ * above); piv + p_off[b] receives m_of[b] 0-based row interchanges
+ * (row j was swapped with row piv[j], applied in order j = 0, 1, ...).
+ * m_of, a_off, p_off are HOST arrays of `batch` entries; A and piv are
+ * device arrays owned by the caller; info (device, may be NULL) is
+ * incremented for every exactly zero pivot.  stream: a hipStream_t or NULL.
+ * Larger matrices are scheduled first.  Returns 0, STMG_EINVAL (bad sizes,
+ * m > 4096) or STMG_EHIP. */
+int stmg_batched_lu(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
+                    const long long *p_off, int *info, void *stream);
+
+/* Solve with the factors of stmg_batched_lu: right-hand side b (device) of
+ * matrix b at element offset b_off[b] (HOST array), overwritten by the
+ * solution.  Same metadata as the factorization. */
+int stmg_batched_lu_solve(int prec, const void *LU, const long long *a_off, const int *m_of, int batch,
+                          const int *piv, const long long *p_off, void *b, const long long *b_off, void *stream);
 
 /* ---- serving (continuous batching of slab solves) ------------------------
  * A request is one slab problem with HOST data: v_prev (Nv1 doubles, may be

@@ -1,6 +1,7 @@
 // extern "C" entry points of the stmg library.
 #include "mg.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -35,6 +36,71 @@ bool check_problem(const stmg_problem *p, std::string &why)
     if (p->k < 0 || p->k > MAX_K) { why = "k must be in 0..3"; return false; }
     if (!(p->tau > 0) || !(p->nu > 0)) { why = "tau and nu must be positive"; return false; }
     return true;
+}
+
+// batched LU (solve == false) or batched substitution (solve == true) of
+// matrices of mixed sizes; host metadata sorted by decreasing size
+int batched_lu_impl(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
+                    const long long *p_off, int *info, void *b, const long long *b_off, void *stream,
+                    bool solve = false)
+{
+    if (!A || !a_off || !m_of || !piv || !p_off || batch < 0) return STMG_EINVAL;
+    if (prec != STMG_F64 && prec != STMG_F32) return STMG_EINVAL;
+    if (batch == 0) return STMG_OK;
+    std::vector<int> ord(batch);
+    int maxm = 0;
+    for (int i = 0; i < batch; ++i) {
+        ord[i] = i;
+        if (m_of[i] < 1 || m_of[i] > 2048 || a_off[i] < 0 || p_off[i] < 0 || (solve && b_off[i] < 0))
+            return STMG_EINVAL;
+        maxm = std::max(maxm, m_of[i]);
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return m_of[x] > m_of[y]; });
+    std::vector<int> ms(batch);
+    std::vector<long long> ao(batch), po(batch), bo(solve ? batch : 0);
+    for (int i = 0; i < batch; ++i) {
+        ms[i] = m_of[ord[i]];
+        ao[i] = a_off[ord[i]];
+        po[i] = p_off[ord[i]];
+        if (solve) bo[i] = b_off[ord[i]];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        DevBuf dm(sizeof(int) * batch), da(sizeof(long long) * batch), dp(sizeof(long long) * batch);
+        DevBuf db(solve ? sizeof(long long) * batch : 0);
+        STMG_HIP(hipMemcpyAsync(dm.p, ms.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
+        STMG_HIP(hipMemcpyAsync(da.p, ao.data(), sizeof(long long) * batch, hipMemcpyHostToDevice, s));
+        STMG_HIP(hipMemcpyAsync(dp.p, po.data(), sizeof(long long) * batch, hipMemcpyHostToDevice, s));
+        if (solve) STMG_HIP(hipMemcpyAsync(db.p, bo.data(), sizeof(long long) * batch, hipMemcpyHostToDevice, s));
+        LuBatch vb{maxm, dm.as<int>(), da.as<long long>(), dp.as<long long>()};
+        hipError_t e;
+        if (solve) {
+            if (prec == STMG_F64)
+                e = launch_batched_solve<double>((const double *)A, piv, maxm, batch, vb, db.as<long long>(),
+                                                 (double *)b, s);
+            else
+                e = launch_batched_solve<float>((const float *)A, piv, maxm, batch, vb, db.as<long long>(),
+                                                (float *)b, s);
+        } else {
+            int dev = 0, lds = 65536;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+                lds = 65536;
+            const size_t max_lds = lds > 8192 ? (size_t)lds - 8192 : (size_t)lds;
+            if (prec == STMG_F64) e = launch_lu<double>((double *)A, piv, maxm, batch, info, max_lds, s, &vb);
+            else e = launch_lu<float>((float *)A, piv, maxm, batch, info, max_lds, s, &vb);
+        }
+        if (e == hipErrorInvalidConfiguration) {
+            (void)hipStreamSynchronize(s);
+            return STMG_EINVAL;
+        }
+        STMG_HIP(e);
+        STMG_HIP(hipStreamSynchronize(s));
+    } catch (const HipError &e) {
+        (void)hipStreamSynchronize(s);
+        return e.code;
+    }
+    return STMG_OK;
 }
 
 } // namespace
@@ -311,6 +377,51 @@ int stmg_smoother_rebuild(stmg_ctx *ctx, const double *u_state)
         mg_rebuild(ctx);
         return STMG_OK;
     });
+}
+
+int stmg_level_patch(stmg_ctx *ctx, int level, int cell, int prec, void *out)
+{
+    if (!ctx || !out || level < 0 || level + 1 >= (int)ctx->levels.size()) return fail(ctx, STMG_EINVAL, "invalid argument");
+    return guarded(ctx, [&]() {
+        MgLevel &M = ctx->mg->lv[level];
+        Level &L = *M.L;
+        if (cell < 0 || cell >= L.ncell) return fail(ctx, STMG_EINVAL, "cell out of range");
+        if (!M.have_patches) return fail(ctx, STMG_ESTATE, "smoother not built (call stmg_smoother_rebuild)");
+        if (prec != ctx->mg->prec) return fail(ctx, STMG_EINVAL, "prec must equal the multigrid precision");
+        auto run = [&](auto tag) {
+            using T = decltype(tag);
+            PatchArgs<T, T> pa{};
+            pa.n0 = L.n[0];
+            pa.n1 = L.n[1];
+            pa.n2 = L.n[2];
+            pa.nt = L.nt;
+            pa.elem = M.elem.as<T>();
+            pa.rec_words = elem_record_words(L.dim, L.r);
+            for (int i = 0; i < L.nt * L.nt; ++i) pa.K[i] = L.tc.K[i];
+            for (int i = 0; i < L.nt; ++i) pa.w[i] = L.tc.w[i];
+            pa.patches = (T *)out;
+            pa.cell0 = cell;
+            STMG_HIP((launch_patch<T, T>(L.dim, L.r, pa, 1, ctx->stream)));
+            STMG_HIP(hipStreamSynchronize(ctx->stream));
+        };
+        if (prec == STMG_F64) run(double(0));
+        else run(float(0));
+        return STMG_OK;
+    });
+}
+
+int stmg_batched_lu(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
+                    const long long *p_off, int *info, void *stream)
+{
+    return batched_lu_impl(prec, A, a_off, m_of, batch, piv, p_off, info, nullptr, nullptr, stream, false);
+}
+
+int stmg_batched_lu_solve(int prec, const void *LU, const long long *a_off, const int *m_of, int batch,
+                          const int *piv, const long long *p_off, void *b, const long long *b_off, void *stream)
+{
+    if (!b || !b_off) return STMG_EINVAL;
+    return batched_lu_impl(prec, const_cast<void *>(LU), a_off, m_of, batch, const_cast<int *>(piv), p_off, nullptr,
+                           b, b_off, stream, true);
 }
 
 int stmg_level_jacobian_vmult(stmg_ctx *ctx, int level, int prec, const void *x, void *y)

@@ -281,6 +281,7 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
     if (M.piv.bytes < (size_t)L.ncell * M.m * 4) M.piv.alloc((size_t)L.ncell * M.m * 4);
     if (!M.info.p) M.info.alloc(4);
     PatchArgs<T, T> pa{};
+    pa.cell0 = -1;
     pa.n0 = L.n[0];
     pa.n1 = L.n[1];
     pa.n2 = L.n[2];

@@ -28,6 +28,7 @@ template <typename TE, typename TP> struct PatchArgs {
     double K[16];
     double w[4];
     TP *patches;           // [cell][m*m] row-major
+    int cell0;             // >= 0: assemble this cell only, into patches[0..m*m)
 };
 
 template <typename T, typename TP> struct SolveArgs {
@@ -98,6 +99,11 @@ hipError_t launch_piv_to_perm(const int *piv, int *perm, int m, long long nmat, 
 size_t solve_td_lds_bytes(int ms, int nt, size_t word);
 template <typename T, typename TP>
 hipError_t launch_solve_td(int dim, int r, const SolveTdArgs<T, TP> &a, int ncell, int ms, hipStream_t s);
+// batched triangular solves with the factors of launch_lu (variable sizes:
+// vb gives sizes and offsets; b_off the element offsets of the right-hand sides)
+template <typename T>
+hipError_t launch_batched_solve(const T *LU, const int *piv, int max_m, int batch, const LuBatch &vb,
+                                const long long *b_off, T *b, hipStream_t s);
 hipError_t launch_dense_solve(const double *LU, const int *piv, int m, const double *rhs, double *x, int nout,
                               hipStream_t s);
 hipError_t launch_identity(double *X, int n, hipStream_t s);

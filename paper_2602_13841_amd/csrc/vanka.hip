@@ -765,13 +765,13 @@ __global__ void __launch_bounds__(256) patch_kernel(PatchArgs<TE, TP> A)
 {
     using Z = VS<DIM, R>;
     constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
-    const int cell = xcd_cell(blockIdx.x, gridDim.x);
+    const int cell = A.cell0 >= 0 ? A.cell0 : xcd_cell(blockIdx.x, gridDim.x);
     const int nt = A.nt;
     const int nv = nt * DIM * NL;
     const int m = nv + nt * NPM;
     const int cc[3] = {cell % A.n0, (cell / A.n0) % A.n1, DIM == 3 ? cell / (A.n0 * A.n1) : 0};
     const int nn[3] = {A.n0, A.n1, A.n2};
-    TP *out = A.patches + (long long)cell * m * m;
+    TP *out = A.patches + (A.cell0 >= 0 ? 0LL : (long long)cell * m * m);
     const long long rw = A.rec_words;
     for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
         int row = (int)(e / m), col = (int)(e % m);
@@ -1705,6 +1705,35 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP>
     }
 }
 
+// batched solves with variable sizes: one workgroup per system
+template <typename T>
+__global__ void __launch_bounds__(SV_THREADS) batched_solve_kernel(const T *LUall, const int *pivall, LuBatch B,
+                                                                    const long long *b_off, T *ball)
+{
+    extern __shared__ unsigned char lds_raw[];
+    T *b = reinterpret_cast<T *>(lds_raw);
+    const int bid = blockIdx.x, tid = threadIdx.x;
+    const int m = B.m_of[bid];
+    T *dblk = b + ((m + 1) & ~1);
+    const T *LU = LUall + B.a_off[bid];
+    const int *piv = pivall + B.p_off[bid];
+    T *x = ball + b_off[bid];
+    for (int r = tid; r < m; r += SV_THREADS) b[r] = x[r];
+    __syncthreads();
+    if (tid == 0)
+        for (int j = 0; j < m; ++j) {
+            const int p = piv[j];
+            if (p != j) {
+                const T t = b[j];
+                b[j] = b[p];
+                b[p] = t;
+            }
+        }
+    __syncthreads();
+    lu_substitute<T>(LU, m, b, dblk);
+    for (int r = tid; r < m; r += SV_THREADS) x[r] = b[r];
+}
+
 // dense solve of one LU-factored system (coarse level): x = A^{-1} rhs
 template <typename T>
 __global__ void __launch_bounds__(SV_THREADS) dense_solve_kernel(const T *LU, const int *piv, int m, const T *rhs,
@@ -1937,6 +1966,24 @@ hipError_t launch_solve_td(int dim, int r, const SolveTdArgs<T, TP> &a, int ncel
 #undef SC
     return hipErrorInvalidValue;
 }
+
+template <typename T>
+hipError_t launch_batched_solve(const T *LU, const int *piv, int max_m, int batch, const LuBatch &vb,
+                                const long long *b_off, T *b, hipStream_t s)
+{
+    if (batch <= 0) return hipSuccess;
+    const size_t bytes = ((size_t)((max_m + 1) & ~1) + 64 * 65) * sizeof(T);
+    hipError_t e = hipFuncSetAttribute((const void *)batched_solve_kernel<T>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batched_solve_kernel<T>, dim3(batch), dim3(SV_THREADS), bytes, s, LU, piv, vb, b_off, b);
+    return hipGetLastError();
+}
+
+template hipError_t launch_batched_solve<double>(const double *, const int *, int, int, const LuBatch &,
+                                                 const long long *, double *, hipStream_t);
+template hipError_t launch_batched_solve<float>(const float *, const int *, int, int, const LuBatch &,
+                                                const long long *, float *, hipStream_t);
 
 hipError_t launch_dense_solve(const double *LU, const int *piv, int m, const double *rhs, double *x, int nout,
                               hipStream_t s)

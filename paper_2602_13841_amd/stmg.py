@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libstmg.so")
 
 STMG_F64 = 0
 STMG_F32 = 1
-STMG_NOT_CONVERGED = 1
+# return codes (include/stmg.h)
+STMG_OK, STMG_EINVAL, STMG_ENOMEM, STMG_EHIP, STMG_ESTATE, STMG_ENONFINITE, STMG_NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1
 
 
 class StmgError(RuntimeError):
@@ -100,6 +101,12 @@ _SIGS = {
     "stmg_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "stmg_timing_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "stmg_timing_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_level_patch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "stmg_batched_lu": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_batched_lu_solve": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -111,7 +118,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             if not hasattr(L, name):
-                continue
+                raise StmgError(f"{LIB_PATH} does not export {name}; rebuild the library")
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
@@ -150,6 +157,36 @@ def make_problem(dim, n, r, k, nu, tau, vertices=None, dirichlet_faces=None, gam
 def footprint_bytes(problem: Problem, options: Options | None = None) -> int:
     o = options if options is not None else default_options()
     return int(lib().stmg_footprint_bytes(ctypes.byref(problem), ctypes.byref(o)))
+
+
+def _host_i64(a):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def batched_lu(A, a_off, m_of, piv, p_off, info=None):
+    """Factor a batch of row-major matrices of mixed sizes in place (device
+    tensors A (float64/float32) and piv (int32); host offsets and sizes)."""
+    import numpy as np
+    ao, po = _host_i64(a_off), _host_i64(p_off)
+    mo = np.ascontiguousarray(m_of, dtype=np.int32)
+    prec = STMG_F64 if A.dtype == torch.float64 else STMG_F32
+    rc = lib().stmg_batched_lu(prec, _ptr(A), ao.ctypes.data, mo.ctypes.data, len(mo), _ptr(piv), po.ctypes.data,
+                               _ptr(info) if info is not None else None, _stream_ptr())
+    if rc != 0:
+        raise StmgError(f"stmg_batched_lu failed ({rc})")
+
+
+def batched_lu_solve(LU, a_off, m_of, piv, p_off, b, b_off):
+    """Solve with the factors of batched_lu; b (device) is overwritten."""
+    import numpy as np
+    ao, po, bo = _host_i64(a_off), _host_i64(p_off), _host_i64(b_off)
+    mo = np.ascontiguousarray(m_of, dtype=np.int32)
+    prec = STMG_F64 if LU.dtype == torch.float64 else STMG_F32
+    rc = lib().stmg_batched_lu_solve(prec, _ptr(LU), ao.ctypes.data, mo.ctypes.data, len(mo), _ptr(piv),
+                                     po.ctypes.data, _ptr(b), bo.ctypes.data, _stream_ptr())
+    if rc != 0:
+        raise StmgError(f"stmg_batched_lu_solve failed ({rc})")
 
 
 def serve(requests, options: Options | None = None, slots: int = 4, hbm_budget: int = 0):
@@ -307,6 +344,16 @@ class Context:
         self._check(lib().stmg_level_jacobian_vmult(self._h, level, self._prec(x.dtype), self._vec(x, x.dtype, N, "x"),
                                                     self._vec(out, x.dtype, N, "y")))
         return out
+
+    def level_patch(self, level, cell):
+        """The full space-time surrogate patch of one cell (m x m, row-major,
+        multigrid precision) after smoother_rebuild."""
+        k, r, n, _ = self.level_info(level)
+        from math import comb
+        m = (k + 1) * (self.dim * (r + 2) ** self.dim + comb(r + self.dim, self.dim))
+        out = torch.empty(m * m, dtype=self.mg_dtype, device="cuda")
+        self._check(lib().stmg_level_patch(self._h, level, cell, self.options.prec_mg, _ptr(out)))
+        return out.view(m, m)
 
     def vanka_smooth(self, level, r, d, sweeps=1):
         N = self.level_info(level)[3]
