@@ -33,7 +33,7 @@ PEAK_HBM = 8.0e12
 # HBM bytes per launch of the FP64 Jacobian volume kernel on this workload:
 # rocprofv3 --pmc FETCH_SIZE (x2, the factor a 1 GiB device copy shows) plus
 # WRITE_SIZE (x1); profiles/cell_kernel_jac_16cube_r2k2.md
-CELL_KERNEL_TRAFFIC_BYTES = (2 * 10056 + 19393) * 1024
+CELL_KERNEL_TRAFFIC_BYTES = (2 * 10062 + 19393) * 1024
 
 WORKLOAD = dict(dim=3, n=(16, 16, 16), r=2, k=2, nu=1e-2, tau=1.0 / 32)
 
@@ -177,7 +177,7 @@ def bench_batched_lu(npatch=4096, seed=6):
     rng2 = np.random.Generator(np.random.PCG64(seed + 1))
     rhs = torch.tensor(rng2.uniform(-1, 1, int(sizes.sum())), device="cuda")
     for name, dt, peak in (("fp64", torch.float64, 78.6e12), ("fp32_mfma", torch.float32, 157.3e12)):
-        A = A64.to(dt)
+        A = A64.to(dt, copy=True)   # A64 stays the unfactored reference
         piv = torch.zeros(int(sizes.sum()), dtype=torch.int32, device="cuda")
         info = torch.zeros(1, dtype=torch.int32, device="cuda")
         torch.cuda.synchronize()
@@ -185,7 +185,7 @@ def bench_batched_lu(npatch=4096, seed=6):
         e0.record()
         stmg.batched_lu(A, a_off, sizes, piv, p_off, info)
         e1.record()
-        b = rhs.to(dt)
+        b = rhs.to(dt, copy=True)   # rhs stays the right-hand side of the check
         stmg.batched_lu_solve(A, a_off, sizes, piv, p_off, b, p_off)
         e2.record()
         torch.cuda.synchronize()

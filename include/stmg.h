@@ -252,7 +252,7 @@ int stmg_newton_gmres_solve(stmg_ctx *ctx, double *u_inout, stmg_stats *stats);
  * device arrays owned by the caller; info (device, may be NULL) is
  * incremented for every exactly zero pivot.  stream: a hipStream_t or NULL.
  * Larger matrices are scheduled first.  Returns 0, STMG_EINVAL (bad sizes,
- * m > 4096) or STMG_EHIP. */
+ * m > 2048) or STMG_EHIP. */
 int stmg_batched_lu(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
                     const long long *p_off, int *info, void *stream);
 

@@ -489,6 +489,11 @@ template <int DIM, int R, int NQ, typename T, Mode MODE> struct Lds {
     using PS = PencilSizes<DIM, NQ, NFA, Z::N1, 1, Z::RP1>;
     static constexpr int TMP1 = PS::BUF1;
     static constexpr int TMP2 = PS::BUF2 > 1 ? PS::BUF2 : 1;
+    // 3D: the first pencil buffer is live only while the quadrature record is
+    // dead (forward z/y stages, backward y/z stages), so it shares its words
+    static constexpr bool T1_IN_Q = DIM == 3 && TMP1 <= Q_SIZE;
+    // only the quadrature weights and abscissae are read from LDS
+    static constexpr int QTAB = (2 * NQ + 1) & ~1;
 };
 
 } // namespace
@@ -541,8 +546,9 @@ __host__ __device__ constexpr int lds_words(int nt, int tabwords)
 {
     using Z = Sizes<DIM, R>;
     using LY = Lds<DIM, R, NQ, T, MODE>;
-    return ((tabwords + 1) & ~1) + nt * DIM * Z::NL + nt * Z::NPF + LY::NFA * Z::NL + DIM * Z::NL + Z::NPF +
-           LY::Q_SIZE + LY::TMP1 + LY::TMP2 + 64;
+    (void)tabwords;
+    return LY::QTAB + nt * DIM * Z::NL + nt * Z::NPF + LY::NFA * Z::NL + Z::NPF + LY::Q_SIZE +
+           (LY::T1_IN_Q ? 0 : LY::TMP1) + LY::TMP2 + 32;
 }
 
 // ---------------------------------------------------------------------------
@@ -571,26 +577,31 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
     // ---- LDS carve-up -------------------------------------------------------
     TableLayout lay;
     lay.init(R, NQ);
-    T *tab = sm;
-    T *xs = tab + ((lay.total + 1) & ~1);          // [nt][DIM][NL] nodal x
+    T *qtab = sm;                                  // [NQ] weights, [NQ] abscissae
+    T *xs = qtab + LY::QTAB;                       // [nt][DIM][NL] nodal x
     T *xpf = xs + nt * DIM * NL;                   // [nt][NPF] full-tensor pressure modes
     constexpr int NFA = LY::NFA;
     T *cur = xpf + nt * NPF;                       // [NFA][NL] nodal xhat^a, state^a (Jac), mixed field
     T *ns = cur + DIM * NL;                        // state (Jac)
-    T *ys = cur + NFA * NL;                        // [DIM][NL] nodal output
-    T *ypf = ys + DIM * NL;                        // [NPF] pressure output (full tensor)
+    T *ys = cur;                                   // [DIM][NL] nodal output (inputs are dead by then)
+    T *ypf = cur + NFA * NL;                       // [NPF] pressure output (full tensor)
     T *Q = ypf + NPF;                              // quadrature record
-    T *t1 = Q + LY::Q_SIZE;
-    T *t2 = t1 + LY::TMP1;
-    T *geo = t2 + LY::TMP2;                        // [8][3] vertices, [6] h_F, [1] volume
+    T *t1 = LY::T1_IN_Q ? Q : Q + LY::Q_SIZE;
+    T *t2 = Q + LY::Q_SIZE + (LY::T1_IN_Q ? 0 : LY::TMP1);
+    T *geo = t2 + LY::TMP2;                        // [8][3] vertices
 
-    for (int i = tid; i < lay.total; i += NTH) tab[i] = A.tab[i];
+    static_assert([] {
+        TableLayout t;
+        t.init(R, NQ);
+        return t.qx == t.qw + NQ;
+    }(), "quadrature weights and abscissae are adjacent in the table block");
+    for (int i = tid; i < 2 * NQ; i += NTH) qtab[i] = A.tab[lay.qw + i];
 
     // 1D matrices of the sweeps: uniform across the workgroup, read through the
     // scalar (read-only) path from global memory; point tables from LDS
     using CP = const __attribute__((address_space(4))) T *;   // constant for the whole kernel
     const CP S = (CP)(A.tab + lay.S), D = (CP)(A.tab + lay.D), Dq = (CP)(A.tab + lay.Dq), Lp = (CP)(A.tab + lay.L);
-    const T *qw = tab + lay.qw, *qx = tab + lay.qx;
+    const T *qw = qtab, *qx = qtab + NQ;
 
     // ---- cell coordinates and nodal gather ------------------------------------
     const int c0 = cell % A.n0;
@@ -605,10 +616,36 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
         return g0 + N0 * (g1 + N1g * g2);
     };
 
+    // state velocity of the next time node, prefetched into registers so its
+    // global latency overlaps the current node's work
+    constexpr int PF = (DIM * NL + NTH - 1) / NTH;
+    T spre[PF];
+    const T *st = MODE == Mode::Jac ? A.state + vec * A.sstride : nullptr;
+    auto load_state = [&](int a) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            const int e = tid + j * NTH;
+            if (e < DIM * NL) {
+                const int l = e % NL, c = e / NL;
+                spre[j] = st[a * A.Nv1 + c * A.Nn + gnode(l)];
+            }
+        }
+    };
+    if constexpr (MODE == Mode::Jac) load_state(0);
+
     const long long pbase = (long long)nt * A.Nv1;
     for (int e = tid; e < nt * DIM * NL; e += NTH) {
         int l = e % NL, c = (e / NL) % DIM, a = e / (NL * DIM);
         xs[e] = x[a * A.Nv1 + c * A.Nn + gnode(l)];
+    }
+    // pressure modes of all time nodes into registers (same batch of loads),
+    // scattered into the zeroed full-tensor array after the barrier
+    constexpr int PP = (MAX_NT * NPM + NTH - 1) / NTH;
+    T ppre[PP];
+#pragma unroll
+    for (int j = 0; j < PP; ++j) {
+        const int e = tid + j * NTH;
+        if (e < nt * NPM) ppre[j] = x[pbase + (e / NPM) * A.Np1 + (long long)cell * NPM + e % NPM];
     }
     for (int e = tid; e < nt * NPF; e += NTH) xpf[e] = 0;
     const T hcar[3] = {T(1) / A.n0, T(1) / A.n1, DIM == 3 ? T(1) / A.n2 : T(1)};
@@ -620,9 +657,10 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
         for (int a = 0; a < 3; ++a) geo[v * 3 + a] = a < DIM ? T(A.vert[vi * DIM + a]) : T(0);
     }
     __syncthreads();
-    for (int e = tid; e < nt * NPM; e += NTH) {
-        int m = e % NPM, a = e / NPM;
-        xpf[a * NPF + pmode_full<DIM, R>(m)] = x[pbase + a * A.Np1 + (long long)cell * NPM + m];
+#pragma unroll
+    for (int j = 0; j < PP; ++j) {
+        const int e = tid + j * NTH;
+        if (e < nt * NPM) xpf[(e / NPM) * NPF + pmode_full<DIM, R>(e % NPM)] = ppre[j];
     }
 
     __syncthreads();
@@ -630,20 +668,30 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
     for (int a = 0; a < nt; ++a) {
         // ---- nodal inputs: xhat^a, state^a (Jac), mixed field sum_b K_ab x^b (- phi0_a vprev)
         constexpr int MIXF = MODE == Mode::Jac ? 2 * DIM : DIM;
-        for (int e = tid; e < DIM * NL; e += NTH) {
-            const int l = e % NL, c = e / NL;
-            cur[e] = xs[(a * DIM + c) * NL + l];
-            if constexpr (MODE == Mode::Jac) {
-                const T *st = A.state + vec * A.sstride;
-                ns[e] = st[a * A.Nv1 + c * A.Nn + gnode(l)];
-            }
-            if constexpr (MODE != Mode::Mass) {
-                T m = 0;
-                for (int b = 0; b < nt; ++b) m += A.K[a * nt + b] * xs[(b * DIM + c) * NL + l];
-                if constexpr (MODE == Mode::Res) {
-                    if (A.vprev) m -= A.phi0[a] * A.vprev[c * A.Nn + gnode(l)];
+        if constexpr (MODE == Mode::Jac) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+                const int e = tid + j * NTH;
+                if (e < DIM * NL) {
+                    const int l = e % NL, c = e / NL;
+                    cur[e] = xs[(a * DIM + c) * NL + l];
+                    ns[e] = spre[j];
+                    T m = 0;
+                    for (int b = 0; b < nt; ++b) m += A.K[a * nt + b] * xs[(b * DIM + c) * NL + l];
+                    cur[MIXF * NL + e] = m;
                 }
-                cur[MIXF * NL + e] = m;
+            }
+            if (a + 1 < nt) load_state(a + 1);
+        } else {
+            for (int e = tid; e < DIM * NL; e += NTH) {
+                const int l = e % NL, c = e / NL;
+                cur[e] = xs[(a * DIM + c) * NL + l];
+                if constexpr (MODE == Mode::Res) {
+                    T m = 0;
+                    for (int b = 0; b < nt; ++b) m += A.K[a * nt + b] * xs[(b * DIM + c) * NL + l];
+                    if (A.vprev) m -= A.phi0[a] * A.vprev[c * A.Nn + gnode(l)];
+                    cur[MIXF * NL + e] = m;
+                }
             }
         }
         __syncthreads();
@@ -758,8 +806,11 @@ template <int DIM, int R, int NQ, typename T> struct FaceLds {
     static constexpr int LP = DIM == 3 ? Z::RP1 * Z::RP1 : Z::RP1;
     static constexpr int L1 = 3 * DIM * LN + LP;
     static constexpr int L2 = DIM == 3 ? 4 * DIM * Z::N1 * NQ + Z::RP1 * NQ : 1;
-    static constexpr int TMP1 = L1 > 256 ? L1 : 256;
-    static constexpr int TMP2 = (L2 > NQF ? L2 : NQF) > 256 ? (L2 > NQF ? L2 : NQF) : 256;
+    // one word per thread of the (64-thread) volume reduction in TMP1
+    static constexpr int TMP1 = L1 > 64 ? L1 : 64;
+    static constexpr int TMP2 = L2 > NQF ? L2 : NQF;
+    // face rows of the 1D tables (Se, De, Le) and the Gauss weights/abscissae
+    static constexpr int FTAB = (4 * Z::N1 + 2 * Z::RP1 + 2 * NQ + 1) & ~1;
 };
 
 template <int DIM, int R, int NQ, typename T>
@@ -767,7 +818,8 @@ __host__ __device__ constexpr int face_lds_words(int tabwords)
 {
     using Z = Sizes<DIM, R>;
     using LY = FaceLds<DIM, R, NQ, T>;
-    return ((tabwords + 1) & ~1) + 4 * DIM * Z::NL + 2 * Z::NPF + LY::Q_SIZE + LY::TMP1 + LY::TMP2 + 64;
+    (void)tabwords;
+    return LY::FTAB + 3 * DIM * Z::NL + 2 * Z::NPF + LY::Q_SIZE + LY::TMP1 + LY::TMP2 + 32;
 }
 
 template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE>
@@ -796,10 +848,10 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
 
     TableLayout lay;
     lay.init(R, NQ);
-    T *tab = sm;
-    T *xs = tab + ((lay.total + 1) & ~1);          // [DIM][NL] nodal x of the time node
+    T *ftab = sm;                                  // Se, De, Le, qw, qx
+    T *xs = ftab + LY::FTAB;                       // [DIM][NL] nodal x of the time node
     T *ns = xs + DIM * NL;                         // [DIM][NL] nodal state
-    T *ys = ns + DIM * NL;                         // [DIM][NL] nodal output
+    T *ys = ns + DIM * NL;                         // [DIM][NL] nodal output (starts at the volume result)
     T *xpf = ys + DIM * NL;                        // [NPF] pressure modes (full tensor)
     T *ypf = xpf + NPF;                            // [NPF] pressure output
     T *Q = ypf + NPF;                              // face record
@@ -807,11 +859,15 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
     T *t2 = t1 + LY::TMP1;
     T *geo = t2 + LY::TMP2;                        // [8][3] vertices, [6] h_F, [1] volume
 
-    for (int i = tid; i < lay.total; i += NTH) tab[i] = A.tab[i];
+    static_assert([] {
+        TableLayout t;
+        t.init(R, NQ);
+        return t.De == t.Se + 2 * (R + 2) && t.qw == t.Le + 2 * (R + 1) && t.qx == t.qw + NQ;
+    }(), "face rows and point tables are adjacent in the table block");
     using CP = const __attribute__((address_space(4))) T *;   // constant for the whole kernel
     const CP S = (CP)(A.tab + lay.S), D = (CP)(A.tab + lay.D), Lp = (CP)(A.tab + lay.L);
-    const T *Se = tab + lay.Se, *De = tab + lay.De, *Lpe = tab + lay.Le, *qw = tab + lay.qw;
-    const T *qx = tab + lay.qx;
+    const T *Se = ftab, *De = ftab + 2 * N1, *Lpe = ftab + 4 * N1, *qw = Lpe + 2 * RP1;
+    const T *qx = qw + NQ;
 
     const int c0 = cell % A.n0;
     const int c1 = (cell / A.n0) % A.n1;
@@ -827,13 +883,54 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
     const long long pbase = (long long)nt * A.Nv1;
     const T hcar[3] = {T(1) / A.n0, T(1) / A.n1, DIM == 3 ? T(1) / A.n2 : T(1)};
     const bool mapped = A.mapped != 0;
+
+    // ---- one batch of global loads: tables, vertices, x and state of the time
+    //      node, the volume result of the cell (accumulated into), pressure
+    //      modes and pressure rows (registers, scattered after the barrier) ----
+    for (int i = tid; i < 4 * N1; i += NTH) ftab[i] = A.tab[lay.Se + i];
+    for (int i = tid; i < 2 * RP1 + 2 * NQ; i += NTH) ftab[4 * N1 + i] = A.tab[lay.Le + i];
     if (mapped && tid < (1 << DIM)) {
         int v = tid;
         int o0 = v & 1, o1 = (v >> 1) & 1, o2 = (v >> 2) & 1;
         long long vi = (c0 + o0) + (long long)(A.n0 + 1) * ((c1 + o1) + (long long)(A.n1 + 1) * (c2 + o2));
-        for (int a = 0; a < 3; ++a) geo[v * 3 + a] = a < DIM ? T(A.vert[vi * DIM + a]) : T(0);
+        for (int k = 0; k < 3; ++k) geo[v * 3 + k] = k < DIM ? T(A.vert[vi * DIM + k]) : T(0);
+    }
+    T *Ec = E + ((long long)cell * nt + a) * DIM * NL;
+    for (int e = tid; e < DIM * NL; e += NTH) {
+        const int l = e % NL, c = e / NL;
+        const long long g = a * A.Nv1 + c * A.Nn + gnode(l);
+        xs[e] = x[g];
+        if constexpr (MODE == Mode::Jac) {
+            const T *st = A.state + vec * A.sstride;
+            ns[e] = st[g];
+        }
+        ys[e] = Ec[e];
+    }
+    constexpr int PP = (NPM + NTH - 1) / NTH;
+    T px[PP], py[PP];
+#pragma unroll
+    for (int j = 0; j < PP; ++j) {
+        const int e = tid + j * NTH;
+        if (e < NPM) {
+            const long long gi = pbase + a * A.Np1 + (long long)cell * NPM + e;
+            px[j] = x[gi];
+            py[j] = y[gi];
+        }
+    }
+    for (int e = tid; e < NPF; e += NTH) {
+        xpf[e] = 0;
+        ypf[e] = 0;
     }
     __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PP; ++j) {
+        const int e = tid + j * NTH;
+        if (e < NPM) {
+            const int f = pmode_full<DIM, R>(e);
+            xpf[f] = px[j];
+            ypf[f] = py[j];
+        }
+    }
     T *hF = geo + 24;   // |K| / |F| per face id
 
     // ---- h_F of the boundary faces (reading: |K|/|F| by the cell's quadrature) ----
@@ -891,23 +988,6 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
 
     {
         const T wa = A.w[a];
-        for (int e = tid; e < DIM * NL; e += NTH) {
-            const int l = e % NL, c = e / NL;
-            const long long g = a * A.Nv1 + c * A.Nn + gnode(l);
-            xs[e] = x[g];
-            if constexpr (MODE == Mode::Jac) {
-                const T *st = A.state + vec * A.sstride;
-                ns[e] = st[g];
-            }
-            ys[e] = 0;
-        }
-        for (int e = tid; e < NPF; e += NTH) {
-            xpf[e] = 0;
-            ypf[e] = 0;
-        }
-        __syncthreads();
-        for (int e = tid; e < NPM; e += NTH) xpf[pmode_full<DIM, R>(e)] = x[pbase + a * A.Np1 + (long long)cell * NPM + e];
-        __syncthreads();
         // ---- boundary faces ----------------------------------------------------------
         {
             {
@@ -1201,14 +1281,12 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
             }
         }
 
-        // ---- add to the volume results -----------------------------------------------
-        T *Ec = E + ((long long)cell * nt + a) * DIM * NL;
-        for (int e = tid; e < DIM * NL; e += NTH) Ec[e] += ys[e];
+        // ---- volume + boundary results back --------------------------------------------
+        for (int e = tid; e < DIM * NL; e += NTH) Ec[e] = ys[e];
         for (int e = tid; e < NPM; e += NTH) {
             const long long gi = pbase + a * A.Np1 + (long long)cell * NPM + e;
-            y[gi] += ypf[pmode_full<DIM, R>(e)];
+            y[gi] = ypf[pmode_full<DIM, R>(e)];
         }
-        __syncthreads();
     }
 }
 
@@ -1216,45 +1294,62 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
 // Gather of the cell-local velocity results: y[a][c][node] = sum over the (up
 // to 2^d) cells holding the node, in a fixed order; minus rhs if given.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void gather_kernel(GatherArgs<T> G)
+template <typename T, int DIM, int R>
+__global__ void __launch_bounds__(256) gather_kernel(GatherArgs<T> G)
 {
-    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long total = (long long)G.nt * G.Nv1;
-    if (idx >= total) return;
-    const int vec = blockIdx.y;
-    const T *E = G.E + (long long)vec * G.nt * G.Nv1 / G.Nv1 * 0;   // offset below
-    long long node = idx % G.Nn;
-    long long ac = idx / G.Nn;              // a*dim + c
-    int c = (int)(ac % G.dim);
-    int a = (int)(ac / G.dim);
-    int r1 = G.r + 1, n1 = G.r + 2;
-    long long N0 = (long long)r1 * G.n0 + 1, N1 = (long long)r1 * G.n1 + 1;
-    long long g0 = node % N0, g1 = (node / N0) % N1, g2 = G.dim == 3 ? node / (N0 * N1) : 0;
-    long long gg[3] = {g0, g1, g2};
-    int ncells[3] = {G.n0, G.n1, G.n2};
-    int cl[3][2], ll[3][2], cnt[3];
+    constexpr int R1 = R + 1, NL1 = R + 2, NLOC = DIM == 3 ? NL1 * NL1 * NL1 : NL1 * NL1;
+    // node blocks: a contiguous node range per XCD (its L2 holds the cells
+    // around those nodes); y = (time node, component), z = right-hand side
+    const unsigned nblk = gridDim.x;
+    const unsigned node = (unsigned)xcd_cell((int)blockIdx.x, (int)nblk) * blockDim.x + threadIdx.x;
+    const unsigned Nn = (unsigned)G.Nn;
+    if (node >= Nn) return;
+    const int ac = blockIdx.y;                  // a * DIM + c
+    const int vec = blockIdx.z;
+    const unsigned N0 = (unsigned)(R1 * G.n0 + 1), N1 = (unsigned)(R1 * G.n1 + 1);
+    const unsigned t = node / N0;
+    const unsigned gg[3] = {node - t * N0, DIM == 3 ? t % N1 : t, DIM == 3 ? t / N1 : 0u};
+    const int ncells[3] = {G.n0, G.n1, G.n2};
+    // along each axis the node lies in cell c_lo (local index l_lo) and, on an
+    // interface between two cells, also in cell c_lo + 1 (local index 0)
+    int clo[3], llo[3];
+    bool two[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-        if (d >= G.dim) { cnt[d] = 1; cl[d][0] = 0; ll[d][0] = 0; continue; }
-        long long cc = gg[d] / r1;
-        int l = (int)(gg[d] % r1);
-        cnt[d] = 0;
-        if (l == 0 && cc > 0) { cl[d][cnt[d]] = (int)cc - 1; ll[d][cnt[d]] = r1; ++cnt[d]; }
-        if (cc < ncells[d]) { cl[d][cnt[d]] = (int)cc; ll[d][cnt[d]] = l; ++cnt[d]; }
+        clo[d] = 0;
+        llo[d] = 0;
+        two[d] = false;
+        if (d < DIM) {
+            const int cc = (int)(gg[d] / R1), l = (int)(gg[d] - (unsigned)cc * R1);
+            const bool iface = l == 0 && cc > 0;
+            clo[d] = iface ? cc - 1 : cc;
+            llo[d] = iface ? R1 : l;
+            two[d] = iface && cc < ncells[d];
+        }
     }
-    long long ncell = (long long)G.n0 * G.n1 * (G.dim == 3 ? G.n2 : 1);
-    const T *Ev = G.E + (long long)vec * ncell * G.nt * G.dim * G.nl;
-    (void)E;
+    const long long ncell = (long long)G.n0 * G.n1 * (DIM == 3 ? G.n2 : 1);
+    // E[cell][a][c][l]: the (a, c) block of a cell starts at (cell * nt * DIM + ac) * NLOC
+    const T *Ev = G.E + (long long)vec * ncell * G.nt * DIM * NLOC + (long long)ac * NLOC;
+    const long long cstride = (long long)G.nt * DIM * NLOC;
+    // all (up to 2^DIM) loads in flight at once; summed in a fixed order
+    // (z outer, x inner; lower cell first), absent cells contributing zero
+    constexpr int NC = 1 << DIM;
+    T v[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const int j0 = k & 1, j1 = (k >> 1) & 1, j2 = DIM == 3 ? (k >> 2) & 1 : 0;
+        const bool ok = (!j0 || two[0]) && (!j1 || two[1]) && (!j2 || two[2]);
+        const long long cell = (clo[0] + j0) + (long long)G.n0 * ((clo[1] + j1) + (long long)G.n1 * (clo[2] + j2));
+        const int l = (j0 ? 0 : llo[0]) + NL1 * ((j1 ? 0 : llo[1]) + NL1 * (j2 ? 0 : llo[2]));
+        v[k] = ok ? Ev[cell * cstride + l] : T(0);
+    }
     T s = 0;
-    for (int i2 = 0; i2 < cnt[2]; ++i2)
-        for (int i1 = 0; i1 < cnt[1]; ++i1)
-            for (int i0 = 0; i0 < cnt[0]; ++i0) {
-                long long cell = cl[0][i0] + (long long)G.n0 * (cl[1][i1] + (long long)G.n1 * cl[2][i2]);
-                int l = ll[0][i0] + n1 * (ll[1][i1] + n1 * ll[2][i2]);
-                s += Ev[((cell * G.nt + a) * G.dim + c) * G.nl + l];
-            }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) s += v[k];
+    const int mult = (two[0] ? 2 : 1) * (two[1] ? 2 : 1) * (two[2] ? 2 : 1);
+    const long long idx = (long long)ac * G.Nn + node;
     T *y = G.y + vec * G.ystride;
-    if (G.inv_mult) s /= T(cnt[0] * cnt[1] * cnt[2]);
+    if (G.inv_mult) s /= T(mult);
     s *= G.alpha;
     if (G.rhs) s -= G.rhs[idx];
     if (G.accumulate) s += y[idx];
@@ -1387,14 +1482,37 @@ hipError_t launch_cell_op(Mode mode, int dim, int r, int nq, const CellArgs<T> &
     return hipErrorInvalidValue;
 }
 
+template <typename T, int DIM, int R>
+static hipError_t launch_gather_t(const GatherArgs<T> &g, int nvec, hipStream_t s)
+{
+    const int threads = 256;
+    dim3 grid((unsigned)((g.Nn + threads - 1) / threads), (unsigned)(g.nt * DIM), (unsigned)nvec);
+    hipLaunchKernelGGL((gather_kernel<T, DIM, R>), grid, dim3(threads), 0, s, g);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_gather(const GatherArgs<T> &g, int nvec, hipStream_t s)
 {
-    long long total = (long long)g.nt * g.Nv1;
-    int threads = 256;
-    dim3 grid((unsigned)((total + threads - 1) / threads), nvec);
-    hipLaunchKernelGGL(gather_kernel<T>, grid, dim3(threads), 0, s, g);
-    return hipGetLastError();
+    // 32-bit node indices inside the kernel
+    if (g.Nn <= 0 || g.Nn >= (1LL << 31) || nvec < 1 || nvec > 65535) return hipErrorInvalidValue;
+    if (g.nl != (g.dim == 3 ? (g.r + 2) * (g.r + 2) * (g.r + 2) : (g.r + 2) * (g.r + 2))) return hipErrorInvalidValue;
+    if (g.dim == 2) {
+        switch (g.r) {
+        case 1: return launch_gather_t<T, 2, 1>(g, nvec, s);
+        case 2: return launch_gather_t<T, 2, 2>(g, nvec, s);
+        case 3: return launch_gather_t<T, 2, 3>(g, nvec, s);
+        default: break;
+        }
+    } else if (g.dim == 3) {
+        switch (g.r) {
+        case 1: return launch_gather_t<T, 3, 1>(g, nvec, s);
+        case 2: return launch_gather_t<T, 3, 2>(g, nvec, s);
+        case 3: return launch_gather_t<T, 3, 3>(g, nvec, s);
+        default: break;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 template hipError_t launch_face_op<double>(Mode, int, int, int, const CellArgs<double> &, int, hipStream_t);

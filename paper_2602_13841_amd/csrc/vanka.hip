@@ -915,6 +915,48 @@ __device__ __forceinline__ void trailing_update(double *A, int m, int j0, int nb
     }
 }
 
+// Composition of the row interchanges of one panel (row c swapped with row
+// sw[c], c = 0 .. nb-1, in order) into one permutation of the affected panel
+// rows: afterwards row aff_dst[i] holds what was in row aff_src[i].  Run by
+// one wavefront: lane i owns entry i (position, content) of the at most 2 nb
+// affected rows, lookups by ballot, swaps by shuffles.
+template <int NB>
+__device__ __forceinline__ void compose_panel_swaps(const int *sw, int nb, int *aff_dst, int *aff_src, int *n_aff)
+{
+    static_assert(2 * NB <= 64, "affected rows of a panel fit one wavefront");
+    const int lane = threadIdx.x & 63;
+    int pos = -1, cont = -1, n = 0;
+    for (int c = 0; c < nb; ++c) {
+        const int p = sw[c];
+        if (p == c) continue;
+        const unsigned long long mc = __ballot(pos == c), mp = __ballot(pos == p);
+        int ic, ip;
+        if (mc) {
+            ic = __builtin_ctzll(mc);
+        } else {
+            ic = n++;
+            if (lane == ic) pos = cont = c;
+        }
+        if (mp) {
+            ip = __builtin_ctzll(mp);
+        } else {
+            ip = n++;
+            if (lane == ip) pos = cont = p;
+        }
+        const int vc = __shfl(cont, ic, 64), vp = __shfl(cont, ip, 64);
+        if (lane == ic) cont = vp;
+        if (lane == ip) cont = vc;
+    }
+    const bool moved = lane < n && pos != cont;
+    const unsigned long long mm = __ballot(moved);
+    if (moved) {
+        const int k = __popcll(mm & ((1ull << lane) - 1ull));
+        aff_dst[k] = pos;
+        aff_src[k] = cont;
+    }
+    if (lane == 0) *n_aff = __popcll(mm);
+}
+
 template <typename T, int NB>
 __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, int *__restrict__ pivall, LuBatch B,
                                                         int *info)
@@ -980,27 +1022,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
             __syncthreads();
         }
         // composed row permutation of this panel: affected local rows dst <- src
-        if (tid == 0) {
-            int pos[2 * NB], cont[2 * NB], n = 0;
-            for (int c = 0; c < nb; ++c) {
-                int p = sw[c];
-                if (p == c) continue;
-                int ic = -1, ip = -1;
-                for (int i = 0; i < n; ++i) {
-                    if (pos[i] == c) ic = i;
-                    if (pos[i] == p) ip = i;
-                }
-                if (ic < 0) { pos[n] = c; cont[n] = c; ic = n++; }
-                if (ip < 0) { pos[n] = p; cont[n] = p; ip = n++; }
-                int t = cont[ic];
-                cont[ic] = cont[ip];
-                cont[ip] = t;
-            }
-            int k = 0;
-            for (int i = 0; i < n; ++i)
-                if (pos[i] != cont[i]) { aff_dst[k] = pos[i]; aff_src[k] = cont[i]; ++k; }
-            n_aff = k;
-        }
+        if (wv == 0) compose_panel_swaps<NB>(sw, nb, aff_dst, aff_src, &n_aff);
         __syncthreads();
         // apply the permutation to whole rows (panel columns are rewritten below)
         const int na = n_aff;
@@ -1034,11 +1056,13 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
                 const int col = cb + tid;
                 T u[NB];
                 for (int c = 0; c < NB; ++c) u[c] = c < nb ? A[(long long)(j0 + c) * m + col] : T(0);
+                // fully unrolled (register array); rows c >= nb stay zero
+#pragma unroll
                 for (int c = 1; c < NB; ++c) {
-                    if (c >= nb) break;
                     T s = u[c];
+#pragma unroll
                     for (int k = 0; k < c; ++k) s -= pan[c * NBP + k] * u[k];
-                    u[c] = s;
+                    if (c < nb) u[c] = s;
                 }
                 for (int c = 0; c < NB; ++c)
                     if (c < nb) {
@@ -1420,27 +1444,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, 
             }
             __syncthreads();
         }
-        if (tid == 0) {
-            int pos[2 * NB], cont[2 * NB], n = 0;
-            for (int c = 0; c < nb; ++c) {
-                const int p = sw[c];
-                if (p == c) continue;
-                int ic = -1, ip = -1;
-                for (int i = 0; i < n; ++i) {
-                    if (pos[i] == c) ic = i;
-                    if (pos[i] == p) ip = i;
-                }
-                if (ic < 0) { pos[n] = c; cont[n] = c; ic = n++; }
-                if (ip < 0) { pos[n] = p; cont[n] = p; ip = n++; }
-                const int t = cont[ic];
-                cont[ic] = cont[ip];
-                cont[ip] = t;
-            }
-            int k = 0;
-            for (int i = 0; i < n; ++i)
-                if (pos[i] != cont[i]) { aff_dst[k] = pos[i]; aff_src[k] = cont[i]; ++k; }
-            n_aff = k;
-        }
+        if (wv == 0) compose_panel_swaps<NB>(sw, nb, aff_dst, aff_src, &n_aff);
         __syncthreads();
         const int na = n_aff;
         if (na > 0) {
@@ -1483,16 +1487,20 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, 
                     vr[c] = ok ? Ar[(long long)(j0 + c) * m + col] : T(0);
                     vi[c] = ok ? Ai[(long long)(j0 + c) * m + col] : T(0);
                 }
+                // fully unrolled (register arrays); rows c >= nb stay zero
+#pragma unroll
                 for (int c = 1; c < NB; ++c) {
-                    if (c >= nb) break;
                     T sr = vr[c], si = vi[c];
+#pragma unroll
                     for (int k = 0; k < c; ++k) {
                         const T lr = pr[c * NBP + k], li = pi[c * NBP + k];
                         sr -= lr * vr[k] - li * vi[k];
                         si -= lr * vi[k] + li * vr[k];
                     }
-                    vr[c] = sr;
-                    vi[c] = si;
+                    if (c < nb) {
+                        vr[c] = sr;
+                        vi[c] = si;
+                    }
                 }
                 for (int c = 0; c < NB; ++c)
                     if (c < nb) {
