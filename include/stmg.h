@@ -240,8 +240,9 @@ int stmg_fgmres(stmg_ctx *ctx, const double *u_state, const double *b, double *x
 int stmg_newton_gmres_solve(stmg_ctx *ctx, double *u_inout, stmg_stats *stats);
 
 /* ---- batched patch factorizations (no context) ---------------------------
- * A batch of dense matrices of mixed sizes, factored in one launch by LU
- * with partial pivoting (the Vanka patch factorization of Sec. "Inexact
+ * A batch of dense matrices of mixed sizes, factored by LU with partial
+ * pivoting, one launch per size class (matrices within a factor 2 of the
+ * class's largest share a launch) (the Vanka patch factorization of Sec. "Inexact
  * space-time Vanka smoother" as a standalone batch; the trailing updates run
  * on MFMA in FP32).  prec: STMG_F64 or STMG_F32.  Matrix b is m_of[b] x
  * m_of[b], row-major, at element offset a_off[b] of the device array A and

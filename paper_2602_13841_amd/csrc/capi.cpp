@@ -87,8 +87,19 @@ int batched_lu_impl(int prec, void *A, const long long *a_off, const int *m_of, 
                 hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
                 lds = 65536;
             const size_t max_lds = lds > 8192 ? (size_t)lds - 8192 : (size_t)lds;
-            if (prec == STMG_F64) e = launch_lu<double>((double *)A, piv, maxm, batch, info, max_lds, s, &vb);
-            else e = launch_lu<float>((float *)A, piv, maxm, batch, info, max_lds, s, &vb);
+            // one launch per size class (consecutive sorted matrices within a
+            // factor 2 of the class's largest): each launch sizes its LDS panel
+            // for its own largest matrix, so small patches share a CU
+            e = hipSuccess;
+            for (int c0 = 0; c0 < batch && e == hipSuccess;) {
+                const int m0 = ms[c0];
+                int c1 = c0 + 1;
+                while (c1 < batch && 2 * ms[c1] > m0) ++c1;
+                LuBatch vc{m0, dm.as<int>() + c0, da.as<long long>() + c0, dp.as<long long>() + c0};
+                if (prec == STMG_F64) e = launch_lu<double>((double *)A, piv, m0, c1 - c0, info, max_lds, s, &vc);
+                else e = launch_lu<float>((float *)A, piv, m0, c1 - c0, info, max_lds, s, &vc);
+                c0 = c1;
+            }
         }
         if (e == hipErrorInvalidConfiguration) {
             (void)hipStreamSynchronize(s);

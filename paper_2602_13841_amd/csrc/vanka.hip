@@ -31,6 +31,7 @@
 #include "stmg_internal.h"
 #include "vanka.h"
 
+#include <cstdlib>
 #include <type_traits>
 
 namespace stmg {
@@ -1082,8 +1083,77 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
 // ---------------------------------------------------------------------------
 constexpr int SV_THREADS = 256;
 
+// b[r] -= L[r, kb:kb+nbk] . b[kb:kb+nbk] for rows r in [rbeg, rend) of a
+// row-major m x m factor (complex planar when CX: Lr/Li and br/bi).  One
+// 16-lane group per row, four columns per lane; each group keeps RU rows of
+// loads in flight before it reduces, so a pass over the rows costs about one
+// memory latency instead of one per row.  Per row the summation order is
+// fixed: columns l16, l16+16, l16+32, l16+48, then a 16-lane xor tree.
+template <typename T, bool CX>
+__device__ __forceinline__ void block_gemv_update(const T *__restrict__ Lr, const T *__restrict__ Li, int m, int kb,
+                                                  int nbk, int rbeg, int rend, T *br, T *bi)
+{
+    constexpr int RU = 4, NG = SV_THREADS / 16;
+    const int tid = threadIdx.x, g = tid >> 4, l16 = tid & 15;
+    T xr[4], xi[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = l16 + 16 * i;
+        const bool ok = c < nbk;
+        xr[i] = ok ? br[kb + c] : T(0);
+        xi[i] = CX && ok ? bi[kb + c] : T(0);
+    }
+#pragma unroll 1
+    for (int r0 = rbeg + g; r0 < rend; r0 += RU * NG) {
+        T lr[RU][4], li[RU][4];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            // unconditional loads from a clamped in-range address, then a
+            // select: every load of the pass is issued before the first wait
+            const int r = r0 + u * NG;
+            const long long o = (long long)min(r, rend - 1) * m + kb;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = l16 + 16 * i;
+                const bool ok = r < rend && c < nbk;
+                const long long oc = o + min(c, nbk - 1);
+                const T vr = Lr[oc];
+                lr[u][i] = ok ? vr : T(0);
+                if constexpr (CX) {
+                    const T vi = Li[oc];
+                    li[u][i] = ok ? vi : T(0);
+                } else {
+                    li[u][i] = T(0);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            T sr = 0, si = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if constexpr (CX) {
+                    sr += lr[u][i] * xr[i] - li[u][i] * xi[i];
+                    si += lr[u][i] * xi[i] + li[u][i] * xr[i];
+                } else {
+                    sr += lr[u][i] * xr[i];
+                }
+            }
+            for (int off = 8; off > 0; off >>= 1) {
+                sr += __shfl_xor(sr, off, 16);
+                if constexpr (CX) si += __shfl_xor(si, off, 16);
+            }
+            const int r = r0 + u * NG;
+            if (l16 == 0 && r < rend) {
+                br[r] -= sr;
+                if constexpr (CX) bi[r] -= si;
+            }
+        }
+    }
+}
+
 template <typename T>
-__device__ void lu_substitute(const T *__restrict__ LU, int m, T *b, T *dblk)
+__device__ __forceinline__ void lu_substitute(const T *__restrict__ LU, int m, T *b, T *dblk)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int g = tid >> 4, l16 = tid & 15;
@@ -1104,12 +1174,7 @@ __device__ void lu_substitute(const T *__restrict__ LU, int m, T *b, T *dblk)
             if (lane < nbk) b[kb + lane] = y;
         }
         __syncthreads();
-        for (int r = kb + nbk + g; r < m; r += SV_THREADS / 16) {
-            T s = 0;
-            for (int c = l16; c < nbk; c += 16) s += LU[(long long)r * m + kb + c] * b[kb + c];
-            for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
-            if (l16 == 0) b[r] -= s;
-        }
+        block_gemv_update<T, false>(LU, nullptr, m, kb, nbk, kb + nbk, m, b, nullptr);
         __syncthreads();
     }
     // backward: upper with diagonal
@@ -1131,12 +1196,7 @@ __device__ void lu_substitute(const T *__restrict__ LU, int m, T *b, T *dblk)
             if (lane < nbk) b[kb + lane] = x;
         }
         __syncthreads();
-        for (int r = g; r < kb; r += SV_THREADS / 16) {
-            T s = 0;
-            for (int c = l16; c < nbk; c += 16) s += LU[(long long)r * m + kb + c] * b[kb + c];
-            for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
-            if (l16 == 0) b[r] -= s;
-        }
+        block_gemv_update<T, false>(LU, nullptr, m, kb, nbk, 0, kb, b, nullptr);
         __syncthreads();
     }
 }
@@ -1537,7 +1597,7 @@ __global__ void piv_to_perm_kernel(const int *__restrict__ piv, int *__restrict_
 // triangular solves with a planar complex row-major LU (unit lower L, upper
 // U), rhs (br, bi) in LDS
 template <typename T>
-__device__ void lu_substitute_c(const T *__restrict__ Lr, const T *__restrict__ Li, int m, T *br, T *bi, T *dr,
+__device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const T *__restrict__ Li, int m, T *br, T *bi, T *dr,
                                 T *di)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1568,23 +1628,7 @@ __device__ void lu_substitute_c(const T *__restrict__ Lr, const T *__restrict__ 
             }
         }
         __syncthreads();
-        for (int r = kb + nbk + g; r < m; r += SV_THREADS / 16) {
-            T sr = 0, si = 0;
-            for (int c = l16; c < nbk; c += 16) {
-                const T lr = Lr[(long long)r * m + kb + c], li = Li[(long long)r * m + kb + c];
-                const T xr = br[kb + c], xi = bi[kb + c];
-                sr += lr * xr - li * xi;
-                si += lr * xi + li * xr;
-            }
-            for (int off = 8; off > 0; off >>= 1) {
-                sr += __shfl_xor(sr, off, 16);
-                si += __shfl_xor(si, off, 16);
-            }
-            if (l16 == 0) {
-                br[r] -= sr;
-                bi[r] -= si;
-            }
-        }
+        block_gemv_update<T, true>(Lr, Li, m, kb, nbk, kb + nbk, m, br, bi);
         __syncthreads();
     }
     const int nblk = (m + 63) / 64;
@@ -1621,23 +1665,7 @@ __device__ void lu_substitute_c(const T *__restrict__ Lr, const T *__restrict__ 
             }
         }
         __syncthreads();
-        for (int r = g; r < kb; r += SV_THREADS / 16) {
-            T sr = 0, si = 0;
-            for (int c = l16; c < nbk; c += 16) {
-                const T lr = Lr[(long long)r * m + kb + c], li = Li[(long long)r * m + kb + c];
-                const T xr = br[kb + c], xi = bi[kb + c];
-                sr += lr * xr - li * xi;
-                si += lr * xi + li * xr;
-            }
-            for (int off = 8; off > 0; off >>= 1) {
-                sr += __shfl_xor(sr, off, 16);
-                si += __shfl_xor(si, off, 16);
-            }
-            if (l16 == 0) {
-                br[r] -= sr;
-                bi[r] -= si;
-            }
-        }
+        block_gemv_update<T, true>(Lr, Li, m, kb, nbk, 0, kb, br, bi);
         __syncthreads();
     }
 }
@@ -1877,14 +1905,38 @@ hipError_t launch_patch(int dim, int r, const PatchArgs<TE, TP> &a, int ncell, h
     return hipErrorInvalidValue;
 }
 
+// largest panel width the patch factorizations may use: 32, or the value of
+// the tuning override STMG_LU_NB (32, 16, 8 or 4)
+static int lu_nb_cap()
+{
+    const char *e = std::getenv("STMG_LU_NB");
+    const int v = e ? std::atoi(e) : 32;
+    return v == 16 || v == 8 || v == 4 ? v : 32;
+}
+
+// LDS of one CU: the panel width is chosen so that two factorizations share
+// a CU when a panel of at least 16 columns allows it (measured on the complex
+// FP32 m = 395 patches: NB 16 with two workgroups per CU is 27 % faster than
+// NB 32 with one; NB 8 with four is slower, and so are the FP64 and the
+// mixed-size real batches when pushed to NB 8)
+constexpr size_t CU_LDS = 160 * 1024;
+
 template <typename T>
 hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds, hipStream_t s, const LuBatch *vb)
 {
     LuBatch B{};
     if (vb) B = *vb;
     else B.uniform_m = m;
+    int cap = lu_nb_cap();
+    // widest panel (at least 16) with two workgroups per CU, else the widest
+    // that fits (narrower panels lose more than the second workgroup gains)
+    for (int nb = cap; nb >= 16; nb /= 2) {
+        const size_t b = nb == 32 ? lu_lds_bytes<32, T>(m) : nb == 16 ? lu_lds_bytes<16, T>(m)
+                       : nb == 8 ? lu_lds_bytes<8, T>(m) : lu_lds_bytes<4, T>(m);
+        if (2 * b <= CU_LDS && b <= max_lds) { cap = nb; break; }
+    }
 #define LUC(NBV)                                                                                                       \
-    if (lu_lds_bytes<NBV, T>(m) <= max_lds) {                                                                          \
+    if (NBV <= cap && lu_lds_bytes<NBV, T>(m) <= max_lds) {                                                            \
         size_t bytes = lu_lds_bytes<NBV, T>(m);                                                                        \
         hipError_t e = hipFuncSetAttribute((const void *)lu_kernel<T, NBV>,                                            \
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                    \
@@ -1930,8 +1982,14 @@ hipError_t launch_patch_td(int dim, int r, const PatchTdArgs<TE, TP> &a, int nce
 template <typename T>
 hipError_t launch_lu_c(T *A, int *piv, int m, long long a_stride, int batch, int *info, size_t max_lds, hipStream_t s)
 {
+    int cap = lu_nb_cap();
+    for (int nb = cap; nb >= 16; nb /= 2) {
+        const size_t b = nb == 32 ? lu_c_lds_bytes<32, T>(m) : nb == 16 ? lu_c_lds_bytes<16, T>(m)
+                       : nb == 8 ? lu_c_lds_bytes<8, T>(m) : lu_c_lds_bytes<4, T>(m);
+        if (2 * b <= CU_LDS && b <= max_lds) { cap = nb; break; }
+    }
 #define LUC(NBV)                                                                                                       \
-    if (lu_c_lds_bytes<NBV, T>(m) <= max_lds) {                                                                        \
+    if (NBV <= cap && lu_c_lds_bytes<NBV, T>(m) <= max_lds) {                                                          \
         size_t bytes = lu_c_lds_bytes<NBV, T>(m);                                                                      \
         hipError_t e = hipFuncSetAttribute((const void *)lu_kernel_c<T, NBV>,                                          \
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                    \
