@@ -92,7 +92,8 @@ def cpu_baseline(U, X, seconds=12.0):
 
 
 SOLVE_WORKLOAD = dict(dim=3, n=(32, 32, 32), r=3, k=1, nu=1e-3, tau=1.0 / 64, perturb=0.2, vert_seed=4, v0_seed=5)
-TIMER_NAMES = ["vanka_elem", "vanka_patch", "vanka_lu", "vanka_apply", "cell_jac_f64", "cell_jac_f32", "face_jac_f64",
+TIMER_NAMES = ["vcycle_graph", "vanka_elem", "vanka_patch", "vanka_lu", "vanka_apply", "cell_jac_f64", "cell_jac_f32",
+               "face_jac_f64",
                "face_jac_f32", "gather_f64",
                "gather_f32", "cell_res_f64", "cell_mass_f64", "coarse_factor", "coarse_solve", "transfer"]
 

@@ -108,6 +108,12 @@ typedef struct {
      * rounding at (k+1)x less factor memory (the default); 0 = factor the
      * full (k+1)-node patch. */
     int vanka_time_decoupled;
+    /* 1 = each FGMRES preconditioner application (the V-cycle of the
+     * hierarchy, Sec. "Preconditioning of GMRES by hp-STMG") replays one
+     * captured HIP graph on two library-owned N-vectors (captured again after
+     * every smoother rebuild or state change; eager launches if capture is
+     * refused); 0 = eager kernel launches.  Results are identical. */
+    int use_graphs;
 } stmg_options;
 
 typedef struct {

@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 using namespace stmg;
@@ -150,6 +152,7 @@ void stmg_default_options(stmg_options *o)
     o->fgmres_maxit = 50;
     o->vanka_weighting = 1;
     o->vanka_time_decoupled = 1;
+    o->use_graphs = 1;
 }
 
 int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_ctx **out)
@@ -165,6 +168,9 @@ int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream,
     else stmg_default_options(&ctx->opt);
     ctx->stream = (hipStream_t)stream;
     int rc = guarded(ctx, [&]() {
+        // construction issues synchronous copies: never concurrent with another
+        // thread's V-cycle capture
+        std::lock_guard<std::recursive_mutex> lk(device_api_mutex());
         std::vector<double> verts;
         if (prob->vertices) {
             long long nv = 1;
@@ -182,6 +188,11 @@ int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream,
         return STMG_OK;
     });
     if (rc != STMG_OK) {
+        const char *ev = std::getenv("STMG_VERBOSE");
+        if (ev && *ev && *ev != '0') {
+            std::fprintf(stderr, "[stmg] create failed (%d): %s\n", rc, ctx->err.c_str());
+            std::fflush(stderr);
+        }
         delete ctx;
         return rc;
     }
@@ -191,6 +202,7 @@ int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream,
 
 int stmg_destroy(stmg_ctx *ctx)
 {
+    std::lock_guard<std::recursive_mutex> lk(device_api_mutex());
     delete ctx;
     return STMG_OK;
 }
@@ -257,6 +269,7 @@ size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt)
         }
     }
     total += (size_t)N0 * 8 * (3 * (size_t)maxit + 12);                       // Krylov bases, Newton vectors
+    if (o.use_graphs) total += (size_t)N0 * 8 * 2;                            // staging of the captured V-cycle
     total += 64u << 20;                                                       // tables, scratch
     return total;
 }

@@ -1050,8 +1050,13 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                                     const int pipe = w / N1, j1 = w - pipe * N1;
                                     const int grp = pipe / DIM, c = pipe - grp * DIM;
                                     const int lf = grp == 0 || grp == 1 ? c : (grp == 2 ? DIM + c : 2 * DIM + c);
-                                    pencil_apply<N1, NQ>(lay + lf * LN + j1 * N1, 1, abuf + pipe * N1 * NQ + j1 * NQ,
-                                                         1, grp == 1 ? D : S);
+                                    // uniform table pointer per branch (scalar-path loads)
+                                    if (grp == 1)
+                                        pencil_apply<N1, NQ>(lay + lf * LN + j1 * N1, 1, abuf + pipe * N1 * NQ + j1 * NQ,
+                                                             1, D);
+                                    else
+                                        pencil_apply<N1, NQ>(lay + lf * LN + j1 * N1, 1, abuf + pipe * N1 * NQ + j1 * NQ,
+                                                             1, S);
                                 } else {
                                     const int j1 = w - NPV * N1;
                                     pencil_apply<RP1, NQ>(play + j1 * RP1, 1, abuf + NPV * N1 * NQ + j1 * NQ, 1, Lp);
@@ -1065,13 +1070,15 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                                 const int grp = of / DIM, c = of - grp * DIM;
                                 if (of < 5 * DIM) {
                                     int pipe, dst;
-                                    CP M = S;
                                     if (grp == 0) { pipe = c; dst = FV + c; }
-                                    else if (grp == 1) { pipe = c; dst = FG + c * DIM + ta1; M = D; }
+                                    else if (grp == 1) { pipe = c; dst = FG + c * DIM + ta1; }
                                     else if (grp == 2) { pipe = DIM + c; dst = FG + c * DIM + ta0; }
                                     else if (grp == 3) { pipe = 2 * DIM + c; dst = FG + c * DIM + ax; }
                                     else { pipe = 3 * DIM + c; dst = FS + c; }
-                                    pencil_apply<N1, NQ>(abuf + pipe * N1 * NQ + q0, NQ, FQ + dst * NQF + q0, NQ, M);
+                                    if (grp == 1)
+                                        pencil_apply<N1, NQ>(abuf + pipe * N1 * NQ + q0, NQ, FQ + dst * NQF + q0, NQ, D);
+                                    else
+                                        pencil_apply<N1, NQ>(abuf + pipe * N1 * NQ + q0, NQ, FQ + dst * NQF + q0, NQ, S);
                                 } else {
                                     pencil_apply<RP1, NQ>(abuf + NPV * N1 * NQ + q0, NQ, FQ + FP * NQF + q0, NQ, Lp);
                                 }
@@ -1083,12 +1090,12 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                                 const int grp = w / DIM, c = w - grp * DIM;
                                 if (w < 4 * DIM) {
                                     int lf, dst;
-                                    CP M = S;
                                     if (grp == 0) { lf = c; dst = FV + c; }
-                                    else if (grp == 1) { lf = c; dst = FG + c * DIM + ta0; M = D; }
+                                    else if (grp == 1) { lf = c; dst = FG + c * DIM + ta0; }
                                     else if (grp == 2) { lf = DIM + c; dst = FG + c * DIM + ax; }
                                     else { lf = 2 * DIM + c; dst = FS + c; }
-                                    pencil_apply<N1, NQ>(lay + lf * LN, 1, FQ + dst * NQF, 1, M);
+                                    if (grp == 1) pencil_apply<N1, NQ>(lay + lf * LN, 1, FQ + dst * NQF, 1, D);
+                                    else pencil_apply<N1, NQ>(lay + lf * LN, 1, FQ + dst * NQF, 1, S);
                                 } else {
                                     pencil_apply<RP1, NQ>(play, 1, FQ + FP * NQF, 1, Lp);
                                 }

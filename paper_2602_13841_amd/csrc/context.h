@@ -5,11 +5,21 @@
 #include "stmg_internal.h"
 
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
 
 namespace stmg {
+
+// Serializes stream capture (V-cycle graphs) with the runtime calls that
+// synchronize the whole device (allocation, free, stream destruction), which
+// other host threads of the process (serving slots) may issue meanwhile.
+inline std::recursive_mutex &device_api_mutex()
+{
+    static std::recursive_mutex m;
+    return m;
+}
 
 struct HipError : std::runtime_error {
     int code;
@@ -33,6 +43,7 @@ struct DevBuf {
     {
         release();
         if (b == 0) return;
+        std::lock_guard<std::recursive_mutex> lk(device_api_mutex());
         if (hipMalloc(&p, b) != hipSuccess) {
             p = nullptr;
             throw HipError("device allocation of " + std::to_string(b) + " bytes failed", STMG_ENOMEM);
@@ -41,7 +52,10 @@ struct DevBuf {
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            std::lock_guard<std::recursive_mutex> lk(device_api_mutex());
+            (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }

@@ -97,6 +97,7 @@ void mg_build(stmg_ctx *ctx)
     mg->omega = o.vanka_omega > 0 ? o.vanka_omega : (mg->weighting ? 1.0 : 1.4 / double(1 << L0.dim));
     mg->nu1 = std::max(0, o.nu1);
     mg->nu2 = std::max(0, o.nu2);
+    mg->use_graph = o.use_graphs != 0;
     int dev = 0, lds = 65536;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
@@ -137,10 +138,10 @@ void mg_build(stmg_ctx *ctx)
         M.L = ctx->levels[l].get();
         size_t N = (size_t)M.L->N;
         M.st64.alloc(N * 8);
-        STMG_HIP(hipMemset(M.st64.p, 0, N * 8));
+        STMG_HIP(hipMemsetAsync(M.st64.p, 0, N * 8, ctx->stream));
         if (mg->prec == STMG_F32) {
             M.st32.alloc(N * 4);
-            STMG_HIP(hipMemset(M.st32.p, 0, N * 4));
+            STMG_HIP(hipMemsetAsync(M.st32.p, 0, N * 4, ctx->stream));
         }
         size_t w = mg->prec == STMG_F64 ? 8 : 4;
         M.r.alloc(N * w);
@@ -161,6 +162,7 @@ void mg_set_state(stmg_ctx *ctx, const double *u)
 {
     Mg &mg = *ctx->mg;
     hipStream_t s = ctx->stream;
+    mg.graph.reset(s);
     const int nl = (int)mg.lv.size();
     STMG_HIP(hipMemcpyAsync(mg.lv[0].st64.p, u, mg.lv[0].L->N * 8, hipMemcpyDeviceToDevice, s));
     for (int l = 1; l < nl; ++l)
@@ -306,6 +308,7 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
 void mg_rebuild(stmg_ctx *ctx)
 {
     Mg &mg = *ctx->mg;
+    mg.graph.reset(ctx->stream);
     TimerScope ts(&ctx->timers, "vanka_rebuild", ctx->stream);
     for (size_t l = 0; l + 1 < mg.lv.size(); ++l) {
         double t0 = verbose() ? now_s() : 0.0;
@@ -416,7 +419,7 @@ template void mg_smooth<float>(stmg_ctx *, int, const float *, float *);
 template void mg_vcycle<double>(stmg_ctx *, int, const double *, double *);
 template void mg_vcycle<float>(stmg_ctx *, int, const float *, float *);
 
-void mg_precondition(stmg_ctx *ctx, const double *v, double *z)
+static void precondition_eager(stmg_ctx *ctx, const double *v, double *z)
 {
     Mg &mg = *ctx->mg;
     MgLevel &M = mg.lv[0];
@@ -428,6 +431,80 @@ void mg_precondition(stmg_ctx *ctx, const double *v, double *z)
     STMG_HIP((vec_cast<double, float>(M.L->N, v, M.r.as<float>(), s)));
     mg_vcycle<float>(ctx, 0, M.r.as<float>(), M.d.as<float>());
     STMG_HIP((vec_cast<float, double>(M.L->N, M.d.as<float>(), z, s)));
+}
+
+// capture the preconditioner application on the staging vectors; false if the
+// runtime refuses (the caller then stays eager)
+static bool capture_vcycle(stmg_ctx *ctx)
+{
+    Mg &mg = *ctx->mg;
+    VcycleGraph &G = mg.graph;
+    hipStream_t s = ctx->stream;
+    const long long N = mg.lv[0].L->N;
+    if (G.in.bytes < (size_t)N * 8) {
+        G.in.alloc((size_t)N * 8);
+        G.out.alloc((size_t)N * 8);
+        G.warm = false;
+    }
+    if (!G.warm) {
+        // one eager cycle first: lazy allocations and kernel attributes happen
+        // outside the capture
+        STMG_HIP(vec_fill<double>(N, 0.0, G.in.as<double>(), s));
+        precondition_eager(ctx, G.in.as<double>(), G.out.as<double>());
+        G.warm = true;
+    }
+    if (!G.cs) STMG_HIP(hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking));
+    std::lock_guard<std::recursive_mutex> lk(device_api_mutex());
+    // record on the private stream: every launch below reads ctx->stream
+    const bool timers_on = ctx->timers.on;
+    ctx->timers.on = false;
+    ctx->stream = G.cs;
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(G.cs, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+        try {
+            precondition_eager(ctx, G.in.as<double>(), G.out.as<double>());
+        } catch (const HipError &) {
+            ok = false;
+        }
+        const hipError_t e = hipStreamEndCapture(G.cs, &g);
+        ok = ok && e == hipSuccess && g != nullptr;
+    }
+    ctx->stream = s;
+    ctx->timers.on = timers_on;
+    if (ok) ok = hipGraphInstantiate(&G.x, g, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {
+        if (g) (void)hipGraphDestroy(g);
+        G.x = nullptr;
+        (void)hipGetLastError();
+        return false;
+    }
+    G.g = g;
+    G.valid = true;
+    return true;
+}
+
+void mg_precondition(stmg_ctx *ctx, const double *v, double *z)
+{
+    Mg &mg = *ctx->mg;
+    VcycleGraph &G = mg.graph;
+    hipStream_t s = ctx->stream;
+    if (!mg.use_graph || G.failed) {
+        precondition_eager(ctx, v, z);
+        return;
+    }
+    if (!G.valid && !capture_vcycle(ctx)) {
+        G.failed = true;
+        precondition_eager(ctx, v, z);
+        return;
+    }
+    const size_t bytes = (size_t)mg.lv[0].L->N * 8;
+    STMG_HIP(hipMemcpyAsync(G.in.p, v, bytes, hipMemcpyDeviceToDevice, s));
+    {
+        TimerScope ts(&ctx->timers, "vcycle_graph", s);
+        STMG_HIP(hipGraphLaunch(G.x, s));
+    }
+    STMG_HIP(hipMemcpyAsync(z, G.out.p, bytes, hipMemcpyDeviceToDevice, s));
 }
 
 // ---------------------------------------------------------------------------

@@ -24,6 +24,39 @@ struct MgLevel {
     DevBuf r, d, t, E;            // work vectors in the multigrid precision
 };
 
+// The FP64 preconditioner application (casts, V-cycle over all levels) as one
+// captured HIP graph: replayed for every FGMRES iteration on fixed staging
+// vectors; captured again after every rebuild or state change.
+struct VcycleGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    bool valid = false;    // captured for the current factors and states
+    bool failed = false;   // capture not possible: eager V-cycles from then on
+    bool warm = false;     // one eager V-cycle on the staging vectors has run
+    DevBuf in, out;        // FP64 staging vectors of the captured cycle
+    // private non-blocking stream the capture is recorded on (the caller's
+    // stream may be the null stream, which cannot be captured, and other
+    // threads' null-stream calls must not synchronize with a capture)
+    hipStream_t cs = nullptr;
+    void reset(hipStream_t s)
+    {
+        if (x || g) (void)hipStreamSynchronize(s);
+        std::lock_guard<std::recursive_mutex> lk(device_api_mutex());
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+        x = nullptr;
+        g = nullptr;
+        valid = false;
+    }
+    ~VcycleGraph()
+    {
+        std::lock_guard<std::recursive_mutex> lk(device_api_mutex());
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
+
 struct Mg {
     int prec = STMG_F32;
     double omega = 0.35;
@@ -38,6 +71,8 @@ struct Mg {
     bool border = false;
     bool state_set = false;
     size_t max_lds = 65536;
+    bool use_graph = true;
+    VcycleGraph graph;
 };
 
 // FGMRES and Newton workspace (FP64)

@@ -59,8 +59,15 @@ extern "C" int stmg_serve(const stmg_request *reqs, int n, const stmg_options *o
     const double t0 = clock_s();
     auto worker = [&]() {
         (void)hipSetDevice(dev);
+        // runtime calls of this thread stay legal while another slot records a
+        // V-cycle graph on its own stream
+        hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+        (void)hipThreadExchangeStreamCaptureMode(&mode);
         hipStream_t s = nullptr;
-        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
+        {
+            std::lock_guard<std::recursive_mutex> lk(stmg::device_api_mutex());
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
+        }
         for (;;) {
             int idx = -1;
             {
@@ -94,9 +101,13 @@ extern "C" int stmg_serve(const stmg_request *reqs, int n, const stmg_options *o
             if (rc == STMG_OK) {
                 stmg_sizes(ctx, &N, &Nv, nullptr);
                 long long Nv1 = Nv / (q.prob.k + 1);
-                bool ok = hipMalloc(&du, N * 8) == hipSuccess;
-                if (ok && q.rhs) ok = hipMalloc(&drhs, N * 8) == hipSuccess;
-                if (ok && q.v_prev) ok = hipMalloc(&dvp, Nv1 * 8) == hipSuccess;
+                bool ok;
+                {
+                    std::lock_guard<std::recursive_mutex> lk(stmg::device_api_mutex());
+                    ok = hipMalloc(&du, N * 8) == hipSuccess;
+                    if (ok && q.rhs) ok = hipMalloc(&drhs, N * 8) == hipSuccess;
+                    if (ok && q.v_prev) ok = hipMalloc(&dvp, Nv1 * 8) == hipSuccess;
+                }
                 if (!ok) rc = STMG_ENOMEM;
                 if (rc == STMG_OK) {
                     if (q.u_init) (void)hipMemcpyAsync(du, q.u_init, N * 8, hipMemcpyHostToDevice, s);
@@ -111,9 +122,17 @@ extern "C" int stmg_serve(const stmg_request *reqs, int n, const stmg_options *o
                     }
                 }
             }
-            if (du) (void)hipFree(du);
-            if (drhs) (void)hipFree(drhs);
-            if (dvp) (void)hipFree(dvp);
+            {
+                std::lock_guard<std::recursive_mutex> lk(stmg::device_api_mutex());
+                if (du) (void)hipFree(du);
+                if (drhs) (void)hipFree(drhs);
+                if (dvp) (void)hipFree(dvp);
+            }
+            if (rc < 0) {
+                std::fprintf(stderr, "[stmg] serve: request %d failed (%d): %s\n", idx, rc,
+                             ctx ? stmg_last_error(ctx) : "context creation failed");
+                std::fflush(stderr);
+            }
             if (ctx) stmg_destroy(ctx);
             (void)hipStreamSynchronize(s);
             R.rc = rc;
@@ -131,6 +150,7 @@ extern "C" int stmg_serve(const stmg_request *reqs, int n, const stmg_options *o
             }
             cv.notify_all();
         }
+        std::lock_guard<std::recursive_mutex> lk(stmg::device_api_mutex());
         (void)hipStreamDestroy(s);
     };
     std::vector<std::thread> th;

@@ -32,7 +32,9 @@
 #include "vanka.h"
 
 #include <cstdlib>
+#include <mutex>
 #include <type_traits>
+#include <unordered_map>
 
 namespace stmg {
 
@@ -1905,6 +1907,20 @@ hipError_t launch_patch(int dim, int r, const PatchArgs<TE, TP> &a, int ncell, h
     return hipErrorInvalidValue;
 }
 
+// dynamic-LDS limit of a kernel, raised only when a launch needs more than
+// any earlier one (keeps driver calls out of replayed or captured launches)
+static hipError_t lds_attr(const void *kern, size_t bytes)
+{
+    static std::mutex mu;
+    static std::unordered_map<const void *, size_t> set;
+    std::lock_guard<std::mutex> lk(mu);
+    size_t &have = set[kern];
+    if (bytes <= have) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) have = bytes;
+    return e;
+}
+
 // largest panel width the patch factorizations may use: 32, or the value of
 // the tuning override STMG_LU_NB (32, 16, 8 or 4)
 static int lu_nb_cap()
@@ -1938,8 +1954,7 @@ hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds
 #define LUC(NBV)                                                                                                       \
     if (NBV <= cap && lu_lds_bytes<NBV, T>(m) <= max_lds) {                                                            \
         size_t bytes = lu_lds_bytes<NBV, T>(m);                                                                        \
-        hipError_t e = hipFuncSetAttribute((const void *)lu_kernel<T, NBV>,                                            \
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                    \
+        hipError_t e = lds_attr((const void *)lu_kernel<T, NBV>, bytes);                    \
         if (e != hipSuccess) return e;                                                                                 \
         hipLaunchKernelGGL((lu_kernel<T, NBV>), dim3(batch), dim3(LU_THREADS), bytes, s, A, piv, B, info);            \
         return hipGetLastError();                                                                                      \
@@ -1955,8 +1970,7 @@ hipError_t launch_solve(int dim, int r, const SolveArgs<T, TP> &a, int ncell, in
     size_t bytes = ((size_t)((m + 1) & ~1) + 64 * 65) * sizeof(TP);
 #define SC(D, RR)                                                                                                      \
     if (dim == D && r == RR) {                                                                                         \
-        hipError_t e = hipFuncSetAttribute((const void *)solve_kernel<D, RR, T, TP>,                                   \
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                    \
+        hipError_t e = lds_attr((const void *)solve_kernel<D, RR, T, TP>, bytes);                    \
         if (e != hipSuccess) return e;                                                                                 \
         hipLaunchKernelGGL((solve_kernel<D, RR, T, TP>), dim3(ncell), dim3(SV_THREADS), bytes, s, a);                 \
         return hipGetLastError();                                                                                      \
@@ -1991,8 +2005,7 @@ hipError_t launch_lu_c(T *A, int *piv, int m, long long a_stride, int batch, int
 #define LUC(NBV)                                                                                                       \
     if (NBV <= cap && lu_c_lds_bytes<NBV, T>(m) <= max_lds) {                                                          \
         size_t bytes = lu_c_lds_bytes<NBV, T>(m);                                                                      \
-        hipError_t e = hipFuncSetAttribute((const void *)lu_kernel_c<T, NBV>,                                          \
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                    \
+        hipError_t e = lds_attr((const void *)lu_kernel_c<T, NBV>, bytes);                    \
         if (e != hipSuccess) return e;                                                                                 \
         hipLaunchKernelGGL((lu_kernel_c<T, NBV>), dim3(batch), dim3(LU_THREADS), bytes, s, A, piv, m, a_stride, info); \
         return hipGetLastError();                                                                                      \
@@ -2022,8 +2035,7 @@ hipError_t launch_solve_td(int dim, int r, const SolveTdArgs<T, TP> &a, int ncel
     size_t bytes = solve_td_lds_bytes(ms, a.nt, sizeof(TP));
 #define SC(D, RR)                                                                                                      \
     if (dim == D && r == RR) {                                                                                         \
-        hipError_t e = hipFuncSetAttribute((const void *)solve_td_kernel<D, RR, T, TP>,                                \
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                    \
+        hipError_t e = lds_attr((const void *)solve_td_kernel<D, RR, T, TP>, bytes);                    \
         if (e != hipSuccess) return e;                                                                                 \
         hipLaunchKernelGGL((solve_td_kernel<D, RR, T, TP>), dim3(ncell), dim3(SV_THREADS), bytes, s, a);              \
         return hipGetLastError();                                                                                      \
@@ -2039,8 +2051,7 @@ hipError_t launch_batched_solve(const T *LU, const int *piv, int max_m, int batc
 {
     if (batch <= 0) return hipSuccess;
     const size_t bytes = ((size_t)((max_m + 1) & ~1) + 64 * 65) * sizeof(T);
-    hipError_t e = hipFuncSetAttribute((const void *)batched_solve_kernel<T>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipError_t e = lds_attr((const void *)batched_solve_kernel<T>, bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(batched_solve_kernel<T>, dim3(batch), dim3(SV_THREADS), bytes, s, LU, piv, vb, b_off, b);
     return hipGetLastError();
@@ -2055,8 +2066,7 @@ hipError_t launch_dense_solve(const double *LU, const int *piv, int m, const dou
                               hipStream_t s)
 {
     size_t bytes = ((size_t)((m + 1) & ~1) + 64 * 65) * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void *)dense_solve_kernel<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipError_t e = lds_attr((const void *)dense_solve_kernel<double>, bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(dense_solve_kernel<double>, dim3(1), dim3(SV_THREADS), bytes, s, LU, piv, m, rhs, x, nout);
     return hipGetLastError();

@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
                 ("rb_theta_N", ctypes.c_double), ("rb_theta_L", ctypes.c_double), ("rb_kappa_abs", ctypes.c_double),
                 ("rb_stag_theta", ctypes.c_double), ("rb_stag_s", ctypes.c_int),
                 ("fgmres_maxit", ctypes.c_int), ("vanka_weighting", ctypes.c_int),
-                ("vanka_time_decoupled", ctypes.c_int)]
+                ("vanka_time_decoupled", ctypes.c_int),
+                ("use_graphs", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -190,6 +190,48 @@ def test_newton_matches_oracle(which, stmg):
     assert rel(u32, U_ref) < 1e-6
 
 
+@pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[4]], ids=[IDS[0], IDS[2], IDS[4]])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_captured_vcycle_equals_eager(case, prec, stmg):
+    """FGMRES with the preconditioner replayed from a captured HIP graph (the
+    default) gives bit-identical iterates to eager launches.  Each context
+    runs several solves: replays of one graph with eager work between them
+    (a Jacobian product, another right-hand side), then a rebuild at a second
+    state (a new capture); every solve is compared with the eager one."""
+    name, d, n, r, k, nu, tau, pert, mask, maxl = case
+    vert = I.perturbed_vertices(d, n, 0.2, 60 + r) if pert else None
+    P = stmg.STMG_F64 if prec == "f64" else stmg.STMG_F32
+    ctx = {g: stmg.Context(d, n, r, k, nu, tau, vertices=vert, dirichlet_faces=mask, prec_mg=P,
+                           max_levels=maxl, use_graphs=g) for g in (0, 1)}
+    N = ctx[0].N
+    s0 = oracle.Slab(oracle.Problem(dim=d, n=n, r=r, k=k, nu=nu, tau=tau, vertices=vert, dirichlet_mask=mask))
+    v = I.smooth_velocity(d, n, r, 31)
+    states = [s0.join(np.array([v] * s0.nt), np.zeros((s0.nt, s0.Np))), 0.3 * I.uniform(N, 32)]
+    E = S.constant_pressure_vectors(s0) if mask is None else None
+    out = {0: [], 1: []}
+    ctx[1].timing(True)
+    for si, U in enumerate(states):
+        for g in (0, 1):
+            ctx[g].smoother_rebuild(dev(U))
+        for rep in range(3):
+            b = I.uniform(N, 40 + 10 * si + rep)
+            if E is not None:
+                b = b - E @ ((E.T @ b) / np.sum(E * E, axis=0))
+            for g in (0, 1):
+                x, its, hist, conv = ctx[g].fgmres(dev(U), dev(b), 1e-8, 40)
+                y = ctx[g].jacobian_vmult(dev(U), x)      # eager work between replays
+                torch.cuda.synchronize()
+                out[g].append((x.cpu().numpy(), its, hist, y.cpu().numpy()))
+    # the replays really ran: one graph launch per preconditioner application
+    ms, launches = ctx[1].timing_get("vcycle_graph")
+    assert launches == sum(o[1] for o in out[1]), launches
+    for (x0, i0, h0, y0), (x1, i1, h1, y1) in zip(out[0], out[1]):
+        assert i0 == i1 and i0 > 0
+        assert h0 == h1
+        assert np.array_equal(x0, x1)
+        assert np.array_equal(y0, y1)
+
+
 @pytest.mark.parametrize("case", [CASES[1], CASES[3]], ids=[IDS[1], IDS[3]])
 def test_plain_sum_vanka_sweep_and_vcycle(case, stmg):
     """Literal plain sum of the patch corrections with a scalar omega (option)."""
