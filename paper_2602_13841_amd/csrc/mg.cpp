@@ -193,7 +193,10 @@ void mg_set_state(stmg_ctx *ctx, const double *u)
         STMG_HIP(launch_coarse_matrix(mg.cY.as<double>(), n, nb, Lc.nt, (long long)Lc.nt * Lc.Nv1, Lc.Np1, Lc.npm,
                                       Lc.ncell, mg.cA.as<double>(), s));
         STMG_HIP(hipMemsetAsync(mg.cinfo.p, 0, 4, s));
-        STMG_HIP(launch_lu<double>(mg.cA.as<double>(), mg.cpiv.as<int>(), m, 1, mg.cinfo.as<int>(), mg.max_lds, s));
+        // one workgroup suffices for small systems; larger ones (e.g. 3^3-cell
+        // coarse meshes, m = 2274) use the device-wide blocked factorization
+        if (m > 256) STMG_HIP(launch_lu_dense(mg.cA.as<double>(), mg.cpiv.as<int>(), m, mg.cinfo.as<int>(), s));
+        else STMG_HIP(launch_lu<double>(mg.cA.as<double>(), mg.cpiv.as<int>(), m, 1, mg.cinfo.as<int>(), mg.max_lds, s));
     }
     mg.state_set = true;
 }

@@ -106,6 +106,9 @@ hipError_t launch_batched_solve(const T *LU, const int *piv, int max_m, int batc
                                 const long long *b_off, T *b, hipStream_t s);
 hipError_t launch_dense_solve(const double *LU, const int *piv, int m, const double *rhs, double *x, int nout,
                               hipStream_t s);
+// LU with partial pivoting of one dense FP64 m x m matrix over the whole
+// device (same format and pivots as launch_lu)
+hipError_t launch_lu_dense(double *A, int *piv, int m, int *info, hipStream_t s);
 hipError_t launch_identity(double *X, int n, hipStream_t s);
 hipError_t launch_coarse_matrix(const double *Y, int n, int nb, int nt, long long pbase, long long Np1, int npm,
                                 long long ncell, double *A, hipStream_t s);

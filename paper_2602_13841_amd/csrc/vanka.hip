@@ -2062,6 +2062,184 @@ template hipError_t launch_batched_solve<double>(const double *, const int *, in
 template hipError_t launch_batched_solve<float>(const float *, const int *, int, int, const LuBatch &,
                                                 const long long *, float *, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Device-wide blocked LU with partial pivoting of ONE dense FP64 matrix (the
+// coarsest-level system): per 32-column panel, a one-workgroup panel
+// factorization, the panel's row interchanges on the other columns, the U12
+// triangular solve and a tiled trailing update over many workgroups.  Same
+// in-place format and pivot convention as lu_kernel (row j swapped with row
+// piv[j], applied in order j = 0, 1, ...).
+// ---------------------------------------------------------------------------
+constexpr int DLU_NB = 32, DLU_PANEL_THREADS = 1024, DLU_TILE = 64;
+
+__global__ void __launch_bounds__(DLU_PANEL_THREADS) dlu_panel_kernel(double *__restrict__ A, int m, int j0, int nb,
+                                                                       int *__restrict__ piv, int *info)
+{
+    __shared__ double rv[DLU_PANEL_THREADS / 64];
+    __shared__ int ri[DLU_PANEL_THREADS / 64];
+    __shared__ double urow[DLU_NB];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int c = 0; c < nb; ++c) {
+        const int col = j0 + c;
+        // pivot: largest modulus in column col on rows col .. m-1 (ties: lowest row)
+        double best = -1.0;
+        int bi = col;
+        for (int r = col + tid; r < m; r += DLU_PANEL_THREADS) {
+            const double v = fabs(A[(long long)r * m + col]);
+            if (v > best) {
+                best = v;
+                bi = r;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ov > best || (ov == best && oi < bi)) {
+                best = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            rv[wv] = best;
+            ri[wv] = bi;
+        }
+        __syncthreads();
+        double bv = rv[0];
+        int p = ri[0];
+        for (int w = 1; w < DLU_PANEL_THREADS / 64; ++w)
+            if (rv[w] > bv || (rv[w] == bv && ri[w] < p)) {
+                bv = rv[w];
+                p = ri[w];
+            }
+        if (tid == 0) {
+            piv[col] = p;
+            if (bv == 0.0 && info) atomicAdd(info, 1);
+        }
+        // interchange inside the panel columns, then the pivot row to LDS
+        if (p != col && tid < nb) {
+            const long long a = (long long)col * m + j0 + tid, b = (long long)p * m + j0 + tid;
+            const double t = A[a];
+            A[a] = A[b];
+            A[b] = t;
+        }
+        __syncthreads();
+        if (tid < nb - c) urow[tid] = A[(long long)col * m + col + tid];
+        __syncthreads();
+        const double d = urow[0];
+        const double inv = d != 0.0 ? 1.0 / d : 0.0;
+        for (int r = col + 1 + tid; r < m; r += DLU_PANEL_THREADS) {
+            double *row = A + (long long)r * m;
+            const double l = row[col] * inv;
+            row[col] = l;
+            for (int cc = 1; cc < nb - c; ++cc) row[col + cc] -= l * urow[cc];
+        }
+        __syncthreads();
+    }
+}
+
+// the panel's interchanges on every column outside the panel, in order
+__global__ void dlu_swap_kernel(double *__restrict__ A, int m, int j0, int nb, const int *__restrict__ piv)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m || (j >= j0 && j < j0 + nb)) return;
+    for (int c = 0; c < nb; ++c) {
+        const int r = j0 + c, p = piv[r];
+        if (p != r) {
+            const double t = A[(long long)r * m + j];
+            A[(long long)r * m + j] = A[(long long)p * m + j];
+            A[(long long)p * m + j] = t;
+        }
+    }
+}
+
+// U12 = L11^{-1} A12 (unit lower L11), one column per thread
+__global__ void __launch_bounds__(256) dlu_trsm_kernel(double *__restrict__ A, int m, int j0, int nb)
+{
+    __shared__ double L[DLU_NB][DLU_NB + 1];
+    for (int e = threadIdx.x; e < DLU_NB * DLU_NB; e += blockDim.x) {
+        const int i = e / DLU_NB, k = e % DLU_NB;
+        L[i][k] = i < nb && k < nb ? A[(long long)(j0 + i) * m + j0 + k] : 0.0;
+    }
+    __syncthreads();
+    const int j = j0 + nb + blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double u[DLU_NB];
+#pragma unroll
+    for (int c = 0; c < DLU_NB; ++c) u[c] = c < nb ? A[(long long)(j0 + c) * m + j] : 0.0;
+#pragma unroll
+    for (int c = 1; c < DLU_NB; ++c) {
+        double sacc = u[c];
+#pragma unroll
+        for (int k = 0; k < c; ++k) sacc -= L[c][k] * u[k];
+        if (c < nb) u[c] = sacc;
+    }
+#pragma unroll
+    for (int c = 0; c < DLU_NB; ++c)
+        if (c < nb) A[(long long)(j0 + c) * m + j] = u[c];
+}
+
+// A22 -= L21 U12 on 64 x 64 tiles, 4 x 4 outputs per thread
+__global__ void __launch_bounds__(256) dlu_update_kernel(double *__restrict__ A, int m, int j0, int nb)
+{
+    __shared__ double Ls[DLU_TILE][DLU_NB + 1];
+    __shared__ double Us[DLU_NB][DLU_TILE + 1];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int base = j0 + nb;
+    const int r0 = base + blockIdx.y * DLU_TILE, c0 = base + blockIdx.x * DLU_TILE;
+    for (int e = tid; e < DLU_TILE * DLU_NB; e += 256) {
+        const int i = e / DLU_NB, k = e % DLU_NB, r = r0 + i;
+        Ls[i][k] = r < m && k < nb ? A[(long long)r * m + j0 + k] : 0.0;
+    }
+    for (int e = tid; e < DLU_NB * DLU_TILE; e += 256) {
+        const int k = e / DLU_TILE, jj = e % DLU_TILE, c = c0 + jj;
+        Us[k][jj] = k < nb && c < m ? A[(long long)(j0 + k) * m + c] : 0.0;
+    }
+    __syncthreads();
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < DLU_NB; ++k) {
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = Ls[ty + 16 * i][k];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = Us[k][tx + 16 * j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
+            if (r < m && c < m) A[(long long)r * m + c] -= acc[i][j];
+        }
+}
+
+hipError_t launch_lu_dense(double *A, int *piv, int m, int *info, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    for (int j0 = 0; j0 < m; j0 += DLU_NB) {
+        const int nb = min(DLU_NB, m - j0);
+        hipLaunchKernelGGL(dlu_panel_kernel, dim3(1), dim3(DLU_PANEL_THREADS), 0, s, A, m, j0, nb, piv, info);
+        hipLaunchKernelGGL(dlu_swap_kernel, dim3((m + 255) / 256), dim3(256), 0, s, A, m, j0, nb, (const int *)piv);
+        const int rest = m - j0 - nb;
+        if (rest > 0) {
+            hipLaunchKernelGGL(dlu_trsm_kernel, dim3((rest + 255) / 256), dim3(256), 0, s, A, m, j0, nb);
+            const int nt = (rest + DLU_TILE - 1) / DLU_TILE;
+            hipLaunchKernelGGL(dlu_update_kernel, dim3(nt, nt), dim3(256), 0, s, A, m, j0, nb);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_dense_solve(const double *LU, const int *piv, int m, const double *rhs, double *x, int nout,
                               hipStream_t s)
 {
