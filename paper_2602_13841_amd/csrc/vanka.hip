@@ -853,34 +853,58 @@ __device__ __forceinline__ void trailing_update(float *A, int m, int j0, int nb,
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r0 = j0 + nb;
-    const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32;
-    for (int t = wv; t < nrt * nct; t += LU_THREADS / 64) {
+    const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32, ntile = nrt * nct;
+    // each wave walks its tiles t = wv, wv + 4, ...; the next tile's C block is
+    // loaded before the current one is computed (tiles are disjoint)
+    auto load = [&](int t, floatx4_t (&c)[2][2]) {
         const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
-        floatx4_t acc[2][2];
+#pragma unroll
         for (int si = 0; si < 2; ++si)
+#pragma unroll
             for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
-                    acc[si][sj][i] = (row < m && col < cb + ncb) ? A[(long long)row * m + col] : 0.0f;
+                    const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
+                    c[si][sj][i] = (row < m && col < cb + ncb) ? A[(long long)row * m + col] : 0.0f;
                 }
+    };
+    floatx4_t acc[2][2], nxt[2][2];
+    if (wv < ntile) load(wv, acc);
+    for (int t = wv; t < ntile; t += LU_THREADS / 64) {
+        const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
+        const int tn = t + LU_THREADS / 64;
+        if (tn < ntile) load(tn, nxt);
         for (int k0 = 0; k0 < nb; k0 += 4) {
             const int k = k0 + (lane >> 4);
             float a[2], b[2];
+#pragma unroll
             for (int si = 0; si < 2; ++si) {
-                int row = R + 16 * si + (lane & 15);
+                const int row = R + 16 * si + (lane & 15);
                 a[si] = (row < m && k < nb) ? -pan[(row - j0) * NBP + k] : 0.0f;
             }
+#pragma unroll
             for (int sj = 0; sj < 2; ++sj) b[sj] = ut[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)];
+#pragma unroll
             for (int si = 0; si < 2; ++si)
+#pragma unroll
                 for (int sj = 0; sj < 2; ++sj)
                     acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[si], b[sj], acc[si][sj], 0, 0, 0);
         }
+#pragma unroll
         for (int si = 0; si < 2; ++si)
+#pragma unroll
             for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
+                    const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
                     if (row < m && col < cb + ncb) A[(long long)row * m + col] = acc[si][sj][i];
                 }
+        if (tn < ntile) {
+#pragma unroll
+            for (int si = 0; si < 2; ++si)
+#pragma unroll
+                for (int sj = 0; sj < 2; ++sj) acc[si][sj] = nxt[si][sj];
+        }
     }
 }
 
@@ -1086,20 +1110,20 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
 constexpr int SV_THREADS = 256;
 
 // b[r] -= L[r, kb:kb+nbk] . b[kb:kb+nbk] for rows r in [rbeg, rend) of a
-// row-major m x m factor (complex planar when CX: Lr/Li and br/bi).  One
-// 16-lane group per row, four columns per lane; each group keeps RU rows of
+// row-major m x m factor (complex planar when CX: Lr/Li and br/bi), nbk <= KB.
+// One 16-lane group per row, KB/16 columns per lane; each group keeps RU rows of
 // loads in flight before it reduces, so a pass over the rows costs about one
 // memory latency instead of one per row.  Per row the summation order is
-// fixed: columns l16, l16+16, l16+32, l16+48, then a 16-lane xor tree.
-template <typename T, bool CX>
+// fixed: columns l16, l16+16, ..., then a 16-lane xor tree.
+template <typename T, bool CX, int KB = 64>
 __device__ __forceinline__ void block_gemv_update(const T *__restrict__ Lr, const T *__restrict__ Li, int m, int kb,
                                                   int nbk, int rbeg, int rend, T *br, T *bi)
 {
-    constexpr int RU = 4, NG = SV_THREADS / 16;
+    constexpr int RU = 4, NG = SV_THREADS / 16, CPL = KB / 16;   // columns per lane
     const int tid = threadIdx.x, g = tid >> 4, l16 = tid & 15;
-    T xr[4], xi[4];
+    T xr[CPL], xi[CPL];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < CPL; ++i) {
         const int c = l16 + 16 * i;
         const bool ok = c < nbk;
         xr[i] = ok ? br[kb + c] : T(0);
@@ -1107,7 +1131,7 @@ __device__ __forceinline__ void block_gemv_update(const T *__restrict__ Lr, cons
     }
 #pragma unroll 1
     for (int r0 = rbeg + g; r0 < rend; r0 += RU * NG) {
-        T lr[RU][4], li[RU][4];
+        T lr[RU][CPL], li[RU][CPL];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             // unconditional loads from a clamped in-range address, then a
@@ -1115,7 +1139,7 @@ __device__ __forceinline__ void block_gemv_update(const T *__restrict__ Lr, cons
             const int r = r0 + u * NG;
             const long long o = (long long)min(r, rend - 1) * m + kb;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < CPL; ++i) {
                 const int c = l16 + 16 * i;
                 const bool ok = r < rend && c < nbk;
                 const long long oc = o + min(c, nbk - 1);
@@ -1133,7 +1157,7 @@ __device__ __forceinline__ void block_gemv_update(const T *__restrict__ Lr, cons
         for (int u = 0; u < RU; ++u) {
             T sr = 0, si = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < CPL; ++i) {
                 if constexpr (CX) {
                     sr += lr[u][i] * xr[i] - li[u][i] * xi[i];
                     si += lr[u][i] * xi[i] + li[u][i] * xr[i];
@@ -1154,51 +1178,51 @@ __device__ __forceinline__ void block_gemv_update(const T *__restrict__ Lr, cons
     }
 }
 
-template <typename T>
+template <typename T, int KB = 64>
 __device__ __forceinline__ void lu_substitute(const T *__restrict__ LU, int m, T *b, T *dblk)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int g = tid >> 4, l16 = tid & 15;
     // forward: unit lower
-    for (int kb = 0; kb < m; kb += 64) {
-        const int nbk = min(64, m - kb);
-        for (int e = tid; e < nbk * 64; e += SV_THREADS) {
-            int i = e / 64, j = e % 64;
-            if (j < nbk) dblk[i * 65 + j] = LU[(long long)(kb + i) * m + kb + j];
+    for (int kb = 0; kb < m; kb += KB) {
+        const int nbk = min(KB, m - kb);
+        for (int e = tid; e < nbk * KB; e += SV_THREADS) {
+            int i = e / KB, j = e % KB;
+            if (j < nbk) dblk[i * (KB + 1) + j] = LU[(long long)(kb + i) * m + kb + j];
         }
         __syncthreads();
         if (wv == 0) {
             T y = lane < nbk ? b[kb + lane] : T(0);
             for (int c = 0; c < nbk; ++c) {
                 T yc = __shfl(y, c, 64);
-                if (lane > c && lane < nbk) y -= dblk[lane * 65 + c] * yc;
+                if (lane > c && lane < nbk) y -= dblk[lane * (KB + 1) + c] * yc;
             }
             if (lane < nbk) b[kb + lane] = y;
         }
         __syncthreads();
-        block_gemv_update<T, false>(LU, nullptr, m, kb, nbk, kb + nbk, m, b, nullptr);
+        block_gemv_update<T, false, KB>(LU, nullptr, m, kb, nbk, kb + nbk, m, b, nullptr);
         __syncthreads();
     }
     // backward: upper with diagonal
-    const int nblk = (m + 63) / 64;
+    const int nblk = (m + KB - 1) / KB;
     for (int bk = nblk - 1; bk >= 0; --bk) {
-        const int kb = bk * 64, nbk = min(64, m - kb);
-        for (int e = tid; e < nbk * 64; e += SV_THREADS) {
-            int i = e / 64, j = e % 64;
-            if (j < nbk) dblk[i * 65 + j] = LU[(long long)(kb + i) * m + kb + j];
+        const int kb = bk * KB, nbk = min(KB, m - kb);
+        for (int e = tid; e < nbk * KB; e += SV_THREADS) {
+            int i = e / KB, j = e % KB;
+            if (j < nbk) dblk[i * (KB + 1) + j] = LU[(long long)(kb + i) * m + kb + j];
         }
         __syncthreads();
         if (wv == 0) {
             T x = lane < nbk ? b[kb + lane] : T(0);
             for (int c = nbk - 1; c >= 0; --c) {
-                T xc = __shfl(x, c, 64) / dblk[c * 65 + c];
+                T xc = __shfl(x, c, 64) / dblk[c * (KB + 1) + c];
                 if (lane == c) x = xc;
-                if (lane < c) x -= dblk[lane * 65 + c] * xc;
+                if (lane < c) x -= dblk[lane * (KB + 1) + c] * xc;
             }
             if (lane < nbk) b[kb + lane] = x;
         }
         __syncthreads();
-        block_gemv_update<T, false>(LU, nullptr, m, kb, nbk, 0, kb, b, nullptr);
+        block_gemv_update<T, false, KB>(LU, nullptr, m, kb, nbk, 0, kb, b, nullptr);
         __syncthreads();
     }
 }
@@ -1330,21 +1354,33 @@ __device__ __forceinline__ void trailing_update_c(float *Ar, float *Ai, int m, i
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r0 = j0 + nb;
-    const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32;
-    for (int t = wv; t < nrt * nct; t += LU_THREADS / 64) {
+    const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32, ntile = nrt * nct;
+    // the next tile's C block (both planes) is loaded before the current one
+    // is computed (tiles are disjoint)
+    auto load = [&](int t, floatx4_t (&xr)[2][2], floatx4_t (&xi)[2][2]) {
         const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
-        floatx4_t cr[2][2], ci[2][2];
+#pragma unroll
         for (int si = 0; si < 2; ++si)
+#pragma unroll
             for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
                     const bool ok = row < m && col < cb + ncb;
-                    cr[si][sj][i] = ok ? Ar[(long long)row * m + col] : 0.0f;
-                    ci[si][sj][i] = ok ? Ai[(long long)row * m + col] : 0.0f;
+                    xr[si][sj][i] = ok ? Ar[(long long)row * m + col] : 0.0f;
+                    xi[si][sj][i] = ok ? Ai[(long long)row * m + col] : 0.0f;
                 }
+    };
+    floatx4_t cr[2][2], ci[2][2], nr[2][2], ni[2][2];
+    if (wv < ntile) load(wv, cr, ci);
+    for (int t = wv; t < ntile; t += LU_THREADS / 64) {
+        const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
+        const int tn = t + LU_THREADS / 64;
+        if (tn < ntile) load(tn, nr, ni);
         for (int k0 = 0; k0 < nb; k0 += 4) {
             const int k = k0 + (lane >> 4);
             float ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
             for (int si = 0; si < 2; ++si) {
                 const int row = R + 16 * si + (lane & 15);
                 const bool ok = row < m && k < nb;
@@ -1352,11 +1388,14 @@ __device__ __forceinline__ void trailing_update_c(float *Ar, float *Ai, int m, i
                 ai[si] = ok ? -pi[(row - j0) * NBP + k] : 0.0f;
                 nai[si] = -ai[si];
             }
+#pragma unroll
             for (int sj = 0; sj < 2; ++sj) {
                 br[sj] = ur[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)];
                 bi[sj] = ui[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)];
             }
+#pragma unroll
             for (int si = 0; si < 2; ++si)
+#pragma unroll
                 for (int sj = 0; sj < 2; ++sj) {
                     cr[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[si], br[sj], cr[si][sj], 0, 0, 0);
                     cr[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[si], bi[sj], cr[si][sj], 0, 0, 0);
@@ -1364,8 +1403,11 @@ __device__ __forceinline__ void trailing_update_c(float *Ar, float *Ai, int m, i
                     ci[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[si], br[sj], ci[si][sj], 0, 0, 0);
                 }
         }
+#pragma unroll
         for (int si = 0; si < 2; ++si)
+#pragma unroll
             for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
                     if (row < m && col < cb + ncb) {
@@ -1373,6 +1415,15 @@ __device__ __forceinline__ void trailing_update_c(float *Ar, float *Ai, int m, i
                         Ai[(long long)row * m + col] = ci[si][sj][i];
                     }
                 }
+        if (tn < ntile) {
+#pragma unroll
+            for (int si = 0; si < 2; ++si)
+#pragma unroll
+                for (int sj = 0; sj < 2; ++sj) {
+                    cr[si][sj] = nr[si][sj];
+                    ci[si][sj] = ni[si][sj];
+                }
+        }
     }
 }
 
@@ -1598,19 +1649,19 @@ __global__ void piv_to_perm_kernel(const int *__restrict__ piv, int *__restrict_
 
 // triangular solves with a planar complex row-major LU (unit lower L, upper
 // U), rhs (br, bi) in LDS
-template <typename T>
+template <typename T, int KB = 64>
 __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const T *__restrict__ Li, int m, T *br, T *bi, T *dr,
                                 T *di)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int g = tid >> 4, l16 = tid & 15;
-    for (int kb = 0; kb < m; kb += 64) {
-        const int nbk = min(64, m - kb);
-        for (int e = tid; e < nbk * 64; e += SV_THREADS) {
-            const int i = e / 64, j = e % 64;
+    for (int kb = 0; kb < m; kb += KB) {
+        const int nbk = min(KB, m - kb);
+        for (int e = tid; e < nbk * KB; e += SV_THREADS) {
+            const int i = e / KB, j = e % KB;
             if (j < nbk) {
-                dr[i * 65 + j] = Lr[(long long)(kb + i) * m + kb + j];
-                di[i * 65 + j] = Li[(long long)(kb + i) * m + kb + j];
+                dr[i * (KB + 1) + j] = Lr[(long long)(kb + i) * m + kb + j];
+                di[i * (KB + 1) + j] = Li[(long long)(kb + i) * m + kb + j];
             }
         }
         __syncthreads();
@@ -1619,7 +1670,7 @@ __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const 
             for (int c = 0; c < nbk; ++c) {
                 const T cr = __shfl(yr, c, 64), ci = __shfl(yi, c, 64);
                 if (lane > c && lane < nbk) {
-                    const T lr = dr[lane * 65 + c], li = di[lane * 65 + c];
+                    const T lr = dr[lane * (KB + 1) + c], li = di[lane * (KB + 1) + c];
                     yr -= lr * cr - li * ci;
                     yi -= lr * ci + li * cr;
                 }
@@ -1630,17 +1681,17 @@ __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const 
             }
         }
         __syncthreads();
-        block_gemv_update<T, true>(Lr, Li, m, kb, nbk, kb + nbk, m, br, bi);
+        block_gemv_update<T, true, KB>(Lr, Li, m, kb, nbk, kb + nbk, m, br, bi);
         __syncthreads();
     }
-    const int nblk = (m + 63) / 64;
+    const int nblk = (m + KB - 1) / KB;
     for (int bk = nblk - 1; bk >= 0; --bk) {
-        const int kb = bk * 64, nbk = min(64, m - kb);
-        for (int e = tid; e < nbk * 64; e += SV_THREADS) {
-            const int i = e / 64, j = e % 64;
+        const int kb = bk * KB, nbk = min(KB, m - kb);
+        for (int e = tid; e < nbk * KB; e += SV_THREADS) {
+            const int i = e / KB, j = e % KB;
             if (j < nbk) {
-                dr[i * 65 + j] = Lr[(long long)(kb + i) * m + kb + j];
-                di[i * 65 + j] = Li[(long long)(kb + i) * m + kb + j];
+                dr[i * (KB + 1) + j] = Lr[(long long)(kb + i) * m + kb + j];
+                di[i * (KB + 1) + j] = Li[(long long)(kb + i) * m + kb + j];
             }
         }
         __syncthreads();
@@ -1648,7 +1699,7 @@ __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const 
             T xr = lane < nbk ? br[kb + lane] : T(0), xi = lane < nbk ? bi[kb + lane] : T(0);
             for (int c = nbk - 1; c >= 0; --c) {
                 const T vr = __shfl(xr, c, 64), vi = __shfl(xi, c, 64);
-                const T ur = dr[c * 65 + c], ui = di[c * 65 + c];
+                const T ur = dr[c * (KB + 1) + c], ui = di[c * (KB + 1) + c];
                 const T den = ur * ur + ui * ui;
                 const T qr = (vr * ur + vi * ui) / den, qi = (vi * ur - vr * ui) / den;
                 if (lane == c) {
@@ -1656,7 +1707,7 @@ __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const 
                     xi = qi;
                 }
                 if (lane < c) {
-                    const T lr = dr[lane * 65 + c], li = di[lane * 65 + c];
+                    const T lr = dr[lane * (KB + 1) + c], li = di[lane * (KB + 1) + c];
                     xr -= lr * qr - li * qi;
                     xi -= lr * qi + li * qr;
                 }
@@ -1667,7 +1718,7 @@ __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const 
             }
         }
         __syncthreads();
-        block_gemv_update<T, true>(Lr, Li, m, kb, nbk, 0, kb, br, bi);
+        block_gemv_update<T, true, KB>(Lr, Li, m, kb, nbk, 0, kb, br, bi);
         __syncthreads();
     }
 }
@@ -1690,7 +1741,11 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP>
     TP *br = out + nt * MSP;
     TP *bi = br + MSP;
     TP *dr = bi + MSP;
-    TP *di = dr + 64 * 65;
+    // diagonal-block width of the substitutions: 32 keeps the LDS at a size
+    // that lets several workgroups share a CU (C3 level 0: FP64 one -> four
+    // workgroups per CU, 27.5 -> 15 ms per sweep; FP32 three -> six)
+    constexpr int KBT = 32;
+    TP *di = dr + KBT * (KBT + 1);
     const int cell = xcd_cell(blockIdx.x, gridDim.x), tid = threadIdx.x;
     const int c0 = cell % A.n0, c1 = (cell / A.n0) % A.n1, c2 = DIM == 3 ? cell / (A.n0 * A.n1) : 0;
     const long long N0 = (long long)(R + 1) * A.n0 + 1, N1g = (long long)(R + 1) * A.n1 + 1;
@@ -1725,8 +1780,8 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP>
         }
         __syncthreads();
         const TP *LU = A.sys[s] + (long long)cell * (cx ? 2 : 1) * MAT;
-        if (cx) lu_substitute_c<TP>(LU, LU + MAT, MS, br, bi, dr, di);
-        else lu_substitute<TP>(LU, MS, br, dr);
+        if (cx) lu_substitute_c<TP, KBT>(LU, LU + MAT, MS, br, bi, dr, di);
+        else lu_substitute<TP, KBT>(LU, MS, br, dr);
         for (int e = tid; e < nt * MS; e += SV_THREADS) {
             const int a = e / MS, j = e - (e / MS) * MS;
             TP v = A.Fre[a * 4 + s] * br[j];
@@ -2026,7 +2081,8 @@ hipError_t launch_piv_to_perm(const int *piv, int *perm, int m, long long nmat, 
 size_t solve_td_lds_bytes(int ms, int nt, size_t word)
 {
     const size_t msp = (size_t)((ms + 1) & ~1);
-    return (2 * nt * msp + 2 * msp + 2 * 64 * 65) * word;
+    const size_t kb = 32;   // diagonal-block width of solve_td_kernel
+    return (2 * nt * msp + 2 * msp + 2 * kb * (kb + 1)) * word;
 }
 
 template <typename T, typename TP>
