@@ -1742,8 +1742,9 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP>
     TP *bi = br + MSP;
     TP *dr = bi + MSP;
     // diagonal-block width of the substitutions: 32 keeps the LDS at a size
-    // that lets several workgroups share a CU (C3 level 0: FP64 one -> four
-    // workgroups per CU, 27.5 -> 15 ms per sweep; FP32 three -> six)
+    // that lets several workgroups share a CU (32^3, r = 3, k = 1, finest
+    // level: FP64 one -> four workgroups per CU, 27.5 -> 12.5 ms per sweep;
+    // FP32 three -> six, 9.6 -> 7.7 ms)
     constexpr int KBT = 32;
     TP *di = dr + KBT * (KBT + 1);
     const int cell = xcd_cell(blockIdx.x, gridDim.x), tid = threadIdx.x;

@@ -98,29 +98,48 @@ __global__ void combination(long long n, int nk, const double *__restrict__ y, c
     }
 }
 
-// y[ot][c][row] (+)= sum_it Tm[ot][it] sum_{k in row} val[k] x[it][c][col[k]]
+// y[ot][c][row] (+)= sum_it Tm[ot][it] sum_{k in row} val[k] x[it][c][col[k]]:
+// one thread per row reads the row's entries once for every component and
+// input time node (at most 3 and 4); per output the sums run over k in order,
+// then over it in order, skipping zero time coefficients
 template <typename T>
-__global__ void kron_csr_kernel(KronCsrArgs<T> A)
+__global__ void __launch_bounds__(256) kron_csr_kernel(KronCsrArgs<T> A)
 {
-    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long total = (long long)A.nt_out * A.ncomp * A.nrows;
-    if (idx >= total) return;
-    int row = (int)(idx % A.nrows);
-    long long rest = idx / A.nrows;
-    int c = (int)(rest % A.ncomp);
-    int ot = (int)(rest / A.ncomp);
-    int k0 = A.rowptr[row], k1 = A.rowptr[row + 1];
-    T acc = 0;
-    for (int it = 0; it < A.nt_in; ++it) {
-        T tm = A.Tm[ot * A.nt_in + it];
-        if (tm == T(0)) continue;
-        const T *xs = A.x + it * A.in_t_stride + c * A.in_c_stride;
-        T s = 0;
-        for (int k = k0; k < k1; ++k) s += A.val[k] * xs[A.col[k]];
-        acc += tm * s;
+    constexpr int MC = 3, MT = 4;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= A.nrows) return;
+    const int k0 = A.rowptr[row], k1 = A.rowptr[row + 1];
+    const int nti = A.nt_in, nc = A.ncomp;
+    T sum[MC][MT];
+#pragma unroll
+    for (int c = 0; c < MC; ++c)
+#pragma unroll
+        for (int it = 0; it < MT; ++it) sum[c][it] = T(0);
+    for (int k = k0; k < k1; ++k) {
+        const T v = A.val[k];
+        const long long cl = A.col[k];
+#pragma unroll
+        for (int c = 0; c < MC; ++c)
+#pragma unroll
+            for (int it = 0; it < MT; ++it)
+                if (c < nc && it < nti) sum[c][it] += v * A.x[it * A.in_t_stride + c * A.in_c_stride + cl];
     }
-    T *yp = A.y + ot * A.out_t_stride + c * A.out_c_stride + row;
-    *yp = A.beta == T(0) ? acc : acc + A.beta * *yp;
+#pragma unroll
+    for (int ot = 0; ot < MT; ++ot)
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+            if (ot >= A.nt_out || c >= nc) continue;
+            T acc = 0;
+#pragma unroll
+            for (int it = 0; it < MT; ++it) {
+                if (it >= nti) continue;
+                const T tm = A.Tm[ot * nti + it];
+                if (tm == T(0)) continue;
+                acc += tm * sum[c][it];
+            }
+            T *yp = A.y + ot * A.out_t_stride + c * A.out_c_stride + row;
+            *yp = A.beta == T(0) ? acc : acc + A.beta * *yp;
+        }
 }
 
 inline int grid_for(long long n, int th = 256)
@@ -176,9 +195,11 @@ hipError_t vec_combination(long long n, int nk, const double *y, const double *Z
 
 template <typename T> hipError_t kron_csr_apply(const KronCsrArgs<T> &a, hipStream_t s)
 {
-    long long total = (long long)a.nt_out * a.ncomp * a.nrows;
-    int th = 256;
-    hipLaunchKernelGGL(kron_csr_kernel<T>, dim3((unsigned)((total + th - 1) / th)), dim3(th), 0, s, a);
+    if (a.ncomp < 1 || a.ncomp > 3 || a.nt_in < 1 || a.nt_in > 4 || a.nt_out < 1 || a.nt_out > 4 || a.nrows < 0)
+        return hipErrorInvalidValue;
+    if (a.nrows == 0) return hipSuccess;
+    const int th = 256;
+    hipLaunchKernelGGL(kron_csr_kernel<T>, dim3((unsigned)((a.nrows + th - 1) / th)), dim3(th), 0, s, a);
     return hipGetLastError();
 }
 
