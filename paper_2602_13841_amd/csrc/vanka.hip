@@ -43,6 +43,30 @@ namespace {
 constexpr int ipow_(int b, int e) { return e == 0 ? 1 : b * ipow_(b, e - 1); }
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
+typedef double doublex4_t __attribute__((ext_vector_type(4)));
+
+// 16 x 16 x 4 matrix FMA per precision (v_mfma_f32_16x16x4f32 /
+// v_mfma_f64_16x16x4f64).  Operands: A lane l -> (row l%16, k l/16), B lane
+// l -> (k l/16, col l%16) in both.  The accumulator differs (measured): lane l
+// register i holds (row 4(l/16)+i, col l%16) in FP32 but (row l/16+4i, col
+// l%16) in FP64; row(g, i) gives the row for lane group g = l/16.
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    using acc = floatx4_t;
+    static __device__ __forceinline__ acc fma(float a, float b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ constexpr int row(int g, int i) { return 4 * g + i; }
+};
+template <> struct Mfma<double> {
+    using acc = doublex4_t;
+    static __device__ __forceinline__ acc fma(double a, double b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ constexpr int row(int g, int i) { return g + 4 * i; }
+};
 
 template <int DIM, int R> struct VS {
     static constexpr int N1 = R + 2;
@@ -510,38 +534,40 @@ __global__ void __launch_bounds__(EL_THREADS) elem_kernel(ElemArgs<T> A)
 }
 
 // ---------------------------------------------------------------------------
-// Volume part of the FP32 element matrices of 3D cells on MFMA.  Every entry
+// Volume part of the element matrices of 3D cells on MFMA (FP32 or FP64).  Every entry
 // is a contraction over the Gauss points, A_ij = sum_q X_i(q) Y_j(q), with
 //   K_ij    = sum_q w (nu grad phi_i . grad phi_j - (v . grad phi_i) phi_j)
 //   N^ce_ij = -sum_q w v_c d_e phi_i phi_j
 //   M_ij    = sum_q w phi_i phi_j
 //   B^c_im  = -sum_q w d_c phi_i psi_m,
-// so each 32 x 32 output tile is a set of small GEMMs (v_mfma_f32_16x16x4f32)
+// so each 32 x 32 output tile is a set of small GEMMs (16 x 16 x 4 MFMA)
 // whose k dimension runs over the points.  Operands are generated per
-// 16-point chunk from the 1D tables and the per-point record (weight, J^{-T},
+// chunk of points (16 in FP32, 8 in FP64 to bound the LDS) from the 1D tables and the per-point record (weight, J^{-T},
 // state v); wave w owns 16 x 16 subtile w of all eleven blocks (K is added to
 // the diagonal component blocks in registers).  Boundary-face terms follow in
 // a second kernel over the boundary cells.
 // ---------------------------------------------------------------------------
 constexpr int EM_THREADS = 256;
-constexpr int EM_KC = 16;                 // points per chunk (4 MFMA k-steps)
+template <typename T> constexpr int em_kc() { return sizeof(T) == 8 ? 8 : 16; }   // points per chunk
 constexpr int EM_NX = 5, EM_NY = 8;       // X {phi, g0, g1, g2, v.g};  Y {nu w g0..2, -w phi, -w v_c phi, w phi}
 constexpr int EM_PR = 13;                 // point record: w, J^{-T} (9), v (3)
 
-template <int R, int NQ>
-__global__ void __launch_bounds__(EM_THREADS) elem_mfma_kernel(ElemArgs<float> A)
+template <int R, int NQ, typename T>
+__global__ void __launch_bounds__(EM_THREADS) elem_mfma_kernel(ElemArgs<T> A)
 {
+    constexpr int EM_KC = em_kc<T>();
+    using ACC = typename Mfma<T>::acc;
     using Z = VS<3, R>;
     constexpr int N1 = Z::N1, NL = Z::NL, RP1 = Z::RP1, NPM = Z::NPM;
     constexpr int NQV = NQ * NQ * NQ;
     constexpr int NTI = (NL + 31) / 32;
     constexpr int NCH = (NQV + EM_KC - 1) / EM_KC;
-    __shared__ float tS[NQ * N1], tD[NQ * N1], tL[NQ * RP1], sqw[NQ], sqx[NQ];
-    __shared__ float vloc[3 * NL];
-    __shared__ float geo[24];
-    __shared__ float prec[NQV * EM_PR];
-    __shared__ float Xs[EM_NX][EM_KC][32];
-    __shared__ float Ys[EM_NY][EM_KC][32];
+    __shared__ T tS[NQ * N1], tD[NQ * N1], tL[NQ * RP1], sqw[NQ], sqx[NQ];
+    __shared__ T vloc[3 * NL];
+    __shared__ T geo[24];
+    __shared__ T prec[NQV * EM_PR];
+    __shared__ T Xs[EM_NX][EM_KC][32];
+    __shared__ T Ys[EM_NY][EM_KC][32];
     __shared__ int pal[32 * 3];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -577,41 +603,41 @@ __global__ void __launch_bounds__(EM_THREADS) elem_mfma_kernel(ElemArgs<float> A
     if (mapped && tid < 8) {
         const int v = tid, o0 = v & 1, o1 = (v >> 1) & 1, o2 = (v >> 2) & 1;
         const long long vi = (c0 + o0) + (long long)(A.n0 + 1) * ((c1 + o1) + (long long)(A.n1 + 1) * (c2 + o2));
-        for (int a = 0; a < 3; ++a) geo[v * 3 + a] = float(A.vert[vi * 3 + a]);
+        for (int a = 0; a < 3; ++a) geo[v * 3 + a] = T(A.vert[vi * 3 + a]);
     }
     __syncthreads();
     // point records
-    const float hcar[3] = {1.0f / A.n0, 1.0f / A.n1, 1.0f / A.n2};
+    const T hcar[3] = {T(1) / A.n0, T(1) / A.n1, T(1) / A.n2};
     for (int q = tid; q < NQV; q += EM_THREADS) {
         const int qi[3] = {q % NQ, (q / NQ) % NQ, q / (NQ * NQ)};
-        float xi[3], Jit[3][3], det;
+        T xi[3], Jit[3][3], det;
         for (int d = 0; d < 3; ++d) xi[d] = sqx[qi[d]];
         if (mapped) {
-            float J[3][3];
+            T J[3][3];
             map_jac_v<3>(geo, xi, J);
             det = inv_t_v<3>(J, Jit);
         } else {
-            det = 1.0f;
+            det = T(1);
             for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) Jit[a][b] = 0.0f;
+                for (int b = 0; b < 3; ++b) Jit[a][b] = T(0);
             for (int d = 0; d < 3; ++d) {
-                Jit[d][d] = 1.0f / hcar[d];
+                Jit[d][d] = T(1) / hcar[d];
                 det *= hcar[d];
             }
         }
-        float *P = prec + q * EM_PR;
+        T *P = prec + q * EM_PR;
         P[0] = det * sqw[qi[0]] * sqw[qi[1]] * sqw[qi[2]];
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) P[1 + 3 * a + b] = Jit[a][b];
-        float v[3] = {0.0f, 0.0f, 0.0f};
+        T v[3] = {T(0), T(0), T(0)};
 #pragma unroll 1
         for (int l2 = 0; l2 < N1; ++l2) {
-            const float s2 = tS[qi[2] * N1 + l2];
+            const T s2 = tS[qi[2] * N1 + l2];
 #pragma unroll 1
             for (int l1 = 0; l1 < N1; ++l1) {
-                const float s12 = s2 * tS[qi[1] * N1 + l1];
+                const T s12 = s2 * tS[qi[1] * N1 + l1];
                 for (int l0 = 0; l0 < N1; ++l0) {
-                    const float s = s12 * tS[qi[0] * N1 + l0];
+                    const T s = s12 * tS[qi[0] * N1 + l0];
                     const int l = (l2 * N1 + l1) * N1 + l0;
                     for (int c = 0; c < 3; ++c) v[c] += vloc[c * NL + l] * s;
                 }
@@ -622,42 +648,42 @@ __global__ void __launch_bounds__(EM_THREADS) elem_mfma_kernel(ElemArgs<float> A
     __syncthreads();
 
     // basis value and physical gradient of node l at point q (zero outside)
-    auto basis = [&](int q, int l, float &phi, float g[3], const float *&P) {
-        phi = 0.0f;
-        g[0] = g[1] = g[2] = 0.0f;
+    auto basis = [&](int q, int l, T &phi, T g[3], const T *&P) {
+        phi = T(0);
+        g[0] = g[1] = g[2] = T(0);
         P = nullptr;
         if (q >= NQV || l >= NL) return;
         const int qi0 = q % NQ, qi1 = (q / NQ) % NQ, qi2 = q / (NQ * NQ);
         const int l0 = l % N1, l1 = (l / N1) % N1, l2 = l / (N1 * N1);
-        const float s0 = tS[qi0 * N1 + l0], s1 = tS[qi1 * N1 + l1], s2 = tS[qi2 * N1 + l2];
-        const float d0 = tD[qi0 * N1 + l0], d1 = tD[qi1 * N1 + l1], d2 = tD[qi2 * N1 + l2];
-        const float gr[3] = {d0 * s1 * s2, s0 * d1 * s2, s0 * s1 * d2};
+        const T s0 = tS[qi0 * N1 + l0], s1 = tS[qi1 * N1 + l1], s2 = tS[qi2 * N1 + l2];
+        const T d0 = tD[qi0 * N1 + l0], d1 = tD[qi1 * N1 + l1], d2 = tD[qi2 * N1 + l2];
+        const T gr[3] = {d0 * s1 * s2, s0 * d1 * s2, s0 * s1 * d2};
         P = prec + q * EM_PR;
         phi = s0 * s1 * s2;
         for (int e = 0; e < 3; ++e) g[e] = P[1 + 3 * e] * gr[0] + P[2 + 3 * e] * gr[1] + P[3 + 3 * e] * gr[2];
     };
 
-    float *Avv = A.out + (long long)cell * A.rec_words;
-    float *Mv = Avv + 9 * NL * NL;
-    float *Avp = Mv + NL * NL;
-    const float nu = A.nu;
+    T *Avv = A.out + (long long)cell * A.rec_words;
+    T *Mv = Avv + 9 * NL * NL;
+    T *Avp = Mv + NL * NL;
+    const T nu = A.nu;
     const int si = wv >> 1, sj = wv & 1;
     const int ar = si * 16 + (lane & 15), bc = sj * 16 + (lane & 15), kl = lane >> 4;
 
     for (int ti = 0; ti < NTI; ++ti)
         for (int tj = 0; tj < NTI; ++tj) {
-            floatx4_t acc[11];
-            for (int b = 0; b < 11; ++b) acc[b] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
+            ACC acc[11];
+            for (int b = 0; b < 11; ++b) acc[b] = ACC{T(0), T(0), T(0), T(0)};
             for (int ch = 0; ch < NCH; ++ch) {
                 const int q0 = ch * EM_KC;
 #pragma unroll 1
                 for (int e = tid; e < 2 * EM_KC * 32; e += EM_THREADS) {
                     const int side = e / (EM_KC * 32), rr = e - side * EM_KC * 32, kq = rr >> 5, col = rr & 31;
-                    float phi, g[3];
-                    const float *P;
+                    T phi, g[3];
+                    const T *P;
                     basis(q0 + kq, (side ? tj : ti) * 32 + col, phi, g, P);
-                    const float w = P ? P[0] : 0.0f;
-                    const float v[3] = {P ? P[10] : 0.0f, P ? P[11] : 0.0f, P ? P[12] : 0.0f};
+                    const T w = P ? P[0] : T(0);
+                    const T v[3] = {P ? P[10] : T(0), P ? P[11] : T(0), P ? P[12] : T(0)};
                     if (side == 0) {
                         Xs[0][kq][col] = phi;
                         Xs[1][kq][col] = g[0];
@@ -679,36 +705,36 @@ __global__ void __launch_bounds__(EM_THREADS) elem_mfma_kernel(ElemArgs<float> A
 #pragma unroll
                 for (int k0 = 0; k0 < EM_KC; k0 += 4) {
                     const int kk = k0 + kl;
-                    const float aphi = Xs[0][kk][ar], ag0 = Xs[1][kk][ar], ag1 = Xs[2][kk][ar], ag2 = Xs[3][kk][ar];
-                    const float avg = Xs[4][kk][ar];
-                    float b[EM_NY];
+                    const T aphi = Xs[0][kk][ar], ag0 = Xs[1][kk][ar], ag1 = Xs[2][kk][ar], ag2 = Xs[3][kk][ar];
+                    const T avg = Xs[4][kk][ar];
+                    T b[EM_NY];
 #pragma unroll
                     for (int t = 0; t < EM_NY; ++t) b[t] = Ys[t][kk][bc];
-                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ag0, b[0], acc[0], 0, 0, 0);
-                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ag1, b[1], acc[0], 0, 0, 0);
-                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ag2, b[2], acc[0], 0, 0, 0);
-                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(avg, b[3], acc[0], 0, 0, 0);
-                    const float ag[3] = {ag0, ag1, ag2};
+                    acc[0] = Mfma<T>::fma(ag0, b[0], acc[0]);
+                    acc[0] = Mfma<T>::fma(ag1, b[1], acc[0]);
+                    acc[0] = Mfma<T>::fma(ag2, b[2], acc[0]);
+                    acc[0] = Mfma<T>::fma(avg, b[3], acc[0]);
+                    const T ag[3] = {ag0, ag1, ag2};
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
 #pragma unroll
                         for (int e = 0; e < 3; ++e)
-                            acc[1 + 3 * c + e] = __builtin_amdgcn_mfma_f32_16x16x4f32(ag[e], b[4 + c], acc[1 + 3 * c + e], 0, 0, 0);
-                    acc[10] = __builtin_amdgcn_mfma_f32_16x16x4f32(aphi, b[7], acc[10], 0, 0, 0);
+                            acc[1 + 3 * c + e] = Mfma<T>::fma(ag[e], b[4 + c], acc[1 + 3 * c + e]);
+                    acc[10] = Mfma<T>::fma(aphi, b[7], acc[10]);
                 }
                 __syncthreads();
             }
-            // D lane l, register i -> (row 4(l/16)+i, col l%16) of the subtile
+            // accumulator register i of lane l -> (row Mfma::row(l/16, i), col l%16)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int row = ti * 32 + si * 16 + 4 * kl + i, col = tj * 32 + sj * 16 + (lane & 15);
+                const int row = ti * 32 + si * 16 + Mfma<T>::row(kl, i), col = tj * 32 + sj * 16 + (lane & 15);
                 if (row < NL && col < NL) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
 #pragma unroll
                         for (int e = 0; e < 3; ++e)
                             Avv[((long long)(c * 3 + e) * NL + row) * NL + col] =
-                                acc[1 + 3 * c + e][i] + (c == e ? acc[0][i] : 0.0f);
+                                acc[1 + 3 * c + e][i] + (c == e ? acc[0][i] : T(0));
                     Mv[(long long)row * NL + col] = acc[10][i];
                 }
             }
@@ -716,22 +742,22 @@ __global__ void __launch_bounds__(EM_THREADS) elem_mfma_kernel(ElemArgs<float> A
 
     // velocity-pressure coupling B^c_im = -sum_q w d_c phi_i psi_m (32 mode columns, NPM valid)
     for (int ti = 0; ti < NTI; ++ti) {
-        floatx4_t acc[3];
-        for (int c = 0; c < 3; ++c) acc[c] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        ACC acc[3];
+        for (int c = 0; c < 3; ++c) acc[c] = ACC{T(0), T(0), T(0), T(0)};
         for (int ch = 0; ch < NCH; ++ch) {
             const int q0 = ch * EM_KC;
             for (int e = tid; e < 2 * EM_KC * 32; e += EM_THREADS) {
                 const int side = e / (EM_KC * 32), rr = e - side * EM_KC * 32, kq = rr >> 5, col = rr & 31;
                 const int q = q0 + kq;
                 if (side == 0) {
-                    float phi, g[3];
-                    const float *P;
+                    T phi, g[3];
+                    const T *P;
                     basis(q, ti * 32 + col, phi, g, P);
                     Xs[1][kq][col] = g[0];
                     Xs[2][kq][col] = g[1];
                     Xs[3][kq][col] = g[2];
                 } else {
-                    float val = 0.0f;
+                    T val = T(0);
                     if (q < NQV && col < NPM) {
                         const int qi0 = q % NQ, qi1 = (q / NQ) % NQ, qi2 = q / (NQ * NQ);
                         val = -prec[q * EM_PR] * tL[qi0 * RP1 + pal[col * 3]] * tL[qi1 * RP1 + pal[col * 3 + 1]] *
@@ -744,16 +770,16 @@ __global__ void __launch_bounds__(EM_THREADS) elem_mfma_kernel(ElemArgs<float> A
 #pragma unroll
             for (int k0 = 0; k0 < EM_KC; k0 += 4) {
                 const int kk = k0 + kl;
-                const float bp = Ys[0][kk][bc];
+                const T bp = Ys[0][kk][bc];
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(Xs[1 + c][kk][ar], bp, acc[c], 0, 0, 0);
+                    acc[c] = Mfma<T>::fma(Xs[1 + c][kk][ar], bp, acc[c]);
             }
             __syncthreads();
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int row = ti * 32 + si * 16 + 4 * kl + i, m = sj * 16 + (lane & 15);
+            const int row = ti * 32 + si * 16 + Mfma<T>::row(kl, i), m = sj * 16 + (lane & 15);
             if (row < NL && m < NPM)
                 for (int c = 0; c < 3; ++c) Avp[((long long)c * NL + row) * NPM + m] = acc[c][i];
         }
@@ -1926,11 +1952,11 @@ int elem_record_words(int dim, int r)
 template <typename T>
 hipError_t launch_elem(int dim, int r, int nq, const ElemArgs<T> &a, int ncell, hipStream_t s)
 {
-    if constexpr (std::is_same<T, float>::value) {
-        // 3D FP32: volume on MFMA, then the boundary faces
+    {
+        // 3D: volume on MFMA, then the boundary faces
 #define EMC(RR, Q)                                                                                                     \
     if (dim == 3 && r == RR && nq == Q) {                                                                              \
-        hipLaunchKernelGGL((elem_mfma_kernel<RR, Q>), dim3(ncell), dim3(EM_THREADS), 0, s, a);                        \
+        hipLaunchKernelGGL((elem_mfma_kernel<RR, Q, T>), dim3(ncell), dim3(EM_THREADS), 0, s, a);                     \
         hipError_t e = hipGetLastError();                                                                              \
         if (e != hipSuccess || a.nbcell <= 0) return e;                                                                \
         hipLaunchKernelGGL((elem_kernel<3, RR, Q, T, true>), dim3(a.nbcell), dim3(EL_THREADS), 0, s, a);              \
