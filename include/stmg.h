@@ -245,6 +245,25 @@ int stmg_fgmres(stmg_ctx *ctx, const double *u_state, const double *b, double *x
  * ||R_0||_M).  stats may be NULL. */
 int stmg_newton_gmres_solve(stmg_ctx *ctx, double *u_inout, stmg_stats *stats);
 
+/* Time marching over consecutive slabs I_1, ..., I_nslabs: the slab-by-slab
+ * solution of Problem LocAlgNS (Sec. "Space-time discretization"), each slab
+ * by stmg_newton_gmres_solve.  The previous-slab velocity of slab n >= 1 is
+ * the discrete velocity at t_{n-1}^-, i.e. the velocity block of the last
+ * time node of slab n-1's solution (the right Radau rule has its last node at
+ * the slab end).
+ *   rhs : device, slab data of slab n at rhs + n * rhs_stride (length N, as
+ *         in stmg_set_slab_data); NULL = zero data
+ *   v0  : device, the initial velocity (length Nv1); NULL = zero
+ *   u   : device, slab n's vector at u + n * u_stride (stride >= N); on entry
+ *         slab 0's entries are its Newton initial guess, slab n >= 1 starts
+ *         from slab n-1's solution; on return every slab's solution
+ *   stats: host array of nslabs entries, or NULL.
+ * Returns 0, STMG_NOT_CONVERGED if some slab stopped short of the tolerance
+ * (marching continues from its last iterate), or a negative error code
+ * (marching stops at that slab). */
+int stmg_march(stmg_ctx *ctx, int nslabs, const double *rhs, long long rhs_stride, const double *v0, double *u,
+               long long u_stride, stmg_stats *stats);
+
 /* ---- batched patch factorizations (no context) ---------------------------
  * A batch of dense matrices of mixed sizes, factored by LU with partial
  * pivoting, one launch per size class (matrices within a factor 2 of the

@@ -537,6 +537,33 @@ int stmg_newton_gmres_solve(stmg_ctx *ctx, double *u_inout, stmg_stats *stats)
     return guarded(ctx, [&]() { return newton_solve(ctx, u_inout, stats); });
 }
 
+int stmg_march(stmg_ctx *ctx, int nslabs, const double *rhs, long long rhs_stride, const double *v0, double *u,
+               long long u_stride, stmg_stats *stats)
+{
+    if (!ctx || !u || nslabs < 0) return fail(ctx, STMG_EINVAL, "invalid argument");
+    const Level &L = *ctx->levels[0];
+    if (u_stride < L.N || (rhs && rhs_stride < L.N)) return fail(ctx, STMG_EINVAL, "stride below the slab size");
+    int worst = STMG_OK;
+    for (int n = 0; n < nslabs; ++n) {
+        double *un = u + (long long)n * u_stride;
+        // velocity at the end of the previous slab: its last time node
+        const double *vp = n == 0 ? v0 : u + (long long)(n - 1) * u_stride + (long long)L.k * L.Nv1;
+        int rc = stmg_set_slab_data(ctx, rhs ? rhs + (long long)n * rhs_stride : nullptr, vp);
+        if (rc < 0) return rc;
+        if (n > 0) {
+            rc = guarded(ctx, [&]() {
+                STMG_HIP(hipMemcpyAsync(un, un - u_stride, (size_t)L.N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+                return STMG_OK;
+            });
+            if (rc < 0) return rc;
+        }
+        rc = stmg_newton_gmres_solve(ctx, un, stats ? &stats[n] : nullptr);
+        if (rc < 0) return rc;
+        if (rc == STMG_NOT_CONVERGED) worst = rc;
+    }
+    return worst;
+}
+
 int stmg_timing_enable(stmg_ctx *ctx, int on)
 {
     if (!ctx) return STMG_EINVAL;

@@ -97,6 +97,8 @@ _SIGS = {
     "stmg_fgmres": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "stmg_newton_gmres_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_march": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p]),
     "stmg_serve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t,
                                   ctypes.c_void_p, ctypes.c_void_p]),
     "stmg_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -396,6 +398,25 @@ class Context:
         rc = self._check(lib().stmg_newton_gmres_solve(self._h, self._vec(u, torch.float64, name="u"),
                                                        ctypes.byref(st)))
         return u, st, rc
+
+    def march(self, nslabs, rhs=None, v0=None, u=None):
+        """stmg_march over `nslabs` slabs.  rhs: device (nslabs, N) FP64 or
+        None; v0: device (Nv1,) or None; u: device (nslabs, N) whose first row
+        is slab 0's initial guess (zeros if None).  Returns (u, stats, rc)."""
+        N, nv1 = self.N, self.Nv // (self.k + 1)
+        if u is None:
+            u = torch.zeros((nslabs, N), dtype=torch.float64, device="cuda")
+        if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous() or tuple(u.shape) != (nslabs, N):
+            raise StmgError(f"u: expected contiguous float64 ({nslabs}, {N}) on the device")
+        pr = None
+        if rhs is not None:
+            if rhs.dtype != torch.float64 or not rhs.is_cuda or not rhs.is_contiguous() or tuple(rhs.shape) != (nslabs, N):
+                raise StmgError(f"rhs: expected contiguous float64 ({nslabs}, {N}) on the device")
+            pr = _ptr(rhs)
+        pv = self._vec(v0, torch.float64, nv1, "v0") if v0 is not None else None
+        st = (Stats * max(nslabs, 1))()
+        rc = self._check(lib().stmg_march(self._h, nslabs, pr, N, pv, _ptr(u), N, st))
+        return u, list(st[:nslabs]), rc
 
     # ---- kernel timers -----------------------------------------------------
     def timing(self, on: bool = True):

@@ -1,0 +1,77 @@
+"""Multi-slab marching of the HIP library (stmg_march) on the manufactured
+problem of Sec. "Convergence test" (r = 3, k = r, nu = 1e-2, tau = h,
+T = 1): space-time errors against the ones the paper prints (Table
+tab:conv-ns, fixture tests/golden/conv_ns_r3.txt) and against the oracle's
+marching on the coarse meshes.  Right-hand sides and error norms come from the
+oracle (test infrastructure); every slab solve runs in the library.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from oracle import errors as E  # noqa: E402
+from oracle import manufactured as MS  # noqa: E402
+
+from test_oracle_convergence import KEYS, oracle_march, paper_errors  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stmg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_13841_amd import stmg as Sm
+    return Sm
+
+
+def gpu_march(stmg, n, prec, r=3, k=3, nu=1e-2):
+    h = 1.0 / n
+    prob = oracle.Problem(dim=2, n=(n, n), r=r, k=k, nu=nu, tau=h)
+    slab = oracle.Slab(prob)
+    # relative stopping only: with the absolute floor 1e-12 of the library
+    # default the slab-mass norm of the residual reaches it on the finest mesh
+    # before the algebraic error drops below the discretization error
+    ctx = stmg.Context(2, (n, n), r, k, nu, h, prec_mg=prec, newton_atol=0.0)
+    assert ctx.N == slab.N
+    rhs = np.stack([MS.slab_rhs(slab, s * h) for s in range(n)])
+    u, stats, rc = ctx.march(n, rhs=torch.tensor(rhs, device="cuda"))
+    assert rc == 0, rc
+    U = u.cpu().numpy()
+    acc = dict.fromkeys(KEYS, 0.0)
+    for s in range(n):
+        e = E.slab_errors(slab, U[s], s * h)
+        for key in KEYS:
+            acc[key] += e[key]
+    its = [st.fgmres_its_total / max(st.newton_its, 1) for st in stats]
+    return {key: float(np.sqrt(v)) for key, v in acc.items()}, float(np.mean([st.newton_its for st in stats])), \
+        float(np.mean(its))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_march_errors_match_paper(prec, stmg):
+    P = stmg.STMG_F32 if prec == "f32" else stmg.STMG_F64
+    g = paper_errors()
+    ns = (2, 4, 8, 16, 32)
+    res = {n: gpu_march(stmg, n, P) for n in ns}
+    for n in ns:
+        e, nl, nlin = res[n]
+        print(f"{prec} h=1/{n}: " + " ".join(f"{k}={e[k]:.5e} ({e[k] / g[1.0 / n][k] - 1:+.4f})" for k in KEYS)
+              + f" newton/slab={nl:.2f} fgmres/newton={nlin:.2f}")
+    # coarse meshes: the same numbers as the oracle's marching
+    for n in (2, 4):
+        eo = oracle_march(n)
+        for key in KEYS:
+            assert abs(res[n][0][key] / eo[key] - 1) < 1e-5, (n, key, res[n][0][key], eo[key])
+    # every mesh: within a few per cent of the printed errors
+    tol = {2: 0.03, 4: 0.01, 8: 0.01, 16: 0.02, 32: 0.03}
+    for n in ns:
+        for key in KEYS:
+            assert abs(res[n][0][key] / g[1.0 / n][key] - 1) < tol[n], (n, key, res[n][0][key], g[1.0 / n][key])
+    # observed orders on the two finest meshes
+    for key in KEYS:
+        eoc = np.log2(res[16][0][key] / res[32][0][key])
+        eoc_paper = np.log2(g[1 / 16][key] / g[1 / 32][key])
+        assert abs(eoc - eoc_paper) < 0.05, (key, eoc, eoc_paper)
