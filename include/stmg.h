@@ -114,6 +114,13 @@ typedef struct {
      * every smoother rebuild or state change; eager launches if capture is
      * refused); 0 = eager kernel launches.  Results are identical. */
     int use_graphs;
+    /* p-coarsening in time (Sec. "Preconditioning of GMRES by hp-STMG"):
+     * 0 = DG(k) kept on every level (default: the V-cycle contraction stays
+     * about 0.3 for k = 2, 3 under h-refinement); 1 = k -> floor(k/2) together
+     * with the spatial p steps, the order the paper states (contraction
+     * 0.56 -> 0.84 for k = 2 and 0.69 -> 0.96 for k = 3 from h = 1/4 to
+     * 1/32 on the 2D convergence problem). */
+    int time_coarsening;
 } stmg_options;
 
 typedef struct {

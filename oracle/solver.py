@@ -46,13 +46,18 @@ from .core import Problem, Slab
 # --------------------------------------------------------------------------
 # hierarchy
 # --------------------------------------------------------------------------
-def level_specs(prob: Problem, max_levels: int = 0):
-    """List of (k, r, n) from finest to coarsest."""
+def level_specs(prob: Problem, max_levels: int = 0, time_coarsening: bool = False):
+    """List of (k, r, n) from finest to coarsest (Sec. "Preconditioning of GMRES
+    by hp-STMG", cycle and coarsening order): first p in space, r -> max(1,
+    floor(r/2)); in time either k -> floor(k/2) with the spatial steps
+    (time_coarsening, the order the paper states) or k kept on every level
+    (default); then h while every n is even and >= 4."""
     specs = [(prob.k, prob.r, tuple(prob.n))]
     k, r, n = prob.k, prob.r, tuple(prob.n)
-    while (r > 1 or k > 1) and (max_levels == 0 or len(specs) < max_levels):
+    while (r > 1 or (time_coarsening and k > 1)) and (max_levels == 0 or len(specs) < max_levels):
         r = max(1, r // 2)
-        k = k // 2 if k >= 2 else k
+        if time_coarsening:
+            k = k // 2 if k >= 2 else k
         specs.append((k, r, n))
     while all(x % 2 == 0 and x >= 4 for x in n) and (max_levels == 0 or len(specs) < max_levels):
         n = tuple(x // 2 for x in n)
@@ -257,13 +262,14 @@ class Level:
 class Hierarchy:
     """hp-STMG hierarchy of one slab problem."""
 
-    def __init__(self, prob: Problem, max_levels: int = 0, omega: float | None = None, weighting: int = 1):
+    def __init__(self, prob: Problem, max_levels: int = 0, omega: float | None = None, weighting: int = 1,
+                 time_coarsening: bool = False):
         self.prob = prob
         self.weighting = weighting
         if omega is None:
             omega = 1.0 if weighting else default_omega(prob.dim)
         self.omega = omega
-        specs = level_specs(prob, max_levels)
+        specs = level_specs(prob, max_levels, time_coarsening)
         self.levels = []
         self.kinds = []
         vert = prob.vertices

@@ -153,6 +153,7 @@ void stmg_default_options(stmg_options *o)
     o->vanka_weighting = 1;
     o->vanka_time_decoupled = 1;
     o->use_graphs = 1;
+    o->time_coarsening = 0;
 }
 
 int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_ctx **out)
@@ -225,9 +226,9 @@ size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt)
     Spec sp{prob->k, prob->r, {prob->n_cells[0], prob->n_cells[1], d == 3 ? prob->n_cells[2] : 1}};
     specs.push_back(sp);
     auto cnt = [&]() { return (int)specs.size(); };
-    while ((sp.r > 1 || sp.k > 1) && (o.max_levels == 0 || cnt() < o.max_levels)) {
+    while ((sp.r > 1 || (o.time_coarsening && sp.k > 1)) && (o.max_levels == 0 || cnt() < o.max_levels)) {
         sp.r = std::max(1, sp.r / 2);
-        sp.k = sp.k >= 2 ? sp.k / 2 : sp.k;
+        if (o.time_coarsening) sp.k = sp.k >= 2 ? sp.k / 2 : sp.k;
         specs.push_back(sp);
     }
     auto hok = [&]() {

@@ -108,9 +108,10 @@ void mg_build(stmg_ctx *ctx)
     std::vector<char> kinds;
     std::vector<double> verts = L0.vert_host;
     auto count = [&]() { return (int)ctx->levels.size(); };
-    while ((r > 1 || k > 1) && (maxl == 0 || count() < maxl)) {
+    const bool tcoarse = o.time_coarsening != 0;
+    while ((r > 1 || (tcoarse && k > 1)) && (maxl == 0 || count() < maxl)) {
         r = std::max(1, r / 2);
-        k = k >= 2 ? k / 2 : k;
+        if (tcoarse) k = k >= 2 ? k / 2 : k;
         auto L = std::make_unique<Level>();
         L->init(ctx->prob, k, r, n[0], n[1], n[2], r == L0.r ? L0.nq : default_nq(r), verts);
         L->timers = &ctx->timers;

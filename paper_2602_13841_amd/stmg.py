@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
                 ("rb_stag_theta", ctypes.c_double), ("rb_stag_s", ctypes.c_int),
                 ("fgmres_maxit", ctypes.c_int), ("vanka_weighting", ctypes.c_int),
                 ("vanka_time_decoupled", ctypes.c_int),
-                ("use_graphs", ctypes.c_int)]
+                ("use_graphs", ctypes.c_int),
+                ("time_coarsening", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

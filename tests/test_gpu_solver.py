@@ -115,6 +115,55 @@ def test_vanka_sweep_and_vcycle(case, prec, stmg):
     assert rel(got, want) < tol
 
 
+TC_CASES = [CASES[1], CASES[4], CASES[7]]
+TC_IDS = [c[0] for c in TC_CASES]
+
+
+@pytest.mark.parametrize("case", TC_CASES, ids=TC_IDS)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_time_coarsening_rule(case, prec, stmg):
+    """p-coarsening in time with the spatial p steps (k -> k/2, option):
+    the same levels, transfers and V-cycle as the oracle's hierarchy built
+    with that rule."""
+    name, d, n, r, k, nu, tau, pert, mask, maxl = case
+    p = stmg.STMG_F64 if prec == "f64" else stmg.STMG_F32
+    dt = torch.float64 if prec == "f64" else torch.float32
+    tol = 1e-9 if prec == "f64" else 2e-4
+    vert = I.perturbed_vertices(d, n, 0.2, 60 + r) if pert else None
+    prob = oracle.Problem(dim=d, n=n, r=r, k=k, nu=nu, tau=tau, vertices=vert, dirichlet_mask=mask)
+    H = S.Hierarchy(prob, max_levels=maxl, time_coarsening=True)
+    assert H.levels[1].slab.prob.k == k // 2
+    ctx = stmg.Context(d, n, r, k, nu, tau, vertices=vert, dirichlet_faces=prob.dirichlet_mask,
+                       prec_mg=p, max_levels=maxl, time_coarsening=1)
+    assert ctx.num_levels() == len(H.levels)
+    for l, L in enumerate(H.levels):
+        assert ctx.level_info(l) == (L.slab.prob.k, L.slab.prob.r, tuple(L.slab.prob.n), L.slab.N)
+    for l in range(len(H.levels) - 1):
+        xc = I.uniform(H.levels[l + 1].slab.N, 50 + l)
+        assert rel(ctx.prolongate(l, dev(xc)).cpu().numpy(), H.P[l] @ xc) < 1e-13
+    s0 = H.levels[0].slab
+    U = I.uniform(s0.N, 53)
+    H.set_state(U)
+    H.rebuild_smoother()
+    ctx.smoother_rebuild(dev(U))
+    r_ = I.uniform(s0.N, 54)
+    assert rel(ctx.vcycle(dev(r_, dt)).cpu().numpy(), H.vcycle(r_)) < tol
+
+
+def test_time_coarsening_newton_matches_oracle(stmg):
+    prob, slab, rhs, vprev, maxl = _newton_case("2d_r2k2_pert_decay")
+    H = S.Hierarchy(prob, max_levels=maxl, time_coarsening=True)
+    U_ref, st_ref = S.newton_solve(slab, H, np.zeros(slab.N), rhs, vprev)
+    assert st_ref.converged
+    ctx = stmg.Context(prob.dim, prob.n, prob.r, prob.k, prob.nu, prob.tau, vertices=prob.vertices,
+                       prec_mg=stmg.STMG_F64, max_levels=maxl, time_coarsening=1)
+    ctx.set_slab_data(None, dev(vprev))
+    u, st, rc = ctx.newton_solve(torch.zeros(slab.N, dtype=torch.float64, device="cuda"))
+    assert rc == 0 and st.newton_its == st_ref.newton_its
+    assert list(st.fgmres_its[: st.newton_its]) == st_ref.fgmres_its
+    assert rel(u.cpu().numpy(), U_ref) < 1e-7
+
+
 @pytest.mark.parametrize("case", CASES[:4], ids=IDS[:4])
 def test_fgmres_matches_oracle(case, stmg):
     prob, H, ctx = make(case, stmg, stmg.STMG_F64)

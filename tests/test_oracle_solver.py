@@ -99,7 +99,13 @@ def test_level_specs():
     sp3 = S.level_specs(Problem(dim=3, n=(32, 32, 32), r=3, k=1, nu=1, tau=1))
     assert sp3 == [(1, 3, (32,) * 3), (1, 1, (32,) * 3), (1, 1, (16,) * 3), (1, 1, (8,) * 3), (1, 1, (4,) * 3),
                    (1, 1, (2,) * 3)]
-    assert S.level_specs(Problem(dim=3, n=(16,) * 3, r=2, k=2, nu=1, tau=1))[1] == (1, 1, (16,) * 3)
+    assert S.level_specs(Problem(dim=3, n=(16,) * 3, r=2, k=2, nu=1, tau=1))[1] == (2, 1, (16,) * 3)
+    assert S.level_specs(Problem(dim=3, n=(16,) * 3, r=2, k=2, nu=1, tau=1), time_coarsening=True)[1] == \
+        (1, 1, (16,) * 3)
+    assert S.level_specs(Problem(dim=2, n=(8, 8), r=1, k=3, nu=1, tau=1)) == [(3, 1, (8, 8)), (3, 1, (4, 4)),
+                                                                              (3, 1, (2, 2))]
+    assert S.level_specs(Problem(dim=2, n=(8, 8), r=1, k=3, nu=1, tau=1), time_coarsening=True)[:2] == \
+        [(3, 1, (8, 8)), (1, 1, (8, 8))]
     assert S.level_specs(Problem(dim=2, n=(8, 8), r=1, k=1, nu=1, tau=1), max_levels=2) == [(1, 1, (8, 8)),
                                                                                             (1, 1, (4, 4))]
 
