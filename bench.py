@@ -142,8 +142,11 @@ def bench_batched_lu(npatch=4096, seed=6):
     space-time surrogate patches (eq. LVS, eq. DefTildeHn) of interior cells of
     8^3-cell meshes (h = 1/8, tau = h/2), (r, k, nu) uniform on {1, 2, 3} x
     {0, 1, 2} x {1, 1e-2, 1e-3} (PCG64 seed), nodal states U(-1, 1); the
-    patches are assembled by the library.  One stmg_batched_lu launch per
-    precision (FP64, FP32 on MFMA), then the triangular solves."""
+    patches are assembled by the library.  One stmg_batched_lu call per
+    precision (FP64; FP32 with FP32, BF16 or FP16 operands of the
+    trailing-update MFMA, FP32 accumulation), then the triangular solves;
+    accuracy as the sampled normwise backward error and the relative
+    distance of the solutions to the FP64 ones."""
     import torch
     from paper_2602_13841_amd import inputs as I
     from paper_2602_13841_amd import stmg
@@ -177,14 +180,17 @@ def bench_batched_lu(npatch=4096, seed=6):
            "lu_flops": flops}
     rng2 = np.random.Generator(np.random.PCG64(seed + 1))
     rhs = torch.tensor(rng2.uniform(-1, 1, int(sizes.sum())), device="cuda")
-    for name, dt, peak in (("fp64", torch.float64, 78.6e12), ("fp32_mfma", torch.float32, 157.3e12)):
+    x64 = None
+    for name, dt, prec, peak in (("fp64", torch.float64, None, 78.6e12), ("fp32_mfma", torch.float32, None, 157.3e12),
+                                 ("fp32_bf16_mfma", torch.float32, stmg.STMG_F32_BF16, 2.5e15),
+                                 ("fp32_f16_mfma", torch.float32, stmg.STMG_F32_F16, 2.5e15)):
         A = A64.to(dt, copy=True)   # A64 stays the unfactored reference
         piv = torch.zeros(int(sizes.sum()), dtype=torch.int32, device="cuda")
         info = torch.zeros(1, dtype=torch.int32, device="cuda")
         torch.cuda.synchronize()
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record()
-        stmg.batched_lu(A, a_off, sizes, piv, p_off, info)
+        stmg.batched_lu(A, a_off, sizes, piv, p_off, info, prec=prec)
         e1.record()
         b = rhs.to(dt, copy=True)   # rhs stays the right-hand side of the check
         stmg.batched_lu_solve(A, a_off, sizes, piv, p_off, b, p_off)
@@ -200,9 +206,14 @@ def bench_batched_lu(npatch=4096, seed=6):
             ri = rhs[p_off[i]: p_off[i] + sizes[i]].cpu().numpy()
             be = np.max(np.abs(M @ xi - ri)) / (np.max(np.abs(M).sum(1)) * np.max(np.abs(xi)) + np.max(np.abs(ri)))
             worst = max(worst, float(be))
+        if x64 is None:
+            x64 = x
+        rel = [float(np.linalg.norm(x[p_off[i]: p_off[i] + sizes[i]] - x64[p_off[i]: p_off[i] + sizes[i]]) /
+                     np.linalg.norm(x64[p_off[i]: p_off[i] + sizes[i]])) for i in range(npatch)]
         out[name] = {"lu_s": t_lu, "patches_per_s": npatch / t_lu, "tflops": flops / t_lu / 1e12,
                      "frac_of_peak": flops / t_lu / peak, "solve_s": t_sv, "zero_pivots": int(info.item()),
-                     "backward_error_sample_max": worst}
+                     "backward_error_sample_max": worst, "rel_err_vs_fp64_median": float(np.median(rel)),
+                     "rel_err_vs_fp64_max": float(np.max(rel))}
         del A, piv, b
         torch.cuda.empty_cache()
     return out

@@ -54,7 +54,14 @@ extern "C" {
 
 typedef struct stmg_ctx stmg_ctx;
 
-typedef enum { STMG_F64 = 0, STMG_F32 = 1 } stmg_prec;
+typedef enum {
+    STMG_F64 = 0,
+    STMG_F32 = 1,
+    /* batched patch factorizations only: FP32 matrices whose trailing
+     * updates take BF16 / FP16 operands on MFMA with FP32 accumulation */
+    STMG_F32_BF16 = 2,
+    STMG_F32_F16 = 3
+} stmg_prec;
 
 /* Data of one slab (Problem LocAlgNS; Nitsche boundary forms eq. def-b-gam,
  * eq. def-a-gam-tp).  Boundary face f = 2*axis + side (side 0: x_axis = 0,
@@ -276,7 +283,10 @@ int stmg_march(stmg_ctx *ctx, int nslabs, const double *rhs, long long rhs_strid
  * pivoting, one launch per size class (matrices within a factor 2 of the
  * class's largest share a launch) (the Vanka patch factorization of Sec. "Inexact
  * space-time Vanka smoother" as a standalone batch; the trailing updates run
- * on MFMA in FP32).  prec: STMG_F64 or STMG_F32.  Matrix b is m_of[b] x
+ * on MFMA in FP32).  prec: STMG_F64, STMG_F32, or STMG_F32_BF16 /
+ * STMG_F32_F16 (FP32 matrices and factors; the L21 and U12 blocks of each
+ * trailing update A22 -= L21 U12 are rounded to BF16 / FP16 for the MFMA,
+ * A22 accumulates in FP32; the solve is the FP32 one).  Matrix b is m_of[b] x
  * m_of[b], row-major, at element offset a_off[b] of the device array A and
  * is overwritten by its factors (unit lower L below the diagonal, U on and
  * above); piv + p_off[b] receives m_of[b] 0-based row interchanges

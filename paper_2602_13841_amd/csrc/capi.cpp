@@ -47,8 +47,11 @@ int batched_lu_impl(int prec, void *A, const long long *a_off, const int *m_of, 
                     bool solve = false)
 {
     if (!A || !a_off || !m_of || !piv || !p_off || batch < 0) return STMG_EINVAL;
-    if (prec != STMG_F64 && prec != STMG_F32) return STMG_EINVAL;
+    if (prec != STMG_F64 && prec != STMG_F32 && prec != STMG_F32_BF16 && prec != STMG_F32_F16) return STMG_EINVAL;
     if (batch == 0) return STMG_OK;
+    // FP32 storage for the three FP32 variants; op = operands of the
+    // trailing-update MFMA
+    const int op = prec == STMG_F32_BF16 ? 1 : (prec == STMG_F32_F16 ? 2 : 0);
     std::vector<int> ord(batch);
     int maxm = 0;
     for (int i = 0; i < batch; ++i) {
@@ -99,7 +102,7 @@ int batched_lu_impl(int prec, void *A, const long long *a_off, const int *m_of, 
                 while (c1 < batch && 2 * ms[c1] > m0) ++c1;
                 LuBatch vc{m0, dm.as<int>() + c0, da.as<long long>() + c0, dp.as<long long>() + c0};
                 if (prec == STMG_F64) e = launch_lu<double>((double *)A, piv, m0, c1 - c0, info, max_lds, s, &vc);
-                else e = launch_lu<float>((float *)A, piv, m0, c1 - c0, info, max_lds, s, &vc);
+                else e = launch_lu<float>((float *)A, piv, m0, c1 - c0, info, max_lds, s, &vc, op);
                 c0 = c1;
             }
         }

@@ -84,10 +84,12 @@ int elem_record_words(int dim, int r);
 template <typename T> hipError_t launch_elem(int dim, int r, int nq, const ElemArgs<T> &a, int ncell, hipStream_t s);
 template <typename TE, typename TP>
 hipError_t launch_patch(int dim, int r, const PatchArgs<TE, TP> &a, int ncell, hipStream_t s);
-// m: the (largest) matrix size; vb: variable sizes (nullptr = all m x m, contiguous)
+// m: the (largest) matrix size; vb: variable sizes (nullptr = all m x m,
+// contiguous); op (FP32 only): operands of the trailing-update MFMA in FP32
+// (0), BF16 (1) or FP16 (2), accumulation in FP32
 template <typename T>
 hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds, hipStream_t s,
-                     const LuBatch *vb = nullptr);
+                     const LuBatch *vb = nullptr, int op = 0);
 template <typename T, typename TP>
 hipError_t launch_solve(int dim, int r, const SolveArgs<T, TP> &a, int ncell, int m, hipStream_t s);
 template <typename TE, typename TP>

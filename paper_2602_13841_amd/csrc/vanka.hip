@@ -43,6 +43,16 @@ namespace {
 constexpr int ipow_(int b, int e) { return e == 0 ? 1 : b * ipow_(b, e - 1); }
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx4_t __attribute__((ext_vector_type(4)));
+typedef short shortx4_t __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs; overflow -> inf)
+__device__ __forceinline__ short bf16_rne(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
 typedef double doublex4_t __attribute__((ext_vector_type(4)));
 
 // 16 x 16 x 4 matrix FMA per precision (v_mfma_f32_16x16x4f32 /
@@ -872,11 +882,16 @@ constexpr int LU_SWC = 64;       // column chunk of the row interchanges
 
 // trailing update A22 -= L21 U12 of one column block, FP32 on MFMA
 // (v_mfma_f32_16x16x4f32: A lane l -> (row l%16, k l/16), B lane l ->
-// (k l/16, col l%16), D lane l reg i -> (row 4(l/16)+i, col l%16))
-template <int NBP>
+// (k l/16, col l%16), D lane l reg i -> (row 4(l/16)+i, col l%16)).
+// OP = 1 / 2: the L21 and U12 operands rounded to BF16 / FP16, products
+// accumulated in FP32 (v_mfma_f32_16x16x16{bf16,f16}: A lane l -> (row l%16,
+// k 4(l/16)+j), B lane l -> (k 4(l/16)+j, col l%16), j < 4; D as above);
+// A22 stays FP32
+template <int NBP, int OP>
 __device__ __forceinline__ void trailing_update(float *A, int m, int j0, int nb, int cb, int ncb, const float *pan,
                                                 const float *ut)
 {
+    constexpr int NB = NBP - 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r0 = j0 + nb;
     const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32, ntile = nrt * nct;
@@ -900,21 +915,56 @@ __device__ __forceinline__ void trailing_update(float *A, int m, int j0, int nb,
         const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
         const int tn = t + LU_THREADS / 64;
         if (tn < ntile) load(tn, nxt);
-        for (int k0 = 0; k0 < nb; k0 += 4) {
-            const int k = k0 + (lane >> 4);
-            float a[2], b[2];
+        if constexpr (OP == 0) {
+            for (int k0 = 0; k0 < nb; k0 += 4) {
+                const int k = k0 + (lane >> 4);
+                float a[2], b[2];
 #pragma unroll
-            for (int si = 0; si < 2; ++si) {
-                const int row = R + 16 * si + (lane & 15);
-                a[si] = (row < m && k < nb) ? -pan[(row - j0) * NBP + k] : 0.0f;
+                for (int si = 0; si < 2; ++si) {
+                    const int row = R + 16 * si + (lane & 15);
+                    a[si] = (row < m && k < nb) ? -pan[(row - j0) * NBP + k] : 0.0f;
+                }
+#pragma unroll
+                for (int sj = 0; sj < 2; ++sj) b[sj] = ut[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)];
+#pragma unroll
+                for (int si = 0; si < 2; ++si)
+#pragma unroll
+                    for (int sj = 0; sj < 2; ++sj)
+                        acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[si], b[sj], acc[si][sj], 0, 0, 0);
             }
+        } else {
+            for (int k0 = 0; k0 < nb; k0 += 16) {
+                shortx4_t as[2], bs[2];
+                halfx4_t ah[2], bh[2];
 #pragma unroll
-            for (int sj = 0; sj < 2; ++sj) b[sj] = ut[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)];
+                for (int j = 0; j < 4; ++j) {
+                    const int k = k0 + 4 * (lane >> 4) + j, kc = min(k, NB - 1);
 #pragma unroll
-            for (int si = 0; si < 2; ++si)
+                    for (int si = 0; si < 2; ++si) {
+                        const int row = R + 16 * si + (lane & 15);
+                        const float v = -pan[(min(row, m - 1) - j0) * NBP + kc];
+                        const float a = (row < m && k < nb) ? v : 0.0f;
+                        if constexpr (OP == 1) as[si][j] = bf16_rne(a);
+                        else ah[si][j] = (_Float16)a;
+                    }
 #pragma unroll
-                for (int sj = 0; sj < 2; ++sj)
-                    acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[si], b[sj], acc[si][sj], 0, 0, 0);
+                    for (int sj = 0; sj < 2; ++sj) {
+                        const float v = ut[kc * LU_CB + (C - cb) + 16 * sj + (lane & 15)];
+                        const float b = k < nb ? v : 0.0f;
+                        if constexpr (OP == 1) bs[sj][j] = bf16_rne(b);
+                        else bh[sj][j] = (_Float16)b;
+                    }
+                }
+#pragma unroll
+                for (int si = 0; si < 2; ++si)
+#pragma unroll
+                    for (int sj = 0; sj < 2; ++sj) {
+                        if constexpr (OP == 1)
+                            acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(as[si], bs[sj], acc[si][sj], 0, 0, 0);
+                        else
+                            acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[si], bh[sj], acc[si][sj], 0, 0, 0);
+                    }
+            }
         }
 #pragma unroll
         for (int si = 0; si < 2; ++si)
@@ -935,7 +985,7 @@ __device__ __forceinline__ void trailing_update(float *A, int m, int j0, int nb,
 }
 
 // FP64: register tiles of 4 x 4 per thread on the vector ALUs
-template <int NBP>
+template <int NBP, int OP>
 __device__ __forceinline__ void trailing_update(double *A, int m, int j0, int nb, int cb, int ncb, const double *pan,
                                                 const double *ut)
 {
@@ -1010,7 +1060,7 @@ __device__ __forceinline__ void compose_panel_swaps(const int *sw, int nb, int *
     if (lane == 0) *n_aff = __popcll(mm);
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int OP = 0>
 __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, int *__restrict__ pivall, LuBatch B,
                                                         int *info)
 {
@@ -1124,7 +1174,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
                     }
             }
             __syncthreads();
-            trailing_update<NBP>(A, m, j0, nb, cb, ncb, pan, ut);
+            trailing_update<NBP, OP>(A, m, j0, nb, cb, ncb, pan, ut);
             __syncthreads();
         }
     }
@@ -2020,8 +2070,10 @@ static int lu_nb_cap()
 constexpr size_t CU_LDS = 160 * 1024;
 
 template <typename T>
-hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds, hipStream_t s, const LuBatch *vb)
+hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds, hipStream_t s, const LuBatch *vb,
+                     int op)
 {
+    if (op < 0 || op > 2 || (op != 0 && !std::is_same<T, float>::value)) return hipErrorInvalidValue;
     LuBatch B{};
     if (vb) B = *vb;
     else B.uniform_m = m;
@@ -2033,16 +2085,25 @@ hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds
                        : nb == 8 ? lu_lds_bytes<8, T>(m) : lu_lds_bytes<4, T>(m);
         if (2 * b <= CU_LDS && b <= max_lds) { cap = nb; break; }
     }
+#define LUK(NBV, OPV)                                                                                                  \
+    {                                                                                                                  \
+        size_t bytes = lu_lds_bytes<NBV, T>(m);                                                                        \
+        hipError_t e = lds_attr((const void *)lu_kernel<T, NBV, OPV>, bytes);                                          \
+        if (e != hipSuccess) return e;                                                                                 \
+        hipLaunchKernelGGL((lu_kernel<T, NBV, OPV>), dim3(batch), dim3(LU_THREADS), bytes, s, A, piv, B, info);       \
+        return hipGetLastError();                                                                                      \
+    }
 #define LUC(NBV)                                                                                                       \
     if (NBV <= cap && lu_lds_bytes<NBV, T>(m) <= max_lds) {                                                            \
-        size_t bytes = lu_lds_bytes<NBV, T>(m);                                                                        \
-        hipError_t e = lds_attr((const void *)lu_kernel<T, NBV>, bytes);                    \
-        if (e != hipSuccess) return e;                                                                                 \
-        hipLaunchKernelGGL((lu_kernel<T, NBV>), dim3(batch), dim3(LU_THREADS), bytes, s, A, piv, B, info);            \
-        return hipGetLastError();                                                                                      \
+        if constexpr (std::is_same<T, float>::value) {                                                                 \
+            if (op == 1) LUK(NBV, 1)                                                                                   \
+            if (op == 2) LUK(NBV, 2)                                                                                   \
+        }                                                                                                              \
+        LUK(NBV, 0)                                                                                                    \
     }
     LUC(32) LUC(16) LUC(8) LUC(4)
 #undef LUC
+#undef LUK
     return hipErrorInvalidConfiguration;
 }
 
@@ -2362,8 +2423,8 @@ template hipError_t launch_elem<float>(int, int, int, const ElemArgs<float> &, i
 template hipError_t launch_patch<double, double>(int, int, const PatchArgs<double, double> &, int, hipStream_t);
 template hipError_t launch_patch<float, float>(int, int, const PatchArgs<float, float> &, int, hipStream_t);
 template hipError_t launch_patch<double, float>(int, int, const PatchArgs<double, float> &, int, hipStream_t);
-template hipError_t launch_lu<double>(double *, int *, int, int, int *, size_t, hipStream_t, const LuBatch *);
-template hipError_t launch_lu<float>(float *, int *, int, int, int *, size_t, hipStream_t, const LuBatch *);
+template hipError_t launch_lu<double>(double *, int *, int, int, int *, size_t, hipStream_t, const LuBatch *, int);
+template hipError_t launch_lu<float>(float *, int *, int, int, int *, size_t, hipStream_t, const LuBatch *, int);
 template hipError_t launch_solve<double, double>(int, int, const SolveArgs<double, double> &, int, int, hipStream_t);
 template hipError_t launch_solve<float, float>(int, int, const SolveArgs<float, float> &, int, int, hipStream_t);
 template hipError_t launch_solve<double, float>(int, int, const SolveArgs<double, float> &, int, int, hipStream_t);

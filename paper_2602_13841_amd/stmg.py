@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libstmg.so")
 
 STMG_F64 = 0
 STMG_F32 = 1
+STMG_F32_BF16 = 2   # batched factorizations: BF16 operands of the FP32 trailing updates
+STMG_F32_F16 = 3    # same with FP16 operands
 # return codes (include/stmg.h)
 STMG_OK, STMG_EINVAL, STMG_ENOMEM, STMG_EHIP, STMG_ESTATE, STMG_ENONFINITE, STMG_NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1
 
@@ -168,13 +170,18 @@ def _host_i64(a):
     return np.ascontiguousarray(a, dtype=np.int64)
 
 
-def batched_lu(A, a_off, m_of, piv, p_off, info=None):
+def batched_lu(A, a_off, m_of, piv, p_off, info=None, prec=None):
     """Factor a batch of row-major matrices of mixed sizes in place (device
-    tensors A (float64/float32) and piv (int32); host offsets and sizes)."""
+    tensors A (float64/float32) and piv (int32); host offsets and sizes).
+    prec: None (from the dtype of A), or STMG_F32_BF16 / STMG_F32_F16 for
+    float32 A with 16-bit operands in the trailing-update MFMA."""
     import numpy as np
     ao, po = _host_i64(a_off), _host_i64(p_off)
     mo = np.ascontiguousarray(m_of, dtype=np.int32)
-    prec = STMG_F64 if A.dtype == torch.float64 else STMG_F32
+    if prec is None:
+        prec = STMG_F64 if A.dtype == torch.float64 else STMG_F32
+    elif (prec == STMG_F64) != (A.dtype == torch.float64):
+        raise StmgError("prec does not match the dtype of A")
     rc = lib().stmg_batched_lu(prec, _ptr(A), ao.ctypes.data, mo.ctypes.data, len(mo), _ptr(piv), po.ctypes.data,
                                _ptr(info) if info is not None else None, _stream_ptr())
     if rc != 0:

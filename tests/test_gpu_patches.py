@@ -95,3 +95,40 @@ def test_batched_lu_mixed_sizes(stmg):
             if dt == torch.float64:
                 ref = np.linalg.solve(M, rhs[i])
                 assert np.max(np.abs(xi - ref)) <= 1e-6 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("which", ["bf16", "f16"])
+def test_batched_lu_16bit_update_operands(which, stmg):
+    """FP32 factorizations whose trailing updates take BF16 / FP16 operands
+    (FP32 accumulation).  Rounding the L21 and U12 entries perturbs every
+    product by at most 2u relative (u = 2^-8 for BF16, 2^-11 for FP16), so the
+    computed factors are exact for A + dA with |dA| <= 2u |L||U|: the normwise
+    backward error of each solve is bounded by 2u rho, rho = || |L||U| || /
+    ||A|| of the matrix's partial-pivoting LU (from scipy, in FP64); checked
+    with a factor 2 of slack plus the FP32 floor."""
+    import scipy.linalg as sla
+    mats = c4_batch()
+    sizes = np.array([A.shape[0] for A in mats], dtype=np.int32)
+    a_off = np.concatenate([[0], np.cumsum(sizes.astype(np.int64) ** 2)[:-1]])
+    p_off = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))[:-1]])
+    rng = np.random.Generator(np.random.PCG64(8))
+    rhs = [rng.uniform(-1, 1, m) for m in sizes]
+    prec, u = (stmg.STMG_F32_BF16, 2.0 ** -8) if which == "bf16" else (stmg.STMG_F32_F16, 2.0 ** -11)
+    xs = {}
+    for name, p in (("f32", None), (which, prec)):
+        A = torch.tensor(np.concatenate([M.ravel() for M in mats]), dtype=torch.float32, device="cuda")
+        piv = torch.zeros(int(sizes.sum()), dtype=torch.int32, device="cuda")
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        stmg.batched_lu(A, a_off, sizes, piv, p_off, info, prec=p)
+        b = torch.tensor(np.concatenate(rhs), dtype=torch.float32, device="cuda")
+        stmg.batched_lu_solve(A, a_off, sizes, piv, p_off, b, p_off)
+        assert int(info.item()) == 0
+        xs[name] = b.double().cpu().numpy()
+    assert not np.array_equal(xs["f32"], xs[which])     # the 16-bit path really ran
+    for i, M in enumerate(mats):
+        _, L, U = sla.lu(M)
+        rho = np.max((np.abs(L) @ np.abs(U)).sum(1)) / np.max(np.abs(M).sum(1))
+        xi = xs[which][p_off[i]: p_off[i] + sizes[i]]
+        be = np.max(np.abs(M @ xi - rhs[i])) / (np.max(np.abs(M).sum(1)) * np.max(np.abs(xi)) +
+                                                np.max(np.abs(rhs[i])))
+        assert be < 4 * u * rho + 2e-6, (i, sizes[i], be, rho)
