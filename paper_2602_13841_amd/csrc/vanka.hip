@@ -1191,11 +1191,11 @@ constexpr int SV_THREADS = 256;
 // loads in flight before it reduces, so a pass over the rows costs about one
 // memory latency instead of one per row.  Per row the summation order is
 // fixed: columns l16, l16+16, ..., then a 16-lane xor tree.
-template <typename T, bool CX, int KB = 64>
+template <typename T, bool CX, int KB = 64, int RU = 4>
 __device__ __forceinline__ void block_gemv_update(const T *__restrict__ Lr, const T *__restrict__ Li, int m, int kb,
                                                   int nbk, int rbeg, int rend, T *br, T *bi)
 {
-    constexpr int RU = 4, NG = SV_THREADS / 16, CPL = KB / 16;   // columns per lane
+    constexpr int NG = SV_THREADS / 16, CPL = KB / 16;   // columns per lane
     const int tid = threadIdx.x, g = tid >> 4, l16 = tid & 15;
     T xr[CPL], xi[CPL];
 #pragma unroll
@@ -1724,15 +1724,19 @@ __global__ void piv_to_perm_kernel(const int *__restrict__ piv, int *__restrict_
 }
 
 // triangular solves with a planar complex row-major LU (unit lower L, upper
-// U), rhs (br, bi) in LDS
-template <typename T, int KB = 64>
+// U), rhs (br, bi) in LDS.  Diagonal blocks of KB rows are solved by one
+// wavefront from LDS; SB of them form a super-block whose rows are updated
+// block by block, while the rows outside the super-block are updated once
+// with all SB*KB columns (longer contiguous row segments per load, two rows
+// per 16-lane group in flight for SB = 2: the same registers as KB columns
+// and four rows)
+template <typename T, int KB = 64, int SB = 1>
 __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const T *__restrict__ Li, int m, T *br, T *bi, T *dr,
                                 T *di)
 {
+    constexpr int SW = SB * KB, RUS = SB == 1 ? 4 : (SB == 2 ? 2 : 1);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int g = tid >> 4, l16 = tid & 15;
-    for (int kb = 0; kb < m; kb += KB) {
-        const int nbk = min(KB, m - kb);
+    auto load_diag = [&](int kb, int nbk) {
         for (int e = tid; e < nbk * KB; e += SV_THREADS) {
             const int i = e / KB, j = e % KB;
             if (j < nbk) {
@@ -1740,61 +1744,76 @@ __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const 
                 di[i * (KB + 1) + j] = Li[(long long)(kb + i) * m + kb + j];
             }
         }
-        __syncthreads();
-        if (wv == 0) {
-            T yr = lane < nbk ? br[kb + lane] : T(0), yi = lane < nbk ? bi[kb + lane] : T(0);
-            for (int c = 0; c < nbk; ++c) {
-                const T cr = __shfl(yr, c, 64), ci = __shfl(yi, c, 64);
-                if (lane > c && lane < nbk) {
-                    const T lr = dr[lane * (KB + 1) + c], li = di[lane * (KB + 1) + c];
-                    yr -= lr * cr - li * ci;
-                    yi -= lr * ci + li * cr;
+    };
+    // forward: unit lower
+    for (int sb = 0; sb < m; sb += SW) {
+        const int se = min(sb + SW, m);
+        for (int kb = sb; kb < se; kb += KB) {
+            const int nbk = min(KB, se - kb);
+            load_diag(kb, nbk);
+            __syncthreads();
+            if (wv == 0) {
+                T yr = lane < nbk ? br[kb + lane] : T(0), yi = lane < nbk ? bi[kb + lane] : T(0);
+                for (int c = 0; c < nbk; ++c) {
+                    const T cr = __shfl(yr, c, 64), ci = __shfl(yi, c, 64);
+                    if (lane > c && lane < nbk) {
+                        const T lr = dr[lane * (KB + 1) + c], li = di[lane * (KB + 1) + c];
+                        yr -= lr * cr - li * ci;
+                        yi -= lr * ci + li * cr;
+                    }
+                }
+                if (lane < nbk) {
+                    br[kb + lane] = yr;
+                    bi[kb + lane] = yi;
                 }
             }
-            if (lane < nbk) {
-                br[kb + lane] = yr;
-                bi[kb + lane] = yi;
+            __syncthreads();
+            if (kb + nbk < se) {
+                block_gemv_update<T, true, KB>(Lr, Li, m, kb, nbk, kb + nbk, se, br, bi);
+                __syncthreads();
             }
         }
-        __syncthreads();
-        block_gemv_update<T, true, KB>(Lr, Li, m, kb, nbk, kb + nbk, m, br, bi);
+        block_gemv_update<T, true, SW, RUS>(Lr, Li, m, sb, se - sb, se, m, br, bi);
         __syncthreads();
     }
-    const int nblk = (m + KB - 1) / KB;
-    for (int bk = nblk - 1; bk >= 0; --bk) {
-        const int kb = bk * KB, nbk = min(KB, m - kb);
-        for (int e = tid; e < nbk * KB; e += SV_THREADS) {
-            const int i = e / KB, j = e % KB;
-            if (j < nbk) {
-                dr[i * (KB + 1) + j] = Lr[(long long)(kb + i) * m + kb + j];
-                di[i * (KB + 1) + j] = Li[(long long)(kb + i) * m + kb + j];
+    // backward: upper with diagonal
+    const int nsb = (m + SW - 1) / SW;
+    for (int bs = nsb - 1; bs >= 0; --bs) {
+        const int sb = bs * SW, se = min(sb + SW, m);
+        const int nin = (se - sb + KB - 1) / KB;
+        for (int j = nin - 1; j >= 0; --j) {
+            const int kb = sb + j * KB, nbk = min(KB, se - kb);
+            load_diag(kb, nbk);
+            __syncthreads();
+            if (wv == 0) {
+                T xr = lane < nbk ? br[kb + lane] : T(0), xi = lane < nbk ? bi[kb + lane] : T(0);
+                for (int c = nbk - 1; c >= 0; --c) {
+                    const T vr = __shfl(xr, c, 64), vi = __shfl(xi, c, 64);
+                    const T ur = dr[c * (KB + 1) + c], ui = di[c * (KB + 1) + c];
+                    const T den = ur * ur + ui * ui;
+                    const T qr = (vr * ur + vi * ui) / den, qi = (vi * ur - vr * ui) / den;
+                    if (lane == c) {
+                        xr = qr;
+                        xi = qi;
+                    }
+                    if (lane < c) {
+                        const T lr = dr[lane * (KB + 1) + c], li = di[lane * (KB + 1) + c];
+                        xr -= lr * qr - li * qi;
+                        xi -= lr * qi + li * qr;
+                    }
+                }
+                if (lane < nbk) {
+                    br[kb + lane] = xr;
+                    bi[kb + lane] = xi;
+                }
+            }
+            __syncthreads();
+            if (kb > sb) {
+                block_gemv_update<T, true, KB>(Lr, Li, m, kb, nbk, sb, kb, br, bi);
+                __syncthreads();
             }
         }
-        __syncthreads();
-        if (wv == 0) {
-            T xr = lane < nbk ? br[kb + lane] : T(0), xi = lane < nbk ? bi[kb + lane] : T(0);
-            for (int c = nbk - 1; c >= 0; --c) {
-                const T vr = __shfl(xr, c, 64), vi = __shfl(xi, c, 64);
-                const T ur = dr[c * (KB + 1) + c], ui = di[c * (KB + 1) + c];
-                const T den = ur * ur + ui * ui;
-                const T qr = (vr * ur + vi * ui) / den, qi = (vi * ur - vr * ui) / den;
-                if (lane == c) {
-                    xr = qr;
-                    xi = qi;
-                }
-                if (lane < c) {
-                    const T lr = dr[lane * (KB + 1) + c], li = di[lane * (KB + 1) + c];
-                    xr -= lr * qr - li * qi;
-                    xi -= lr * qi + li * qr;
-                }
-            }
-            if (lane < nbk) {
-                br[kb + lane] = xr;
-                bi[kb + lane] = xi;
-            }
-        }
-        __syncthreads();
-        block_gemv_update<T, true, KB>(Lr, Li, m, kb, nbk, 0, kb, br, bi);
+        block_gemv_update<T, true, SW, RUS>(Lr, Li, m, sb, se - sb, 0, sb, br, bi);
         __syncthreads();
     }
 }
@@ -1819,8 +1838,9 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP>
     TP *dr = bi + MSP;
     // diagonal-block width of the substitutions: 32 keeps the LDS at a size
     // that lets several workgroups share a CU (32^3, r = 3, k = 1, finest
-    // level: FP64 one -> four workgroups per CU, 27.5 -> 12.5 ms per sweep;
-    // FP32 three -> six, 9.6 -> 7.7 ms)
+    // level: FP64 four instead of one, FP32 six instead of three); the
+    // complex substitution updates the rows outside pairs of blocks with 64
+    // columns at once (4 % faster sweeps than 32)
     constexpr int KBT = 32;
     TP *di = dr + KBT * (KBT + 1);
     const int cell = xcd_cell(blockIdx.x, gridDim.x), tid = threadIdx.x;
@@ -1857,7 +1877,7 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP>
         }
         __syncthreads();
         const TP *LU = A.sys[s] + (long long)cell * (cx ? 2 : 1) * MAT;
-        if (cx) lu_substitute_c<TP, KBT>(LU, LU + MAT, MS, br, bi, dr, di);
+        if (cx) lu_substitute_c<TP, KBT, 2>(LU, LU + MAT, MS, br, bi, dr, di);
         else lu_substitute<TP, KBT>(LU, MS, br, dr);
         for (int e = tid; e < nt * MS; e += SV_THREADS) {
             const int a = e / MS, j = e - (e / MS) * MS;
