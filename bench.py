@@ -98,7 +98,7 @@ TIMER_NAMES = ["vcycle_graph", "vanka_elem", "vanka_patch", "vanka_lu", "vanka_a
                "gather_f32", "cell_res_f64", "cell_mass_f64", "coarse_factor", "coarse_solve", "transfer"]
 
 
-def bench_solve(prec, warm=True):
+def bench_solve(prec, warm=True, **opts):
     """One Newton-FGMRES slab solve of the 32^3 perturbed-mesh workload
     (r=3, k=1, Re=1000, tau=1/64), previous-slab velocity = smooth field,
     zero initial guess, stopping at |R|_M <= 1e-8 |R_0|_M.  Returns solves/s,
@@ -110,13 +110,13 @@ def bench_solve(prec, warm=True):
     d, n = w["dim"], w["n"]
     if warm:
         # load the code objects of this configuration on a small mesh
-        c = stmg.Context(d, (4, 4, 4), w["r"], w["k"], w["nu"], w["tau"], prec_mg=prec)
+        c = stmg.Context(d, (4, 4, 4), w["r"], w["k"], w["nu"], w["tau"], prec_mg=prec, **opts)
         c.set_slab_data(None, torch.tensor(I.smooth_velocity(d, (4, 4, 4), w["r"], 1), device="cuda"))
         c.newton_solve(torch.zeros(c.N, dtype=torch.float64, device="cuda"))
         del c
     vert = I.perturbed_vertices(d, n, w["perturb"], w["vert_seed"])
     ctx = stmg.Context(d, n, w["r"], w["k"], w["nu"], w["tau"], vertices=vert, prec_mg=prec,
-                       newton_rtol=1e-8, newton_atol=0.0)
+                       newton_rtol=1e-8, newton_atol=0.0, **opts)
     ctx.set_slab_data(None, torch.tensor(I.smooth_velocity(d, n, w["r"], w["v0_seed"]), device="cuda"))
     u = torch.zeros(ctx.N, dtype=torch.float64, device="cuda")
     ctx.timing_reset()
@@ -367,11 +367,13 @@ def main():
     if not args.no_solve:
         print("[bench] slab solve, FP32 multigrid", file=sys.stderr, flush=True)
         s32 = bench_solve(stmg.STMG_F32)
+        print("[bench] slab solve, FP32 multigrid, BF16 copy of the patch factors", file=sys.stderr, flush=True)
+        s16 = bench_solve(stmg.STMG_F32, vanka_factor_bf16=1)
         print("[bench] slab solve, FP64 multigrid", file=sys.stderr, flush=True)
         s64 = bench_solve(stmg.STMG_F64)
         out["solve"] = {"workload": "3D 32^3 hexes perturbed by 0.2h, Q4/P3disc (r=3) x DG(1), Re=1000, "
                                     "tau=1/64, smooth previous-slab velocity, |R|_M <= 1e-8 |R_0|_M",
-                        "fp32_mg": s32, "fp64_mg": s64,
+                        "fp32_mg": s32, "fp32_mg_bf16_factors": s16, "fp64_mg": s64,
                         "speedup_fp32_vs_fp64": s64["wall_s"] / s32["wall_s"]}
     if not args.no_batched_lu:
         print("[bench] batched patch factorizations", file=sys.stderr, flush=True)

@@ -128,6 +128,12 @@ typedef struct {
      * 0.56 -> 0.84 for k = 2 and 0.69 -> 0.96 for k = 3 from h = 1/4 to
      * 1/32 on the 2D convergence problem). */
     int time_coarsening;
+    /* FP32 multigrid with time-decoupled patches only (ignored otherwise):
+     * the factors are still computed in FP32, but the smoothing sweeps read a
+     * BF16 copy (round to nearest even; half the bytes per sweep, entries
+     * relative to 2^-9), widened to FP32 for the substitutions.  0 (default)
+     * or 1.  The copy adds half of the FP32 factor bytes to the footprint. */
+    int vanka_factor_bf16;
 } stmg_options;
 
 typedef struct {

@@ -157,6 +157,7 @@ void stmg_default_options(stmg_options *o)
     o->vanka_time_decoupled = 1;
     o->use_graphs = 1;
     o->time_coarsening = 0;
+    o->vanka_factor_bf16 = 0;
 }
 
 int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_ctx **out)
@@ -265,6 +266,8 @@ size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt)
             if (o.vanka_time_decoupled) {
                 const long long ms = d * nl + npm;                          // nt real-plane equivalents
                 total += (size_t)ncell * nt * ms * ms * w + (size_t)ncell * nt * ms * 8;
+                if (o.vanka_factor_bf16 && o.prec_mg == STMG_F32)
+                    total += (size_t)ncell * nt * ms * ms * 2;              // BF16 copy of the factors
             } else {
                 total += (size_t)ncell * m * m * w + (size_t)ncell * m * 4;   // patch factors
             }

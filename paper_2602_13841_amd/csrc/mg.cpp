@@ -98,6 +98,7 @@ void mg_build(stmg_ctx *ctx)
     mg->nu1 = std::max(0, o.nu1);
     mg->nu2 = std::max(0, o.nu2);
     mg->use_graph = o.use_graphs != 0;
+    mg->factor_bf16 = o.vanka_factor_bf16 != 0 && mg->prec == STMG_F32 && mg->td;
     int dev = 0, lds = 65536;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
@@ -244,6 +245,7 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
             M.piv_off[sy] = (long long)sy * L.ncell * ms;
             off += (long long)L.ncell * (M.tdg.cplx[sy] ? 2 : 1) * mat;
         }
+        M.nfac = off;
         const size_t pb = (size_t)off * sizeof(T), ib = (size_t)M.tdg.nsys * L.ncell * ms * 4;
         if (M.patches.bytes < pb) M.patches.alloc(pb);
         if (M.piv.bytes < ib) M.piv.alloc(ib);
@@ -278,6 +280,13 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
                     STMG_HIP(launch_lu<T>(A, pv, M.ms, (int)L.ncell, M.info.as<int>(), max_lds, s));
             }
             STMG_HIP(launch_piv_to_perm(M.piv.as<int>(), M.perm.as<int>(), M.ms, (long long)M.tdg.nsys * L.ncell, s));
+            if constexpr (std::is_same<T, float>::value) {
+                if (ctx->mg->factor_bf16) {
+                    // the sweeps read a BF16 copy of the factors (half the bytes)
+                    if (M.fac16.bytes < (size_t)off * 2) M.fac16.alloc((size_t)off * 2);
+                    STMG_HIP(launch_pack_bf16(M.patches.as<float>(), M.fac16.as<unsigned short>(), off, s));
+                }
+            }
         }
         M.have_patches = true;
         return;
@@ -337,7 +346,40 @@ template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
     L.apply<T>(Mode::Jac, state_of<T>(M), d, t, nullptr, nullptr, 1, s);
     STMG_HIP(vec_axpby<T>(L.N, T(1), r, T(-1), t, s));
     TimerScope ts(&ctx->timers, "vanka_apply", s);
-    if (mg.td) {
+    bool applied = false;
+    if constexpr (std::is_same<T, float>::value) {
+        if (mg.td && mg.factor_bf16) {
+            SolveTdArgs<float, float, unsigned short> sb{};
+            sb.n0 = L.n[0];
+            sb.n1 = L.n[1];
+            sb.n2 = L.n[2];
+            sb.nt = L.nt;
+            sb.Nn = L.Nn;
+            sb.Nv1 = L.Nv1;
+            sb.Np1 = L.Np1;
+            sb.defect = t;
+            sb.nsys = M.tdg.nsys;
+            for (int sy = 0; sy < M.tdg.nsys; ++sy) {
+                sb.cplx[sy] = M.tdg.cplx[sy];
+                sb.sys[sy] = M.fac16.as<unsigned short>() + M.sys_off[sy];
+                sb.perm[sy] = M.perm.as<int>() + M.piv_off[sy];
+                for (int a = 0; a < L.nt; ++a) {
+                    sb.Tre[sy * 4 + a] = (float)M.tdg.Tre[sy * MAX_NT + a];
+                    sb.Tim[sy * 4 + a] = (float)M.tdg.Tim[sy * MAX_NT + a];
+                    sb.Fre[a * 4 + sy] = (float)M.tdg.Fre[a * MAX_NT + sy];
+                    sb.Fim[a * 4 + sy] = (float)M.tdg.Fim[a * MAX_NT + sy];
+                }
+            }
+            sb.E = M.E.as<float>();
+            sb.d = d;
+            sb.omega = (float)mg.omega;
+            STMG_HIP(launch_solve_td_bf16(L.dim, L.r, sb, (int)L.ncell, M.ms, s));
+            applied = true;
+        }
+    }
+    if (applied) {
+        // patch corrections already in M.E
+    } else if (mg.td) {
         SolveTdArgs<T, T> sa{};
         sa.n0 = L.n[0];
         sa.n1 = L.n[1];

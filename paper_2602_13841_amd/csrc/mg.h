@@ -21,6 +21,8 @@ struct MgLevel {
     int ms = 0;                   // spatial patch size
     long long sys_off[MAX_NT] = {0, 0, 0, 0}, piv_off[MAX_NT] = {0, 0, 0, 0};
     DevBuf perm;
+    long long nfac = 0;           // factor entries of all systems (time-decoupled)
+    DevBuf fac16;                 // BF16 copy of the FP32 factors (option)
     DevBuf r, d, t, E;            // work vectors in the multigrid precision
 };
 
@@ -62,6 +64,7 @@ struct Mg {
     double omega = 0.35;
     int weighting = 0;
     bool td = true;               // time-decoupled patch solves
+    bool factor_bf16 = false;     // FP32 patch factors applied from a BF16 copy
     int nu1 = 1, nu2 = 1;
     std::vector<MgLevel> lv;
     std::vector<std::unique_ptr<Transfer>> tr;   // tr[l]: level l -> l+1

@@ -55,14 +55,16 @@ template <typename TE, typename TP> struct PatchTdArgs {
     TP *sys[4];            // per system: [cell][plane][ms][ms] row-major
 };
 
-template <typename T, typename TP> struct SolveTdArgs {
+// TF: storage type of the LU factors (TP, or unsigned short = BF16 bits of
+// FP32 factors, widened to TP on load)
+template <typename T, typename TP, typename TF = TP> struct SolveTdArgs {
     int n0, n1, n2;
     int nt;
     long long Nn, Nv1, Np1;
     const T *defect;
     int nsys;
     int cplx[4];
-    const TP *sys[4];      // LU factors per system
+    const TF *sys[4];      // LU factors per system
     const int *perm[4];    // row permutation per system: [cell][ms]
     TP Tre[16], Tim[16];   // [s * 4 + a]
     TP Fre[16], Fim[16];   // [a * 4 + s]
@@ -101,6 +103,11 @@ hipError_t launch_piv_to_perm(const int *piv, int *perm, int m, long long nmat, 
 size_t solve_td_lds_bytes(int ms, int nt, size_t word);
 template <typename T, typename TP>
 hipError_t launch_solve_td(int dim, int r, const SolveTdArgs<T, TP> &a, int ncell, int ms, hipStream_t s);
+// the same with BF16-stored FP32 factors
+hipError_t launch_solve_td_bf16(int dim, int r, const SolveTdArgs<float, float, unsigned short> &a, int ncell, int ms,
+                                hipStream_t s);
+// FP32 -> BF16 bits (round to nearest even), n elements
+hipError_t launch_pack_bf16(const float *src, unsigned short *dst, long long n, hipStream_t s);
 // batched triangular solves with the factors of launch_lu (variable sizes:
 // vb gives sizes and offsets; b_off the element offsets of the right-hand sides)
 template <typename T>

@@ -31,6 +31,7 @@
 #include "stmg_internal.h"
 #include "vanka.h"
 
+#include <algorithm>
 #include <cstdlib>
 #include <mutex>
 #include <type_traits>
@@ -52,6 +53,13 @@ __device__ __forceinline__ short bf16_rne(float f)
     unsigned u = __float_as_uint(f);
     u += 0x7fffu + ((u >> 16) & 1u);
     return (short)(u >> 16);
+}
+
+// load one stored factor entry as T (unsigned short: BF16 bits, exact widening)
+template <typename T, typename TF> __device__ __forceinline__ T ld_factor(const TF *p)
+{
+    if constexpr (std::is_same<TF, unsigned short>::value) return (T)__uint_as_float((unsigned)(*p) << 16);
+    else return (T)(*p);
 }
 typedef double doublex4_t __attribute__((ext_vector_type(4)));
 
@@ -1191,8 +1199,8 @@ constexpr int SV_THREADS = 256;
 // loads in flight before it reduces, so a pass over the rows costs about one
 // memory latency instead of one per row.  Per row the summation order is
 // fixed: columns l16, l16+16, ..., then a 16-lane xor tree.
-template <typename T, bool CX, int KB = 64, int RU = 4>
-__device__ __forceinline__ void block_gemv_update(const T *__restrict__ Lr, const T *__restrict__ Li, int m, int kb,
+template <typename T, bool CX, int KB = 64, int RU = 4, typename TF = T>
+__device__ __forceinline__ void block_gemv_update(const TF *__restrict__ Lr, const TF *__restrict__ Li, int m, int kb,
                                                   int nbk, int rbeg, int rend, T *br, T *bi)
 {
     constexpr int NG = SV_THREADS / 16, CPL = KB / 16;   // columns per lane
@@ -1219,10 +1227,10 @@ __device__ __forceinline__ void block_gemv_update(const T *__restrict__ Lr, cons
                 const int c = l16 + 16 * i;
                 const bool ok = r < rend && c < nbk;
                 const long long oc = o + min(c, nbk - 1);
-                const T vr = Lr[oc];
+                const T vr = ld_factor<T>(Lr + oc);
                 lr[u][i] = ok ? vr : T(0);
                 if constexpr (CX) {
-                    const T vi = Li[oc];
+                    const T vi = ld_factor<T>(Li + oc);
                     li[u][i] = ok ? vi : T(0);
                 } else {
                     li[u][i] = T(0);
@@ -1254,8 +1262,8 @@ __device__ __forceinline__ void block_gemv_update(const T *__restrict__ Lr, cons
     }
 }
 
-template <typename T, int KB = 64>
-__device__ __forceinline__ void lu_substitute(const T *__restrict__ LU, int m, T *b, T *dblk)
+template <typename T, int KB = 64, typename TF = T>
+__device__ __forceinline__ void lu_substitute(const TF *__restrict__ LU, int m, T *b, T *dblk)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int g = tid >> 4, l16 = tid & 15;
@@ -1264,7 +1272,7 @@ __device__ __forceinline__ void lu_substitute(const T *__restrict__ LU, int m, T
         const int nbk = min(KB, m - kb);
         for (int e = tid; e < nbk * KB; e += SV_THREADS) {
             int i = e / KB, j = e % KB;
-            if (j < nbk) dblk[i * (KB + 1) + j] = LU[(long long)(kb + i) * m + kb + j];
+            if (j < nbk) dblk[i * (KB + 1) + j] = ld_factor<T>(LU + (long long)(kb + i) * m + kb + j);
         }
         __syncthreads();
         if (wv == 0) {
@@ -1276,7 +1284,7 @@ __device__ __forceinline__ void lu_substitute(const T *__restrict__ LU, int m, T
             if (lane < nbk) b[kb + lane] = y;
         }
         __syncthreads();
-        block_gemv_update<T, false, KB>(LU, nullptr, m, kb, nbk, kb + nbk, m, b, nullptr);
+        block_gemv_update<T, false, KB, 4, TF>(LU, (const TF *)nullptr, m, kb, nbk, kb + nbk, m, b, nullptr);
         __syncthreads();
     }
     // backward: upper with diagonal
@@ -1285,7 +1293,7 @@ __device__ __forceinline__ void lu_substitute(const T *__restrict__ LU, int m, T
         const int kb = bk * KB, nbk = min(KB, m - kb);
         for (int e = tid; e < nbk * KB; e += SV_THREADS) {
             int i = e / KB, j = e % KB;
-            if (j < nbk) dblk[i * (KB + 1) + j] = LU[(long long)(kb + i) * m + kb + j];
+            if (j < nbk) dblk[i * (KB + 1) + j] = ld_factor<T>(LU + (long long)(kb + i) * m + kb + j);
         }
         __syncthreads();
         if (wv == 0) {
@@ -1298,7 +1306,7 @@ __device__ __forceinline__ void lu_substitute(const T *__restrict__ LU, int m, T
             if (lane < nbk) b[kb + lane] = x;
         }
         __syncthreads();
-        block_gemv_update<T, false, KB>(LU, nullptr, m, kb, nbk, 0, kb, b, nullptr);
+        block_gemv_update<T, false, KB, 4, TF>(LU, (const TF *)nullptr, m, kb, nbk, 0, kb, b, nullptr);
         __syncthreads();
     }
 }
@@ -1730,9 +1738,9 @@ __global__ void piv_to_perm_kernel(const int *__restrict__ piv, int *__restrict_
 // with all SB*KB columns (longer contiguous row segments per load, two rows
 // per 16-lane group in flight for SB = 2: the same registers as KB columns
 // and four rows)
-template <typename T, int KB = 64, int SB = 1>
-__device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const T *__restrict__ Li, int m, T *br, T *bi, T *dr,
-                                T *di)
+template <typename T, int KB = 64, int SB = 1, typename TF = T>
+__device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const TF *__restrict__ Li, int m, T *br, T *bi,
+                                                T *dr, T *di)
 {
     constexpr int SW = SB * KB, RUS = SB == 1 ? 4 : (SB == 2 ? 2 : 1);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1740,8 +1748,8 @@ __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const 
         for (int e = tid; e < nbk * KB; e += SV_THREADS) {
             const int i = e / KB, j = e % KB;
             if (j < nbk) {
-                dr[i * (KB + 1) + j] = Lr[(long long)(kb + i) * m + kb + j];
-                di[i * (KB + 1) + j] = Li[(long long)(kb + i) * m + kb + j];
+                dr[i * (KB + 1) + j] = ld_factor<T>(Lr + (long long)(kb + i) * m + kb + j);
+                di[i * (KB + 1) + j] = ld_factor<T>(Li + (long long)(kb + i) * m + kb + j);
             }
         }
     };
@@ -1769,11 +1777,11 @@ __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const 
             }
             __syncthreads();
             if (kb + nbk < se) {
-                block_gemv_update<T, true, KB>(Lr, Li, m, kb, nbk, kb + nbk, se, br, bi);
+                block_gemv_update<T, true, KB, 4, TF>(Lr, Li, m, kb, nbk, kb + nbk, se, br, bi);
                 __syncthreads();
             }
         }
-        block_gemv_update<T, true, SW, RUS>(Lr, Li, m, sb, se - sb, se, m, br, bi);
+        block_gemv_update<T, true, SW, RUS, TF>(Lr, Li, m, sb, se - sb, se, m, br, bi);
         __syncthreads();
     }
     // backward: upper with diagonal
@@ -1809,11 +1817,11 @@ __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const 
             }
             __syncthreads();
             if (kb > sb) {
-                block_gemv_update<T, true, KB>(Lr, Li, m, kb, nbk, sb, kb, br, bi);
+                block_gemv_update<T, true, KB, 4, TF>(Lr, Li, m, kb, nbk, sb, kb, br, bi);
                 __syncthreads();
             }
         }
-        block_gemv_update<T, true, SW, RUS>(Lr, Li, m, sb, se - sb, 0, sb, br, bi);
+        block_gemv_update<T, true, SW, RUS, TF>(Lr, Li, m, sb, se - sb, 0, sb, br, bi);
         __syncthreads();
     }
 }
@@ -1822,8 +1830,8 @@ __device__ __forceinline__ void lu_substitute_c(const T *__restrict__ Lr, const 
 // time nodes, per eigen-system transform (with the LU row permutation),
 // substitute, transform back; velocity to the cell buffer E, pressure
 // updated in place (pressure unknowns belong to one cell)
-template <int DIM, int R, typename T, typename TP>
-__global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP> A)
+template <int DIM, int R, typename T, typename TP, typename TF = TP>
+__global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP, TF> A)
 {
     using Z = VS<DIM, R>;
     constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
@@ -1876,9 +1884,9 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP>
             bi[i] = si;
         }
         __syncthreads();
-        const TP *LU = A.sys[s] + (long long)cell * (cx ? 2 : 1) * MAT;
-        if (cx) lu_substitute_c<TP, KBT, 2>(LU, LU + MAT, MS, br, bi, dr, di);
-        else lu_substitute<TP, KBT>(LU, MS, br, dr);
+        const TF *LU = A.sys[s] + (long long)cell * (cx ? 2 : 1) * MAT;
+        if (cx) lu_substitute_c<TP, KBT, 2, TF>(LU, LU + MAT, MS, br, bi, dr, di);
+        else lu_substitute<TP, KBT, TF>(LU, MS, br, dr);
         for (int e = tid; e < nt * MS; e += SV_THREADS) {
             const int a = e / MS, j = e - (e / MS) * MS;
             TP v = A.Fre[a * 4 + s] * br[j];
@@ -2207,6 +2215,39 @@ hipError_t launch_solve_td(int dim, int r, const SolveTdArgs<T, TP> &a, int ncel
     SC(2, 1) SC(2, 2) SC(2, 3) SC(3, 1) SC(3, 2) SC(3, 3)
 #undef SC
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_solve_td_bf16(int dim, int r, const SolveTdArgs<float, float, unsigned short> &a, int ncell, int ms,
+                                hipStream_t s)
+{
+    using T = float;
+    using TP = float;
+    size_t bytes = solve_td_lds_bytes(ms, a.nt, sizeof(TP));
+#define SC(D, RR)                                                                                                      \
+    if (dim == D && r == RR) {                                                                                         \
+        hipError_t e = lds_attr((const void *)solve_td_kernel<D, RR, T, TP, unsigned short>, bytes);                    \
+        if (e != hipSuccess) return e;                                                                                 \
+        hipLaunchKernelGGL((solve_td_kernel<D, RR, T, TP, unsigned short>), dim3(ncell), dim3(SV_THREADS), bytes, s, a);              \
+        return hipGetLastError();                                                                                      \
+    }
+    SC(2, 1) SC(2, 2) SC(2, 3) SC(3, 1) SC(3, 2) SC(3, 3)
+#undef SC
+    return hipErrorInvalidValue;
+}
+
+__global__ void pack_bf16_kernel(const float *__restrict__ src, unsigned short *__restrict__ dst, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (unsigned short)bf16_rne(src[i]);
+}
+
+hipError_t launch_pack_bf16(const float *src, unsigned short *dst, long long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int th = 256;
+    const long long nb = std::min<long long>((n + th - 1) / th, 65536);
+    hipLaunchKernelGGL(pack_bf16_kernel, dim3((unsigned)nb), dim3(th), 0, s, src, dst, n);
+    return hipGetLastError();
 }
 
 template <typename T>

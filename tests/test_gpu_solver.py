@@ -239,6 +239,43 @@ def test_newton_matches_oracle(which, stmg):
     assert rel(u32, U_ref) < 1e-6
 
 
+@pytest.mark.parametrize("which", ["3d_4cube_r1k1", "2d_r2k2_pert_decay"])
+def test_bf16_factor_copy_newton_matches_oracle(which, stmg):
+    """FP32 multigrid whose sweeps read a BF16 copy of the patch factors: the
+    preconditioner changes, the converged slab solution does not (same FP64
+    residual tolerance, solution within the FP32-multigrid bar of the
+    oracle's); the V-cycle stays within a few per cent of the FP32-factor one
+    (factor entries perturbed by at most 2^-9 relative)."""
+    prob, slab, rhs, vprev, maxl = _newton_case(which)
+    H = S.Hierarchy(prob, max_levels=maxl)
+    U_ref, st_ref = S.newton_solve(slab, H, np.zeros(slab.N), rhs, vprev)
+    out = {}
+    for bf in (0, 1):
+        ctx = stmg.Context(prob.dim, prob.n, prob.r, prob.k, prob.nu, prob.tau, vertices=prob.vertices,
+                           prec_mg=stmg.STMG_F32, max_levels=maxl, vanka_factor_bf16=bf)
+        ctx.set_slab_data(dev(rhs) if rhs is not None else None, dev(vprev))
+        U = I.uniform(slab.N, 61)
+        ctx.smoother_rebuild(dev(U))
+        r_ = I.uniform(slab.N, 62)
+        vc = ctx.vcycle(dev(r_, torch.float32)).cpu().numpy()
+        u, st, rc = ctx.newton_solve(torch.zeros(slab.N, dtype=torch.float64, device="cuda"))
+        out[bf] = (vc, u.cpu().numpy(), st, rc)
+    vc32, _, _, _ = out[0]
+    vc16, u16, st16, rc16 = out[1]
+    assert not np.array_equal(vc16, vc32)              # the BF16 copy is what the sweeps read
+    assert rel(vc16, vc32) < 5e-2
+    assert rc16 == 0
+    assert st16.res_M <= max(1e-12, 1e-8 * st16.res0_M)
+    # with Dirichlet data on the whole boundary the pressure is fixed up to a
+    # constant per time node, which the preconditioner may shift
+    E = S.constant_pressure_vectors(slab)
+    diff = u16 - U_ref
+    diff -= E @ np.linalg.lstsq(E, diff, rcond=None)[0]
+    assert np.max(np.abs(diff)) < 1e-6 * np.max(np.abs(U_ref))
+    print(f"{which}: FGMRES per Newton step FP32 factors {list(out[0][2].fgmres_its[: out[0][2].newton_its])}, "
+          f"BF16 copy {list(st16.fgmres_its[: st16.newton_its])}")
+
+
 @pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[4]], ids=[IDS[0], IDS[2], IDS[4]])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_captured_vcycle_equals_eager(case, prec, stmg):
