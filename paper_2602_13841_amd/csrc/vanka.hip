@@ -1737,13 +1737,38 @@ __global__ void piv_to_perm_kernel(const int *__restrict__ piv, int *__restrict_
 // block by block, while the rows outside the super-block are updated once
 // with all SB*KB columns (longer contiguous row segments per load, two rows
 // per 16-lane group in flight for SB = 2: the same registers as KB columns
-// and four rows)
-template <typename T, int KB = 64, int SB = 1, typename TF = T>
+// and four rows).  With PF the next diagonal block is loaded into registers
+// while the current one is solved and the rows are updated, and stored into
+// the second LDS block (dr[2 KB(KB+1)] and di likewise must then hold two
+// blocks): the factors are read-only, so its load never waits for the solve.
+template <typename T, int KB = 64, int SB = 1, typename TF = T, bool PF = false>
 __device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const TF *__restrict__ Li, int m, T *br, T *bi,
                                                 T *dr, T *di)
 {
     constexpr int SW = SB * KB, RUS = SB == 1 ? 4 : (SB == 2 ? 2 : 1);
+    constexpr int DPT = (KB * KB + SV_THREADS - 1) / SV_THREADS, DB = KB * (KB + 1);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    T pr[DPT], pi[DPT];
+    // clamped unconditional loads of a diagonal block into registers
+    auto diag_regs = [&](int kb, int nbk) {
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) {
+            const int e = tid + q * SV_THREADS, i = min(e / KB, nbk - 1), j = min(e % KB, nbk - 1);
+            const long long o = (long long)(kb + i) * m + kb + j;
+            pr[q] = ld_factor<T>(Lr + o);
+            pi[q] = ld_factor<T>(Li + o);
+        }
+    };
+    auto diag_store = [&](int buf, int nbk) {
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) {
+            const int e = tid + q * SV_THREADS, i = e / KB, j = e % KB;
+            if (e < KB * KB && i < nbk && j < nbk) {
+                dr[buf * DB + i * (KB + 1) + j] = pr[q];
+                di[buf * DB + i * (KB + 1) + j] = pi[q];
+            }
+        }
+    };
     auto load_diag = [&](int kb, int nbk) {
         for (int e = tid; e < nbk * KB; e += SV_THREADS) {
             const int i = e / KB, j = e % KB;
@@ -1754,18 +1779,28 @@ __device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const
         }
     };
     // forward: unit lower
+    int cur = 0;
+    if constexpr (PF) {
+        diag_regs(0, min(KB, m));
+        diag_store(0, min(KB, m));
+    }
     for (int sb = 0; sb < m; sb += SW) {
         const int se = min(sb + SW, m);
         for (int kb = sb; kb < se; kb += KB) {
-            const int nbk = min(KB, se - kb);
-            load_diag(kb, nbk);
+            const int nbk = min(KB, se - kb), kn = kb + KB;
+            if constexpr (PF) {
+                if (kn < m) diag_regs(kn, min(KB, m - kn));
+            } else {
+                load_diag(kb, nbk);
+            }
             __syncthreads();
             if (wv == 0) {
+                const T *cr_ = dr + cur * DB, *ci_ = di + cur * DB;
                 T yr = lane < nbk ? br[kb + lane] : T(0), yi = lane < nbk ? bi[kb + lane] : T(0);
                 for (int c = 0; c < nbk; ++c) {
                     const T cr = __shfl(yr, c, 64), ci = __shfl(yi, c, 64);
                     if (lane > c && lane < nbk) {
-                        const T lr = dr[lane * (KB + 1) + c], li = di[lane * (KB + 1) + c];
+                        const T lr = cr_[lane * (KB + 1) + c], li = ci_[lane * (KB + 1) + c];
                         yr -= lr * cr - li * ci;
                         yi -= lr * ci + li * cr;
                     }
@@ -1778,26 +1813,41 @@ __device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const
             __syncthreads();
             if (kb + nbk < se) {
                 block_gemv_update<T, true, KB, 4, TF>(Lr, Li, m, kb, nbk, kb + nbk, se, br, bi);
-                __syncthreads();
             }
+            if constexpr (PF) {
+                if (kn < m) diag_store(cur ^ 1, min(KB, m - kn));
+                cur ^= 1;
+            }
+            __syncthreads();
         }
         block_gemv_update<T, true, SW, RUS, TF>(Lr, Li, m, sb, se - sb, se, m, br, bi);
         __syncthreads();
     }
     // backward: upper with diagonal
     const int nsb = (m + SW - 1) / SW;
+    const int nblk = (m + KB - 1) / KB;
+    if constexpr (PF) {
+        const int kl = (nblk - 1) * KB;
+        diag_regs(kl, m - kl);
+        diag_store(cur, m - kl);
+    }
     for (int bs = nsb - 1; bs >= 0; --bs) {
         const int sb = bs * SW, se = min(sb + SW, m);
         const int nin = (se - sb + KB - 1) / KB;
         for (int j = nin - 1; j >= 0; --j) {
-            const int kb = sb + j * KB, nbk = min(KB, se - kb);
-            load_diag(kb, nbk);
+            const int kb = sb + j * KB, nbk = min(KB, se - kb), kn = kb - KB;
+            if constexpr (PF) {
+                if (kn >= 0) diag_regs(kn, KB);
+            } else {
+                load_diag(kb, nbk);
+            }
             __syncthreads();
             if (wv == 0) {
+                const T *cr_ = dr + cur * DB, *ci_ = di + cur * DB;
                 T xr = lane < nbk ? br[kb + lane] : T(0), xi = lane < nbk ? bi[kb + lane] : T(0);
                 for (int c = nbk - 1; c >= 0; --c) {
                     const T vr = __shfl(xr, c, 64), vi = __shfl(xi, c, 64);
-                    const T ur = dr[c * (KB + 1) + c], ui = di[c * (KB + 1) + c];
+                    const T ur = cr_[c * (KB + 1) + c], ui = ci_[c * (KB + 1) + c];
                     const T den = ur * ur + ui * ui;
                     const T qr = (vr * ur + vi * ui) / den, qi = (vi * ur - vr * ui) / den;
                     if (lane == c) {
@@ -1805,7 +1855,7 @@ __device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const
                         xi = qi;
                     }
                     if (lane < c) {
-                        const T lr = dr[lane * (KB + 1) + c], li = di[lane * (KB + 1) + c];
+                        const T lr = cr_[lane * (KB + 1) + c], li = ci_[lane * (KB + 1) + c];
                         xr -= lr * qr - li * qi;
                         xi -= lr * qi + li * qr;
                     }
@@ -1818,8 +1868,12 @@ __device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const
             __syncthreads();
             if (kb > sb) {
                 block_gemv_update<T, true, KB, 4, TF>(Lr, Li, m, kb, nbk, sb, kb, br, bi);
-                __syncthreads();
             }
+            if constexpr (PF) {
+                if (kn >= 0) diag_store(cur ^ 1, KB);
+                cur ^= 1;
+            }
+            __syncthreads();
         }
         block_gemv_update<T, true, SW, RUS, TF>(Lr, Li, m, sb, se - sb, 0, sb, br, bi);
         __syncthreads();
@@ -1850,7 +1904,10 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP,
     // complex substitution updates the rows outside pairs of blocks with 64
     // columns at once (4 % faster sweeps than 32)
     constexpr int KBT = 32;
-    TP *di = dr + KBT * (KBT + 1);
+    // FP32, patches above 128 unknowns: two diagonal blocks per plane (the
+    // next one is prefetched)
+    constexpr bool PFD = sizeof(TP) == 4 && MS > 128;
+    TP *di = dr + (PFD ? 2 : 1) * KBT * (KBT + 1);
     const int cell = xcd_cell(blockIdx.x, gridDim.x), tid = threadIdx.x;
     const int c0 = cell % A.n0, c1 = (cell / A.n0) % A.n1, c2 = DIM == 3 ? cell / (A.n0 * A.n1) : 0;
     const long long N0 = (long long)(R + 1) * A.n0 + 1, N1g = (long long)(R + 1) * A.n1 + 1;
@@ -1885,7 +1942,7 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP,
         }
         __syncthreads();
         const TF *LU = A.sys[s] + (long long)cell * (cx ? 2 : 1) * MAT;
-        if (cx) lu_substitute_c<TP, KBT, 2, TF>(LU, LU + MAT, MS, br, bi, dr, di);
+        if (cx) lu_substitute_c<TP, KBT, 2, TF, PFD>(LU, LU + MAT, MS, br, bi, dr, di);
         else lu_substitute<TP, KBT, TF>(LU, MS, br, dr);
         for (int e = tid; e < nt * MS; e += SV_THREADS) {
             const int a = e / MS, j = e - (e / MS) * MS;
@@ -2198,7 +2255,8 @@ size_t solve_td_lds_bytes(int ms, int nt, size_t word)
 {
     const size_t msp = (size_t)((ms + 1) & ~1);
     const size_t kb = 32;   // diagonal-block width of solve_td_kernel
-    return (2 * nt * msp + 2 * msp + 2 * kb * (kb + 1)) * word;
+    const size_t nd = word == 4 && ms > 128 ? 4 : 2;   // FP32 (ms > 128): the next block is prefetched
+    return (2 * nt * msp + 2 * msp + nd * kb * (kb + 1)) * word;
 }
 
 template <typename T, typename TP>
