@@ -1669,43 +1669,51 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, 
             Ai[g] = pi[r * NBP + c];
         }
         __syncthreads();
+        // U12 = L11^{-1} A12 for every column right of the panel at once (one
+        // thread per column, all waves), written back to A; each trailing
+        // update then takes its U12 block from there
+#pragma unroll 1
+        for (int col = j0 + nb + tid; col < m; col += LU_THREADS) {
+            // compiler-only barrier: keeps the L11 reads from LDS inside the
+            // loop (hoisted, they would hold NB(NB-1) values in registers)
+            asm volatile("" ::: "memory");
+            T vr[NB], vi[NB];
+            for (int c = 0; c < NB; ++c) {
+                const bool ok = c < nb;
+                vr[c] = ok ? Ar[(long long)(j0 + c) * m + col] : T(0);
+                vi[c] = ok ? Ai[(long long)(j0 + c) * m + col] : T(0);
+            }
+            // fully unrolled (register arrays); rows c >= nb stay zero
+#pragma unroll
+            for (int c = 1; c < NB; ++c) {
+                T sr = vr[c], si = vi[c];
+#pragma unroll
+                for (int k = 0; k < c; ++k) {
+                    const T lr = pr[c * NBP + k], li = pi[c * NBP + k];
+                    sr -= lr * vr[k] - li * vi[k];
+                    si -= lr * vi[k] + li * vr[k];
+                }
+                if (c < nb) {
+                    vr[c] = sr;
+                    vi[c] = si;
+                }
+            }
+            for (int c = 0; c < NB; ++c)
+                if (c < nb) {
+                    Ar[(long long)(j0 + c) * m + col] = vr[c];
+                    Ai[(long long)(j0 + c) * m + col] = vi[c];
+                }
+        }
+        __syncthreads();
         for (int cb = j0 + nb; cb < m; cb += LU_CB) {
             const int ncb = min(LU_CB, m - cb);
             for (int e = tid; e < NB * LU_CB; e += LU_THREADS) {
-                ur[e] = T(0);
-                ui[e] = T(0);
-            }
-            __syncthreads();
-            if (tid < ncb) {
-                const int col = cb + tid;
-                T vr[NB], vi[NB];
-                for (int c = 0; c < NB; ++c) {
-                    const bool ok = c < nb;
-                    vr[c] = ok ? Ar[(long long)(j0 + c) * m + col] : T(0);
-                    vi[c] = ok ? Ai[(long long)(j0 + c) * m + col] : T(0);
-                }
-                // fully unrolled (register arrays); rows c >= nb stay zero
-#pragma unroll
-                for (int c = 1; c < NB; ++c) {
-                    T sr = vr[c], si = vi[c];
-#pragma unroll
-                    for (int k = 0; k < c; ++k) {
-                        const T lr = pr[c * NBP + k], li = pi[c * NBP + k];
-                        sr -= lr * vr[k] - li * vi[k];
-                        si -= lr * vi[k] + li * vr[k];
-                    }
-                    if (c < nb) {
-                        vr[c] = sr;
-                        vi[c] = si;
-                    }
-                }
-                for (int c = 0; c < NB; ++c)
-                    if (c < nb) {
-                        Ar[(long long)(j0 + c) * m + col] = vr[c];
-                        Ai[(long long)(j0 + c) * m + col] = vi[c];
-                        ur[c * LU_CB + tid] = vr[c];
-                        ui[c * LU_CB + tid] = vi[c];
-                    }
+                const int c = e / LU_CB, j = e % LU_CB;
+                const bool ok = c < nb && j < ncb;
+                const long long g = (long long)(j0 + min(c, nb - 1)) * m + cb + min(j, ncb - 1);
+                const T a = Ar[g], b = Ai[g];
+                ur[e] = ok ? a : T(0);
+                ui[e] = ok ? b : T(0);
             }
             __syncthreads();
             trailing_update_c<NBP>(Ar, Ai, m, j0, nb, cb, ncb, pr, pi, ur, ui);
