@@ -245,13 +245,17 @@ def bench_serve(nreq, slots):
     _, res2, wall2 = stmg.serve(reqs, o, slots=slots, hbm_budget=budget)
     lat = np.array([x.latency_s for x in res2])
     ok = sum(1 for x in res + res2 if x.rc == 0)
-    classes = {}
+    classes, sizes = {}, {}
     for q, x in zip(reqs, res2):
         classes.setdefault(f"{q['dim']}D", []).append(x.latency_s)
+        sizes.setdefault(f"{q['dim']}D n={q['n'][0]}", []).append(x.latency_s)
     return {"requests": nreq, "slots": slots, "hbm_budget_GB": budget / 1e9, "closed_loop_wall_s": wall,
             "solves_per_s": X, "arrival_rate": lam, "poisson_wall_s": wall2,
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "p50_by_dim": {k: float(np.percentile(v, 50)) for k, v in classes.items()},
+            "p99_by_dim": {k: float(np.percentile(v, 99)) for k, v in classes.items()},
+            "p50_p99_by_size": {k: [float(np.percentile(v, 50)), float(np.percentile(v, 99)), len(v)]
+                                for k, v in sorted(sizes.items())},
             "converged": ok, "runs": 2 * nreq}
 
 
@@ -265,7 +269,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-batched-lu", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true",
                     help="one 1 GiB device-to-device copy first (reference for the rocprofv3 byte counters)")
