@@ -373,11 +373,14 @@ def main():
         s32 = bench_solve(stmg.STMG_F32)
         print("[bench] slab solve, FP32 multigrid, BF16 copy of the patch factors", file=sys.stderr, flush=True)
         s16 = bench_solve(stmg.STMG_F32, vanka_factor_bf16=1)
+        print("[bench] slab solve, FP32 multigrid, diagonal Vanka", file=sys.stderr, flush=True)
+        sdv = bench_solve(stmg.STMG_F32, vanka_diagonal=1)
         print("[bench] slab solve, FP64 multigrid", file=sys.stderr, flush=True)
         s64 = bench_solve(stmg.STMG_F64)
         out["solve"] = {"workload": "3D 32^3 hexes perturbed by 0.2h, Q4/P3disc (r=3) x DG(1), Re=1000, "
                                     "tau=1/64, smooth previous-slab velocity, |R|_M <= 1e-8 |R_0|_M",
-                        "fp32_mg": s32, "fp32_mg_bf16_factors": s16, "fp64_mg": s64,
+                        "fp32_mg": s32, "fp32_mg_bf16_factors": s16, "fp32_mg_diagonal_vanka": sdv,
+                        "fp64_mg": s64,
                         "speedup_fp32_vs_fp64": s64["wall_s"] / s32["wall_s"]}
     if not args.no_batched_lu:
         print("[bench] batched patch factorizations", file=sys.stderr, flush=True)

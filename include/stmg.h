@@ -134,6 +134,12 @@ typedef struct {
      * relative to 2^-9), widened to FP32 for the substitutions.  0 (default)
      * or 1.  The copy adds half of the FP32 factor bytes to the footprint. */
     int vanka_factor_bf16;
+    /* Diagonal Vanka (the cheaper smoothing the paper's conclusions call
+     * for): in every patch system the velocity-velocity block keeps only its
+     * spatial diagonal (time coupling and pressure blocks stay), and the
+     * patch is solved through its pressure Schur complement.  Time-decoupled
+     * patches only (ignored otherwise).  0 (default) or 1. */
+    int vanka_diagonal;
 } stmg_options;
 
 typedef struct {

@@ -158,6 +158,7 @@ void stmg_default_options(stmg_options *o)
     o->use_graphs = 1;
     o->time_coarsening = 0;
     o->vanka_factor_bf16 = 0;
+    o->vanka_diagonal = 0;
 }
 
 int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_ctx **out)

@@ -98,7 +98,8 @@ void mg_build(stmg_ctx *ctx)
     mg->nu1 = std::max(0, o.nu1);
     mg->nu2 = std::max(0, o.nu2);
     mg->use_graph = o.use_graphs != 0;
-    mg->factor_bf16 = o.vanka_factor_bf16 != 0 && mg->prec == STMG_F32 && mg->td;
+    mg->diag = o.vanka_diagonal != 0 && mg->td;
+    mg->factor_bf16 = o.vanka_factor_bf16 != 0 && mg->prec == STMG_F32 && mg->td && !mg->diag;
     int dev = 0, lds = 65536;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
@@ -269,6 +270,31 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
             STMG_HIP((launch_patch_td<T, T>(L.dim, L.r, pa, (int)L.ncell, s)));
         }
         STMG_HIP(hipMemsetAsync(M.info.p, 0, 4, s));
+        if (ctx->mg->diag) {
+            // diagonal Vanka: D^{-1} and the LU of the pressure Schur
+            // complement per system; the systems stay unfactored
+            const int nv = L.dim * L.nl, npm = L.npm, ns = M.tdg.nsys;
+            const size_t bd = (size_t)ns * L.ncell * 2 * nv * sizeof(T);
+            const size_t bs = (size_t)ns * L.ncell * 2 * npm * npm * sizeof(T);
+            const size_t bp = (size_t)ns * L.ncell * npm * sizeof(int);
+            if (M.dv_dinv.bytes < bd) M.dv_dinv.alloc(bd);
+            if (M.dv_schur.bytes < bs) M.dv_schur.alloc(bs);
+            if (M.dv_piv.bytes < bp) M.dv_piv.alloc(bp);
+            DvArgs<T> da{};
+            da.nsys = ns;
+            for (int sy = 0; sy < ns; ++sy) {
+                da.cplx[sy] = M.tdg.cplx[sy];
+                da.sys[sy] = M.patches.as<T>() + M.sys_off[sy];
+                da.dinv[sy] = M.dv_dinv.as<T>() + (size_t)sy * L.ncell * 2 * nv;
+                da.schur[sy] = M.dv_schur.as<T>() + (size_t)sy * L.ncell * 2 * npm * npm;
+                da.spiv[sy] = M.dv_piv.as<int>() + (size_t)sy * L.ncell * npm;
+            }
+            da.info = M.info.as<int>();
+            TimerScope ts(&ctx->timers, "vanka_lu", s);
+            STMG_HIP(launch_dv_setup<T>(L.dim, L.r, da, (int)L.ncell, s));
+            M.have_patches = true;
+            return;
+        }
         {
             TimerScope ts(&ctx->timers, "vanka_lu", s);
             for (int sy = 0; sy < M.tdg.nsys; ++sy) {
@@ -347,8 +373,39 @@ template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
     STMG_HIP(vec_axpby<T>(L.N, T(1), r, T(-1), t, s));
     TimerScope ts(&ctx->timers, "vanka_apply", s);
     bool applied = false;
+    if (mg.td && mg.diag) {
+        const int nv = L.dim * L.nl, npm = L.npm;
+        DvArgs<T> da{};
+        da.n0 = L.n[0];
+        da.n1 = L.n[1];
+        da.n2 = L.n[2];
+        da.nt = L.nt;
+        da.Nn = L.Nn;
+        da.Nv1 = L.Nv1;
+        da.Np1 = L.Np1;
+        da.defect = t;
+        da.nsys = M.tdg.nsys;
+        for (int sy = 0; sy < M.tdg.nsys; ++sy) {
+            da.cplx[sy] = M.tdg.cplx[sy];
+            da.sys[sy] = M.patches.as<T>() + M.sys_off[sy];
+            da.dinv[sy] = M.dv_dinv.as<T>() + (size_t)sy * L.ncell * 2 * nv;
+            da.schur[sy] = M.dv_schur.as<T>() + (size_t)sy * L.ncell * 2 * npm * npm;
+            da.spiv[sy] = M.dv_piv.as<int>() + (size_t)sy * L.ncell * npm;
+            for (int a = 0; a < L.nt; ++a) {
+                da.Tre[sy * 4 + a] = (T)M.tdg.Tre[sy * MAX_NT + a];
+                da.Tim[sy * 4 + a] = (T)M.tdg.Tim[sy * MAX_NT + a];
+                da.Fre[a * 4 + sy] = (T)M.tdg.Fre[a * MAX_NT + sy];
+                da.Fim[a * 4 + sy] = (T)M.tdg.Fim[a * MAX_NT + sy];
+            }
+        }
+        da.E = M.E.as<T>();
+        da.d = d;
+        da.omega = (T)mg.omega;
+        STMG_HIP(launch_solve_dv<T>(L.dim, L.r, da, (int)L.ncell, s));
+        applied = true;
+    }
     if constexpr (std::is_same<T, float>::value) {
-        if (mg.td && mg.factor_bf16) {
+        if (!applied && mg.td && mg.factor_bf16) {
             SolveTdArgs<float, float, unsigned short> sb{};
             sb.n0 = L.n[0];
             sb.n1 = L.n[1];

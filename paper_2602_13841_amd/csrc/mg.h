@@ -23,6 +23,7 @@ struct MgLevel {
     DevBuf perm;
     long long nfac = 0;           // factor entries of all systems (time-decoupled)
     DevBuf fac16;                 // BF16 copy of the FP32 factors (option)
+    DevBuf dv_dinv, dv_schur, dv_piv;   // diagonal Vanka: D^{-1}, Schur LU, pivots
     DevBuf r, d, t, E;            // work vectors in the multigrid precision
 };
 
@@ -65,6 +66,7 @@ struct Mg {
     int weighting = 0;
     bool td = true;               // time-decoupled patch solves
     bool factor_bf16 = false;     // FP32 patch factors applied from a BF16 copy
+    bool diag = false;            // diagonal Vanka (velocity blocks by their diagonal)
     int nu1 = 1, nu2 = 1;
     std::vector<MgLevel> lv;
     std::vector<std::unique_ptr<Transfer>> tr;   // tr[l]: level l -> l+1

@@ -108,6 +108,33 @@ hipError_t launch_solve_td_bf16(int dim, int r, const SolveTdArgs<float, float, 
                                 hipStream_t s);
 // FP32 -> BF16 bits (round to nearest even), n elements
 hipError_t launch_pack_bf16(const float *src, unsigned short *dst, long long n, hipStream_t s);
+
+// diagonal Vanka on the time-decoupled patch systems: in every (possibly
+// complex) spatial system of a cell the velocity-velocity block is replaced
+// by its diagonal D, so the system is solved by the pressure Schur complement
+// S = C - B D^{-1} B^T (npm x npm).  sys: the unfactored systems (ms x ms
+// row-major, planar complex); dinv: [cell][2][nv] D^{-1} (re, im); schur:
+// [cell][2][npm npm] LU of S; spiv: [cell][npm] its row interchanges.
+template <typename T> struct DvArgs {
+    int n0, n1, n2;
+    int nt;
+    long long Nn, Nv1, Np1;
+    const T *defect;
+    int nsys;
+    int cplx[4];
+    const T *sys[4];
+    T *dinv[4];
+    T *schur[4];
+    int *spiv[4];
+    T Tre[16], Tim[16];    // [s * 4 + a]
+    T Fre[16], Fim[16];    // [a * 4 + s]
+    T *E;
+    T *d;
+    T omega;
+    int *info;             // incremented per exactly zero Schur pivot (may be NULL)
+};
+template <typename T> hipError_t launch_dv_setup(int dim, int r, const DvArgs<T> &a, int ncell, hipStream_t s);
+template <typename T> hipError_t launch_solve_dv(int dim, int r, const DvArgs<T> &a, int ncell, hipStream_t s);
 // batched triangular solves with the factors of launch_lu (variable sizes:
 // vb gives sizes and offsets; b_off the element offsets of the right-hand sides)
 template <typename T>

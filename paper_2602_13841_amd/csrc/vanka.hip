@@ -1968,6 +1968,277 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Diagonal Vanka on the time-decoupled patch systems (the cheaper smoother the
+// paper's conclusions point to): each spatial system [[A, B^T], [B, C]] of a
+// cell is replaced by [[diag(A), B^T], [B, C]] and solved through the
+// pressure Schur complement S = C - B diag(A)^{-1} B^T.  Complex systems are
+// planar (re plane, then im plane); real systems have no im plane.
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ void cmul(T ar, T ai, T br, T bi, T &cr, T &ci)
+{
+    cr = ar * br - ai * bi;
+    ci = ar * bi + ai * br;
+}
+
+// rebuild: D^{-1}, S and its LU (partial pivoting, one wavefront) per (cell,
+// system); grid (ncell, nsys)
+template <int DIM, int R, typename T>
+__global__ void __launch_bounds__(SV_THREADS) dv_setup_kernel(DvArgs<T> A)
+{
+    using Z = VS<DIM, R>;
+    constexpr int NV = DIM * Z::NL, NPM = Z::NPM, MS = NV + NPM;
+    constexpr long long MAT = (long long)MS * MS;
+    static_assert(NPM <= 64, "one lane per Schur row");
+    __shared__ T dvr[NV], dvi[NV], sr[NPM * NPM], si[NPM * NPM];
+    const int cell = blockIdx.x, sy = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const bool cx = A.cplx[sy] != 0;
+    const T *Mr = A.sys[sy] + (long long)cell * (cx ? 2 : 1) * MAT;
+    const T *Mi = Mr + MAT;   // read only when cx
+    T *gd = A.dinv[sy] + (long long)cell * 2 * NV;
+    for (int i = tid; i < NV; i += SV_THREADS) {
+        const T ar = Mr[(long long)i * MS + i], ai = cx ? Mi[(long long)i * MS + i] : T(0);
+        const T den = ar * ar + ai * ai;
+        const T ir = den != T(0) ? ar / den : T(0), ii = den != T(0) ? -ai / den : T(0);
+        dvr[i] = ir;
+        dvi[i] = ii;
+        gd[i] = ir;
+        gd[NV + i] = ii;
+    }
+    __syncthreads();
+    for (int e = tid; e < NPM * NPM; e += SV_THREADS) {
+        const int j = e / NPM, k = e - (e / NPM) * NPM;
+        const long long rj = (long long)(NV + j) * MS;
+        T acr = Mr[rj + NV + k], aci = cx ? Mi[rj + NV + k] : T(0);
+        for (int i = 0; i < NV; ++i) {
+            const long long ci_ = (long long)i * MS + NV + k;
+            const T bre = Mr[rj + i], bim = cx ? Mi[rj + i] : T(0);          // B[j][i]
+            const T cre = Mr[ci_], cim = cx ? Mi[ci_] : T(0);                   // B^T[i][k]
+            T tr, ti, ur, ui;
+            cmul(bre, bim, dvr[i], dvi[i], tr, ti);
+            cmul(tr, ti, cre, cim, ur, ui);
+            acr -= ur;
+            aci -= ui;
+        }
+        sr[e] = acr;
+        si[e] = aci;
+    }
+    __syncthreads();
+    if (wv == 0) {
+        int *pv = A.spiv[sy] + (long long)cell * NPM;
+        for (int c = 0; c < NPM; ++c) {
+            T best = T(-1);
+            int bi = c;
+            if (lane >= c && lane < NPM) {
+                const T x = sr[lane * NPM + c], y = si[lane * NPM + c];
+                best = x * x + y * y;
+                bi = lane;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const T ov = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ov > best || (ov == best && oi < bi)) {
+                    best = ov;
+                    bi = oi;
+                }
+            }
+            const int p = bi;
+            if (lane == 0) {
+                pv[c] = p;
+                if (best == T(0) && A.info) atomicAdd(A.info, 1);
+            }
+            if (p != c && lane < NPM) {
+                T t = sr[c * NPM + lane];
+                sr[c * NPM + lane] = sr[p * NPM + lane];
+                sr[p * NPM + lane] = t;
+                t = si[c * NPM + lane];
+                si[c * NPM + lane] = si[p * NPM + lane];
+                si[p * NPM + lane] = t;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const T dr = sr[c * NPM + c], di = si[c * NPM + c];
+            const T den = dr * dr + di * di;
+            const T ir = den != T(0) ? dr / den : T(0), ii = den != T(0) ? -di / den : T(0);
+            if (lane > c && lane < NPM) {
+                T lr, li;
+                cmul(sr[lane * NPM + c], si[lane * NPM + c], ir, ii, lr, li);
+                sr[lane * NPM + c] = lr;
+                si[lane * NPM + c] = li;
+                for (int cc = c + 1; cc < NPM; ++cc) {
+                    T ur, ui;
+                    cmul(lr, li, sr[c * NPM + cc], si[c * NPM + cc], ur, ui);
+                    sr[lane * NPM + cc] -= ur;
+                    si[lane * NPM + cc] -= ui;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+    T *gs = A.schur[sy] + (long long)cell * 2 * NPM * NPM;
+    for (int e = tid; e < NPM * NPM; e += SV_THREADS) {
+        gs[e] = sr[e];
+        gs[NPM * NPM + e] = si[e];
+    }
+}
+
+// one diagonal-Vanka patch solve per cell: gather the patch defect of all
+// time nodes, per eigen-system transform, t = D^{-1} f, h = g - B t,
+// p = S^{-1} h, u = t - D^{-1} B^T p, transform back; velocity to the cell
+// buffer E, pressure updated in place
+template <int DIM, int R, typename T>
+__global__ void __launch_bounds__(SV_THREADS) solve_dv_kernel(DvArgs<T> A)
+{
+    using Z = VS<DIM, R>;
+    constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
+    constexpr int NV = DIM * NL, MS = NV + NPM, MSP = (MS + 1) & ~1;
+    constexpr long long MAT = (long long)MS * MS;
+    static_assert(NPM <= 64, "one lane per Schur row");
+    extern __shared__ unsigned char lds_raw[];
+    const int nt = A.nt;
+    T *rl = reinterpret_cast<T *>(lds_raw);   // [nt][MS] patch defect
+    T *out = rl + nt * MSP;                   // [nt][MS] patch correction
+    T *br = out + nt * MSP;                   // system right-hand side / solution
+    T *bi = br + MSP;
+    T *hr = bi + MSP;                         // [NPM] Schur right-hand side
+    T *hi = hr + NPM;
+    const int cell = xcd_cell(blockIdx.x, gridDim.x), tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int c0 = cell % A.n0, c1 = (cell / A.n0) % A.n1, c2 = DIM == 3 ? cell / (A.n0 * A.n1) : 0;
+    const long long N0 = (long long)(R + 1) * A.n0 + 1, N1g = (long long)(R + 1) * A.n1 + 1;
+    const long long pbase = (long long)nt * A.Nv1;
+    for (int e = tid; e < nt * MS; e += SV_THREADS) {
+        const int a = e / MS, j = e - (e / MS) * MS;
+        long long g;
+        if (j < NV) {
+            const int l = j % NL, c = j / NL;
+            const int i0 = l % N1, i1 = (l / N1) % N1, i2 = DIM == 3 ? l / (N1 * N1) : 0;
+            g = a * A.Nv1 + c * A.Nn +
+                (((long long)(R + 1) * c0 + i0) + N0 * (((long long)(R + 1) * c1 + i1) + N1g * ((long long)(R + 1) * c2 + i2)));
+        } else {
+            g = pbase + a * A.Np1 + (long long)cell * NPM + (j - NV);
+        }
+        rl[a * MSP + j] = A.defect[g];
+        out[a * MSP + j] = T(0);
+    }
+    __syncthreads();
+    for (int sy = 0; sy < A.nsys; ++sy) {
+        const bool cx = A.cplx[sy] != 0;
+        const T *Mr = A.sys[sy] + (long long)cell * (cx ? 2 : 1) * MAT;
+        const T *Mi = Mr + MAT;   // read only when cx
+        const T *dv = A.dinv[sy] + (long long)cell * 2 * NV;
+        // transform, then t = D^{-1} f on the velocity part
+        for (int i = tid; i < MS; i += SV_THREADS) {
+            T xr = 0, xi = 0;
+            for (int a = 0; a < nt; ++a) {
+                xr += A.Tre[sy * 4 + a] * rl[a * MSP + i];
+                xi += A.Tim[sy * 4 + a] * rl[a * MSP + i];
+            }
+            if (i < NV) cmul(xr, xi, dv[i], dv[NV + i], xr, xi);
+            br[i] = xr;
+            bi[i] = xi;
+        }
+        __syncthreads();
+        // h = g - B t: one wavefront per pressure row
+        for (int j = wv; j < NPM; j += SV_THREADS / 64) {
+            const long long rj = (long long)(NV + j) * MS;
+            T sr_ = 0, si_ = 0;
+            for (int i = lane; i < NV; i += 64) {
+                T ur, ui;
+                cmul(Mr[rj + i], cx ? Mi[rj + i] : T(0), br[i], bi[i], ur, ui);
+                sr_ += ur;
+                si_ += ui;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                sr_ += __shfl_xor(sr_, off, 64);
+                si_ += __shfl_xor(si_, off, 64);
+            }
+            if (lane == 0) {
+                hr[j] = br[NV + j] - sr_;
+                hi[j] = bi[NV + j] - si_;
+            }
+        }
+        __syncthreads();
+        // p = S^{-1} h (row interchanges, unit lower, upper): one wavefront
+        if (wv == 0) {
+            const T *Sr = A.schur[sy] + (long long)cell * 2 * NPM * NPM, *Si = Sr + NPM * NPM;
+            const int *pv = A.spiv[sy] + (long long)cell * NPM;
+            if (lane == 0)
+                for (int j = 0; j < NPM; ++j) {
+                    const int p = pv[j];
+                    if (p != j) {
+                        T t = hr[j];
+                        hr[j] = hr[p];
+                        hr[p] = t;
+                        t = hi[j];
+                        hi[j] = hi[p];
+                        hi[p] = t;
+                    }
+                }
+            __builtin_amdgcn_wave_barrier();
+            T xr = lane < NPM ? hr[lane] : T(0), xi = lane < NPM ? hi[lane] : T(0);
+            for (int c = 0; c < NPM; ++c) {
+                const T cr = __shfl(xr, c, 64), ci = __shfl(xi, c, 64);
+                if (lane > c && lane < NPM) {
+                    T ur, ui;
+                    cmul(Sr[lane * NPM + c], Si[lane * NPM + c], cr, ci, ur, ui);
+                    xr -= ur;
+                    xi -= ui;
+                }
+            }
+            for (int c = NPM - 1; c >= 0; --c) {
+                const T vr = __shfl(xr, c, 64), vi = __shfl(xi, c, 64);
+                const T ur = Sr[c * NPM + c], ui = Si[c * NPM + c];
+                const T den = ur * ur + ui * ui;
+                const T qr = (vr * ur + vi * ui) / den, qi = (vi * ur - vr * ui) / den;
+                if (lane == c) {
+                    xr = qr;
+                    xi = qi;
+                }
+                if (lane < c) {
+                    T wr, wi;
+                    cmul(Sr[lane * NPM + c], Si[lane * NPM + c], qr, qi, wr, wi);
+                    xr -= wr;
+                    xi -= wi;
+                }
+            }
+            if (lane < NPM) {
+                br[NV + lane] = xr;
+                bi[NV + lane] = xi;
+            }
+        }
+        __syncthreads();
+        // u = t - D^{-1} B^T p
+        for (int i = tid; i < NV; i += SV_THREADS) {
+            const long long ri = (long long)i * MS + NV;
+            T sr_ = 0, si_ = 0;
+            for (int j = 0; j < NPM; ++j) {
+                T ur, ui;
+                cmul(Mr[ri + j], cx ? Mi[ri + j] : T(0), br[NV + j], bi[NV + j], ur, ui);
+                sr_ += ur;
+                si_ += ui;
+            }
+            T wr, wi;
+            cmul(sr_, si_, dv[i], dv[NV + i], wr, wi);
+            br[i] -= wr;
+            bi[i] -= wi;
+        }
+        __syncthreads();
+        for (int e = tid; e < nt * MS; e += SV_THREADS) {
+            const int a = e / MS, j = e - (e / MS) * MS;
+            T v = A.Fre[a * 4 + sy] * br[j];
+            if (cx) v -= A.Fim[a * 4 + sy] * bi[j];
+            out[a * MSP + j] += v;
+        }
+        __syncthreads();
+    }
+    T *Ec = A.E + (long long)cell * nt * NV;
+    for (int e = tid; e < nt * MS; e += SV_THREADS) {
+        const int a = e / MS, j = e - (e / MS) * MS;
+        if (j < NV) Ec[a * NV + j] = out[a * MSP + j];
+        else A.d[pbase + a * A.Np1 + (long long)cell * NPM + (j - NV)] += A.omega * out[a * MSP + j];
+    }
+}
+
 // batched solves with variable sizes: one workgroup per system
 template <typename T>
 __global__ void __launch_bounds__(SV_THREADS) batched_solve_kernel(const T *LUall, const int *pivall, LuBatch B,
@@ -2315,6 +2586,44 @@ hipError_t launch_pack_bf16(const float *src, unsigned short *dst, long long n, 
     hipLaunchKernelGGL(pack_bf16_kernel, dim3((unsigned)nb), dim3(th), 0, s, src, dst, n);
     return hipGetLastError();
 }
+
+template <typename T> hipError_t launch_dv_setup(int dim, int r, const DvArgs<T> &a, int ncell, hipStream_t s)
+{
+    if (ncell <= 0) return hipSuccess;
+    if (a.nsys < 1 || a.nsys > 4) return hipErrorInvalidValue;
+#define DC(D, RR)                                                                                                      \
+    if (dim == D && r == RR) {                                                                                         \
+        hipLaunchKernelGGL((dv_setup_kernel<D, RR, T>), dim3(ncell, a.nsys), dim3(SV_THREADS), 0, s, a);               \
+        return hipGetLastError();                                                                                      \
+    }
+    DC(2, 1) DC(2, 2) DC(2, 3) DC(3, 1) DC(3, 2) DC(3, 3)
+#undef DC
+    return hipErrorInvalidValue;
+}
+
+template <typename T> hipError_t launch_solve_dv(int dim, int r, const DvArgs<T> &a, int ncell, hipStream_t s)
+{
+    if (ncell <= 0) return hipSuccess;
+    const int npm = dim == 2 ? (r + 1) * (r + 2) / 2 : (r + 1) * (r + 2) * (r + 3) / 6;
+    const int ms = dim * (dim == 2 ? (r + 2) * (r + 2) : (r + 2) * (r + 2) * (r + 2)) + npm;
+    const size_t msp = (size_t)((ms + 1) & ~1);
+    const size_t bytes = (2 * (size_t)a.nt * msp + 2 * msp + 2 * (size_t)npm) * sizeof(T);
+#define SC(D, RR)                                                                                                      \
+    if (dim == D && r == RR) {                                                                                         \
+        hipError_t e = lds_attr((const void *)solve_dv_kernel<D, RR, T>, bytes);                                       \
+        if (e != hipSuccess) return e;                                                                                 \
+        hipLaunchKernelGGL((solve_dv_kernel<D, RR, T>), dim3(ncell), dim3(SV_THREADS), bytes, s, a);                   \
+        return hipGetLastError();                                                                                      \
+    }
+    SC(2, 1) SC(2, 2) SC(2, 3) SC(3, 1) SC(3, 2) SC(3, 3)
+#undef SC
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_dv_setup<double>(int, int, const DvArgs<double> &, int, hipStream_t);
+template hipError_t launch_dv_setup<float>(int, int, const DvArgs<float> &, int, hipStream_t);
+template hipError_t launch_solve_dv<double>(int, int, const DvArgs<double> &, int, hipStream_t);
+template hipError_t launch_solve_dv<float>(int, int, const DvArgs<float> &, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_batched_solve(const T *LU, const int *piv, int max_m, int batch, const LuBatch &vb,

@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
                 ("vanka_time_decoupled", ctypes.c_int),
                 ("use_graphs", ctypes.c_int),
                 ("time_coarsening", ctypes.c_int),
-                ("vanka_factor_bf16", ctypes.c_int)]
+                ("vanka_factor_bf16", ctypes.c_int),
+                ("vanka_diagonal", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

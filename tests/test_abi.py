@@ -34,7 +34,7 @@ def test_default_options():
     o = stmg.default_options()
     assert o.prec_mg == stmg.STMG_F32 and o.nu1 == 1 and o.nu2 == 1
     assert o.vanka_weighting == 1 and o.vanka_time_decoupled == 1 and o.use_graphs == 1
-    assert o.time_coarsening == 0 and o.vanka_factor_bf16 == 0
+    assert o.time_coarsening == 0 and o.vanka_factor_bf16 == 0 and o.vanka_diagonal == 0
     assert o.newton_rtol == 1e-8 and o.fgmres_maxit == 50
     assert (o.ew_eta0, o.ew_c, o.ew_theta, o.ew_eta_min) == (0.4, 0.5, 1.5, 1e-3)
 

@@ -249,3 +249,40 @@ def test_newton_c1_manufactured_converges():
     V, _ = slab.split(U)
     vend = V[-1].reshape(2, -1).T
     assert np.max(np.abs(vend - vex)) < 0.05 * np.max(np.abs(vex))
+
+
+def test_diagonal_vanka_patch_is_schur_elimination():
+    """Diagonal Vanka patch (velocity-velocity blocks reduced to their spatial
+    diagonal, time coupling kept) solved directly equals the block elimination
+    written from its definition: per spatial velocity unknown i the (k+1) x
+    (k+1) time block D_i of the exact patch, S = C - B D^{-1} B^T,
+    p = S^{-1}(g - B D^{-1} f), u = D^{-1}(f - B^T p)."""
+    import scipy.linalg as sla
+    for k in (0, 1, 2):
+        prob = Problem(dim=2, n=(4, 4), r=1, k=k, nu=0.05, tau=0.1)
+        H = S.Hierarchy(prob, max_levels=2, diagonal=True)
+        s = H.levels[0].slab
+        U = I.uniform(s.N, 70 + k)
+        H.set_state(U)
+        V, _ = s.split(U)
+        Jt = s.jacobian(U, surrogate_state=s.tt.phimid @ V)
+        idx = S.patch_indices(s)[5]
+        P = Jt[idx][:, idx].toarray()
+        nv = prob.dim * s.space.nl
+        nt = s.nt
+        n = nt * nv
+        rhs = I.uniform(len(idx), 80 + k)
+        f, g = rhs[:n], rhs[n:]
+        Dinv = np.zeros((n, n))
+        for i in range(nv):
+            ii = [a * nv + i for a in range(nt)]
+            Dinv[np.ix_(ii, ii)] = np.linalg.inv(P[np.ix_(ii, ii)])
+        B, BT, C = P[n:, :n], P[:n, n:], P[n:, n:]
+        p = np.linalg.solve(C - B @ Dinv @ BT, g - B @ Dinv @ f)
+        u = Dinv @ (f - BT @ p)
+        x = sla.lu_solve(sla.lu_factor(S.diagonal_velocity_block(s, P)), rhs)
+        assert np.allclose(x, np.concatenate([u, p]), rtol=1e-9, atol=1e-12 * np.max(np.abs(x)))
+        # the smoother uses exactly these patches
+        H.rebuild_smoother()
+        lu = H.levels[0].patches[5][1]
+        assert np.allclose(sla.lu_solve(lu, rhs), x, rtol=1e-12, atol=1e-14 * np.max(np.abs(x)))
