@@ -137,8 +137,10 @@ typedef struct {
     /* Diagonal Vanka (the cheaper smoothing the paper's conclusions call
      * for): in every patch system the velocity-velocity block keeps only its
      * spatial diagonal (time coupling and pressure blocks stay), and the
-     * patch is solved through its pressure Schur complement.  Time-decoupled
-     * patches only (ignored otherwise).  0 (default) or 1. */
+     * patch is solved through its pressure Schur complement.  2: the
+     * velocity-velocity blocks keep their node blocks instead (all velocity
+     * components of one node).  Time-decoupled patches only (ignored
+     * otherwise).  0 (default), 1 or 2. */
     int vanka_diagonal;
 } stmg_options;
 

@@ -263,7 +263,7 @@ class Hierarchy:
     """hp-STMG hierarchy of one slab problem."""
 
     def __init__(self, prob: Problem, max_levels: int = 0, omega: float | None = None, weighting: int = 1,
-                 time_coarsening: bool = False, diagonal: bool = False):
+                 time_coarsening: bool = False, diagonal: int = 0):
         self.prob = prob
         self.weighting = weighting
         self.diagonal = diagonal
@@ -322,7 +322,7 @@ class Hierarchy:
         Jt = s.jacobian(L.state, surrogate_state=vstar)
         mats = [Jt[idx][:, idx].toarray() for idx in patch_indices(s)]
         if self.diagonal:
-            mats = [diagonal_velocity_block(s, A) for A in mats]
+            mats = [diagonal_velocity_block(s, A, self.diagonal == 2) for A in mats]
         L.patches = [(idx, sla.lu_factor(A)) for idx, A in zip(patch_indices(s), mats)]
         mult = np.zeros(s.N)
         for idx, _ in L.patches:
@@ -403,17 +403,20 @@ def patch_indices(s: Slab):
     return out
 
 
-def diagonal_velocity_block(s: Slab, A):
+def diagonal_velocity_block(s: Slab, A, node_blocks: bool = False):
     """Diagonal Vanka (the cheaper smoother the paper's conclusions point to,
     after John's diagonal Vanka): in the patch matrix (velocity [a][c][node],
     then pressure [a][mode]) every velocity-velocity time block keeps only its
-    spatial diagonal (same component and node); the time coupling and the
+    spatial diagonal (same component and node), or with node_blocks the
+    entries of the same node (all component pairs); the time coupling and the
     pressure blocks stay."""
-    nv = s.prob.dim * s.space.nl
+    nl = s.space.nl
+    nv = s.prob.dim * nl
     n = s.nt * nv
     vi = np.arange(n) % nv
+    key = vi % nl if node_blocks else vi
     B = np.array(A, dtype=float)
-    B[:n, :n] *= vi[:, None] == vi[None, :]
+    B[:n, :n] *= key[:, None] == key[None, :]
     return B
 
 

@@ -99,6 +99,7 @@ void mg_build(stmg_ctx *ctx)
     mg->nu2 = std::max(0, o.nu2);
     mg->use_graph = o.use_graphs != 0;
     mg->diag = o.vanka_diagonal != 0 && mg->td;
+    mg->diag_block = o.vanka_diagonal == 2;
     mg->factor_bf16 = o.vanka_factor_bf16 != 0 && mg->prec == STMG_F32 && mg->td && !mg->diag;
     int dev = 0, lds = 65536;
     if (hipGetDevice(&dev) == hipSuccess &&
@@ -273,7 +274,7 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
         if (ctx->mg->diag) {
             // diagonal Vanka: D^{-1} and the LU of the pressure Schur
             // complement per system; the systems stay unfactored
-            const int nv = L.dim * L.nl, npm = L.npm, ns = M.tdg.nsys;
+            const int nv = ctx->mg->diag_block ? L.nl * L.dim * L.dim : L.dim * L.nl, npm = L.npm, ns = M.tdg.nsys;
             const size_t bd = (size_t)ns * L.ncell * 2 * nv * sizeof(T);
             const size_t bs = (size_t)ns * L.ncell * 2 * npm * npm * sizeof(T);
             const size_t bp = (size_t)ns * L.ncell * npm * sizeof(int);
@@ -290,6 +291,7 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
                 da.spiv[sy] = M.dv_piv.as<int>() + (size_t)sy * L.ncell * npm;
             }
             da.info = M.info.as<int>();
+            da.block = ctx->mg->diag_block ? 1 : 0;
             TimerScope ts(&ctx->timers, "vanka_lu", s);
             STMG_HIP(launch_dv_setup<T>(L.dim, L.r, da, (int)L.ncell, s));
             M.have_patches = true;
@@ -374,7 +376,7 @@ template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
     TimerScope ts(&ctx->timers, "vanka_apply", s);
     bool applied = false;
     if (mg.td && mg.diag) {
-        const int nv = L.dim * L.nl, npm = L.npm;
+        const int nv = mg.diag_block ? L.nl * L.dim * L.dim : L.dim * L.nl, npm = L.npm;   // stored D^{-1} entries
         DvArgs<T> da{};
         da.n0 = L.n[0];
         da.n1 = L.n[1];
@@ -401,6 +403,7 @@ template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
         da.E = M.E.as<T>();
         da.d = d;
         da.omega = (T)mg.omega;
+        da.block = mg.diag_block ? 1 : 0;
         STMG_HIP(launch_solve_dv<T>(L.dim, L.r, da, (int)L.ncell, s));
         applied = true;
     }

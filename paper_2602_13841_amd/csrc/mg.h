@@ -67,6 +67,7 @@ struct Mg {
     bool td = true;               // time-decoupled patch solves
     bool factor_bf16 = false;     // FP32 patch factors applied from a BF16 copy
     bool diag = false;            // diagonal Vanka (velocity blocks by their diagonal)
+    bool diag_block = false;      // ... or by their node blocks (all components of a node)
     int nu1 = 1, nu2 = 1;
     std::vector<MgLevel> lv;
     std::vector<std::unique_ptr<Transfer>> tr;   // tr[l]: level l -> l+1

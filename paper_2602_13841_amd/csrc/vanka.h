@@ -111,7 +111,8 @@ hipError_t launch_pack_bf16(const float *src, unsigned short *dst, long long n, 
 
 // diagonal Vanka on the time-decoupled patch systems: in every (possibly
 // complex) spatial system of a cell the velocity-velocity block is replaced
-// by its diagonal D, so the system is solved by the pressure Schur complement
+// by its diagonal D (or its node blocks: all velocity components of one
+// node), so the system is solved by the pressure Schur complement
 // S = C - B D^{-1} B^T (npm x npm).  sys: the unfactored systems (ms x ms
 // row-major, planar complex); dinv: [cell][2][nv] D^{-1} (re, im); schur:
 // [cell][2][npm npm] LU of S; spiv: [cell][npm] its row interchanges.
@@ -132,6 +133,8 @@ template <typename T> struct DvArgs {
     T *d;
     T omega;
     int *info;             // incremented per exactly zero Schur pivot (may be NULL)
+    int block;             // 0: diagonal D; 1: DIM x DIM node blocks (all
+                           // components of a node); dinv then [cell][2][nl][DIM][DIM]
 };
 template <typename T> hipError_t launch_dv_setup(int dim, int r, const DvArgs<T> &a, int ncell, hipStream_t s);
 template <typename T> hipError_t launch_solve_dv(int dim, int r, const DvArgs<T> &a, int ncell, hipStream_t s);

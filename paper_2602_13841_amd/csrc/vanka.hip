@@ -1981,44 +1981,172 @@ template <typename T> __device__ __forceinline__ void cmul(T ar, T ai, T br, T b
     ci = ar * bi + ai * br;
 }
 
-// rebuild: D^{-1}, S and its LU (partial pivoting, one wavefront) per (cell,
-// system); grid (ncell, nsys)
-template <int DIM, int R, typename T>
+// inverse of a small complex N x N block in registers (Gauss-Jordan with
+// partial pivoting); a singular block gives zeros
+template <int N, typename T> __device__ __forceinline__ void cinv_small(T (&ar)[N][N], T (&ai)[N][N])
+{
+    T xr[N][N], xi[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            xr[i][j] = i == j ? T(1) : T(0);
+            xi[i][j] = T(0);
+        }
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        int p = c;
+        T best = ar[c][c] * ar[c][c] + ai[c][c] * ai[c][c];
+#pragma unroll
+        for (int r = c + 1; r < N; ++r) {
+            const T v = ar[r][c] * ar[r][c] + ai[r][c] * ai[r][c];
+            if (v > best) {
+                best = v;
+                p = r;
+            }
+        }
+        if (best == T(0)) ok = false;
+#pragma unroll
+        for (int r = c + 1; r < N; ++r)
+            if (r == p) {
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    T t = ar[c][j]; ar[c][j] = ar[r][j]; ar[r][j] = t;
+                    t = ai[c][j]; ai[c][j] = ai[r][j]; ai[r][j] = t;
+                    t = xr[c][j]; xr[c][j] = xr[r][j]; xr[r][j] = t;
+                    t = xi[c][j]; xi[c][j] = xi[r][j]; xi[r][j] = t;
+                }
+            }
+        const T den = ar[c][c] * ar[c][c] + ai[c][c] * ai[c][c];
+        const T ir = den != T(0) ? ar[c][c] / den : T(0), ii = den != T(0) ? -ai[c][c] / den : T(0);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            T tr, ti;
+            cmul(ar[c][j], ai[c][j], ir, ii, tr, ti);
+            ar[c][j] = tr;
+            ai[c][j] = ti;
+            cmul(xr[c][j], xi[c][j], ir, ii, tr, ti);
+            xr[c][j] = tr;
+            xi[c][j] = ti;
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+            if (r != c) {
+                const T fr = ar[r][c], fi = ai[r][c];
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    T tr, ti;
+                    cmul(fr, fi, ar[c][j], ai[c][j], tr, ti);
+                    ar[r][j] -= tr;
+                    ai[r][j] -= ti;
+                    cmul(fr, fi, xr[c][j], xi[c][j], tr, ti);
+                    xr[r][j] -= tr;
+                    xi[r][j] -= ti;
+                }
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            ar[i][j] = ok ? xr[i][j] : T(0);
+            ai[i][j] = ok ? xi[i][j] : T(0);
+        }
+}
+
+// rebuild: D^{-1} (diagonal, or BLK: DIM x DIM node blocks), S and its LU
+// (partial pivoting, one wavefront) per (cell, system); grid (ncell, nsys)
+template <int DIM, int R, typename T, bool BLK>
 __global__ void __launch_bounds__(SV_THREADS) dv_setup_kernel(DvArgs<T> A)
 {
     using Z = VS<DIM, R>;
-    constexpr int NV = DIM * Z::NL, NPM = Z::NPM, MS = NV + NPM;
+    constexpr int NL = Z::NL, NV = DIM * NL, NPM = Z::NPM, MS = NV + NPM;
+    constexpr int ND = BLK ? NL * DIM * DIM : NV;   // stored D^{-1} entries per plane
     constexpr long long MAT = (long long)MS * MS;
     static_assert(NPM <= 64, "one lane per Schur row");
-    __shared__ T dvr[NV], dvi[NV], sr[NPM * NPM], si[NPM * NPM];
+    __shared__ T dvr[ND], dvi[ND], sr[NPM * NPM], si[NPM * NPM];
     const int cell = blockIdx.x, sy = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const bool cx = A.cplx[sy] != 0;
     const T *Mr = A.sys[sy] + (long long)cell * (cx ? 2 : 1) * MAT;
     const T *Mi = Mr + MAT;   // read only when cx
-    T *gd = A.dinv[sy] + (long long)cell * 2 * NV;
-    for (int i = tid; i < NV; i += SV_THREADS) {
-        const T ar = Mr[(long long)i * MS + i], ai = cx ? Mi[(long long)i * MS + i] : T(0);
-        const T den = ar * ar + ai * ai;
-        const T ir = den != T(0) ? ar / den : T(0), ii = den != T(0) ? -ai / den : T(0);
-        dvr[i] = ir;
-        dvi[i] = ii;
-        gd[i] = ir;
-        gd[NV + i] = ii;
+    T *gd = A.dinv[sy] + (long long)cell * 2 * ND;
+    if constexpr (BLK) {
+        // node l: unknowns c NL + l, c < DIM; block stored [l][c][c']
+        for (int l = tid; l < NL; l += SV_THREADS) {
+            T br_[DIM][DIM], bi_[DIM][DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                for (int c2 = 0; c2 < DIM; ++c2) {
+                    const long long o = (long long)(c * NL + l) * MS + c2 * NL + l;
+                    br_[c][c2] = Mr[o];
+                    bi_[c][c2] = cx ? Mi[o] : T(0);
+                }
+            cinv_small<DIM, T>(br_, bi_);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                for (int c2 = 0; c2 < DIM; ++c2) {
+                    const int q = (l * DIM + c) * DIM + c2;
+                    dvr[q] = br_[c][c2];
+                    dvi[q] = bi_[c][c2];
+                    gd[q] = br_[c][c2];
+                    gd[ND + q] = bi_[c][c2];
+                }
+        }
+    } else {
+        for (int i = tid; i < NV; i += SV_THREADS) {
+            const T ar = Mr[(long long)i * MS + i], ai = cx ? Mi[(long long)i * MS + i] : T(0);
+            const T den = ar * ar + ai * ai;
+            const T ir = den != T(0) ? ar / den : T(0), ii = den != T(0) ? -ai / den : T(0);
+            dvr[i] = ir;
+            dvi[i] = ii;
+            gd[i] = ir;
+            gd[ND + i] = ii;
+        }
     }
     __syncthreads();
     for (int e = tid; e < NPM * NPM; e += SV_THREADS) {
         const int j = e / NPM, k = e - (e / NPM) * NPM;
         const long long rj = (long long)(NV + j) * MS;
         T acr = Mr[rj + NV + k], aci = cx ? Mi[rj + NV + k] : T(0);
-        for (int i = 0; i < NV; ++i) {
-            const long long ci_ = (long long)i * MS + NV + k;
-            const T bre = Mr[rj + i], bim = cx ? Mi[rj + i] : T(0);          // B[j][i]
-            const T cre = Mr[ci_], cim = cx ? Mi[ci_] : T(0);                   // B^T[i][k]
-            T tr, ti, ur, ui;
-            cmul(bre, bim, dvr[i], dvi[i], tr, ti);
-            cmul(tr, ti, cre, cim, ur, ui);
-            acr -= ur;
-            aci -= ui;
+        if constexpr (BLK) {
+            for (int l = 0; l < NL; ++l) {
+                T wr[DIM], wi[DIM];   // (D_l^{-1} B^T[:, k]) for the node's components
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    wr[c] = 0;
+                    wi[c] = 0;
+#pragma unroll
+                    for (int c2 = 0; c2 < DIM; ++c2) {
+                        const long long o = (long long)(c2 * NL + l) * MS + NV + k;
+                        T tr, ti;
+                        cmul(dvr[(l * DIM + c) * DIM + c2], dvi[(l * DIM + c) * DIM + c2], Mr[o], cx ? Mi[o] : T(0),
+                             tr, ti);
+                        wr[c] += tr;
+                        wi[c] += ti;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    T tr, ti;
+                    cmul(Mr[rj + c * NL + l], cx ? Mi[rj + c * NL + l] : T(0), wr[c], wi[c], tr, ti);
+                    acr -= tr;
+                    aci -= ti;
+                }
+            }
+        } else {
+            for (int i = 0; i < NV; ++i) {
+                const long long ci_ = (long long)i * MS + NV + k;
+                const T bre = Mr[rj + i], bim = cx ? Mi[rj + i] : T(0);          // B[j][i]
+                const T cre = Mr[ci_], cim = cx ? Mi[ci_] : T(0);                   // B^T[i][k]
+                T tr, ti, ur, ui;
+                cmul(bre, bim, dvr[i], dvi[i], tr, ti);
+                cmul(tr, ti, cre, cim, ur, ui);
+                acr -= ur;
+                aci -= ui;
+            }
         }
         sr[e] = acr;
         si[e] = aci;
@@ -2086,7 +2214,7 @@ __global__ void __launch_bounds__(SV_THREADS) dv_setup_kernel(DvArgs<T> A)
 // time nodes, per eigen-system transform, t = D^{-1} f, h = g - B t,
 // p = S^{-1} h, u = t - D^{-1} B^T p, transform back; velocity to the cell
 // buffer E, pressure updated in place
-template <int DIM, int R, typename T>
+template <int DIM, int R, typename T, bool BLK>
 __global__ void __launch_bounds__(SV_THREADS) solve_dv_kernel(DvArgs<T> A)
 {
     using Z = VS<DIM, R>;
@@ -2125,7 +2253,8 @@ __global__ void __launch_bounds__(SV_THREADS) solve_dv_kernel(DvArgs<T> A)
         const bool cx = A.cplx[sy] != 0;
         const T *Mr = A.sys[sy] + (long long)cell * (cx ? 2 : 1) * MAT;
         const T *Mi = Mr + MAT;   // read only when cx
-        const T *dv = A.dinv[sy] + (long long)cell * 2 * NV;
+        constexpr int ND = BLK ? NL * DIM * DIM : NV;
+        const T *dv = A.dinv[sy] + (long long)cell * 2 * ND;
         // transform, then t = D^{-1} f on the velocity part
         for (int i = tid; i < MS; i += SV_THREADS) {
             T xr = 0, xi = 0;
@@ -2133,11 +2262,37 @@ __global__ void __launch_bounds__(SV_THREADS) solve_dv_kernel(DvArgs<T> A)
                 xr += A.Tre[sy * 4 + a] * rl[a * MSP + i];
                 xi += A.Tim[sy * 4 + a] * rl[a * MSP + i];
             }
-            if (i < NV) cmul(xr, xi, dv[i], dv[NV + i], xr, xi);
+            if (!BLK && i < NV) cmul(xr, xi, dv[i], dv[ND + i], xr, xi);
             br[i] = xr;
             bi[i] = xi;
         }
         __syncthreads();
+        if constexpr (BLK) {
+            // node blocks: t_l = D_l^{-1} f_l (one thread per node)
+            for (int l = tid; l < NL; l += SV_THREADS) {
+                T fr[DIM], fi[DIM];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    fr[c] = br[c * NL + l];
+                    fi[c] = bi[c * NL + l];
+                }
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    T sr_ = 0, si_ = 0;
+#pragma unroll
+                    for (int c2 = 0; c2 < DIM; ++c2) {
+                        const int q = (l * DIM + c) * DIM + c2;
+                        T tr, ti;
+                        cmul(dv[q], dv[ND + q], fr[c2], fi[c2], tr, ti);
+                        sr_ += tr;
+                        si_ += ti;
+                    }
+                    br[c * NL + l] = sr_;
+                    bi[c * NL + l] = si_;
+                }
+            }
+            __syncthreads();
+        }
         // h = g - B t: one wavefront per pressure row
         for (int j = wv; j < NPM; j += SV_THREADS / 64) {
             const long long rj = (long long)(NV + j) * MS;
@@ -2208,19 +2363,54 @@ __global__ void __launch_bounds__(SV_THREADS) solve_dv_kernel(DvArgs<T> A)
         }
         __syncthreads();
         // u = t - D^{-1} B^T p
-        for (int i = tid; i < NV; i += SV_THREADS) {
-            const long long ri = (long long)i * MS + NV;
-            T sr_ = 0, si_ = 0;
-            for (int j = 0; j < NPM; ++j) {
-                T ur, ui;
-                cmul(Mr[ri + j], cx ? Mi[ri + j] : T(0), br[NV + j], bi[NV + j], ur, ui);
-                sr_ += ur;
-                si_ += ui;
+        if constexpr (BLK) {
+            for (int l = tid; l < NL; l += SV_THREADS) {
+                T qr[DIM], qi[DIM];   // (B^T p) at the node's components
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    const long long ri = (long long)(c * NL + l) * MS + NV;
+                    T sr_ = 0, si_ = 0;
+#pragma unroll 4
+                    for (int j = 0; j < NPM; ++j) {
+                        T ur, ui;
+                        cmul(Mr[ri + j], cx ? Mi[ri + j] : T(0), br[NV + j], bi[NV + j], ur, ui);
+                        sr_ += ur;
+                        si_ += ui;
+                    }
+                    qr[c] = sr_;
+                    qi[c] = si_;
+                }
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    T sr_ = 0, si_ = 0;
+#pragma unroll
+                    for (int c2 = 0; c2 < DIM; ++c2) {
+                        const int q = (l * DIM + c) * DIM + c2;
+                        T tr, ti;
+                        cmul(dv[q], dv[ND + q], qr[c2], qi[c2], tr, ti);
+                        sr_ += tr;
+                        si_ += ti;
+                    }
+                    br[c * NL + l] -= sr_;
+                    bi[c * NL + l] -= si_;
+                }
             }
-            T wr, wi;
-            cmul(sr_, si_, dv[i], dv[NV + i], wr, wi);
-            br[i] -= wr;
-            bi[i] -= wi;
+        } else {
+            for (int i = tid; i < NV; i += SV_THREADS) {
+                const long long ri = (long long)i * MS + NV;
+                T sr_ = 0, si_ = 0;
+#pragma unroll 4
+                for (int j = 0; j < NPM; ++j) {
+                    T ur, ui;
+                    cmul(Mr[ri + j], cx ? Mi[ri + j] : T(0), br[NV + j], bi[NV + j], ur, ui);
+                    sr_ += ur;
+                    si_ += ui;
+                }
+                T wr, wi;
+                cmul(sr_, si_, dv[i], dv[ND + i], wr, wi);
+                br[i] -= wr;
+                bi[i] -= wi;
+            }
         }
         __syncthreads();
         for (int e = tid; e < nt * MS; e += SV_THREADS) {
@@ -2593,7 +2783,10 @@ template <typename T> hipError_t launch_dv_setup(int dim, int r, const DvArgs<T>
     if (a.nsys < 1 || a.nsys > 4) return hipErrorInvalidValue;
 #define DC(D, RR)                                                                                                      \
     if (dim == D && r == RR) {                                                                                         \
-        hipLaunchKernelGGL((dv_setup_kernel<D, RR, T>), dim3(ncell, a.nsys), dim3(SV_THREADS), 0, s, a);               \
+        if (a.block)                                                                                                   \
+            hipLaunchKernelGGL((dv_setup_kernel<D, RR, T, true>), dim3(ncell, a.nsys), dim3(SV_THREADS), 0, s, a);     \
+        else                                                                                                           \
+            hipLaunchKernelGGL((dv_setup_kernel<D, RR, T, false>), dim3(ncell, a.nsys), dim3(SV_THREADS), 0, s, a);    \
         return hipGetLastError();                                                                                      \
     }
     DC(2, 1) DC(2, 2) DC(2, 3) DC(3, 1) DC(3, 2) DC(3, 3)
@@ -2610,9 +2803,15 @@ template <typename T> hipError_t launch_solve_dv(int dim, int r, const DvArgs<T>
     const size_t bytes = (2 * (size_t)a.nt * msp + 2 * msp + 2 * (size_t)npm) * sizeof(T);
 #define SC(D, RR)                                                                                                      \
     if (dim == D && r == RR) {                                                                                         \
-        hipError_t e = lds_attr((const void *)solve_dv_kernel<D, RR, T>, bytes);                                       \
-        if (e != hipSuccess) return e;                                                                                 \
-        hipLaunchKernelGGL((solve_dv_kernel<D, RR, T>), dim3(ncell), dim3(SV_THREADS), bytes, s, a);                   \
+        if (a.block) {                                                                                                 \
+            hipError_t e = lds_attr((const void *)solve_dv_kernel<D, RR, T, true>, bytes);                             \
+            if (e != hipSuccess) return e;                                                                             \
+            hipLaunchKernelGGL((solve_dv_kernel<D, RR, T, true>), dim3(ncell), dim3(SV_THREADS), bytes, s, a);         \
+        } else {                                                                                                       \
+            hipError_t e = lds_attr((const void *)solve_dv_kernel<D, RR, T, false>, bytes);                            \
+            if (e != hipSuccess) return e;                                                                             \
+            hipLaunchKernelGGL((solve_dv_kernel<D, RR, T, false>), dim3(ncell), dim3(SV_THREADS), bytes, s, a);        \
+        }                                                                                                              \
         return hipGetLastError();                                                                                      \
     }
     SC(2, 1) SC(2, 2) SC(2, 3) SC(3, 1) SC(3, 2) SC(3, 3)

@@ -245,7 +245,8 @@ DV_IDS = [c[0] for c in DV_CASES]
 
 @pytest.mark.parametrize("case", DV_CASES, ids=DV_IDS)
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_diagonal_vanka_sweep_and_vcycle(case, prec, stmg):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_diagonal_vanka_sweep_and_vcycle(case, prec, mode, stmg):
     """Diagonal Vanka (option): the library's Schur-complement patch solves
     on the time-decoupled systems against the oracle's dense solves of the
     diagonal-velocity patches (real and complex eigen-systems, k = 0 ... 3)."""
@@ -255,9 +256,9 @@ def test_diagonal_vanka_sweep_and_vcycle(case, prec, stmg):
     tol = 1e-9 if prec == "f64" else 2e-4
     vert = I.perturbed_vertices(d, n, 0.2, 60 + r) if pert else None
     prob = oracle.Problem(dim=d, n=n, r=r, k=k, nu=nu, tau=tau, vertices=vert, dirichlet_mask=mask)
-    H = S.Hierarchy(prob, max_levels=maxl, diagonal=True)
+    H = S.Hierarchy(prob, max_levels=maxl, diagonal=mode)
     ctx = stmg.Context(d, n, r, k, nu, tau, vertices=vert, dirichlet_faces=prob.dirichlet_mask,
-                       prec_mg=p, max_levels=maxl, vanka_diagonal=1)
+                       prec_mg=p, max_levels=maxl, vanka_diagonal=mode)
     s0 = H.levels[0].slab
     U = I.uniform(s0.N, 63)
     H.set_state(U)
@@ -274,19 +275,20 @@ def test_diagonal_vanka_sweep_and_vcycle(case, prec, stmg):
 
 
 @pytest.mark.parametrize("which", ["c1_manufactured", "3d_4cube_r1k1"])
-def test_diagonal_vanka_newton_matches_oracle(which, stmg):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_diagonal_vanka_newton_matches_oracle(which, mode, stmg):
     prob, slab, rhs, vprev, maxl = _newton_case(which)
-    H = S.Hierarchy(prob, max_levels=maxl, diagonal=True)
+    H = S.Hierarchy(prob, max_levels=maxl, diagonal=mode)
     U_ref, st_ref = S.newton_solve(slab, H, np.zeros(slab.N), rhs, vprev)
     assert st_ref.converged
     ctx = stmg.Context(prob.dim, prob.n, prob.r, prob.k, prob.nu, prob.tau, vertices=prob.vertices,
-                       prec_mg=stmg.STMG_F64, max_levels=maxl, vanka_diagonal=1)
+                       prec_mg=stmg.STMG_F64, max_levels=maxl, vanka_diagonal=mode)
     ctx.set_slab_data(dev(rhs) if rhs is not None else None, dev(vprev))
     u, st, rc = ctx.newton_solve(torch.zeros(slab.N, dtype=torch.float64, device="cuda"))
     assert rc == 0 and st.newton_its == st_ref.newton_its
     assert list(st.fgmres_its[: st.newton_its]) == st_ref.fgmres_its
     assert rel(u.cpu().numpy(), U_ref) < 1e-7
-    print(f"{which}: diagonal Vanka FGMRES per Newton step {st_ref.fgmres_its}")
+    print(f"{which}: diagonal Vanka (mode {mode}) FGMRES per Newton step {st_ref.fgmres_its}")
 
 
 @pytest.mark.parametrize("which", ["3d_4cube_r1k1", "2d_r2k2_pert_decay"])

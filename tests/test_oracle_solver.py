@@ -251,16 +251,18 @@ def test_newton_c1_manufactured_converges():
     assert np.max(np.abs(vend - vex)) < 0.05 * np.max(np.abs(vex))
 
 
-def test_diagonal_vanka_patch_is_schur_elimination():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_diagonal_vanka_patch_is_schur_elimination(mode):
     """Diagonal Vanka patch (velocity-velocity blocks reduced to their spatial
-    diagonal, time coupling kept) solved directly equals the block elimination
-    written from its definition: per spatial velocity unknown i the (k+1) x
-    (k+1) time block D_i of the exact patch, S = C - B D^{-1} B^T,
+    diagonal, or mode 2 to their node blocks, time coupling kept) solved
+    directly equals the block elimination written from its definition: per
+    spatial velocity unknown i (mode 2: per node, all components) the block D_i
+    of the exact patch over the time nodes, S = C - B D^{-1} B^T,
     p = S^{-1}(g - B D^{-1} f), u = D^{-1}(f - B^T p)."""
     import scipy.linalg as sla
     for k in (0, 1, 2):
         prob = Problem(dim=2, n=(4, 4), r=1, k=k, nu=0.05, tau=0.1)
-        H = S.Hierarchy(prob, max_levels=2, diagonal=True)
+        H = S.Hierarchy(prob, max_levels=2, diagonal=mode)
         s = H.levels[0].slab
         U = I.uniform(s.N, 70 + k)
         H.set_state(U)
@@ -274,13 +276,15 @@ def test_diagonal_vanka_patch_is_schur_elimination():
         rhs = I.uniform(len(idx), 80 + k)
         f, g = rhs[:n], rhs[n:]
         Dinv = np.zeros((n, n))
-        for i in range(nv):
-            ii = [a * nv + i for a in range(nt)]
+        nl = s.space.nl
+        groups = [[i] for i in range(nv)] if mode == 1 else [[c * nl + l for c in range(prob.dim)] for l in range(nl)]
+        for grp in groups:
+            ii = [a * nv + i for a in range(nt) for i in grp]
             Dinv[np.ix_(ii, ii)] = np.linalg.inv(P[np.ix_(ii, ii)])
         B, BT, C = P[n:, :n], P[:n, n:], P[n:, n:]
         p = np.linalg.solve(C - B @ Dinv @ BT, g - B @ Dinv @ f)
         u = Dinv @ (f - BT @ p)
-        x = sla.lu_solve(sla.lu_factor(S.diagonal_velocity_block(s, P)), rhs)
+        x = sla.lu_solve(sla.lu_factor(S.diagonal_velocity_block(s, P, mode == 2)), rhs)
         assert np.allclose(x, np.concatenate([u, p]), rtol=1e-9, atol=1e-12 * np.max(np.abs(x)))
         # the smoother uses exactly these patches
         H.rebuild_smoother()
