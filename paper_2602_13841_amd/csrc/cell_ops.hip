@@ -649,6 +649,12 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
     }
     for (int e = tid; e < nt * NPF; e += NTH) xpf[e] = 0;
     const T hcar[3] = {T(1) / A.n0, T(1) / A.n1, DIM == 3 ? T(1) / A.n2 : T(1)};
+    // Cartesian cells: J^{-T} = diag(1/h) and det J, the same for every point
+    // (formed once here instead of per point and time node)
+    const T hinv[3] = {T(1) / hcar[0], T(1) / hcar[1], T(1) / hcar[2]};
+    T det_c = 1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) det_c *= hcar[d];
     const bool mapped = A.mapped != 0;
     if (mapped && tid < (1 << DIM)) {
         int v = tid;
@@ -712,7 +718,16 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
                 T xi[3] = {0, 0, 0}, Jit[3][3];
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) xi[d] = qx[qi[d]];
-                const T det = geometry<DIM>(mapped, geo, xi, hcar, Jit);
+                T det;
+                if (mapped) {
+                    det = geometry<DIM>(true, geo, xi, hcar, Jit);
+                } else {
+#pragma unroll
+                    for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+                        for (int b2 = 0; b2 < 3; ++b2) Jit[a2][b2] = a2 == b2 && a2 < DIM ? hinv[a2] : T(0);
+                    det = det_c;
+                }
                 T jxw = det;
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) jxw *= qw[qi[d]];
