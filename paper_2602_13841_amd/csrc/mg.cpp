@@ -364,15 +364,19 @@ void mg_rebuild(stmg_ctx *ctx)
     }
 }
 
-template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
+template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d, bool d_zero)
 {
     Mg &mg = *ctx->mg;
     MgLevel &M = mg.lv[l];
     Level &L = *M.L;
     hipStream_t s = ctx->stream;
     T *t = M.t.as<T>();
-    L.apply<T>(Mode::Jac, state_of<T>(M), d, t, nullptr, nullptr, 1, s);
-    STMG_HIP(vec_axpby<T>(L.N, T(1), r, T(-1), t, s));
+    const T *defect = r;   // r - J d with d = 0
+    if (!d_zero) {
+        L.apply<T>(Mode::Jac, state_of<T>(M), d, t, nullptr, nullptr, 1, s);
+        STMG_HIP(vec_axpby<T>(L.N, T(1), r, T(-1), t, s));
+        defect = t;
+    }
     TimerScope ts(&ctx->timers, "vanka_apply", s);
     bool applied = false;
     if (mg.td && mg.diag) {
@@ -385,7 +389,7 @@ template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
         da.Nn = L.Nn;
         da.Nv1 = L.Nv1;
         da.Np1 = L.Np1;
-        da.defect = t;
+        da.defect = defect;
         da.nsys = M.tdg.nsys;
         for (int sy = 0; sy < M.tdg.nsys; ++sy) {
             da.cplx[sy] = M.tdg.cplx[sy];
@@ -417,7 +421,7 @@ template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
             sb.Nn = L.Nn;
             sb.Nv1 = L.Nv1;
             sb.Np1 = L.Np1;
-            sb.defect = t;
+            sb.defect = defect;
             sb.nsys = M.tdg.nsys;
             for (int sy = 0; sy < M.tdg.nsys; ++sy) {
                 sb.cplx[sy] = M.tdg.cplx[sy];
@@ -448,7 +452,7 @@ template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
         sa.Nn = L.Nn;
         sa.Nv1 = L.Nv1;
         sa.Np1 = L.Np1;
-        sa.defect = t;
+        sa.defect = defect;
         sa.nsys = M.tdg.nsys;
         for (int sy = 0; sy < M.tdg.nsys; ++sy) {
             sa.cplx[sy] = M.tdg.cplx[sy];
@@ -474,7 +478,7 @@ template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d)
         sa.Nn = L.Nn;
         sa.Nv1 = L.Nv1;
         sa.Np1 = L.Np1;
-        sa.defect = t;
+        sa.defect = defect;
         sa.patches = M.patches.as<T>();
         sa.piv = M.piv.as<int>();
         sa.E = M.E.as<T>();
@@ -509,7 +513,7 @@ template <typename T> void mg_vcycle(stmg_ctx *ctx, int l, const T *r, T *d)
         return;
     }
     STMG_HIP(vec_fill<T>(L.N, T(0), d, s));
-    for (int i = 0; i < mg.nu1; ++i) mg_smooth<T>(ctx, l, r, d);
+    for (int i = 0; i < mg.nu1; ++i) mg_smooth<T>(ctx, l, r, d, i == 0);
     T *t = M.t.as<T>();
     L.apply<T>(Mode::Jac, state_of<T>(M), d, t, nullptr, nullptr, 1, s);
     STMG_HIP(vec_axpby<T>(L.N, T(1), r, T(-1), t, s));
@@ -520,8 +524,8 @@ template <typename T> void mg_vcycle(stmg_ctx *ctx, int l, const T *r, T *d)
     for (int i = 0; i < mg.nu2; ++i) mg_smooth<T>(ctx, l, r, d);
 }
 
-template void mg_smooth<double>(stmg_ctx *, int, const double *, double *);
-template void mg_smooth<float>(stmg_ctx *, int, const float *, float *);
+template void mg_smooth<double>(stmg_ctx *, int, const double *, double *, bool);
+template void mg_smooth<float>(stmg_ctx *, int, const float *, float *, bool);
 template void mg_vcycle<double>(stmg_ctx *, int, const double *, double *);
 template void mg_vcycle<float>(stmg_ctx *, int, const float *, float *);
 

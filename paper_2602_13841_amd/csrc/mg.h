@@ -93,7 +93,9 @@ struct Krylov {
 void mg_build(stmg_ctx *ctx);
 void mg_set_state(stmg_ctx *ctx, const double *u);
 void mg_rebuild(stmg_ctx *ctx);
-template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d);
+// one Vanka sweep d <- d + omega S(r - J d); d_zero: d is known to be zero
+// (first pre-smoothing step of a cycle), so the defect is r itself
+template <typename T> void mg_smooth(stmg_ctx *ctx, int l, const T *r, T *d, bool d_zero = false);
 template <typename T> void mg_vcycle(stmg_ctx *ctx, int l, const T *r, T *d);
 // z = B v for FP64 vectors on the finest level (casts around the cycle)
 void mg_precondition(stmg_ctx *ctx, const double *v, double *z);
