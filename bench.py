@@ -275,7 +275,7 @@ def main():
                     help="one 1 GiB device-to-device copy first (reference for the rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the slab solver runs on one GPU; multi-GPU sharding is not implemented, --gpus must be 1"}))
         sys.exit(2)
 
     import torch
