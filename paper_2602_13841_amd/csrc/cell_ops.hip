@@ -25,6 +25,7 @@
 #include "stmg_internal.h"
 
 #include <mutex>
+#include <type_traits>
 
 namespace stmg {
 
@@ -1006,11 +1007,13 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
         // ---- boundary faces ----------------------------------------------------------
         {
             {
-                for (int ax = 0; ax < DIM; ++ax) {
-                    for (int side = 0; side < 2; ++side) {
+                // one face; the normal axis is a compile-time constant so that
+                // the strides and index selections of the stages fold
+                auto face_one = [&](auto axc, int side) {
+                        constexpr int ax = decltype(axc)::value;
                         const int cc = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
                         const int nn = ax == 0 ? A.n0 : (ax == 1 ? A.n1 : A.n2);
-                        if (!(side == 0 ? cc == 0 : cc == nn - 1)) continue;
+                        if (!(side == 0 ? cc == 0 : cc == nn - 1)) return;
                         const int fid = 2 * ax + side;
                         const bool isD = (A.dmask >> fid) & 1u;
                         // face record (each field NQF long):
@@ -1019,9 +1022,9 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                         // penalty length: |K|/|F| over the squared velocity degree
                         const T hf = hF[fid] / T((R + 1) * (R + 1));
                         // tangential axes (ta0 < ta1) and strides of the nodal / modal tensors
-                        const int ta0 = DIM == 2 ? 1 - ax : (ax == 0 ? 1 : 0);
-                        const int ta1 = DIM == 2 ? 0 : (ax == 2 ? 1 : 2);
-                        const int sN[3] = {1, N1, N1 * N1}, sP[3] = {1, RP1, RP1 * RP1};
+                        constexpr int ta0 = DIM == 2 ? 1 - ax : (ax == 0 ? 1 : 0);
+                        constexpr int ta1 = DIM == 2 ? 0 : (ax == 2 ? 1 : 2);
+                        constexpr int sN[3] = {1, N1, N1 * N1}, sP[3] = {1, RP1, RP1 * RP1};
                         const T *Srow = Se + side * N1, *Drow = De + side * N1, *Lrow = Lpe + side * RP1;
                         constexpr int LN = DIM == 3 ? N1 * N1 : N1;      // nodes of a layer
                         constexpr int LP = DIM == 3 ? RP1 * RP1 : RP1;   // modes of a layer
@@ -1298,8 +1301,12 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                             }
                         }
                         __syncthreads();
-                    }
-                }
+                };
+                // faces in the fixed order x-, x+, y-, y+, z-, z+
+                for (int side = 0; side < 2; ++side) face_one(std::integral_constant<int, 0>{}, side);
+                for (int side = 0; side < 2; ++side) face_one(std::integral_constant<int, 1>{}, side);
+                if constexpr (DIM == 3)
+                    for (int side = 0; side < 2; ++side) face_one(std::integral_constant<int, 2>{}, side);
             }
         }
 
