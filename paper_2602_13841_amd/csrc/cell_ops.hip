@@ -1007,10 +1007,11 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
         // ---- boundary faces ----------------------------------------------------------
         {
             {
-                // one face; the normal axis is a compile-time constant so that
-                // the strides and index selections of the stages fold
-                auto face_one = [&](auto axc, int side) {
+                // one face; its normal axis and side are compile-time constants
+                // so that the strides and index selections of the stages fold
+                auto face_one = [&](auto axc, auto sidec) {
                         constexpr int ax = decltype(axc)::value;
+                        constexpr int side = decltype(sidec)::value;
                         const int cc = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
                         const int nn = ax == 0 ? A.n0 : (ax == 1 ? A.n1 : A.n2);
                         if (!(side == 0 ? cc == 0 : cc == nn - 1)) return;
@@ -1303,10 +1304,17 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                         __syncthreads();
                 };
                 // faces in the fixed order x-, x+, y-, y+, z-, z+
-                for (int side = 0; side < 2; ++side) face_one(std::integral_constant<int, 0>{}, side);
-                for (int side = 0; side < 2; ++side) face_one(std::integral_constant<int, 1>{}, side);
-                if constexpr (DIM == 3)
-                    for (int side = 0; side < 2; ++side) face_one(std::integral_constant<int, 2>{}, side);
+                using I0 = std::integral_constant<int, 0>;
+                using I1 = std::integral_constant<int, 1>;
+                using I2 = std::integral_constant<int, 2>;
+                face_one(I0{}, I0{});
+                face_one(I0{}, I1{});
+                face_one(I1{}, I0{});
+                face_one(I1{}, I1{});
+                if constexpr (DIM == 3) {
+                    face_one(I2{}, I0{});
+                    face_one(I2{}, I1{});
+                }
             }
         }
 
