@@ -815,7 +815,9 @@ template <int DIM, int R, int NQ, typename T> struct FaceLds {
     static constexpr int NQV = ipow(NQ, DIM);
     static constexpr int NQF = ipow(NQ, DIM - 1);
     static constexpr int NF_F = DIM + DIM * DIM + DIM + 1;    // xhat, grad xhat, v, p
-    static constexpr int Q_SIZE = NF_F * NQF + (DIM + DIM * DIM + 1) * NQF;
+    // the point terms overwrite their inputs with the (fewer) output fields
+    static_assert(DIM + DIM * DIM + 1 <= NF_F, "face outputs fit over the inputs");
+    static constexpr int Q_SIZE = NF_F * NQF;
     // normal-reduced layers and the tangential pencil buffer (also used by the
     // h_F reductions: one word per thread, NQF face points)
     static constexpr int LN = DIM == 3 ? Z::N1 * Z::N1 : Z::N1;
@@ -825,6 +827,11 @@ template <int DIM, int R, int NQ, typename T> struct FaceLds {
     // one word per thread of the (64-thread) volume reduction in TMP1
     static constexpr int TMP1 = L1 > 64 ? L1 : 64;
     static constexpr int TMP2 = L2 > NQF ? L2 : NQF;
+    // 3D: the layer buffer is live only while the face record is dead (the
+    // normal reduction and the first tangential stage; the last tangential
+    // stage and the normal expansion), so it shares its words
+    static constexpr bool T1_IN_Q = DIM == 3;
+    static constexpr int SCR1 = T1_IN_Q ? (Q_SIZE > TMP1 ? Q_SIZE : TMP1) : Q_SIZE + TMP1;
     // face rows of the 1D tables (Se, De, Le) and the Gauss weights/abscissae
     static constexpr int FTAB = (4 * Z::N1 + 2 * Z::RP1 + 2 * NQ + 1) & ~1;
 };
@@ -835,7 +842,7 @@ __host__ __device__ constexpr int face_lds_words(int tabwords)
     using Z = Sizes<DIM, R>;
     using LY = FaceLds<DIM, R, NQ, T>;
     (void)tabwords;
-    return LY::FTAB + 3 * DIM * Z::NL + 2 * Z::NPF + LY::Q_SIZE + LY::TMP1 + LY::TMP2 + 32;
+    return LY::FTAB + 3 * DIM * Z::NL + 2 * Z::NPF + LY::SCR1 + LY::TMP2 + 32;
 }
 
 template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE>
@@ -871,8 +878,8 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
     T *xpf = ys + DIM * NL;                        // [NPF] pressure modes (full tensor)
     T *ypf = xpf + NPF;                            // [NPF] pressure output
     T *Q = ypf + NPF;                              // face record
-    T *t1 = Q + LY::Q_SIZE;
-    T *t2 = t1 + LY::TMP1;
+    T *t1 = LY::T1_IN_Q ? Q : Q + LY::Q_SIZE;
+    T *t2 = Q + LY::SCR1;
     T *geo = t2 + LY::TMP2;                        // [8][3] vertices, [6] h_F, [1] volume
 
     static_assert([] {
@@ -1034,7 +1041,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                         T *abuf = t2;                                    // 3D: [pipe][j1][q0]
                         T *FQ = Q;
                         constexpr int FV = 0, FG = DIM, FS = DIM + DIM * DIM, FP = 2 * DIM + DIM * DIM;
-                        constexpr int FO = 2 * DIM + DIM * DIM + 1;
+                        constexpr int FO = 0;   // outputs over the inputs, point by point
                         // 1. reduce along the normal: value layers of xhat and v, normal-derivative
                         //    layers of xhat, value layer of the pressure modes
                         for (int w = tid; w < 3 * DIM * LN + LP; w += NTH) {
