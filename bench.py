@@ -33,7 +33,7 @@ PEAK_HBM = 8.0e12
 # HBM bytes per launch of the FP64 Jacobian volume kernel on this workload:
 # rocprofv3 --pmc FETCH_SIZE (x2, the factor a 1 GiB device copy shows) plus
 # WRITE_SIZE (x1); profiles/cell_kernel_jac_16cube_r2k2.md
-CELL_KERNEL_TRAFFIC_BYTES = int((2 * 10057.875 + 19392.75) * 1024)
+CELL_KERNEL_TRAFFIC_BYTES = int((2 * 10057.75 + 19392.75) * 1024)
 
 WORKLOAD = dict(dim=3, n=(16, 16, 16), r=2, k=2, nu=1e-2, tau=1.0 / 32)
 
