@@ -157,11 +157,16 @@ typedef struct {
 void stmg_default_options(stmg_options *opt);
 
 /* Device bytes the library allocates for a problem (workspace of all levels,
- * patch factors, Krylov bases). */
+ * patch factors, Krylov bases); 0 for an invalid problem or options (see
+ * stmg_create). */
 size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt);
 
 /* Create a context on the current HIP device.  stream: hipStream_t or NULL.
- * Returns STMG_EINVAL for unsupported (dim, r, k, n_q) combinations. */
+ * Returns STMG_EINVAL, before any device work, for unsupported (dim, r, k,
+ * n_q) combinations and for options outside their documented ranges
+ * (prec_mg other than STMG_F64/STMG_F32, a negative count, a flag other than
+ * 0/1, vanka_diagonal other than 0/1/2); with the environment variable
+ * STMG_VERBOSE set the reason is printed on stderr. */
 int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_ctx **out);
 int stmg_destroy(stmg_ctx *ctx);
 const char *stmg_last_error(const stmg_ctx *ctx);

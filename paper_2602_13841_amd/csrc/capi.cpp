@@ -40,6 +40,31 @@ bool check_problem(const stmg_problem *p, std::string &why)
     return true;
 }
 
+// enumerated and counted options outside their documented ranges are
+// rejected rather than read as the nearest meaning
+bool check_options(const stmg_options *o, std::string &why)
+{
+    if (!o) return true;
+    auto flag = [](int v) { return v == 0 || v == 1; };
+    if (o->prec_mg != STMG_F64 && o->prec_mg != STMG_F32) { why = "prec_mg must be STMG_F64 or STMG_F32"; return false; }
+    if (o->n_q < 0 || o->max_levels < 0 || o->nu1 < 0 || o->nu2 < 0) {
+        why = "n_q, max_levels, nu1 and nu2 must be >= 0";
+        return false;
+    }
+    if (o->newton_maxit < 1 || o->fgmres_maxit < 1) { why = "newton_maxit and fgmres_maxit must be >= 1"; return false; }
+    if (!(o->vanka_omega >= 0) || !(o->newton_rtol >= 0) || !(o->newton_atol >= 0)) {
+        why = "vanka_omega, newton_rtol and newton_atol must be >= 0";
+        return false;
+    }
+    if (!flag(o->vanka_weighting) || !flag(o->vanka_time_decoupled) || !flag(o->use_graphs) ||
+        !flag(o->time_coarsening) || !flag(o->vanka_factor_bf16)) {
+        why = "vanka_weighting, vanka_time_decoupled, use_graphs, time_coarsening and vanka_factor_bf16 must be 0 or 1";
+        return false;
+    }
+    if (o->vanka_diagonal < 0 || o->vanka_diagonal > 2) { why = "vanka_diagonal must be 0, 1 or 2"; return false; }
+    return true;
+}
+
 // batched LU (solve == false) or batched substitution (solve == true) of
 // matrices of mixed sizes; host metadata sorted by decreasing size
 int batched_lu_impl(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
@@ -166,7 +191,14 @@ int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream,
     if (!out) return STMG_EINVAL;
     *out = nullptr;
     std::string why;
-    if (!check_problem(prob, why)) return STMG_EINVAL;
+    if (!check_problem(prob, why) || !check_options(opt, why)) {
+        const char *ev = std::getenv("STMG_VERBOSE");
+        if (ev && *ev && *ev != '0') {
+            std::fprintf(stderr, "[stmg] create rejected: %s\n", why.c_str());
+            std::fflush(stderr);
+        }
+        return STMG_EINVAL;
+    }
     stmg_ctx *ctx = new stmg_ctx();
     ctx->prob = *prob;
     ctx->prob.vertices = nullptr;
@@ -218,7 +250,7 @@ const char *stmg_last_error(const stmg_ctx *ctx) { return ctx ? ctx->err.c_str()
 size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt)
 {
     std::string why;
-    if (!check_problem(prob, why)) return 0;
+    if (!check_problem(prob, why) || !check_options(opt, why)) return 0;
     stmg_options o;
     if (opt) o = *opt;
     else stmg_default_options(&o);

@@ -61,3 +61,16 @@ def test_batched_lu_rejects_bad_arguments_before_any_device_work():
         assert rc == stmg.STMG_EINVAL
     rc = L.stmg_batched_lu(stmg.STMG_F32, None, off.ctypes.data, off.ctypes.data, 1, None, off.ctypes.data, None, None)
     assert rc == stmg.STMG_EINVAL
+
+
+@pytest.mark.parametrize("bad", [dict(prec_mg=stmg.STMG_F32_BF16), dict(prec_mg=7), dict(vanka_diagonal=3),
+                                 dict(vanka_factor_bf16=2), dict(time_coarsening=-1), dict(use_graphs=2),
+                                 dict(nu1=-1), dict(newton_maxit=0), dict(fgmres_maxit=0), dict(vanka_omega=-1.0)])
+def test_options_outside_their_ranges_are_rejected_before_any_device_work(bad):
+    p, _ = stmg.make_problem(3, (4, 4, 4), 2, 1, 1e-2, 0.1)
+    assert stmg.footprint_bytes(p, stmg.default_options()) > 0
+    o = stmg.default_options(**bad)
+    assert stmg.footprint_bytes(p, o) == 0
+    h = ctypes.c_void_p()
+    assert stmg.lib().stmg_create(ctypes.byref(p), ctypes.byref(o), None, ctypes.byref(h)) == stmg.STMG_EINVAL
+    assert not h.value
