@@ -297,10 +297,10 @@ size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt)
         if (l + 1 < specs.size()) {
             total += (size_t)Nv1 * w + (size_t)ncell * (d * d * nl * nl + nl * nl + d * nl * npm) * w;
             if (o.vanka_time_decoupled) {
-                const long long ms = d * nl + npm;                          // nt real-plane equivalents
-                total += (size_t)ncell * nt * ms * ms * w + (size_t)ncell * nt * ms * 8;
+                const long long ms = d * nl + npm, ld = td_ld((int)ms);     // nt real-plane equivalents
+                total += (size_t)ncell * nt * ms * ld * w + (size_t)ncell * nt * ms * 8;
                 if (o.vanka_factor_bf16 && o.prec_mg == STMG_F32)
-                    total += (size_t)ncell * nt * ms * ms * 2;              // BF16 copy of the factors
+                    total += (size_t)ncell * nt * ms * ld * 2;              // BF16 copy of the factors
             } else {
                 total += (size_t)ncell * m * m * w + (size_t)ncell * m * 4;   // patch factors
             }

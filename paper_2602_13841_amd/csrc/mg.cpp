@@ -240,7 +240,7 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
     if (ctx->mg->td) {
         // one spatial matrix per eigen-system of the time coupling
         M.tdg = time_diagonalization(L.tc);
-        const long long ms = M.ms, mat = ms * ms;
+        const long long ms = M.ms, ld = td_ld(M.ms), mat = ms * ld;   // rows padded to 32 elements
         long long off = 0;
         for (int sy = 0; sy < M.tdg.nsys; ++sy) {
             M.sys_off[sy] = off;
@@ -303,9 +303,13 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
                 T *A = M.patches.as<T>() + M.sys_off[sy];
                 int *pv = M.piv.as<int>() + M.piv_off[sy];
                 if (M.tdg.cplx[sy])
-                    STMG_HIP(launch_lu_c<T>(A, pv, M.ms, 2 * mat, (int)L.ncell, M.info.as<int>(), max_lds, s));
-                else
-                    STMG_HIP(launch_lu<T>(A, pv, M.ms, (int)L.ncell, M.info.as<int>(), max_lds, s));
+                    STMG_HIP(launch_lu_c<T>(A, pv, M.ms, (int)ld, 2 * mat, (int)L.ncell, M.info.as<int>(), max_lds, s));
+                else {
+                    LuBatch vb{};
+                    vb.uniform_m = M.ms;
+                    vb.uniform_ld = (int)ld;
+                    STMG_HIP(launch_lu<T>(A, pv, M.ms, (int)L.ncell, M.info.as<int>(), max_lds, s, &vb));
+                }
             }
             STMG_HIP(launch_piv_to_perm(M.piv.as<int>(), M.perm.as<int>(), M.ms, (long long)M.tdg.nsys * L.ncell, s));
             if constexpr (std::is_same<T, float>::value) {

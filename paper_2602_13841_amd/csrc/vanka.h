@@ -44,7 +44,8 @@ template <typename T, typename TP> struct SolveArgs {
 };
 
 // time-decoupled patches (one spatial matrix per eigen-system of the time
-// coupling; complex systems planar: real plane then imaginary plane)
+// coupling, ms rows of stride td_ld(ms); complex systems planar: real plane
+// then imaginary plane)
 template <typename TE, typename TP> struct PatchTdArgs {
     int n0, n1, n2;
     const TE *elem;
@@ -75,11 +76,18 @@ template <typename T, typename TP, typename TF = TP> struct SolveTdArgs {
 
 // a batch of LU factorizations: uniform size m, or per-matrix sizes and
 // offsets (elements of A, entries of the pivot array)
+// row stride of the time-decoupled patch systems (elements): every row starts
+// on a 32-element boundary (128 bytes in FP32, 64 in the BF16 copy), so the
+// 32-column blocks the substitutions read cover whole memory sectors instead
+// of sharing their edge sectors with the neighbouring block
+constexpr int td_ld(int ms) { return (ms + 31) & ~31; }
+
 struct LuBatch {
     int uniform_m;
     const int *m_of;
     const long long *a_off;
     const long long *p_off;
+    int uniform_ld;   // row stride of every matrix (0: its size m)
 };
 
 int elem_record_words(int dim, int r);
@@ -98,7 +106,8 @@ template <typename TE, typename TP>
 hipError_t launch_patch_td(int dim, int r, const PatchTdArgs<TE, TP> &a, int ncell, hipStream_t s);
 // batched complex LU: matrix b at A + b * a_stride (real plane, imaginary plane)
 template <typename T>
-hipError_t launch_lu_c(T *A, int *piv, int m, long long a_stride, int batch, int *info, size_t max_lds, hipStream_t s);
+hipError_t launch_lu_c(T *A, int *piv, int m, int ld, long long a_stride, int batch, int *info, size_t max_lds,
+                       hipStream_t s);
 hipError_t launch_piv_to_perm(const int *piv, int *perm, int m, long long nmat, hipStream_t s);
 size_t solve_td_lds_bytes(int ms, int nt, size_t word);
 template <typename T, typename TP>
@@ -114,7 +123,7 @@ hipError_t launch_pack_bf16(const float *src, unsigned short *dst, long long n, 
 // by its diagonal D (or its node blocks: all velocity components of one
 // node), so the system is solved by the pressure Schur complement
 // S = C - B D^{-1} B^T (npm x npm).  sys: the unfactored systems (ms x ms
-// row-major, planar complex); dinv: [cell][2][nv] D^{-1} (re, im); schur:
+// row-major with row stride td_ld(ms), planar complex); dinv: [cell][2][nv] D^{-1} (re, im); schur:
 // [cell][2][npm npm] LU of S; spiv: [cell][npm] its row interchanges.
 template <typename T> struct DvArgs {
     int n0, n1, n2;

@@ -896,7 +896,7 @@ constexpr int LU_SWC = 64;       // column chunk of the row interchanges
 // k 4(l/16)+j), B lane l -> (k 4(l/16)+j, col l%16), j < 4; D as above);
 // A22 stays FP32
 template <int NBP, int OP>
-__device__ __forceinline__ void trailing_update(float *A, int m, int j0, int nb, int cb, int ncb, const float *pan,
+__device__ __forceinline__ void trailing_update(float *A, int m, int ld, int j0, int nb, int cb, int ncb, const float *pan,
                                                 const float *ut)
 {
     constexpr int NB = NBP - 1;
@@ -914,7 +914,7 @@ __device__ __forceinline__ void trailing_update(float *A, int m, int j0, int nb,
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
-                    c[si][sj][i] = (row < m && col < cb + ncb) ? A[(long long)row * m + col] : 0.0f;
+                    c[si][sj][i] = (row < m && col < cb + ncb) ? A[(long long)row * ld + col] : 0.0f;
                 }
     };
     floatx4_t acc[2][2], nxt[2][2];
@@ -981,7 +981,7 @@ __device__ __forceinline__ void trailing_update(float *A, int m, int j0, int nb,
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
-                    if (row < m && col < cb + ncb) A[(long long)row * m + col] = acc[si][sj][i];
+                    if (row < m && col < cb + ncb) A[(long long)row * ld + col] = acc[si][sj][i];
                 }
         if (tn < ntile) {
 #pragma unroll
@@ -994,7 +994,7 @@ __device__ __forceinline__ void trailing_update(float *A, int m, int j0, int nb,
 
 // FP64: register tiles of 4 x 4 per thread on the vector ALUs
 template <int NBP, int OP>
-__device__ __forceinline__ void trailing_update(double *A, int m, int j0, int nb, int cb, int ncb, const double *pan,
+__device__ __forceinline__ void trailing_update(double *A, int m, int ld, int j0, int nb, int cb, int ncb, const double *pan,
                                                 const double *ut)
 {
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
@@ -1005,7 +1005,7 @@ __device__ __forceinline__ void trailing_update(double *A, int m, int j0, int nb
             for (int i = 0; i < 4; ++i)
                 for (int j = 0; j < 4; ++j) {
                     int row = R + ty + 16 * i, col = C + tx + 16 * j;
-                    acc[i][j] = (row < m && col < cb + ncb) ? A[(long long)row * m + col] : 0.0;
+                    acc[i][j] = (row < m && col < cb + ncb) ? A[(long long)row * ld + col] : 0.0;
                 }
             for (int k = 0; k < nb; ++k) {
                 double a[4], b[4];
@@ -1020,7 +1020,7 @@ __device__ __forceinline__ void trailing_update(double *A, int m, int j0, int nb
             for (int i = 0; i < 4; ++i)
                 for (int j = 0; j < 4; ++j) {
                     int row = R + ty + 16 * i, col = C + tx + 16 * j;
-                    if (row < m && col < cb + ncb) A[(long long)row * m + col] = acc[i][j];
+                    if (row < m && col < cb + ncb) A[(long long)row * ld + col] = acc[i][j];
                 }
         }
     }
@@ -1076,7 +1076,8 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
     extern __shared__ unsigned char lds_raw[];
     const int bid = blockIdx.x;
     const int m = B.m_of ? B.m_of[bid] : B.uniform_m;
-    T *A = Aall + (B.a_off ? B.a_off[bid] : (long long)bid * m * m);
+    const int ld = B.uniform_ld > 0 ? B.uniform_ld : m;   // row stride
+    T *A = Aall + (B.a_off ? B.a_off[bid] : (long long)bid * m * ld);
     int *piv = pivall + (B.p_off ? B.p_off[bid] : (long long)bid * m);
     T *pan = reinterpret_cast<T *>(lds_raw);          // [m][NBP] panel rows
     T *ut = pan + (size_t)m * NBP;                     // [NB][LU_CB] U12 block
@@ -1091,7 +1092,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
         const int nb = min(NB, m - j0), mr = m - j0;
         for (int e = tid; e < mr * nb; e += LU_THREADS) {
             int r = e / nb, c = e % nb;
-            pan[r * NBP + c] = A[(long long)(j0 + r) * m + j0 + c];
+            pan[r * NBP + c] = A[(long long)(j0 + r) * ld + j0 + c];
         }
         __syncthreads();
         for (int c = 0; c < nb; ++c) {
@@ -1142,12 +1143,12 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
                 const int nc = min(LU_SWC, m - c0);
                 for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
                     int i = e / LU_SWC, j = e % LU_SWC;
-                    if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * m + c0 + j];
+                    if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * ld + c0 + j];
                 }
                 __syncthreads();
                 for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
                     int i = e / LU_SWC, j = e % LU_SWC;
-                    if (j < nc) A[(long long)(j0 + aff_dst[i]) * m + c0 + j] = stg[i * LU_SWC + j];
+                    if (j < nc) A[(long long)(j0 + aff_dst[i]) * ld + c0 + j] = stg[i * LU_SWC + j];
                 }
                 __syncthreads();
             }
@@ -1155,7 +1156,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
         // write the factored panel back
         for (int e = tid; e < mr * nb; e += LU_THREADS) {
             int r = e / nb, c = e % nb;
-            A[(long long)(j0 + r) * m + j0 + c] = pan[r * NBP + c];
+            A[(long long)(j0 + r) * ld + j0 + c] = pan[r * NBP + c];
         }
         __syncthreads();
         // U12 = L11^{-1} A12 and the trailing update, one column block at a time
@@ -1166,7 +1167,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
             if (tid < ncb) {
                 const int col = cb + tid;
                 T u[NB];
-                for (int c = 0; c < NB; ++c) u[c] = c < nb ? A[(long long)(j0 + c) * m + col] : T(0);
+                for (int c = 0; c < NB; ++c) u[c] = c < nb ? A[(long long)(j0 + c) * ld + col] : T(0);
                 // fully unrolled (register array); rows c >= nb stay zero
 #pragma unroll
                 for (int c = 1; c < NB; ++c) {
@@ -1177,12 +1178,12 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
                 }
                 for (int c = 0; c < NB; ++c)
                     if (c < nb) {
-                        A[(long long)(j0 + c) * m + col] = u[c];
+                        A[(long long)(j0 + c) * ld + col] = u[c];
                         ut[c * LU_CB + tid] = u[c];
                     }
             }
             __syncthreads();
-            trailing_update<NBP, OP>(A, m, j0, nb, cb, ncb, pan, ut);
+            trailing_update<NBP, OP>(A, m, ld, j0, nb, cb, ncb, pan, ut);
             __syncthreads();
         }
     }
@@ -1194,13 +1195,13 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
 constexpr int SV_THREADS = 256;
 
 // b[r] -= L[r, kb:kb+nbk] . b[kb:kb+nbk] for rows r in [rbeg, rend) of a
-// row-major m x m factor (complex planar when CX: Lr/Li and br/bi), nbk <= KB.
+// row-major factor with row stride ld (complex planar when CX: Lr/Li and br/bi), nbk <= KB.
 // One 16-lane group per row, KB/16 columns per lane; each group keeps RU rows of
 // loads in flight before it reduces, so a pass over the rows costs about one
 // memory latency instead of one per row.  Per row the summation order is
 // fixed: columns l16, l16+16, ..., then a 16-lane xor tree.
 template <typename T, bool CX, int KB = 64, int RU = 4, typename TF = T>
-__device__ __forceinline__ void block_gemv_update(const TF *__restrict__ Lr, const TF *__restrict__ Li, int m, int kb,
+__device__ __forceinline__ void block_gemv_update(const TF *__restrict__ Lr, const TF *__restrict__ Li, int ld, int kb,
                                                   int nbk, int rbeg, int rend, T *br, T *bi)
 {
     constexpr int NG = SV_THREADS / 16, CPL = KB / 16;   // columns per lane
@@ -1221,7 +1222,7 @@ __device__ __forceinline__ void block_gemv_update(const TF *__restrict__ Lr, con
             // unconditional loads from a clamped in-range address, then a
             // select: every load of the pass is issued before the first wait
             const int r = r0 + u * NG;
-            const long long o = (long long)min(r, rend - 1) * m + kb;
+            const long long o = (long long)min(r, rend - 1) * ld + kb;
 #pragma unroll
             for (int i = 0; i < CPL; ++i) {
                 const int c = l16 + 16 * i;
@@ -1263,7 +1264,7 @@ __device__ __forceinline__ void block_gemv_update(const TF *__restrict__ Lr, con
 }
 
 template <typename T, int KB = 64, typename TF = T>
-__device__ __forceinline__ void lu_substitute(const TF *__restrict__ LU, int m, T *b, T *dblk)
+__device__ __forceinline__ void lu_substitute(const TF *__restrict__ LU, int m, int ld, T *b, T *dblk)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int g = tid >> 4, l16 = tid & 15;
@@ -1272,7 +1273,7 @@ __device__ __forceinline__ void lu_substitute(const TF *__restrict__ LU, int m, 
         const int nbk = min(KB, m - kb);
         for (int e = tid; e < nbk * KB; e += SV_THREADS) {
             int i = e / KB, j = e % KB;
-            if (j < nbk) dblk[i * (KB + 1) + j] = ld_factor<T>(LU + (long long)(kb + i) * m + kb + j);
+            if (j < nbk) dblk[i * (KB + 1) + j] = ld_factor<T>(LU + (long long)(kb + i) * ld + kb + j);
         }
         __syncthreads();
         if (wv == 0) {
@@ -1284,7 +1285,7 @@ __device__ __forceinline__ void lu_substitute(const TF *__restrict__ LU, int m, 
             if (lane < nbk) b[kb + lane] = y;
         }
         __syncthreads();
-        block_gemv_update<T, false, KB, 4, TF>(LU, (const TF *)nullptr, m, kb, nbk, kb + nbk, m, b, nullptr);
+        block_gemv_update<T, false, KB, 4, TF>(LU, (const TF *)nullptr, ld, kb, nbk, kb + nbk, m, b, nullptr);
         __syncthreads();
     }
     // backward: upper with diagonal
@@ -1293,7 +1294,7 @@ __device__ __forceinline__ void lu_substitute(const TF *__restrict__ LU, int m, 
         const int kb = bk * KB, nbk = min(KB, m - kb);
         for (int e = tid; e < nbk * KB; e += SV_THREADS) {
             int i = e / KB, j = e % KB;
-            if (j < nbk) dblk[i * (KB + 1) + j] = ld_factor<T>(LU + (long long)(kb + i) * m + kb + j);
+            if (j < nbk) dblk[i * (KB + 1) + j] = ld_factor<T>(LU + (long long)(kb + i) * ld + kb + j);
         }
         __syncthreads();
         if (wv == 0) {
@@ -1306,7 +1307,7 @@ __device__ __forceinline__ void lu_substitute(const TF *__restrict__ LU, int m, 
             if (lane < nbk) b[kb + lane] = x;
         }
         __syncthreads();
-        block_gemv_update<T, false, KB, 4, TF>(LU, (const TF *)nullptr, m, kb, nbk, 0, kb, b, nullptr);
+        block_gemv_update<T, false, KB, 4, TF>(LU, (const TF *)nullptr, ld, kb, nbk, 0, kb, b, nullptr);
         __syncthreads();
     }
 }
@@ -1351,7 +1352,7 @@ __global__ void __launch_bounds__(SV_THREADS) solve_kernel(SolveArgs<T, TP> A)
             }
         }
     __syncthreads();
-    lu_substitute<TP>(A.patches + (long long)cell * m * m, m, b, dblk);
+    lu_substitute<TP>(A.patches + (long long)cell * m * m, m, m, b, dblk);
     // velocity -> cell-local buffer [cell][a][c][l]; pressure += omega * x
     T *Ec = A.E + (long long)cell * nv;
     for (int row = tid; row < m; row += SV_THREADS) {
@@ -1378,7 +1379,8 @@ __global__ void __launch_bounds__(256) patch_td_kernel(PatchTdArgs<TE, TP> A)
     using Z = VS<DIM, R>;
     constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
     constexpr int NV = DIM * NL, MS = NV + NPM;
-    constexpr long long MAT = (long long)MS * MS;
+    constexpr int LDM = td_ld(MS);
+    constexpr long long MAT = (long long)MS * LDM;
     const int cell = xcd_cell(blockIdx.x, gridDim.x);
     const int cc[3] = {cell % A.n0, (cell / A.n0) % A.n1, DIM == 3 ? cell / (A.n0 * A.n1) : 0};
     const int nn[3] = {A.n0, A.n1, A.n2};
@@ -1423,9 +1425,9 @@ __global__ void __launch_bounds__(256) patch_td_kernel(PatchTdArgs<TE, TP> A)
             lv = (double)own[(long long)col * NPM + (row - NV)];
         }
         for (int s = 0; s < A.nsys; ++s) {
-            TP *o = A.sys[s] + (long long)cell * (A.cplx[s] ? 2 : 1) * MAT;
-            o[e] = (TP)(A.lre[s] * mv + lv);
-            if (A.cplx[s]) o[MAT + e] = (TP)(A.lim[s] * mv);
+            TP *o = A.sys[s] + (long long)cell * (A.cplx[s] ? 2 : 1) * MAT + (long long)row * LDM + col;
+            o[0] = (TP)(A.lre[s] * mv + lv);
+            if (A.cplx[s]) o[MAT] = (TP)(A.lim[s] * mv);
         }
     }
 }
@@ -1433,7 +1435,7 @@ __global__ void __launch_bounds__(256) patch_td_kernel(PatchTdArgs<TE, TP> A)
 // complex trailing update C -= L21 U12 of one column block (planar), FP32 on
 // MFMA: four real products per k step
 template <int NBP>
-__device__ __forceinline__ void trailing_update_c(float *Ar, float *Ai, int m, int j0, int nb, int cb, int ncb,
+__device__ __forceinline__ void trailing_update_c(float *Ar, float *Ai, int m, int ld, int j0, int nb, int cb, int ncb,
                                                   const float *pr, const float *pi, const float *ur, const float *ui)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1451,8 +1453,8 @@ __device__ __forceinline__ void trailing_update_c(float *Ar, float *Ai, int m, i
                 for (int i = 0; i < 4; ++i) {
                     const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
                     const bool ok = row < m && col < cb + ncb;
-                    xr[si][sj][i] = ok ? Ar[(long long)row * m + col] : 0.0f;
-                    xi[si][sj][i] = ok ? Ai[(long long)row * m + col] : 0.0f;
+                    xr[si][sj][i] = ok ? Ar[(long long)row * ld + col] : 0.0f;
+                    xi[si][sj][i] = ok ? Ai[(long long)row * ld + col] : 0.0f;
                 }
     };
     floatx4_t cr[2][2], ci[2][2], nr[2][2], ni[2][2];
@@ -1495,8 +1497,8 @@ __device__ __forceinline__ void trailing_update_c(float *Ar, float *Ai, int m, i
                 for (int i = 0; i < 4; ++i) {
                     const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
                     if (row < m && col < cb + ncb) {
-                        Ar[(long long)row * m + col] = cr[si][sj][i];
-                        Ai[(long long)row * m + col] = ci[si][sj][i];
+                        Ar[(long long)row * ld + col] = cr[si][sj][i];
+                        Ai[(long long)row * ld + col] = ci[si][sj][i];
                     }
                 }
         if (tn < ntile) {
@@ -1513,7 +1515,7 @@ __device__ __forceinline__ void trailing_update_c(float *Ar, float *Ai, int m, i
 
 // FP64: complex register tiles of 4 x 4 per thread on the vector ALUs
 template <int NBP>
-__device__ __forceinline__ void trailing_update_c(double *Ar, double *Ai, int m, int j0, int nb, int cb, int ncb,
+__device__ __forceinline__ void trailing_update_c(double *Ar, double *Ai, int m, int ld, int j0, int nb, int cb, int ncb,
                                                   const double *pr, const double *pi, const double *ur,
                                                   const double *ui)
 {
@@ -1526,8 +1528,8 @@ __device__ __forceinline__ void trailing_update_c(double *Ar, double *Ai, int m,
                 for (int j = 0; j < 4; ++j) {
                     const int row = R + ty + 16 * i, col = C + tx + 16 * j;
                     const bool ok = row < m && col < cb + ncb;
-                    cr[i][j] = ok ? Ar[(long long)row * m + col] : 0.0;
-                    ci[i][j] = ok ? Ai[(long long)row * m + col] : 0.0;
+                    cr[i][j] = ok ? Ar[(long long)row * ld + col] : 0.0;
+                    ci[i][j] = ok ? Ai[(long long)row * ld + col] : 0.0;
                 }
             for (int k = 0; k < nb; ++k) {
                 double ar[4], ai[4], br[4], bi[4];
@@ -1550,8 +1552,8 @@ __device__ __forceinline__ void trailing_update_c(double *Ar, double *Ai, int m,
                 for (int j = 0; j < 4; ++j) {
                     const int row = R + ty + 16 * i, col = C + tx + 16 * j;
                     if (row < m && col < cb + ncb) {
-                        Ar[(long long)row * m + col] = cr[i][j];
-                        Ai[(long long)row * m + col] = ci[i][j];
+                        Ar[(long long)row * ld + col] = cr[i][j];
+                        Ai[(long long)row * ld + col] = ci[i][j];
                     }
                 }
         }
@@ -1564,13 +1566,13 @@ __device__ __forceinline__ void trailing_update_c(double *Ar, double *Ai, int m,
 // kernel
 template <typename T, int NB>
 __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, int *__restrict__ pivall, int m,
-                                                          long long a_stride, int *info)
+                                                          int ld, long long a_stride, int *info)
 {
     constexpr int NBP = NB + 1;
     extern __shared__ unsigned char lds_raw[];
     const int bid = blockIdx.x;
     T *Ar = Aall + (long long)bid * a_stride;
-    T *Ai = Ar + (long long)m * m;
+    T *Ai = Ar + (long long)m * ld;
     int *piv = pivall + (long long)bid * m;
     T *pr = reinterpret_cast<T *>(lds_raw);           // [m][NBP] panel, real
     T *pi = pr + (size_t)m * NBP;                      // [m][NBP] panel, imaginary
@@ -1587,7 +1589,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, 
         const int nb = min(NB, m - j0), mr = m - j0;
         for (int e = tid; e < mr * nb; e += LU_THREADS) {
             const int r = e / nb, c = e % nb;
-            const long long g = (long long)(j0 + r) * m + j0 + c;
+            const long long g = (long long)(j0 + r) * ld + j0 + c;
             pr[r * NBP + c] = Ar[g];
             pi[r * NBP + c] = Ai[g];
         }
@@ -1651,12 +1653,12 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, 
                     const int nc = min(LU_SWC, m - c0);
                     for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
                         const int i = e / LU_SWC, j = e % LU_SWC;
-                        if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * m + c0 + j];
+                        if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * ld + c0 + j];
                     }
                     __syncthreads();
                     for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
                         const int i = e / LU_SWC, j = e % LU_SWC;
-                        if (j < nc) A[(long long)(j0 + aff_dst[i]) * m + c0 + j] = stg[i * LU_SWC + j];
+                        if (j < nc) A[(long long)(j0 + aff_dst[i]) * ld + c0 + j] = stg[i * LU_SWC + j];
                     }
                     __syncthreads();
                 }
@@ -1664,7 +1666,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, 
         }
         for (int e = tid; e < mr * nb; e += LU_THREADS) {
             const int r = e / nb, c = e % nb;
-            const long long g = (long long)(j0 + r) * m + j0 + c;
+            const long long g = (long long)(j0 + r) * ld + j0 + c;
             Ar[g] = pr[r * NBP + c];
             Ai[g] = pi[r * NBP + c];
         }
@@ -1680,8 +1682,8 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, 
             T vr[NB], vi[NB];
             for (int c = 0; c < NB; ++c) {
                 const bool ok = c < nb;
-                vr[c] = ok ? Ar[(long long)(j0 + c) * m + col] : T(0);
-                vi[c] = ok ? Ai[(long long)(j0 + c) * m + col] : T(0);
+                vr[c] = ok ? Ar[(long long)(j0 + c) * ld + col] : T(0);
+                vi[c] = ok ? Ai[(long long)(j0 + c) * ld + col] : T(0);
             }
             // fully unrolled (register arrays); rows c >= nb stay zero
 #pragma unroll
@@ -1700,8 +1702,8 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, 
             }
             for (int c = 0; c < NB; ++c)
                 if (c < nb) {
-                    Ar[(long long)(j0 + c) * m + col] = vr[c];
-                    Ai[(long long)(j0 + c) * m + col] = vi[c];
+                    Ar[(long long)(j0 + c) * ld + col] = vr[c];
+                    Ai[(long long)(j0 + c) * ld + col] = vi[c];
                 }
         }
         __syncthreads();
@@ -1710,13 +1712,13 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, 
             for (int e = tid; e < NB * LU_CB; e += LU_THREADS) {
                 const int c = e / LU_CB, j = e % LU_CB;
                 const bool ok = c < nb && j < ncb;
-                const long long g = (long long)(j0 + min(c, nb - 1)) * m + cb + min(j, ncb - 1);
+                const long long g = (long long)(j0 + min(c, nb - 1)) * ld + cb + min(j, ncb - 1);
                 const T a = Ar[g], b = Ai[g];
                 ur[e] = ok ? a : T(0);
                 ui[e] = ok ? b : T(0);
             }
             __syncthreads();
-            trailing_update_c<NBP>(Ar, Ai, m, j0, nb, cb, ncb, pr, pi, ur, ui);
+            trailing_update_c<NBP>(Ar, Ai, m, ld, j0, nb, cb, ncb, pr, pi, ur, ui);
             __syncthreads();
         }
     }
@@ -1750,7 +1752,7 @@ __global__ void piv_to_perm_kernel(const int *__restrict__ piv, int *__restrict_
 // the second LDS block (dr[2 KB(KB+1)] and di likewise must then hold two
 // blocks): the factors are read-only, so its load never waits for the solve.
 template <typename T, int KB = 64, int SB = 1, typename TF = T, bool PF = false>
-__device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const TF *__restrict__ Li, int m, T *br, T *bi,
+__device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const TF *__restrict__ Li, int m, int ld, T *br, T *bi,
                                                 T *dr, T *di)
 {
     constexpr int SW = SB * KB, RUS = SB == 1 ? 4 : (SB == 2 ? 2 : 1);
@@ -1762,7 +1764,7 @@ __device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const
 #pragma unroll
         for (int q = 0; q < DPT; ++q) {
             const int e = tid + q * SV_THREADS, i = min(e / KB, nbk - 1), j = min(e % KB, nbk - 1);
-            const long long o = (long long)(kb + i) * m + kb + j;
+            const long long o = (long long)(kb + i) * ld + kb + j;
             pr[q] = ld_factor<T>(Lr + o);
             pi[q] = ld_factor<T>(Li + o);
         }
@@ -1781,8 +1783,8 @@ __device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const
         for (int e = tid; e < nbk * KB; e += SV_THREADS) {
             const int i = e / KB, j = e % KB;
             if (j < nbk) {
-                dr[i * (KB + 1) + j] = ld_factor<T>(Lr + (long long)(kb + i) * m + kb + j);
-                di[i * (KB + 1) + j] = ld_factor<T>(Li + (long long)(kb + i) * m + kb + j);
+                dr[i * (KB + 1) + j] = ld_factor<T>(Lr + (long long)(kb + i) * ld + kb + j);
+                di[i * (KB + 1) + j] = ld_factor<T>(Li + (long long)(kb + i) * ld + kb + j);
             }
         }
     };
@@ -1820,7 +1822,7 @@ __device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const
             }
             __syncthreads();
             if (kb + nbk < se) {
-                block_gemv_update<T, true, KB, 4, TF>(Lr, Li, m, kb, nbk, kb + nbk, se, br, bi);
+                block_gemv_update<T, true, KB, 4, TF>(Lr, Li, ld, kb, nbk, kb + nbk, se, br, bi);
             }
             if constexpr (PF) {
                 if (kn < m) diag_store(cur ^ 1, min(KB, m - kn));
@@ -1828,7 +1830,7 @@ __device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const
             }
             __syncthreads();
         }
-        block_gemv_update<T, true, SW, RUS, TF>(Lr, Li, m, sb, se - sb, se, m, br, bi);
+        block_gemv_update<T, true, SW, RUS, TF>(Lr, Li, ld, sb, se - sb, se, m, br, bi);
         __syncthreads();
     }
     // backward: upper with diagonal
@@ -1875,7 +1877,7 @@ __device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const
             }
             __syncthreads();
             if (kb > sb) {
-                block_gemv_update<T, true, KB, 4, TF>(Lr, Li, m, kb, nbk, sb, kb, br, bi);
+                block_gemv_update<T, true, KB, 4, TF>(Lr, Li, ld, kb, nbk, sb, kb, br, bi);
             }
             if constexpr (PF) {
                 if (kn >= 0) diag_store(cur ^ 1, KB);
@@ -1883,7 +1885,7 @@ __device__ __forceinline__ void lu_substitute_c(const TF *__restrict__ Lr, const
             }
             __syncthreads();
         }
-        block_gemv_update<T, true, SW, RUS, TF>(Lr, Li, m, sb, se - sb, 0, sb, br, bi);
+        block_gemv_update<T, true, SW, RUS, TF>(Lr, Li, ld, sb, se - sb, 0, sb, br, bi);
         __syncthreads();
     }
 }
@@ -1898,7 +1900,8 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP,
     using Z = VS<DIM, R>;
     constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
     constexpr int NV = DIM * NL, MS = NV + NPM, MSP = (MS + 1) & ~1;
-    constexpr long long MAT = (long long)MS * MS;
+    constexpr int LDM = td_ld(MS);
+    constexpr long long MAT = (long long)MS * LDM;
     extern __shared__ unsigned char lds_raw[];
     const int nt = A.nt;
     TP *rl = reinterpret_cast<TP *>(lds_raw);   // [nt][MS] patch defect
@@ -1950,8 +1953,8 @@ __global__ void __launch_bounds__(SV_THREADS) solve_td_kernel(SolveTdArgs<T, TP,
         }
         __syncthreads();
         const TF *LU = A.sys[s] + (long long)cell * (cx ? 2 : 1) * MAT;
-        if (cx) lu_substitute_c<TP, KBT, 2, TF, PFD>(LU, LU + MAT, MS, br, bi, dr, di);
-        else lu_substitute<TP, KBT, TF>(LU, MS, br, dr);
+        if (cx) lu_substitute_c<TP, KBT, 2, TF, PFD>(LU, LU + MAT, MS, LDM, br, bi, dr, di);
+        else lu_substitute<TP, KBT, TF>(LU, MS, LDM, br, dr);
         for (int e = tid; e < nt * MS; e += SV_THREADS) {
             const int a = e / MS, j = e - (e / MS) * MS;
             TP v = A.Fre[a * 4 + s] * br[j];
@@ -2063,7 +2066,8 @@ __global__ void __launch_bounds__(SV_THREADS) dv_setup_kernel(DvArgs<T> A)
     using Z = VS<DIM, R>;
     constexpr int NL = Z::NL, NV = DIM * NL, NPM = Z::NPM, MS = NV + NPM;
     constexpr int ND = BLK ? NL * DIM * DIM : NV;   // stored D^{-1} entries per plane
-    constexpr long long MAT = (long long)MS * MS;
+    constexpr int LDM = td_ld(MS);
+    constexpr long long MAT = (long long)MS * LDM;
     static_assert(NPM <= 64, "one lane per Schur row");
     __shared__ T dvr[ND], dvi[ND], sr[NPM * NPM], si[NPM * NPM];
     const int cell = blockIdx.x, sy = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -2079,7 +2083,7 @@ __global__ void __launch_bounds__(SV_THREADS) dv_setup_kernel(DvArgs<T> A)
             for (int c = 0; c < DIM; ++c)
 #pragma unroll
                 for (int c2 = 0; c2 < DIM; ++c2) {
-                    const long long o = (long long)(c * NL + l) * MS + c2 * NL + l;
+                    const long long o = (long long)(c * NL + l) * LDM + c2 * NL + l;
                     br_[c][c2] = Mr[o];
                     bi_[c][c2] = cx ? Mi[o] : T(0);
                 }
@@ -2097,7 +2101,7 @@ __global__ void __launch_bounds__(SV_THREADS) dv_setup_kernel(DvArgs<T> A)
         }
     } else {
         for (int i = tid; i < NV; i += SV_THREADS) {
-            const T ar = Mr[(long long)i * MS + i], ai = cx ? Mi[(long long)i * MS + i] : T(0);
+            const T ar = Mr[(long long)i * LDM + i], ai = cx ? Mi[(long long)i * LDM + i] : T(0);
             const T den = ar * ar + ai * ai;
             const T ir = den != T(0) ? ar / den : T(0), ii = den != T(0) ? -ai / den : T(0);
             dvr[i] = ir;
@@ -2109,7 +2113,7 @@ __global__ void __launch_bounds__(SV_THREADS) dv_setup_kernel(DvArgs<T> A)
     __syncthreads();
     for (int e = tid; e < NPM * NPM; e += SV_THREADS) {
         const int j = e / NPM, k = e - (e / NPM) * NPM;
-        const long long rj = (long long)(NV + j) * MS;
+        const long long rj = (long long)(NV + j) * LDM;
         T acr = Mr[rj + NV + k], aci = cx ? Mi[rj + NV + k] : T(0);
         if constexpr (BLK) {
             for (int l = 0; l < NL; ++l) {
@@ -2120,7 +2124,7 @@ __global__ void __launch_bounds__(SV_THREADS) dv_setup_kernel(DvArgs<T> A)
                     wi[c] = 0;
 #pragma unroll
                     for (int c2 = 0; c2 < DIM; ++c2) {
-                        const long long o = (long long)(c2 * NL + l) * MS + NV + k;
+                        const long long o = (long long)(c2 * NL + l) * LDM + NV + k;
                         T tr, ti;
                         cmul(dvr[(l * DIM + c) * DIM + c2], dvi[(l * DIM + c) * DIM + c2], Mr[o], cx ? Mi[o] : T(0),
                              tr, ti);
@@ -2138,7 +2142,7 @@ __global__ void __launch_bounds__(SV_THREADS) dv_setup_kernel(DvArgs<T> A)
             }
         } else {
             for (int i = 0; i < NV; ++i) {
-                const long long ci_ = (long long)i * MS + NV + k;
+                const long long ci_ = (long long)i * LDM + NV + k;
                 const T bre = Mr[rj + i], bim = cx ? Mi[rj + i] : T(0);          // B[j][i]
                 const T cre = Mr[ci_], cim = cx ? Mi[ci_] : T(0);                   // B^T[i][k]
                 T tr, ti, ur, ui;
@@ -2220,7 +2224,8 @@ __global__ void __launch_bounds__(SV_THREADS) solve_dv_kernel(DvArgs<T> A)
     using Z = VS<DIM, R>;
     constexpr int N1 = Z::N1, NL = Z::NL, NPM = Z::NPM;
     constexpr int NV = DIM * NL, MS = NV + NPM, MSP = (MS + 1) & ~1;
-    constexpr long long MAT = (long long)MS * MS;
+    constexpr int LDM = td_ld(MS);
+    constexpr long long MAT = (long long)MS * LDM;
     static_assert(NPM <= 64, "one lane per Schur row");
     extern __shared__ unsigned char lds_raw[];
     const int nt = A.nt;
@@ -2295,7 +2300,7 @@ __global__ void __launch_bounds__(SV_THREADS) solve_dv_kernel(DvArgs<T> A)
         }
         // h = g - B t: one wavefront per pressure row
         for (int j = wv; j < NPM; j += SV_THREADS / 64) {
-            const long long rj = (long long)(NV + j) * MS;
+            const long long rj = (long long)(NV + j) * LDM;
             T sr_ = 0, si_ = 0;
             for (int i = lane; i < NV; i += 64) {
                 T ur, ui;
@@ -2368,7 +2373,7 @@ __global__ void __launch_bounds__(SV_THREADS) solve_dv_kernel(DvArgs<T> A)
                 T qr[DIM], qi[DIM];   // (B^T p) at the node's components
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) {
-                    const long long ri = (long long)(c * NL + l) * MS + NV;
+                    const long long ri = (long long)(c * NL + l) * LDM + NV;
                     T sr_ = 0, si_ = 0;
 #pragma unroll 4
                     for (int j = 0; j < NPM; ++j) {
@@ -2397,7 +2402,7 @@ __global__ void __launch_bounds__(SV_THREADS) solve_dv_kernel(DvArgs<T> A)
             }
         } else {
             for (int i = tid; i < NV; i += SV_THREADS) {
-                const long long ri = (long long)i * MS + NV;
+                const long long ri = (long long)i * LDM + NV;
                 T sr_ = 0, si_ = 0;
 #pragma unroll 4
                 for (int j = 0; j < NPM; ++j) {
@@ -2454,7 +2459,7 @@ __global__ void __launch_bounds__(SV_THREADS) batched_solve_kernel(const T *LUal
             }
         }
     __syncthreads();
-    lu_substitute<T>(LU, m, b, dblk);
+    lu_substitute<T>(LU, m, m, b, dblk);
     for (int r = tid; r < m; r += SV_THREADS) x[r] = b[r];
 }
 
@@ -2479,7 +2484,7 @@ __global__ void __launch_bounds__(SV_THREADS) dense_solve_kernel(const T *LU, co
             }
         }
     __syncthreads();
-    lu_substitute<T>(LU, m, b, dblk);
+    lu_substitute<T>(LU, m, m, b, dblk);
     for (int r = tid; r < nout; r += SV_THREADS) x[r] = b[r];
 }
 
@@ -2691,7 +2696,8 @@ hipError_t launch_patch_td(int dim, int r, const PatchTdArgs<TE, TP> &a, int nce
 }
 
 template <typename T>
-hipError_t launch_lu_c(T *A, int *piv, int m, long long a_stride, int batch, int *info, size_t max_lds, hipStream_t s)
+hipError_t launch_lu_c(T *A, int *piv, int m, int ld, long long a_stride, int batch, int *info, size_t max_lds,
+                       hipStream_t s)
 {
     int cap = lu_nb_cap();
     for (int nb = cap; nb >= 16; nb /= 2) {
@@ -2704,7 +2710,7 @@ hipError_t launch_lu_c(T *A, int *piv, int m, long long a_stride, int batch, int
         size_t bytes = lu_c_lds_bytes<NBV, T>(m);                                                                      \
         hipError_t e = lds_attr((const void *)lu_kernel_c<T, NBV>, bytes);                    \
         if (e != hipSuccess) return e;                                                                                 \
-        hipLaunchKernelGGL((lu_kernel_c<T, NBV>), dim3(batch), dim3(LU_THREADS), bytes, s, A, piv, m, a_stride, info); \
+        hipLaunchKernelGGL((lu_kernel_c<T, NBV>), dim3(batch), dim3(LU_THREADS), bytes, s, A, piv, m, ld, a_stride, info); \
         return hipGetLastError();                                                                                      \
     }
     LUC(32) LUC(16) LUC(8) LUC(4)
@@ -3065,8 +3071,8 @@ template hipError_t launch_solve<float, float>(int, int, const SolveArgs<float, 
 template hipError_t launch_solve<double, float>(int, int, const SolveArgs<double, float> &, int, int, hipStream_t);
 template hipError_t launch_patch_td<double, double>(int, int, const PatchTdArgs<double, double> &, int, hipStream_t);
 template hipError_t launch_patch_td<float, float>(int, int, const PatchTdArgs<float, float> &, int, hipStream_t);
-template hipError_t launch_lu_c<double>(double *, int *, int, long long, int, int *, size_t, hipStream_t);
-template hipError_t launch_lu_c<float>(float *, int *, int, long long, int, int *, size_t, hipStream_t);
+template hipError_t launch_lu_c<double>(double *, int *, int, int, long long, int, int *, size_t, hipStream_t);
+template hipError_t launch_lu_c<float>(float *, int *, int, int, long long, int, int *, size_t, hipStream_t);
 template hipError_t launch_solve_td<double, double>(int, int, const SolveTdArgs<double, double> &, int, int,
                                                     hipStream_t);
 template hipError_t launch_solve_td<float, float>(int, int, const SolveTdArgs<float, float> &, int, int, hipStream_t);
