@@ -76,11 +76,13 @@ template <typename T, typename TP, typename TF = TP> struct SolveTdArgs {
 
 // a batch of LU factorizations: uniform size m, or per-matrix sizes and
 // offsets (elements of A, entries of the pivot array)
-// row stride of the time-decoupled patch systems (elements): every row starts
-// on a 32-element boundary (128 bytes in FP32, 64 in the BF16 copy), so the
-// 32-column blocks the substitutions read cover whole memory sectors instead
-// of sharing their edge sectors with the neighbouring block
-constexpr int td_ld(int ms) { return (ms + 31) & ~31; }
+// row stride of the time-decoupled patch systems (elements): above 128
+// unknowns every row starts on a 32-element boundary (128 bytes in FP32, 64 in
+// the BF16 copy), so the 32-column blocks the substitutions read cover whole
+// memory sectors instead of sharing their edge sectors with the neighbouring
+// block; smaller systems stay unpadded (the padded form of their sweep needs
+// more registers than it saves in bytes)
+constexpr int td_ld(int ms) { return ms > 128 ? (ms + 31) & ~31 : ms; }
 
 struct LuBatch {
     int uniform_m;
