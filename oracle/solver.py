@@ -536,68 +536,151 @@ class NewtonStats:
     res0: float = 0.0
     res: float = 0.0
     history: list = field(default_factory=list)
+    etas: list = field(default_factory=list)
+    alphas: list = field(default_factory=list)
     converged: bool = False
 
 
-def _interp_step(alpha, phi0, g0, fails):
-    """Backtracking step: minimizer of the quadratic through (0, phi0, g0) and
-    the last failure, or of the cubic through the last two failures; None if
-    undefined."""
-    a1, p1 = fails[-1]
-    if len(fails) == 1:
-        den = 2.0 * (p1 - phi0 - g0 * a1)
-        if den <= 0.0:
+def forcing_term(eta_prev, res_norm, res_norm_prev, p: NewtonParams):
+    """Eisenstat-Walker forcing term of the next linear solve (eq. ew): the
+    ratio of the current to the previous residual M-norm (denominator kept
+    above eps), raised to theta.  Reading: the factor c_eta multiplies the
+    previous forcing term and the result is held in [eta_min, eta_max], the
+    form the appendix's Newton algorithm states with the parameter names of
+    Sec. "Numerical experiments"."""
+    ratio = res_norm / max(res_norm_prev, p.eps)
+    return float(np.clip(p.c_eta * eta_prev * ratio ** p.theta, p.eta_min, p.eta_max))
+
+
+class MeritMemory:
+    """The nonmonotone reference of the line search (Grippo-Lampariello-Lucidi,
+    Sec. "Inexact Newton-Krylov method"): the largest of the last `size`
+    accepted merit values of the slab's Newton iteration, seeded with the
+    initial merit value; size 0 = the monotone rule (reference = phi(0))."""
+
+    def __init__(self, phi_initial, size):
+        self.size = size
+        self.values = [phi_initial]
+
+    def reference(self, phi0):
+        return max(self.values) if self.size > 0 else phi0
+
+    def remember(self, phi):
+        if self.size > 0:
+            self.values = (self.values + [phi])[-self.size:]
+
+
+def model_minimizer(phi0, g0, failures):
+    """Trial step from a polynomial model of the merit function along the
+    Newton direction (reading: quadratic after the first rejected step,
+    cubic after later ones).  The quadratic q(a) = phi0 + g0 a + b a^2 takes
+    phi at the last rejected step; the cubic phi0 + g0 a + b a^2 + c a^3 takes
+    phi at the last two rejected steps.  Returns the model's local minimizer,
+    or None when the model has none (a concave quadratic, a singular fit, no
+    real critical point)."""
+    a1, p1 = failures[-1]
+    if len(failures) == 1:
+        curv = p1 - phi0 - g0 * a1                    # b a1^2
+        if curv <= 0.0:
             return None
-        return -g0 * a1 * a1 / den
-    a2, p2 = fails[-2]
-    # cubic phi(a) = phi0 + g0 a + b a^2 + c a^3 through (a1,p1), (a2,p2)
-    r1 = p1 - phi0 - g0 * a1
-    r2 = p2 - phi0 - g0 * a2
+        return -g0 * a1 * a1 / (2.0 * curv)
+    a2, p2 = failures[-2]
+    # solve [a1^2 a1^3; a2^2 a2^3] [b; c] = [e1; e2] by Cramer's rule
+    e1 = p1 - phi0 - g0 * a1
+    e2 = p2 - phi0 - g0 * a2
     det = a1 * a1 * a2 * a2 * (a1 - a2)
     if det == 0.0:
         return None
-    cc = (a2 * a2 * r1 - a1 * a1 * r2) / det
-    bb = (-a2 ** 3 * r1 + a1 ** 3 * r2) / det
-    if cc == 0.0:
-        if bb <= 0.0:
-            return None
-        return -g0 / (2.0 * bb)
-    disc = bb * bb - 3.0 * cc * g0
+    c3 = (a2 * a2 * e1 - a1 * a1 * e2) / det
+    b2 = (a1 ** 3 * e2 - a2 ** 3 * e1) / det
+    if c3 == 0.0:
+        return -g0 / (2.0 * b2) if b2 > 0.0 else None
+    # phi'(a) = g0 + 2 b a + 3 c a^2 = 0; the root where phi'' > 0
+    disc = b2 * b2 - 3.0 * c3 * g0
     if disc < 0.0:
         return None
-    return (-bb + np.sqrt(disc)) / (3.0 * cc)
+    return (-b2 + np.sqrt(disc)) / (3.0 * c3)
 
 
-def armijo(phi, phi0, g0, window, p: NewtonParams, stats: NewtonStats):
-    """Alg. "Armijo": nonmonotone sufficient decrease against max(window),
-    interpolated backtracking clamped to [0.1 alpha, 0.5 alpha], at most
-    max_backtracks reductions, alpha_min as the fallback step."""
+def line_search(phi, phi0, g0, memory: MeritMemory, p: NewtonParams):
+    """Step length by the nonmonotone Armijo condition (eq. armijo against the
+    remembered reference): the first trial is lambda0; a rejected step is
+    replaced by the model minimizer held in [0.1 alpha, 0.5 alpha] (tau alpha
+    when the model has none); after max_backtracks rejections, or once the
+    step would fall to alpha_min, the step is alpha_min.  Returns (alpha,
+    accepted merit value or None, number of rejected steps)."""
     alpha = p.lambda0
-    fails = []
-    nback = 0
+    failures = []
     while alpha > p.alpha_min:
         phit = phi(alpha)
-        phimax = max(window) if p.window > 0 else phi0
-        if phit <= phimax + p.c * alpha * g0:
-            if p.window > 0:
-                window.append(phit)
-                del window[:-p.window]
-            return alpha, phit
-        fails.append((alpha, phit))
-        nback += 1
-        stats.backtracks += 1
-        if nback > p.max_backtracks:
+        if phit <= memory.reference(phi0) + p.c * alpha * g0:
+            memory.remember(phit)
+            return alpha, phit, len(failures)
+        failures.append((alpha, phit))
+        if len(failures) > p.max_backtracks:
             break
-        ai = _interp_step(alpha, phi0, g0, fails)
-        if ai is None or not np.isfinite(ai):
-            alpha = p.tau * alpha
-        else:
-            alpha = min(max(ai, 0.1 * alpha), 0.5 * alpha)
-    return p.alpha_min, None
+        trial = model_minimizer(phi0, g0, failures)
+        alpha = p.tau * alpha if trial is None or not np.isfinite(trial) else \
+            min(max(trial, 0.1 * alpha), 0.5 * alpha)
+    return p.alpha_min, None, len(failures)
+
+
+def fgmres_stagnated(history, s, theta):
+    """Stagnation of the FGMRES residual estimates: s consecutive ratios
+    r_{j+1} / r_j of at least theta (the third rebuild criterion of the
+    remark after Lemma "patch perturbation")."""
+    run = 0
+    for a, b in zip(history[:-1], history[1:]):
+        if a <= 0:
+            continue
+        run = run + 1 if b / a >= theta else 0
+        if run >= s:
+            return True
+    return False
+
+
+class RebuildPolicy:
+    """When the midpoint-frozen smoother is rebuilt (the criteria of the
+    remark after Lemma "patch perturbation"; thresholds are reading S9).
+    Before a Newton step: when none is built yet, on Newton deterioration
+    (the last residual contraction rho >= theta_N) or on linear
+    deterioration (the last FGMRES count kappa >= max(theta_L kappa_ref,
+    kappa_abs), kappa_ref = the count recorded at the last rebuild of this
+    kind).  After a step: when the step's FGMRES residuals stagnated."""
+
+    def __init__(self, p: NewtonParams):
+        self.p = p
+        self.rho = 1.0
+        self.kappa = 1
+        self.kappa_ref = 1
+        self.built = False
+
+    def due_before_step(self):
+        p = self.p
+        return (not self.built) or self.rho >= p.theta_N or \
+            self.kappa >= max(p.theta_L * self.kappa_ref, p.kappa_abs)
+
+    def rebuilt_before_step(self):
+        self.built = True
+        self.kappa_ref = max(1, self.kappa)
+
+    def record_step(self, res_norm, res_norm_prev, fgmres_its):
+        self.rho = res_norm / max(res_norm_prev, self.p.eps)
+        self.kappa = max(1, fgmres_its)
+
+    def due_after_step(self, fgmres_history):
+        return fgmres_stagnated(fgmres_history, self.p.stag_s, self.p.stag_theta)
 
 
 def newton_solve(slab: Slab, hier: Hierarchy, U0, rhs=None, vprev=None, p: NewtonParams = NewtonParams(),
                  nu1=1, nu2=1):
+    """Inexact Newton method for R_n(U; V_{n-1}) = 0 (Sec. "Inexact
+    Newton-Krylov method"): the correction solves eq. lin-sys by FGMRES to
+    the relative M-norm accuracy of eq. inexact with the forcing term of
+    eq. ew, preconditioned by one hp-STMG V-cycle; the step length comes from
+    the nonmonotone Armijo rule on phi(a) = 1/2 ||R(U + a dU)||_M^2 with
+    phi'(0) = (M R)^T J dU (reading S6); the smoother follows RebuildPolicy.
+    Stops when ||R||_M <= max(atol, rtol ||R_0||_M) or after maxit steps."""
     M = slab.slab_mass()
     U = np.array(U0, dtype=float)
     st = NewtonStats()
@@ -609,59 +692,42 @@ def newton_solve(slab: Slab, hier: Hierarchy, U0, rhs=None, vprev=None, p: Newto
         return np.sqrt(max(v @ (M @ v), 0.0))
 
     r = R(U)
-    n0 = mnorm(r)
-    st.res0 = n0
-    nrm = n0
-    n_prev = n0
-    eta = p.eta0
-    rho_prev, kappa_prev, kappa_ref = 1.0, 1, 1
-    window = [0.5 * n0 * n0]
-    k = 0
-    st.history.append(n0)
-    while nrm > max(p.atol, p.rtol * n0) and k < p.maxit:
+    res = mnorm(r)
+    st.res0 = res
+    st.history.append(res)
+    target = max(p.atol, p.rtol * res)
+    memory = MeritMemory(0.5 * res * res, p.window)
+    policy = RebuildPolicy(p)
+    eta, res_before = p.eta0, res
+    while res > target and st.newton_its < p.maxit:
         hier.set_state(U)
-        if hier.levels[0].patches is None or rho_prev >= p.theta_N or \
-                kappa_prev >= max(p.theta_L * kappa_ref, p.kappa_abs):
+        if policy.due_before_step():
             hier.rebuild_smoother()
             st.rebuilds += 1
-            kappa_ref = max(1, kappa_prev)
-        if k > 0:
-            eta = min(max(p.c_eta * eta * (nrm / max(n_prev, p.eps)) ** p.theta, p.eta_min), p.eta_max)
+            policy.rebuilt_before_step()
+        if st.newton_its > 0:
+            eta = forcing_term(eta, res, res_before, p)
+        st.etas.append(eta)
         J = hier.levels[0].J
-        res = fgmres(lambda z: J @ z, lambda v: hier.vcycle(v, 0, nu1, nu2), lambda v: M @ v, -r, eta,
+        lin = fgmres(lambda z: J @ z, lambda v: hier.vcycle(v, 0, nu1, nu2), lambda v: M @ v, -r, eta,
                      p.fgmres_maxit)
-        dU = res.x
-        st.fgmres_its.append(res.its)
-        phi0 = 0.5 * nrm * nrm
+        dU = lin.x
+        st.fgmres_its.append(lin.its)
         g0 = (M @ r) @ (J @ dU)
-
-        def phi(a):
-            ra = R(U + a * dU)
-            return 0.5 * mnorm(ra) ** 2
-
-        alpha, _ = armijo(phi, phi0, g0, window, p, st)
+        alpha, _, nback = line_search(lambda a: 0.5 * mnorm(R(U + a * dU)) ** 2, 0.5 * res * res, g0, memory, p)
+        st.backtracks += nback
+        st.alphas.append(alpha)
         U = U + alpha * dU
-        n_prev = nrm
+        res_before = res
         r = R(U)
-        nrm = mnorm(r)
-        st.history.append(nrm)
-        rho_prev = nrm / max(n_prev, p.eps)
-        kappa_prev = max(1, res.its)
-        # stagnation of the FGMRES residuals over s consecutive iterations
-        hh = res.history
-        ratios = [hh[i + 1] / hh[i] for i in range(len(hh) - 1) if hh[i] > 0]
-        run = 0
-        stag = False
-        for q in ratios:
-            run = run + 1 if q >= p.stag_theta else 0
-            if run >= p.stag_s:
-                stag = True
-        if stag:
+        res = mnorm(r)
+        st.history.append(res)
+        policy.record_step(res, res_before, lin.its)
+        if policy.due_after_step(lin.history):
             hier.set_state(U)
             hier.rebuild_smoother()
             st.rebuilds += 1
-        k += 1
-    st.newton_its = k
-    st.res = nrm
-    st.converged = nrm <= max(p.atol, p.rtol * n0)
+        st.newton_its += 1
+    st.res = res
+    st.converged = res <= target
     return U, st

@@ -2,6 +2,7 @@
 #include "mg.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -37,6 +38,11 @@ bool check_problem(const stmg_problem *p, std::string &why)
     if (p->r < 1 || p->r > 3) { why = "r must be in 1..3"; return false; }
     if (p->k < 0 || p->k > MAX_K) { why = "k must be in 0..3"; return false; }
     if (!(p->tau > 0) || !(p->nu > 0)) { why = "tau and nu must be positive"; return false; }
+    // transfer matrices and node gathers index the velocity nodes of one
+    // component with 32 bits; a p-transfer row holds up to 3^d entries
+    long long nodes = 1;
+    for (int a = 0; a < p->dim; ++a) nodes *= (long long)(p->r + 1) * p->n_cells[a] + 1;
+    if (nodes > INT_MAX / 27) { why = "mesh too large (velocity nodes per component above 2^31 / 27)"; return false; }
     return true;
 }
 

@@ -82,6 +82,11 @@ void Krylov::ensure(long long N_, int maxit_)
     h.alloc(sizeof(double) * 3 * (maxit + 2));
     partial.alloc(sizeof(double) * multidot_partial_words(maxit + 1));
     y.alloc(sizeof(double) * (maxit + 1));
+    H.alloc(sizeof(double) * (maxit + 1) * maxit);
+    cs.alloc(sizeof(double) * maxit);
+    sn.alloc(sizeof(double) * maxit);
+    g.alloc(sizeof(double) * (maxit + 1));
+    report.alloc(sizeof(double) * 2);
     for (DevBuf *b : {&r, &Mr, &dU, &Ut, &rt, &tmp}) b->alloc(sizeof(double) * N);
     dot.alloc(8 * 8);
 }
@@ -619,261 +624,6 @@ void mg_precondition(stmg_ctx *ctx, const double *v, double *z)
         STMG_HIP(hipGraphLaunch(G.x, s));
     }
     STMG_HIP(hipMemcpyAsync(z, G.out.p, bytes, hipMemcpyDeviceToDevice, s));
-}
-
-// ---------------------------------------------------------------------------
-// FGMRES
-// ---------------------------------------------------------------------------
-FgmresOut fgmres(stmg_ctx *ctx, const double *state, const double *b, double *x, double rtol, int maxit)
-{
-    Level &L = *ctx->levels[0];
-    const long long N = L.N;
-    hipStream_t s = ctx->stream;
-    Krylov &K = ctx->kry;
-    K.ensure(N, maxit);
-    double *V = K.V.as<double>(), *MV = K.MV.as<double>(), *Z = K.Z.as<double>();
-    double *w = K.w.as<double>(), *u = K.u.as<double>(), *h = K.h.as<double>(), *part = K.partial.as<double>();
-    FgmresOut out;
-    STMG_HIP(hipMemcpyAsync(V, b, N * 8, hipMemcpyDeviceToDevice, s));
-    L.apply<double>(Mode::Mass, nullptr, V, MV, nullptr, nullptr, 1, s);
-    STMG_HIP(vec_multidot(N, 1, MV, V, N, h, part, 0, s));
-    double beta2 = 0;
-    STMG_HIP(hipMemcpyAsync(&beta2, h, 8, hipMemcpyDeviceToHost, s));
-    STMG_HIP(hipStreamSynchronize(s));
-    const double beta = std::sqrt(std::max(beta2, 0.0));
-    out.hist.push_back(beta);
-    if (beta == 0.0) {
-        STMG_HIP(vec_fill<double>(N, 0.0, x, s));
-        out.converged = true;
-        return out;
-    }
-    STMG_HIP(vec_axpby<double>(N, 1.0 / beta, V, 0.0, V, s));
-    STMG_HIP(vec_axpby<double>(N, 1.0 / beta, MV, 0.0, MV, s));
-    std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0);
-    std::vector<double> hh(2 * (maxit + 1) + 1);
-    g[0] = beta;
-    int its = 0;
-    for (int j = 0; j < maxit; ++j) {
-        double *vj = V + (long long)j * N, *zj = Z + (long long)j * N;
-        mg_precondition(ctx, vj, zj);
-        L.apply<double>(Mode::Jac, state, zj, w, nullptr, nullptr, 1, s);
-        L.apply<double>(Mode::Mass, nullptr, w, u, nullptr, nullptr, 1, s);
-        double *h1 = h, *h2 = h + (maxit + 1), *hn = h + 2 * (maxit + 1);
-        STMG_HIP(vec_multidot(N, j + 1, u, V, N, h1, part, 0, s));
-        STMG_HIP(vec_subtract_combination(N, j + 1, h1, V, N, w, s));
-        STMG_HIP(vec_subtract_combination(N, j + 1, h1, MV, N, u, s));
-        STMG_HIP(vec_multidot(N, j + 1, u, V, N, h2, part, 0, s));
-        STMG_HIP(vec_subtract_combination(N, j + 1, h2, V, N, w, s));
-        STMG_HIP(vec_subtract_combination(N, j + 1, h2, MV, N, u, s));
-        STMG_HIP(vec_multidot(N, 1, u, w, N, hn, part, 0, s));
-        STMG_HIP(hipMemcpyAsync(hh.data(), h, sizeof(double) * (2 * (maxit + 1) + 1), hipMemcpyDeviceToHost, s));
-        STMG_HIP(hipStreamSynchronize(s));
-        std::vector<double> col(j + 2);
-        for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[(maxit + 1) + i];
-        const double hnv = std::sqrt(std::max(hh[2 * (maxit + 1)], 0.0));
-        col[j + 1] = hnv;
-        for (int i = 0; i < j; ++i) {
-            double t = cs[i] * col[i] + sn[i] * col[i + 1];
-            col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-            col[i] = t;
-        }
-        double den = std::hypot(col[j], col[j + 1]);
-        if (den > 0) {
-            cs[j] = col[j] / den;
-            sn[j] = col[j + 1] / den;
-        } else {
-            cs[j] = 1.0;
-            sn[j] = 0.0;
-        }
-        col[j] = cs[j] * col[j] + sn[j] * col[j + 1];
-        col[j + 1] = 0.0;
-        for (int i = 0; i <= j + 1; ++i) H[(size_t)i * maxit + j] = col[i];
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        its = j + 1;
-        const double res = std::fabs(g[j + 1]);
-        out.hist.push_back(res);
-        if (res <= rtol * beta || hnv == 0.0) {
-            out.converged = res <= rtol * beta;
-            break;
-        }
-        STMG_HIP(vec_axpby<double>(N, 1.0 / hnv, w, 0.0, V + (long long)(j + 1) * N, s));
-        STMG_HIP(vec_axpby<double>(N, 1.0 / hnv, u, 0.0, MV + (long long)(j + 1) * N, s));
-    }
-    // back substitution H y = g
-    std::vector<double> y(its, 0.0);
-    for (int i = its - 1; i >= 0; --i) {
-        double t = g[i];
-        for (int k = i + 1; k < its; ++k) t -= H[(size_t)i * maxit + k] * y[k];
-        y[i] = t / H[(size_t)i * maxit + i];
-    }
-    STMG_HIP(hipMemcpyAsync(K.y.p, y.data(), sizeof(double) * its, hipMemcpyHostToDevice, s));
-    STMG_HIP(vec_combination(N, its, K.y.as<double>(), Z, N, x, s));
-    STMG_HIP(hipStreamSynchronize(s));
-    out.its = its;
-    return out;
-}
-
-// ---------------------------------------------------------------------------
-// Newton
-// ---------------------------------------------------------------------------
-namespace {
-
-bool interp_step(double phi0, double g0, const std::vector<std::pair<double, double>> &fails, double &out)
-{
-    const double a1 = fails.back().first, p1 = fails.back().second;
-    if (fails.size() == 1) {
-        double den = 2.0 * (p1 - phi0 - g0 * a1);
-        if (den <= 0.0) return false;
-        out = -g0 * a1 * a1 / den;
-        return true;
-    }
-    const double a2 = fails[fails.size() - 2].first, p2 = fails[fails.size() - 2].second;
-    double r1 = p1 - phi0 - g0 * a1, r2 = p2 - phi0 - g0 * a2;
-    double det = a1 * a1 * a2 * a2 * (a1 - a2);
-    if (det == 0.0) return false;
-    double cc = (a2 * a2 * r1 - a1 * a1 * r2) / det;
-    double bb = (-a2 * a2 * a2 * r1 + a1 * a1 * a1 * r2) / det;
-    if (cc == 0.0) {
-        if (bb <= 0.0) return false;
-        out = -g0 / (2.0 * bb);
-        return true;
-    }
-    double disc = bb * bb - 3.0 * cc * g0;
-    if (disc < 0.0) return false;
-    out = (-bb + std::sqrt(disc)) / (3.0 * cc);
-    return true;
-}
-
-} // namespace
-
-int newton_solve(stmg_ctx *ctx, double *U, stmg_stats *stats)
-{
-    auto t0 = std::chrono::steady_clock::now();
-    Level &L = *ctx->levels[0];
-    Mg &mg = *ctx->mg;
-    const stmg_options &p = ctx->opt;
-    const long long N = L.N;
-    hipStream_t s = ctx->stream;
-    Krylov &W = ctx->kry;
-    const double *rhs = ctx->has_rhs ? ctx->rhs.as<double>() : nullptr;
-    const double *vprev = ctx->has_vprev ? ctx->vprev.as<double>() : nullptr;
-    W.ensure(N, std::max(1, p.fgmres_maxit));
-    double *part = W.partial.as<double>();
-    auto dotM = [&](const double *a, const double *Mb) {
-        STMG_HIP(vec_multidot(N, 1, a, Mb, N, W.dot.as<double>(), part, 0, s));
-        double v = 0;
-        STMG_HIP(hipMemcpyAsync(&v, W.dot.p, 8, hipMemcpyDeviceToHost, s));
-        STMG_HIP(hipStreamSynchronize(s));
-        return v;
-    };
-    auto residual = [&](const double *X, double *R) { L.apply<double>(Mode::Res, nullptr, X, R, rhs, vprev, 1, s); };
-    auto mnorm = [&](const double *v) {
-        L.apply<double>(Mode::Mass, nullptr, v, W.tmp.as<double>(), nullptr, nullptr, 1, s);
-        return std::sqrt(std::max(dotM(v, W.tmp.as<double>()), 0.0));
-    };
-    const double eps = 1e-30;
-    stmg_stats st{};
-    residual(U, W.r.as<double>());
-    const double n0 = mnorm(W.r.as<double>());
-    if (!std::isfinite(n0)) {
-        ctx->err = "non-finite initial residual";
-        return STMG_ENONFINITE;
-    }
-    st.res0_M = n0;
-    double nrm = n0, n_prev = n0, eta = p.ew_eta0, rho_prev = 1.0;
-    int kappa_prev = 1, kappa_ref = 1, k = 0;
-    std::vector<double> window{0.5 * n0 * n0};
-    for (size_t l = 0; l < mg.lv.size(); ++l) mg.lv[l].have_patches = false;
-    while (nrm > std::max(p.newton_atol, p.newton_rtol * n0) && k < p.newton_maxit) {
-        mg_set_state(ctx, U);
-        if (!mg.lv[0].have_patches || rho_prev >= p.rb_theta_N ||
-            kappa_prev >= std::max(p.rb_theta_L * kappa_ref, p.rb_kappa_abs)) {
-            mg_rebuild(ctx);
-            st.rebuilds++;
-            kappa_ref = std::max(1, kappa_prev);
-        }
-        if (k > 0)
-            eta = std::min(std::max(p.ew_c * eta * std::pow(nrm / std::max(n_prev, eps), p.ew_theta), p.ew_eta_min),
-                           p.ew_eta_max);
-        // solve J dU = -r
-        STMG_HIP(vec_axpby<double>(N, -1.0, W.r.as<double>(), 0.0, W.rt.as<double>(), s));
-        FgmresOut fo = fgmres(ctx, U, W.rt.as<double>(), W.dU.as<double>(), eta, p.fgmres_maxit);
-        if (k < 64) st.fgmres_its[k] = fo.its;
-        st.fgmres_its_total += fo.its;
-        // g0 = (M r) . (J dU)
-        L.apply<double>(Mode::Mass, nullptr, W.r.as<double>(), W.Mr.as<double>(), nullptr, nullptr, 1, s);
-        L.apply<double>(Mode::Jac, U, W.dU.as<double>(), W.tmp.as<double>(), nullptr, nullptr, 1, s);
-        const double g0 = dotM(W.tmp.as<double>(), W.Mr.as<double>());
-        const double phi0 = 0.5 * nrm * nrm;
-        // Armijo with nonmonotone window
-        double alpha = p.ls_lambda0, accepted = -1.0;
-        std::vector<std::pair<double, double>> fails;
-        int nback = 0;
-        while (alpha > p.ls_alpha_min) {
-            STMG_HIP(hipMemcpyAsync(W.Ut.p, U, N * 8, hipMemcpyDeviceToDevice, s));
-            STMG_HIP(vec_axpby<double>(N, alpha, W.dU.as<double>(), 1.0, W.Ut.as<double>(), s));
-            residual(W.Ut.as<double>(), W.rt.as<double>());
-            const double mt = mnorm(W.rt.as<double>());
-            const double phit = 0.5 * mt * mt;
-            double phimax = phi0;
-            if (p.ls_window > 0) phimax = *std::max_element(window.begin(), window.end());
-            if (std::isfinite(phit) && phit <= phimax + p.ls_c * alpha * g0) {
-                if (p.ls_window > 0) {
-                    window.push_back(phit);
-                    if ((int)window.size() > p.ls_window) window.erase(window.begin(), window.end() - p.ls_window);
-                }
-                accepted = alpha;
-                break;
-            }
-            fails.push_back({alpha, phit});
-            nback++;
-            st.backtracks++;
-            if (nback > p.ls_max_backtracks) break;
-            double ai = 0;
-            if (!interp_step(phi0, g0, fails, ai) || !std::isfinite(ai)) alpha = p.ls_tau * alpha;
-            else alpha = std::min(std::max(ai, 0.1 * alpha), 0.5 * alpha);
-        }
-        if (accepted < 0) alpha = p.ls_alpha_min;
-        STMG_HIP(vec_axpby<double>(N, alpha, W.dU.as<double>(), 1.0, U, s));
-        n_prev = nrm;
-        residual(U, W.r.as<double>());
-        nrm = mnorm(W.r.as<double>());
-        if (!std::isfinite(nrm)) {
-            ctx->err = "non-finite residual";
-            return STMG_ENONFINITE;
-        }
-        rho_prev = nrm / std::max(n_prev, eps);
-        kappa_prev = std::max(1, fo.its);
-        int run = 0;
-        bool stag = false;
-        for (size_t i = 0; i + 1 < fo.hist.size(); ++i) {
-            if (fo.hist[i] <= 0) continue;
-            double q = fo.hist[i + 1] / fo.hist[i];
-            run = q >= p.rb_stag_theta ? run + 1 : 0;
-            if (run >= p.rb_stag_s) stag = true;
-        }
-        if (stag) {
-            mg_set_state(ctx, U);
-            mg_rebuild(ctx);
-            st.rebuilds++;
-        }
-        ++k;
-        if (verbose()) {
-            std::fprintf(stderr,
-                         "[stmg] newton %d: |R|_M %.3e (rho %.3f) fgmres %d (eta %.2e reached %.2e) alpha %.3g "
-                         "rebuilds %d  %.2f s\n",
-                         k, nrm, rho_prev, fo.its, eta, fo.hist.back() / fo.hist.front(), alpha, st.rebuilds,
-                         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
-            std::fflush(stderr);
-        }
-    }
-    STMG_HIP(hipStreamSynchronize(s));
-    st.newton_its = k;
-    st.res_M = nrm;
-    st.wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (stats) *stats = st;
-    return nrm <= std::max(p.newton_atol, p.newton_rtol * n0) ? STMG_OK : STMG_NOT_CONVERGED;
 }
 
 } // namespace stmg

@@ -86,6 +86,7 @@ struct Krylov {
     int maxit = 0;
     long long N = 0;
     DevBuf V, MV, Z, w, u, h, partial, y;
+    DevBuf H, cs, sn, g, report;            // Givens form of the Hessenberg system
     DevBuf r, Mr, dU, Ut, rt, tmp, dot;     // Newton vectors
     void ensure(long long N_, int maxit_);
 };

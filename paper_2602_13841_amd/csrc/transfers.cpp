@@ -20,7 +20,9 @@
 #include "transfers.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <stdexcept>
 
 namespace stmg {
 
@@ -52,6 +54,8 @@ HostCsr tensor_csr(int dim, const std::vector<std::vector<std::vector<Entry>>> &
         nrows *= Nrow[a];
         ncols *= Ncol[a];
     }
+    // the device CSR kernels index rows, columns and entries with 32 bits
+    if (nrows > INT_MAX || ncols > INT_MAX) throw std::invalid_argument("transfer matrix too large for 32-bit indices");
     A.nrows = (int)nrows;
     A.ncols = (int)ncols;
     A.rowptr.assign(nrows + 1, 0);
@@ -72,6 +76,8 @@ HostCsr tensor_csr(int dim, const std::vector<std::vector<std::vector<Entry>>> &
             stride *= Ncol[a];
         }
         std::sort(cur.begin(), cur.end(), [](const Entry &x, const Entry &y) { return x.col < y.col; });
+        if ((long long)A.col.size() + (long long)cur.size() > INT_MAX)
+            throw std::invalid_argument("transfer matrix has more than 2^31 - 1 entries");
         for (const Entry &e : cur) {
             if (e.val == 0.0) continue;
             A.col.push_back((int)e.col);

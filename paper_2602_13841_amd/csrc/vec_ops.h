@@ -21,6 +21,18 @@ hipError_t vec_subtract_combination(long long n, int nk, const double *h, const 
 hipError_t vec_combination(long long n, int nk, const double *y, const double *Z, long long ldz, double *x,
                            hipStream_t s);
 
+// FGMRES least-squares bookkeeping in FP64 on the device (Givens form of the
+// Hessenberg system).  H: (maxit+1) x maxit column-major; cs, sn: maxit;
+// g: maxit+1.  Column j of H is h1[i] + h2[i] (the two Gram-Schmidt passes,
+// i <= j) with sqrt(max(hn, 0)) below the diagonal; the previous rotations
+// are applied to it, the rotation eliminating its subdiagonal entry is
+// formed and applied to g.  report[0] = |g[j+1]| (the residual estimate),
+// report[1] = the subdiagonal entry before rotation.
+hipError_t krylov_givens_column(int j, int maxit, const double *h1, const double *h2, const double *hn, double *H,
+                                double *cs, double *sn, double *g, double *report, hipStream_t s);
+// y = H(0:its, 0:its)^{-1} g(0:its) (upper triangular, column-major ld maxit+1)
+hipError_t krylov_upper_solve(int its, int maxit, const double *H, const double *g, double *y, hipStream_t s);
+
 // y[ot][c][row] = sum_it Tm[ot][it] (CSR x[it][c][.])[row] + beta * y
 template <typename T> struct KronCsrArgs {
     const int *rowptr;

@@ -142,6 +142,48 @@ __global__ void __launch_bounds__(256) kron_csr_kernel(KronCsrArgs<T> A)
         }
 }
 
+// one thread: the rotations of a column depend on each other in order, and a
+// column has at most maxit + 1 entries
+__global__ void givens_column_kernel(int j, int maxit, const double *__restrict__ h1, const double *__restrict__ h2,
+                                     const double *__restrict__ hn, double *__restrict__ H, double *__restrict__ cs,
+                                     double *__restrict__ sn, double *__restrict__ g, double *__restrict__ report)
+{
+    if (threadIdx.x != 0) return;
+    double *col = H + (long long)j * (maxit + 1);
+    for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+    const double sub = sqrt(fmax(hn[0], 0.0));
+    col[j + 1] = sub;
+    for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double den = hypot(a, b);
+    const double c = den > 0.0 ? a / den : 1.0, sv = den > 0.0 ? b / den : 0.0;
+    cs[j] = c;
+    sn[j] = sv;
+    col[j] = c * a + sv * b;
+    col[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sv * gj;
+    g[j] = c * gj;
+    report[0] = fabs(g[j + 1]);
+    report[1] = sub;
+}
+
+__global__ void upper_solve_kernel(int its, int maxit, const double *__restrict__ H, const double *__restrict__ g,
+                                   double *__restrict__ y)
+{
+    if (threadIdx.x != 0) return;
+    const long long ld = maxit + 1;
+    for (int i = its - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int k = i + 1; k < its; ++k) t -= H[k * ld + i] * y[k];
+        y[i] = t / H[i * ld + i];
+    }
+}
+
 inline int grid_for(long long n, int th = 256)
 {
     long long b = (n + th - 1) / th;
@@ -190,6 +232,19 @@ hipError_t vec_combination(long long n, int nk, const double *y, const double *Z
                            hipStream_t s)
 {
     hipLaunchKernelGGL(combination, dim3(grid_for(n)), dim3(256), 0, s, n, nk, y, Z, ldz, x);
+    return hipGetLastError();
+}
+
+hipError_t krylov_givens_column(int j, int maxit, const double *h1, const double *h2, const double *hn, double *H,
+                                double *cs, double *sn, double *g, double *report, hipStream_t s)
+{
+    hipLaunchKernelGGL(givens_column_kernel, dim3(1), dim3(64), 0, s, j, maxit, h1, h2, hn, H, cs, sn, g, report);
+    return hipGetLastError();
+}
+
+hipError_t krylov_upper_solve(int its, int maxit, const double *H, const double *g, double *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(upper_solve_kernel, dim3(1), dim3(64), 0, s, its, maxit, H, g, y);
     return hipGetLastError();
 }
 

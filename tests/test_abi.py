@@ -74,3 +74,18 @@ def test_options_outside_their_ranges_are_rejected_before_any_device_work(bad):
     h = ctypes.c_void_p()
     assert stmg.lib().stmg_create(ctypes.byref(p), ctypes.byref(o), None, ctypes.byref(h)) == stmg.STMG_EINVAL
     assert not h.value
+
+
+@pytest.mark.parametrize("dim,n,r", [(3, 128, 3), (3, 110, 3), (2, 20000, 3)])
+def test_meshes_beyond_32_bit_transfer_indices_are_rejected(dim, n, r):
+    """A mesh whose velocity nodes per component exceed 2^31 / 27 would
+    overflow the 32-bit CSR indices of the grid transfers: rejected with
+    STMG_EINVAL before any device work (footprint 0)."""
+    p, _ = stmg.make_problem(dim, (n,) * dim, r, 1, 1e-3, 1 / 64)
+    o = stmg.default_options()
+    assert stmg.footprint_bytes(p, o) == 0
+    h = ctypes.c_void_p()
+    assert stmg.lib().stmg_create(ctypes.byref(p), ctypes.byref(o), None, ctypes.byref(h)) == stmg.STMG_EINVAL
+    assert not h.value
+    ok, _ = stmg.make_problem(dim, (64,) * dim if dim == 3 else (1000,) * dim, r, 1, 1e-3, 1 / 64)
+    assert stmg.footprint_bytes(ok, o) > 0

@@ -239,6 +239,42 @@ def test_newton_matches_oracle(which, stmg):
     assert rel(u32, U_ref) < 1e-6
 
 
+_NEVER = dict(theta_N=1e9, theta_L=1e9, kappa_abs=1e9, stag_theta=2.0)
+TRIGGERS = {
+    "none": _NEVER,
+    "newton": {**_NEVER, "theta_N": 0.0},
+    "linear": {**_NEVER, "theta_L": 0.0, "kappa_abs": 1.0},
+    "stagnation": {**_NEVER, "stag_theta": 0.0, "stag_s": 1},
+    "tight_linesearch": {"c": 0.5, "window": 0},
+}
+
+
+@pytest.mark.parametrize("trigger", list(TRIGGERS))
+def test_newton_control_forced_matches_oracle(trigger, stmg):
+    """Each smoother rebuild criterion forced by its threshold (and a line
+    search made to backtrack): the library's Newton, FGMRES, rebuild and
+    backtrack counts equal the oracle's (FP64 multigrid)."""
+    kw = TRIGGERS[trigger]
+    prob, slab, rhs, vprev, maxl = _newton_case("c1_manufactured")
+    p = S.NewtonParams(**kw)
+    U_ref, st_ref = S.newton_solve(slab, S.Hierarchy(prob, max_levels=maxl), np.zeros(slab.N), rhs, vprev, p)
+    names = {"theta_N": "rb_theta_N", "theta_L": "rb_theta_L", "kappa_abs": "rb_kappa_abs",
+             "stag_theta": "rb_stag_theta", "stag_s": "rb_stag_s", "c": "ls_c", "window": "ls_window",
+             "lambda0": "ls_lambda0"}
+    ctx = stmg.Context(prob.dim, prob.n, prob.r, prob.k, prob.nu, prob.tau, prec_mg=stmg.STMG_F64, max_levels=maxl,
+                       **{names[a]: v for a, v in kw.items()})
+    ctx.set_slab_data(dev(rhs), dev(vprev))
+    u, st, rc = ctx.newton_solve(torch.zeros(slab.N, dtype=torch.float64, device="cuda"))
+    print(f"{trigger}: oracle newton {st_ref.newton_its} fgmres {st_ref.fgmres_its} rebuilds {st_ref.rebuilds} "
+          f"backtracks {st_ref.backtracks}; library {st.newton_its} {list(st.fgmres_its[:st.newton_its])} "
+          f"{st.rebuilds} {st.backtracks}")
+    assert rc == (0 if st_ref.converged else 1)
+    assert st.newton_its == st_ref.newton_its
+    assert list(st.fgmres_its[: st.newton_its]) == st_ref.fgmres_its
+    assert st.rebuilds == st_ref.rebuilds and st.backtracks == st_ref.backtracks
+    assert rel(u.cpu().numpy(), U_ref) < 1e-7
+
+
 DV_CASES = [CASES[0], CASES[1], CASES[4], CASES[7], CASES[8]]
 DV_IDS = [c[0] for c in DV_CASES]
 

@@ -222,12 +222,11 @@ def test_fgmres_exact_preconditioner_and_m_norm_residual():
 
 def test_armijo_quadratic_interpolation_exact():
     p = S.NewtonParams(window=0)
-    st = S.NewtonStats()
     # phi(a) = (a - 0.3)^2: phi0 = 0.09, g0 = -0.6; full step fails, the
     # quadratic model is exact, its minimizer 0.3 is inside [0.1, 0.5]
     phi = lambda a: (a - 0.3) ** 2
-    alpha, val = S.armijo(phi, 0.09, -0.6, [0.09], p, st)
-    assert abs(alpha - 0.3) < 1e-14 and st.backtracks == 1
+    alpha, val, nback = S.line_search(phi, 0.09, -0.6, S.MeritMemory(0.09, 0), p)
+    assert abs(alpha - 0.3) < 1e-14 and nback == 1
 
 
 def test_newton_c1_manufactured_converges():
