@@ -318,6 +318,21 @@ int stmg_march(stmg_ctx *ctx, int nslabs, const double *rhs, long long rhs_strid
 int stmg_batched_lu(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
                     const long long *p_off, int *info, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * factorization as stmg_batched_lu, with the device staging of the
+ * per-matrix sizes and offsets (32 bytes per matrix) in a fixed library
+ * array of STMG_NOALLOC_MAX_BATCH entries per device (2 MiB, held by every
+ * device the library runs on until the process ends) instead of a per-call
+ * allocation; it calls no hipMalloc or hipFree.  Returns STMG_EINVAL for
+ * batch > STMG_NOALLOC_MAX_BATCH.  All calls on one device share the array
+ * and every call overwrites it before use: calls that overlap on one device
+ * (other host threads, other streams) race and must be serialized by the
+ * caller.  The call synchronizes `stream` before it returns. */
+#define STMG_NOALLOC_MAX_BATCH 65536
+int stmg_batched_lu_noalloc(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
+                            const long long *p_off, int *info, void *stream);
+
 /* Solve with the factors of stmg_batched_lu: right-hand side b (device) of
  * matrix b at element offset b_off[b] (HOST array), overwritten by the
  * solution.  Same metadata as the factorization. */

@@ -1,4 +1,5 @@
 // extern "C" entry points of the stmg library.
+#include "lu_batch.h"
 #include "mg.h"
 
 #include <algorithm>
@@ -69,85 +70,6 @@ bool check_options(const stmg_options *o, std::string &why)
     }
     if (o->vanka_diagonal < 0 || o->vanka_diagonal > 2) { why = "vanka_diagonal must be 0, 1 or 2"; return false; }
     return true;
-}
-
-// batched LU (solve == false) or batched substitution (solve == true) of
-// matrices of mixed sizes; host metadata sorted by decreasing size
-int batched_lu_impl(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
-                    const long long *p_off, int *info, void *b, const long long *b_off, void *stream,
-                    bool solve = false)
-{
-    if (!A || !a_off || !m_of || !piv || !p_off || batch < 0) return STMG_EINVAL;
-    if (prec != STMG_F64 && prec != STMG_F32 && prec != STMG_F32_BF16 && prec != STMG_F32_F16) return STMG_EINVAL;
-    if (batch == 0) return STMG_OK;
-    // FP32 storage for the three FP32 variants; op = operands of the
-    // trailing-update MFMA
-    const int op = prec == STMG_F32_BF16 ? 1 : (prec == STMG_F32_F16 ? 2 : 0);
-    std::vector<int> ord(batch);
-    int maxm = 0;
-    for (int i = 0; i < batch; ++i) {
-        ord[i] = i;
-        if (m_of[i] < 1 || m_of[i] > 2048 || a_off[i] < 0 || p_off[i] < 0 || (solve && b_off[i] < 0))
-            return STMG_EINVAL;
-        maxm = std::max(maxm, m_of[i]);
-    }
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return m_of[x] > m_of[y]; });
-    std::vector<int> ms(batch);
-    std::vector<long long> ao(batch), po(batch), bo(solve ? batch : 0);
-    for (int i = 0; i < batch; ++i) {
-        ms[i] = m_of[ord[i]];
-        ao[i] = a_off[ord[i]];
-        po[i] = p_off[ord[i]];
-        if (solve) bo[i] = b_off[ord[i]];
-    }
-    hipStream_t s = (hipStream_t)stream;
-    try {
-        DevBuf dm(sizeof(int) * batch), da(sizeof(long long) * batch), dp(sizeof(long long) * batch);
-        DevBuf db(solve ? sizeof(long long) * batch : 0);
-        STMG_HIP(hipMemcpyAsync(dm.p, ms.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
-        STMG_HIP(hipMemcpyAsync(da.p, ao.data(), sizeof(long long) * batch, hipMemcpyHostToDevice, s));
-        STMG_HIP(hipMemcpyAsync(dp.p, po.data(), sizeof(long long) * batch, hipMemcpyHostToDevice, s));
-        if (solve) STMG_HIP(hipMemcpyAsync(db.p, bo.data(), sizeof(long long) * batch, hipMemcpyHostToDevice, s));
-        LuBatch vb{maxm, dm.as<int>(), da.as<long long>(), dp.as<long long>()};
-        hipError_t e;
-        if (solve) {
-            if (prec == STMG_F64)
-                e = launch_batched_solve<double>((const double *)A, piv, maxm, batch, vb, db.as<long long>(),
-                                                 (double *)b, s);
-            else
-                e = launch_batched_solve<float>((const float *)A, piv, maxm, batch, vb, db.as<long long>(),
-                                                (float *)b, s);
-        } else {
-            int dev = 0, lds = 65536;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-                lds = 65536;
-            const size_t max_lds = lds > 8192 ? (size_t)lds - 8192 : (size_t)lds;
-            // one launch per size class (consecutive sorted matrices within a
-            // factor 2 of the class's largest): each launch sizes its LDS panel
-            // for its own largest matrix, so small patches share a CU
-            e = hipSuccess;
-            for (int c0 = 0; c0 < batch && e == hipSuccess;) {
-                const int m0 = ms[c0];
-                int c1 = c0 + 1;
-                while (c1 < batch && 2 * ms[c1] > m0) ++c1;
-                LuBatch vc{m0, dm.as<int>() + c0, da.as<long long>() + c0, dp.as<long long>() + c0};
-                if (prec == STMG_F64) e = launch_lu<double>((double *)A, piv, m0, c1 - c0, info, max_lds, s, &vc);
-                else e = launch_lu<float>((float *)A, piv, m0, c1 - c0, info, max_lds, s, &vc, op);
-                c0 = c1;
-            }
-        }
-        if (e == hipErrorInvalidConfiguration) {
-            (void)hipStreamSynchronize(s);
-            return STMG_EINVAL;
-        }
-        STMG_HIP(e);
-        STMG_HIP(hipStreamSynchronize(s));
-    } catch (const HipError &e) {
-        (void)hipStreamSynchronize(s);
-        return e.code;
-    }
-    return STMG_OK;
 }
 
 } // namespace
@@ -483,15 +405,23 @@ int stmg_level_patch(stmg_ctx *ctx, int level, int cell, int prec, void *out)
 int stmg_batched_lu(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
                     const long long *p_off, int *info, void *stream)
 {
-    return batched_lu_impl(prec, A, a_off, m_of, batch, piv, p_off, info, nullptr, nullptr, stream, false);
+    return batched_lu_run(prec, A, a_off, m_of, batch, piv, p_off, info, nullptr, nullptr, stream, false,
+                          MetaStaging::PerCall);
+}
+
+int stmg_batched_lu_noalloc(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
+                            const long long *p_off, int *info, void *stream)
+{
+    return batched_lu_run(prec, A, a_off, m_of, batch, piv, p_off, info, nullptr, nullptr, stream, false,
+                          MetaStaging::Fixed);
 }
 
 int stmg_batched_lu_solve(int prec, const void *LU, const long long *a_off, const int *m_of, int batch,
                           const int *piv, const long long *p_off, void *b, const long long *b_off, void *stream)
 {
     if (!b || !b_off) return STMG_EINVAL;
-    return batched_lu_impl(prec, const_cast<void *>(LU), a_off, m_of, batch, const_cast<int *>(piv), p_off, nullptr,
-                           b, b_off, stream, true);
+    return batched_lu_run(prec, const_cast<void *>(LU), a_off, m_of, batch, const_cast<int *>(piv), p_off, nullptr,
+                          b, b_off, stream, true, MetaStaging::PerCall);
 }
 
 int stmg_level_jacobian_vmult(stmg_ctx *ctx, int level, int prec, const void *x, void *y)

@@ -112,6 +112,9 @@ _SIGS = {
     "stmg_level_patch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "stmg_batched_lu": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_batched_lu_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
     "stmg_batched_lu_solve": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p]),
@@ -172,11 +175,16 @@ def _host_i64(a):
     return np.ascontiguousarray(a, dtype=np.int64)
 
 
-def batched_lu(A, a_off, m_of, piv, p_off, info=None, prec=None):
+STMG_NOALLOC_MAX_BATCH = 65536
+
+
+def batched_lu(A, a_off, m_of, piv, p_off, info=None, prec=None, noalloc=False):
     """Factor a batch of row-major matrices of mixed sizes in place (device
     tensors A (float64/float32) and piv (int32); host offsets and sizes).
     prec: None (from the dtype of A), or STMG_F32_BF16 / STMG_F32_F16 for
-    float32 A with 16-bit operands in the trailing-update MFMA."""
+    float32 A with 16-bit operands in the trailing-update MFMA.  noalloc:
+    call stmg_batched_lu_noalloc (metadata staged in the library's fixed
+    per-device array, batch <= STMG_NOALLOC_MAX_BATCH)."""
     import numpy as np
     ao, po = _host_i64(a_off), _host_i64(p_off)
     mo = np.ascontiguousarray(m_of, dtype=np.int32)
@@ -184,10 +192,11 @@ def batched_lu(A, a_off, m_of, piv, p_off, info=None, prec=None):
         prec = STMG_F64 if A.dtype == torch.float64 else STMG_F32
     elif (prec == STMG_F64) != (A.dtype == torch.float64):
         raise StmgError("prec does not match the dtype of A")
-    rc = lib().stmg_batched_lu(prec, _ptr(A), ao.ctypes.data, mo.ctypes.data, len(mo), _ptr(piv), po.ctypes.data,
-                               _ptr(info) if info is not None else None, _stream_ptr())
+    f = lib().stmg_batched_lu_noalloc if noalloc else lib().stmg_batched_lu
+    rc = f(prec, _ptr(A), ao.ctypes.data, mo.ctypes.data, len(mo), _ptr(piv), po.ctypes.data,
+           _ptr(info) if info is not None else None, _stream_ptr())
     if rc != 0:
-        raise StmgError(f"stmg_batched_lu failed ({rc})")
+        raise StmgError(f"stmg_batched_lu{'_noalloc' if noalloc else ''} failed ({rc})")
 
 
 def batched_lu_solve(LU, a_off, m_of, piv, p_off, b, b_off):
