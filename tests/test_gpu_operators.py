@@ -155,3 +155,25 @@ def test_full_size_sampled_rows(which, stmg):
     assert np.max(np.abs(got32[rows] - want)) / scale < TOL32
     # FP32 against FP64 over the whole vector
     assert np.max(np.abs(got32 - got)) / scale < TOL32
+
+
+def test_full_c2_vmult_whole_vector(stmg):
+    """The 16^3 Q3/P2disc x DG(2) vmult benchmark workload (smooth
+    divergence-free state, nu = 1e-2, tau = 1/32) over the WHOLE slab vector
+    (1,181,721 entries, every cell, node and time node) against the oracle's
+    element-by-element action: FP64 <= 1e-12, FP32 <= 1e-5 relative, in the
+    launch configuration the benchmark times."""
+    import time
+    d, n, r, k, nu, tau = 3, (16, 16, 16), 2, 2, 1e-2, 1 / 32
+    U = I.slab_state(d, n, r, k, 3, kind="smooth")
+    slab = oracle.Slab(oracle.Problem(dim=d, n=n, r=r, k=k, nu=nu, tau=tau))
+    X = I.uniform(slab.N, 2)
+    t0 = time.time()
+    want = slab.vmult(U, X)
+    print(f"oracle element action over {slab.N} rows: {time.time() - t0:.1f} s", flush=True)
+    ctx = stmg.Context(d, n, r, k, nu, tau)
+    Ud, Xd = dev(U), dev(X)
+    got = ctx.jacobian_vmult(Ud, Xd).cpu().numpy()
+    assert rel(got, want) < TOL64
+    got32 = ctx.jacobian_vmult(Ud.float(), Xd.float()).double().cpu().numpy()
+    assert rel(got32, want) < TOL32

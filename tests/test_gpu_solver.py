@@ -516,3 +516,43 @@ def test_serving_rejects_oversized_request(stmg):
     reqs = _serving_mix()[:2]
     with pytest.raises(stmg.StmgError):
         stmg.serve(reqs, stmg.default_options(), slots=2, hbm_budget=1 << 20)
+
+
+def _pressure_fixed(slab, U):
+    """U with the constant pressure of each time node removed (the mean over
+    cells of the mode-0 coefficient), the part of the solution that Gamma_D =
+    the whole boundary leaves undetermined."""
+    U = np.array(U, dtype=float)
+    npm = slab.space.npm
+    for a in range(slab.nt):
+        base = slab.nt * slab.Nv + a * slab.Np
+        p0 = U[base: base + slab.Np: npm]
+        U[base: base + slab.Np: npm] = p0 - p0.mean()
+    return U
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_served_results_match_oracle(prec, stmg):
+    """Every request of the serving mix, served concurrently, against the
+    oracle's Newton-FGMRES-hp-STMG solve of the same request: with the
+    multigrid in FP64 identical Newton and FGMRES counts and the solution to
+    1e-7; with the default FP32 multigrid the solution to 1e-6 (both up to
+    the constant pressure of each time node)."""
+    reqs = _serving_mix()
+    p = stmg.STMG_F64 if prec == "f64" else stmg.STMG_F32
+    served, res, _ = stmg.serve(reqs, stmg.default_options(prec_mg=p), slots=4, hbm_budget=0)
+    for i, q in enumerate(reqs):
+        prob = oracle.Problem(dim=q["dim"], n=q["n"], r=q["r"], k=q["k"], nu=q["nu"], tau=q["tau"])
+        slab = oracle.Slab(prob)
+        U_ref, st_ref = S.newton_solve(slab, S.Hierarchy(prob), np.zeros(slab.N), None, q["v_prev"])
+        assert st_ref.converged and res[i].rc == 0
+        err = rel(_pressure_fixed(slab, served[i]), _pressure_fixed(slab, U_ref))
+        print(f"request {i} ({q['dim']}D n={q['n']} r={q['r']} k={q['k']}): oracle newton {st_ref.newton_its} "
+              f"fgmres {st_ref.fgmres_its}, served {res[i].stats.newton_its} "
+              f"{list(res[i].stats.fgmres_its[:res[i].stats.newton_its])}, rel err {err:.1e}")
+        if prec == "f64":
+            assert res[i].stats.newton_its == st_ref.newton_its
+            assert list(res[i].stats.fgmres_its[: st_ref.newton_its]) == st_ref.fgmres_its
+            assert err < 1e-7
+        else:
+            assert err < 1e-6
