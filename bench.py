@@ -30,10 +30,35 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 78.6e12      # 256 CU * 4 SIMD * 16 FP64 lanes/clk * 2 flop * 2.4 GHz
 PEAK_HBM = 8.0e12
-# HBM bytes per launch of the FP64 Jacobian volume kernel on this workload:
-# rocprofv3 --pmc FETCH_SIZE (x2, the factor a 1 GiB device copy shows) plus
-# WRITE_SIZE (x1); profiles/cell_kernel_jac_16cube_r2k2.md
-CELL_KERNEL_TRAFFIC_BYTES = int((2 * 10057.75 + 19392.75) * 1024)
+# HBM bytes per launch of the FP64 Jacobian volume kernel on this workload come
+# from the rocprofv3 counter summary below (FETCH_SIZE x2, the factor a 1 GiB
+# device copy shows, plus WRITE_SIZE x1); they count only while the kernel
+# source still has the hash the counters were taken with.
+COUNTERS = os.path.join(ROOT, "profiles", "cell_kernel_jac_16cube_r2k2.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2602_13841_amd", "csrc", "cell_ops.hip")
+
+
+def source_sha(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def counter_traffic():
+    """(bytes per launch, date) from the committed counter summary when its
+    recorded source hash matches the current kernel source, else (None, why)."""
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None, "no counter summary"
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            key, v = line[2:].split(": ", 1)
+            vals[key.strip()] = v.strip()
+    if vals.get("source_sha") != source_sha(KERNEL_SOURCE):
+        return None, "kernel changed since the counters were taken"
+    return int(vals["traffic_bytes_per_launch"]), vals.get("date", "")
 
 WORKLOAD = dict(dim=3, n=(16, 16, 16), r=2, k=2, nu=1e-2, tau=1.0 / 32)
 
@@ -62,9 +87,59 @@ def vmult_flops(dim, n, r, k, nq):
     return ncell * nt * (mix + fwd + coll + qp + bwd)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_solve_c1():
+    """The oracle's Newton-FGMRES-hp-STMG solve of the 2D 4x4 Q2/P1disc x DG(1)
+    slab (tau = 0.1, nu = 1, manufactured forcing, 2 levels) on the host:
+    solve time and the paper's throughput measure theta = N / W."""
+    import oracle
+    from oracle import manufactured as MS
+    from oracle import solver as S
+    prob = oracle.Problem(dim=2, n=(4, 4), r=1, k=1, nu=1.0, tau=0.1)
+    slab = oracle.Slab(prob)
+    rhs = MS.slab_rhs(slab, 0.0)
+    t0 = time.perf_counter()
+    _, st = S.newton_solve(slab, S.Hierarchy(prob, max_levels=2), np.zeros(slab.N), rhs, np.zeros(slab.Nv))
+    dt = time.perf_counter() - t0
+    return {"N": slab.N, "wall_s": dt, "theta_dof_per_s": slab.N / dt, "newton": st.newton_its,
+            "fgmres": st.fgmres_its}
+
+
+def cpu_lu_sample(seconds=6.0, seed=6):
+    """FP64 LU with partial pivoting (the oracle's patch factorization routine,
+    scipy.linalg.lu_factor) of seeded dense matrices with the sizes of the
+    mixed patch batch, on the host, for about `seconds`: GFLOP/s (2/3 m^3)."""
+    import scipy.linalg as sla
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = [(k + 1) * (3 * (r + 2) ** 3 + {1: 4, 2: 10, 3: 20}[r]) for r, k in
+             zip(rng.integers(1, 4, 4096), rng.integers(0, 3, 4096))]
+    flops, done, t0 = 0.0, 0, time.perf_counter()
+    for m in sizes:
+        A = rng.uniform(-1, 1, (m, m)) + 0.5 * np.sqrt(m) * np.eye(m)
+        sla.lu_factor(A, overwrite_a=True, check_finite=False)
+        flops += 2.0 / 3.0 * m ** 3
+        done += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"matrices": done, "gflops": flops / dt / 1e9, "wall_s": dt,
+            "patches_per_s_scaled_to_4096": done / dt}
+
+
 def cpu_baseline(U, X, seconds=12.0):
     """The oracle's element-by-element Jacobian action on a bounded sample of
-    cells of the same workload, timed on the host cores; scaled to DoF/s."""
+    cells of the same workload, timed on the host cores; scaled to DoF/s.
+    Beside it: the CPU model, the oracle's slab solve of the 2D 4x4 problem
+    and FP64 LU of a sample of the mixed patch sizes."""
     import oracle
     w = WORKLOAD
     prob = oracle.Problem(dim=w["dim"], n=w["n"], r=w["r"], k=w["k"], nu=w["nu"], tau=w["tau"])
@@ -88,7 +163,8 @@ def cpu_baseline(U, X, seconds=12.0):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": slab.N * frac / dt, "unit": "DoF/s", "cores": threads, "kind": "oracle",
             "sample": f"{done_cells} cells x {slab.nt} time nodes of the 16^3 workload "
-                      f"({100 * frac:.1f}% of one vmult), element-matrix action, {dt:.1f} s"}
+                      f"({100 * frac:.1f}% of one vmult), element-matrix action, {dt:.1f} s",
+            "cpu_model": cpu_model(), "solve_2d_4x4": cpu_solve_c1(), "lu_fp64_patch_sizes": cpu_lu_sample()}
 
 
 SOLVE_WORKLOAD = dict(dim=3, n=(32, 32, 32), r=3, k=1, nu=1e-3, tau=1.0 / 64, perturb=0.2, vert_seed=4, v0_seed=5)
@@ -146,7 +222,10 @@ def bench_batched_lu(npatch=4096, seed=6):
     precision (FP64; FP32 with FP32, BF16 or FP16 operands of the
     trailing-update MFMA, FP32 accumulation), then the triangular solves;
     accuracy as the sampled normwise backward error and the relative
-    distance of the solutions to the FP64 ones."""
+    distance of the solutions to the FP64 ones.  Each factorization is timed
+    as one persistent launch with the tuned table and, as the untuned
+    reference, as one launch per size class.  (The patches come from the
+    library: only the cpu_baseline leg runs the oracle.)"""
     import torch
     from paper_2602_13841_amd import inputs as I
     from paper_2602_13841_amd import stmg
@@ -187,6 +266,16 @@ def bench_batched_lu(npatch=4096, seed=6):
         A = A64.to(dt, copy=True)   # A64 stays the unfactored reference
         piv = torch.zeros(int(sizes.sum()), dtype=torch.int32, device="cuda")
         info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        # untuned reference: one launch per size class
+        torch.cuda.synchronize()
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0.record()
+        stmg.batched_lu(A, a_off, sizes, piv, p_off, info, prec=prec, config=(0, None))
+        r1.record()
+        torch.cuda.synchronize()
+        t_ref = r0.elapsed_time(r1) * 1e-3
+        A.copy_(A64.to(dt))
+        info.zero_()
         torch.cuda.synchronize()
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record()
@@ -211,7 +300,8 @@ def bench_batched_lu(npatch=4096, seed=6):
         rel = [float(np.linalg.norm(x[p_off[i]: p_off[i] + sizes[i]] - x64[p_off[i]: p_off[i] + sizes[i]]) /
                      np.linalg.norm(x64[p_off[i]: p_off[i] + sizes[i]])) for i in range(npatch)]
         out[name] = {"lu_s": t_lu, "patches_per_s": npatch / t_lu, "tflops": flops / t_lu / 1e12,
-                     "frac_of_peak": flops / t_lu / peak, "solve_s": t_sv, "zero_pivots": int(info.item()),
+                     "frac_of_peak": flops / t_lu / peak, "one_launch_per_size_class_s": t_ref,
+                     "tuned_speedup": t_ref / t_lu, "solve_s": t_sv, "zero_pivots": int(info.item()),
                      "backward_error_sample_max": worst, "rel_err_vs_fp64_median": float(np.median(rel)),
                      "rel_err_vs_fp64_max": float(np.max(rel))}
         del A, piv, b
@@ -245,6 +335,27 @@ def bench_serve(nreq, slots):
     _, res2, wall2 = stmg.serve(reqs, o, slots=slots, hbm_budget=budget)
     lat = np.array([x.latency_s for x in res2])
     ok = sum(1 for x in res + res2 if x.rc == 0)
+    # how often a request shares the device with another of the same
+    # discretization (the only case where merging cell-kernel launches across
+    # requests could apply): fraction of in-slot time with such a partner
+    def same_shape_overlap(rs):
+        key = [(q["dim"], tuple(q["n"]), q["r"], q["k"]) for q in reqs]
+        tot = shared = 0.0
+        for i, x in enumerate(rs):
+            tot += x.end_s - x.start_s
+            iv = sorted((max(x.start_s, y.start_s), min(x.end_s, y.end_s)) for j, y in enumerate(rs)
+                        if j != i and key[j] == key[i] and min(x.end_s, y.end_s) > max(x.start_s, y.start_s))
+            cur = None
+            for a, b in iv:
+                if cur is None or a > cur[1]:
+                    if cur:
+                        shared += cur[1] - cur[0]
+                    cur = [a, b]
+                else:
+                    cur[1] = max(cur[1], b)
+            if cur:
+                shared += cur[1] - cur[0]
+        return shared / max(tot, 1e-30)
     classes, sizes = {}, {}
     for q, x in zip(reqs, res2):
         classes.setdefault(f"{q['dim']}D", []).append(x.latency_s)
@@ -256,7 +367,10 @@ def bench_serve(nreq, slots):
             "p99_by_dim": {k: float(np.percentile(v, 99)) for k, v in classes.items()},
             "p50_p99_by_size": {k: [float(np.percentile(v, 50)), float(np.percentile(v, 99)), len(v)]
                                 for k, v in sorted(sizes.items())},
-            "converged": ok, "runs": 2 * nreq}
+            "converged": ok, "runs": 2 * nreq,
+            "shapes": len({(q["dim"], tuple(q["n"]), q["r"], q["k"]) for q in reqs}),
+            "pooled_context_reuse": [sum(x.reused_context for x in res), sum(x.reused_context for x in res2)],
+            "same_shape_overlap_fraction": [same_shape_overlap(res), same_shape_overlap(res2)]}
 
 
 def main():
@@ -298,7 +412,7 @@ def main():
     U = I.slab_state(w["dim"], w["n"], w["r"], w["k"], 3, kind="smooth")
     X = I.uniform(N, 2)
 
-    def run(dtype, steps, warmup):
+    def run(dtype, steps, warmup, ctx=ctx):
         per_set = 3 * N * (8 if dtype == torch.float64 else 4)
         nsets = max(2, int(np.ceil(args.rotate_bytes / per_set)))
         Us = [torch.tensor(U, dtype=dtype, device=dev) for _ in range(nsets)]
@@ -329,19 +443,59 @@ def main():
         face_ms, face_n = ctx.timing_get("face_jac_" + suffix)
         gat_ms, gat_n = ctx.timing_get("gather_" + suffix)
         ctx.timing_reset()
+        # pass 3: at least 100 applications timed one by one (events on the
+        # current stream, which the library launches on): median and spread
+        nper = max(steps, 100)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nper)]
+        torch.cuda.synchronize()
+        for i in range(nper):
+            j = i % nsets
+            evs[i][0].record()
+            ctx.jacobian_vmult(Us[j], Xs[j], Ys[j])
+            evs[i][1].record()
+        torch.cuda.synchronize()
+        per = np.array([a.elapsed_time(b) for a, b in evs])
         del Us, Xs, Ys
         torch.cuda.empty_cache()
+        stats = {"timed_one_by_one": nper, "median_ms": float(np.median(per)), "p10_ms": float(np.percentile(per, 10)),
+                 "p90_ms": float(np.percentile(per, 90))}
         return ((t1 - t0) / steps, cell_ms / max(cell_n, 1), face_ms / max(face_n, 1), gat_ms / max(gat_n, 1),
-                nsets)
+                nsets, stats)
 
-    t64, cell64, face64, gat64, nsets64 = run(torch.float64, args.steps, args.warmup)
-    t32, cell32, face32, gat32, nsets32 = run(torch.float32, args.steps, args.warmup)
+    # device copy of 1 GiB each way: the HBM rate a plain copy reaches here
+    src_ = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst_ = torch.empty_like(src_)
+    for _ in range(2):
+        dst_.copy_(src_)
+    ce = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    torch.cuda.synchronize()
+    for a, b in ce:
+        a.record()
+        dst_.copy_(src_)
+        b.record()
+    torch.cuda.synchronize()
+    copy_s = min(a.elapsed_time(b) for a, b in ce) * 1e-3
+    copy_gbs = 2 * src_.numel() * 8 / copy_s / 1e9
+    del src_, dst_
+    torch.cuda.empty_cache()
 
+    t64, cell64, face64, gat64, nsets64, per64 = run(torch.float64, args.steps, args.warmup)
+    t32, cell32, face32, gat32, nsets32, per32 = run(torch.float32, args.steps, args.warmup)
     del ctx
     torch.cuda.empty_cache()
+    # the same workload with the cheaper spatial quadrature n_q = r + 2
+    nq_p = w["r"] + 2
+    ctxp = stmg.Context(w["dim"], w["n"], w["r"], w["k"], w["nu"], w["tau"], n_q=nq_p)
+    tp64, cellp64, facep64, gatp64, _, perp64 = run(torch.float64, args.steps, args.warmup, ctxp)
+    tp32, cellp32, facep32, gatp32, _, perp32 = run(torch.float32, args.steps, args.warmup, ctxp)
+    del ctxp
+    torch.cuda.empty_cache()
+
     flops = vmult_flops(w["dim"], w["n"], w["r"], w["k"], nq)
+    flops_p = vmult_flops(w["dim"], w["n"], w["r"], w["k"], nq_p)
     bytes64 = (2 * N + Nv) * 8
     achieved = flops / (cell64 * 1e-3)
+    traffic, traffic_note = counter_traffic()
     out = {
         "metric": "space-time DoF/s Jacobian vmult FP64 vs FP32; slab solves/s; p50/p99 latency",
         "value": N / t64,
@@ -359,14 +513,24 @@ def main():
                                "tau=1/32, smooth divergence-free Fourier state",
                    "N": N, "n_q": nq, "rotating_sets": nsets64},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": CELL_KERNEL_TRAFFIC_BYTES,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
+                     "traffic_source": traffic_note,
                      "kernel": "cell_kernel<3,2,5,Jac,f64> (volume terms)", "flops_per_launch": flops,
                      "kernel_ms": cell64},
         "roofline_hbm": {"achieved": bytes64 / ((cell64 + face64 + gat64) * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
                          "unit": "GB/s", "frac": bytes64 / ((cell64 + face64 + gat64) * 1e-3) / PEAK_HBM,
-                         "algorithmic_bytes": bytes64, "cell_ms": cell64, "face_ms": face64, "gather_ms": gat64},
+                         "algorithmic_bytes": bytes64, "cell_ms": cell64, "face_ms": face64, "gather_ms": gat64,
+                         "device_copy_GBps": copy_gbs, "frac_of_device_copy": bytes64 / (t64 * copy_gbs * 1e9)},
+        "per_application_fp64": per64,
         "fp32": {"value": N / t32, "unit": "DoF/s", "ms_per_step": t32 * 1e3, "cell_ms": cell32,
-                 "face_ms": face32, "gather_ms": gat32, "speedup_vs_fp64": t64 / t32},
+                 "face_ms": face32, "gather_ms": gat32, "speedup_vs_fp64": t64 / t32, "per_application": per32},
+        "nq_r_plus_2": {"n_q": nq_p, "fp64": {"value": N / tp64, "ms_per_step": tp64 * 1e3, "cell_ms": cellp64,
+                                               "face_ms": facep64, "gather_ms": gatp64, "per_application": perp64,
+                                               "alu_frac": flops_p / (cellp64 * 1e-3) / PEAK_FP64_VALU,
+                                               "hbm_frac": bytes64 / (tp64 * PEAK_HBM)},
+                        "fp32": {"value": N / tp32, "ms_per_step": tp32 * 1e3, "cell_ms": cellp32,
+                                 "face_ms": facep32, "gather_ms": gatp32, "per_application": perp32,
+                                 "hbm_frac": bytes64 / 2 / (tp32 * PEAK_HBM)}},
     }
     if not args.no_solve:
         print("[bench] slab solve, FP32 multigrid", file=sys.stderr, flush=True)

@@ -17,9 +17,14 @@
  *
  * Memory: every vector argument is a DEVICE pointer owned by the caller
  * (e.g. a torch tensor); the library never frees it.  FP64 arguments are
- * double*, FP32 arguments float* (selected by a stmg_prec argument).  The
- * library allocates its own device workspace when the context is created
- * (query it with stmg_footprint_bytes) and frees it in stmg_destroy.
+ * double*, FP32 arguments float* (selected by a stmg_prec argument).  All
+ * device memory of a context (level tables, transfer matrices, operator
+ * work buffers, smoother factors, coarse-level matrices, Krylov bases, the
+ * staging of the captured V-cycle, slab data) is laid out once, when the
+ * context is created, in one block of exactly stmg_footprint_bytes bytes:
+ * the caller's workspace (e.g. a torch tensor, so that the caller's
+ * allocator is the only one) or one library allocation; nothing is
+ * allocated afterwards.
  *
  * Streams: all work of a context is enqueued on the hipStream_t given at
  * creation (NULL = the default stream).  Calls that return scalars or
@@ -156,20 +161,38 @@ typedef struct {
 
 void stmg_default_options(stmg_options *opt);
 
-/* Device bytes the library allocates for a problem (workspace of all levels,
- * patch factors, Krylov bases); 0 for an invalid problem or options (see
- * stmg_create). */
+/* Device bytes a context of this problem and these options consumes: the
+ * exact size of its workspace, measured by running the context's own
+ * construction code without device memory (host only, no GPU needed); 0 for
+ * an invalid problem or options (see stmg_create). */
 size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt);
 
-/* Create a context on the current HIP device.  stream: hipStream_t or NULL.
- * Returns STMG_EINVAL, before any device work, for unsupported (dim, r, k,
- * n_q) combinations and for options outside their documented ranges
- * (prec_mg other than STMG_F64/STMG_F32, a negative count, a flag other than
- * 0/1, vanka_diagonal other than 0/1/2); with the environment variable
- * STMG_VERBOSE set the reason is printed on stderr. */
-int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_ctx **out);
+/* Create a context on the current HIP device.  workspace: DEVICE pointer to
+ * ws_bytes >= stmg_footprint_bytes bytes, 256-byte aligned, owned by the
+ * caller and used by the context until stmg_destroy (the library then calls
+ * no device allocator for this context); NULL = the library allocates one
+ * block of the footprint itself and frees it in stmg_destroy.  stream:
+ * hipStream_t or NULL.  Returns STMG_EINVAL, before any device work, for
+ * unsupported (dim, r, k, n_q) combinations, options outside their
+ * documented ranges (prec_mg other than STMG_F64/STMG_F32, a negative count,
+ * a flag other than 0/1, vanka_diagonal other than 0/1/2) or a misaligned
+ * workspace, STMG_ENOMEM for a workspace smaller than the footprint; with the
+ * environment variable STMG_VERBOSE set the reason is printed on stderr. */
+int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *workspace, size_t ws_bytes, void *stream,
+                stmg_ctx **out);
+/* Bytes of the workspace the context has laid out (equal to
+ * stmg_footprint_bytes of its problem and options, up to the final 256-byte
+ * rounding). */
+size_t stmg_workspace_used(const stmg_ctx *ctx);
 int stmg_destroy(stmg_ctx *ctx);
 const char *stmg_last_error(const stmg_ctx *ctx);
+
+/* New viscosity nu and slab length tau for an existing context (same mesh,
+ * degrees, boundary data and options): the time matrices of every level are
+ * recomputed; the state, smoother and captured V-cycle are invalidated (the
+ * next stmg_set_state / stmg_smoother_rebuild / Newton solve sets them up
+ * again); slab data stay.  Synchronizes the context stream. */
+int stmg_set_coefficients(stmg_ctx *ctx, double nu, double tau);
 
 /* Sizes of the slab vectors: total N, velocity part (k+1)Nv1, pressure part. */
 int stmg_sizes(const stmg_ctx *ctx, long long *n_total, long long *n_velocity, long long *n_pressure);
@@ -195,7 +218,8 @@ int stmg_residual(stmg_ctx *ctx, const double *u, double *r);
 int stmg_jacobian_vmult(stmg_ctx *ctx, int prec, const void *u_state, const void *x, void *y);
 
 /* Batched form: nvec vectors stored contiguously with stride N (x, y) and
- * the same state for all. */
+ * the same state for all (applied one vector per launch on the finest
+ * level: the work buffers are laid out for one). */
 int stmg_jacobian_vmult_batched(stmg_ctx *ctx, int prec, const void *u_state, const void *x, void *y, int nvec);
 
 /* y = blockdiag(M^tau (x) M_h, M^tau (x) M_h^p) x: the weight of the norm
@@ -263,7 +287,8 @@ int stmg_restrict(stmg_ctx *ctx, int level, int prec, const void *xf, void *yc);
 /* Right-preconditioned flexible GMRES on J(u_state) x = b (FP64, zero
  * initial guess, Arnoldi in the M inner product, preconditioner = one
  * V-cycle), stopped when the M-norm residual estimate is <= rtol ||b||_M or
- * after maxit iterations.  its: iterations; hist: its+1 residual estimates
+ * after maxit iterations (maxit <= opt.fgmres_maxit, the size of the Krylov
+ * workspace; STMG_EINVAL otherwise).  its: iterations; hist: its+1 residual estimates
  * (host array, may be NULL).  Needs a built smoother.  Returns
  * STMG_NOT_CONVERGED at the iteration limit. */
 int stmg_fgmres(stmg_ctx *ctx, const double *u_state, const double *b, double *x, double rtol, int maxit, int *its,
@@ -299,24 +324,40 @@ int stmg_march(stmg_ctx *ctx, int nslabs, const double *rhs, long long rhs_strid
 
 /* ---- batched patch factorizations (no context) ---------------------------
  * A batch of dense matrices of mixed sizes, factored by LU with partial
- * pivoting, one launch per size class (matrices within a factor 2 of the
- * class's largest share a launch) (the Vanka patch factorization of Sec. "Inexact
- * space-time Vanka smoother" as a standalone batch; the trailing updates run
- * on MFMA in FP32).  prec: STMG_F64, STMG_F32, or STMG_F32_BF16 /
- * STMG_F32_F16 (FP32 matrices and factors; the L21 and U12 blocks of each
- * trailing update A22 -= L21 U12 are rounded to BF16 / FP16 for the MFMA,
- * A22 accumulates in FP32; the solve is the FP32 one).  Matrix b is m_of[b] x
- * m_of[b], row-major, at element offset a_off[b] of the device array A and
- * is overwritten by its factors (unit lower L below the diagonal, U on and
- * above); piv + p_off[b] receives m_of[b] 0-based row interchanges
- * (row j was swapped with row piv[j], applied in order j = 0, 1, ...).
- * m_of, a_off, p_off are HOST arrays of `batch` entries; A and piv are
- * device arrays owned by the caller; info (device, may be NULL) is
- * incremented for every exactly zero pivot.  stream: a hipStream_t or NULL.
- * Larger matrices are scheduled first.  Returns 0, STMG_EINVAL (bad sizes,
- * m > 2048) or STMG_EHIP. */
+ * pivoting (the Vanka patch factorization of Sec. "Inexact space-time Vanka
+ * smoother" as a standalone batch) in ONE persistent launch: a grid of
+ * workgroups sized to stay resident takes the matrices, largest first, from a
+ * device work queue; each matrix is factored by one workgroup with blocked
+ * right-looking panels in LDS and the trailing updates on MFMA
+ * (v_mfma_f32_16x16x4f32 in FP32, v_mfma_f64_16x16x4f64 in FP64).  The
+ * workgroups per CU and the panel width of each size class come from a table
+ * written by the package's tuner (paper_2602_13841_amd/tune_lu.py).  prec:
+ * STMG_F64, STMG_F32, or STMG_F32_BF16 / STMG_F32_F16 (FP32 matrices and
+ * factors; the L21 and U12 blocks of each trailing update A22 -= L21 U12 are
+ * rounded to BF16 / FP16 for the MFMA, A22 accumulates in FP32; the solve is
+ * the FP32 one).  Matrix b is m_of[b] x m_of[b], row-major, at element offset
+ * a_off[b] of the device array A and is overwritten by its factors (unit
+ * lower L below the diagonal, U on and above); piv + p_off[b] receives
+ * m_of[b] 0-based row interchanges (row j was swapped with row piv[j],
+ * applied in order j = 0, 1, ...).  m_of, a_off, p_off are HOST arrays of
+ * `batch` entries; A and piv are device arrays owned by the caller; info
+ * (device, may be NULL) is incremented for every exactly zero pivot.
+ * stream: a hipStream_t or NULL; the call synchronizes it.  Returns 0,
+ * STMG_EINVAL (bad sizes, m > 2048), STMG_ENOMEM or STMG_EHIP. */
 int stmg_batched_lu(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
                     const long long *p_off, int *info, void *stream);
+
+/* Tuning form of stmg_batched_lu (used by the tuner): explicit launch
+ * parameters instead of the table.  wg_per_cu in 1..4 sets the LDS budget of
+ * the persistent launch (160 KiB / wg_per_cu per workgroup); nb_by_class[c]
+ * in {4, 8, 16} is the panel width for matrices of size <= 128, 256, 512,
+ * 1024, 2048 (c = 0..4), halved while the panel does not fit the budget.
+ * wg_per_cu = 0: one launch per size class instead (no work queue), the
+ * untuned reference.  threads (256 or 512): the workgroup that factors one
+ * matrix (4 or 8 wavefronts).  Other arguments as in stmg_batched_lu. */
+int stmg_batched_lu_config(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
+                           const long long *p_off, int *info, int wg_per_cu, int threads, const int *nb_by_class,
+                           void *stream);
 
 /* For callers that cannot allocate device memory (code under stream
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
@@ -360,15 +401,22 @@ typedef struct {
     int rc;                   /* return code of the solve */
     size_t footprint;         /* device bytes reserved for the request */
     stmg_stats stats;
+    int reused_context;       /* 1: served by a pooled context of an earlier request */
 } stmg_request_result;
 
-/* Serve n requests with `slots` concurrent solves on the current device:
- * FIFO in arrival order, a request is admitted when it has arrived, a slot
- * is free and its footprint (stmg_footprint_bytes) fits in hbm_budget bytes
- * (0 = no budget).  Every admitted request runs on its own stream and
- * context, so the work of overlapping requests overlaps on the device.
- * wall_s: total time (may be NULL).  Returns 0, or the last negative
- * request code; STMG_ENOMEM if a single request exceeds the budget. */
+/* Serve n requests with `slots` concurrent solves on the current device
+ * (continuous batching).  When a slot is free, the earliest arrived request
+ * that fits is admitted (first fit in arrival order): it fits when an idle
+ * context of the same discretization (everything but nu and tau) is pooled,
+ * or when its footprint (stmg_footprint_bytes) next to the running requests
+ * stays within hbm_budget bytes (0 = 85 % of the device memory free at the
+ * start), idle pooled contexts being destroyed for it.  Every admitted
+ * request runs on its own stream and context, so the work of overlapping
+ * requests overlaps on the device; finished contexts return to the pool and
+ * are reused (stmg_set_coefficients) by later requests of the same shape.
+ * Request vectors are staged in per-slot device buffers sized for the largest
+ * request.  wall_s: total time (may be NULL).  Returns 0, or the last
+ * negative request code; STMG_ENOMEM if a single request exceeds the budget. */
 int stmg_serve(const stmg_request *reqs, int n, const stmg_options *opt, int slots, size_t hbm_budget,
                stmg_request_result *res, double *wall_s);
 

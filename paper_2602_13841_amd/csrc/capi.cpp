@@ -1,9 +1,11 @@
 // extern "C" entry points of the stmg library.
 #include "lu_batch.h"
+#include "lu_tuning.h"
 #include "mg.h"
 
 #include <algorithm>
 #include <climits>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -114,57 +116,114 @@ void stmg_default_options(stmg_options *o)
     o->vanka_diagonal = 0;
 }
 
-int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *stream, stmg_ctx **out)
+namespace {
+
+// Builds the levels, transfers and every buffer of a context, all drawn from
+// ctx->arena (counting mode: sizes only, no device work).
+void build_context(stmg_ctx *ctx, const stmg_problem *prob)
 {
-    if (!out) return STMG_EINVAL;
-    *out = nullptr;
-    std::string why;
-    if (!check_problem(prob, why) || !check_options(opt, why)) {
-        const char *ev = std::getenv("STMG_VERBOSE");
-        if (ev && *ev && *ev != '0') {
-            std::fprintf(stderr, "[stmg] create rejected: %s\n", why.c_str());
-            std::fflush(stderr);
-        }
-        return STMG_EINVAL;
+    ArenaScope scope(&ctx->arena);
+    std::vector<double> verts;
+    if (prob->vertices) {
+        long long nv = 1;
+        for (int a = 0; a < prob->dim; ++a) nv *= prob->n_cells[a] + 1;
+        verts.assign(prob->vertices, prob->vertices + nv * prob->dim);
     }
+    auto L = std::make_unique<Level>();
+    L->init(*prob, prob->k, prob->r, prob->n_cells[0], prob->n_cells[1], prob->dim == 3 ? prob->n_cells[2] : 1,
+            ctx->opt.n_q, verts);
+    if (L->nq != default_nq(L->r) && L->nq != L->r + 2) throw std::runtime_error("n_q must be ceil((3r+4)/2) or r+2");
+    L->timers = &ctx->timers;
+    ctx->levels.push_back(std::move(L));
+    mg_build(ctx);
+}
+
+stmg_ctx *new_context(const stmg_problem *prob, const stmg_options *opt, void *stream)
+{
     stmg_ctx *ctx = new stmg_ctx();
     ctx->prob = *prob;
     ctx->prob.vertices = nullptr;
     if (opt) ctx->opt = *opt;
     else stmg_default_options(&ctx->opt);
     ctx->stream = (hipStream_t)stream;
+    return ctx;
+}
+
+// bytes a context of this problem consumes: the construction run in counting
+// mode (0 if it cannot be built)
+size_t measure_context(const stmg_problem *prob, const stmg_options *opt)
+{
+    std::unique_ptr<stmg_ctx> ctx(new_context(prob, opt, nullptr));
+    ctx->arena.counting = true;
+    try {
+        build_context(ctx.get(), prob);
+    } catch (const std::exception &) {
+        return 0;
+    }
+    return (ctx->arena.used + Arena::ALIGN - 1) & ~(Arena::ALIGN - 1);
+}
+
+void verbose_reject(const char *what, const std::string &why)
+{
+    const char *ev = std::getenv("STMG_VERBOSE");
+    if (ev && *ev && *ev != '0') {
+        std::fprintf(stderr, "[stmg] %s: %s\n", what, why.c_str());
+        std::fflush(stderr);
+    }
+}
+
+} // namespace
+
+int stmg_create(const stmg_problem *prob, const stmg_options *opt, void *workspace, size_t ws_bytes, void *stream,
+                stmg_ctx **out)
+{
+    if (!out) return STMG_EINVAL;
+    *out = nullptr;
+    std::string why;
+    if (!check_problem(prob, why) || !check_options(opt, why)) {
+        verbose_reject("create rejected", why);
+        return STMG_EINVAL;
+    }
+    const size_t need = measure_context(prob, opt);
+    if (need == 0) {
+        verbose_reject("create rejected", "the problem cannot be laid out");
+        return STMG_EINVAL;
+    }
+    if (workspace && ((uintptr_t)workspace % Arena::ALIGN != 0)) {
+        verbose_reject("create rejected", "workspace not aligned to 256 bytes");
+        return STMG_EINVAL;
+    }
+    if (workspace && ws_bytes < need) {
+        verbose_reject("create rejected", "workspace of " + std::to_string(ws_bytes) + " bytes, " +
+                                              std::to_string(need) + " needed");
+        return STMG_ENOMEM;
+    }
+    stmg_ctx *ctx = new_context(prob, opt, stream);
     int rc = guarded(ctx, [&]() {
         // construction issues synchronous copies: never concurrent with another
         // thread's V-cycle capture
         std::lock_guard<std::recursive_mutex> lk(device_api_mutex());
-        std::vector<double> verts;
-        if (prob->vertices) {
-            long long nv = 1;
-            for (int a = 0; a < prob->dim; ++a) nv *= prob->n_cells[a] + 1;
-            verts.assign(prob->vertices, prob->vertices + nv * prob->dim);
+        if (workspace) {
+            ctx->arena.base = static_cast<unsigned char *>(workspace);
+            ctx->arena.cap = ws_bytes;
+        } else {
+            ctx->own_block.alloc(need);   // the one device allocation of the context
+            ctx->arena.base = ctx->own_block.as<unsigned char>();
+            ctx->arena.cap = need;
         }
-        auto L = std::make_unique<Level>();
-        L->init(*prob, prob->k, prob->r, prob->n_cells[0], prob->n_cells[1], prob->dim == 3 ? prob->n_cells[2] : 1,
-                ctx->opt.n_q, verts);
-        if (L->nq != default_nq(L->r) && L->nq != L->r + 2)
-            throw std::runtime_error("n_q must be ceil((3r+4)/2) or r+2");
-        L->timers = &ctx->timers;
-        ctx->levels.push_back(std::move(L));
-        mg_build(ctx);
+        build_context(ctx, prob);
         return STMG_OK;
     });
     if (rc != STMG_OK) {
-        const char *ev = std::getenv("STMG_VERBOSE");
-        if (ev && *ev && *ev != '0') {
-            std::fprintf(stderr, "[stmg] create failed (%d): %s\n", rc, ctx->err.c_str());
-            std::fflush(stderr);
-        }
+        verbose_reject("create failed", std::to_string(rc) + " " + ctx->err);
         delete ctx;
         return rc;
     }
     *out = ctx;
     return STMG_OK;
 }
+
+size_t stmg_workspace_used(const stmg_ctx *ctx) { return ctx ? ctx->arena.used : 0; }
 
 int stmg_destroy(stmg_ctx *ctx)
 {
@@ -179,67 +238,27 @@ size_t stmg_footprint_bytes(const stmg_problem *prob, const stmg_options *opt)
 {
     std::string why;
     if (!check_problem(prob, why) || !check_options(opt, why)) return 0;
-    stmg_options o;
-    if (opt) o = *opt;
-    else stmg_default_options(&o);
-    const int d = prob->dim;
-    const size_t w = o.prec_mg == STMG_F64 ? 8 : 4;
-    const int maxit = o.fgmres_maxit > 0 ? o.fgmres_maxit : 50;
-    // level specs (same rule as the hierarchy)
-    struct Spec { int k, r, n[3]; };
-    std::vector<Spec> specs;
-    Spec sp{prob->k, prob->r, {prob->n_cells[0], prob->n_cells[1], d == 3 ? prob->n_cells[2] : 1}};
-    specs.push_back(sp);
-    auto cnt = [&]() { return (int)specs.size(); };
-    while ((sp.r > 1 || (o.time_coarsening && sp.k > 1)) && (o.max_levels == 0 || cnt() < o.max_levels)) {
-        sp.r = std::max(1, sp.r / 2);
-        if (o.time_coarsening) sp.k = sp.k >= 2 ? sp.k / 2 : sp.k;
-        specs.push_back(sp);
-    }
-    auto hok = [&]() {
-        for (int a = 0; a < d; ++a)
-            if (sp.n[a] % 2 != 0 || sp.n[a] < 4) return false;
-        return true;
-    };
-    while (hok() && (o.max_levels == 0 || cnt() < o.max_levels)) {
-        for (int a = 0; a < d; ++a) sp.n[a] /= 2;
-        specs.push_back(sp);
-    }
-    size_t total = 0;
-    long long N0 = 0;
-    for (size_t l = 0; l < specs.size(); ++l) {
-        const Spec &q = specs[l];
-        long long ncell = 1, nn = 1, nl = 1;
-        for (int a = 0; a < d; ++a) {
-            ncell *= q.n[a];
-            nn *= (long long)(q.r + 1) * q.n[a] + 1;
-            nl *= q.r + 2;
+    return measure_context(prob, opt);
+}
+
+int stmg_set_coefficients(stmg_ctx *ctx, double nu, double tau)
+{
+    if (!ctx || !(nu > 0) || !(tau > 0)) return fail(ctx, STMG_EINVAL, "nu and tau must be positive");
+    return guarded(ctx, [&]() {
+        STMG_HIP(hipStreamSynchronize(ctx->stream));
+        for (auto &L : ctx->levels) {
+            L->nu = nu;
+            L->tau = tau;
+            L->tc = time_coefficients(L->k, tau);
         }
-        const long long npm = d == 2 ? (q.r + 1) * (q.r + 2) / 2 : (q.r + 1) * (q.r + 2) * (q.r + 3) / 6;
-        const long long nt = q.k + 1, Nv1 = d * nn, N = nt * (Nv1 + ncell * npm);
-        const long long m = nt * (d * nl + npm);
-        if (l == 0) N0 = N;
-        total += (size_t)N * (8 + 4) + 3 * (size_t)N * w;                  // states, work vectors
-        total += (size_t)ncell * nt * d * nl * (8 + 4 + w);                // cell-local result buffers
-        total += (size_t)nn * (size_t)std::pow(q.r + 3, d) * 16 * 3;       // transfer CSRs (upper bound)
-        if (l + 1 < specs.size()) {
-            total += (size_t)Nv1 * w + (size_t)ncell * (d * d * nl * nl + nl * nl + d * nl * npm) * w;
-            if (o.vanka_time_decoupled) {
-                const long long ms = d * nl + npm, ld = td_ld((int)ms);     // nt real-plane equivalents
-                total += (size_t)ncell * nt * ms * ld * w + (size_t)ncell * nt * ms * 8;
-                if (o.vanka_factor_bf16 && o.prec_mg == STMG_F32)
-                    total += (size_t)ncell * nt * ms * ld * 2;              // BF16 copy of the factors
-            } else {
-                total += (size_t)ncell * m * m * w + (size_t)ncell * m * 4;   // patch factors
-            }
-        } else {
-            total += (size_t)N * N * 8 * 2 + (size_t)(N + nt) * (N + nt) * 8 + (size_t)N * ncell * nt * d * nl * 8;
-        }
-    }
-    total += (size_t)N0 * 8 * (3 * (size_t)maxit + 12);                       // Krylov bases, Newton vectors
-    if (o.use_graphs) total += (size_t)N0 * 8 * 2;                            // staging of the captured V-cycle
-    total += 64u << 20;                                                       // tables, scratch
-    return total;
+        ctx->prob.nu = nu;
+        ctx->prob.tau = tau;
+        Mg &mg = *ctx->mg;
+        mg.graph.reset(ctx->stream);
+        mg.state_set = false;
+        for (auto &M : mg.lv) M.have_patches = false;
+        return STMG_OK;
+    });
 }
 
 int stmg_sizes(const stmg_ctx *ctx, long long *n_total, long long *n_velocity, long long *n_pressure)
@@ -258,12 +277,12 @@ int stmg_set_slab_data(stmg_ctx *ctx, const double *rhs, const double *v_prev)
     return guarded(ctx, [&]() {
         const Level &L = *ctx->levels[0];
         if (rhs) {
-            if (ctx->rhs.bytes < (size_t)L.N * 8) ctx->rhs.alloc((size_t)L.N * 8);
+            ctx->rhs.require((size_t)L.N * 8, "rhs");
             STMG_HIP(hipMemcpyAsync(ctx->rhs.p, rhs, (size_t)L.N * 8, hipMemcpyDeviceToDevice, ctx->stream));
         }
         ctx->has_rhs = rhs != nullptr;
         if (v_prev) {
-            if (ctx->vprev.bytes < (size_t)L.Nv1 * 8) ctx->vprev.alloc((size_t)L.Nv1 * 8);
+            ctx->vprev.require((size_t)L.Nv1 * 8, "v_prev");
             STMG_HIP(hipMemcpyAsync(ctx->vprev.p, v_prev, (size_t)L.Nv1 * 8, hipMemcpyDeviceToDevice, ctx->stream));
         }
         ctx->has_vprev = v_prev != nullptr;
@@ -407,6 +426,23 @@ int stmg_batched_lu(int prec, void *A, const long long *a_off, const int *m_of, 
 {
     return batched_lu_run(prec, A, a_off, m_of, batch, piv, p_off, info, nullptr, nullptr, stream, false,
                           MetaStaging::PerCall);
+}
+
+int stmg_batched_lu_config(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,
+                           const long long *p_off, int *info, int wg_per_cu, int threads, const int *nb_by_class,
+                           void *stream)
+{
+    if (wg_per_cu < 0 || wg_per_cu > 4 || (wg_per_cu > 0 && !nb_by_class)) return STMG_EINVAL;
+    if (threads != 256 && threads != 512) return STMG_EINVAL;
+    LuTune t{wg_per_cu, threads, {16, 16, 16, 16, 16}};
+    if (wg_per_cu > 0)
+        for (int c = 0; c < LU_TUNE_CLASSES; ++c) {
+            const int nb = nb_by_class[c];
+            if (nb != 4 && nb != 8 && nb != 16) return STMG_EINVAL;
+            t.nb[c] = nb;
+        }
+    return batched_lu_run(prec, A, a_off, m_of, batch, piv, p_off, info, nullptr, nullptr, stream, false,
+                          MetaStaging::PerCall, &t);
 }
 
 int stmg_batched_lu_noalloc(int prec, void *A, const long long *a_off, const int *m_of, int batch, int *piv,

@@ -555,7 +555,10 @@ __host__ __device__ constexpr int lds_words(int nt, int tabwords)
 // ---------------------------------------------------------------------------
 // The cell kernel
 // ---------------------------------------------------------------------------
-template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE>
+// MAPPED: vertex-perturbed (multilinear) cells with J^{-T} and det J per
+// point; else affine axis-aligned cells, whose J^{-T} = diag(1/h) is applied
+// as a diagonal (a third of the point arithmetic of the general 3 x 3 form)
+template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE, bool MAPPED>
 __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
 {
     using Z = Sizes<DIM, R>;
@@ -656,7 +659,7 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
     T det_c = 1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) det_c *= hcar[d];
-    const bool mapped = A.mapped != 0;
+    constexpr bool mapped = MAPPED;
     if (mapped && tid < (1 << DIM)) {
         int v = tid;
         int o0 = v & 1, o1 = (v >> 1) & 1, o2 = (v >> 2) & 1;
@@ -720,13 +723,9 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) xi[d] = qx[qi[d]];
                 T det;
-                if (mapped) {
+                if constexpr (MAPPED) {
                     det = geometry<DIM>(true, geo, xi, hcar, Jit);
                 } else {
-#pragma unroll
-                    for (int a2 = 0; a2 < 3; ++a2)
-#pragma unroll
-                        for (int b2 = 0; b2 < 3; ++b2) Jit[a2][b2] = a2 == b2 && a2 < DIM ? hinv[a2] : T(0);
                     det = det_c;
                 }
                 T jxw = det;
@@ -756,8 +755,12 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
 #pragma unroll
                         for (int d = 0; d < DIM; ++d) {
                             T g = 0;
+                            if constexpr (MAPPED) {
 #pragma unroll
-                            for (int jd = 0; jd < DIM; ++jd) g += Jit[d][jd] * gref[jd];
+                                for (int jd = 0; jd < DIM; ++jd) g += Jit[d][jd] * gref[jd];
+                            } else {
+                                g = hinv[d] * gref[d];
+                            }
                             if (d == c) divx += g;
                             // nu grad x - x (x) v - v (x) x - p I (Jacobian); Res: v = x, one convective term
                             Fc[d] = A.nu * g - xh[c] * v[d] - (MODE == Mode::Jac ? v[c] * xh[d] : T(0));
@@ -766,8 +769,12 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
 #pragma unroll
                         for (int jd = 0; jd < DIM; ++jd) {
                             T s = 0;
+                            if constexpr (MAPPED) {
 #pragma unroll
-                            for (int d = 0; d < DIM; ++d) s += Fc[d] * Jit[d][jd];
+                                for (int d = 0; d < DIM; ++d) s += Fc[d] * Jit[d][jd];
+                            } else {
+                                s = Fc[jd] * hinv[jd];
+                            }
                             G[(c * DIM + jd) * NQV + q] = s * sc;
                         }
                     }
@@ -1432,10 +1439,11 @@ static hipError_t launch_one(const CellArgs<T> &a, int nvec, hipStream_t s)
     TableLayout lay;
     lay.init(R, NQ);
     size_t bytes = (size_t)lds_words<DIM, R, NQ, T, MODE>(a.nt, lay.total) * sizeof(T);
-    auto kern = cell_kernel<DIM, R, NQ, NTH, T, MODE>;
+    auto kern = a.mapped ? cell_kernel<DIM, R, NQ, NTH, T, MODE, true> : cell_kernel<DIM, R, NQ, NTH, T, MODE, false>;
     static std::mutex mu;
     std::lock_guard<std::mutex> lk(mu);
-    static size_t attr_bytes = 0;
+    static size_t attr_bytes[2] = {0, 0};   // per kernel (affine, mapped)
+    size_t &have = attr_bytes[a.mapped ? 1 : 0];
     static int max_lds = -1;
     if (max_lds < 0) {
         int dev = 0;
@@ -1444,10 +1452,10 @@ static hipError_t launch_one(const CellArgs<T> &a, int nvec, hipStream_t s)
             max_lds = 65536;
     }
     if (bytes > (size_t)max_lds) return hipErrorInvalidConfiguration;
-    if (bytes > attr_bytes) {
+    if (bytes > have) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
-        attr_bytes = bytes;
+        have = bytes;
     }
     dim3 grid(a.ncell, nvec);
     hipLaunchKernelGGL(kern, grid, dim3(NTH), bytes, s, a);

@@ -33,16 +33,65 @@ struct HipError : std::runtime_error {
             throw ::stmg::HipError(std::string(#call) + ": " + hipGetErrorString(e_), STMG_EHIP);           \
     } while (0)
 
-// device allocation owned by a context
+// The device memory of one context: one block (the caller's workspace, or a
+// single library allocation) handed out in creation order, each piece on a
+// 256-byte boundary.  In counting mode no memory exists: only the sizes are
+// added up (this is how stmg_footprint_bytes measures a context, by running
+// the same construction code), and no device work may be issued.
+struct Arena {
+    unsigned char *base = nullptr;
+    size_t cap = 0, used = 0;
+    bool counting = false;
+    static constexpr size_t ALIGN = 256;
+    void *take(size_t b)
+    {
+        const size_t off = (used + ALIGN - 1) & ~(ALIGN - 1);
+        if (!counting && off + b > cap)
+            throw HipError("context workspace exhausted: " + std::to_string(off + b) + " of " +
+                               std::to_string(cap) + " bytes", STMG_ENOMEM);
+        used = off + b;
+        // counting mode: a distinct non-null address that is never dereferenced
+        return counting ? reinterpret_cast<void *>(ALIGN + off) : base + off;
+    }
+};
+
+// arena that DevBuf allocations of the calling thread draw from (null: none)
+inline Arena *&current_arena()
+{
+    static thread_local Arena *a = nullptr;
+    return a;
+}
+
+struct ArenaScope {
+    Arena *prev;
+    explicit ArenaScope(Arena *a) : prev(current_arena()) { current_arena() = a; }
+    ~ArenaScope() { current_arena() = prev; }
+};
+
+// true while a context is being measured (no device work allowed)
+inline bool arena_counting()
+{
+    return current_arena() && current_arena()->counting;
+}
+
+// device buffer of a context: a piece of the current arena when one is set
+// (released with the arena), else its own allocation
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool from_arena = false;
     DevBuf() = default;
     explicit DevBuf(size_t b) { alloc(b); }
     void alloc(size_t b)
     {
         release();
         if (b == 0) return;
+        if (Arena *a = current_arena()) {
+            p = a->take(b);
+            bytes = b;
+            from_arena = true;
+            return;
+        }
         std::lock_guard<std::recursive_mutex> lk(device_api_mutex());
         if (hipMalloc(&p, b) != hipSuccess) {
             p = nullptr;
@@ -50,22 +99,30 @@ struct DevBuf {
         }
         bytes = b;
     }
+    // a buffer of at least b bytes must exist (allocated when the context was built)
+    void require(size_t b, const char *what) const
+    {
+        if (bytes < b)
+            throw HipError(std::string("workspace buffer ") + what + " smaller than needed", STMG_ESTATE);
+    }
     void release()
     {
-        if (p) {
+        if (p && !from_arena) {
             std::lock_guard<std::recursive_mutex> lk(device_api_mutex());
             (void)hipFree(p);
         }
         p = nullptr;
         bytes = 0;
+        from_arena = false;
     }
     ~DevBuf() { release(); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes)
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), from_arena(o.from_arena)
     {
         o.p = nullptr;
         o.bytes = 0;
+        o.from_arena = false;
     }
     DevBuf &operator=(DevBuf &&o) noexcept
     {
@@ -73,8 +130,10 @@ struct DevBuf {
             release();
             p = o.p;
             bytes = o.bytes;
+            from_arena = o.from_arena;
             o.p = nullptr;
             o.bytes = 0;
+            o.from_arena = false;
         }
         return *this;
     }
@@ -171,8 +230,13 @@ struct Level {
     int nbcell = 0;
     Timers *timers = nullptr;
 
+    int nvec_cap64 = 1, nvec_cap32 = 1;   // vectors one operator launch handles (work buffer size)
+
     void init(const stmg_problem &p, int k_, int r_, int nx, int ny, int nz, int nq_,
               const std::vector<double> &verts);
+    // cell-local result buffers for nvec64 FP64 and nvec32 FP32 vectors per
+    // launch (0: that precision not used on this level)
+    void alloc_work(int nvec64, int nvec32);
     template <typename T> CellArgs<T> cell_args() const;
     template <typename T> GatherArgs<T> gather_args() const;
     // apply one of the cell operators (Jacobian, residual, mass) on stream s

@@ -43,10 +43,13 @@ void Level::init(const stmg_problem &p, int k_, int r_, int nx, int ny, int nz, 
     lay.init(r, nq);
     std::vector<double> tb = build_table_block(r, nq, lay);
     std::vector<float> tbf(tb.begin(), tb.end());
+    const bool dry = arena_counting();   // measuring only: no device work
     tab64.alloc(tb.size() * sizeof(double));
     tab32.alloc(tbf.size() * sizeof(float));
-    STMG_HIP(hipMemcpy(tab64.p, tb.data(), tb.size() * sizeof(double), hipMemcpyHostToDevice));
-    STMG_HIP(hipMemcpy(tab32.p, tbf.data(), tbf.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (!dry) {
+        STMG_HIP(hipMemcpy(tab64.p, tb.data(), tb.size() * sizeof(double), hipMemcpyHostToDevice));
+        STMG_HIP(hipMemcpy(tab32.p, tbf.data(), tbf.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     {
         std::vector<int> bc;
         for (long long c = 0; c < ncell; ++c) {
@@ -57,15 +60,24 @@ void Level::init(const stmg_problem &p, int k_, int r_, int nx, int ny, int nz, 
         }
         nbcell = (int)bc.size();
         bcells.alloc(std::max<size_t>(bc.size(), 1) * sizeof(int));
-        if (!bc.empty())
+        if (!bc.empty() && !dry)
             STMG_HIP(hipMemcpy(bcells.p, bc.data(), bc.size() * sizeof(int), hipMemcpyHostToDevice));
     }
     mapped = !verts.empty();
     vert_host = verts;
     if (mapped) {
         vert.alloc(verts.size() * sizeof(double));
-        STMG_HIP(hipMemcpy(vert.p, verts.data(), verts.size() * sizeof(double), hipMemcpyHostToDevice));
+        if (!dry) STMG_HIP(hipMemcpy(vert.p, verts.data(), verts.size() * sizeof(double), hipMemcpyHostToDevice));
     }
+}
+
+void Level::alloc_work(int nvec64, int nvec32)
+{
+    const size_t cellw = (size_t)ncell * nt * dim * nl;
+    nvec_cap64 = nvec64;
+    nvec_cap32 = nvec32;
+    if (nvec64 > 0) E64.alloc(nvec64 * cellw * 8);
+    if (nvec32 > 0) E32.alloc(nvec32 * cellw * 4);
 }
 
 template <typename T> CellArgs<T> Level::cell_args() const
@@ -120,9 +132,21 @@ template <typename T>
 void Level::apply(Mode mode, const T *state, const T *x, T *y, const T *rhs, const T *vprev, int nvec,
                   hipStream_t s)
 {
-    DevBuf &Eb = std::is_same<T, double>::value ? E64 : E32;
-    size_t need = (size_t)nvec * ncell * nt * dim * nl * sizeof(T);
-    if (Eb.bytes < need) Eb.alloc(need);
+    const bool f64 = std::is_same<T, double>::value;
+    // the work buffers were sized at creation for cap vectors per launch:
+    // larger batches run in chunks of cap vectors
+    const int cap = f64 ? nvec_cap64 : nvec_cap32;
+    if (cap < 1) throw HipError("operator precision not prepared on this level", STMG_EINVAL);
+    if (nvec > cap) {
+        for (int v0 = 0; v0 < nvec; v0 += cap) {
+            const int nv = std::min(cap, nvec - v0);
+            apply<T>(mode, state, x + (long long)v0 * N, y + (long long)v0 * N, rhs, vprev, nv, s);
+        }
+        return;
+    }
+    DevBuf &Eb = f64 ? E64 : E32;
+    Eb.require((size_t)nvec * ncell * nt * dim * nl * sizeof(T), "E");
+    const bool faces = mode != Mode::Mass && nbcell > 0;
     CellArgs<T> a = cell_args<T>();
     a.x = x;
     a.state = state;
@@ -135,15 +159,15 @@ void Level::apply(Mode mode, const T *state, const T *x, T *y, const T *rhs, con
     a.sstride = 0;
     static const char *names64[3] = {"cell_jac_f64", "cell_res_f64", "cell_mass_f64"};
     static const char *names32[3] = {"cell_jac_f32", "cell_res_f32", "cell_mass_f32"};
-    const char *nm = std::is_same<T, double>::value ? names64[(int)mode] : names32[(int)mode];
+    const char *nm = f64 ? names64[(int)mode] : names32[(int)mode];
     {
         TimerScope ts(timers, nm, s);
         STMG_HIP(launch_cell_op<T>(mode, dim, r, nq, a, nvec, s));
     }
-    if (mode != Mode::Mass) {
+    if (faces) {
         static const char *fn64[2] = {"face_jac_f64", "face_res_f64"};
         static const char *fn32[2] = {"face_jac_f32", "face_res_f32"};
-        TimerScope ts(timers, std::is_same<T, double>::value ? fn64[(int)mode] : fn32[(int)mode], s);
+        TimerScope ts(timers, f64 ? fn64[(int)mode] : fn32[(int)mode], s);
         STMG_HIP(launch_face_op<T>(mode, dim, r, nq, a, nvec, s));
     }
     GatherArgs<T> g = gather_args<T>();
@@ -152,7 +176,7 @@ void Level::apply(Mode mode, const T *state, const T *x, T *y, const T *rhs, con
     g.y = y;
     g.ystride = N;
     {
-        TimerScope ts(timers, std::is_same<T, double>::value ? "gather_f64" : "gather_f32", s);
+        TimerScope ts(timers, f64 ? "gather_f64" : "gather_f32", s);
         STMG_HIP(launch_gather<T>(g, nvec, s));
     }
 }

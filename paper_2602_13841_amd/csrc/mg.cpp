@@ -72,6 +72,7 @@ std::vector<double> coarse_vertices(const std::vector<double> &v, int dim, const
 void Krylov::ensure(long long N_, int maxit_)
 {
     if (N_ == N && maxit_ <= maxit) return;
+    if (maxit > 0) throw HipError("Krylov workspace was sized for fewer iterations", STMG_EINVAL);
     N = N_;
     maxit = maxit_;
     V.alloc(sizeof(double) * N * (maxit + 1));
@@ -147,10 +148,10 @@ void mg_build(stmg_ctx *ctx)
         M.L = ctx->levels[l].get();
         size_t N = (size_t)M.L->N;
         M.st64.alloc(N * 8);
-        STMG_HIP(hipMemsetAsync(M.st64.p, 0, N * 8, ctx->stream));
+        if (!arena_counting()) STMG_HIP(vec_fill<double>((long long)N, 0.0, M.st64.as<double>(), ctx->stream));
         if (mg->prec == STMG_F32) {
             M.st32.alloc(N * 4);
-            STMG_HIP(hipMemsetAsync(M.st32.p, 0, N * 4, ctx->stream));
+            if (!arena_counting()) STMG_HIP(vec_fill<float>((long long)N, 0.0f, M.st32.as<float>(), ctx->stream));
         }
         size_t w = mg->prec == STMG_F64 ? 8 : 4;
         M.r.alloc(N * w);
@@ -165,6 +166,89 @@ void mg_build(stmg_ctx *ctx)
     }
     mg->border = L0.dmask == (unsigned)((1 << (2 * L0.dim)) - 1);
     ctx->mg = std::move(mg);
+    mg_allocate(ctx);
+}
+
+// Every buffer the context will use, allocated once here with its final size
+// (nothing is allocated later, so the bytes consumed at creation are the
+// context's whole footprint): operator work buffers, smoother buffers of every
+// smoothed level, the coarse-level matrices, the Krylov and Newton vectors,
+// the staging of the captured V-cycle and the slab data.
+void mg_allocate(stmg_ctx *ctx)
+{
+    Mg &mg = *ctx->mg;
+    const stmg_options &o = ctx->opt;
+    const int nl = (int)mg.lv.size();
+    const size_t w = mg.prec == STMG_F64 ? 8 : 4;
+    for (int l = 0; l < nl; ++l) {
+        Level &L = *mg.lv[l].L;
+        // FP64 everywhere (Newton, level states, the coarse matrix assembly with
+        // one column per unknown on the coarsest level), FP32 for an FP32
+        // multigrid and for FP32 applications of the slab operator
+        const bool coarsest = l == nl - 1;
+        L.alloc_work(coarsest ? (int)std::max<long long>(1, L.N) : 1,
+                     (mg.prec == STMG_F32 || l == 0) ? 1 : 0);
+    }
+    for (int l = 0; l + 1 < nl; ++l) {
+        MgLevel &M = mg.lv[l];
+        Level &L = *M.L;
+        M.vstar.alloc((size_t)L.Nv1 * w);
+        M.elem.alloc((size_t)L.ncell * elem_record_words(L.dim, L.r) * w);
+        M.m = L.nt * (L.dim * L.nl + L.npm);
+        M.ms = L.dim * L.nl + L.npm;
+        M.info.alloc(4);
+        if (mg.td) {
+            // one spatial system per eigen-system of the time coupling; which
+            // systems are complex depends only on k
+            M.tdg = time_diagonalization(L.tc);
+            const long long ms = M.ms, ld = td_ld(M.ms), mat = ms * ld;
+            long long off = 0;
+            for (int sy = 0; sy < M.tdg.nsys; ++sy) {
+                M.sys_off[sy] = off;
+                M.piv_off[sy] = (long long)sy * L.ncell * ms;
+                off += (long long)L.ncell * (M.tdg.cplx[sy] ? 2 : 1) * mat;
+            }
+            M.nfac = off;
+            M.patches.alloc((size_t)off * w);
+            const size_t ib = (size_t)M.tdg.nsys * L.ncell * ms * 4;
+            M.piv.alloc(ib);
+            M.perm.alloc(ib);
+            if (mg.diag) {
+                const int nv = mg.diag_block ? L.nl * L.dim * L.dim : L.dim * L.nl, npm = L.npm, ns = M.tdg.nsys;
+                M.dv_dinv.alloc((size_t)ns * L.ncell * 2 * nv * w);
+                M.dv_schur.alloc((size_t)ns * L.ncell * 2 * npm * npm * w);
+                M.dv_piv.alloc((size_t)ns * L.ncell * npm * sizeof(int));
+            } else if (mg.factor_bf16) {
+                M.fac16.alloc((size_t)off * 2);
+            }
+        } else {
+            M.patches.alloc((size_t)L.ncell * M.m * M.m * w);
+            M.piv.alloc((size_t)L.ncell * M.m * 4);
+        }
+    }
+    // coarsest level: dense Jacobian (bordered by the constant pressures of
+    // each time node when every face is Dirichlet) and its LU
+    {
+        Level &Lc = *mg.lv[nl - 1].L;
+        const int n = (int)Lc.N, m = n + (mg.border ? Lc.nt : 0);
+        mg.cX.alloc((size_t)n * n * 8);
+        mg.cY.alloc((size_t)n * n * 8);
+        mg.cA.alloc((size_t)m * m * 8);
+        mg.cpiv.alloc((size_t)m * 4);
+        mg.cinfo.alloc(4);
+        mg.cr64.alloc((size_t)m * 8);
+        mg.cx64.alloc((size_t)m * 8);
+        mg.cn = n;
+        mg.cm = m;
+    }
+    const long long N = mg.lv[0].L->N;
+    ctx->kry.ensure(N, std::max(1, o.fgmres_maxit));
+    if (mg.use_graph) {
+        mg.graph.in.alloc((size_t)N * 8);
+        mg.graph.out.alloc((size_t)N * 8);
+    }
+    ctx->rhs.alloc((size_t)N * 8);
+    ctx->vprev.alloc((size_t)mg.lv[0].L->Nv1 * 8);
 }
 
 void mg_set_state(stmg_ctx *ctx, const double *u)
@@ -184,17 +268,7 @@ void mg_set_state(stmg_ctx *ctx, const double *u)
     MgLevel &C = mg.lv[nl - 1];
     Level &Lc = *C.L;
     const int n = (int)Lc.N, nb = mg.border ? Lc.nt : 0, m = n + nb;
-    if (mg.cn != n) {
-        mg.cX.alloc((size_t)n * n * 8);
-        mg.cY.alloc((size_t)n * n * 8);
-        mg.cA.alloc((size_t)m * m * 8);
-        mg.cpiv.alloc((size_t)m * 4);
-        mg.cinfo.alloc(4);
-        mg.cr64.alloc((size_t)m * 8);
-        mg.cx64.alloc((size_t)m * 8);
-        mg.cn = n;
-        mg.cm = m;
-    }
+    if (mg.cn != n || mg.cm != m) throw HipError("coarse-level buffers not prepared", STMG_ESTATE);
     {
         TimerScope ts(&ctx->timers, "coarse_factor", s);
         STMG_HIP(launch_identity(mg.cX.as<double>(), n, s));
@@ -214,11 +288,10 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
 {
     Level &L = *M.L;
     hipStream_t s = ctx->stream;
-    M.vstar.alloc((size_t)L.Nv1 * sizeof(T));
+    M.vstar.require((size_t)L.Nv1 * sizeof(T), "vstar");
     STMG_HIP(launch_midpoint<T>(state_of<T>(M), L.Nv1, L.nt, L.tc.phimid, M.vstar.as<T>(), s));
     const long long rw = elem_record_words(L.dim, L.r);
-    size_t eb = (size_t)L.ncell * rw * sizeof(T);
-    if (M.elem.bytes < eb) M.elem.alloc(eb);
+    M.elem.require((size_t)L.ncell * rw * sizeof(T), "elem");
     ElemArgs<T> ea{};
     ea.n0 = L.n[0];
     ea.n1 = L.n[1];
@@ -253,11 +326,7 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
             off += (long long)L.ncell * (M.tdg.cplx[sy] ? 2 : 1) * mat;
         }
         M.nfac = off;
-        const size_t pb = (size_t)off * sizeof(T), ib = (size_t)M.tdg.nsys * L.ncell * ms * 4;
-        if (M.patches.bytes < pb) M.patches.alloc(pb);
-        if (M.piv.bytes < ib) M.piv.alloc(ib);
-        if (M.perm.bytes < ib) M.perm.alloc(ib);
-        if (!M.info.p) M.info.alloc(4);
+        M.patches.require((size_t)off * sizeof(T), "patches");
         PatchTdArgs<T, T> pa{};
         pa.n0 = L.n[0];
         pa.n1 = L.n[1];
@@ -280,12 +349,9 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
             // diagonal Vanka: D^{-1} and the LU of the pressure Schur
             // complement per system; the systems stay unfactored
             const int nv = ctx->mg->diag_block ? L.nl * L.dim * L.dim : L.dim * L.nl, npm = L.npm, ns = M.tdg.nsys;
-            const size_t bd = (size_t)ns * L.ncell * 2 * nv * sizeof(T);
-            const size_t bs = (size_t)ns * L.ncell * 2 * npm * npm * sizeof(T);
-            const size_t bp = (size_t)ns * L.ncell * npm * sizeof(int);
-            if (M.dv_dinv.bytes < bd) M.dv_dinv.alloc(bd);
-            if (M.dv_schur.bytes < bs) M.dv_schur.alloc(bs);
-            if (M.dv_piv.bytes < bp) M.dv_piv.alloc(bp);
+            M.dv_dinv.require((size_t)ns * L.ncell * 2 * nv * sizeof(T), "dv_dinv");
+            M.dv_schur.require((size_t)ns * L.ncell * 2 * npm * npm * sizeof(T), "dv_schur");
+            M.dv_piv.require((size_t)ns * L.ncell * npm * sizeof(int), "dv_piv");
             DvArgs<T> da{};
             da.nsys = ns;
             for (int sy = 0; sy < ns; ++sy) {
@@ -320,7 +386,7 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
             if constexpr (std::is_same<T, float>::value) {
                 if (ctx->mg->factor_bf16) {
                     // the sweeps read a BF16 copy of the factors (half the bytes)
-                    if (M.fac16.bytes < (size_t)off * 2) M.fac16.alloc((size_t)off * 2);
+                    M.fac16.require((size_t)off * 2, "fac16");
                     STMG_HIP(launch_pack_bf16(M.patches.as<float>(), M.fac16.as<unsigned short>(), off, s));
                 }
             }
@@ -328,10 +394,8 @@ template <typename T> static void rebuild_level(stmg_ctx *ctx, MgLevel &M, size_
         M.have_patches = true;
         return;
     }
-    size_t pb = (size_t)L.ncell * M.m * M.m * sizeof(T);
-    if (M.patches.bytes < pb) M.patches.alloc(pb);
-    if (M.piv.bytes < (size_t)L.ncell * M.m * 4) M.piv.alloc((size_t)L.ncell * M.m * 4);
-    if (!M.info.p) M.info.alloc(4);
+    M.patches.require((size_t)L.ncell * M.m * M.m * sizeof(T), "patches");
+    M.piv.require((size_t)L.ncell * M.m * 4, "piv");
     PatchArgs<T, T> pa{};
     pa.cell0 = -1;
     pa.n0 = L.n[0];
@@ -560,11 +624,8 @@ static bool capture_vcycle(stmg_ctx *ctx)
     VcycleGraph &G = mg.graph;
     hipStream_t s = ctx->stream;
     const long long N = mg.lv[0].L->N;
-    if (G.in.bytes < (size_t)N * 8) {
-        G.in.alloc((size_t)N * 8);
-        G.out.alloc((size_t)N * 8);
-        G.warm = false;
-    }
+    G.in.require((size_t)N * 8, "graph staging");
+    G.out.require((size_t)N * 8, "graph staging");
     if (!G.warm) {
         // one eager cycle first: lazy allocations and kernel attributes happen
         // outside the capture

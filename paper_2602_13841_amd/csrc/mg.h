@@ -92,6 +92,7 @@ struct Krylov {
 };
 
 void mg_build(stmg_ctx *ctx);
+void mg_allocate(stmg_ctx *ctx);
 void mg_set_state(stmg_ctx *ctx, const double *u);
 void mg_rebuild(stmg_ctx *ctx);
 // one Vanka sweep d <- d + omega S(r - J d); d_zero: d is known to be zero
@@ -112,6 +113,10 @@ int newton_solve(stmg_ctx *ctx, double *u, stmg_stats *stats);
 } // namespace stmg
 
 struct stmg_ctx {
+    // device memory of the context (declared first: released last, after
+    // every buffer that points into it)
+    stmg::Arena arena;
+    stmg::DevBuf own_block;   // the arena's block when the library allocated it
     stmg_problem prob{};
     stmg_options opt{};
     hipStream_t stream = nullptr;

@@ -46,7 +46,7 @@ void locate(long long g, int r, int ncell, int &cell, int &loc)
 }
 
 HostCsr tensor_csr(int dim, const std::vector<std::vector<std::vector<Entry>>> &axes, const long long Nrow[3],
-                   const long long Ncol[3])
+                   const long long Ncol[3], bool count_only)
 {
     HostCsr A;
     long long nrows = 1, ncols = 1;
@@ -58,6 +58,20 @@ HostCsr tensor_csr(int dim, const std::vector<std::vector<std::vector<Entry>>> &
     if (nrows > INT_MAX || ncols > INT_MAX) throw std::invalid_argument("transfer matrix too large for 32-bit indices");
     A.nrows = (int)nrows;
     A.ncols = (int)ncols;
+    if (count_only) {
+        // a row's entries are the nonzero products of one nonzero 1D entry per
+        // axis, so the total factorizes over the axes
+        long long nnz = 1;
+        for (int a = 0; a < dim; ++a) {
+            long long s = 0;
+            for (const auto &lst : axes[a])
+                for (const Entry &e : lst) s += e.val != 0.0;
+            nnz *= s;
+        }
+        if (nnz > INT_MAX) throw std::invalid_argument("transfer matrix has more than 2^31 - 1 entries");
+        A.counted_nnz = nnz;
+        return A;
+    }
     A.rowptr.assign(nrows + 1, 0);
     std::vector<Entry> cur, nxt;
     for (long long row = 0; row < nrows; ++row) {
@@ -95,6 +109,10 @@ HostCsr transpose(const HostCsr &A)
     HostCsr B;
     B.nrows = A.ncols;
     B.ncols = A.nrows;
+    if (A.counted_nnz >= 0) {
+        B.counted_nnz = A.counted_nnz;
+        return B;
+    }
     B.rowptr.assign(B.nrows + 1, 0);
     for (int c : A.col) B.rowptr[c + 1]++;
     for (int i = 0; i < B.nrows; ++i) B.rowptr[i + 1] += B.rowptr[i];
@@ -110,7 +128,7 @@ HostCsr transpose(const HostCsr &A)
     return B;
 }
 
-HostCsr velocity_prolongation(const Level &f, const Level &c, char kind)
+HostCsr velocity_prolongation(const Level &f, const Level &c, char kind, bool count_only)
 {
     std::vector<double> glf, glc;
     lobatto_points(f.r + 2, glf);
@@ -138,10 +156,10 @@ HostCsr velocity_prolongation(const Level &f, const Level &c, char kind)
             for (int j = 0; j < c.r + 2; ++j) axes[a][g].push_back(Entry{(long long)(c.r + 1) * cc + j, L[j]});
         }
     }
-    return tensor_csr(f.dim, axes, Nf, Nc);
+    return tensor_csr(f.dim, axes, Nf, Nc, count_only);
 }
 
-HostCsr state_interpolation(const Level &f, const Level &c, char kind)
+HostCsr state_interpolation(const Level &f, const Level &c, char kind, bool count_only)
 {
     std::vector<double> glf, glc;
     lobatto_points(f.r + 2, glf);
@@ -170,17 +188,18 @@ HostCsr state_interpolation(const Level &f, const Level &c, char kind)
             for (int j = 0; j < f.r + 2; ++j) axes[a][g].push_back(Entry{(long long)(f.r + 1) * cf + j, L[j]});
         }
     }
-    return tensor_csr(f.dim, axes, Nc, Nf);
+    return tensor_csr(f.dim, axes, Nc, Nf, count_only);
 }
 
-HostCsr pressure_prolongation(const Level &f, const Level &c, char kind)
+HostCsr pressure_prolongation(const Level &f, const Level &c, char kind, bool count_only)
 {
     std::vector<int> mf = pressure_multi_indices(f.r, f.dim), mc = pressure_multi_indices(c.r, c.dim);
     int nf = (int)mf.size() / 3, nc = (int)mc.size() / 3;
     HostCsr A;
     A.nrows = (int)(f.ncell * nf);
     A.ncols = (int)(c.ncell * nc);
-    A.rowptr.assign(A.nrows + 1, 0);
+    if (count_only) A.counted_nnz = 0;
+    else A.rowptr.assign(A.nrows + 1, 0);
     // 1D child integrals m1[o][alpha][beta] = int_0^1 L_alpha(s) L_beta((o+s)/2) ds
     int rmax = std::max(f.r, c.r);
     std::vector<double> gx, gw;
@@ -214,11 +233,15 @@ HostCsr pressure_prolongation(const Level &f, const Level &c, char kind)
                     for (int a = 0; a < f.dim; ++a) v *= m1(cf[a] % 2, mf[3 * i + a], mc[3 * j + a]);
                 }
                 if (v != 0.0) {
+                    if (count_only) {
+                        ++A.counted_nnz;
+                        continue;
+                    }
                     A.col.push_back((int)(ccell * nc + j));
                     A.val.push_back(v);
                 }
             }
-            A.rowptr[row + 1] = (int)A.col.size();
+            if (!count_only) A.rowptr[row + 1] = (int)A.col.size();
         }
     }
     return A;
@@ -228,11 +251,12 @@ void DevCsr::upload(const HostCsr &A)
 {
     nrows = A.nrows;
     ncols = A.ncols;
-    nnz = (long long)A.col.size();
+    nnz = A.nnz();
     rowptr.alloc(sizeof(int) * (nrows + 1));
     col.alloc(sizeof(int) * std::max<long long>(nnz, 1));
     val64.alloc(sizeof(double) * std::max<long long>(nnz, 1));
     val32.alloc(sizeof(float) * std::max<long long>(nnz, 1));
+    if (arena_counting()) return;
     std::vector<float> vf(A.val.begin(), A.val.end());
     STMG_HIP(hipMemcpy(rowptr.p, A.rowptr.data(), sizeof(int) * (nrows + 1), hipMemcpyHostToDevice));
     if (nnz) {
@@ -247,6 +271,7 @@ static void upload_dense(DevBuf &b64, DevBuf &b32, const std::vector<double> &v)
     std::vector<float> f(v.begin(), v.end());
     b64.alloc(v.size() * sizeof(double));
     b32.alloc(v.size() * sizeof(float));
+    if (arena_counting()) return;
     STMG_HIP(hipMemcpy(b64.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
     STMG_HIP(hipMemcpy(b32.p, f.data(), v.size() * sizeof(float), hipMemcpyHostToDevice));
 }
@@ -254,13 +279,14 @@ static void upload_dense(DevBuf &b64, DevBuf &b32, const std::vector<double> &v)
 void Transfer::build(const Level &f, const Level &c, char kind_)
 {
     kind = kind_;
-    HostCsr Pv = velocity_prolongation(f, c, kind);
-    HostCsr Pp = pressure_prolongation(f, c, kind);
+    const bool dry = arena_counting();
+    HostCsr Pv = velocity_prolongation(f, c, kind, dry);
+    HostCsr Pp = pressure_prolongation(f, c, kind, dry);
     vel.upload(Pv);
     velT.upload(transpose(Pv));
     pres.upload(Pp);
     presT.upload(transpose(Pp));
-    state.upload(state_interpolation(f, c, kind));
+    state.upload(state_interpolation(f, c, kind, dry));
     std::vector<double> Pt = time_embedding(f.k, c.k);           // [a_f][b_c]
     std::vector<double> PtT(Pt.size());
     for (int a = 0; a < f.nt; ++a)

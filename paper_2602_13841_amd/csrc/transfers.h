@@ -10,6 +10,8 @@ struct HostCsr {
     int nrows = 0, ncols = 0;
     std::vector<int> rowptr, col;
     std::vector<double> val;
+    long long counted_nnz = -1;   // >= 0: only the sizes were computed (arrays empty)
+    long long nnz() const { return counted_nnz >= 0 ? counted_nnz : (long long)col.size(); }
 };
 
 struct DevCsr {
@@ -19,10 +21,12 @@ struct DevCsr {
     void upload(const HostCsr &A);
 };
 
+// count_only: rows, columns and the number of entries, no arrays (used when a
+// context is only measured)
 HostCsr transpose(const HostCsr &A);
-HostCsr velocity_prolongation(const Level &f, const Level &c, char kind);
-HostCsr state_interpolation(const Level &f, const Level &c, char kind);
-HostCsr pressure_prolongation(const Level &f, const Level &c, char kind);
+HostCsr velocity_prolongation(const Level &f, const Level &c, char kind, bool count_only = false);
+HostCsr state_interpolation(const Level &f, const Level &c, char kind, bool count_only = false);
+HostCsr pressure_prolongation(const Level &f, const Level &c, char kind, bool count_only = false);
 
 struct Transfer {
     char kind = 'h';

@@ -92,6 +92,26 @@ struct LuBatch {
     int uniform_ld;   // row stride of every matrix (0: its size m)
 };
 
+// a batch of LU factorizations taken from a device work queue by a fixed grid
+// of workgroups (metadata sorted by decreasing size; counter zero at launch)
+struct LuQueue {
+    int batch;
+    const int *m_of;          // matrix sizes
+    const long long *a_off;   // element offsets of the matrices (row stride = size)
+    const long long *p_off;   // offsets of their pivots
+    const int *nb_of;         // panel width per matrix: 32, 16, 8 or 4
+    int *counter;             // next queue position
+};
+
+// LDS bytes of one factorization of an m x m matrix with panel width nb
+size_t lu_panel_lds_bytes(int nb, int m, bool f64);
+// persistent launch: `grid` workgroups of `threads` (256 or 512) threads with
+// `lds_bytes` of dynamic LDS each (>= lu_panel_lds_bytes of every matrix); op
+// as for launch_lu
+template <typename T>
+hipError_t launch_lu_queue(T *A, int *piv, const LuQueue &q, size_t lds_bytes, int grid, int threads, int *info,
+                           hipStream_t s, int op = 0);
+
 int elem_record_words(int dim, int r);
 template <typename T> hipError_t launch_elem(int dim, int r, int nq, const ElemArgs<T> &a, int ncell, hipStream_t s);
 template <typename TE, typename TP>

@@ -895,7 +895,7 @@ constexpr int LU_SWC = 64;       // column chunk of the row interchanges
 // accumulated in FP32 (v_mfma_f32_16x16x16{bf16,f16}: A lane l -> (row l%16,
 // k 4(l/16)+j), B lane l -> (k 4(l/16)+j, col l%16), j < 4; D as above);
 // A22 stays FP32
-template <int NBP, int OP>
+template <int NBP, int OP, int NTH = LU_THREADS, int PF = 1>
 __device__ __forceinline__ void trailing_update(float *A, int m, int ld, int j0, int nb, int cb, int ncb, const float *pan,
                                                 const float *ut)
 {
@@ -917,12 +917,21 @@ __device__ __forceinline__ void trailing_update(float *A, int m, int ld, int j0,
                     c[si][sj][i] = (row < m && col < cb + ncb) ? A[(long long)row * ld + col] : 0.0f;
                 }
     };
-    floatx4_t acc[2][2], nxt[2][2];
+    // PF tiles ahead: the C blocks of the next PF tiles of this wave are in
+    // flight while the current one is computed
+    constexpr int S = NTH / 64;
+    floatx4_t acc[2][2], nxt[2][2], nxt2[2][2];
     if (wv < ntile) load(wv, acc);
-    for (int t = wv; t < ntile; t += LU_THREADS / 64) {
+    if constexpr (PF > 1)
+        if (wv + S < ntile) load(wv + S, nxt);
+    for (int t = wv; t < ntile; t += S) {
         const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
-        const int tn = t + LU_THREADS / 64;
-        if (tn < ntile) load(tn, nxt);
+        const int tn = t + S;
+        if constexpr (PF > 1) {
+            if (t + 2 * S < ntile) load(t + 2 * S, nxt2);
+        } else {
+            if (tn < ntile) load(tn, nxt);
+        }
         if constexpr (OP == 0) {
             for (int k0 = 0; k0 < nb; k0 += 4) {
                 const int k = k0 + (lane >> 4);
@@ -987,40 +996,82 @@ __device__ __forceinline__ void trailing_update(float *A, int m, int ld, int j0,
 #pragma unroll
             for (int si = 0; si < 2; ++si)
 #pragma unroll
-                for (int sj = 0; sj < 2; ++sj) acc[si][sj] = nxt[si][sj];
+                for (int sj = 0; sj < 2; ++sj) {
+                    acc[si][sj] = nxt[si][sj];
+                    if constexpr (PF > 1) nxt[si][sj] = nxt2[si][sj];
+                }
         }
     }
 }
 
-// FP64: register tiles of 4 x 4 per thread on the vector ALUs
-template <int NBP, int OP>
-__device__ __forceinline__ void trailing_update(double *A, int m, int ld, int j0, int nb, int cb, int ncb, const double *pan,
-                                                const double *ut)
+// FP64 on MFMA (v_mfma_f64_16x16x4f64; operands as in FP32, accumulator lane
+// l register i -> (row l/16 + 4i, col l%16)): each wave walks 32 x 32 tiles
+// of the column block, the next tile's C block loaded before the current one
+// is computed
+template <int NBP, int OP, int NTH = LU_THREADS, int PF = 1>
+__device__ __forceinline__ void trailing_update(double *A, int m, int ld, int j0, int nb, int cb, int ncb,
+                                                const double *pan, const double *ut)
 {
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r0 = j0 + nb;
-    for (int R = r0; R < m; R += 64) {
-        for (int C = cb; C < cb + ncb; C += 64) {
-            double acc[4][4];
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) {
-                    int row = R + ty + 16 * i, col = C + tx + 16 * j;
-                    acc[i][j] = (row < m && col < cb + ncb) ? A[(long long)row * ld + col] : 0.0;
-                }
-            for (int k = 0; k < nb; ++k) {
-                double a[4], b[4];
+    const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32, ntile = nrt * nct;
+    auto load = [&](int t, doublex4_t (&c)[2][2]) {
+        const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
+#pragma unroll
+        for (int si = 0; si < 2; ++si)
+#pragma unroll
+            for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    int row = R + ty + 16 * i;
-                    a[i] = row < m ? pan[(row - j0) * NBP + k] : 0.0;
+                    const int row = R + 16 * si + (lane >> 4) + 4 * i, col = C + 16 * sj + (lane & 15);
+                    c[si][sj][i] = (row < m && col < cb + ncb) ? A[(long long)row * ld + col] : 0.0;
                 }
-                for (int j = 0; j < 4; ++j) b[j] = ut[k * LU_CB + (C - cb) + tx + 16 * j];
-                for (int i = 0; i < 4; ++i)
-                    for (int j = 0; j < 4; ++j) acc[i][j] -= a[i] * b[j];
+    };
+    constexpr int S = NTH / 64;
+    doublex4_t acc[2][2], nxt[2][2], nxt2[2][2];
+    if (wv < ntile) load(wv, acc);
+    if constexpr (PF > 1)
+        if (wv + S < ntile) load(wv + S, nxt);
+    for (int t = wv; t < ntile; t += S) {
+        const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
+        const int tn = t + S;
+        if constexpr (PF > 1) {
+            if (t + 2 * S < ntile) load(t + 2 * S, nxt2);
+        } else {
+            if (tn < ntile) load(tn, nxt);
+        }
+        for (int k0 = 0; k0 < nb; k0 += 4) {
+            const int k = k0 + (lane >> 4);
+            double a[2], b[2];
+#pragma unroll
+            for (int si = 0; si < 2; ++si) {
+                const int row = R + 16 * si + (lane & 15);
+                a[si] = (row < m && k < nb) ? -pan[(row - j0) * NBP + k] : 0.0;
             }
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) {
-                    int row = R + ty + 16 * i, col = C + tx + 16 * j;
-                    if (row < m && col < cb + ncb) A[(long long)row * ld + col] = acc[i][j];
+#pragma unroll
+            for (int sj = 0; sj < 2; ++sj) b[sj] = k < nb ? ut[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)] : 0.0;
+#pragma unroll
+            for (int si = 0; si < 2; ++si)
+#pragma unroll
+                for (int sj = 0; sj < 2; ++sj)
+                    acc[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[si], b[sj], acc[si][sj], 0, 0, 0);
+        }
+#pragma unroll
+        for (int si = 0; si < 2; ++si)
+#pragma unroll
+            for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = R + 16 * si + (lane >> 4) + 4 * i, col = C + 16 * sj + (lane & 15);
+                    if (row < m && col < cb + ncb) A[(long long)row * ld + col] = acc[si][sj][i];
+                }
+        if (tn < ntile) {
+#pragma unroll
+            for (int si = 0; si < 2; ++si)
+#pragma unroll
+                for (int sj = 0; sj < 2; ++sj) {
+                    acc[si][sj] = nxt[si][sj];
+                    if constexpr (PF > 1) nxt[si][sj] = nxt2[si][sj];
                 }
         }
     }
@@ -1068,29 +1119,25 @@ __device__ __forceinline__ void compose_panel_swaps(const int *sw, int nb, int *
     if (lane == 0) *n_aff = __popcll(mm);
 }
 
-template <typename T, int NB, int OP = 0>
-__global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, int *__restrict__ pivall, LuBatch B,
-                                                        int *info)
+// LU with partial pivoting of one m x m matrix (row stride ld) by the whole
+// workgroup with panels of NB columns in LDS (lds_raw: lu_lds_bytes<NB, T>(m))
+template <typename T, int NB, int OP, int NTH = LU_THREADS, int PF = 1>
+__device__ __forceinline__ void lu_one(T *__restrict__ A, int m, int ld, int *__restrict__ piv, int *info,
+                                       unsigned char *lds_raw)
 {
     constexpr int NBP = NB + 1;
-    extern __shared__ unsigned char lds_raw[];
-    const int bid = blockIdx.x;
-    const int m = B.m_of ? B.m_of[bid] : B.uniform_m;
-    const int ld = B.uniform_ld > 0 ? B.uniform_ld : m;   // row stride
-    T *A = Aall + (B.a_off ? B.a_off[bid] : (long long)bid * m * ld);
-    int *piv = pivall + (B.p_off ? B.p_off[bid] : (long long)bid * m);
     T *pan = reinterpret_cast<T *>(lds_raw);          // [m][NBP] panel rows
     T *ut = pan + (size_t)m * NBP;                     // [NB][LU_CB] U12 block
     T *stg = ut + (size_t)NB * LU_CB;                  // [2 NB][LU_SWC] row interchange staging
-    __shared__ T rv[LU_THREADS / 64];
-    __shared__ int ri[LU_THREADS / 64];
+    __shared__ T rv[NTH / 64];
+    __shared__ int ri[NTH / 64];
     __shared__ int sw[NB];
     __shared__ int aff_src[2 * NB], aff_dst[2 * NB];
     __shared__ int n_aff;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int j0 = 0; j0 < m; j0 += NB) {
         const int nb = min(NB, m - j0), mr = m - j0;
-        for (int e = tid; e < mr * nb; e += LU_THREADS) {
+        for (int e = tid; e < mr * nb; e += NTH) {
             int r = e / nb, c = e % nb;
             pan[r * NBP + c] = A[(long long)(j0 + r) * ld + j0 + c];
         }
@@ -1098,7 +1145,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
         for (int c = 0; c < nb; ++c) {
             T best = T(-1);
             int bi = c;
-            for (int r = c + tid; r < mr; r += LU_THREADS) {
+            for (int r = c + tid; r < mr; r += NTH) {
                 T v = fabs(pan[r * NBP + c]);
                 if (v > best) { best = v; bi = r; }
             }
@@ -1111,7 +1158,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
             __syncthreads();
             T bv = rv[0];
             int p = ri[0];
-            for (int w = 1; w < LU_THREADS / 64; ++w)
+            for (int w = 1; w < NTH / 64; ++w)
                 if (rv[w] > bv || (rv[w] == bv && ri[w] < p)) { bv = rv[w]; p = ri[w]; }
             if (tid == 0) {
                 piv[j0 + c] = j0 + p;
@@ -1126,7 +1173,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
             __syncthreads();
             const T d = pan[c * NBP + c];
             const T inv = d != T(0) ? T(1) / d : T(0);
-            for (int r = c + 1 + tid; r < mr; r += LU_THREADS) {
+            for (int r = c + 1 + tid; r < mr; r += NTH) {
                 T l = pan[r * NBP + c] * inv;
                 pan[r * NBP + c] = l;
                 for (int cc = c + 1; cc < nb; ++cc) pan[r * NBP + cc] -= l * pan[c * NBP + cc];
@@ -1141,12 +1188,12 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
         if (na > 0) {
             for (int c0 = 0; c0 < m; c0 += LU_SWC) {
                 const int nc = min(LU_SWC, m - c0);
-                for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
+                for (int e = tid; e < na * LU_SWC; e += NTH) {
                     int i = e / LU_SWC, j = e % LU_SWC;
                     if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * ld + c0 + j];
                 }
                 __syncthreads();
-                for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
+                for (int e = tid; e < na * LU_SWC; e += NTH) {
                     int i = e / LU_SWC, j = e % LU_SWC;
                     if (j < nc) A[(long long)(j0 + aff_dst[i]) * ld + c0 + j] = stg[i * LU_SWC + j];
                 }
@@ -1154,7 +1201,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
             }
         }
         // write the factored panel back
-        for (int e = tid; e < mr * nb; e += LU_THREADS) {
+        for (int e = tid; e < mr * nb; e += NTH) {
             int r = e / nb, c = e % nb;
             A[(long long)(j0 + r) * ld + j0 + c] = pan[r * NBP + c];
         }
@@ -1162,7 +1209,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
         // U12 = L11^{-1} A12 and the trailing update, one column block at a time
         for (int cb = j0 + nb; cb < m; cb += LU_CB) {
             const int ncb = min(LU_CB, m - cb);
-            for (int e = tid; e < NB * LU_CB; e += LU_THREADS) ut[e] = T(0);
+            for (int e = tid; e < NB * LU_CB; e += NTH) ut[e] = T(0);
             __syncthreads();
             if (tid < ncb) {
                 const int col = cb + tid;
@@ -1183,9 +1230,55 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, in
                     }
             }
             __syncthreads();
-            trailing_update<NBP, OP>(A, m, ld, j0, nb, cb, ncb, pan, ut);
+            trailing_update<NBP, OP, NTH, PF>(A, m, ld, j0, nb, cb, ncb, pan, ut);
             __syncthreads();
         }
+    }
+}
+
+
+template <typename T, int NB, int OP = 0>
+__global__ void __launch_bounds__(LU_THREADS) lu_kernel(T *__restrict__ Aall, int *__restrict__ pivall, LuBatch B,
+                                                        int *info)
+{
+    extern __shared__ unsigned char lds_raw[];
+    const int bid = blockIdx.x;
+    const int m = B.m_of ? B.m_of[bid] : B.uniform_m;
+    const int ld = B.uniform_ld > 0 ? B.uniform_ld : m;   // row stride
+    T *A = Aall + (B.a_off ? B.a_off[bid] : (long long)bid * m * ld);
+    int *piv = pivall + (B.p_off ? B.p_off[bid] : (long long)bid * m);
+    lu_one<T, NB, OP>(A, m, ld, piv, info, lds_raw);
+}
+
+// Persistent batched LU of matrices of mixed sizes: a fixed grid of
+// workgroups takes matrices from a device work queue (the metadata sorted by
+// decreasing size, a counter that starts at zero) until the queue is empty;
+// each matrix is factored with the panel width nb_of[i] (16, 8 or 4) chosen
+// on the host, whose panel fits the launch's LDS (32-wide panels are left
+// out: their register arrays would set the register count, and with it the
+// occupancy, of every matrix of the launch).  Every thread of a workgroup reads the
+// same queue position, so the whole workgroup leaves the loop together.
+template <typename T, int OP, int NTH>
+__global__ void __launch_bounds__(NTH) lu_queue_kernel(T *__restrict__ Aall, int *__restrict__ pivall,
+                                                              LuQueue Q, int *info)
+{
+    extern __shared__ unsigned char lds_raw[];
+    __shared__ int item;
+    for (;;) {
+        if (threadIdx.x == 0) item = atomicAdd(Q.counter, 1);
+        __syncthreads();
+        const int i = item;
+        __syncthreads();
+        if (i >= Q.batch) break;
+        const int m = Q.m_of[i];
+        T *A = Aall + Q.a_off[i];
+        int *piv = pivall + Q.p_off[i];
+        switch (Q.nb_of[i]) {
+        case 16: lu_one<T, 16, OP, NTH, 2>(A, m, m, piv, info, lds_raw); break;
+        case 8: lu_one<T, 8, OP, NTH, 2>(A, m, m, piv, info, lds_raw); break;
+        default: lu_one<T, 4, OP, NTH, 2>(A, m, m, piv, info, lds_raw); break;
+        }
+        __syncthreads();
     }
 }
 
@@ -2666,6 +2759,44 @@ hipError_t launch_lu(T *A, int *piv, int m, int batch, int *info, size_t max_lds
     return hipErrorInvalidConfiguration;
 }
 
+size_t lu_panel_lds_bytes(int nb, int m, bool f64)
+{
+    if (f64)
+        return nb == 32 ? lu_lds_bytes<32, double>(m) : nb == 16 ? lu_lds_bytes<16, double>(m)
+             : nb == 8 ? lu_lds_bytes<8, double>(m) : lu_lds_bytes<4, double>(m);
+    return nb == 32 ? lu_lds_bytes<32, float>(m) : nb == 16 ? lu_lds_bytes<16, float>(m)
+         : nb == 8 ? lu_lds_bytes<8, float>(m) : lu_lds_bytes<4, float>(m);
+}
+
+template <typename T>
+hipError_t launch_lu_queue(T *A, int *piv, const LuQueue &q, size_t lds_bytes, int grid, int threads, int *info,
+                           hipStream_t s, int op)
+{
+    if (op < 0 || op > 2 || (op != 0 && !std::is_same<T, float>::value) || grid < 1) return hipErrorInvalidValue;
+    if (threads != 256 && threads != 512) return hipErrorInvalidValue;
+    if (q.batch <= 0) return hipSuccess;
+#define LUQ(OPV, NTV)                                                                                                  \
+    {                                                                                                                  \
+        hipError_t e = lds_attr((const void *)lu_queue_kernel<T, OPV, NTV>, lds_bytes);                                \
+        if (e != hipSuccess) return e;                                                                                 \
+        hipLaunchKernelGGL((lu_queue_kernel<T, OPV, NTV>), dim3(grid), dim3(NTV), lds_bytes, s, A, piv, q, info);      \
+        return hipGetLastError();                                                                                      \
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        if (op == 1) {
+            if (threads == 512) LUQ(1, 512)
+            LUQ(1, 256)
+        }
+        if (op == 2) {
+            if (threads == 512) LUQ(2, 512)
+            LUQ(2, 256)
+        }
+    }
+    if (threads == 512) LUQ(0, 512)
+    LUQ(0, 256)
+#undef LUQ
+}
+
 template <typename T, typename TP>
 hipError_t launch_solve(int dim, int r, const SolveArgs<T, TP> &a, int ncell, int m, hipStream_t s)
 {
@@ -3065,6 +3196,9 @@ template hipError_t launch_patch<double, double>(int, int, const PatchArgs<doubl
 template hipError_t launch_patch<float, float>(int, int, const PatchArgs<float, float> &, int, hipStream_t);
 template hipError_t launch_patch<double, float>(int, int, const PatchArgs<double, float> &, int, hipStream_t);
 template hipError_t launch_lu<double>(double *, int *, int, int, int *, size_t, hipStream_t, const LuBatch *, int);
+template hipError_t launch_lu_queue<double>(double *, int *, const LuQueue &, size_t, int, int, int *, hipStream_t,
+                                            int);
+template hipError_t launch_lu_queue<float>(float *, int *, const LuQueue &, size_t, int, int, int *, hipStream_t, int);
 template hipError_t launch_lu<float>(float *, int *, int, int, int *, size_t, hipStream_t, const LuBatch *, int);
 template hipError_t launch_solve<double, double>(int, int, const SolveArgs<double, double> &, int, int, hipStream_t);
 template hipError_t launch_solve<float, float>(int, int, const SolveArgs<float, float> &, int, int, hipStream_t);

@@ -64,7 +64,8 @@ class Request(ctypes.Structure):
 
 class RequestResult(ctypes.Structure):
     _fields_ = [("start_s", ctypes.c_double), ("end_s", ctypes.c_double), ("latency_s", ctypes.c_double),
-                ("rc", ctypes.c_int), ("footprint", ctypes.c_size_t), ("stats", Stats)]
+                ("rc", ctypes.c_int), ("footprint", ctypes.c_size_t), ("stats", Stats),
+                ("reused_context", ctypes.c_int)]
 
 
 _lib = None
@@ -73,9 +74,12 @@ _lib = None
 _SIGS = {
     "stmg_default_options": (None, [ctypes.c_void_p]),
     "stmg_footprint_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_void_p]),
-    "stmg_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_workspace_used": (ctypes.c_size_t, [ctypes.c_void_p]),
     "stmg_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "stmg_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "stmg_set_coefficients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]),
     "stmg_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "stmg_set_slab_data": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "stmg_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -112,6 +116,9 @@ _SIGS = {
     "stmg_level_patch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "stmg_batched_lu": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "stmg_batched_lu_config": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "stmg_batched_lu_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p]),
@@ -178,13 +185,15 @@ def _host_i64(a):
 STMG_NOALLOC_MAX_BATCH = 65536
 
 
-def batched_lu(A, a_off, m_of, piv, p_off, info=None, prec=None, noalloc=False):
+def batched_lu(A, a_off, m_of, piv, p_off, info=None, prec=None, noalloc=False, config=None):
     """Factor a batch of row-major matrices of mixed sizes in place (device
     tensors A (float64/float32) and piv (int32); host offsets and sizes).
     prec: None (from the dtype of A), or STMG_F32_BF16 / STMG_F32_F16 for
     float32 A with 16-bit operands in the trailing-update MFMA.  noalloc:
     call stmg_batched_lu_noalloc (metadata staged in the library's fixed
-    per-device array, batch <= STMG_NOALLOC_MAX_BATCH)."""
+    per-device array, batch <= STMG_NOALLOC_MAX_BATCH).  config: (wg_per_cu,
+    [nb per size class], threads) for stmg_batched_lu_config (wg_per_cu 0 =
+    one launch per size class; threads 256 or 512, default 256)."""
     import numpy as np
     ao, po = _host_i64(a_off), _host_i64(p_off)
     mo = np.ascontiguousarray(m_of, dtype=np.int32)
@@ -192,9 +201,17 @@ def batched_lu(A, a_off, m_of, piv, p_off, info=None, prec=None, noalloc=False):
         prec = STMG_F64 if A.dtype == torch.float64 else STMG_F32
     elif (prec == STMG_F64) != (A.dtype == torch.float64):
         raise StmgError("prec does not match the dtype of A")
-    f = lib().stmg_batched_lu_noalloc if noalloc else lib().stmg_batched_lu
-    rc = f(prec, _ptr(A), ao.ctypes.data, mo.ctypes.data, len(mo), _ptr(piv), po.ctypes.data,
-           _ptr(info) if info is not None else None, _stream_ptr())
+    ip = _ptr(info) if info is not None else None
+    if config is not None:
+        nbc = np.ascontiguousarray(config[1] if config[0] else [16] * 5, dtype=np.int32)
+        threads = int(config[2]) if len(config) > 2 else 256
+        rc = lib().stmg_batched_lu_config(prec, _ptr(A), ao.ctypes.data, mo.ctypes.data, len(mo), _ptr(piv),
+                                          po.ctypes.data, ip, int(config[0]), threads, nbc.ctypes.data,
+                                          _stream_ptr())
+    else:
+        f = lib().stmg_batched_lu_noalloc if noalloc else lib().stmg_batched_lu
+        rc = f(prec, _ptr(A), ao.ctypes.data, mo.ctypes.data, len(mo), _ptr(piv), po.ctypes.data, ip,
+               _stream_ptr())
     if rc != 0:
         raise StmgError(f"stmg_batched_lu{'_noalloc' if noalloc else ''} failed ({rc})")
 
@@ -263,8 +280,15 @@ class Context:
         p, self._vert = make_problem(dim, n, r, k, nu, tau, vertices, dirichlet_faces, gamma1, gamma2)
         self.problem = p
         self.options = options if options is not None else default_options(**opt_overrides)
+        # the whole device memory of the context: one torch buffer of the
+        # footprint (torch stays the only allocator); kept alive with the context
+        self.footprint = footprint_bytes(p, self.options)
+        if self.footprint == 0:
+            raise StmgError("stmg_footprint_bytes rejected the problem or options")
+        self._workspace = torch.empty(self.footprint, dtype=torch.uint8, device="cuda")
         h = ctypes.c_void_p()
-        rc = lib().stmg_create(ctypes.byref(p), ctypes.byref(self.options), _stream_ptr(), ctypes.byref(h))
+        rc = lib().stmg_create(ctypes.byref(p), ctypes.byref(self.options), _ptr(self._workspace), self.footprint,
+                               _stream_ptr(), ctypes.byref(h))
         if rc != 0:
             raise StmgError(f"stmg_create failed with code {rc}")
         self._h = h
@@ -283,6 +307,11 @@ class Context:
         if getattr(self, "_h", None):
             lib().stmg_destroy(self._h)
             self._h = None
+        self._workspace = None
+
+    def workspace_used(self):
+        """Bytes of the workspace the context laid out."""
+        return int(lib().stmg_workspace_used(self._h))
 
     def __del__(self):
         try:

@@ -72,7 +72,7 @@ def test_options_outside_their_ranges_are_rejected_before_any_device_work(bad):
     o = stmg.default_options(**bad)
     assert stmg.footprint_bytes(p, o) == 0
     h = ctypes.c_void_p()
-    assert stmg.lib().stmg_create(ctypes.byref(p), ctypes.byref(o), None, ctypes.byref(h)) == stmg.STMG_EINVAL
+    assert stmg.lib().stmg_create(ctypes.byref(p), ctypes.byref(o), None, 0, None, ctypes.byref(h)) == stmg.STMG_EINVAL
     assert not h.value
 
 
@@ -85,7 +85,22 @@ def test_meshes_beyond_32_bit_transfer_indices_are_rejected(dim, n, r):
     o = stmg.default_options()
     assert stmg.footprint_bytes(p, o) == 0
     h = ctypes.c_void_p()
-    assert stmg.lib().stmg_create(ctypes.byref(p), ctypes.byref(o), None, ctypes.byref(h)) == stmg.STMG_EINVAL
+    assert stmg.lib().stmg_create(ctypes.byref(p), ctypes.byref(o), None, 0, None, ctypes.byref(h)) == stmg.STMG_EINVAL
     assert not h.value
     ok, _ = stmg.make_problem(dim, (64,) * dim if dim == 3 else (1000,) * dim, r, 1, 1e-3, 1 / 64)
     assert stmg.footprint_bytes(ok, o) > 0
+
+
+def test_footprint_is_deterministic_and_option_dependent():
+    """The footprint is the byte count of the context's own construction run
+    without device memory: repeatable, a multiple of 256, and it grows with
+    every buffer an option adds (FP64 multigrid, BF16 factor copy, diagonal
+    Vanka, full space-time patches, captured V-cycle staging)."""
+    p, _ = stmg.make_problem(3, (4, 4, 4), 2, 1, 1e-2, 0.1)
+    base = stmg.footprint_bytes(p, stmg.default_options())
+    assert base > 0 and base % 256 == 0 and base == stmg.footprint_bytes(p, stmg.default_options())
+    for opt in (dict(prec_mg=stmg.STMG_F64), dict(vanka_factor_bf16=1), dict(vanka_diagonal=1),
+                dict(vanka_time_decoupled=0)):
+        assert stmg.footprint_bytes(p, stmg.default_options(**opt)) > base, opt
+    assert stmg.footprint_bytes(p, stmg.default_options(use_graphs=0)) < base
+    assert stmg.footprint_bytes(p, stmg.default_options(fgmres_maxit=20)) < base

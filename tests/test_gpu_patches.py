@@ -132,3 +132,38 @@ def test_batched_lu_16bit_update_operands(which, stmg):
         be = np.max(np.abs(M @ xi - rhs[i])) / (np.max(np.abs(M).sum(1)) * np.max(np.abs(xi)) +
                                                 np.max(np.abs(rhs[i])))
         assert be < 4 * u * rho + 2e-6, (i, sizes[i], be, rho)
+
+
+@pytest.mark.parametrize("config", [(0, None), (1, [16] * 5), (2, [8] * 5, 512), (3, [4, 8, 16, 16, 8]),
+                                    (1, [16] * 5, 512), (4, [16, 16, 8, 4, 4])],
+                         ids=lambda c: f"wg{c[0]}_t{c[2] if len(c) > 2 else 256}")
+def test_batched_lu_launch_configurations(config, stmg):
+    """The persistent work-queue factorization with any workgroups-per-CU /
+    panel-width setting the tuner may choose (and the one-launch-per-size-
+    class reference): every solve has a normwise backward error at the
+    precision's level, and the zero-pivot count is zero."""
+    rng = np.random.Generator(np.random.PCG64(19))
+    sizes = [int(m) for m in rng.choice([85, 170, 202, 255, 395, 404, 606, 790, 1185], 23)] + [1, 2, 33]
+    mats = []
+    for i, m in enumerate(sizes):
+        A = I.uniform(m * m, 500 + i).reshape(m, m)
+        A[np.arange(m), np.arange(m)] += 0.5 * m ** 0.5
+        mats.append(A)
+    m64 = np.array(sizes, dtype=np.int64)
+    a_off = np.concatenate([[0], np.cumsum(m64 ** 2)[:-1]])
+    p_off = np.concatenate([[0], np.cumsum(m64)[:-1]])
+    rhs = [I.uniform(m, 900 + i) for i, m in enumerate(sizes)]
+    for dt, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+        A = torch.tensor(np.concatenate([M.ravel() for M in mats]), dtype=dt, device="cuda")
+        piv = torch.zeros(int(m64.sum()), dtype=torch.int32, device="cuda")
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        stmg.batched_lu(A, a_off, sizes, piv, p_off, info, config=config)
+        b = torch.tensor(np.concatenate(rhs), dtype=dt, device="cuda")
+        stmg.batched_lu_solve(A, a_off, sizes, piv, p_off, b, p_off)
+        x = b.double().cpu().numpy()
+        assert int(info.item()) == 0
+        for i, M in enumerate(mats):
+            xi = x[p_off[i]: p_off[i] + sizes[i]]
+            be = np.max(np.abs(M @ xi - rhs[i])) / (np.max(np.abs(M).sum(1)) * np.max(np.abs(xi)) +
+                                                    np.max(np.abs(rhs[i])))
+            assert be < tol, (config, dt, i, sizes[i], be)

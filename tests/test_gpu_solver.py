@@ -556,3 +556,119 @@ def test_served_results_match_oracle(prec, stmg):
             assert err < 1e-7
         else:
             assert err < 1e-6
+
+
+def test_scaled_c3_solve_matches_oracle(stmg):
+    """The scaled analogue of the 32^3 solve benchmark: 8^3 hexes perturbed by
+    0.2h, Q4/P3disc x DG(1), nu = 1e-3 (Re = 1000), tau = 1/64, smooth
+    previous-slab velocity, ||R||_M <= 1e-8 ||R_0||_M.  Expected values: the
+    oracle's solve, stored by tests/golden/make_scaled_c3.py.  With the
+    multigrid in FP64 the Newton, FGMRES and rebuild counts equal the
+    oracle's and the sampled solution entries agree to 1e-7 (pressure up to
+    the constant of each time node); with the default FP32 multigrid the
+    counts are reported and the solution agrees to 1e-6."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "scaled_c3_8cube_r3k1.json")))
+    s = gold["spec"]
+    n = (s["n"],) * 3
+    vert = I.perturbed_vertices(3, n, s["pert"], s["vert_seed"])
+    vprev = I.smooth_velocity(3, n, s["r"], s["vprev_seed"])
+    prob = oracle.Problem(dim=3, n=n, r=s["r"], k=s["k"], nu=s["nu"], tau=s["tau"], vertices=vert)
+    slab = oracle.Slab(prob)
+    idx = np.array(gold["sample_index"])
+    want = np.array(gold["sample_value"])
+    npm = slab.space.npm
+    pbase = slab.nt * slab.Nv
+    is_p0 = (idx >= pbase) & (((idx - pbase) % slab.Np) % npm == 0)
+    node_of = np.where(idx >= pbase, (idx - pbase) // slab.Np, 0)
+    want = want - np.where(is_p0, np.array(gold["pressure_mode0_mean"])[node_of], 0.0)
+    for prec in (stmg.STMG_F64, stmg.STMG_F32):
+        ctx = stmg.Context(3, n, s["r"], s["k"], s["nu"], s["tau"], vertices=vert, prec_mg=prec)
+        assert ctx.N == gold["N"]
+        ctx.set_slab_data(None, dev(vprev))
+        u, st, rc = ctx.newton_solve(torch.zeros(ctx.N, dtype=torch.float64, device="cuda"))
+        U = u.cpu().numpy()
+        P = U[pbase:].reshape(slab.nt, -1)
+        means = [P[a, ::npm].mean() for a in range(slab.nt)]
+        got = U[idx] - np.where(is_p0, np.array(means)[node_of], 0.0)
+        err = float(np.max(np.abs(got - want)) / max(gold["max_abs_velocity"], gold["max_abs_pressure"]))
+        counts = list(st.fgmres_its[: st.newton_its])
+        print(f"{'f64' if prec == stmg.STMG_F64 else 'f32'} multigrid: newton {st.newton_its} fgmres {counts} "
+              f"rebuilds {st.rebuilds} (oracle {gold['newton_its']} {gold['fgmres_its']} {gold['rebuilds']}), "
+              f"sampled rel err {err:.1e}, {st.wall_s:.2f} s", flush=True)
+        assert rc == 0
+        if prec == stmg.STMG_F64:
+            assert st.newton_its == gold["newton_its"] and counts == gold["fgmres_its"]
+            assert st.rebuilds == gold["rebuilds"]
+            assert abs(st.res0_M - gold["res0_M"]) <= 1e-12 * gold["res0_M"]
+            assert err < 1e-7
+        else:
+            assert err < 1e-6
+
+
+def test_serving_context_pool_reuse_is_exact(stmg):
+    """Requests of one discretization but different viscosities served in
+    turn on one slot reuse a pooled context (only nu and tau reset); each
+    result is bitwise the result of the same request on a fresh context."""
+    base = [(2, (4, 4), 1, 1), (3, (2, 2, 2), 2, 1)]
+    reqs = []
+    for j, nu in enumerate((1.0, 1e-2, 1e-3, 1.0)):
+        for i, (d, n, r, k) in enumerate(base):
+            reqs.append(dict(dim=d, n=n, r=r, k=k, nu=nu, tau=0.1 if j % 2 else 0.05, arrival_s=0.0,
+                             v_prev=I.smooth_velocity(d, n, r, 300 + i)))
+    served, res, _ = stmg.serve(reqs, stmg.default_options(), slots=1)
+    assert sum(r.reused_context for r in res) == len(reqs) - len(base)
+    for i, q in enumerate(reqs):
+        alone, res1, _ = stmg.serve([q], stmg.default_options(), slots=1)
+        assert res1[0].reused_context == 0 and res[i].rc == 0
+        assert np.array_equal(alone[0], served[i]), i
+        assert res1[0].stats.newton_its == res[i].stats.newton_its
+
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(d=2, n=(4, 4), r=1, k=1, opt={}),
+    dict(d=3, n=(4, 4, 4), r=2, k=2, opt=dict(prec_mg=1)),
+    dict(d=3, n=(3, 3, 3), r=1, k=1, opt=dict(vanka_diagonal=2)),
+    dict(d=3, n=(4, 4, 4), r=3, k=1, opt=dict(vanka_factor_bf16=1), pert=True),
+    dict(d=2, n=(6, 6), r=2, k=0, opt=dict(prec_mg=0, vanka_time_decoupled=0, use_graphs=0)),
+], ids=lambda c: f"{c['d']}d_n{c['n'][0]}_r{c['r']}k{c['k']}_{'_'.join(f'{a}{b}' for a, b in c['opt'].items())}")
+def test_workspace_is_the_whole_footprint(cfg, stmg):
+    """All device memory of a context sits in the caller's workspace of
+    stmg_footprint_bytes bytes: the context lays out exactly that many bytes
+    (up to the final 256-byte rounding), and creation plus a Newton solve
+    allocate nothing outside torch's allocator (device memory taken outside
+    torch, after one warm-up run of the same configuration has loaded the
+    code objects, at most 4 MiB: the runtime's own graph and kernel-argument
+    objects)."""
+    import gc
+    d, n, r, k = cfg["d"], cfg["n"], cfg["r"], cfg["k"]
+    vert = I.perturbed_vertices(d, n, 0.2, 3) if cfg.get("pert") else None
+    opts = {"prec_mg": stmg.STMG_F32, **cfg["opt"]}
+    p, _ = stmg.make_problem(d, n, r, k, 1e-2, 0.1, vertices=vert)
+    fp = stmg.footprint_bytes(p, stmg.default_options(**opts))
+    vprev = dev(I.smooth_velocity(d, n, r, 9))
+
+    def run():
+        ctx = stmg.Context(d, n, r, k, 1e-2, 0.1, vertices=vert, **opts)
+        ctx.set_slab_data(None, vprev)
+        u, st, rc = ctx.newton_solve(torch.zeros(ctx.N, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        return ctx, u, rc
+
+    ctx, u, rc = run()                  # warm-up: code objects of this configuration
+    assert rc == 0 and ctx.footprint == fp
+    assert fp - 256 < ctx.workspace_used() <= fp
+    del ctx, u
+    gc.collect()
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    res0 = torch.cuda.memory_reserved()
+    ctx, u, rc = run()
+    free1, _ = torch.cuda.mem_get_info()
+    res1 = torch.cuda.memory_reserved()
+    outside_torch = (free0 - free1) - (res1 - res0)
+    print(f"footprint {fp} B, laid out {ctx.workspace_used()} B, device memory outside torch {outside_torch} B")
+    assert rc == 0
+    assert outside_torch <= 4 << 20
