@@ -811,6 +811,533 @@ __global__ void __launch_bounds__(NTH) cell_kernel(CellArgs<T> A)
 }
 
 // ---------------------------------------------------------------------------
+// 3D Jacobian volume kernel (eq. JacobianLocal, convective part eq. Defcp).
+//
+// Same cell / time-node decomposition as cell_kernel, different contraction
+// order: the reference gradient of the direction field is obtained by
+// contracting with the nodal derivative table D along the axis in question
+// (z and y during the first two sweeps, x in the last), not by collocation at
+// the Gauss points.  The last forward contraction then needs only rows that
+// the earlier sweeps left in LDS, so one thread per quadrature point finishes
+// the interpolation, evaluates the point physics and writes its 13
+// coefficients; three sweeps take them back to the nodes and the last one
+// writes E and the pressure rows from registers.  Per time node that is six
+// barrier-separated stages (z, y, x + physics, x^T, y^T, z^T).  The
+// time-mixed field sum_b K_ab x^b is formed while loading the z columns.
+// Every item type of a stage starts on a wavefront boundary so that no
+// wavefront executes two item types.
+// ---------------------------------------------------------------------------
+constexpr int al64(int v) { return (v + 63) & ~63; }
+constexpr int al4(int v) { return (v + 3) & ~3; }
+
+template <int R, int NQ> struct JacLds {
+    static constexpr int N1 = R + 2, RP1 = R + 1, NL = N1 * N1 * N1, NQV = NQ * NQ * NQ;
+    static constexpr int QN2 = NQ * N1 * N1;     // one field after the z sweep [qz][j][i]
+    static constexpr int QQN = NQ * NQ * N1;     // one field after the y sweep [qz][qy][i]
+    // 1D tables (rows per quadrature point for the thread-per-point stage)
+    static constexpr int TS = 0, TD = TS + NQ * N1, TL = TD + NQ * N1, QW = TL + NQ * RP1, QX = QW + NQ;
+    static constexpr int GEO = al4(QX + NQ);     // [8][3] vertices (mapped cells)
+    // region P: z-sweep results (xhat along z by S and by D, state, mixed field,
+    // pressure), then the point record [13][NQV], then the y^T results; the
+    // nodal state of the next time node sits behind the z-sweep results
+    static constexpr int ZXS = 0, ZXD = 3 * QN2, ZS = 6 * QN2, ZM = 9 * QN2, ZP = 12 * QN2;
+    static constexpr int NSO = al4(ZP + NQ * RP1 * RP1);
+    static constexpr int WA = 0, WC = 3 * QN2, WP = 6 * QN2;
+    static constexpr int RPW = al4(NSO + 3 * NL > 13 * NQV ? NSO + 3 * NL : 13 * NQV);
+    // region Y: y-sweep results (xhat: S_y S_z, D_y S_z, S_y D_z; state; mixed;
+    // pressure), then the x^T results (value + x-gradient, y-gradient,
+    // z-gradient coefficients; pressure)
+    static constexpr int YSS = 0, YDS = 3 * QQN, YSD = 6 * QQN, YS = 9 * QQN, YM = 12 * QQN, YP = 15 * QQN;
+    static constexpr int BA = 0, BB = 3 * QQN, BC = 6 * QQN, BP = 9 * QQN;
+    static constexpr int RYW = al4(15 * QQN + NQ * NQ * RP1);
+    static constexpr int RP = GEO + 24, RY = RP + RPW;
+    // then [nt][NPF] pressure modes and [nt][3][NL] nodal x of all time nodes
+    static constexpr int XP0 = RY + RYW;
+    static_assert(WP + NQ * RP1 * RP1 <= NSO, "y^T results stay clear of the nodal state");
+};
+
+template <int R, int NQ, typename T>
+__host__ __device__ constexpr int jac_lds_words(int nt)
+{
+    using LY = JacLds<R, NQ>;
+    return LY::XP0 + nt * ((R + 1) * (R + 1) * (R + 1) + 3 * LY::NL);
+}
+
+// position of the pressure multi-index (i0, i1, i2) in the admissible
+// ordering of pmode_full (first index fastest), or -1 if its degree exceeds R
+template <int R>
+__device__ __forceinline__ int pmode_compact(int i0, int i1, int i2)
+{
+    if (i0 + i1 + i2 > R) return -1;
+    int cnt = 0;
+    for (int a2 = 0; a2 < i2; ++a2) cnt += (R - a2 + 1) * (R - a2 + 2) / 2;
+    for (int a1 = 0; a1 < i1; ++a1) cnt += R - i2 - a1 + 1;
+    return cnt + i0;
+}
+
+template <int R, int NQ, int NTH, typename T, bool MAPPED>
+__global__ void __launch_bounds__(NTH) jac_cell_kernel(CellArgs<T> A)
+{
+    using LY = JacLds<R, NQ>;
+    constexpr int N1 = R + 2, RP1 = R + 1, NL = LY::NL, NPF = RP1 * RP1 * RP1, NPM = Sizes<3, R>::NPM;
+    constexpr int NQV = LY::NQV, QN2 = LY::QN2, QQN = LY::QQN, N2 = N1 * N1, RP2 = RP1 * RP1;
+
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    T *tS = sm + LY::TS, *tD = sm + LY::TD, *tL = sm + LY::TL, *qw = sm + LY::QW, *qxs = sm + LY::QX;
+    T *geo = sm + LY::GEO;
+    T *P = sm + LY::RP, *Y = sm + LY::RY;
+    T *NS = P + LY::NSO;
+    const int nt = A.nt;
+    T *XP = sm + LY::XP0;                 // [nt][NPF]
+    T *XS = XP + nt * NPF;                // [nt][3][NL]
+
+    const int tid = threadIdx.x;
+    const int cell = xcd_cell(blockIdx.x, gridDim.x);
+    const int vec = blockIdx.y;
+    const T *__restrict__ x = A.x + vec * A.xstride;
+    T *__restrict__ y = A.y + vec * A.ystride;
+    T *__restrict__ E = A.E + (long long)vec * A.ncell * nt * 3 * NL;
+
+    TableLayout lay;
+    lay.init(R, NQ);
+    // matrices indexed by compile-time row/column in the sweeps: scalar path
+    using CP = const __attribute__((address_space(4))) T *;
+    const CP S = (CP)(A.tab + lay.S), D = (CP)(A.tab + lay.D), L = (CP)(A.tab + lay.L);
+    // rows selected by the point's own x index: from LDS
+    for (int i = tid; i < NQ * N1; i += NTH) {
+        tS[i] = A.tab[lay.S + i];
+        tD[i] = A.tab[lay.D + i];
+    }
+    for (int i = tid; i < NQ * RP1; i += NTH) tL[i] = A.tab[lay.L + i];
+    for (int i = tid; i < NQ; i += NTH) {
+        qw[i] = A.tab[lay.qw + i];
+        qxs[i] = A.tab[lay.qx + i];
+    }
+
+    const int c0 = cell % A.n0;
+    const int c1 = (cell / A.n0) % A.n1;
+    const int c2 = cell / (A.n0 * A.n1);
+    const long long N0 = (long long)(R + 1) * A.n0 + 1;
+    const long long N1g = (long long)(R + 1) * A.n1 + 1;
+    auto gnode = [&](int l) -> long long {
+        int i0 = l % N1, i1 = (l / N1) % N1, i2 = l / N2;
+        long long g0 = (long long)(R + 1) * c0 + i0, g1 = (long long)(R + 1) * c1 + i1;
+        long long g2 = (long long)(R + 1) * c2 + i2;
+        return g0 + N0 * (g1 + N1g * g2);
+    };
+
+    // state of a time node into registers (element e = tid + j * NTH)
+    constexpr int PF = (3 * NL + NTH - 1) / NTH;
+    T spre[PF];
+    const T *st = A.state + vec * A.sstride;
+    auto load_state = [&](int a) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            const int e = tid + j * NTH;
+            if (e < 3 * NL) {
+                const int l = e % NL, c = e / NL;
+                spre[j] = st[a * A.Nv1 + c * A.Nn + gnode(l)];
+            }
+        }
+    };
+    auto store_state = [&]() {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            const int e = tid + j * NTH;
+            if (e < 3 * NL) NS[e] = spre[j];
+        }
+    };
+    load_state(0);
+    for (int e = tid; e < nt * 3 * NL; e += NTH) {
+        const int l = e % NL, c = (e / NL) % 3, a = e / (3 * NL);
+        XS[e] = x[a * A.Nv1 + c * A.Nn + gnode(l)];
+    }
+    const long long pbase = (long long)nt * A.Nv1;
+    constexpr int PP = (MAX_NT * NPM + NTH - 1) / NTH;
+    T ppre[PP];
+#pragma unroll
+    for (int j = 0; j < PP; ++j) {
+        const int e = tid + j * NTH;
+        if (e < nt * NPM) ppre[j] = x[pbase + (e / NPM) * A.Np1 + (long long)cell * NPM + e % NPM];
+    }
+    for (int e = tid; e < nt * NPF; e += NTH) XP[e] = 0;
+    const T hcar[3] = {T(1) / A.n0, T(1) / A.n1, T(1) / A.n2};
+    const T hinv[3] = {T(1) / hcar[0], T(1) / hcar[1], T(1) / hcar[2]};
+    const T det_c = hcar[0] * hcar[1] * hcar[2];
+    if (MAPPED && tid < 8) {
+        const int v = tid, o0 = v & 1, o1 = (v >> 1) & 1, o2 = (v >> 2) & 1;
+        const long long vi = (c0 + o0) + (long long)(A.n0 + 1) * ((c1 + o1) + (long long)(A.n1 + 1) * (c2 + o2));
+        for (int k = 0; k < 3; ++k) geo[v * 3 + k] = T(A.vert[vi * 3 + k]);
+    }
+    store_state();
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PP; ++j) {
+        const int e = tid + j * NTH;
+        if (e < nt * NPM) XP[(e / NPM) * NPF + pmode_full<3, R>(e % NPM)] = ppre[j];
+    }
+    if (nt > 1) load_state(1);
+    __syncthreads();
+
+    for (int a = 0; a < nt; ++a) {
+        // ---- z sweep: xhat by S and D, state and mixed field by S, pressure by L
+        {
+            constexpr int NX = 3 * N2, O1 = al64(NX), O2 = O1 + al64(3 * N2), TOT = O2 + RP2;
+            for (int w = tid; w < TOT; w += NTH) {
+                if (w < NX) {
+                    const int c = w / N2, ji = w - c * N2;
+                    const T *src = XS + (a * 3 + c) * NL + ji;
+                    T u[N1];
+#pragma unroll
+                    for (int k = 0; k < N1; ++k) u[k] = src[k * N2];
+                    T *oS = P + LY::ZXS + c * QN2 + ji, *oD = P + LY::ZXD + c * QN2 + ji;
+#pragma unroll
+                    for (int qz = 0; qz < NQ; ++qz) {
+                        T s = 0, d = 0;
+#pragma unroll
+                        for (int k = 0; k < N1; ++k) {
+                            s += S[qz * N1 + k] * u[k];
+                            d += D[qz * N1 + k] * u[k];
+                        }
+                        oS[qz * N2] = s;
+                        oD[qz * N2] = d;
+                    }
+                } else if (w >= O1 && w < O1 + 3 * N2) {
+                    const int ww = w - O1, c = ww / N2, ji = ww - c * N2;
+                    T u[N1], m[N1];
+#pragma unroll
+                    for (int k = 0; k < N1; ++k) {
+                        u[k] = NS[c * NL + k * N2 + ji];
+                        m[k] = 0;
+                    }
+                    for (int b = 0; b < nt; ++b) {
+                        const T kab = A.K[a * nt + b];
+                        const T *src = XS + (b * 3 + c) * NL + ji;
+#pragma unroll
+                        for (int k = 0; k < N1; ++k) m[k] += kab * src[k * N2];
+                    }
+                    T *os = P + LY::ZS + c * QN2 + ji, *om = P + LY::ZM + c * QN2 + ji;
+#pragma unroll
+                    for (int qz = 0; qz < NQ; ++qz) {
+                        T s = 0, mm = 0;
+#pragma unroll
+                        for (int k = 0; k < N1; ++k) {
+                            s += S[qz * N1 + k] * u[k];
+                            mm += S[qz * N1 + k] * m[k];
+                        }
+                        os[qz * N2] = s;
+                        om[qz * N2] = mm;
+                    }
+                } else if (w >= O2) {
+                    const int ji = w - O2;
+                    const T *src = XP + a * NPF + ji;
+                    T u[RP1];
+#pragma unroll
+                    for (int k = 0; k < RP1; ++k) u[k] = src[k * RP2];
+                    T *op = P + LY::ZP + ji;
+#pragma unroll
+                    for (int qz = 0; qz < NQ; ++qz) {
+                        T s = 0;
+#pragma unroll
+                        for (int k = 0; k < RP1; ++k) s += L[qz * RP1 + k] * u[k];
+                        op[qz * RP2] = s;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // ---- y sweep: xhat -> S_y S_z, D_y S_z, S_y D_z; state, mixed -> S_y; pressure -> L
+        {
+            constexpr int NX = 3 * NQ * N1, O1 = al64(NX), O2 = O1 + al64(3 * NQ * N1), TOT = O2 + NQ * RP1;
+            for (int w = tid; w < TOT; w += NTH) {
+                if (w < NX) {
+                    const int c = w / (NQ * N1), rr = w - c * NQ * N1, qz = rr / N1, i = rr - qz * N1;
+                    const T *sS = P + LY::ZXS + c * QN2 + qz * N2 + i, *sD = P + LY::ZXD + c * QN2 + qz * N2 + i;
+                    T u[N1], v[N1];
+#pragma unroll
+                    for (int j = 0; j < N1; ++j) {
+                        u[j] = sS[j * N1];
+                        v[j] = sD[j * N1];
+                    }
+                    const int ob = c * QQN + qz * NQ * N1 + i;
+#pragma unroll
+                    for (int qy = 0; qy < NQ; ++qy) {
+                        T ss = 0, ds = 0, sd = 0;
+#pragma unroll
+                        for (int j = 0; j < N1; ++j) {
+                            ss += S[qy * N1 + j] * u[j];
+                            ds += D[qy * N1 + j] * u[j];
+                            sd += S[qy * N1 + j] * v[j];
+                        }
+                        Y[LY::YSS + ob + qy * N1] = ss;
+                        Y[LY::YDS + ob + qy * N1] = ds;
+                        Y[LY::YSD + ob + qy * N1] = sd;
+                    }
+                } else if (w >= O1 && w < O1 + 3 * NQ * N1) {
+                    const int ww = w - O1, c = ww / (NQ * N1), rr = ww - c * NQ * N1, qz = rr / N1, i = rr - qz * N1;
+                    const T *sS = P + LY::ZS + c * QN2 + qz * N2 + i, *sM = P + LY::ZM + c * QN2 + qz * N2 + i;
+                    T u[N1], m[N1];
+#pragma unroll
+                    for (int j = 0; j < N1; ++j) {
+                        u[j] = sS[j * N1];
+                        m[j] = sM[j * N1];
+                    }
+                    const int ob = c * QQN + qz * NQ * N1 + i;
+#pragma unroll
+                    for (int qy = 0; qy < NQ; ++qy) {
+                        T s = 0, mm = 0;
+#pragma unroll
+                        for (int j = 0; j < N1; ++j) {
+                            s += S[qy * N1 + j] * u[j];
+                            mm += S[qy * N1 + j] * m[j];
+                        }
+                        Y[LY::YS + ob + qy * N1] = s;
+                        Y[LY::YM + ob + qy * N1] = mm;
+                    }
+                } else if (w >= O2) {
+                    const int ww = w - O2, qz = ww / RP1, ip = ww - qz * RP1;
+                    const T *src = P + LY::ZP + qz * RP2 + ip;
+                    T u[RP1];
+#pragma unroll
+                    for (int j = 0; j < RP1; ++j) u[j] = src[j * RP1];
+                    T *op = Y + LY::YP + qz * NQ * RP1 + ip;
+#pragma unroll
+                    for (int qy = 0; qy < NQ; ++qy) {
+                        T s = 0;
+#pragma unroll
+                        for (int j = 0; j < RP1; ++j) s += L[qy * RP1 + j] * u[j];
+                        op[qy * RP1] = s;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // ---- x sweep and point physics: one thread per quadrature point ---------------
+        {
+            const T wa = A.w[a];
+            for (int q = tid; q < NQV; q += NTH) {
+                const int qx = q % NQ, qy = (q / NQ) % NQ, qz = q / (NQ * NQ);
+                const int row = qz * NQ + qy;
+                T sx[N1], dx[N1], lx[RP1];
+#pragma unroll
+                for (int i = 0; i < N1; ++i) {
+                    sx[i] = tS[qx * N1 + i];
+                    dx[i] = tD[qx * N1 + i];
+                }
+#pragma unroll
+                for (int i = 0; i < RP1; ++i) lx[i] = tL[qx * RP1 + i];
+                T xh[3], gref[3][3], v[3], xm[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int rb = c * QQN + row * N1;
+                    T a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+#pragma unroll
+                    for (int i = 0; i < N1; ++i) {
+                        const T u = Y[LY::YSS + rb + i];
+                        a0 += sx[i] * u;
+                        a1 += dx[i] * u;
+                        a2 += sx[i] * Y[LY::YDS + rb + i];
+                        a3 += sx[i] * Y[LY::YSD + rb + i];
+                        a4 += sx[i] * Y[LY::YS + rb + i];
+                        a5 += sx[i] * Y[LY::YM + rb + i];
+                    }
+                    xh[c] = a0;
+                    gref[c][0] = a1;
+                    gref[c][1] = a2;
+                    gref[c][2] = a3;
+                    v[c] = a4;
+                    xm[c] = a5;
+                }
+                T ph = 0;
+#pragma unroll
+                for (int i = 0; i < RP1; ++i) ph += lx[i] * Y[LY::YP + row * RP1 + i];
+                T det, Jit[3][3];
+                if constexpr (MAPPED) {
+                    const T xi[3] = {qxs[qx], qxs[qy], qxs[qz]};
+                    det = geometry<3>(true, geo, xi, hcar, Jit);
+                } else {
+                    det = det_c;
+                }
+                const T jxw = det * qw[qx] * qw[qy] * qw[qz];
+                const T sc = wa * jxw;
+                T divx = 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    T Fc[3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        T g = 0;
+                        if constexpr (MAPPED) {
+#pragma unroll
+                            for (int jd = 0; jd < 3; ++jd) g += Jit[d][jd] * gref[c][jd];
+                        } else {
+                            g = hinv[d] * gref[c][d];
+                        }
+                        if (d == c) divx += g;
+                        // nu grad x - x (x) v - v (x) x - p I
+                        Fc[d] = A.nu * g - xh[c] * v[d] - v[c] * xh[d];
+                        if (d == c) Fc[d] -= ph;
+                    }
+#pragma unroll
+                    for (int jd = 0; jd < 3; ++jd) {
+                        T s = 0;
+                        if constexpr (MAPPED) {
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) s += Fc[d] * Jit[d][jd];
+                        } else {
+                            s = Fc[jd] * hinv[jd];
+                        }
+                        P[(3 + c * 3 + jd) * NQV + q] = s * sc;
+                    }
+                    P[c * NQV + q] = jxw * xm[c];
+                }
+                P[12 * NQV + q] = -sc * divx;
+            }
+            __syncthreads();
+        }
+        // ---- x^T: per (component, qz, qy) pencil, value + x-gradient (S, D), y- and
+        //      z-gradient coefficients (S); pressure by L
+        {
+            constexpr int NI = 3 * NQ * NQ, O1 = al64(NI), TOT = O1 + NQ * NQ;
+            for (int w = tid; w < TOT; w += NTH) {
+                if (w < NI) {
+                    const int c = w / (NQ * NQ), row = w - c * NQ * NQ;
+                    const T *pv = P + c * NQV + row * NQ, *pg = P + (3 + c * 3) * NQV + row * NQ;
+                    T u[NQ], g0[NQ], g1[NQ], g2[NQ];
+#pragma unroll
+                    for (int o = 0; o < NQ; ++o) {
+                        u[o] = pv[o];
+                        g0[o] = pg[o];
+                        g1[o] = pg[NQV + o];
+                        g2[o] = pg[2 * NQV + o];
+                    }
+                    const int ob = c * QQN + row * N1;
+#pragma unroll
+                    for (int i = 0; i < N1; ++i) {
+                        T sa = 0, sb = 0, scc = 0;
+#pragma unroll
+                        for (int o = 0; o < NQ; ++o) {
+                            sa += S[o * N1 + i] * u[o];
+                            sa += D[o * N1 + i] * g0[o];
+                            sb += S[o * N1 + i] * g1[o];
+                            scc += S[o * N1 + i] * g2[o];
+                        }
+                        Y[LY::BA + ob + i] = sa;
+                        Y[LY::BB + ob + i] = sb;
+                        Y[LY::BC + ob + i] = scc;
+                    }
+                } else if (w >= O1) {
+                    const int row = w - O1;
+                    const T *pp = P + 12 * NQV + row * NQ;
+                    T u[NQ];
+#pragma unroll
+                    for (int o = 0; o < NQ; ++o) u[o] = pp[o];
+#pragma unroll
+                    for (int i = 0; i < RP1; ++i) {
+                        T s = 0;
+#pragma unroll
+                        for (int o = 0; o < NQ; ++o) s += L[o * RP1 + i] * u[o];
+                        Y[LY::BP + row * RP1 + i] = s;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // ---- y^T: per (component, qz, i) pencil; pressure by L
+        {
+            constexpr int NI = 3 * NQ * N1, O1 = al64(NI), TOT = O1 + NQ * RP1;
+            for (int w = tid; w < TOT; w += NTH) {
+                if (w < NI) {
+                    const int c = w / (NQ * N1), rr = w - c * NQ * N1, qz = rr / N1, i = rr - qz * N1;
+                    const int sb = c * QQN + qz * NQ * N1 + i;
+                    T ua[NQ], ub[NQ], uc[NQ];
+#pragma unroll
+                    for (int o = 0; o < NQ; ++o) {
+                        ua[o] = Y[LY::BA + sb + o * N1];
+                        ub[o] = Y[LY::BB + sb + o * N1];
+                        uc[o] = Y[LY::BC + sb + o * N1];
+                    }
+                    const int ob = c * QN2 + qz * N2 + i;
+#pragma unroll
+                    for (int j = 0; j < N1; ++j) {
+                        T sa = 0, scc = 0;
+#pragma unroll
+                        for (int o = 0; o < NQ; ++o) {
+                            sa += S[o * N1 + j] * ua[o];
+                            sa += D[o * N1 + j] * ub[o];
+                            scc += S[o * N1 + j] * uc[o];
+                        }
+                        P[LY::WA + ob + j * N1] = sa;
+                        P[LY::WC + ob + j * N1] = scc;
+                    }
+                } else if (w >= O1) {
+                    const int ww = w - O1, qz = ww / RP1, ip = ww - qz * RP1;
+                    T u[NQ];
+#pragma unroll
+                    for (int o = 0; o < NQ; ++o) u[o] = Y[LY::BP + qz * NQ * RP1 + o * RP1 + ip];
+#pragma unroll
+                    for (int j = 0; j < RP1; ++j) {
+                        T s = 0;
+#pragma unroll
+                        for (int o = 0; o < NQ; ++o) s += L[o * RP1 + j] * u[o];
+                        P[LY::WP + qz * RP2 + j * RP1 + ip] = s;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // ---- z^T: per (component, j, i) column, straight to E; pressure rows; the
+        //      next time node's state into LDS (clear of the y^T results)
+        {
+            constexpr int NI = 3 * N2, O1 = al64(NI), TOT = O1 + RP2;
+            T *Ec = E + ((long long)cell * nt + a) * 3 * NL;
+            for (int w = tid; w < TOT; w += NTH) {
+                if (w < NI) {
+                    const int c = w / N2, ji = w - c * N2;
+                    T ua[NQ], uc[NQ];
+#pragma unroll
+                    for (int o = 0; o < NQ; ++o) {
+                        ua[o] = P[LY::WA + c * QN2 + o * N2 + ji];
+                        uc[o] = P[LY::WC + c * QN2 + o * N2 + ji];
+                    }
+#pragma unroll
+                    for (int k = 0; k < N1; ++k) {
+                        T s = 0;
+#pragma unroll
+                        for (int o = 0; o < NQ; ++o) {
+                            s += S[o * N1 + k] * ua[o];
+                            s += D[o * N1 + k] * uc[o];
+                        }
+                        Ec[c * NL + k * N2 + ji] = s;
+                    }
+                } else if (w >= O1) {
+                    const int ji = w - O1, jp = ji / RP1, ip = ji - jp * RP1;
+                    T u[NQ];
+#pragma unroll
+                    for (int o = 0; o < NQ; ++o) u[o] = P[LY::WP + o * RP2 + ji];
+#pragma unroll
+                    for (int kp = 0; kp < RP1; ++kp) {
+                        const int e = pmode_compact<R>(ip, jp, kp);
+                        if (e >= 0) {
+                            T s = 0;
+#pragma unroll
+                            for (int o = 0; o < NQ; ++o) s += L[o * RP1 + kp] * u[o];
+                            y[pbase + a * A.Np1 + (long long)cell * NPM + e] = s;
+                        }
+                    }
+                }
+            }
+            if (a + 1 < nt) {
+                store_state();
+                if (a + 2 < nt) load_state(a + 2);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Boundary-face kernel: the Nitsche and convective boundary terms (eq.
 // def-a-gam-tp, eq. def-b-gam) of the cells on the domain boundary, one
 // workgroup per boundary cell and time node.  Runs after the volume
@@ -849,7 +1376,7 @@ __host__ __device__ constexpr int face_lds_words(int tabwords)
     using Z = Sizes<DIM, R>;
     using LY = FaceLds<DIM, R, NQ, T>;
     (void)tabwords;
-    return LY::FTAB + 3 * DIM * Z::NL + 2 * Z::NPF + LY::SCR1 + LY::TMP2 + 32;
+    return LY::FTAB + 2 * DIM * Z::NL + 2 * Z::NPF + LY::SCR1 + LY::TMP2 + 32;
 }
 
 template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE>
@@ -881,8 +1408,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
     T *ftab = sm;                                  // Se, De, Le, qw, qx
     T *xs = ftab + LY::FTAB;                       // [DIM][NL] nodal x of the time node
     T *ns = xs + DIM * NL;                         // [DIM][NL] nodal state
-    T *ys = ns + DIM * NL;                         // [DIM][NL] nodal output (starts at the volume result)
-    T *xpf = ys + DIM * NL;                        // [NPF] pressure modes (full tensor)
+    T *xpf = ns + DIM * NL;                        // [NPF] pressure modes (full tensor)
     T *ypf = xpf + NPF;                            // [NPF] pressure output
     T *Q = ypf + NPF;                              // face record
     T *t1 = LY::T1_IN_Q ? Q : Q + LY::Q_SIZE;
@@ -925,16 +1451,25 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
         long long vi = (c0 + o0) + (long long)(A.n0 + 1) * ((c1 + o1) + (long long)(A.n1 + 1) * (c2 + o2));
         for (int k = 0; k < 3; ++k) geo[v * 3 + k] = k < DIM ? T(A.vert[vi * DIM + k]) : T(0);
     }
+    // nodal velocity output, starting at the volume result: element
+    // e = tid + j * NTH lives in yr[j] of its thread (registers, not LDS, so
+    // that 16 of these workgroups fit a CU in FP64)
     T *Ec = E + ((long long)cell * nt + a) * DIM * NL;
-    for (int e = tid; e < DIM * NL; e += NTH) {
-        const int l = e % NL, c = e / NL;
-        const long long g = a * A.Nv1 + c * A.Nn + gnode(l);
-        xs[e] = x[g];
-        if constexpr (MODE == Mode::Jac) {
-            const T *st = A.state + vec * A.sstride;
-            ns[e] = st[g];
+    constexpr int YR = (DIM * NL + NTH - 1) / NTH;
+    T yr[YR];
+#pragma unroll
+    for (int j = 0; j < YR; ++j) {
+        const int e = tid + j * NTH;
+        if (e < DIM * NL) {
+            const int l = e % NL, c = e / NL;
+            const long long g = a * A.Nv1 + c * A.Nn + gnode(l);
+            xs[e] = x[g];
+            if constexpr (MODE == Mode::Jac) {
+                const T *st = A.state + vec * A.sstride;
+                ns[e] = st[g];
+            }
+            yr[j] = Ec[e];
         }
-        ys[e] = Ec[e];
     }
     constexpr int PP = (NPM + NTH - 1) / NTH;
     T px[PP], py[PP];
@@ -1301,19 +1836,22 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                             }
                             __syncthreads();
                         }
-                        // 5. expansion along the normal into the nodal / modal outputs
-                        for (int w = tid; w < DIM * NL + NPF; w += NTH) {
+                        // 5. expansion along the normal into the nodal (registers) and
+                        //    modal outputs
+#pragma unroll
+                        for (int j = 0; j < YR; ++j) {
+                            const int w = tid + j * NTH;
                             if (w < DIM * NL) {
                                 const int c = w / NL, l = w - c * NL;
                                 const int li[3] = {l % N1, (l / N1) % N1, DIM == 3 ? l / (N1 * N1) : 0};
                                 const int it = li[ta0] + (DIM == 3 ? N1 * li[ta1] : 0);
-                                ys[w] += Srow[li[ax]] * Alay[c * LN + it] + Drow[li[ax]] * Blay[c * LN + it];
-                            } else {
-                                const int m = w - DIM * NL;
-                                const int mi[3] = {m % RP1, (m / RP1) % RP1, DIM == 3 ? m / (RP1 * RP1) : 0};
-                                const int it = mi[ta0] + (DIM == 3 ? RP1 * mi[ta1] : 0);
-                                ypf[m] += Lrow[mi[ax]] * Play[it];
+                                yr[j] += Srow[li[ax]] * Alay[c * LN + it] + Drow[li[ax]] * Blay[c * LN + it];
                             }
+                        }
+                        for (int m = tid; m < NPF; m += NTH) {
+                            const int mi[3] = {m % RP1, (m / RP1) % RP1, DIM == 3 ? m / (RP1 * RP1) : 0};
+                            const int it = mi[ta0] + (DIM == 3 ? RP1 * mi[ta1] : 0);
+                            ypf[m] += Lrow[mi[ax]] * Play[it];
                         }
                         __syncthreads();
                 };
@@ -1333,7 +1871,11 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
         }
 
         // ---- volume + boundary results back --------------------------------------------
-        for (int e = tid; e < DIM * NL; e += NTH) Ec[e] = ys[e];
+#pragma unroll
+        for (int j = 0; j < YR; ++j) {
+            const int e = tid + j * NTH;
+            if (e < DIM * NL) Ec[e] = yr[j];
+        }
         for (int e = tid; e < NPM; e += NTH) {
             const long long gi = pbase + a * A.Np1 + (long long)cell * NPM + e;
             y[gi] = ypf[pmode_full<DIM, R>(e)];
@@ -1432,9 +1974,50 @@ static hipError_t launch_face(const CellArgs<T> &a, int nvec, hipStream_t s)
     return hipGetLastError();
 }
 
+// workgroup size of jac_cell_kernel, measured at 16^3 cells on one MI355X
+// (time per launch, 128 vs 256 threads): r = 1, n_q = 4: FP64 28 vs 44 us,
+// FP32 19 vs 26; r = 2, n_q = 5: FP64 78 vs 73, FP32 42 vs 46; r = 2,
+// n_q = 4: FP64 58 vs 64, FP32 34 vs 40; r = 3, n_q = 7 (k = 1): FP64 231
+// vs 150, FP32 106 vs 88
+template <int R, int NQ, typename T> constexpr int jac_threads()
+{
+    if (R == 3) return 256;
+    if (R == 2 && NQ == 5 && sizeof(T) == 8) return 256;
+    return 128;
+}
+
+template <int R, int NQ, typename T>
+static hipError_t launch_jac(const CellArgs<T> &a, int nvec, hipStream_t s)
+{
+    constexpr int NTH = jac_threads<R, NQ, T>();
+    size_t bytes = (size_t)jac_lds_words<R, NQ, T>(a.nt) * sizeof(T);
+    auto kern = a.mapped ? jac_cell_kernel<R, NQ, NTH, T, true> : jac_cell_kernel<R, NQ, NTH, T, false>;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    static size_t attr_bytes[2] = {0, 0};   // per kernel (affine, mapped)
+    size_t &have = attr_bytes[a.mapped ? 1 : 0];
+    static int max_lds = -1;
+    if (max_lds < 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            max_lds = 65536;
+    }
+    if (bytes > (size_t)max_lds) return hipErrorInvalidConfiguration;
+    if (bytes > have) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        have = bytes;
+    }
+    dim3 grid(a.ncell, nvec);
+    hipLaunchKernelGGL(kern, grid, dim3(NTH), bytes, s, a);
+    return hipGetLastError();
+}
+
 template <int DIM, int R, int NQ, typename T, Mode MODE>
 static hipError_t launch_one(const CellArgs<T> &a, int nvec, hipStream_t s)
 {
+    if constexpr (DIM == 3 && MODE == Mode::Jac) return launch_jac<R, NQ, T>(a, nvec, s);
     constexpr int NTH = DIM == 2 ? 64 : 256;
     TableLayout lay;
     lay.init(R, NQ);
