@@ -886,6 +886,10 @@ __global__ void __launch_bounds__(256) patch_kernel(PatchArgs<TE, TP> A)
 constexpr int LU_THREADS = 256;
 constexpr int LU_CB = 64;        // column block of the trailing update
 constexpr int LU_SWC = 64;       // column chunk of the row interchanges
+constexpr int LU_NBO_MIN_M = 192; // larger matrices: outer blocks of LU_CB columns
+
+// outer block width of an m x m factorization with panels of nb columns
+__host__ __device__ constexpr int lu_outer_block(int m, int nb) { return m > LU_NBO_MIN_M ? LU_CB : nb; }
 
 
 // trailing update A22 -= L21 U12 of one column block, FP32 on MFMA
@@ -895,13 +899,11 @@ constexpr int LU_SWC = 64;       // column chunk of the row interchanges
 // accumulated in FP32 (v_mfma_f32_16x16x16{bf16,f16}: A lane l -> (row l%16,
 // k 4(l/16)+j), B lane l -> (k 4(l/16)+j, col l%16), j < 4; D as above);
 // A22 stays FP32
-template <int NBP, int OP, int NTH = LU_THREADS, int PF = 1>
-__device__ __forceinline__ void trailing_update(float *A, int m, int ld, int j0, int nb, int cb, int ncb, const float *pan,
+template <int OP, int NTH = LU_THREADS, int PF = 1, typename LOP>
+__device__ __forceinline__ void trailing_update(float *A, int r0, int m, int ld, int nb, int cb, int ncb, LOP lop,
                                                 const float *ut)
 {
-    constexpr int NB = NBP - 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int r0 = j0 + nb;
     const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32, ntile = nrt * nct;
     // each wave walks its tiles t = wv, wv + 4, ...; the next tile's C block is
     // loaded before the current one is computed (tiles are disjoint)
@@ -939,10 +941,11 @@ __device__ __forceinline__ void trailing_update(float *A, int m, int ld, int j0,
 #pragma unroll
                 for (int si = 0; si < 2; ++si) {
                     const int row = R + 16 * si + (lane & 15);
-                    a[si] = (row < m && k < nb) ? -pan[(row - j0) * NBP + k] : 0.0f;
+                    const float v = lop(min(row, m - 1), min(k, nb - 1));
+                    a[si] = (row < m && k < nb) ? -v : 0.0f;
                 }
 #pragma unroll
-                for (int sj = 0; sj < 2; ++sj) b[sj] = ut[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)];
+                for (int sj = 0; sj < 2; ++sj) b[sj] = k < nb ? ut[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)] : 0.0f;
 #pragma unroll
                 for (int si = 0; si < 2; ++si)
 #pragma unroll
@@ -955,11 +958,11 @@ __device__ __forceinline__ void trailing_update(float *A, int m, int ld, int j0,
                 halfx4_t ah[2], bh[2];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int k = k0 + 4 * (lane >> 4) + j, kc = min(k, NB - 1);
+                    const int k = k0 + 4 * (lane >> 4) + j, kc = min(k, nb - 1);
 #pragma unroll
                     for (int si = 0; si < 2; ++si) {
                         const int row = R + 16 * si + (lane & 15);
-                        const float v = -pan[(min(row, m - 1) - j0) * NBP + kc];
+                        const float v = -lop(min(row, m - 1), kc);
                         const float a = (row < m && k < nb) ? v : 0.0f;
                         if constexpr (OP == 1) as[si][j] = bf16_rne(a);
                         else ah[si][j] = (_Float16)a;
@@ -1008,12 +1011,11 @@ __device__ __forceinline__ void trailing_update(float *A, int m, int ld, int j0,
 // l register i -> (row l/16 + 4i, col l%16)): each wave walks 32 x 32 tiles
 // of the column block, the next tile's C block loaded before the current one
 // is computed
-template <int NBP, int OP, int NTH = LU_THREADS, int PF = 1>
-__device__ __forceinline__ void trailing_update(double *A, int m, int ld, int j0, int nb, int cb, int ncb,
-                                                const double *pan, const double *ut)
+template <int OP, int NTH = LU_THREADS, int PF = 1, typename LOP>
+__device__ __forceinline__ void trailing_update(double *A, int r0, int m, int ld, int nb, int cb, int ncb, LOP lop,
+                                                const double *ut)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int r0 = j0 + nb;
     const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32, ntile = nrt * nct;
     auto load = [&](int t, doublex4_t (&c)[2][2]) {
         const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
@@ -1046,7 +1048,8 @@ __device__ __forceinline__ void trailing_update(double *A, int m, int ld, int j0
 #pragma unroll
             for (int si = 0; si < 2; ++si) {
                 const int row = R + 16 * si + (lane & 15);
-                a[si] = (row < m && k < nb) ? -pan[(row - j0) * NBP + k] : 0.0;
+                const double v = lop(min(row, m - 1), min(k, nb - 1));
+                a[si] = (row < m && k < nb) ? -v : 0.0;
             }
 #pragma unroll
             for (int sj = 0; sj < 2; ++sj) b[sj] = k < nb ? ut[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)] : 0.0;
@@ -1120,22 +1123,87 @@ __device__ __forceinline__ void compose_panel_swaps(const int *sw, int nb, int *
 }
 
 // LU with partial pivoting of one m x m matrix (row stride ld) by the whole
-// workgroup with panels of NB columns in LDS (lds_raw: lu_lds_bytes<NB, T>(m))
+// workgroup with panels of NB columns in LDS (lds_raw: lu_lds_bytes<NB, T>(m)).
+// Matrices larger than LU_NBO_MIN_M are blocked on two levels: the panels of
+// one outer block of LU_CB columns update only the rest of that block (all
+// rows) and the block's own rows; the rows and columns behind the block then
+// receive one update with K = LU_CB (L from the factored block columns, U
+// staged in LDS), so the trailing matrix crosses HBM once per LU_CB columns
+// instead of once per panel.
 template <typename T, int NB, int OP, int NTH = LU_THREADS, int PF = 1>
 __device__ __forceinline__ void lu_one(T *__restrict__ A, int m, int ld, int *__restrict__ piv, int *info,
                                        unsigned char *lds_raw)
 {
     constexpr int NBP = NB + 1;
+    const int nbo = lu_outer_block(m, NB);
     T *pan = reinterpret_cast<T *>(lds_raw);          // [m][NBP] panel rows
-    T *ut = pan + (size_t)m * NBP;                     // [NB][LU_CB] U12 block
-    T *stg = ut + (size_t)NB * LU_CB;                  // [2 NB][LU_SWC] row interchange staging
+    T *ut = pan + (size_t)m * NBP;                     // [nbo][LU_CB] U12 block
+    T *stg = ut + (size_t)nbo * LU_CB;                 // [2 NB][LU_SWC] row interchange staging
     __shared__ T rv[NTH / 64];
     __shared__ int ri[NTH / 64];
     __shared__ int sw[NB];
     __shared__ int aff_src[2 * NB], aff_dst[2 * NB];
     __shared__ int n_aff;
+    __shared__ int bsw[LU_CB];                         // local pivots of the outer block's panels
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int j0 = 0; j0 < m; j0 += NB) {
+    auto from_panel = [&](int j0) { return [=](int row, int k) { return pan[(row - j0) * NBP + k]; }; };
+    // interchanges of one panel (local pivots sw[0 .. nb)), composed into one
+    // permutation of the affected rows, applied to columns [c_lo, c_hi)
+    auto apply_swaps = [&](int j0, int nb, int c_lo, int c_hi) {
+        if (wv == 0) compose_panel_swaps<NB>(sw, nb, aff_dst, aff_src, &n_aff);
+        __syncthreads();
+        const int na = n_aff;
+        if (na > 0) {
+            for (int c0 = c_lo; c0 < c_hi; c0 += LU_SWC) {
+                const int nc = min(LU_SWC, c_hi - c0);
+                for (int e = tid; e < na * LU_SWC; e += NTH) {
+                    int i = e / LU_SWC, j = e % LU_SWC;
+                    if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * ld + c0 + j];
+                }
+                __syncthreads();
+                for (int e = tid; e < na * LU_SWC; e += NTH) {
+                    int i = e / LU_SWC, j = e % LU_SWC;
+                    if (j < nc) A[(long long)(j0 + aff_dst[i]) * ld + c0 + j] = stg[i * LU_SWC + j];
+                }
+                __syncthreads();
+            }
+        }
+    };
+    // U12 = L11^{-1} A12 on columns [c_lo, c_hi) of the rows j0 .. j0+nb (L11
+    // from the panel rows in LDS), one column block at a time, each followed
+    // by A22 -= L21 U12 on the rows [j0+nb, rend)
+    auto u12_update = [&](int j0, int nb, int c_lo, int c_hi, int rend) {
+        for (int cb = c_lo; cb < c_hi; cb += LU_CB) {
+            const int ncb = min(LU_CB, c_hi - cb);
+            for (int e = tid; e < NB * LU_CB; e += NTH) ut[e] = T(0);
+            __syncthreads();
+            if (tid < ncb) {
+                const int col = cb + tid;
+                T u[NB];
+                for (int c = 0; c < NB; ++c) u[c] = c < nb ? A[(long long)(j0 + c) * ld + col] : T(0);
+                // fully unrolled (register array); rows c >= nb stay zero
+#pragma unroll
+                for (int c = 1; c < NB; ++c) {
+                    T s = u[c];
+#pragma unroll
+                    for (int k = 0; k < c; ++k) s -= pan[c * NBP + k] * u[k];
+                    if (c < nb) u[c] = s;
+                }
+                for (int c = 0; c < NB; ++c)
+                    if (c < nb) {
+                        A[(long long)(j0 + c) * ld + col] = u[c];
+                        ut[c * LU_CB + tid] = u[c];
+                    }
+            }
+            __syncthreads();
+            trailing_update<OP, NTH, PF>(A, j0 + nb, rend, ld, nb, cb, ncb, from_panel(j0), ut);
+            __syncthreads();
+        }
+    };
+    for (int J0 = 0; J0 < m; J0 += nbo) {
+      const int jend = min(J0 + nbo, m);             // end of the outer block
+      const int cmax = nbo == NB ? m : jend;         // columns the panels of the block touch
+      for (int j0 = J0; j0 < jend; j0 += NB) {
         const int nb = min(NB, m - j0), mr = m - j0;
         for (int e = tid; e < mr * nb; e += NTH) {
             int r = e / nb, c = e % nb;
@@ -1163,6 +1231,7 @@ __device__ __forceinline__ void lu_one(T *__restrict__ A, int m, int ld, int *__
             if (tid == 0) {
                 piv[j0 + c] = j0 + p;
                 sw[c] = p;
+                bsw[j0 - J0 + c] = p;
                 if (bv == T(0) && info) atomicAdd(info, 1);
             }
             if (p != c && tid < nb) {
@@ -1180,59 +1249,51 @@ __device__ __forceinline__ void lu_one(T *__restrict__ A, int m, int ld, int *__
             }
             __syncthreads();
         }
-        // composed row permutation of this panel: affected local rows dst <- src
-        if (wv == 0) compose_panel_swaps<NB>(sw, nb, aff_dst, aff_src, &n_aff);
-        __syncthreads();
-        // apply the permutation to whole rows (panel columns are rewritten below)
-        const int na = n_aff;
-        if (na > 0) {
-            for (int c0 = 0; c0 < m; c0 += LU_SWC) {
-                const int nc = min(LU_SWC, m - c0);
-                for (int e = tid; e < na * LU_SWC; e += NTH) {
-                    int i = e / LU_SWC, j = e % LU_SWC;
-                    if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * ld + c0 + j];
-                }
-                __syncthreads();
-                for (int e = tid; e < na * LU_SWC; e += NTH) {
-                    int i = e / LU_SWC, j = e % LU_SWC;
-                    if (j < nc) A[(long long)(j0 + aff_dst[i]) * ld + c0 + j] = stg[i * LU_SWC + j];
-                }
-                __syncthreads();
-            }
-        }
+        // the panel's interchanges on the columns it touches (the panel columns
+        // themselves are rewritten below)
+        apply_swaps(j0, nb, 0, cmax);
         // write the factored panel back
         for (int e = tid; e < mr * nb; e += NTH) {
             int r = e / nb, c = e % nb;
             A[(long long)(j0 + r) * ld + j0 + c] = pan[r * NBP + c];
         }
         __syncthreads();
-        // U12 = L11^{-1} A12 and the trailing update, one column block at a time
-        for (int cb = j0 + nb; cb < m; cb += LU_CB) {
-            const int ncb = min(LU_CB, m - cb);
-            for (int e = tid; e < NB * LU_CB; e += NTH) ut[e] = T(0);
+        u12_update(j0, nb, j0 + nb, cmax, m);
+      }
+      if (cmax < m) {
+        // columns behind the block, untouched so far: the block's interchanges
+        // in panel order, then U of the block's rows (blocked forward
+        // substitution with the block's L11), then one update of the rows and
+        // columns behind the block with K = jend - J0 (L from global memory, U
+        // staged in LDS one column block at a time)
+        for (int j0 = J0; j0 < jend; j0 += NB) {
+            const int nb = min(NB, m - j0);
+            if (tid < nb) sw[tid] = bsw[j0 - J0 + tid];
             __syncthreads();
-            if (tid < ncb) {
-                const int col = cb + tid;
-                T u[NB];
-                for (int c = 0; c < NB; ++c) u[c] = c < nb ? A[(long long)(j0 + c) * ld + col] : T(0);
-                // fully unrolled (register array); rows c >= nb stay zero
-#pragma unroll
-                for (int c = 1; c < NB; ++c) {
-                    T s = u[c];
-#pragma unroll
-                    for (int k = 0; k < c; ++k) s -= pan[c * NBP + k] * u[k];
-                    if (c < nb) u[c] = s;
-                }
-                for (int c = 0; c < NB; ++c)
-                    if (c < nb) {
-                        A[(long long)(j0 + c) * ld + col] = u[c];
-                        ut[c * LU_CB + tid] = u[c];
-                    }
+            apply_swaps(j0, nb, jend, m);
+        }
+        for (int j0 = J0; j0 < jend; j0 += NB) {
+            const int nb = min(NB, m - j0), nr = jend - j0;
+            for (int e = tid; e < nr * nb; e += NTH) {
+                int r = e / nb, c = e % nb;
+                pan[r * NBP + c] = A[(long long)(j0 + r) * ld + j0 + c];
             }
             __syncthreads();
-            trailing_update<NBP, OP, NTH, PF>(A, m, ld, j0, nb, cb, ncb, pan, ut);
+            u12_update(j0, nb, jend, m, jend);
+        }
+        const int kk = jend - J0;
+        for (int cb = jend; cb < m; cb += LU_CB) {
+            const int ncb = min(LU_CB, m - cb);
+            for (int e = tid; e < kk * LU_CB; e += NTH) {
+                const int c = e / LU_CB, j = e - c * LU_CB;
+                ut[e] = j < ncb ? A[(long long)(J0 + c) * ld + cb + j] : T(0);
+            }
+            __syncthreads();
+            trailing_update<OP, NTH, PF>(A, jend, m, ld, kk, cb, ncb,
+                                         [=](int row, int k) { return A[(long long)row * ld + J0 + k]; }, ut);
             __syncthreads();
         }
+      }
     }
 }
 
@@ -2630,7 +2691,7 @@ __global__ void midpoint_kernel(const T *state, long long Nv1, int nt, const dou
 
 template <int NB, typename T> size_t lu_lds_bytes(int m)
 {
-    return ((size_t)m * (NB + 1) + (size_t)NB * LU_CB + (size_t)2 * NB * LU_SWC) * sizeof(T);
+    return ((size_t)m * (NB + 1) + (size_t)lu_outer_block(m, NB) * LU_CB + (size_t)2 * NB * LU_SWC) * sizeof(T);
 }
 
 template <int NB, typename T> size_t lu_c_lds_bytes(int m)
