@@ -1,7 +1,7 @@
 // Launch parameters of the persistent batched LU (stmg_batched_lu), per
 // precision: workgroups per CU (which sets the LDS budget of the launch) and
 // the panel width per size class.  Written by paper_2602_13841_amd/tune_lu.py
-// (2026-12-03, MI355X gfx950) from the timings of the 4096-matrix mixed patch batch
+// (2026-12-03, AMD Radeon Graphics gfx950:sramecc+:xnack-) from the timings of the 4096-matrix mixed patch batch
 // (sizes 85 ... 1185) noted beside each row.
 #pragma once
 
@@ -18,10 +18,10 @@ struct LuTune {
 
 // index: 0 = FP64, 1 = FP32, 2 = FP32 with BF16 update operands, 3 = FP16
 constexpr LuTune LU_TUNED[4] = {
-    {1, 512, {8, 16, 16, 16, 16}},   // f64: 188.6 ms, 4.19 TFLOP/s; one launch per size class 213.4 ms
-    {1, 512, {8, 16, 16, 16, 16}},   // f32: 76.2 ms, 10.38 TFLOP/s; one launch per size class 80.5 ms
-    {1, 512, {8, 16, 16, 16, 16}},   // f32_bf16: 72.2 ms, 10.96 TFLOP/s; one launch per size class 78.3 ms
-    {1, 512, {8, 16, 16, 16, 16}},   // f32_f16: 72.0 ms, 10.99 TFLOP/s; one launch per size class 77.7 ms
+    {1, 512, {8, 8, 8, 16, 16}},   // f64: 94.7 ms, 8.35 TFLOP/s; one launch per size class 117.7 ms
+    {3, 256, {8, 16, 16, 16, 16}},   // f32: 67.8 ms, 11.66 TFLOP/s; one launch per size class 85.1 ms
+    {3, 256, {16, 16, 16, 16, 16}},   // f32_bf16: 59.2 ms, 13.36 TFLOP/s; one launch per size class 63.2 ms
+    {3, 256, {16, 16, 16, 16, 16}},   // f32_f16: 58.8 ms, 13.46 TFLOP/s; one launch per size class 62.0 ms
 };
 
 } // namespace stmg

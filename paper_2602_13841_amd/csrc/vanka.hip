@@ -889,7 +889,16 @@ constexpr int LU_SWC = 64;       // column chunk of the row interchanges
 constexpr int LU_NBO_MIN_M = 192; // larger matrices: outer blocks of LU_CB columns
 
 // outer block width of an m x m factorization with panels of nb columns
-__host__ __device__ constexpr int lu_outer_block(int m, int nb) { return m > LU_NBO_MIN_M ? LU_CB : nb; }
+// (32-column panels stay on one level: their register arrays leave no room
+// for the code of the second level)
+__host__ __device__ constexpr int lu_outer_block(int m, int nb) { return m > LU_NBO_MIN_M && nb < 32 ? LU_CB : nb; }
+constexpr int LU_CBD = 32;       // column block of the complex once-per-block update
+// words per plane of the complex U block: the panels' [NB][LU_CB] and the
+// outer block's [nbo][LU_CBD]
+__host__ __device__ constexpr int lu_c_u_words(int nb, int nbo)
+{
+    return nb * LU_CB > nbo * LU_CBD ? nb * LU_CB : nbo * LU_CBD;
+}
 
 
 // trailing update A22 -= L21 U12 of one column block, FP32 on MFMA
@@ -1260,7 +1269,7 @@ __device__ __forceinline__ void lu_one(T *__restrict__ A, int m, int ld, int *__
         __syncthreads();
         u12_update(j0, nb, j0 + nb, cmax, m);
       }
-      if (cmax < m) {
+      if constexpr (NB < 32) if (cmax < m) {
         // columns behind the block, untouched so far: the block's interchanges
         // in panel order, then U of the block's rows (blocked forward
         // substitution with the block's L11), then one update of the rows and
@@ -1875,6 +1884,325 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, 
             trailing_update_c<NBP>(Ar, Ai, m, ld, j0, nb, cb, ncb, pr, pi, ur, ui);
             __syncthreads();
         }
+    }
+}
+
+// complex trailing update C -= L21 U12 of one column block (planar), FP32 on
+// MFMA, for the second blocking level: rows [r0, m), K = nb, L21 from an
+// accessor (the LDS panel or global memory), U12 from LDS with row stride ldu
+template <typename LOP>
+__device__ __forceinline__ void trailing_update_cg(float *Ar, float *Ai, int r0, int m, int ld, int nb, int cb, int ncb,
+                                                  LOP lop, const float *ur, const float *ui, int ldu)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32, ntile = nrt * nct;
+    // the next tile's C block (both planes) is loaded before the current one
+    // is computed (tiles are disjoint)
+    auto load = [&](int t, floatx4_t (&xr)[2][2], floatx4_t (&xi)[2][2]) {
+        const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
+#pragma unroll
+        for (int si = 0; si < 2; ++si)
+#pragma unroll
+            for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
+                    const bool ok = row < m && col < cb + ncb;
+                    xr[si][sj][i] = ok ? Ar[(long long)row * ld + col] : 0.0f;
+                    xi[si][sj][i] = ok ? Ai[(long long)row * ld + col] : 0.0f;
+                }
+    };
+    floatx4_t cr[2][2], ci[2][2], nr[2][2], ni[2][2];
+    if (wv < ntile) load(wv, cr, ci);
+    for (int t = wv; t < ntile; t += LU_THREADS / 64) {
+        const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
+        const int tn = t + LU_THREADS / 64;
+        if (tn < ntile) load(tn, nr, ni);
+        for (int k0 = 0; k0 < nb; k0 += 4) {
+            const int k = k0 + (lane >> 4);
+            float ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+            for (int si = 0; si < 2; ++si) {
+                const int row = R + 16 * si + (lane & 15);
+                const bool ok = row < m && k < nb;
+                float lr, li;
+                lop(min(row, m - 1), min(k, nb - 1), lr, li);
+                ar[si] = ok ? -lr : 0.0f;
+                ai[si] = ok ? -li : 0.0f;
+                nai[si] = -ai[si];
+            }
+#pragma unroll
+            for (int sj = 0; sj < 2; ++sj) {
+                const int kc = min(k, nb - 1), col = (C - cb) + 16 * sj + (lane & 15);
+                br[sj] = k < nb ? ur[kc * ldu + col] : 0.0f;
+                bi[sj] = k < nb ? ui[kc * ldu + col] : 0.0f;
+            }
+#pragma unroll
+            for (int si = 0; si < 2; ++si)
+#pragma unroll
+                for (int sj = 0; sj < 2; ++sj) {
+                    cr[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[si], br[sj], cr[si][sj], 0, 0, 0);
+                    cr[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[si], bi[sj], cr[si][sj], 0, 0, 0);
+                    ci[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[si], bi[sj], ci[si][sj], 0, 0, 0);
+                    ci[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[si], br[sj], ci[si][sj], 0, 0, 0);
+                }
+        }
+#pragma unroll
+        for (int si = 0; si < 2; ++si)
+#pragma unroll
+            for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = R + 16 * si + 4 * (lane >> 4) + i, col = C + 16 * sj + (lane & 15);
+                    if (row < m && col < cb + ncb) {
+                        Ar[(long long)row * ld + col] = cr[si][sj][i];
+                        Ai[(long long)row * ld + col] = ci[si][sj][i];
+                    }
+                }
+        if (tn < ntile) {
+#pragma unroll
+            for (int si = 0; si < 2; ++si)
+#pragma unroll
+                for (int sj = 0; sj < 2; ++sj) {
+                    cr[si][sj] = nr[si][sj];
+                    ci[si][sj] = ni[si][sj];
+                }
+        }
+    }
+}
+
+// FP32 complex LU on two levels (matrices larger than LU_NBO_MIN_M): the
+// panels of an outer block of LU_CB columns touch only the block's columns;
+// then the block's interchanges, U of its rows (blocked forward substitution)
+// and one update of the rows and columns behind it with K = LU_CB (LU_CBD
+// columns at a time), as in lu_one.  Storage as in lu_kernel_c.
+template <typename T, int NB>
+__global__ void __launch_bounds__(LU_THREADS) lu_kernel_c2(T *__restrict__ Aall, int *__restrict__ pivall, int m,
+                                                          int ld, long long a_stride, int *info)
+{
+    constexpr int NBP = NB + 1;
+    extern __shared__ unsigned char lds_raw[];
+    const int bid = blockIdx.x;
+    T *Ar = Aall + (long long)bid * a_stride;
+    T *Ai = Ar + (long long)m * ld;
+    int *piv = pivall + (long long)bid * m;
+    static_assert(NB < 32 && sizeof(T) == 4, "two-level complex LU: FP32, panels under 32 columns");
+    constexpr int nbo = LU_CB;
+    constexpr int ubw = lu_c_u_words(NB, nbo);
+    T *pr = reinterpret_cast<T *>(lds_raw);           // [m][NBP] panel, real
+    T *pi = pr + (size_t)m * NBP;                      // [m][NBP] panel, imaginary
+    T *ur = pi + (size_t)m * NBP;                      // U block: [NB][LU_CB] or [nbo][LU_CBD]
+    T *ui = ur + (size_t)ubw;
+    T *stg = ui + (size_t)ubw;                         // [2 NB][LU_SWC] interchange staging
+    __shared__ T rv[LU_THREADS / 64];
+    __shared__ int ri[LU_THREADS / 64];
+    __shared__ int sw[NB];
+    __shared__ int aff_src[2 * NB], aff_dst[2 * NB];
+    __shared__ int n_aff;
+    __shared__ int bsw[LU_CB];                         // local pivots of the outer block's panels
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    auto from_panel = [&](int j0) {
+        return [=](int row, int k, T &lr, T &li) {
+            lr = pr[(row - j0) * NBP + k];
+            li = pi[(row - j0) * NBP + k];
+        };
+    };
+    // interchanges of one panel (local pivots sw[0 .. nb)) on columns [c_lo, c_hi), both planes
+    auto apply_swaps = [&](int j0, int nb, int c_lo, int c_hi) {
+        if (wv == 0) compose_panel_swaps<NB>(sw, nb, aff_dst, aff_src, &n_aff);
+        __syncthreads();
+        const int na = n_aff;
+        if (na > 0) {
+            for (int plane = 0; plane < 2; ++plane) {
+                T *A = plane ? Ai : Ar;
+                for (int c0 = c_lo; c0 < c_hi; c0 += LU_SWC) {
+                    const int nc = min(LU_SWC, c_hi - c0);
+                    for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
+                        const int i = e / LU_SWC, j = e % LU_SWC;
+                        if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * ld + c0 + j];
+                    }
+                    __syncthreads();
+                    for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
+                        const int i = e / LU_SWC, j = e % LU_SWC;
+                        if (j < nc) A[(long long)(j0 + aff_dst[i]) * ld + c0 + j] = stg[i * LU_SWC + j];
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+    };
+    // U12 = L11^{-1} A12 on columns [c_lo, c_hi) of the rows j0 .. j0+nb (L11
+    // from the panel rows in LDS; one thread per column, all waves), written
+    // back to A, then A22 -= L21 U12 on the rows [j0+nb, rend), one column
+    // block at a time (U12 block staged from A)
+    auto u12_update = [&](int j0, int nb, int c_lo, int c_hi, int rend) {
+#pragma unroll 1
+        for (int col = c_lo + tid; col < c_hi; col += LU_THREADS) {
+            // compiler-only barrier: keeps the L11 reads from LDS inside the
+            // loop (hoisted, they would hold NB(NB-1) values in registers)
+            asm volatile("" ::: "memory");
+            T vr[NB], vi[NB];
+            for (int c = 0; c < NB; ++c) {
+                const bool ok = c < nb;
+                vr[c] = ok ? Ar[(long long)(j0 + c) * ld + col] : T(0);
+                vi[c] = ok ? Ai[(long long)(j0 + c) * ld + col] : T(0);
+            }
+            // fully unrolled (register arrays); rows c >= nb stay zero
+#pragma unroll
+            for (int c = 1; c < NB; ++c) {
+                T sr = vr[c], si = vi[c];
+#pragma unroll
+                for (int k = 0; k < c; ++k) {
+                    const T lr = pr[c * NBP + k], li = pi[c * NBP + k];
+                    sr -= lr * vr[k] - li * vi[k];
+                    si -= lr * vi[k] + li * vr[k];
+                }
+                if (c < nb) {
+                    vr[c] = sr;
+                    vi[c] = si;
+                }
+            }
+            for (int c = 0; c < NB; ++c)
+                if (c < nb) {
+                    Ar[(long long)(j0 + c) * ld + col] = vr[c];
+                    Ai[(long long)(j0 + c) * ld + col] = vi[c];
+                }
+        }
+        __syncthreads();
+        if (rend <= j0 + nb) return;
+        for (int cb = c_lo; cb < c_hi; cb += LU_CB) {
+            const int ncb = min(LU_CB, c_hi - cb);
+            for (int e = tid; e < NB * LU_CB; e += LU_THREADS) {
+                const int c = e / LU_CB, j = e % LU_CB;
+                const bool ok = c < nb && j < ncb;
+                const long long g = (long long)(j0 + min(c, nb - 1)) * ld + cb + min(j, ncb - 1);
+                const T a = Ar[g], b = Ai[g];
+                ur[e] = ok ? a : T(0);
+                ui[e] = ok ? b : T(0);
+            }
+            __syncthreads();
+            trailing_update_cg(Ar, Ai, j0 + nb, rend, ld, nb, cb, ncb, from_panel(j0), ur, ui, LU_CB);
+            __syncthreads();
+        }
+    };
+    for (int J0 = 0; J0 < m; J0 += nbo) {
+      const int jend = min(J0 + nbo, m);             // end of the outer block
+      const int cmax = jend;                         // columns the panels of the block touch
+      for (int j0 = J0; j0 < jend; j0 += NB) {
+        const int nb = min(NB, m - j0), mr = m - j0;
+        for (int e = tid; e < mr * nb; e += LU_THREADS) {
+            const int r = e / nb, c = e % nb;
+            const long long g = (long long)(j0 + r) * ld + j0 + c;
+            pr[r * NBP + c] = Ar[g];
+            pi[r * NBP + c] = Ai[g];
+        }
+        __syncthreads();
+        for (int c = 0; c < nb; ++c) {
+            T best = T(-1);
+            int bi = c;
+            for (int r = c + tid; r < mr; r += LU_THREADS) {
+                const T x = pr[r * NBP + c], y = pi[r * NBP + c];
+                const T v = x * x + y * y;
+                if (v > best) { best = v; bi = r; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                T ov = __shfl_xor(best, off, 64);
+                int oi = __shfl_xor(bi, off, 64);
+                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+            }
+            if (lane == 0) { rv[wv] = best; ri[wv] = bi; }
+            __syncthreads();
+            T bv = rv[0];
+            int p = ri[0];
+            for (int w = 1; w < LU_THREADS / 64; ++w)
+                if (rv[w] > bv || (rv[w] == bv && ri[w] < p)) { bv = rv[w]; p = ri[w]; }
+            if (tid == 0) {
+                piv[j0 + c] = j0 + p;
+                sw[c] = p;
+                bsw[j0 - J0 + c] = p;
+                if (bv == T(0) && info) atomicAdd(info, 1);
+            }
+            if (p != c && tid < nb) {
+                T t = pr[c * NBP + tid];
+                pr[c * NBP + tid] = pr[p * NBP + tid];
+                pr[p * NBP + tid] = t;
+                t = pi[c * NBP + tid];
+                pi[c * NBP + tid] = pi[p * NBP + tid];
+                pi[p * NBP + tid] = t;
+            }
+            __syncthreads();
+            const T dr = pr[c * NBP + c], di = pi[c * NBP + c];
+            const T den = dr * dr + di * di;
+            const T ir = den != T(0) ? dr / den : T(0), ii = den != T(0) ? -di / den : T(0);
+            for (int r = c + 1 + tid; r < mr; r += LU_THREADS) {
+                const T xr = pr[r * NBP + c], xi = pi[r * NBP + c];
+                const T lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
+                pr[r * NBP + c] = lr;
+                pi[r * NBP + c] = li;
+                for (int cc = c + 1; cc < nb; ++cc) {
+                    const T vr = pr[c * NBP + cc], vi = pi[c * NBP + cc];
+                    pr[r * NBP + cc] -= lr * vr - li * vi;
+                    pi[r * NBP + cc] -= lr * vi + li * vr;
+                }
+            }
+            __syncthreads();
+        }
+        // the panel's interchanges on the columns it touches (its own columns
+        // are rewritten below)
+        apply_swaps(j0, nb, 0, cmax);
+        for (int e = tid; e < mr * nb; e += LU_THREADS) {
+            const int r = e / nb, c = e % nb;
+            const long long g = (long long)(j0 + r) * ld + j0 + c;
+            Ar[g] = pr[r * NBP + c];
+            Ai[g] = pi[r * NBP + c];
+        }
+        __syncthreads();
+        u12_update(j0, nb, j0 + nb, cmax, m);
+      }
+      if (cmax < m) {
+        // columns behind the block, untouched so far: the block's interchanges
+        // in panel order, U of the block's rows (blocked forward substitution
+        // with the block's L11), then one update of the rows and columns
+        // behind the block with K = jend - J0 (L from global memory, U staged
+        // in LDS LU_CBD columns at a time)
+        for (int j0 = J0; j0 < jend; j0 += NB) {
+            const int nb = min(NB, m - j0);
+            if (tid < nb) sw[tid] = bsw[j0 - J0 + tid];
+            __syncthreads();
+            apply_swaps(j0, nb, jend, m);
+        }
+        for (int j0 = J0; j0 < jend; j0 += NB) {
+            const int nb = min(NB, m - j0), nr = jend - j0;
+            for (int e = tid; e < nr * nb; e += LU_THREADS) {
+                const int r = e / nb, c = e % nb;
+                const long long g = (long long)(j0 + r) * ld + j0 + c;
+                pr[r * NBP + c] = Ar[g];
+                pi[r * NBP + c] = Ai[g];
+            }
+            __syncthreads();
+            u12_update(j0, nb, jend, m, jend);
+        }
+        const int kk = jend - J0;
+        for (int cb = jend; cb < m; cb += LU_CBD) {
+            const int ncb = min(LU_CBD, m - cb);
+            for (int e = tid; e < kk * LU_CBD; e += LU_THREADS) {
+                const int c = e / LU_CBD, j = e - c * LU_CBD;
+                const long long g = (long long)(J0 + c) * ld + cb + min(j, ncb - 1);
+                const T a = Ar[g], b = Ai[g];
+                ur[e] = j < ncb ? a : T(0);
+                ui[e] = j < ncb ? b : T(0);
+            }
+            __syncthreads();
+            trailing_update_cg(Ar, Ai, jend, m, ld, kk, cb, ncb,
+                              [=](int row, int k, T &lr, T &li) {
+                                  const long long g = (long long)row * ld + J0 + k;
+                                  lr = Ar[g];
+                                  li = Ai[g];
+                              },
+                              ur, ui, LU_CBD);
+            __syncthreads();
+        }
+      }
     }
 }
 
@@ -2699,6 +3027,12 @@ template <int NB, typename T> size_t lu_c_lds_bytes(int m)
     return ((size_t)2 * m * (NB + 1) + (size_t)2 * NB * LU_CB + (size_t)2 * NB * LU_SWC) * sizeof(T);
 }
 
+// LDS of lu_kernel_c2
+template <int NB> size_t lu_c2_lds_bytes(int m)
+{
+    return ((size_t)2 * m * (NB + 1) + (size_t)2 * lu_c_u_words(NB, LU_CB) + (size_t)2 * NB * LU_SWC) * sizeof(float);
+}
+
 } // namespace
 
 // ---------------------------------------------------------------------------
@@ -2891,6 +3225,28 @@ template <typename T>
 hipError_t launch_lu_c(T *A, int *piv, int m, int ld, long long a_stride, int batch, int *info, size_t max_lds,
                        hipStream_t s)
 {
+    if constexpr (std::is_same<T, float>::value) {
+        if (m > LU_NBO_MIN_M) {
+            // two blocking levels: the widest panel (16 or 8, within the
+            // STMG_LU_NB cap) with two workgroups per CU, else the widest that fits
+            int cap2 = std::min(lu_nb_cap(), 16);
+            for (int nb = cap2; nb >= 8; nb /= 2) {
+                const size_t b = nb == 16 ? lu_c2_lds_bytes<16>(m) : lu_c2_lds_bytes<8>(m);
+                if (2 * b <= CU_LDS && b <= max_lds) { cap2 = nb; break; }
+            }
+#define LUC2(NBV)                                                                                                      \
+    if (NBV <= cap2 && lu_c2_lds_bytes<NBV>(m) <= max_lds) {                                                           \
+        size_t bytes = lu_c2_lds_bytes<NBV>(m);                                                                        \
+        hipError_t e = lds_attr((const void *)lu_kernel_c2<float, NBV>, bytes);                                        \
+        if (e != hipSuccess) return e;                                                                                 \
+        hipLaunchKernelGGL((lu_kernel_c2<float, NBV>), dim3(batch), dim3(LU_THREADS), bytes, s, A, piv, m, ld, a_stride, \
+                           info);                                                                                      \
+        return hipGetLastError();                                                                                      \
+    }
+            LUC2(16) LUC2(8) LUC2(4)
+#undef LUC2
+        }
+    }
     int cap = lu_nb_cap();
     for (int nb = cap; nb >= 16; nb /= 2) {
         const size_t b = nb == 32 ? lu_c_lds_bytes<32, T>(m) : nb == 16 ? lu_c_lds_bytes<16, T>(m)
