@@ -1163,18 +1163,34 @@ __device__ __forceinline__ void lu_one(T *__restrict__ A, int m, int ld, int *__
         __syncthreads();
         const int na = n_aff;
         if (na > 0) {
-            for (int c0 = c_lo; c0 < c_hi; c0 += LU_SWC) {
-                const int nc = min(LU_SWC, c_hi - c0);
-                for (int e = tid; e < na * LU_SWC; e += NTH) {
-                    int i = e / LU_SWC, j = e % LU_SWC;
-                    if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * ld + c0 + j];
+            if constexpr (NB <= 16) {
+                // one column per thread: the column's affected entries to
+                // registers, then to their new rows (columns are independent:
+                // no staging, no barrier between column chunks)
+                for (int col = c_lo + tid; col < c_hi; col += NTH) {
+                    T v[2 * NB];
+#pragma unroll
+                    for (int i = 0; i < 2 * NB; ++i)
+                        if (i < na) v[i] = A[(long long)(j0 + aff_src[i]) * ld + col];
+#pragma unroll
+                    for (int i = 0; i < 2 * NB; ++i)
+                        if (i < na) A[(long long)(j0 + aff_dst[i]) * ld + col] = v[i];
                 }
                 __syncthreads();
-                for (int e = tid; e < na * LU_SWC; e += NTH) {
-                    int i = e / LU_SWC, j = e % LU_SWC;
-                    if (j < nc) A[(long long)(j0 + aff_dst[i]) * ld + c0 + j] = stg[i * LU_SWC + j];
+            } else {
+                for (int c0 = c_lo; c0 < c_hi; c0 += LU_SWC) {
+                    const int nc = min(LU_SWC, c_hi - c0);
+                    for (int e = tid; e < na * LU_SWC; e += NTH) {
+                        int i = e / LU_SWC, j = e % LU_SWC;
+                        if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * ld + c0 + j];
+                    }
+                    __syncthreads();
+                    for (int e = tid; e < na * LU_SWC; e += NTH) {
+                        int i = e / LU_SWC, j = e % LU_SWC;
+                        if (j < nc) A[(long long)(j0 + aff_dst[i]) * ld + c0 + j] = stg[i * LU_SWC + j];
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
         }
     };
