@@ -24,6 +24,7 @@
 //          M-norm of eq. inexact)
 #include "stmg_internal.h"
 
+#include <cstdlib>
 #include <mutex>
 #include <type_traits>
 
@@ -875,15 +876,18 @@ __device__ __forceinline__ int pmode_compact(int i0, int i1, int i2)
     return cnt + i0;
 }
 
-template <int R, int NQ, int NTH, typename T, bool MAPPED>
-__global__ void __launch_bounds__(NTH) jac_cell_kernel(CellArgs<T> A)
+// FUSED: the boundary-face items run in the same launch and add onto this
+// cell's E entries and pressure rows; for cells on the domain boundary the
+// volume result is then added atomically too (onto entries zeroed before the
+// launch)
+template <int R, int NQ, int NTH, typename T, bool MAPPED, bool FUSED>
+__device__ __forceinline__ void jac_cell_body(const CellArgs<T> &A, const int cell, const int vec, T *sm,
+                                              const int tid)
 {
     using LY = JacLds<R, NQ>;
     constexpr int N1 = R + 2, RP1 = R + 1, NL = LY::NL, NPF = RP1 * RP1 * RP1, NPM = Sizes<3, R>::NPM;
     constexpr int NQV = LY::NQV, QN2 = LY::QN2, QQN = LY::QQN, N2 = N1 * N1, RP2 = RP1 * RP1;
 
-    extern __shared__ unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);
     T *tS = sm + LY::TS, *tD = sm + LY::TD, *tL = sm + LY::TL, *qw = sm + LY::QW, *qxs = sm + LY::QX;
     T *geo = sm + LY::GEO;
     T *P = sm + LY::RP, *Y = sm + LY::RY;
@@ -892,9 +896,6 @@ __global__ void __launch_bounds__(NTH) jac_cell_kernel(CellArgs<T> A)
     T *XP = sm + LY::XP0;                 // [nt][NPF]
     T *XS = XP + nt * NPF;                // [nt][3][NL]
 
-    const int tid = threadIdx.x;
-    const int cell = xcd_cell(blockIdx.x, gridDim.x);
-    const int vec = blockIdx.y;
     const T *__restrict__ x = A.x + vec * A.xstride;
     T *__restrict__ y = A.y + vec * A.ystride;
     T *__restrict__ E = A.E + (long long)vec * A.ncell * nt * 3 * NL;
@@ -918,6 +919,8 @@ __global__ void __launch_bounds__(NTH) jac_cell_kernel(CellArgs<T> A)
     const int c0 = cell % A.n0;
     const int c1 = (cell / A.n0) % A.n1;
     const int c2 = cell / (A.n0 * A.n1);
+    const bool atomic_out =
+        FUSED && (c0 == 0 || c0 == A.n0 - 1 || c1 == 0 || c1 == A.n1 - 1 || c2 == 0 || c2 == A.n2 - 1);
     const long long N0 = (long long)(R + 1) * A.n0 + 1;
     const long long N1g = (long long)(R + 1) * A.n1 + 1;
     auto gnode = [&](int l) -> long long {
@@ -1309,7 +1312,8 @@ __global__ void __launch_bounds__(NTH) jac_cell_kernel(CellArgs<T> A)
                             s += S[o * N1 + k] * ua[o];
                             s += D[o * N1 + k] * uc[o];
                         }
-                        Ec[c * NL + k * N2 + ji] = s;
+                        if (atomic_out) unsafeAtomicAdd(Ec + c * NL + k * N2 + ji, s);
+                        else Ec[c * NL + k * N2 + ji] = s;
                     }
                 } else if (w >= O1) {
                     const int ji = w - O1, jp = ji / RP1, ip = ji - jp * RP1;
@@ -1323,7 +1327,8 @@ __global__ void __launch_bounds__(NTH) jac_cell_kernel(CellArgs<T> A)
                             T s = 0;
 #pragma unroll
                             for (int o = 0; o < NQ; ++o) s += L[o * RP1 + kp] * u[o];
-                            y[pbase + a * A.Np1 + (long long)cell * NPM + e] = s;
+                            if (atomic_out) unsafeAtomicAdd(y + pbase + a * A.Np1 + (long long)cell * NPM + e, s);
+                            else y[pbase + a * A.Np1 + (long long)cell * NPM + e] = s;
                         }
                     }
                 }
@@ -1335,6 +1340,14 @@ __global__ void __launch_bounds__(NTH) jac_cell_kernel(CellArgs<T> A)
             __syncthreads();
         }
     }
+}
+
+template <int R, int NQ, int NTH, typename T, bool MAPPED>
+__global__ void __launch_bounds__(NTH) jac_cell_kernel(CellArgs<T> A)
+{
+    extern __shared__ unsigned char smem_raw[];
+    jac_cell_body<R, NQ, NTH, T, MAPPED, false>(A, xcd_cell(blockIdx.x, gridDim.x), blockIdx.y,
+                                                reinterpret_cast<T *>(smem_raw), threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1379,8 +1392,28 @@ __host__ __device__ constexpr int face_lds_words(int tabwords)
     return LY::FTAB + 2 * DIM * Z::NL + 2 * Z::NPF + LY::SCR1 + LY::TMP2 + 32;
 }
 
-template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE>
-__global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
+// barrier of one face item: the workgroup, or (FUSED: several items per
+// workgroup, one per wavefront, each with its own LDS slice) the wavefront,
+// whose LDS accesses complete in issue order
+template <bool WAVE> __device__ __forceinline__ void face_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// One (boundary cell, time node) item, bsl = index into the boundary cells x
+// time nodes, by NTH = 64 threads.  Not FUSED: added to the volume result
+// already in E and in the pressure rows.  FUSED: the volume pass runs in the
+// same launch and adds its result atomically as well, onto entries zeroed
+// before the launch; with exactly two contributions per entry the sum does not
+// depend on their order, so results stay bitwise reproducible.
+template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE, bool FUSED>
+__device__ __forceinline__ void face_item(const CellArgs<T> &A, const int bsl, const int vec, T *sm, const int tid)
 {
     using Z = Sizes<DIM, R>;
     using LY = FaceLds<DIM, R, NQ, T>;
@@ -1390,14 +1423,9 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
     constexpr int N12 = DIM == 2 ? 1 : N1;
     constexpr int RP12 = DIM == 2 ? 1 : RP1;
 
-    extern __shared__ unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);
-
-    const int tid = threadIdx.x;
-    const int bsl = xcd_cell(blockIdx.x, gridDim.x);
+    static_assert(NTH == 64, "one wavefront per face item");
     const int cell = A.bcells[bsl / A.nt];
-    const int a = bsl % A.nt;                     // one time node per workgroup
-    const int vec = blockIdx.y;
+    const int a = bsl % A.nt;                     // one time node per item
     const int nt = A.nt;
     const T *__restrict__ x = A.x + vec * A.xstride;
     T *__restrict__ y = A.y + vec * A.ystride;
@@ -1468,7 +1496,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                 const T *st = A.state + vec * A.sstride;
                 ns[e] = st[g];
             }
-            yr[j] = Ec[e];
+            yr[j] = FUSED ? T(0) : Ec[e];
         }
     }
     constexpr int PP = (NPM + NTH - 1) / NTH;
@@ -1479,14 +1507,14 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
         if (e < NPM) {
             const long long gi = pbase + a * A.Np1 + (long long)cell * NPM + e;
             px[j] = x[gi];
-            py[j] = y[gi];
+            py[j] = FUSED ? T(0) : y[gi];
         }
     }
     for (int e = tid; e < NPF; e += NTH) {
         xpf[e] = 0;
         ypf[e] = 0;
     }
-    __syncthreads();
+    face_sync<FUSED>();
 #pragma unroll
     for (int j = 0; j < PP; ++j) {
         const int e = tid + j * NTH;
@@ -1515,13 +1543,13 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                 part += w;
             }
             t1[tid] = part;
-            __syncthreads();
+            face_sync<FUSED>();
             if (tid == 0) {
                 T vol = 0;
                 for (int i = 0; i < NTH; ++i) vol += t1[i];
                 geo[30] = vol;
             }
-            __syncthreads();
+            face_sync<FUSED>();
             // face areas: one face at a time, fixed order
             for (int fid = 0; fid < 2 * DIM; ++fid) {
                 int ax = fid / 2, side = fid % 2;
@@ -1538,17 +1566,17 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                     for (int d = 0; d < DIM; ++d) len += Jit[d][ax] * Jit[d][ax];
                     t2[q] = fabs(det) * sqrt(len) * wt;
                 }
-                __syncthreads();
+                face_sync<FUSED>();
                 if (tid == 0) {
                     T area = 0;
                     for (int q = 0; q < NQF; ++q) area += t2[q];
                     hF[fid] = geo[30] / area;
                 }
-                __syncthreads();
+                face_sync<FUSED>();
             }
         }
     }
-    __syncthreads();
+    face_sync<FUSED>();
 
 
     {
@@ -1608,7 +1636,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                                 play[it] = s;
                             }
                         }
-                        __syncthreads();
+                        face_sync<FUSED>();
                         // 2. tangential interpolation to the face points q = q0 + NQ q1
                         if constexpr (DIM == 3) {
                             // contract t0: pipes xS (DIM), xD (DIM), nS (DIM), vS (DIM), p; item (pipe, j1)
@@ -1630,7 +1658,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                                     pencil_apply<RP1, NQ>(play + j1 * RP1, 1, abuf + NPV * N1 * NQ + j1 * NQ, 1, Lp);
                                 }
                             }
-                            __syncthreads();
+                            face_sync<FUSED>();
                             // contract t1: item (output field, q0); outputs x (S), g_t1 (D), g_t0, g_ax, v, p
                             constexpr int NOF = 5 * DIM + 1;
                             for (int w = tid; w < NOF * NQ; w += NTH) {
@@ -1651,7 +1679,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                                     pencil_apply<RP1, NQ>(abuf + NPV * N1 * NQ + q0, NQ, FQ + FP * NQF + q0, NQ, Lp);
                                 }
                             }
-                            __syncthreads();
+                            face_sync<FUSED>();
                         } else {
                             // one tangential axis: item = output field
                             for (int w = tid; w < 4 * DIM + 1; w += NTH) {
@@ -1668,7 +1696,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                                     pencil_apply<RP1, NQ>(play, 1, FQ + FP * NQF, 1, Lp);
                                 }
                             }
-                            __syncthreads();
+                            face_sync<FUSED>();
                         }
                         // 3. point terms
                         for (int q = tid; q < NQF; q += NTH) {
@@ -1748,7 +1776,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                                 }
                             FQ[(FO + DIM + DIM * DIM) * NQF + q] = sc * pco;
                         }
-                        __syncthreads();
+                        face_sync<FUSED>();
                         // 4. transposed tangential passes into value / normal-derivative layers
                         //    A_c (value layer: val, tangential gradient coefficients), B_c (normal
                         //    derivative layer: normal gradient coefficient), P (pressure)
@@ -1783,7 +1811,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                                     pencil_apply_t<RP1, NQ>(FQ + (FO + DIM + DIM * DIM) * NQF + q0, NQ, out, NQ, Lp);
                                 }
                             }
-                            __syncthreads();
+                            face_sync<FUSED>();
                             // contract q0: item (layer, j1); A_c = S^T(pipe c) + D^T(pipe DIM+c), B_c = S^T(pipe 2DIM+c)
                             for (int w = tid; w < 2 * DIM * N1 + RP1; w += NTH) {
                                 if (w < 2 * DIM * N1) {
@@ -1810,7 +1838,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                                     pencil_apply_t<RP1, NQ>(abuf + 3 * DIM * N1 * NQ + j1 * NQ, 1, Play + j1 * RP1, 1, Lp);
                                 }
                             }
-                            __syncthreads();
+                            face_sync<FUSED>();
                         } else {
                             for (int w = tid; w < 2 * DIM + 1; w += NTH) {
                                 const int grp = w / DIM, c = w - grp * DIM;
@@ -1834,7 +1862,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                                     pencil_apply_t<RP1, NQ>(FQ + (FO + DIM + DIM * DIM) * NQF, 1, Play, 1, Lp);
                                 }
                             }
-                            __syncthreads();
+                            face_sync<FUSED>();
                         }
                         // 5. expansion along the normal into the nodal (registers) and
                         //    modal outputs
@@ -1853,7 +1881,7 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
                             const int it = mi[ta0] + (DIM == 3 ? RP1 * mi[ta1] : 0);
                             ypf[m] += Lrow[mi[ax]] * Play[it];
                         }
-                        __syncthreads();
+                        face_sync<FUSED>();
                 };
                 // faces in the fixed order x-, x+, y-, y+, z-, z+
                 using I0 = std::integral_constant<int, 0>;
@@ -1874,12 +1902,81 @@ __global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
 #pragma unroll
         for (int j = 0; j < YR; ++j) {
             const int e = tid + j * NTH;
-            if (e < DIM * NL) Ec[e] = yr[j];
+            if (e < DIM * NL) {
+                if constexpr (FUSED) unsafeAtomicAdd(Ec + e, yr[j]);
+                else Ec[e] = yr[j];
+            }
         }
         for (int e = tid; e < NPM; e += NTH) {
             const long long gi = pbase + a * A.Np1 + (long long)cell * NPM + e;
-            y[gi] = ypf[pmode_full<DIM, R>(e)];
+            if constexpr (FUSED) unsafeAtomicAdd(y + gi, ypf[pmode_full<DIM, R>(e)]);
+            else y[gi] = ypf[pmode_full<DIM, R>(e)];
         }
+    }
+}
+
+template <int DIM, int R, int NQ, int NTH, typename T, Mode MODE>
+__global__ void __launch_bounds__(NTH) face_kernel(CellArgs<T> A)
+{
+    extern __shared__ unsigned char smem_raw[];
+    face_item<DIM, R, NQ, NTH, T, MODE, false>(A, xcd_cell(blockIdx.x, gridDim.x), blockIdx.y,
+                                              reinterpret_cast<T *>(smem_raw), threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// 3D Jacobian, volume and boundary faces in one launch.  Workgroups come in
+// groups of eight consecutive blocks (one per XCD); after every `period`
+// volume groups comes one face group, whose workgroups give each of their
+// NTH / 64 wavefronts one (boundary cell, time node) item with its own LDS
+// slice, so face work runs beside the volume work instead of after it.
+// Volume groups keep the XCD-contiguous cell order of xcd_cell.  The E
+// entries and pressure rows of boundary cells are zeroed before the launch
+// (zero_boundary_kernel); both passes add onto them atomically.
+// ---------------------------------------------------------------------------
+struct FusedGrid {
+    int nvg;      // volume groups: ceil(ncell / 8)
+    int nfg;      // face groups
+    int period;   // volume groups per face group
+};
+
+template <int R, int NQ, int NTH, typename T, bool MAPPED>
+__global__ void __launch_bounds__(NTH) jac_fused_kernel(CellArgs<T> A, FusedGrid F)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    const int b = blockIdx.x, x = b & 7, g = b >> 3;
+    const int p1 = F.period + 1, per = g / p1, pos = g - per * p1;
+    if (pos == F.period && per < F.nfg) {
+        constexpr int W = NTH / 64;
+        const int w = threadIdx.x >> 6;
+        const int item = (per * 8 + x) * W + w;
+        if (item >= A.nbcell * A.nt) return;   // whole wavefront; face items synchronize per wavefront
+        face_item<3, R, NQ, 64, T, Mode::Jac, true>(A, item, blockIdx.y, sm + w * face_lds_words<3, R, NQ, T>(0),
+                                                    threadIdx.x & 63);
+        return;
+    }
+    const int vg = g - min(per, F.nfg);
+    const int q = A.ncell >> 3, rem = A.ncell & 7;
+    if (vg >= q + (x < rem ? 1 : 0)) return;   // whole workgroup
+    jac_cell_body<R, NQ, NTH, T, MAPPED, true>(A, x * q + min(x, rem) + vg, blockIdx.y, sm, threadIdx.x);
+}
+
+// E entries (3 (r+2)^3 per time node) and pressure rows of the boundary cells,
+// all time nodes and vectors, set to zero
+template <typename T>
+__global__ void __launch_bounds__(256) zero_boundary_kernel(CellArgs<T> A, int nl, int npm)
+{
+    const int per = 3 * nl + npm;
+    const long long n = (long long)A.nbcell * A.nt * per;
+    const int vec = blockIdx.y;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const int e = (int)(i % per);
+        const long long bsl = i / per;
+        const int cell = A.bcells[bsl / A.nt], a = (int)(bsl % A.nt);
+        if (e < 3 * nl)
+            A.E[(long long)vec * A.ncell * A.nt * 3 * nl + ((long long)cell * A.nt + a) * 3 * nl + e] = T(0);
+        else
+            A.y[vec * A.ystride + (long long)A.nt * A.Nv1 + a * A.Np1 + (long long)cell * npm + (e - 3 * nl)] = T(0);
     }
 }
 
@@ -2014,6 +2111,62 @@ static hipError_t launch_jac(const CellArgs<T> &a, int nvec, hipStream_t s)
     return hipGetLastError();
 }
 
+// 3D Jacobian with its boundary faces in one launch (after zeroing what both
+// passes add to)
+template <int R, int NQ, typename T>
+static hipError_t launch_jac_fused(const CellArgs<T> &a, int nvec, hipStream_t s)
+{
+    constexpr int NTH = jac_threads<R, NQ, T>();
+    constexpr int W = NTH / 64;
+    constexpr int nl = (R + 2) * (R + 2) * (R + 2), npm = Sizes<3, R>::NPM;
+    if (a.nbcell > 0) {
+        const long long n = (long long)a.nbcell * a.nt * (3 * nl + npm);
+        const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+        hipLaunchKernelGGL(zero_boundary_kernel<T>, dim3(blocks, nvec), dim3(256), 0, s, a, nl, npm);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    FusedGrid F;
+    F.nvg = (a.ncell + 7) / 8;
+    const int fwg = (a.nbcell * a.nt + W - 1) / W;
+    F.nfg = (fwg + 7) / 8;
+    F.period = F.nfg > 0 ? F.nvg / F.nfg : F.nvg;
+    const size_t words = std::max<size_t>(jac_lds_words<R, NQ, T>(a.nt), (size_t)W * face_lds_words<3, R, NQ, T>(0));
+    const size_t bytes = words * sizeof(T);
+    auto kern = a.mapped ? jac_fused_kernel<R, NQ, NTH, T, true> : jac_fused_kernel<R, NQ, NTH, T, false>;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    static size_t attr_bytes[2] = {0, 0};   // per kernel (affine, mapped)
+    size_t &have = attr_bytes[a.mapped ? 1 : 0];
+    static int max_lds = -1;
+    if (max_lds < 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            max_lds = 65536;
+    }
+    if (bytes > (size_t)max_lds) return hipErrorInvalidConfiguration;
+    if (bytes > have) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        have = bytes;
+    }
+    dim3 grid(8 * (F.nvg + F.nfg), nvec);
+    hipLaunchKernelGGL(kern, grid, dim3(NTH), bytes, s, a, F);
+    return hipGetLastError();
+}
+
+template <int R, typename T>
+static hipError_t dispatch_fused_nq(int nq, const CellArgs<T> &a, int nvec, hipStream_t s)
+{
+    constexpr int NQD = (3 * R + 5) / 2;
+    if (nq == NQD) return launch_jac_fused<R, NQD, T>(a, nvec, s);
+    if constexpr (R + 2 != NQD) {
+        if (nq == R + 2) return launch_jac_fused<R, R + 2, T>(a, nvec, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <int DIM, int R, int NQ, typename T, Mode MODE>
 static hipError_t launch_one(const CellArgs<T> &a, int nvec, hipStream_t s)
 {
@@ -2102,6 +2255,36 @@ hipError_t launch_face_op(Mode mode, int dim, int r, int nq, const CellArgs<T> &
     return hipErrorInvalidValue;
 }
 
+// whether the 3D Jacobian runs its boundary faces in the volume launch: in
+// FP32 only.  Measured on one MI355X, one Jacobian application at 16^3 cells
+// (separate launches vs one launch): r = 2, n_q = 5: FP64 117 vs 138 us (the
+// union of both passes needs 133 VGPRs, a workgroup per CU less than the
+// volume pass alone), FP32 79 vs 74; n_q = 4: FP64 97 vs 98, FP32 67 vs 62;
+// the 32^3 r = 3 slab solve 2.18 s either way.  STMG_JAC_FUSED=0/1 overrides
+// the choice (for measurement).
+bool jac_fuse_faces(int r, int nq, bool f64)
+{
+    static const int env = [] {
+        const char *e = std::getenv("STMG_JAC_FUSED");
+        return e ? std::atoi(e) : -1;
+    }();
+    if (env == 0 || env == 1) return env == 1;
+    (void)r;
+    (void)nq;
+    return !f64;
+}
+
+template <typename T>
+hipError_t launch_jac_fused_op(int r, int nq, const CellArgs<T> &a, int nvec, hipStream_t s)
+{
+    switch (r) {
+    case 1: return dispatch_fused_nq<1, T>(nq, a, nvec, s);
+    case 2: return dispatch_fused_nq<2, T>(nq, a, nvec, s);
+    case 3: return dispatch_fused_nq<3, T>(nq, a, nvec, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_cell_op(Mode mode, int dim, int r, int nq, const CellArgs<T> &a, int nvec, hipStream_t s)
 {
@@ -2152,6 +2335,8 @@ hipError_t launch_gather(const GatherArgs<T> &g, int nvec, hipStream_t s)
 
 template hipError_t launch_face_op<double>(Mode, int, int, int, const CellArgs<double> &, int, hipStream_t);
 template hipError_t launch_face_op<float>(Mode, int, int, int, const CellArgs<float> &, int, hipStream_t);
+template hipError_t launch_jac_fused_op<double>(int, int, const CellArgs<double> &, int, hipStream_t);
+template hipError_t launch_jac_fused_op<float>(int, int, const CellArgs<float> &, int, hipStream_t);
 template hipError_t launch_cell_op<double>(Mode, int, int, int, const CellArgs<double> &, int, hipStream_t);
 template hipError_t launch_cell_op<float>(Mode, int, int, int, const CellArgs<float> &, int, hipStream_t);
 template hipError_t launch_gather<double>(const GatherArgs<double> &, int, hipStream_t);

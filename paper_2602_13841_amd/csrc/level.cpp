@@ -160,11 +160,14 @@ void Level::apply(Mode mode, const T *state, const T *x, T *y, const T *rhs, con
     static const char *names64[3] = {"cell_jac_f64", "cell_res_f64", "cell_mass_f64"};
     static const char *names32[3] = {"cell_jac_f32", "cell_res_f32", "cell_mass_f32"};
     const char *nm = f64 ? names64[(int)mode] : names32[(int)mode];
+    // 3D Jacobian: the boundary faces run in the same launch as the volume
+    const bool fused = mode == Mode::Jac && dim == 3 && jac_fuse_faces(r, nq, f64);
     {
         TimerScope ts(timers, nm, s);
-        STMG_HIP(launch_cell_op<T>(mode, dim, r, nq, a, nvec, s));
+        if (fused) STMG_HIP(launch_jac_fused_op<T>(r, nq, a, nvec, s));
+        else STMG_HIP(launch_cell_op<T>(mode, dim, r, nq, a, nvec, s));
     }
-    if (faces) {
+    if (faces && !fused) {
         static const char *fn64[2] = {"face_jac_f64", "face_res_f64"};
         static const char *fn32[2] = {"face_jac_f32", "face_res_f32"};
         TimerScope ts(timers, f64 ? fn64[(int)mode] : fn32[(int)mode], s);

@@ -143,5 +143,10 @@ template <typename T>
 hipError_t launch_face_op(Mode mode, int dim, int r, int nq, const CellArgs<T> &a, int nvec, hipStream_t s);
 template <typename T>
 hipError_t launch_gather(const GatherArgs<T> &g, int nvec, hipStream_t s);
+// 3D Jacobian: volume and boundary-face terms in one launch (replaces
+// launch_cell_op + launch_face_op for Mode::Jac, dim 3)
+template <typename T>
+hipError_t launch_jac_fused_op(int r, int nq, const CellArgs<T> &a, int nvec, hipStream_t s);
+bool jac_fuse_faces(int r, int nq, bool f64);
 
 } // namespace stmg
