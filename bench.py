@@ -184,7 +184,17 @@ def cpu_baseline(U, X, seconds=12.0):
     return {"value": slab.N * frac / dt, "unit": "DoF/s", "cores": threads, "kind": "oracle",
             "sample": f"{done_cells} cells x {slab.nt} time nodes of the 16^3 workload "
                       f"({100 * frac:.1f}% of one vmult), element-matrix action, {dt:.1f} s",
-            "cpu_model": cpu_model(), "solve_2d_4x4": cpu_solve_c1(), "lu_fp64_patch_sizes": cpu_lu_sample()}
+            "cpu_model": cpu_model(), "solve_2d_4x4": cpu_solve_c1(), "lu_fp64_patch_sizes": cpu_lu_sample(),
+            "residual_16cube": cpu_residual(slab, U)}
+
+
+def cpu_residual(slab, U):
+    """The oracle's slab residual R_n(U) (eq. InAlgNS, element loop) of the
+    whole 16^3 workload on the host: wall time and DoF/s."""
+    t0 = time.perf_counter()
+    slab.residual(U)
+    dt = time.perf_counter() - t0
+    return {"N": slab.N, "wall_s": dt, "dof_per_s": slab.N / dt}
 
 
 SOLVE_WORKLOAD = dict(dim=3, n=(32, 32, 32), r=3, k=1, nu=1e-3, tau=1.0 / 64, perturb=0.2, vert_seed=4, v0_seed=5)
@@ -501,6 +511,31 @@ def main():
 
     t64, cell64, face64, gat64, nsets64, per64 = run(torch.float64, args.steps, args.warmup)
     t32, cell32, face32, gat32, nsets32, per32 = run(torch.float32, args.steps, args.warmup)
+
+    # the FP64 slab residual R_n(U) of the same workload (eq. InAlgNS): at least
+    # 100 applications timed one by one, input sets rotating as above
+    def run_residual(nrep=100, warmup=5):
+        per_set = 2 * N * 8
+        nsets = max(2, int(np.ceil(args.rotate_bytes / per_set)))
+        Us = [torch.tensor(U, device=dev) for _ in range(nsets)]
+        Rs = [torch.empty(N, dtype=torch.float64, device=dev) for _ in range(nsets)]
+        for i in range(warmup):
+            ctx.residual(Us[i % nsets], Rs[i % nsets])
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nrep)]
+        torch.cuda.synchronize()
+        for i in range(nrep):
+            evs[i][0].record()
+            ctx.residual(Us[i % nsets], Rs[i % nsets])
+            evs[i][1].record()
+        torch.cuda.synchronize()
+        per = np.array([a.elapsed_time(b) for a, b in evs])
+        del Us, Rs
+        torch.cuda.empty_cache()
+        return {"value": N / (np.median(per) * 1e-3), "unit": "DoF/s", "median_ms": float(np.median(per)),
+                "p10_ms": float(np.percentile(per, 10)), "p90_ms": float(np.percentile(per, 90)),
+                "timed_one_by_one": nrep, "rotating_sets": nsets}
+
+    res64 = run_residual()
     del ctx
     torch.cuda.empty_cache()
     # the same workload with the cheaper spatial quadrature n_q = r + 2
@@ -544,6 +579,7 @@ def main():
                          "algorithmic_bytes": bytes64, "cell_ms": cell64, "face_ms": face64, "gather_ms": gat64,
                          "device_copy_GBps": copy_gbs, "frac_of_device_copy": bytes64 / (t64 * copy_gbs * 1e9)},
         "per_application_fp64": per64,
+        "residual_fp64": res64,
         "fp32": {"value": N / t32, "unit": "DoF/s", "ms_per_step": t32 * 1e3, "cell_ms": cell32,
                  "face_ms": face32, "gather_ms": gat32, "speedup_vs_fp64": t64 / t32, "per_application": per32},
         "nq_r_plus_2": {"n_q": nq_p, "fp64": {"value": N / tp64, "ms_per_step": tp64 * 1e3, "cell_ms": cellp64,
