@@ -944,22 +944,35 @@ __device__ __forceinline__ void trailing_update(float *A, int r0, int m, int ld,
             if (tn < ntile) load(tn, nxt);
         }
         if constexpr (OP == 0) {
-            for (int k0 = 0; k0 < nb; k0 += 4) {
-                const int k = k0 + (lane >> 4);
-                float a[2], b[2];
+            // L operands of UK k-steps loaded before their products (the
+            // once-per-block update reads L from global memory: one latency
+            // per UK steps instead of one per step)
+            constexpr int UK = 8;
+            for (int k0 = 0; k0 < nb; k0 += 4 * UK) {
+                float a[UK][2];
 #pragma unroll
-                for (int si = 0; si < 2; ++si) {
-                    const int row = R + 16 * si + (lane & 15);
-                    const float v = lop(min(row, m - 1), min(k, nb - 1));
-                    a[si] = (row < m && k < nb) ? -v : 0.0f;
+                for (int u = 0; u < UK; ++u) {
+                    const int k = k0 + 4 * u + (lane >> 4);
+#pragma unroll
+                    for (int si = 0; si < 2; ++si) {
+                        const int row = R + 16 * si + (lane & 15);
+                        const float v = lop(min(row, m - 1), min(k, nb - 1));
+                        a[u][si] = (row < m && k < nb) ? -v : 0.0f;
+                    }
                 }
 #pragma unroll
-                for (int sj = 0; sj < 2; ++sj) b[sj] = k < nb ? ut[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)] : 0.0f;
-#pragma unroll
-                for (int si = 0; si < 2; ++si)
+                for (int u = 0; u < UK; ++u) {
+                    const int k = k0 + 4 * u + (lane >> 4), kc = min(k, nb - 1);
+                    float b[2];
 #pragma unroll
                     for (int sj = 0; sj < 2; ++sj)
-                        acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[si], b[sj], acc[si][sj], 0, 0, 0);
+                        b[sj] = k < nb ? ut[kc * LU_CB + (C - cb) + 16 * sj + (lane & 15)] : 0.0f;
+#pragma unroll
+                    for (int si = 0; si < 2; ++si)
+#pragma unroll
+                        for (int sj = 0; sj < 2; ++sj)
+                            acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][si], b[sj], acc[si][sj], 0, 0, 0);
+                }
             }
         } else {
             for (int k0 = 0; k0 < nb; k0 += 16) {
@@ -1051,22 +1064,33 @@ __device__ __forceinline__ void trailing_update(double *A, int r0, int m, int ld
         } else {
             if (tn < ntile) load(tn, nxt);
         }
-        for (int k0 = 0; k0 < nb; k0 += 4) {
-            const int k = k0 + (lane >> 4);
-            double a[2], b[2];
+        // L operands of UK k-steps loaded before their products (see FP32)
+        constexpr int UK = 4;
+        for (int k0 = 0; k0 < nb; k0 += 4 * UK) {
+            double a[UK][2];
 #pragma unroll
-            for (int si = 0; si < 2; ++si) {
-                const int row = R + 16 * si + (lane & 15);
-                const double v = lop(min(row, m - 1), min(k, nb - 1));
-                a[si] = (row < m && k < nb) ? -v : 0.0;
+            for (int u = 0; u < UK; ++u) {
+                const int k = k0 + 4 * u + (lane >> 4);
+#pragma unroll
+                for (int si = 0; si < 2; ++si) {
+                    const int row = R + 16 * si + (lane & 15);
+                    const double v = lop(min(row, m - 1), min(k, nb - 1));
+                    a[u][si] = (row < m && k < nb) ? -v : 0.0;
+                }
             }
 #pragma unroll
-            for (int sj = 0; sj < 2; ++sj) b[sj] = k < nb ? ut[k * LU_CB + (C - cb) + 16 * sj + (lane & 15)] : 0.0;
-#pragma unroll
-            for (int si = 0; si < 2; ++si)
+            for (int u = 0; u < UK; ++u) {
+                const int k = k0 + 4 * u + (lane >> 4), kc = min(k, nb - 1);
+                double b[2];
 #pragma unroll
                 for (int sj = 0; sj < 2; ++sj)
-                    acc[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[si], b[sj], acc[si][sj], 0, 0, 0);
+                    b[sj] = k < nb ? ut[kc * LU_CB + (C - cb) + 16 * sj + (lane & 15)] : 0.0;
+#pragma unroll
+                for (int si = 0; si < 2; ++si)
+#pragma unroll
+                    for (int sj = 0; sj < 2; ++sj)
+                        acc[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][si], b[sj], acc[si][sj], 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int si = 0; si < 2; ++si)
@@ -1934,34 +1958,44 @@ __device__ __forceinline__ void trailing_update_cg(float *Ar, float *Ai, int r0,
         const int R = r0 + 32 * (t / nct), C = cb + 32 * (t % nct);
         const int tn = t + LU_THREADS / 64;
         if (tn < ntile) load(tn, nr, ni);
-        for (int k0 = 0; k0 < nb; k0 += 4) {
-            const int k = k0 + (lane >> 4);
-            float ar[2], ai[2], nai[2], br[2], bi[2];
+        // L operands of UK k-steps loaded before their products (the L of
+        // the once-per-block update comes from global memory)
+        constexpr int UK = 4;
+        for (int k0 = 0; k0 < nb; k0 += 4 * UK) {
+            float ar[UK][2], ai[UK][2];
 #pragma unroll
-            for (int si = 0; si < 2; ++si) {
-                const int row = R + 16 * si + (lane & 15);
-                const bool ok = row < m && k < nb;
-                float lr, li;
-                lop(min(row, m - 1), min(k, nb - 1), lr, li);
-                ar[si] = ok ? -lr : 0.0f;
-                ai[si] = ok ? -li : 0.0f;
-                nai[si] = -ai[si];
+            for (int u = 0; u < UK; ++u) {
+                const int k = k0 + 4 * u + (lane >> 4);
+#pragma unroll
+                for (int si = 0; si < 2; ++si) {
+                    const int row = R + 16 * si + (lane & 15);
+                    const bool ok = row < m && k < nb;
+                    float lr, li;
+                    lop(min(row, m - 1), min(k, nb - 1), lr, li);
+                    ar[u][si] = ok ? -lr : 0.0f;
+                    ai[u][si] = ok ? -li : 0.0f;
+                }
             }
 #pragma unroll
-            for (int sj = 0; sj < 2; ++sj) {
-                const int kc = min(k, nb - 1), col = (C - cb) + 16 * sj + (lane & 15);
-                br[sj] = k < nb ? ur[kc * ldu + col] : 0.0f;
-                bi[sj] = k < nb ? ui[kc * ldu + col] : 0.0f;
-            }
-#pragma unroll
-            for (int si = 0; si < 2; ++si)
+            for (int u = 0; u < UK; ++u) {
+                const int k = k0 + 4 * u + (lane >> 4), kc = min(k, nb - 1);
+                float br[2], bi[2];
 #pragma unroll
                 for (int sj = 0; sj < 2; ++sj) {
-                    cr[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[si], br[sj], cr[si][sj], 0, 0, 0);
-                    cr[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[si], bi[sj], cr[si][sj], 0, 0, 0);
-                    ci[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[si], bi[sj], ci[si][sj], 0, 0, 0);
-                    ci[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[si], br[sj], ci[si][sj], 0, 0, 0);
+                    const int col = (C - cb) + 16 * sj + (lane & 15);
+                    br[sj] = k < nb ? ur[kc * ldu + col] : 0.0f;
+                    bi[sj] = k < nb ? ui[kc * ldu + col] : 0.0f;
                 }
+#pragma unroll
+                for (int si = 0; si < 2; ++si)
+#pragma unroll
+                    for (int sj = 0; sj < 2; ++sj) {
+                        cr[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[u][si], br[sj], cr[si][sj], 0, 0, 0);
+                        cr[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[u][si], bi[sj], cr[si][sj], 0, 0, 0);
+                        ci[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[u][si], bi[sj], ci[si][sj], 0, 0, 0);
+                        ci[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[u][si], br[sj], ci[si][sj], 0, 0, 0);
+                    }
+            }
         }
 #pragma unroll
         for (int si = 0; si < 2; ++si)
