@@ -570,7 +570,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
                      "traffic_source": traffic_note,
-                     "kernel": "jac_cell_kernel<2,5,256,f64> (3D Jacobian volume terms)",
+                     "kernel": "jac_cell_kernel<2,5,192,f64> (3D Jacobian volume terms)",
                      "flops_per_launch": flops,
                      "flops_per_launch_performed": vmult_flops_performed(w["n"], w["r"], w["k"], nq),
                      "kernel_ms": cell64},

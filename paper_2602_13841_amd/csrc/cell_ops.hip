@@ -2075,11 +2075,15 @@ static hipError_t launch_face(const CellArgs<T> &a, int nvec, hipStream_t s)
 // (time per launch, 128 vs 256 threads): r = 1, n_q = 4: FP64 28 vs 44 us,
 // FP32 19 vs 26; r = 2, n_q = 5: FP64 78 vs 73, FP32 42 vs 46; r = 2,
 // n_q = 4: FP64 58 vs 64, FP32 34 vs 40; r = 3, n_q = 7 (k = 1): FP64 231
-// vs 150, FP32 106 vs 88
+// vs 150, FP32 106 vs 88.  192 threads: FP64 r = 2, n_q = 5 72 us (at 121
+// VGPRs a CU holds five 3-wavefront groups against four of 4 wavefronts, and
+// five groups' LDS, 31.6 KB each, still fit in 160 KB); FP32 r = 3 87 us
+// against 93 at 256 (130 VGPRs: four groups against three).  FP64 r = 3
+// (178 VGPRs, two wavefronts per SIMD) gains nothing from it: 185 us.
 template <int R, int NQ, typename T> constexpr int jac_threads()
 {
-    if (R == 3) return 256;
-    if (R == 2 && NQ == 5 && sizeof(T) == 8) return 256;
+    if (R == 3) return sizeof(T) == 8 ? 256 : 192;
+    if (R == 2 && NQ == 5 && sizeof(T) == 8) return 192;
     return 128;
 }
 
