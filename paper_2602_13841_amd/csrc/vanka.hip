@@ -910,7 +910,7 @@ __host__ __device__ constexpr int lu_c_u_words(int nb, int nbo)
 // A22 stays FP32
 template <int OP, int NTH = LU_THREADS, int PF = 1, typename LOP>
 __device__ __forceinline__ void trailing_update(float *A, int r0, int m, int ld, int nb, int cb, int ncb, LOP lop,
-                                                const float *ut)
+                                                const float *ut, int ldu = LU_CB)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32, ntile = nrt * nct;
@@ -966,7 +966,7 @@ __device__ __forceinline__ void trailing_update(float *A, int r0, int m, int ld,
                     float b[2];
 #pragma unroll
                     for (int sj = 0; sj < 2; ++sj)
-                        b[sj] = k < nb ? ut[kc * LU_CB + (C - cb) + 16 * sj + (lane & 15)] : 0.0f;
+                        b[sj] = k < nb ? ut[kc * ldu + (C - cb) + 16 * sj + (lane & 15)] : 0.0f;
 #pragma unroll
                     for (int si = 0; si < 2; ++si)
 #pragma unroll
@@ -991,7 +991,7 @@ __device__ __forceinline__ void trailing_update(float *A, int r0, int m, int ld,
                     }
 #pragma unroll
                     for (int sj = 0; sj < 2; ++sj) {
-                        const float v = ut[kc * LU_CB + (C - cb) + 16 * sj + (lane & 15)];
+                        const float v = ut[kc * ldu + (C - cb) + 16 * sj + (lane & 15)];
                         const float b = k < nb ? v : 0.0f;
                         if constexpr (OP == 1) bs[sj][j] = bf16_rne(b);
                         else bh[sj][j] = (_Float16)b;
@@ -1035,7 +1035,7 @@ __device__ __forceinline__ void trailing_update(float *A, int r0, int m, int ld,
 // is computed
 template <int OP, int NTH = LU_THREADS, int PF = 1, typename LOP>
 __device__ __forceinline__ void trailing_update(double *A, int r0, int m, int ld, int nb, int cb, int ncb, LOP lop,
-                                                const double *ut)
+                                                const double *ut, int ldu = LU_CB)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nrt = (m - r0 + 31) / 32, nct = (ncb + 31) / 32, ntile = nrt * nct;
@@ -1084,7 +1084,7 @@ __device__ __forceinline__ void trailing_update(double *A, int r0, int m, int ld
                 double b[2];
 #pragma unroll
                 for (int sj = 0; sj < 2; ++sj)
-                    b[sj] = k < nb ? ut[kc * LU_CB + (C - cb) + 16 * sj + (lane & 15)] : 0.0;
+                    b[sj] = k < nb ? ut[kc * ldu + (C - cb) + 16 * sj + (lane & 15)] : 0.0;
 #pragma unroll
                 for (int si = 0; si < 2; ++si)
 #pragma unroll
@@ -1330,16 +1330,21 @@ __device__ __forceinline__ void lu_one(T *__restrict__ A, int m, int ld, int *__
             __syncthreads();
             u12_update(j0, nb, jend, m, jend);
         }
+        // U staged in the panel and U regions (free here), in column blocks
+        // as wide as they hold: every column block reads L once more from
+        // global memory
         const int kk = jend - J0;
-        for (int cb = jend; cb < m; cb += LU_CB) {
-            const int ncb = min(LU_CB, m - cb);
-            for (int e = tid; e < kk * LU_CB; e += NTH) {
-                const int c = e / LU_CB, j = e - c * LU_CB;
-                ut[e] = j < ncb ? A[(long long)(J0 + c) * ld + cb + j] : T(0);
+        const int cbw = max(LU_CB, min((int)(((size_t)m * NBP + (size_t)nbo * LU_CB) / kk) & ~31, (m - jend + 31) & ~31));
+        T *uw = pan;
+        for (int cb = jend; cb < m; cb += cbw) {
+            const int ncb = min(cbw, m - cb);
+            for (int e = tid; e < kk * cbw; e += NTH) {
+                const int c = e / cbw, j = e - c * cbw;
+                uw[e] = j < ncb ? A[(long long)(J0 + c) * ld + cb + j] : T(0);
             }
             __syncthreads();
             trailing_update<OP, NTH, PF>(A, jend, m, ld, kk, cb, ncb,
-                                         [=](int row, int k) { return A[(long long)row * ld + J0 + k]; }, ut);
+                                         [=](int row, int k) { return A[(long long)row * ld + J0 + k]; }, uw, cbw);
             __syncthreads();
         }
       }
@@ -2232,15 +2237,20 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c2(T *__restrict__ Aall,
             __syncthreads();
             u12_update(j0, nb, jend, m, jend);
         }
+        // the U rows are staged in the panel and U regions (free here), in
+        // column blocks as wide as they hold: every column block reads L once
+        // more from global memory
         const int kk = jend - J0;
-        for (int cb = jend; cb < m; cb += LU_CBD) {
-            const int ncb = min(LU_CBD, m - cb);
-            for (int e = tid; e < kk * LU_CBD; e += LU_THREADS) {
-                const int c = e / LU_CBD, j = e - c * LU_CBD;
+        const int cbw = max(LU_CBD, min(((2 * m * NBP + 2 * ubw) / (2 * kk)) & ~31, (m - jend + 31) & ~31));
+        T *vr = pr, *vi = pr + (size_t)kk * cbw;
+        for (int cb = jend; cb < m; cb += cbw) {
+            const int ncb = min(cbw, m - cb);
+            for (int e = tid; e < kk * cbw; e += LU_THREADS) {
+                const int c = e / cbw, j = e - c * cbw;
                 const long long g = (long long)(J0 + c) * ld + cb + min(j, ncb - 1);
                 const T a = Ar[g], b = Ai[g];
-                ur[e] = j < ncb ? a : T(0);
-                ui[e] = j < ncb ? b : T(0);
+                vr[e] = j < ncb ? a : T(0);
+                vi[e] = j < ncb ? b : T(0);
             }
             __syncthreads();
             trailing_update_cg(Ar, Ai, jend, m, ld, kk, cb, ncb,
@@ -2249,7 +2259,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c2(T *__restrict__ Aall,
                                   lr = Ar[g];
                                   li = Ai[g];
                               },
-                              ur, ui, LU_CBD);
+                              vr, vi, cbw);
             __syncthreads();
         }
       }
