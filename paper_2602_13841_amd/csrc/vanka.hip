@@ -1768,6 +1768,32 @@ __device__ __forceinline__ void trailing_update_c(double *Ar, double *Ai, int m,
     }
 }
 
+// the composed interchanges of one panel (row j0 + aff_src[i] moves to row
+// j0 + aff_dst[i], i < na) on columns [c_lo, c_hi), one plane after the
+// other: one column per thread, its affected entries through registers
+// (columns are independent: no staging and no barrier between column chunks)
+template <int NB, typename T>
+__device__ __forceinline__ void swap_columns_c(T *Ar, T *Ai, int ld, int j0, int na, const int *aff_src,
+                                               const int *aff_dst, int c_lo, int c_hi)
+{
+#pragma unroll 1
+    for (int col = c_lo + (int)threadIdx.x; col < c_hi; col += LU_THREADS)
+#pragma unroll 1
+        for (int plane = 0; plane < 2; ++plane) {
+            // compiler-only barrier: keeps the row indices' LDS reads inside
+            // the loop (hoisted, 4 NB row offsets would stay in registers)
+            asm volatile("" ::: "memory");
+            T *A = plane ? Ai : Ar;
+            T v[2 * NB];
+#pragma unroll
+            for (int i = 0; i < 2 * NB; ++i)
+                if (i < na) v[i] = A[(long long)(j0 + aff_src[i]) * ld + col];
+#pragma unroll
+            for (int i = 0; i < 2 * NB; ++i)
+                if (i < na) A[(long long)(j0 + aff_dst[i]) * ld + col] = v[i];
+        }
+}
+
 // batched blocked complex LU with partial pivoting (largest modulus), planar
 // row-major storage: matrix b at Aall + b * a_stride, real plane then
 // imaginary plane; same panel / interchange / update structure as the real
@@ -1854,7 +1880,12 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c(T *__restrict__ Aall, 
         if (wv == 0) compose_panel_swaps<NB>(sw, nb, aff_dst, aff_src, &n_aff);
         __syncthreads();
         const int na = n_aff;
-        if (na > 0) {
+        if constexpr (NB <= 16) {
+            if (na > 0) {
+                swap_columns_c<NB>(Ar, Ai, ld, j0, na, aff_src, aff_dst, 0, m);
+                __syncthreads();
+            }
+        } else if (na > 0) {
             for (int plane = 0; plane < 2; ++plane) {
                 T *A = plane ? Ai : Ar;
                 for (int c0 = 0; c0 < m; c0 += LU_SWC) {
@@ -2048,7 +2079,6 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c2(T *__restrict__ Aall,
     T *pi = pr + (size_t)m * NBP;                      // [m][NBP] panel, imaginary
     T *ur = pi + (size_t)m * NBP;                      // U block: [NB][LU_CB] or [nbo][LU_CBD]
     T *ui = ur + (size_t)ubw;
-    T *stg = ui + (size_t)ubw;                         // [2 NB][LU_SWC] interchange staging
     __shared__ T rv[LU_THREADS / 64];
     __shared__ int ri[LU_THREADS / 64];
     __shared__ int sw[NB];
@@ -2068,22 +2098,8 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c2(T *__restrict__ Aall,
         __syncthreads();
         const int na = n_aff;
         if (na > 0) {
-            for (int plane = 0; plane < 2; ++plane) {
-                T *A = plane ? Ai : Ar;
-                for (int c0 = c_lo; c0 < c_hi; c0 += LU_SWC) {
-                    const int nc = min(LU_SWC, c_hi - c0);
-                    for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
-                        const int i = e / LU_SWC, j = e % LU_SWC;
-                        if (j < nc) stg[i * LU_SWC + j] = A[(long long)(j0 + aff_src[i]) * ld + c0 + j];
-                    }
-                    __syncthreads();
-                    for (int e = tid; e < na * LU_SWC; e += LU_THREADS) {
-                        const int i = e / LU_SWC, j = e % LU_SWC;
-                        if (j < nc) A[(long long)(j0 + aff_dst[i]) * ld + c0 + j] = stg[i * LU_SWC + j];
-                    }
-                    __syncthreads();
-                }
-            }
+            swap_columns_c<NB>(Ar, Ai, ld, j0, na, aff_src, aff_dst, c_lo, c_hi);
+            __syncthreads();
         }
     };
     // U12 = L11^{-1} A12 on columns [c_lo, c_hi) of the rows j0 .. j0+nb (L11
@@ -3090,7 +3106,7 @@ template <int NB, typename T> size_t lu_c_lds_bytes(int m)
 // LDS of lu_kernel_c2
 template <int NB> size_t lu_c2_lds_bytes(int m)
 {
-    return ((size_t)2 * m * (NB + 1) + (size_t)2 * lu_c_u_words(NB, LU_CB) + (size_t)2 * NB * LU_SWC) * sizeof(float);
+    return ((size_t)2 * m * (NB + 1) + (size_t)2 * lu_c_u_words(NB, LU_CB)) * sizeof(float);
 }
 
 } // namespace
