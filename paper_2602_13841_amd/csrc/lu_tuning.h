@@ -18,10 +18,10 @@ struct LuTune {
 
 // index: 0 = FP64, 1 = FP32, 2 = FP32 with BF16 update operands, 3 = FP16
 constexpr LuTune LU_TUNED[4] = {
-    {1, 512, {8, 8, 16, 16, 16}},   // f64: 82.8 ms, 9.56 TFLOP/s; one launch per size class 91.3 ms
-    {3, 256, {8, 16, 16, 16, 4}},   // f32: 62.7 ms, 12.61 TFLOP/s; one launch per size class 63.8 ms
-    {3, 256, {8, 16, 16, 8, 16}},   // f32_bf16: 60.0 ms, 13.18 TFLOP/s; one launch per size class 63.4 ms
-    {3, 256, {8, 16, 16, 16, 8}},   // f32_f16: 59.4 ms, 13.33 TFLOP/s; one launch per size class 62.3 ms
+    {1, 512, {8, 8, 16, 16, 8}},   // f64: 77.9 ms, 10.16 TFLOP/s; one launch per size class 87.9 ms
+    {3, 256, {8, 16, 16, 8, 4}},   // f32: 56.8 ms, 13.92 TFLOP/s; one launch per size class 63.6 ms
+    {3, 256, {8, 16, 16, 8, 8}},   // f32_bf16: 53.1 ms, 14.89 TFLOP/s; one launch per size class 60.2 ms
+    {3, 256, {8, 16, 16, 8, 16}},   // f32_f16: 52.9 ms, 14.96 TFLOP/s; one launch per size class 59.9 ms
 };
 
 } // namespace stmg
