@@ -228,8 +228,9 @@ int stmg_mass_vmult(stmg_ctx *ctx, int prec, const void *x, void *y);
 
 /* ---- hp space-time multigrid (Sec. "Preconditioning of GMRES by hp
  * space-time multigrid") ----------------------------------------------------
- * Levels: 0 = the slab itself; p-coarsening first, (k, r) -> (k//2 if k >= 2
- * else k, max(1, r//2)), then h-coarsening of the mesh while every n_cells
+ * Levels: 0 = the slab itself; p-coarsening first, (k, r) -> (k, max(1,
+ * r//2)) by default, or (k//2 if k >= 2 else k, max(1, r//2)) with
+ * opt.time_coarsening = 1, then h-coarsening of the mesh while every n_cells
  * is even and >= 4 (capped by opt.max_levels).  Level vectors use the slab
  * layout of their own (k, r, n_cells). */
 int stmg_num_levels(const stmg_ctx *ctx);

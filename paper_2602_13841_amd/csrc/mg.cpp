@@ -2,12 +2,14 @@
 // multigrid"), FGMRES (eq. inexact) and the inexact Newton method with
 // Eisenstat-Walker forcing and nonmonotone Armijo backtracking (Alg.
 // "Inexact Newton-Krylov", Alg. "Armijo").  Host code driving device
-// kernels; control decisions (Givens rotations, stopping tests, line search)
-// use scalars read back once per iteration.
+// kernels; the Givens rotations run on the device (one FP64 workgroup), and
+// the stopping tests and the line search use scalars read back once per
+// iteration.
 //
 // Readings where the paper leaves details open:
-// * hierarchy: p-coarsening first, (k, r) -> (k//2 if k >= 2 else k,
-//   max(1, r//2)), then h-coarsening while every n is even and >= 4;
+// * hierarchy: p-coarsening first, (k, r) -> (k, max(1, r//2)) by default,
+//   (k//2 if k >= 2 else k, max(1, r//2)) with time_coarsening = 1, then
+//   h-coarsening while every n is even and >= 4;
 // * level operators: rediscretized at the finer state evaluated at the
 //   coarser nodes and Radau nodes; the coarsest level is solved directly in
 //   FP64, bordered by the constant pressure of each time node when Gamma_D
