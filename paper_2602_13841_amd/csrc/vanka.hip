@@ -893,6 +893,7 @@ constexpr int LU_NBO_MIN_M = 192; // larger matrices: outer blocks of LU_CB colu
 // for the code of the second level)
 __host__ __device__ constexpr int lu_outer_block(int m, int nb) { return m > LU_NBO_MIN_M && nb < 32 ? LU_CB : nb; }
 constexpr int LU_CBD = 32;       // column block of the complex once-per-block update
+constexpr int LU_C2_ROWS = 4;    // panel rows per thread of lu_kernel_c2 (m <= LU_C2_ROWS LU_THREADS)
 // words per plane of the complex U block: the panels' [NB][LU_CB] and the
 // outer block's [nbo][LU_CBD]
 __host__ __device__ constexpr int lu_c_u_words(int nb, int nbo)
@@ -2079,8 +2080,9 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c2(T *__restrict__ Aall,
     T *pi = pr + (size_t)m * NBP;                      // [m][NBP] panel, imaginary
     T *ur = pi + (size_t)m * NBP;                      // U block: [NB][LU_CB] or [nbo][LU_CBD]
     T *ui = ur + (size_t)ubw;
-    __shared__ T rv[LU_THREADS / 64];
-    __shared__ int ri[LU_THREADS / 64];
+    int *pa = reinterpret_cast<int *>(ui + ubw);     // [m] panel row holding each logical row
+    __shared__ T rv[2][LU_THREADS / 64];               // pivot candidates per wave, by column parity
+    __shared__ int rl[2][LU_THREADS / 64], rp[2][LU_THREADS / 64];
     __shared__ int sw[NB];
     __shared__ int aff_src[2 * NB], aff_dst[2 * NB];
     __shared__ int n_aff;
@@ -2088,8 +2090,9 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c2(T *__restrict__ Aall,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     auto from_panel = [&](int j0) {
         return [=](int row, int k, T &lr, T &li) {
-            lr = pr[(row - j0) * NBP + k];
-            li = pi[(row - j0) * NBP + k];
+            const int o = pa[row - j0] * NBP + k;
+            lr = pr[o];
+            li = pi[o];
         };
     };
     // interchanges of one panel (local pivots sw[0 .. nb)) on columns [c_lo, c_hi), both planes
@@ -2122,9 +2125,10 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c2(T *__restrict__ Aall,
 #pragma unroll
             for (int c = 1; c < NB; ++c) {
                 T sr = vr[c], si = vi[c];
+                const int pc = c < nb ? pa[c] * NBP : 0;
 #pragma unroll
                 for (int k = 0; k < c; ++k) {
-                    const T lr = pr[c * NBP + k], li = pi[c * NBP + k];
+                    const T lr = pr[pc + k], li = pi[pc + k];
                     sr -= lr * vr[k] - li * vi[k];
                     si -= lr * vi[k] + li * vr[k];
                 }
@@ -2168,64 +2172,86 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c2(T *__restrict__ Aall,
             pi[r * NBP + c] = Ai[g];
         }
         __syncthreads();
+        // The panel rows stay where they are: each thread owns the rows
+        // tid + i LU_THREADS and keeps their logical positions (lg, moved by
+        // the interchanges) and whether they are pivotal yet (dn) in
+        // registers.  A pivot row is not written while its column is
+        // eliminated, and each thread searches only the rows it updated
+        // itself, so each column takes one barrier; ties go to the smaller
+        // logical row, so the pivots and factors are those of the panel with
+        // its rows interchanged.
+        int lg[LU_C2_ROWS];
+        unsigned dn = 0;
+#pragma unroll
+        for (int i = 0; i < LU_C2_ROWS; ++i) lg[i] = tid + i * LU_THREADS;
         for (int c = 0; c < nb; ++c) {
+            const int buf = c & 1;
             T best = T(-1);
-            int bi = c;
-            for (int r = c + tid; r < mr; r += LU_THREADS) {
-                const T x = pr[r * NBP + c], y = pi[r * NBP + c];
-                const T v = x * x + y * y;
-                if (v > best) { best = v; bi = r; }
+            int bl = 0x7fffffff, bp = 0;
+#pragma unroll
+            for (int i = 0; i < LU_C2_ROWS; ++i) {
+                const int r = tid + i * LU_THREADS;
+                if (r < mr && !((dn >> i) & 1u)) {
+                    const T x = pr[r * NBP + c], y = pi[r * NBP + c];
+                    const T v = x * x + y * y;
+                    if (v > best || (v == best && lg[i] < bl)) { best = v; bl = lg[i]; bp = r; }
+                }
             }
             for (int off = 32; off > 0; off >>= 1) {
-                T ov = __shfl_xor(best, off, 64);
-                int oi = __shfl_xor(bi, off, 64);
-                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+                const T ov = __shfl_xor(best, off, 64);
+                const int ol = __shfl_xor(bl, off, 64), op = __shfl_xor(bp, off, 64);
+                if (ov > best || (ov == best && ol < bl)) { best = ov; bl = ol; bp = op; }
             }
-            if (lane == 0) { rv[wv] = best; ri[wv] = bi; }
+            if (lane == 0) { rv[buf][wv] = best; rl[buf][wv] = bl; rp[buf][wv] = bp; }
             __syncthreads();
-            T bv = rv[0];
-            int p = ri[0];
+            T bv = rv[buf][0];
+            int p = rl[buf][0], P = rp[buf][0];
             for (int w = 1; w < LU_THREADS / 64; ++w)
-                if (rv[w] > bv || (rv[w] == bv && ri[w] < p)) { bv = rv[w]; p = ri[w]; }
+                if (rv[buf][w] > bv || (rv[buf][w] == bv && rl[buf][w] < p)) { bv = rv[buf][w]; p = rl[buf][w]; P = rp[buf][w]; }
             if (tid == 0) {
                 piv[j0 + c] = j0 + p;
                 sw[c] = p;
                 bsw[j0 - J0 + c] = p;
                 if (bv == T(0) && info) atomicAdd(info, 1);
             }
-            if (p != c && tid < nb) {
-                T t = pr[c * NBP + tid];
-                pr[c * NBP + tid] = pr[p * NBP + tid];
-                pr[p * NBP + tid] = t;
-                t = pi[c * NBP + tid];
-                pi[c * NBP + tid] = pi[p * NBP + tid];
-                pi[p * NBP + tid] = t;
-            }
-            __syncthreads();
-            const T dr = pr[c * NBP + c], di = pi[c * NBP + c];
+            const T dr = pr[P * NBP + c], di = pi[P * NBP + c];
             const T den = dr * dr + di * di;
             const T ir = den != T(0) ? dr / den : T(0), ii = den != T(0) ? -di / den : T(0);
-            for (int r = c + 1 + tid; r < mr; r += LU_THREADS) {
+#pragma unroll
+            for (int i = 0; i < LU_C2_ROWS; ++i) {
+                const int r = tid + i * LU_THREADS;
+                if (r >= mr || ((dn >> i) & 1u)) continue;
+                if (r == P) {
+                    lg[i] = c;
+                    dn |= 1u << i;
+                    continue;
+                }
+                if (lg[i] == c) lg[i] = p;
                 const T xr = pr[r * NBP + c], xi = pi[r * NBP + c];
                 const T lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
                 pr[r * NBP + c] = lr;
                 pi[r * NBP + c] = li;
                 for (int cc = c + 1; cc < nb; ++cc) {
-                    const T vr = pr[c * NBP + cc], vi = pi[c * NBP + cc];
+                    const T vr = pr[P * NBP + cc], vi = pi[P * NBP + cc];
                     pr[r * NBP + cc] -= lr * vr - li * vi;
                     pi[r * NBP + cc] -= lr * vi + li * vr;
                 }
             }
-            __syncthreads();
         }
+#pragma unroll
+        for (int i = 0; i < LU_C2_ROWS; ++i) {
+            const int r = tid + i * LU_THREADS;
+            if (r < mr) pa[lg[i]] = r;
+        }
+        __syncthreads();
         // the panel's interchanges on the columns it touches (its own columns
         // are rewritten below)
         apply_swaps(j0, nb, 0, cmax);
         for (int e = tid; e < mr * nb; e += LU_THREADS) {
             const int r = e / nb, c = e % nb;
             const long long g = (long long)(j0 + r) * ld + j0 + c;
-            Ar[g] = pr[r * NBP + c];
-            Ai[g] = pi[r * NBP + c];
+            Ar[g] = pr[pa[r] * NBP + c];
+            Ai[g] = pi[pa[r] * NBP + c];
         }
         __syncthreads();
         u12_update(j0, nb, j0 + nb, cmax, m);
@@ -2250,6 +2276,7 @@ __global__ void __launch_bounds__(LU_THREADS) lu_kernel_c2(T *__restrict__ Aall,
                 pr[r * NBP + c] = Ar[g];
                 pi[r * NBP + c] = Ai[g];
             }
+            for (int r = tid; r < nr; r += LU_THREADS) pa[r] = r;   // rows reloaded in logical order
             __syncthreads();
             u12_update(j0, nb, jend, m, jend);
         }
@@ -3103,10 +3130,10 @@ template <int NB, typename T> size_t lu_c_lds_bytes(int m)
     return ((size_t)2 * m * (NB + 1) + (size_t)2 * NB * LU_CB + (size_t)2 * NB * LU_SWC) * sizeof(T);
 }
 
-// LDS of lu_kernel_c2
+// LDS of lu_kernel_c2 (panel, U block, logical-to-panel row map)
 template <int NB> size_t lu_c2_lds_bytes(int m)
 {
-    return ((size_t)2 * m * (NB + 1) + (size_t)2 * lu_c_u_words(NB, LU_CB)) * sizeof(float);
+    return ((size_t)2 * m * (NB + 1) + (size_t)2 * lu_c_u_words(NB, LU_CB) + (size_t)m) * sizeof(float);
 }
 
 } // namespace
@@ -3302,7 +3329,7 @@ hipError_t launch_lu_c(T *A, int *piv, int m, int ld, long long a_stride, int ba
                        hipStream_t s)
 {
     if constexpr (std::is_same<T, float>::value) {
-        if (m > LU_NBO_MIN_M) {
+        if (m > LU_NBO_MIN_M && m <= LU_C2_ROWS * LU_THREADS) {
             // two blocking levels: the widest panel (16 or 8, within the
             // STMG_LU_NB cap) with two workgroups per CU, else the widest that fits
             int cap2 = std::min(lu_nb_cap(), 16);
