@@ -1595,14 +1595,24 @@ __global__ void __launch_bounds__(256) patch_td_kernel(PatchTdArgs<TE, TP> A)
     const int nn[3] = {A.n0, A.n1, A.n2};
     const long long rw = A.rec_words;
     const TE *own = A.elem + (long long)cell * rw + DIM * DIM * NL * NL + NL * NL;
+    // velocity index -> component, node and the node's per-axis positions,
+    // packed (bits 0-3, 4-7, 8-11: positions; 12-19: node; 20-21: component)
+    static_assert(N1 <= 16 && NL <= 256, "patch index packing");
+    __shared__ int dec[NV];
+    for (int t = threadIdx.x; t < NV; t += blockDim.x) {
+        const int i = t % NL, c = t / NL;
+        dec[t] = (i % N1) | (((i / N1) % N1) << 4) | ((DIM == 3 ? i / (N1 * N1) : 0) << 8) | (i << 12) | (c << 20);
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < MS * MS; e += blockDim.x) {
         const int row = e / MS, col = e - (e / MS) * MS;
         double mv = 0, lv = 0;
         if (row < NV && col < NV) {
-            const int i = row % NL, c = row / NL, j = col % NL, e2 = col / NL;
+            const int dr = dec[row], dc = dec[col];
+            const int i = (dr >> 12) & 255, c = dr >> 20, j = (dc >> 12) & 255, e2 = dc >> 20;
             const bool need_m = c == e2;
-            int li[3] = {i % N1, (i / N1) % N1, DIM == 3 ? i / (N1 * N1) : 0};
-            int lj[3] = {j % N1, (j / N1) % N1, DIM == 3 ? j / (N1 * N1) : 0};
+            int li[3] = {dr & 15, (dr >> 4) & 15, (dr >> 8) & 15};
+            int lj[3] = {dc & 15, (dc >> 4) & 15, (dc >> 8) & 15};
             // neighbour offsets per axis that hold both nodes
             int opts[3][3], nopt[3];
             for (int ax = 0; ax < 3; ++ax) {
