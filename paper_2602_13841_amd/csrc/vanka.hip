@@ -191,8 +191,14 @@ __global__ void __launch_bounds__(EL_THREADS) elem_kernel(ElemArgs<T> A)
     __shared__ T qw[NQ], qx[NQ];
     __shared__ T vloc[DIM * NL];
     __shared__ T geo[32];
-    __shared__ T prec[PCH * PREC];
-    __shared__ int pidx[PCH * 3];                 // per-axis 1D index (>=0 Gauss, -1 s=0, -2 s=1)
+    // point records: all of them, built once, where they fit (the boundary-face
+    // points of a 3D cell in FP32: at most 6 NQF), else one chunk at a time
+    constexpr int NPTS_MAX = (FACE_ONLY ? 0 : NQV) + 2 * DIM * NQF;
+    constexpr int NPCH_MAX = (NPTS_MAX + PCH - 1) / PCH * PCH;
+    constexpr bool PRE = (size_t)NPCH_MAX * (PREC * sizeof(T) + 3 * sizeof(int)) <= 32768;
+    constexpr int NREC = PRE ? NPCH_MAX : PCH;
+    __shared__ T prec[NREC * PREC];
+    __shared__ int pidx[NREC * 3];                // per-axis 1D index (>=0 Gauss, -1 s=0, -2 s=1)
     __shared__ T Bi[PCH * TILE * 4], Bj[PCH * TILE * 4];
     __shared__ T red[NT];
     __shared__ int faces[6];
@@ -300,13 +306,10 @@ __global__ void __launch_bounds__(EL_THREADS) elem_kernel(ElemArgs<T> A)
     auto dv = [&](int idx, int i) -> T { return idx >= 0 ? tabD[idx * N1 + i] : tabDe[(idx == -1 ? 0 : 1) * N1 + i]; };
     auto lv = [&](int idx, int i) -> T { return idx >= 0 ? tabL[idx * RP1 + i] : tabLe[(idx == -1 ? 0 : 1) * RP1 + i]; };
 
-    // point records of chunk ch -> prec / pidx (threads < PCH)
-    auto build_chunk = [&](int ch) {
-        if (tid < PCH) {
-            const int p0 = ch * PCH + tid;
+    // point record of point p0 -> P / ix
+    auto build_point = [&](int p0, T *P, int *ix) {
+        {
             const int p = FACE_ONLY ? p0 + NQV : p0;
-            T *P = prec + tid * PREC;
-            int *ix = pidx + tid * 3;
             if (p0 >= npts) {
                 P[P_W] = 0;
                 P[P_FACE] = T(-2);
@@ -387,7 +390,16 @@ __global__ void __launch_bounds__(EL_THREADS) elem_kernel(ElemArgs<T> A)
             }
         }
     };
-    // basis values/gradients of node l at chunk point p -> B[(p*TILE + slot)*4 ..]
+    // chunk ch of the point records (threads < PCH), or all at once
+    auto build_chunk = [&](int ch) {
+        if constexpr (!PRE)
+            if (tid < PCH) build_point(ch * PCH + tid, prec + tid * PREC, pidx + tid * 3);
+    };
+    if constexpr (PRE) {
+        for (int p0 = tid; p0 < nchunks * PCH; p0 += NT) build_point(p0, prec + p0 * PREC, pidx + p0 * 3);
+        __syncthreads();
+    }
+    // basis values/gradients of node l at point record p -> B[(p*TILE + slot)*4 ..]
     auto basis = [&](int p, int l, T *out) {
         const int *ix = pidx + p * 3;
         const T *P = prec + p * PREC;
@@ -432,20 +444,21 @@ __global__ void __launch_bounds__(EL_THREADS) elem_kernel(ElemArgs<T> A)
             for (int ch = 0; ch < nchunks; ++ch) {
                 build_chunk(ch);
                 __syncthreads();
+                const int cb0 = PRE ? ch * PCH : 0;   // first record of the chunk
                 for (int e = tid; e < PCH * TILE; e += NT) {
                     int p = e / TILE, s = e % TILE;
                     T tmp[4];
                     int li = ib + s, lj = jb + s;
-                    if (li < NL) basis(p, li, tmp);
+                    if (li < NL) basis(cb0 + p, li, tmp);
                     else tmp[0] = tmp[1] = tmp[2] = tmp[3] = 0;
                     for (int k = 0; k < 4; ++k) Bi[(p * TILE + s) * 4 + k] = tmp[k];
-                    if (lj < NL) basis(p, lj, tmp);
+                    if (lj < NL) basis(cb0 + p, lj, tmp);
                     else tmp[0] = tmp[1] = tmp[2] = tmp[3] = 0;
                     for (int k = 0; k < 4; ++k) Bj[(p * TILE + s) * 4 + k] = tmp[k];
                 }
                 __syncthreads();
                 for (int p = 0; p < PCH; ++p) {
-                    const T *P = prec + p * PREC;
+                    const T *P = prec + (cb0 + p) * PREC;
                     const T w = P[P_W];
                     if (w == T(0)) continue;
                     const T face = P[P_FACE];
@@ -515,6 +528,7 @@ __global__ void __launch_bounds__(EL_THREADS) elem_kernel(ElemArgs<T> A)
         for (int ch = 0; ch < nchunks; ++ch) {
             build_chunk(ch);
             __syncthreads();
+            const int cb0 = PRE ? ch * PCH : 0;   // first record of the chunk
             for (int s = 0; s < PPT; ++s) {
                 int pr = tid + s * NT;
                 if (pr >= NPAIR) break;
@@ -522,14 +536,14 @@ __global__ void __launch_bounds__(EL_THREADS) elem_kernel(ElemArgs<T> A)
                 int al[3] = {0, 0, 0};
                 pmode<DIM, R>(m, al);
                 for (int p = 0; p < PCH; ++p) {
-                    const T *P = prec + p * PREC;
+                    const T *P = prec + (cb0 + p) * PREC;
                     T w = P[P_W];
                     if (w == T(0)) continue;
-                    const int *ix = pidx + p * 3;
+                    const int *ix = pidx + (cb0 + p) * 3;
                     T psi = 1;
                     for (int a = 0; a < DIM; ++a) psi *= lv(ix[a], al[a]);
                     T b[4];
-                    basis(p, i, b);
+                    basis(cb0 + p, i, b);
                     if (P[P_FACE] < T(-0.5)) {
                         for (int c = 0; c < DIM; ++c) acc[s][c] -= w * psi * b[1 + c];
                     } else if (P[P_ISD] != T(0)) {
