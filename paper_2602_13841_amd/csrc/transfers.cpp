@@ -300,6 +300,16 @@ void Transfer::build(const Level &f, const Level &c, char kind_)
     upload_dense(It64, It32, L);
 }
 
+// lanes per row of a transfer: FP32 (the multigrid's own precision) reads long
+// rows with lane groups; FP64 keeps one thread per row, whose sums run over
+// the row in order (the exact-parity path: its iteration counts match the
+// oracle's, and a reordered sum can flip a line-search decision on a knife
+// edge)
+template <typename T> static int lanes(const DevCsr &M)
+{
+    return std::is_same<T, float>::value ? kron_lanes(M.nnz, M.nrows) : 1;
+}
+
 template <typename T> static const T *pick(const DevBuf &b64, const DevBuf &b32)
 {
     return std::is_same<T, double>::value ? (const T *)b64.p : (const T *)b32.p;
@@ -313,6 +323,7 @@ void Transfer::prolongate(const Level &f, const Level &c, const T *xc, T *yf, T 
     a.col = vel.col.as<int>();
     a.val = pick<T>(vel.val64, vel.val32);
     a.nrows = vel.nrows;
+    a.lpr = lanes<T>(vel);
     a.nt_out = f.nt;
     a.nt_in = c.nt;
     a.ncomp = f.dim;
@@ -329,6 +340,7 @@ void Transfer::prolongate(const Level &f, const Level &c, const T *xc, T *yf, T 
     a.col = pres.col.as<int>();
     a.val = pick<T>(pres.val64, pres.val32);
     a.nrows = pres.nrows;
+    a.lpr = lanes<T>(pres);
     a.ncomp = 1;
     a.in_t_stride = c.Np1;
     a.in_c_stride = 0;
@@ -347,6 +359,7 @@ void Transfer::restrict_(const Level &f, const Level &c, const T *xf, T *yc, hip
     a.col = velT.col.as<int>();
     a.val = pick<T>(velT.val64, velT.val32);
     a.nrows = velT.nrows;
+    a.lpr = lanes<T>(velT);
     a.nt_out = c.nt;
     a.nt_in = f.nt;
     a.ncomp = f.dim;
@@ -363,6 +376,7 @@ void Transfer::restrict_(const Level &f, const Level &c, const T *xf, T *yc, hip
     a.col = presT.col.as<int>();
     a.val = pick<T>(presT.val64, presT.val32);
     a.nrows = presT.nrows;
+    a.lpr = lanes<T>(presT);
     a.ncomp = 1;
     a.in_t_stride = f.Np1;
     a.in_c_stride = 0;
@@ -381,6 +395,7 @@ void Transfer::interpolate_state(const Level &f, const Level &c, const T *vf, T 
     a.col = state.col.as<int>();
     a.val = pick<T>(state.val64, state.val32);
     a.nrows = state.nrows;
+    a.lpr = lanes<T>(state);
     a.nt_out = c.nt;
     a.nt_in = f.nt;
     a.ncomp = f.dim;

@@ -45,7 +45,16 @@ template <typename T> struct KronCsrArgs {
     const T *x;
     T *y;
     T beta;
+    int lpr;                  // lanes per row (1, 4, 16 or 64; 0 = 1), see kron_lanes
 };
+// lanes per CSR row for a matrix with nnz entries in nrows rows: long rows
+// (restrictions gather hundreds of fine values) are read by a group of
+// lanes, consecutive entries by consecutive lanes
+inline int kron_lanes(long long nnz, long long nrows)
+{
+    const long long avg = nrows > 0 ? nnz / nrows : 0;
+    return avg < 6 ? 1 : avg < 24 ? 4 : avg < 96 ? 16 : 64;
+}
 template <typename T> hipError_t kron_csr_apply(const KronCsrArgs<T> &a, hipStream_t s);
 
 } // namespace stmg

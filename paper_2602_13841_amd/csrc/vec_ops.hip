@@ -99,15 +99,18 @@ __global__ void combination(long long n, int nk, const double *__restrict__ y, c
 }
 
 // y[ot][c][row] (+)= sum_it Tm[ot][it] sum_{k in row} val[k] x[it][c][col[k]]:
-// one thread per row reads the row's entries once for every component and
-// input time node (at most 3 and 4); per output the sums run over k in order,
-// then over it in order, skipping zero time coefficients
-template <typename T>
+// LPR lanes per row read the row's entries once for every component and input
+// time node (at most 3 and 4), lane j the entries k0 + j, k0 + j + LPR, ...;
+// per output the lane sums run over their k in order and are added by a fixed
+// xor tree, then the time coefficients in order, skipping zero ones
+template <typename T, int LPR>
 __global__ void __launch_bounds__(256) kron_csr_kernel(KronCsrArgs<T> A)
 {
     constexpr int MC = 3, MT = 4;
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= A.nrows) return;
+    static_assert(LPR >= 1 && LPR <= 64 && (LPR & (LPR - 1)) == 0, "lanes per row: a power of two up to 64");
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = (int)(g / LPR), sub = (int)(g % LPR);
+    if (row >= A.nrows) return;   // whole groups of LPR lanes
     const int k0 = A.rowptr[row], k1 = A.rowptr[row + 1];
     const int nti = A.nt_in, nc = A.ncomp;
     T sum[MC][MT];
@@ -115,7 +118,7 @@ __global__ void __launch_bounds__(256) kron_csr_kernel(KronCsrArgs<T> A)
     for (int c = 0; c < MC; ++c)
 #pragma unroll
         for (int it = 0; it < MT; ++it) sum[c][it] = T(0);
-    for (int k = k0; k < k1; ++k) {
+    for (int k = k0 + sub; k < k1; k += LPR) {
         const T v = A.val[k];
         const long long cl = A.col[k];
 #pragma unroll
@@ -123,6 +126,15 @@ __global__ void __launch_bounds__(256) kron_csr_kernel(KronCsrArgs<T> A)
 #pragma unroll
             for (int it = 0; it < MT; ++it)
                 if (c < nc && it < nti) sum[c][it] += v * A.x[it * A.in_t_stride + c * A.in_c_stride + cl];
+    }
+    if constexpr (LPR > 1) {
+#pragma unroll
+        for (int off = LPR / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int c = 0; c < MC; ++c)
+#pragma unroll
+                for (int it = 0; it < MT; ++it) sum[c][it] += __shfl_xor(sum[c][it], off, 64);
+        if (sub != 0) return;
     }
 #pragma unroll
     for (int ot = 0; ot < MT; ++ot)
@@ -254,7 +266,15 @@ template <typename T> hipError_t kron_csr_apply(const KronCsrArgs<T> &a, hipStre
         return hipErrorInvalidValue;
     if (a.nrows == 0) return hipSuccess;
     const int th = 256;
-    hipLaunchKernelGGL(kron_csr_kernel<T>, dim3((unsigned)((a.nrows + th - 1) / th)), dim3(th), 0, s, a);
+    const long long n1 = a.nrows;
+    switch (a.lpr) {
+    case 0:
+    case 1: hipLaunchKernelGGL((kron_csr_kernel<T, 1>), dim3((unsigned)((n1 + th - 1) / th)), dim3(th), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((kron_csr_kernel<T, 4>), dim3((unsigned)((4 * n1 + th - 1) / th)), dim3(th), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((kron_csr_kernel<T, 16>), dim3((unsigned)((16 * n1 + th - 1) / th)), dim3(th), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((kron_csr_kernel<T, 64>), dim3((unsigned)((64 * n1 + th - 1) / th)), dim3(th), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
